@@ -1,0 +1,342 @@
+"""Pins of the CPU oracle against closed forms, library routines and identities.
+
+Nothing here compares the oracle with a re-typed copy of itself: the
+operators are pinned by DST-I eigenpairs and by an independent Kronecker
+assembly; the direct solve by scipy's sparse LU; the transfers by their
+adjoint relation and exactness on linear data; the V-cycle by the textbook
+two-grid error-propagation operator; FGMRES by dense Krylov least squares.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spl
+
+from paper_2203_11025_amd import inputs
+from tests import pins
+
+RNG = np.random.default_rng(12345)
+
+
+def crandn(*shape):
+    return RNG.standard_normal(shape) + 1j * RNG.standard_normal(shape)
+
+
+def hetero(n, seed=0):
+    kap = inputs.smooth_medium(n, max(1.0, n / 8), seed=seed)
+    gam = inputs.sponge_gamma(n, width=max(2, n // 8))
+    return kap, gam, inputs.omega_for_ppw(n)
+
+
+# ---------------------------------------------------------------- operators
+
+@pytest.mark.parametrize("shift", [0.0, 0.5])
+@pytest.mark.parametrize("kl", [(1, 1), (3, 5), (7, 2), (16, 16)])
+def test_apply_dst_eigenpairs(oracle, shift, kl):
+    """Constant kappa and gamma: A is diagonalised by the 2D DST-I (eq. 2.1-2.2)."""
+    n, kap0, gam0 = 16, 0.8, 0.03
+    om = inputs.omega_for_ppw(n)
+    k, l = kl
+    phi = pins.dst_mode(n, k, l)
+    kap = np.full((n, n), kap0)
+    gam = np.full((n, n), gam0)
+    y = oracle.apply(kap, gam, om, phi, shift=shift)
+    lam = pins.dst_eigenvalue(n, k, l, kap0, gam0, om, shift)
+    np.testing.assert_allclose(y, lam * phi, rtol=0, atol=1e-9 * abs(lam))
+
+
+def test_kron_assembly_pinned_by_dst():
+    """The independent sparse assembly used below obeys the same eigenpairs."""
+    n, kap0, gam0 = 12, 0.6, 0.2
+    om = inputs.omega_for_ppw(n)
+    A = pins.helmholtz_matrix(np.full((n, n), kap0), np.full((n, n), gam0), om, 0.5)
+    for k, l in [(1, 2), (5, 5), (12, 3)]:
+        phi = pins.dst_mode(n, k, l)
+        lam = pins.dst_eigenvalue(n, k, l, kap0, gam0, om, 0.5)
+        np.testing.assert_allclose(A @ phi.ravel(), lam * phi.ravel(), atol=1e-9 * abs(lam))
+
+
+@pytest.mark.parametrize("shift", [0.0, 0.5])
+def test_apply_matches_kron_heterogeneous(oracle, shift):
+    n = 24
+    kap, gam, om = hetero(n, 3)
+    x = crandn(n, n)
+    y = oracle.apply(kap, gam, om, x, shift=shift)
+    A = pins.helmholtz_matrix(kap, gam, om, shift)
+    ref = (A @ x.ravel()).reshape(n, n)
+    np.testing.assert_allclose(y, ref, rtol=1e-13, atol=1e-10 * np.abs(ref).max())
+
+
+def test_apply_complex_symmetric_not_hermitian(oracle):
+    """A^T = A (bilinear form symmetric) while A != A^H because of attenuation."""
+    n = 20
+    kap, gam, om = hetero(n, 4)
+    x, y = crandn(n, n), crandn(n, n)
+    Ax = oracle.apply(kap, gam, om, x)
+    Ay = oracle.apply(kap, gam, om, y)
+    lhs, rhs = np.sum(y * Ax), np.sum(x * Ay)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    herm_l, herm_r = np.vdot(y, Ax), np.vdot(Ay, x)
+    assert abs(herm_l - herm_r) > 1e-3 * abs(herm_l)
+
+
+def test_imaginary_part_sign(oracle):
+    """Attenuation enters as +i omega^2 kappa^2 gamma on the diagonal (eq. 2.1)."""
+    n = 8
+    kap = np.full((n, n), 1.0)
+    gam = np.full((n, n), 0.25)
+    om = 3.0
+    e = np.zeros((n, n), complex)
+    e[4, 4] = 1.0
+    y = oracle.apply(kap, gam, om, e)
+    assert y[4, 4].imag == pytest.approx(om ** 2 * 0.25)
+    yM = oracle.apply(kap, gam, om, e, shift=0.5)
+    assert yM[4, 4].imag == pytest.approx(om ** 2 * 0.75)
+
+
+# ---------------------------------------------------------------- transfers
+
+def test_restriction_is_quarter_prolongation_transpose(oracle):
+    """Eq. 2.9: the two fixed kernels differ by 1/4 and are mutual transposes."""
+    n = 16
+    x = crandn(n, n)
+    yc = crandn(n // 2, n // 2)
+    lhs = np.sum(oracle.restrict(x) * yc)
+    rhs = 0.25 * np.sum(x * oracle.prolong(yc))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_transfers_match_1d_kron(oracle):
+    n = 16
+    x = crandn(n, n)
+    R1, P1 = pins.restrict_1d(n // 2), pins.prolong_1d(n // 2)
+    np.testing.assert_allclose(oracle.restrict(x), R1 @ x @ R1.T, atol=1e-14)
+    xc = crandn(n // 2, n // 2)
+    np.testing.assert_allclose(oracle.prolong(xc), P1 @ xc @ P1.T, atol=1e-14)
+
+
+def test_prolongation_exact_on_linear(oracle):
+    """Bilinear interpolation reproduces coarse-linear data away from the far edge."""
+    nc = 8
+    I, J = np.meshgrid(np.arange(nc), np.arange(nc), indexing="ij")
+    ec = 2.0 + 0.5 * I - 1.5 * J + 0.25j * I
+    e = oracle.prolong(ec)
+    i, j = np.meshgrid(np.arange(2 * nc), np.arange(2 * nc), indexing="ij")
+    exact = 2.0 + 0.25 * i - 0.75 * j + 0.125j * i
+    np.testing.assert_allclose(e[: 2 * nc - 1, : 2 * nc - 1], exact[: 2 * nc - 1, : 2 * nc - 1],
+                               atol=1e-13)
+
+
+def test_restriction_exact_on_linear_interior(oracle):
+    n = 16
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    f = 1.0 + 0.3 * i + 0.7j * j
+    fc = oracle.restrict(f)
+    I, J = np.meshgrid(np.arange(n // 2), np.arange(n // 2), indexing="ij")
+    exact = 1.0 + 0.3 * (2 * I) + 0.7j * (2 * J)
+    np.testing.assert_allclose(fc[1:, 1:], exact[1:, 1:], atol=1e-13)
+    np.testing.assert_allclose(oracle.restrict(np.ones((n, n)))[1:, 1:], 1.0, atol=1e-15)
+
+
+def test_injection(oracle):
+    f = RNG.standard_normal((8, 8))
+    np.testing.assert_array_equal(oracle.inject(f), f[::2, ::2])
+
+
+# ---------------------------------------------------------------- smoothing
+
+def test_jacobi_on_eigenmode(oracle):
+    """Two damped Jacobi sweeps on a DST mode with constant coefficients:
+    x1 = w f/d, x2 = x1 + w (1 - lam w/d) f/d (closed form)."""
+    n, kap0, gam0, w = 16, 0.9, 0.1, 0.8
+    om = inputs.omega_for_ppw(n)
+    kap, gam = np.full((n, n), kap0), np.full((n, n), gam0)
+    phi = pins.dst_mode(n, 4, 9)
+    lam = pins.dst_eigenvalue(n, 4, 9, kap0, gam0, om, 0.5)
+    d = 4 * n * n - om ** 2 * kap0 ** 2 * (1 - 1j * (gam0 + 0.5))
+    x1 = oracle.jacobi(kap, gam, om, phi, np.zeros((n, n)), shift=0.5, weight=w)
+    np.testing.assert_allclose(x1, w * phi / d, atol=1e-15)
+    x2 = oracle.jacobi(kap, gam, om, phi, x1, shift=0.5, weight=w)
+    np.testing.assert_allclose(x2, (w + w * (1 - lam * w / d)) * phi / d, atol=1e-14)
+
+
+def test_jacobi_fixed_point(oracle):
+    n = 16
+    kap, gam, om = hetero(n, 5)
+    A = pins.helmholtz_matrix(kap, gam, om)
+    u = crandn(n, n)
+    f = (A @ u.ravel()).reshape(n, n)
+    np.testing.assert_allclose(oracle.jacobi(kap, gam, om, f, u), u, atol=1e-10)
+
+
+# ---------------------------------------------------------------- direct solve
+
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_band_solve_matches_scipy(oracle, n):
+    kap, gam, om = hetero(n, n)
+    M = pins.helmholtz_matrix(kap, gam, om, 0.5)
+    b = crandn(n, n)
+    x = oracle.band_solve(kap, gam, om, b, shift=0.5)
+    ref = spl.spsolve(M, b.ravel()).reshape(n, n)
+    np.testing.assert_allclose(x, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+def test_band_solve_needs_pivoting(oracle):
+    """A zero leading diagonal entry forces a row interchange (pivoted LU)."""
+    n = 8
+    om = 2.0 * n  # 4/h^2 - om^2 kappa^2 = 0 with kappa = 1, gamma = 0 at (0,0)
+    kap = np.full((n, n), 0.5)
+    gam = np.full((n, n), 0.05)
+    kap[0, 0] = 1.0
+    gam[0, 0] = 0.0
+    A = pins.helmholtz_matrix(kap, gam, om)
+    assert abs(A[0, 0]) < 1e-9
+    b = crandn(n, n)
+    x = oracle.band_solve(kap, gam, om, b)
+    np.testing.assert_allclose(A @ x.ravel(), b.ravel(), atol=1e-9 * np.abs(b).max())
+
+
+# ---------------------------------------------------------------- V-cycle
+
+def _dense(A):
+    return A.toarray() if hasattr(A, "toarray") else np.asarray(A)
+
+
+def _vcycle_matrix(kap, gam, om, levels, h, beta=0.5, w=0.8):
+    n = kap.shape[0]
+    M = _dense(pins.helmholtz_matrix(kap, gam, om, beta, h=h))
+    Minv = np.linalg.inv(M)
+    if levels == 1:
+        return Minv
+    nc = n // 2
+    Bc = _vcycle_matrix(kap[::2, ::2], gam[::2, ::2], om, levels - 1, 2 * h, beta, w)
+    R1, P1 = pins.restrict_1d(nc), pins.prolong_1d(nc)
+    R, P = np.kron(R1, R1), np.kron(P1, P1)
+    Id = np.eye(n * n)
+    S = w * np.diag(1.0 / np.diag(M))
+    Es = Id - S @ M
+    E = Es @ (Id - P @ Bc @ R @ M) @ Es
+    return (Id - E) @ Minv
+
+
+@pytest.mark.parametrize("n,levels", [(8, 2), (16, 2), (16, 3)])
+def test_vcycle_equals_error_propagation_form(oracle, n, levels):
+    kap, gam, om = hetero(n, 7)
+    H = oracle.Hierarchy(kap, gam, om, levels)
+    B = _vcycle_matrix(kap.astype(np.float64), gam.astype(np.float64), om, levels, 1.0 / n)
+    f = crandn(n, n)
+    v = H.vcycle(f)
+    ref = (B @ f.ravel()).reshape(n, n)
+    np.testing.assert_allclose(v, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+
+
+def test_vcycle_one_level_is_exact_inverse(oracle):
+    n = 16
+    kap, gam, om = hetero(n, 8)
+    H = oracle.Hierarchy(kap, gam, om, 1)
+    f = crandn(n, n)
+    v = H.vcycle(f)
+    M = pins.helmholtz_matrix(kap, gam, om, 0.5)
+    np.testing.assert_allclose(M @ v.ravel(), f.ravel(), atol=1e-9 * np.abs(f).max())
+
+
+def test_vcycle_linear_and_complex_symmetric(oracle):
+    n = 32
+    kap, gam, om = hetero(n, 9)
+    H = oracle.Hierarchy(kap, gam, om, 3)
+    x, y = crandn(n, n), crandn(n, n)
+    a, b = 0.3 - 1.2j, 2.0 + 0.5j
+    np.testing.assert_allclose(H.vcycle(a * x + b * y), a * H.vcycle(x) + b * H.vcycle(y),
+                               atol=1e-12 * np.abs(H.vcycle(x)).max())
+    lhs, rhs = np.sum(y * H.vcycle(x)), np.sum(x * H.vcycle(y))
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+
+
+def test_hierarchy_injects_coefficients(oracle):
+    n = 32
+    kap, gam, om = hetero(n, 10)
+    H = oracle.Hierarchy(kap, gam, om, 3)
+    n2, k2, g2 = H.level(2)
+    assert n2 == 8
+    np.testing.assert_array_equal(k2, kap.astype(np.float64)[::4, ::4])
+    np.testing.assert_array_equal(g2, gam.astype(np.float64)[::4, ::4])
+
+
+# ---------------------------------------------------------------- FGMRES
+
+def test_fgmres_identity_prec_is_krylov_minimiser(oracle):
+    """With the identity as preconditioner, k FGMRES steps from x0 = 0 give
+    argmin over K_k(A, b) of ||b - A x|| (dense least squares)."""
+    n, k = 12, 7
+    kap, gam, om = hetero(n, 11)
+    H = oracle.Hierarchy(kap, gam, om, 2)
+    A = pins.helmholtz_matrix(kap, gam, om)
+    b = crandn(n, n).ravel()
+    x, st = H.fgmres(b.reshape(n, n), m=20, tol=1e-14, maxit=k, prec=lambda v: v)
+    assert st["iterations"] == k
+    K = np.empty((n * n, k), complex)
+    v = b.copy()
+    for i in range(k):
+        K[:, i] = v
+        v = A @ v
+    Q, _ = np.linalg.qr(K)
+    c, *_ = np.linalg.lstsq(A @ Q, b, rcond=None)
+    ref = Q @ c
+    np.testing.assert_allclose(x.ravel(), ref, rtol=0, atol=1e-8 * np.abs(ref).max())
+
+
+def test_fgmres_exact_prec_one_step(oracle):
+    n = 16
+    kap, gam, om = hetero(n, 12)
+    A = pins.helmholtz_matrix(kap, gam, om)
+    lu = spl.splu(A)
+    H = oracle.Hierarchy(kap, gam, om, 2)
+    b = crandn(n, n)
+    x, st = H.fgmres(b, m=10, tol=1e-10, prec=lambda v: lu.solve(v.ravel()).reshape(n, n))
+    assert st["iterations"] == 1 and st["converged"]
+
+
+def test_fgmres_sl_manufactured_solution(oracle):
+    n = 64
+    kap, gam, om = hetero(n, 13)
+    A = pins.helmholtz_matrix(kap, gam, om)
+    u = crandn(n, n)
+    b = (A @ u.ravel()).reshape(n, n)
+    H = oracle.Hierarchy(kap, gam, om, 3)
+    x, st = H.fgmres(b, m=10, tol=1e-10)
+    assert st["converged"] and st["true_relres"] <= 1e-10
+    r = b.ravel() - A @ x.ravel()
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
+    assert np.linalg.norm(x - u) / np.linalg.norm(u) < 1e-6
+
+
+def test_fgmres_point_source_matches_spsolve(oracle):
+    P = inputs.config_problem("plain128")
+    n = P["n"]
+    H = oracle.Hierarchy(P["kappa"], P["gamma"], P["omega"], P["levels"])
+    x, st = H.fgmres(P["b"][0], m=P["m"], tol=1e-7)
+    assert st["converged"] and st["true_relres"] <= 1e-7
+    A = pins.helmholtz_matrix(P["kappa"], P["gamma"], P["omega"])
+    ref = spl.spsolve(A, P["b"][0].ravel().astype(complex))
+    # ||x - x*|| / ||x*|| <= cond-type factor * tol (factor ~13 measured at 128^2)
+    assert np.linalg.norm(x.ravel() - ref) / np.linalg.norm(ref) < 3e-6
+
+
+def test_fgmres_zero_rhs(oracle):
+    n = 16
+    kap, gam, om = hetero(n, 14)
+    H = oracle.Hierarchy(kap, gam, om, 2)
+    x, st = H.fgmres(np.zeros((n, n)), m=5, tol=1e-7)
+    assert st["converged"] and st["iterations"] == 0 and np.all(x == 0)
+
+
+def test_fgmres_maxit_reports_not_converged(oracle):
+    n = 32
+    kap, gam, om = hetero(n, 15)
+    H = oracle.Hierarchy(kap, gam, om, 2)
+    x, st = H.fgmres(inputs.point_source(n), m=10, tol=1e-12, maxit=3)
+    assert not st["converged"] and st["iterations"] == 3
+
+
+def test_convergence_factor_geometric(oracle):
+    hist = 0.5 ** np.arange(30)
+    rho, T = oracle.convergence_factor(hist)
+    assert T == 20 and rho == pytest.approx(0.5)
