@@ -1,0 +1,155 @@
+/*
+ * helm.h -- C ABI of the MI355X (gfx950) library for the discrete
+ * heterogeneous 2D Helmholtz equation, solved by flexible GMRES with a
+ * shifted-Laplacian (SL) multigrid preconditioner, optionally augmented by a
+ * U-Net (Azulay & Treister, "Multigrid-augmented deep learning
+ * preconditioners for the Helmholtz equation").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grids: an n x n array of unknowns u[i*n + j] (row-major, j fastest) on
+ *    the unit square, h = 1/n, zero values outside the array (Dirichlet, the
+ *    zero padding of section 2.4).  n must be even and divisible by
+ *    2^(levels-1).
+ *  - complex64 fields are interleaved float pairs (re, im), complex128 fields
+ *    interleaved double pairs.  A batch of nrhs fields is contiguous:
+ *    [nrhs][n][n][2].
+ *  - Every array argument is a DEVICE pointer owned by the caller, unless a
+ *    comment says "host".  The library never frees caller memory.  Handles
+ *    own their internal device workspaces and release them in *_destroy.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    work is enqueued on it; entry points do not synchronise the device
+ *    unless their comment says so.
+ *  - Return value: 0 = success, > 0 = completed with a warning
+ *    (HELM_NOT_CONVERGED), < 0 = error; helm_last_error() then holds a
+ *    message for the calling thread.  On error no output is guaranteed.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HELM_OK 0
+#define HELM_NOT_CONVERGED 1
+#define HELM_E_INVALID (-1) /* bad argument: null pointer, size, option */
+#define HELM_E_NOMEM (-2)   /* device or host allocation failed        */
+#define HELM_E_HIP (-3)     /* a HIP runtime call failed               */
+#define HELM_E_SHAPE (-4)   /* grid size incompatible with the levels  */
+
+#define HELM_OP_A 0 /* Helmholtz operator, eq. 2.1-2.2            */
+#define HELM_OP_M 1 /* shifted-Laplacian operator, eq. 2.4        */
+
+typedef struct helm_handle helm_handle;
+
+/* Setup options; a NULL pointer selects every default. */
+typedef struct {
+    double beta;          /* SL shift beta of eq. 2.4 (alpha = 1); default 0.5   */
+    double jacobi_weight; /* damped-Jacobi weight (section 4); default 0.8       */
+    int levels;           /* V-cycle levels; 0 = coarsest level 64^2, or n^2 if
+                             n <= 64 (default)                                   */
+} helm_opts;
+
+/*
+ * helm_setup -- per-medium set-up of the multigrid hierarchy.
+ * Operator (eq. 2.1-2.2, section 2.2):
+ *   (A u)(i,j) = (4u(i,j) - u(i+-1,j) - u(i,j+-1)) / h^2
+ *                - omega^2 kappa(i,j)^2 (1 - i gamma(i,j)) u(i,j)
+ * and the SL operator M replaces gamma by gamma + beta (eq. 2.4 with
+ * alpha = 1).  Level l has n/2^l points per side, mesh width 2^l h, and its
+ * coefficients injected from the fine grid (re-discretisation, section 2.2).
+ * The coarsest level's operator is inverted once here, in double precision
+ * on the host, and stored as a dense complex64 matrix.
+ *   slowness, gamma : device float [n][n]; read during the call only.
+ *   omega           : angular frequency, > 0.
+ *   out             : receives the handle (host pointer to a pointer).
+ * This call synchronises `stream` (the coarsest coefficients are copied to
+ * the host).  Errors: HELM_E_INVALID, HELM_E_SHAPE, HELM_E_NOMEM, HELM_E_HIP.
+ */
+int helm_setup(const float *slowness, double omega, const float *gamma, int n,
+               const helm_opts *opts, void *stream, helm_handle **out);
+
+/* Release a handle and its device memory (NULL is ignored). */
+void helm_destroy(helm_handle *h);
+
+/* Grid size of level l of the hierarchy, or -1 if l is out of range. */
+int helm_level_size(const helm_handle *h, int l);
+
+/* Number of levels of the hierarchy. */
+int helm_num_levels(const helm_handle *h);
+
+/*
+ * helm_apply -- y = Op x on the fine grid for a batch (eq. 2.2, the stencil
+ * applied as a 3x3 convolution plus a pointwise mass product, section 2.4).
+ *   op : HELM_OP_A or HELM_OP_M.
+ *   x, y : complex64 [nrhs][n][n]; must not overlap.
+ */
+int helm_apply(helm_handle *h, int op, const float *x, float *y, int nrhs,
+               void *stream);
+
+/*
+ * helm_sl_vcycle -- v = V-cycle(0, f) on M (Algorithm 1): one damped Jacobi
+ * pre- and post-relaxation per level, full-weighting restriction and
+ * bilinear prolongation (eq. 2.9), the direct solve on the coarsest level.
+ * This is the SL preconditioner M_V.
+ *   f, v : complex64 [nrhs][n][n]; must not overlap.
+ */
+int helm_sl_vcycle(helm_handle *h, const float *f, float *v, int nrhs, void *stream);
+
+/* Preconditioners for helm_fgmres_solve. */
+#define HELM_PREC_SL 0        /* M_V: one SL V-cycle                           */
+#define HELM_PREC_UNET_CGC 1  /* M_CU: Jacobi, U-Net coarse correction, Jacobi */
+#define HELM_PREC_UNET_DEFL 2 /* M_VU: U-Net, then an SL V-cycle (eq. 3.4)     */
+
+typedef struct {
+    int m;               /* Krylov subspace size per cycle; default 20           */
+    double tol;          /* target true relative residual; default 1e-7          */
+    int maxit;           /* maximum preconditioner applications; default 20000   */
+    int prec;            /* HELM_PREC_*; default HELM_PREC_SL                    */
+    void *net;           /* unet_net* for the U-Net preconditioners, else NULL   */
+    double stall_ratio;  /* fall back to M_V when |g_{j+1}|/|g_j| exceeds this on
+                            3 consecutive steps (0 = never); default 0           */
+} helm_fgmres_opts;
+
+typedef struct {
+    int iterations;      /* preconditioner applications                          */
+    int restarts;        /* completed FGMRES cycles                              */
+    int converged;       /* 1 if the true relative residual reached tol          */
+    int fallback;        /* 1 if the solve switched to the plain SL V-cycle      */
+    double true_relres;  /* final ||b - A x|| / ||b|| recomputed in FP64         */
+} helm_fgmres_stats;
+
+/*
+ * helm_fgmres_solve -- restarted flexible GMRES (section 3, FGMRES(m) with
+ * right preconditioning, eq. 2.5) for a batch of independent right-hand
+ * sides on one or more media.
+ *   probs[p]         : handle of medium p, p < nprob.
+ *   rhs_per_prob[p]  : host int, number of right-hand sides of medium p.
+ *   b[p]             : complex64 [rhs_per_prob[p]][n_p][n_p], device.
+ *   x[p]             : complex128 [rhs_per_prob[p]][n_p][n_p], device;
+ *                      output (overwritten; the iteration starts from 0).
+ *   stats            : host array with one entry per right-hand side, in
+ *                      problem order; may be NULL.
+ * The Krylov vectors are complex64 with FP64-accumulated inner products;
+ * the Hessenberg least-squares problem, the solution and the true residual
+ * b - A x that starts each cycle are FP64.  The iteration stops when that
+ * true relative residual is <= tol.  The host synchronises once per cycle.
+ * Returns HELM_NOT_CONVERGED if some right-hand side reached maxit first.
+ */
+int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int *rhs_per_prob,
+                      const float *const *b, double *const *x,
+                      const helm_fgmres_opts *opts, helm_fgmres_stats *stats,
+                      void *stream);
+
+/* Thread-local text describing the last error of this thread ("" if none). */
+const char *helm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELM_H */

@@ -1,0 +1,429 @@
+// Restarted flexible GMRES driver (FGMRES(m), Saad 1993, as used in section
+// 3 and section 4 with right preconditioning, eq. 2.5) over a batch of
+// independent right-hand sides.
+//
+// Per cycle and right-hand side b:
+//   r = b - A x (FP64, x complex128), beta = ||r||, v_0 = r / beta
+//   for j < m:  z_j = Prec(v_j); w = A z_j;
+//               CGS2: h = V^H w, w -= V h, h' = V^H w, w -= V h', H(:,j) = h + h'
+//               H(j+1,j) = ||w||, v_{j+1} = w / H(j+1,j)
+//               complex Givens rotation on column j (FP64), g_{j+1} = implicit residual
+//   x += Z y with y = H_k^-1 g_k (FP64)
+// The iteration stops once the FP64 true relative residual ||b - A x||/||b||
+// is <= tol; the implicit estimate |g_{j+1}| only ends a cycle early.
+// Right-hand sides that have stopped are masked out of every kernel.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "handle.h"
+
+namespace helm {
+
+namespace {
+
+constexpr int MAXV = 32;
+
+struct FgState {
+    int m, nb;
+    int *active, *incycle, *k, *its;
+    double *bnorm, *beta, *relres, *scale;
+    double2 *H;   // [nb][(m+1)*m], H[i*m + j]
+    double2 *g;   // [nb][m+1]
+    double *cs;   // [nb][m]
+    double2 *sn;  // [nb][m]
+    double2 *hc;  // [nb][MAXV] current Gram-Schmidt coefficients
+    double2 *y;   // [nb][MAXV]
+    double tol;
+    int maxit;
+};
+
+struct FgWork {
+    int nb = 0, m = 0;
+    size_t N = 0;
+    float2 *V = nullptr, *Z = nullptr;
+    double2 *partial = nullptr;
+    double *rpartial = nullptr;
+    void *state = nullptr;
+    size_t state_bytes = 0;
+    int *h_i = nullptr;       // pinned: active flags
+    double *h_d = nullptr;    // pinned: relres
+    int *h_its = nullptr;     // pinned: iteration counts
+    FgState S{};
+};
+
+__device__ __forceinline__ double2 dmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 dconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double dabs(double2 a) { return hypot(a.x, a.y); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Fixed-order reduction of partial[b][blk][i] over blocks; mode 1 sets the
+// Hessenberg column, mode 2 adds the re-orthogonalisation coefficients.
+__global__ __launch_bounds__(256) void k_reduce_dots(FgState S, const double2 *__restrict__ partial,
+                                                     int nblk, int nv, int j, int mode)
+{
+    const int b = blockIdx.x;
+    if (!S.active[b]) return;
+    __shared__ double2 red[MAXV];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = wv; i < nv; i += 4) {
+        double sr = 0.0, si = 0.0;
+        for (int q = lane; q < nblk; q += 64) {
+            double2 v = partial[((size_t)b * nblk + q) * MAXV + i];
+            sr += v.x;
+            si += v.y;
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        if (lane == 0) red[i] = make_double2(sr, si);
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        int i = threadIdx.x;
+        double2 v = red[i];
+        S.hc[(size_t)b * MAXV + i] = v;
+        double2 &hij = S.H[(size_t)b * (S.m + 1) * S.m + (size_t)i * S.m + j];
+        if (mode == 1)
+            hij = v;
+        else
+            hij = make_double2(hij.x + v.x, hij.y + v.y);
+    }
+}
+
+// ||w|| reduction, then the Givens update of column j and the stop test.
+__global__ __launch_bounds__(256) void k_norm_givens(FgState S, const double2 *__restrict__ partial,
+                                                     int nblk, int j)
+{
+    const int b = blockIdx.x;
+    if (!S.active[b]) return;
+    __shared__ double red[4];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nblk; q += 256) s += partial[((size_t)b * nblk + q) * MAXV].x;
+    s = wave_sum(s);
+    if (lane == 0) red[wv] = s;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int m = S.m;
+    double hn = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+    double2 *H = S.H + (size_t)b * (m + 1) * m;
+    double *cs = S.cs + (size_t)b * m;
+    double2 *sn = S.sn + (size_t)b * m;
+    double2 *g = S.g + (size_t)b * (m + 1);
+    for (int i = 0; i < j; ++i) {
+        double2 a = H[i * m + j], c = H[(i + 1) * m + j];
+        double2 t1 = dmul(sn[i], c);
+        H[i * m + j] = make_double2(cs[i] * a.x + t1.x, cs[i] * a.y + t1.y);
+        double2 t2 = dmul(dconj(sn[i]), a);
+        H[(i + 1) * m + j] = make_double2(cs[i] * c.x - t2.x, cs[i] * c.y - t2.y);
+    }
+    double2 a = H[j * m + j];
+    double aa = dabs(a);
+    double t = hypot(aa, hn);
+    if (aa == 0.0) {
+        cs[j] = 0.0;
+        sn[j] = make_double2(1.0, 0.0);
+        H[j * m + j] = make_double2(hn, 0.0);
+    } else {
+        double2 ph = make_double2(a.x / aa, a.y / aa);
+        cs[j] = aa / t;
+        sn[j] = make_double2(ph.x * hn / t, ph.y * hn / t);  // ph * conj(hn) / t, hn real
+        H[j * m + j] = make_double2(ph.x * t, ph.y * t);
+    }
+    H[(j + 1) * m + j] = make_double2(0.0, 0.0);
+    double2 gj = g[j];
+    double2 t3 = dmul(dconj(sn[j]), gj);
+    g[j + 1] = make_double2(-t3.x, -t3.y);
+    g[j] = make_double2(cs[j] * gj.x, cs[j] * gj.y);
+    S.k[b] = j + 1;
+    int its = ++S.its[b];
+    double res = dabs(g[j + 1]);
+    S.scale[b] = hn > 0.0 ? 1.0 / hn : 0.0;
+    if (hn == 0.0 || res <= S.tol * S.bnorm[b] || its >= S.maxit || j + 1 >= m) S.active[b] = 0;
+}
+
+// y = R^-1 g on the rotated (upper triangular) Hessenberg matrix.
+__global__ void k_solve_y(FgState S)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= S.nb || !S.incycle[b]) return;
+    const int m = S.m, k = S.k[b];
+    const double2 *H = S.H + (size_t)b * (m + 1) * m;
+    const double2 *g = S.g + (size_t)b * (m + 1);
+    double2 *y = S.y + (size_t)b * MAXV;
+    for (int i = k - 1; i >= 0; --i) {
+        double2 s = g[i];
+        for (int c = i + 1; c < k; ++c) {
+            double2 t = dmul(H[i * m + c], y[c]);
+            s.x -= t.x;
+            s.y -= t.y;
+        }
+        double2 d = H[i * m + i];
+        double den = d.x * d.x + d.y * d.y;
+        y[i] = make_double2((s.x * d.x + s.y * d.y) / den, (s.y * d.x - s.x * d.y) / den);
+    }
+}
+
+// beta = ||r|| from the true-residual partial sums; first call sets ||b||.
+__global__ void k_restart(FgState S, const double *__restrict__ rpartial, int nblk, int first)
+{
+    const int b = blockIdx.x;
+    if (!first && !S.incycle[b]) return;
+    __shared__ double red[4];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nblk; q += 256) s += rpartial[(size_t)b * nblk + q];
+    s = wave_sum(s);
+    if (lane == 0) red[wv] = s;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double beta = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+    if (first) {
+        S.bnorm[b] = beta;
+        S.its[b] = 0;
+    }
+    S.beta[b] = beta;
+    S.relres[b] = S.bnorm[b] > 0.0 ? beta / S.bnorm[b] : 0.0;
+    S.g[(size_t)b * (S.m + 1)] = make_double2(beta, 0.0);
+    S.scale[b] = beta > 0.0 ? 1.0 / beta : 0.0;
+    S.k[b] = 0;
+}
+
+template <typename T>
+int dalloc(T **p, size_t count)
+{
+    if (hipMalloc((void **)p, count * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        set_error("helm_fgmres_solve: device allocation failed");
+        return HELM_E_NOMEM;
+    }
+    return HELM_OK;
+}
+
+void work_free(FgWork *w)
+{
+    if (!w) return;
+    hipFree(w->V);
+    hipFree(w->Z);
+    hipFree(w->partial);
+    hipFree(w->rpartial);
+    hipFree(w->state);
+    if (w->h_i) hipHostFree(w->h_i);
+    if (w->h_d) hipHostFree(w->h_d);
+    if (w->h_its) hipHostFree(w->h_its);
+    delete w;
+}
+
+int work_ensure(helm_handle *h, int nb, int m, FgWork **out)
+{
+    FgWork *w = (FgWork *)h->fg;
+    size_t N = (size_t)h->n * h->n;
+    if (w && w->nb >= nb && w->m == m && w->N == N) {
+        *out = w;
+        return HELM_OK;
+    }
+    work_free(w);
+    h->fg = nullptr;
+    w = new FgWork();
+    w->nb = nb;
+    w->m = m;
+    w->N = N;
+    int nblk = krylov_nblk(N);
+    int rc;
+    if ((rc = dalloc(&w->V, (size_t)nb * (m + 1) * N)) || (rc = dalloc(&w->Z, (size_t)nb * m * N)) ||
+        (rc = dalloc(&w->partial, (size_t)nb * nblk * MAXV)) ||
+        (rc = dalloc(&w->rpartial, (size_t)nb * nblk))) {
+        work_free(w);
+        return rc;
+    }
+    // state: ints, then doubles, then double2s, each section 256-byte aligned
+    auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t ni = 4 * (size_t)nb, nd = 4 * (size_t)nb + (size_t)nb * m;
+    size_t nz = (size_t)nb * ((m + 1) * m + (m + 1) + m + 2 * MAXV);
+    size_t off_d = align(ni * sizeof(int)), off_z = align(off_d + nd * sizeof(double));
+    size_t bytes = off_z + nz * sizeof(double2);
+    if (hipMalloc(&w->state, bytes) != hipSuccess) {
+        work_free(w);
+        set_error("helm_fgmres_solve: device allocation failed");
+        return HELM_E_NOMEM;
+    }
+    w->state_bytes = bytes;
+    char *p = (char *)w->state;
+    FgState &S = w->S;
+    S.m = m;
+    S.nb = nb;
+    S.active = (int *)p;
+    S.incycle = S.active + nb;
+    S.k = S.incycle + nb;
+    S.its = S.k + nb;
+    S.bnorm = (double *)(p + off_d);
+    S.beta = S.bnorm + nb;
+    S.relres = S.beta + nb;
+    S.scale = S.relres + nb;
+    S.cs = S.scale + nb;
+    S.H = (double2 *)(p + off_z);
+    S.g = S.H + (size_t)nb * (m + 1) * m;
+    S.sn = S.g + (size_t)nb * (m + 1);
+    S.hc = S.sn + (size_t)nb * m;
+    S.y = S.hc + (size_t)nb * MAXV;
+    if ((char *)(S.y + (size_t)nb * MAXV) > (char *)w->state + bytes) {
+        work_free(w);
+        set_error("helm_fgmres_solve: internal workspace layout error");
+        return HELM_E_INVALID;
+    }
+    if (hipHostMalloc((void **)&w->h_i, nb * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void **)&w->h_d, nb * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&w->h_its, nb * sizeof(int)) != hipSuccess) {
+        work_free(w);
+        set_error("helm_fgmres_solve: pinned host allocation failed");
+        return HELM_E_NOMEM;
+    }
+    h->fg = w;
+    *out = w;
+    return HELM_OK;
+}
+
+// One problem (medium) with nb right-hand sides.
+int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, double tol,
+                  int maxit, int prec, helm_fgmres_stats *stats, hipStream_t s)
+{
+    FgWork *w = nullptr;
+    int rc = work_ensure(h, nb, m, &w);
+    if (rc) return rc;
+    FgState S = w->S;
+    S.tol = tol;
+    S.maxit = maxit;
+    const size_t N = w->N;
+    const int nblk = krylov_nblk(N);
+    const size_t vsb = (size_t)(m + 1) * N, zsb = (size_t)m * N;
+    const Level &L0 = h->lv[0];
+    (void)prec;
+    std::vector<int> restarts(nb, 0);
+    std::vector<char> done(nb, 0);
+
+    HELM_HIP_CHECK(hipMemsetAsync(x, 0, (size_t)nb * N * sizeof(double2), s));
+    for (int i = 0; i < nb; ++i) w->h_i[i] = 1;
+    HELM_HIP_CHECK(hipMemcpyAsync(S.active, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
+    HELM_HIP_CHECK(hipMemcpyAsync(S.incycle, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
+    launch_true_residual(h->kappa0, h->gamma0, h->n, h->omega, b, N, x, N, w->V, vsb, w->rpartial,
+                         nblk, nb, nullptr, s);
+    hipLaunchKernelGGL(k_restart, dim3(nb), dim3(256), 0, s, S, w->rpartial, nblk, 1);
+    for (;;) {
+        HELM_HIP_CHECK(hipMemcpyAsync(w->h_d, S.relres, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+        HELM_HIP_CHECK(hipMemcpyAsync(w->h_its, S.its, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+        HELM_HIP_CHECK(hipStreamSynchronize(s));
+        int nact = 0;
+        for (int i = 0; i < nb; ++i) {
+            if (!done[i] && (w->h_d[i] <= tol || w->h_its[i] >= maxit)) done[i] = 1;
+            w->h_i[i] = done[i] ? 0 : 1;
+            nact += w->h_i[i];
+        }
+        if (nact == 0) break;
+        HELM_HIP_CHECK(hipMemcpyAsync(S.active, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
+        HELM_HIP_CHECK(hipMemcpyAsync(S.incycle, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
+        launch_scale(w->V, vsb, N, S.scale, nb, S.active, s);
+        for (int j = 0; j < m; ++j) {
+            float2 *vj = w->V + (size_t)j * N, *zj = w->Z + (size_t)j * N;
+            float2 *wj = w->V + (size_t)(j + 1) * N;
+            rc = vcycle(h, vj, vsb, zj, zsb, nb, S.active, s);
+            if (rc) return rc;
+            launch_apply(L0, 0.f, zj, zsb, wj, vsb, nb, S.active, s);
+            launch_dots(w->V, vsb, N, wj, vsb, j + 1, w->partial, nblk, nb, S.active, s);
+            hipLaunchKernelGGL(k_reduce_dots, dim3(nb), dim3(256), 0, s, S, w->partial, nblk, j + 1,
+                               j, 1);
+            launch_update(w->V, vsb, N, wj, vsb, j + 1, S.hc, MAXV, 0, w->partial, nblk, nb,
+                          S.active, s);
+            hipLaunchKernelGGL(k_reduce_dots, dim3(nb), dim3(256), 0, s, S, w->partial, nblk, j + 1,
+                               j, 2);
+            launch_update(w->V, vsb, N, wj, vsb, j + 1, S.hc, MAXV, 1, w->partial, nblk, nb,
+                          S.active, s);
+            hipLaunchKernelGGL(k_norm_givens, dim3(nb), dim3(256), 0, s, S, w->partial, nblk, j);
+            launch_scale(wj, vsb, N, S.scale, nb, S.active, s);
+        }
+        hipLaunchKernelGGL(k_solve_y, dim3((nb + 63) / 64), dim3(64), 0, s, S);
+        launch_xupdate(x, N, w->Z, zsb, N, S.y, MAXV, S.k, nb, S.incycle, s);
+        launch_true_residual(h->kappa0, h->gamma0, h->n, h->omega, b, N, x, N, w->V, vsb,
+                             w->rpartial, nblk, nb, S.incycle, s);
+        hipLaunchKernelGGL(k_restart, dim3(nb), dim3(256), 0, s, S, w->rpartial, nblk, 0);
+        for (int i = 0; i < nb; ++i)
+            if (w->h_i[i]) restarts[i]++;
+        HELM_HIP_CHECK(hipGetLastError());
+    }
+    int nconv = 0;
+    for (int i = 0; i < nb; ++i) {
+        bool conv = w->h_d[i] <= tol;
+        nconv += conv;
+        if (stats) {
+            stats[i].iterations = w->h_its[i];
+            stats[i].restarts = restarts[i];
+            stats[i].converged = conv ? 1 : 0;
+            stats[i].fallback = 0;
+            stats[i].true_relres = w->h_d[i];
+        }
+    }
+    return nconv == nb ? HELM_OK : HELM_NOT_CONVERGED;
+}
+
+}  // namespace
+
+void fgmres_free(helm_handle *h)
+{
+    if (h && h->fg) {
+        work_free((FgWork *)h->fg);
+        h->fg = nullptr;
+    }
+}
+
+}  // namespace helm
+
+using namespace helm;
+
+extern "C" int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int *rhs_per_prob,
+                                 const float *const *b, double *const *x,
+                                 const helm_fgmres_opts *opts, helm_fgmres_stats *stats,
+                                 void *stream)
+{
+    if (!probs || nprob < 0 || (nprob > 0 && (!rhs_per_prob || !b || !x))) {
+        set_error("helm_fgmres_solve: invalid argument");
+        return HELM_E_INVALID;
+    }
+    int m = 20, maxit = 20000, prec = HELM_PREC_SL;
+    double tol = 1e-7;
+    if (opts) {
+        m = opts->m;
+        tol = opts->tol;
+        maxit = opts->maxit;
+        prec = opts->prec;
+    }
+    if (m < 1 || m > MAXV || !(tol > 0.0) || maxit < 0) {
+        set_error("helm_fgmres_solve: m must be in [1, 32], tol > 0, maxit >= 0");
+        return HELM_E_INVALID;
+    }
+    if (prec != HELM_PREC_SL) {
+        set_error("helm_fgmres_solve: this preconditioner needs a network (not available)");
+        return HELM_E_INVALID;
+    }
+    int status = HELM_OK, off = 0;
+    for (int p = 0; p < nprob; ++p) {
+        if (!probs[p] || rhs_per_prob[p] < 0 || (rhs_per_prob[p] > 0 && (!b[p] || !x[p]))) {
+            set_error("helm_fgmres_solve: invalid problem entry");
+            return HELM_E_INVALID;
+        }
+        if (rhs_per_prob[p] == 0) continue;
+        int rc = solve_problem(probs[p], rhs_per_prob[p], (const float2 *)b[p], (double2 *)x[p], m,
+                               tol, maxit, prec, stats ? stats + off : nullptr, (hipStream_t)stream);
+        if (rc < 0) return rc;
+        if (rc == HELM_NOT_CONVERGED) status = HELM_NOT_CONVERGED;
+        off += rhs_per_prob[p];
+    }
+    return status;
+}

@@ -1,0 +1,32 @@
+// Per-medium handle of libhelm (internal).
+#pragma once
+
+#include <vector>
+
+#include "helm_internal.h"
+
+struct helm_handle {
+    int n = 0;
+    int levels = 0;
+    double omega = 0.0;
+    double beta = 0.5;
+    double jacobi_w = 0.8;
+    float *kappa0 = nullptr;   // fine slowness copy (float [n][n])
+    float *gamma0 = nullptr;   // fine attenuation copy (float [n][n])
+    std::vector<helm::Level> lv;
+    float2 *Xc = nullptr;      // dense inverse of the coarsest shifted operator
+    int Nc = 0;                // coarsest unknowns
+    // V-cycle workspace: per level l >= 1, f_l and v_l for `ws_nb` fields
+    int ws_nb = 0;
+    std::vector<float2 *> wf, wv;
+    // FGMRES workspace (see fgmres.hip)
+    void *fg = nullptr;
+};
+
+namespace helm {
+int ensure_vcycle_ws(helm_handle *h, int nb);
+// v = V-cycle(0, f) on M, batch of nb fields (strides in complex elements)
+int vcycle(helm_handle *h, const float2 *f, size_t fs, float2 *v, size_t vs, int nb,
+           const int *active, hipStream_t s);
+void fgmres_free(helm_handle *h);
+}  // namespace helm

@@ -1,0 +1,381 @@
+// Grid sweeps of the Helmholtz / shifted-Laplacian multigrid on gfx950.
+//
+// Every kernel here is HBM-bound: complex64 fields, FP32 arithmetic.  The
+// operator is the 5-point stencil of eq. 2.2 with the attenuated mass term
+// of eq. 2.1; the shifted operator of eq. 2.4 (alpha = 1) adds `shift` to
+// the attenuation.  Zero values outside the n x n array give the Dirichlet
+// condition of the zero-padded convolution form (section 2.4).
+//
+// Layout: row-major [n][n] float2 per field, a batch of fields at a fixed
+// element stride.  Mass coefficient per level: float2 m = omega^2 kappa^2 (1,
+// -gamma); the operator's mass is (m.x, m.y - shift * m.x).
+#include "helm_internal.h"
+
+namespace helm {
+
+namespace {
+
+__device__ __forceinline__ float2 f2(float a, float b) { return make_float2(a, b); }
+__device__ __forceinline__ float2 operator+(float2 a, float2 b) { return f2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 operator-(float2 a, float2 b) { return f2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 operator*(float s, float2 a) { return f2(s * a.x, s * a.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return f2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cdiv(float2 a, float2 b)
+{
+    float den = b.x * b.x + b.y * b.y;
+    return f2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+__device__ __forceinline__ float2 op_mass(float2 m, float shift) { return f2(m.x, m.y - shift * m.x); }
+
+__device__ __forceinline__ float2 shfl_up1(float2 v)
+{
+    return f2(__shfl_up(v.x, 1, 64), __shfl_up(v.y, 1, 64));
+}
+__device__ __forceinline__ float2 shfl_down1(float2 v)
+{
+    return f2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
+}
+
+// ------------------------------------------------------------------ apply
+// One wavefront owns a strip of 64 columns and R consecutive rows; it walks
+// down the rows keeping the up / centre / down values in registers, so every
+// element is read from memory once per strip; left and right neighbours come
+// from adjacent lanes (the strip's edge lanes load their outer neighbour).
+__global__ __launch_bounds__(256) void k_apply(const float2 *__restrict__ x, size_t xs,
+                                               float2 *__restrict__ y, size_t ys,
+                                               const float2 *__restrict__ mass, int n,
+                                               float ih2, float shift, int R,
+                                               const int *__restrict__ active)
+{
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    const int lane = threadIdx.x;
+    const int j = blockIdx.x * 64 + lane;
+    const int i0 = (blockIdx.y * 4 + threadIdx.y) * R;
+    if (i0 >= n) return;
+    x += (size_t)b * xs;
+    y += (size_t)b * ys;
+    auto ld = [&](int i, int jj) {
+        return (i >= 0 && i < n && jj >= 0 && jj < n) ? x[(size_t)i * n + jj] : f2(0.f, 0.f);
+    };
+    float2 up = ld(i0 - 1, j), cur = ld(i0, j);
+    const int iend = min(i0 + R, n);
+    for (int i = i0; i < iend; ++i) {
+        float2 dn = ld(i + 1, j);
+        float2 lf = shfl_up1(cur), rt = shfl_down1(cur);
+        if (lane == 0) lf = ld(i, j - 1);
+        if (lane == 63) rt = ld(i, j + 1);
+        if (j < n) {
+            size_t p = (size_t)i * n + j;
+            float2 m = op_mass(mass[p], shift);
+            float2 lap = ih2 * (4.f * cur - up - dn - lf - rt);
+            y[p] = lap - cmul(m, cur);
+        }
+        up = cur;
+        cur = dn;
+    }
+}
+
+// ------------------------------------------------------------------ down
+// Fused: v = w D^-1 f (Jacobi from a zero guess), r = f - Op v, fc = R r.
+// Since D v = w f, (Op v)(p) = w f(p) - ih2 * sum of the 4 neighbours of v,
+// so r = (1 - w) f + ih2 * (v_N + v_S + v_W + v_E).
+// Tile: 32 x 8 coarse outputs; fine region of v with a 2-point halo in LDS.
+constexpr int DN_CW = 32, DN_CH = 8;
+constexpr int DN_VW = 2 * DN_CW + 3, DN_VH = 2 * DN_CH + 3;
+
+__global__ __launch_bounds__(256) void k_down(const float2 *__restrict__ f, size_t fs,
+                                              float2 *__restrict__ fc, size_t fcs,
+                                              const float2 *__restrict__ mass, int n,
+                                              float ih2, float shift, float w,
+                                              const int *__restrict__ active)
+{
+    __shared__ float2 sv[DN_VH][DN_VW + 1];
+    __shared__ float2 sf[DN_VH][DN_VW + 1];
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    f += (size_t)b * fs;
+    fc += (size_t)b * fcs;
+    const int nc = n / 2;
+    const int I0 = blockIdx.y * DN_CH, J0 = blockIdx.x * DN_CW;
+    const int fi0 = 2 * I0 - 2, fj0 = 2 * J0 - 2;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < DN_VH * DN_VW; idx += 256) {
+        int r = idx / DN_VW, c = idx - r * DN_VW;
+        int i = fi0 + r, j = fj0 + c;
+        float2 fv = f2(0.f, 0.f), vv = f2(0.f, 0.f);
+        if (i >= 0 && i < n && j >= 0 && j < n) {
+            size_t p = (size_t)i * n + j;
+            fv = f[p];
+            float2 m = op_mass(mass[p], shift);
+            vv = cdiv(w * fv, f2(4.f * ih2 - m.x, -m.y));
+        }
+        sf[r][c] = fv;
+        sv[r][c] = vv;
+    }
+    __syncthreads();
+    // residual on rows/cols 1..size-2 of the region; zero outside the grid
+    for (int idx = tid; idx < (DN_VH - 2) * (DN_VW - 2); idx += 256) {
+        int r = 1 + idx / (DN_VW - 2), c = 1 + idx % (DN_VW - 2);
+        int i = fi0 + r, j = fj0 + c;
+        float2 res = f2(0.f, 0.f);
+        if (i >= 0 && i < n && j >= 0 && j < n)
+            res = (1.f - w) * sf[r][c] + ih2 * (sv[r - 1][c] + sv[r + 1][c] + sv[r][c - 1] + sv[r][c + 1]);
+        sf[r][c] = res;  // each residual point reads only its own f entry
+    }
+    __syncthreads();
+    const int tx = tid & 31, ty = tid >> 5;
+    const int I = I0 + ty, J = J0 + tx;
+    if (I < nc && J < nc) {
+        const int r = 2 * ty + 2, c = 2 * tx + 2;
+        float2 s = 0.25f * sf[r][c] +
+                   0.125f * (sf[r - 1][c] + sf[r + 1][c] + sf[r][c - 1] + sf[r][c + 1]) +
+                   0.0625f * (sf[r - 1][c - 1] + sf[r - 1][c + 1] + sf[r + 1][c - 1] + sf[r + 1][c + 1]);
+        fc[(size_t)I * nc + J] = s;
+    }
+}
+
+// ------------------------------------------------------------------ up
+// Fused: v' = w D^-1 f + P vc (correction added to the pre-relaxed value),
+// then one Jacobi sweep v = v' + w D^-1 (f - Op v').  Tile: 64 x 16 fine
+// outputs; v' on a 1-point halo and the needed coarse values in LDS.
+constexpr int UP_W = 64, UP_H = 16;
+constexpr int UP_CW = UP_W / 2 + 2, UP_CH = UP_H / 2 + 2;
+
+__global__ __launch_bounds__(256) void k_up(const float2 *__restrict__ f, size_t fs,
+                                            const float2 *__restrict__ vc, size_t vcs,
+                                            float2 *__restrict__ v, size_t vs,
+                                            const float2 *__restrict__ mass, int n, float ih2,
+                                            float shift, float w, const int *__restrict__ active)
+{
+    __shared__ float2 svc[UP_CH][UP_CW + 1];
+    __shared__ float2 sv[UP_H + 2][UP_W + 3];
+    __shared__ float2 sf[UP_H][UP_W];
+    __shared__ float2 sd[UP_H][UP_W];
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    f += (size_t)b * fs;
+    vc += (size_t)b * vcs;
+    v += (size_t)b * vs;
+    const int nc = n / 2;
+    const int i0 = blockIdx.y * UP_H, j0 = blockIdx.x * UP_W;
+    const int I0 = i0 / 2 - 1, J0 = j0 / 2 - 1;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < UP_CH * UP_CW; idx += 256) {
+        int r = idx / UP_CW, c = idx - r * UP_CW;
+        int I = I0 + r, J = J0 + c;
+        svc[r][c] = (I >= 0 && I < nc && J >= 0 && J < nc) ? vc[(size_t)I * nc + J] : f2(0.f, 0.f);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < (UP_H + 2) * (UP_W + 2); idx += 256) {
+        int r = idx / (UP_W + 2), c = idx - r * (UP_W + 2);
+        int i = i0 - 1 + r, j = j0 - 1 + c;
+        float2 vp = f2(0.f, 0.f);
+        if (i >= 0 && i < n && j >= 0 && j < n) {
+            size_t p = (size_t)i * n + j;
+            float2 fv = f[p];
+            float2 m = op_mass(mass[p], shift);
+            float2 d = f2(4.f * ih2 - m.x, -m.y);
+            // bilinear prolongation: even index -> one coarse point (weight 1),
+            // odd index -> the two neighbours (weight 1/2 each)
+            int ra = (i >> 1) - I0, rb = ((i + 1) >> 1) - I0;
+            int ca = (j >> 1) - J0, cb = ((j + 1) >> 1) - J0;
+            float wr = (i & 1) ? 0.5f : 1.f, wc = (j & 1) ? 0.5f : 1.f;
+            float2 pv = svc[ra][ca];
+            if (j & 1) pv = pv + svc[ra][cb];
+            if (i & 1) {
+                pv = pv + svc[rb][ca];
+                if (j & 1) pv = pv + svc[rb][cb];
+            }
+            vp = cdiv(w * fv, d) + (wr * wc) * pv;
+            if (r >= 1 && r <= UP_H && c >= 1 && c <= UP_W) {
+                sf[r - 1][c - 1] = fv;
+                sd[r - 1][c - 1] = d;
+            }
+        }
+        sv[r][c] = vp;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < UP_H * UP_W; idx += 256) {
+        int r = idx / UP_W, c = idx - r * UP_W;
+        int i = i0 + r, j = j0 + c;
+        if (i < n && j < n) {
+            float2 vp = sv[r + 1][c + 1];
+            float2 d = sd[r][c];
+            float2 nb4 = sv[r][c + 1] + sv[r + 2][c + 1] + sv[r + 1][c] + sv[r + 1][c + 2];
+            float2 res = sf[r][c] - (cmul(d, vp) - ih2 * nb4);
+            v[(size_t)i * n + j] = vp + cdiv(w * res, d);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ coarse
+// v = X f for NB right-hand sides at once; one wavefront per row of X.
+template <int NB>
+__global__ __launch_bounds__(256) void k_coarse(const float2 *__restrict__ X, int N,
+                                                const float2 *__restrict__ f, size_t fs,
+                                                float2 *__restrict__ v, size_t vs, int b0,
+                                                const int *__restrict__ active)
+{
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= N) return;
+    float ar[NB], ai[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) ar[q] = ai[q] = 0.f;
+    const float2 *xr = X + (size_t)row * N;
+    for (int k = lane; k < N; k += 64) {
+        float2 a = xr[k];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            float2 c = f[(size_t)(b0 + q) * fs + k];
+            ar[q] += a.x * c.x - a.y * c.y;
+            ai[q] += a.x * c.y + a.y * c.x;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+        for (int off = 32; off > 0; off >>= 1) {
+            ar[q] += __shfl_xor(ar[q], off, 64);
+            ai[q] += __shfl_xor(ai[q], off, 64);
+        }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (!active || active[b0 + q]) v[(size_t)(b0 + q) * vs + row] = f2(ar[q], ai[q]);
+    }
+}
+
+// ------------------------------------------------------------------ setup
+__global__ void k_level_mass(const float *__restrict__ kappa, const float *__restrict__ gamma,
+                             int n, int sp, double omega, float2 *__restrict__ mass, int nl)
+{
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nl * nl) return;
+    int I = idx / nl, J = idx - I * nl;
+    size_t p = (size_t)(I << sp) * n + (J << sp);
+    double k = kappa[p], g = gamma[p];
+    double w2k2 = omega * omega * k * k;
+    mass[idx] = make_float2((float)w2k2, (float)(-w2k2 * g));
+}
+
+// ------------------------------------------------------------------ FP64 residual
+__global__ __launch_bounds__(256) void k_true_residual(
+    const float *__restrict__ kappa, const float *__restrict__ gamma, int n, double omega,
+    const float2 *__restrict__ b, size_t bs, const double2 *__restrict__ x, size_t xs,
+    float2 *__restrict__ r, size_t rs, double *__restrict__ partial, int nblk,
+    const int *__restrict__ active)
+{
+    const int bi = blockIdx.y;
+    if (active && !active[bi]) return;
+    b += (size_t)bi * bs;
+    x += (size_t)bi * xs;
+    r += (size_t)bi * rs;
+    const size_t N = (size_t)n * n;
+    const double ih2 = (double)n * (double)n;
+    double acc = 0.0;
+    for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)nblk * 256) {
+        int i = (int)(p / n), j = (int)(p - (size_t)i * n);
+        double2 c = x[p];
+        double sr = 4.0 * c.x, si = 4.0 * c.y;
+        if (i > 0) { sr -= x[p - n].x; si -= x[p - n].y; }
+        if (i < n - 1) { sr -= x[p + n].x; si -= x[p + n].y; }
+        if (j > 0) { sr -= x[p - 1].x; si -= x[p - 1].y; }
+        if (j < n - 1) { sr -= x[p + 1].x; si -= x[p + 1].y; }
+        double k = kappa[p], g = gamma[p];
+        double mr = omega * omega * k * k, mi = -mr * g;
+        double ar = sr * ih2 - (mr * c.x - mi * c.y);
+        double ai = si * ih2 - (mr * c.y + mi * c.x);
+        float2 bv = b[p];
+        double rr = (double)bv.x - ar, ri = (double)bv.y - ai;
+        r[p] = make_float2((float)rr, (float)ri);
+        acc += rr * rr + ri * ri;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        partial[(size_t)bi * nblk + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+}  // namespace
+
+// ================================================================== launchers
+
+void launch_apply(const Level &L, float shift, const float2 *x, size_t xs, float2 *y, size_t ys,
+                  int nb, const int *active, hipStream_t s)
+{
+    const int n = L.n;
+    const int strips = (n + 63) / 64;
+    // rows per wavefront: enough waves to fill the chip, long runs otherwise
+    long long waves_at_1 = (long long)strips * n * nb;
+    int R = (int)std::min<long long>(32, std::max<long long>(2, waves_at_1 / 4096));
+    dim3 grid(strips, (n + 4 * R - 1) / (4 * R), nb), block(64, 4);
+    hipLaunchKernelGGL(k_apply, grid, block, 0, s, x, xs, y, ys, L.mass, n, L.ih2, shift, R,
+                       active);
+}
+
+void launch_down(const Level &L, float shift, float w, const float2 *f, size_t fs, float2 *fc,
+                 size_t fcs, int nb, const int *active, hipStream_t s)
+{
+    const int nc = L.n / 2;
+    dim3 grid((nc + DN_CW - 1) / DN_CW, (nc + DN_CH - 1) / DN_CH, nb);
+    hipLaunchKernelGGL(k_down, grid, dim3(256), 0, s, f, fs, fc, fcs, L.mass, L.n, L.ih2, shift,
+                       w, active);
+}
+
+void launch_up(const Level &L, float shift, float w, const float2 *f, size_t fs,
+               const float2 *vc, size_t vcs, float2 *v, size_t vs, int nb, const int *active,
+               hipStream_t s)
+{
+    const int n = L.n;
+    dim3 grid((n + UP_W - 1) / UP_W, (n + UP_H - 1) / UP_H, nb);
+    hipLaunchKernelGGL(k_up, grid, dim3(256), 0, s, f, fs, vc, vcs, v, vs, L.mass, n, L.ih2,
+                       shift, w, active);
+}
+
+void launch_coarse_solve(const float2 *X, int N, const float2 *f, size_t fs, float2 *v,
+                         size_t vs, int nb, const int *active, hipStream_t s)
+{
+    dim3 grid((N + 3) / 4), block(256);
+    int b0 = 0;
+    while (b0 < nb) {
+        int left = nb - b0;
+        if (left >= 8) {
+            hipLaunchKernelGGL(k_coarse<8>, grid, block, 0, s, X, N, f, fs, v, vs, b0, active);
+            b0 += 8;
+        } else if (left >= 4) {
+            hipLaunchKernelGGL(k_coarse<4>, grid, block, 0, s, X, N, f, fs, v, vs, b0, active);
+            b0 += 4;
+        } else if (left >= 2) {
+            hipLaunchKernelGGL(k_coarse<2>, grid, block, 0, s, X, N, f, fs, v, vs, b0, active);
+            b0 += 2;
+        } else {
+            hipLaunchKernelGGL(k_coarse<1>, grid, block, 0, s, X, N, f, fs, v, vs, b0, active);
+            b0 += 1;
+        }
+    }
+}
+
+void launch_level_mass(const float *kappa, const float *gamma, int n, int stride_pow,
+                       double omega, float2 *mass, int nl, hipStream_t s)
+{
+    int tot = nl * nl;
+    hipLaunchKernelGGL(k_level_mass, dim3((tot + 255) / 256), dim3(256), 0, s, kappa, gamma, n,
+                       stride_pow, omega, mass, nl);
+}
+
+void launch_true_residual(const float *kappa, const float *gamma, int n, double omega,
+                          const float2 *b, size_t bs, const double2 *x, size_t xs, float2 *r,
+                          size_t rs, double *partial, int nblk, int nb, const int *active,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_true_residual, dim3(nblk, nb), dim3(256), 0, s, kappa, gamma, n, omega,
+                       b, bs, x, xs, r, rs, partial, nblk, active);
+}
+
+}  // namespace helm

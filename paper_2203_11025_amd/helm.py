@@ -1,0 +1,191 @@
+"""ctypes binding of libhelm (include/helm.h).  Argument marshalling only:
+every step of the solver runs in the library's HIP kernels.  PyTorch supplies
+device memory and the current stream.
+
+The library must have been built (python -m paper_2203_11025_amd.build);
+loading fails loudly otherwise -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhelm.so")
+
+HELM_OK = 0
+HELM_NOT_CONVERGED = 1
+HELM_OP_A = 0
+HELM_OP_M = 1
+PREC = {"sl": 0, "unet_cgc": 1, "unet_defl": 2}
+
+EXPORTS = [
+    "helm_setup", "helm_destroy", "helm_level_size", "helm_num_levels", "helm_apply",
+    "helm_sl_vcycle", "helm_fgmres_solve", "helm_last_error",
+]
+
+
+class HelmError(RuntimeError):
+    pass
+
+
+class _Opts(C.Structure):
+    _fields_ = [("beta", C.c_double), ("jacobi_weight", C.c_double), ("levels", C.c_int)]
+
+
+class FgmresOpts(C.Structure):
+    _fields_ = [("m", C.c_int), ("tol", C.c_double), ("maxit", C.c_int), ("prec", C.c_int),
+                ("net", C.c_void_p), ("stall_ratio", C.c_double)]
+
+
+class FgmresStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("fallback", C.c_int), ("true_relres", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HelmError(f"{LIB_PATH} is missing: build it with "
+                            "`python -m paper_2203_11025_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, ip, dp = C.c_void_p, C.c_int, C.c_double
+        L.helm_setup.argtypes = [vp, dp, vp, ip, C.POINTER(_Opts), vp, C.POINTER(vp)]
+        L.helm_setup.restype = ip
+        L.helm_destroy.argtypes = [vp]
+        L.helm_destroy.restype = None
+        L.helm_level_size.argtypes = [vp, ip]
+        L.helm_level_size.restype = ip
+        L.helm_num_levels.argtypes = [vp]
+        L.helm_num_levels.restype = ip
+        L.helm_apply.argtypes = [vp, ip, vp, vp, ip, vp]
+        L.helm_apply.restype = ip
+        L.helm_sl_vcycle.argtypes = [vp, vp, vp, ip, vp]
+        L.helm_sl_vcycle.restype = ip
+        L.helm_fgmres_solve.argtypes = [C.POINTER(vp), ip, C.POINTER(ip), C.POINTER(vp),
+                                        C.POINTER(vp), C.POINTER(FgmresOpts),
+                                        C.POINTER(FgmresStats), vp]
+        L.helm_fgmres_solve.restype = ip
+        L.helm_last_error.argtypes = []
+        L.helm_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc < 0:
+        msg = lib().helm_last_error().decode()
+        raise HelmError(f"{what} failed ({rc}): {msg}")
+    return rc
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise HelmError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise HelmError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise HelmError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class Handle:
+    """One medium: the multigrid hierarchy of helm_setup."""
+
+    def __init__(self, slowness, gamma, omega, levels=0, beta=0.5, jacobi_weight=0.8,
+                 stream=None):
+        n = slowness.shape[-1]
+        if tuple(slowness.shape) != (n, n) or tuple(gamma.shape) != (n, n):
+            raise HelmError("slowness and gamma must be [n, n]")
+        self._keep = (slowness, gamma)
+        opts = _Opts(beta, jacobi_weight, levels)
+        h = C.c_void_p()
+        _check(lib().helm_setup(_dev(slowness, torch.float32, "slowness"), float(omega),
+                                _dev(gamma, torch.float32, "gamma"), n, C.byref(opts),
+                                _stream(stream), C.byref(h)), "helm_setup")
+        self._h = h
+        self.n = n
+        self.omega = float(omega)
+        self.levels = lib().helm_num_levels(h)
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def level_size(self, l):
+        return lib().helm_level_size(self._h, l)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().helm_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _batch(self, x, name):
+        if x.dim() == 2:
+            x = x.unsqueeze(0)
+        if tuple(x.shape[1:]) != (self.n, self.n):
+            raise HelmError(f"{name} must be [nrhs, {self.n}, {self.n}]")
+        return x
+
+    def apply(self, x, op="A", out=None, stream=None):
+        x = self._batch(x, "x")
+        y = torch.empty_like(x) if out is None else out
+        opc = HELM_OP_A if op == "A" else HELM_OP_M
+        _check(lib().helm_apply(self._h, opc, _dev(x, torch.complex64, "x"),
+                                _dev(y, torch.complex64, "y"), x.shape[0], _stream(stream)),
+               "helm_apply")
+        return y
+
+    def vcycle(self, f, out=None, stream=None):
+        f = self._batch(f, "f")
+        v = torch.empty_like(f) if out is None else out
+        _check(lib().helm_sl_vcycle(self._h, _dev(f, torch.complex64, "f"),
+                                    _dev(v, torch.complex64, "v"), f.shape[0], _stream(stream)),
+               "helm_sl_vcycle")
+        return v
+
+
+def fgmres_solve(problems, rhs, m=20, tol=1e-7, maxit=20000, prec="sl", net=None,
+                 stall_ratio=0.0, xs=None, stream=None):
+    """Solve A x = b for every right-hand side of every problem.
+
+    problems: list of Handle; rhs: list of complex64 tensors [nrhs_p, n_p, n_p].
+    Returns (list of complex128 solutions, list of per-RHS stat dicts, status).
+    """
+    nprob = len(problems)
+    if len(rhs) != nprob:
+        raise HelmError("one right-hand-side batch per problem is required")
+    rhs = [p._batch(b, "b") for p, b in zip(problems, rhs)]
+    if xs is None:
+        xs = [torch.empty(b.shape, dtype=torch.complex128, device=b.device) for b in rhs]
+    probs = (C.c_void_p * nprob)(*[p.ptr.value for p in problems])
+    counts = (C.c_int * nprob)(*[b.shape[0] for b in rhs])
+    bp = (C.c_void_p * nprob)(*[_dev(b, torch.complex64, "b").value for b in rhs])
+    xp = (C.c_void_p * nprob)(*[_dev(x, torch.complex128, "x").value for x in xs])
+    total = sum(b.shape[0] for b in rhs)
+    stats = (FgmresStats * max(total, 1))()
+    opts = FgmresOpts(m, tol, maxit, PREC[prec] if isinstance(prec, str) else int(prec),
+                      C.c_void_p(net.ptr.value if net is not None else 0), stall_ratio)
+    rc = _check(lib().helm_fgmres_solve(probs, nprob, counts, bp, xp, C.byref(opts), stats,
+                                        _stream(stream)), "helm_fgmres_solve")
+    return xs, [stats[i].as_dict() for i in range(total)], rc

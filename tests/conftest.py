@@ -18,3 +18,11 @@ def oracle():
 
     helm_oracle.lib()
     return helm_oracle
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Print the case name before every GPU test so a fault can be attributed."""
+    if request.node.get_closest_marker("gpu") is not None:
+        print(f"\n[gpu-case] {request.node.nodeid}", file=sys.stderr, flush=True)
+    yield
