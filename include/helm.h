@@ -145,6 +145,22 @@ int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int *rhs_per_p
                       const helm_fgmres_opts *opts, helm_fgmres_stats *stats,
                       void *stream);
 
+/*
+ * Kernel timing hook (measurement support, not part of the method).  While
+ * active, the library records a HIP event pair on the launch stream around
+ * every launch of one kernel family; helm_profile_stop synchronises on those
+ * events and returns the summed device time and the number of launches.
+ * The hook is process-wide; concurrent solves on several threads share it.
+ */
+#define HELM_PROF_NONE 0
+#define HELM_PROF_COARSE 1 /* dense coarsest-level solve (one per V-cycle)   */
+#define HELM_PROF_DOWN 2   /* fused pre-smooth + residual + restriction      */
+#define HELM_PROF_UP 3     /* fused prolongation + post-smooth               */
+#define HELM_PROF_CGS 4    /* the three Gram-Schmidt passes of an Arnoldi step */
+#define HELM_PROF_APPLY 5  /* stencil apply                                   */
+int helm_profile_start(int family);
+int helm_profile_stop(double *total_ms, long long *launches);
+
 /* Thread-local text describing the last error of this thread ("" if none). */
 const char *helm_last_error(void);
 

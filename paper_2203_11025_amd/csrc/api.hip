@@ -159,11 +159,11 @@ int ensure_vcycle_ws(helm_handle *h, int nb)
 }
 
 int vcycle(helm_handle *h, const float2 *f, size_t fs, float2 *v, size_t vs, int nb,
-           const int *active, hipStream_t s)
+           const int *active, hipStream_t s, const double *scale)
 {
     const int L = h->levels;
     if (L == 1) {
-        launch_coarse_solve(h->Xc, h->Nc, f, fs, v, vs, nb, active, s);
+        launch_coarse_solve(h->Xc, h->Nc, f, fs, v, vs, nb, active, s, scale);
         return HELM_OK;
     }
     int rc = ensure_vcycle_ws(h, nb);
@@ -174,7 +174,8 @@ int vcycle(helm_handle *h, const float2 *f, size_t fs, float2 *v, size_t vs, int
         const float2 *src = l == 0 ? f : h->wf[l];
         size_t ss = l == 0 ? fs : (size_t)h->lv[l].n * h->lv[l].n;
         size_t ds = (size_t)h->lv[l + 1].n * h->lv[l + 1].n;
-        launch_down(h->lv[l], sh, w, src, ss, h->wf[l + 1], ds, nb, active, s);
+        launch_down(h->lv[l], sh, w, src, ss, h->wf[l + 1], ds, nb, active, s,
+                    l == 0 ? scale : nullptr);
     }
     size_t Nc = (size_t)h->Nc;
     launch_coarse_solve(h->Xc, h->Nc, h->wf[L - 1], Nc, h->wv[L - 1], Nc, nb, active, s);
@@ -186,7 +187,8 @@ int vcycle(helm_handle *h, const float2 *f, size_t fs, float2 *v, size_t vs, int
         size_t ss = l == 0 ? fs : Nl;
         float2 *dst = l == 0 ? v : h->wv[l];
         size_t dstr = l == 0 ? vs : Nl;
-        launch_up(h->lv[l], sh, w, src, ss, h->wv[l + 1], Nn, dst, dstr, nb, active, s);
+        launch_up(h->lv[l], sh, w, src, ss, h->wv[l + 1], Nn, dst, dstr, nb, active, s,
+                  l == 0 ? scale : nullptr);
     }
     return HELM_OK;
 }

@@ -23,22 +23,6 @@ namespace helm {
 
 namespace {
 
-constexpr int MAXV = 32;
-
-struct FgState {
-    int m, nb;
-    int *active, *incycle, *k, *its;
-    double *bnorm, *beta, *relres, *scale;
-    double2 *H;   // [nb][(m+1)*m], H[i*m + j]
-    double2 *g;   // [nb][m+1]
-    double *cs;   // [nb][m]
-    double2 *sn;  // [nb][m]
-    double2 *hc;  // [nb][MAXV] current Gram-Schmidt coefficients
-    double2 *y;   // [nb][MAXV]
-    double tol;
-    int maxit;
-};
-
 struct FgWork {
     int nb = 0, m = 0;
     size_t N = 0;
@@ -66,111 +50,41 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Fixed-order reduction of partial[b][blk][i] over blocks; mode 1 sets the
-// Hessenberg column, mode 2 adds the re-orthogonalisation coefficients.
-__global__ __launch_bounds__(256) void k_reduce_dots(FgState S, const double2 *__restrict__ partial,
-                                                     int nblk, int nv, int j, int mode)
+// y = R^-1 g on the rotated (upper triangular) Hessenberg matrix: one
+// wavefront per right-hand side, lane t owns row t; column-oriented back
+// substitution with the pivot value broadcast from its lane.
+__global__ __launch_bounds__(64) void k_solve_y(FgState S)
 {
     const int b = blockIdx.x;
-    if (!S.active[b]) return;
-    __shared__ double2 red[MAXV];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = wv; i < nv; i += 4) {
-        double sr = 0.0, si = 0.0;
-        for (int q = lane; q < nblk; q += 64) {
-            double2 v = partial[((size_t)b * nblk + q) * MAXV + i];
-            sr += v.x;
-            si += v.y;
-        }
-        sr = wave_sum(sr);
-        si = wave_sum(si);
-        if (lane == 0) red[i] = make_double2(sr, si);
-    }
-    __syncthreads();
-    if (threadIdx.x < nv) {
-        int i = threadIdx.x;
-        double2 v = red[i];
-        S.hc[(size_t)b * MAXV + i] = v;
-        double2 &hij = S.H[(size_t)b * (S.m + 1) * S.m + (size_t)i * S.m + j];
-        if (mode == 1)
-            hij = v;
-        else
-            hij = make_double2(hij.x + v.x, hij.y + v.y);
-    }
-}
-
-// ||w|| reduction, then the Givens update of column j and the stop test.
-__global__ __launch_bounds__(256) void k_norm_givens(FgState S, const double2 *__restrict__ partial,
-                                                     int nblk, int j)
-{
-    const int b = blockIdx.x;
-    if (!S.active[b]) return;
-    __shared__ double red[4];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double s = 0.0;
-    for (int q = threadIdx.x; q < nblk; q += 256) s += partial[((size_t)b * nblk + q) * MAXV].x;
-    s = wave_sum(s);
-    if (lane == 0) red[wv] = s;
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    const int m = S.m;
-    double hn = sqrt((red[0] + red[1]) + (red[2] + red[3]));
-    double2 *H = S.H + (size_t)b * (m + 1) * m;
-    double *cs = S.cs + (size_t)b * m;
-    double2 *sn = S.sn + (size_t)b * m;
-    double2 *g = S.g + (size_t)b * (m + 1);
-    for (int i = 0; i < j; ++i) {
-        double2 a = H[i * m + j], c = H[(i + 1) * m + j];
-        double2 t1 = dmul(sn[i], c);
-        H[i * m + j] = make_double2(cs[i] * a.x + t1.x, cs[i] * a.y + t1.y);
-        double2 t2 = dmul(dconj(sn[i]), a);
-        H[(i + 1) * m + j] = make_double2(cs[i] * c.x - t2.x, cs[i] * c.y - t2.y);
-    }
-    double2 a = H[j * m + j];
-    double aa = dabs(a);
-    double t = hypot(aa, hn);
-    if (aa == 0.0) {
-        cs[j] = 0.0;
-        sn[j] = make_double2(1.0, 0.0);
-        H[j * m + j] = make_double2(hn, 0.0);
-    } else {
-        double2 ph = make_double2(a.x / aa, a.y / aa);
-        cs[j] = aa / t;
-        sn[j] = make_double2(ph.x * hn / t, ph.y * hn / t);  // ph * conj(hn) / t, hn real
-        H[j * m + j] = make_double2(ph.x * t, ph.y * t);
-    }
-    H[(j + 1) * m + j] = make_double2(0.0, 0.0);
-    double2 gj = g[j];
-    double2 t3 = dmul(dconj(sn[j]), gj);
-    g[j + 1] = make_double2(-t3.x, -t3.y);
-    g[j] = make_double2(cs[j] * gj.x, cs[j] * gj.y);
-    S.k[b] = j + 1;
-    int its = ++S.its[b];
-    double res = dabs(g[j + 1]);
-    S.scale[b] = hn > 0.0 ? 1.0 / hn : 0.0;
-    if (hn == 0.0 || res <= S.tol * S.bnorm[b] || its >= S.maxit || j + 1 >= m) S.active[b] = 0;
-}
-
-// y = R^-1 g on the rotated (upper triangular) Hessenberg matrix.
-__global__ void k_solve_y(FgState S)
-{
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= S.nb || !S.incycle[b]) return;
-    const int m = S.m, k = S.k[b];
+    if (!S.incycle[b]) return;
+    const int m = S.m, k = S.k[b], t = threadIdx.x;
     const double2 *H = S.H + (size_t)b * (m + 1) * m;
-    const double2 *g = S.g + (size_t)b * (m + 1);
-    double2 *y = S.y + (size_t)b * MAXV;
-    for (int i = k - 1; i >= 0; --i) {
-        double2 s = g[i];
-        for (int c = i + 1; c < k; ++c) {
-            double2 t = dmul(H[i * m + c], y[c]);
-            s.x -= t.x;
-            s.y -= t.y;
+    double2 hrow[MAXV];
+    double2 s = make_double2(0.0, 0.0);
+    if (t < k) s = S.g[(size_t)b * (m + 1) + t];
+#pragma unroll
+    for (int c = 0; c < MAXV; ++c)
+        hrow[c] = (t < k && c < k) ? H[t * m + c] : make_double2(0.0, 0.0);
+    double2 yv = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = MAXV - 1; i >= 0; --i) {
+        if (i < k) {
+            double2 mine = make_double2(0.0, 0.0);
+            if (t == i) {
+                double2 d = hrow[i];
+                double den = d.x * d.x + d.y * d.y;
+                mine = make_double2((s.x * d.x + s.y * d.y) / den, (s.y * d.x - s.x * d.y) / den);
+                yv = mine;
+            }
+            double2 yi = make_double2(__shfl(mine.x, i, 64), __shfl(mine.y, i, 64));
+            if (t < i) {
+                double2 q = dmul(hrow[i], yi);
+                s.x -= q.x;
+                s.y -= q.y;
+            }
         }
-        double2 d = H[i * m + i];
-        double den = d.x * d.x + d.y * d.y;
-        y[i] = make_double2((s.x * d.x + s.y * d.y) / den, (s.y * d.x - s.x * d.y) / den);
     }
+    if (t < k) S.y[(size_t)b * MAXV + t] = yv;
 }
 
 // beta = ||r|| from the true-residual partial sums; first call sets ||b||.
@@ -240,15 +154,15 @@ int work_ensure(helm_handle *h, int nb, int m, FgWork **out)
     int nblk = krylov_nblk(N);
     int rc;
     if ((rc = dalloc(&w->V, (size_t)nb * (m + 1) * N)) || (rc = dalloc(&w->Z, (size_t)nb * m * N)) ||
-        (rc = dalloc(&w->partial, (size_t)nb * nblk * MAXV)) ||
+        (rc = dalloc(&w->partial, (size_t)nb * nblk * MAXP)) ||
         (rc = dalloc(&w->rpartial, (size_t)nb * nblk))) {
         work_free(w);
         return rc;
     }
     // state: ints, then doubles, then double2s, each section 256-byte aligned
     auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    size_t ni = 4 * (size_t)nb, nd = 4 * (size_t)nb + (size_t)nb * m;
-    size_t nz = (size_t)nb * ((m + 1) * m + (m + 1) + m + 2 * MAXV);
+    size_t ni = 4 * (size_t)nb, nd = 5 * (size_t)nb + (size_t)nb * m;
+    size_t nz = (size_t)nb * ((m + 1) * m + (m + 1) + m + 3 * MAXV);
     size_t off_d = align(ni * sizeof(int)), off_z = align(off_d + nd * sizeof(double));
     size_t bytes = off_z + nz * sizeof(double2);
     if (hipMalloc(&w->state, bytes) != hipSuccess) {
@@ -269,16 +183,23 @@ int work_ensure(helm_handle *h, int nb, int m, FgWork **out)
     S.beta = S.bnorm + nb;
     S.relres = S.beta + nb;
     S.scale = S.relres + nb;
-    S.cs = S.scale + nb;
+    S.nu = S.scale + nb;
+    S.cs = S.nu + nb;
     S.H = (double2 *)(p + off_z);
     S.g = S.H + (size_t)nb * (m + 1) * m;
     S.sn = S.g + (size_t)nb * (m + 1);
     S.hc = S.sn + (size_t)nb * m;
-    S.y = S.hc + (size_t)nb * MAXV;
+    S.ac = S.hc + (size_t)nb * MAXV;
+    S.y = S.ac + (size_t)nb * MAXV;
     if ((char *)(S.y + (size_t)nb * MAXV) > (char *)w->state + bytes) {
         work_free(w);
         set_error("helm_fgmres_solve: internal workspace layout error");
         return HELM_E_INVALID;
+    }
+    if (hipMemset(w->state, 0, bytes) != hipSuccess) {
+        work_free(w);
+        set_error("helm_fgmres_solve: clearing the solver state failed");
+        return HELM_E_HIP;
     }
     if (hipHostMalloc((void **)&w->h_i, nb * sizeof(int)) != hipSuccess ||
         hipHostMalloc((void **)&w->h_d, nb * sizeof(double)) != hipSuccess ||
@@ -330,26 +251,17 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
         if (nact == 0) break;
         HELM_HIP_CHECK(hipMemcpyAsync(S.active, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
         HELM_HIP_CHECK(hipMemcpyAsync(S.incycle, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
-        launch_scale(w->V, vsb, N, S.scale, nb, S.active, s);
         for (int j = 0; j < m; ++j) {
             float2 *vj = w->V + (size_t)j * N, *zj = w->Z + (size_t)j * N;
             float2 *wj = w->V + (size_t)(j + 1) * N;
-            rc = vcycle(h, vj, vsb, zj, zsb, nb, S.active, s);
+            // slot j holds the candidate direction, unnormalised; the V-cycle
+            // reads it scaled by 1 / (its norm)
+            rc = vcycle(h, vj, vsb, zj, zsb, nb, S.active, s, S.scale);
             if (rc) return rc;
             launch_apply(L0, 0.f, zj, zsb, wj, vsb, nb, S.active, s);
-            launch_dots(w->V, vsb, N, wj, vsb, j + 1, w->partial, nblk, nb, S.active, s);
-            hipLaunchKernelGGL(k_reduce_dots, dim3(nb), dim3(256), 0, s, S, w->partial, nblk, j + 1,
-                               j, 1);
-            launch_update(w->V, vsb, N, wj, vsb, j + 1, S.hc, MAXV, 0, w->partial, nblk, nb,
-                          S.active, s);
-            hipLaunchKernelGGL(k_reduce_dots, dim3(nb), dim3(256), 0, s, S, w->partial, nblk, j + 1,
-                               j, 2);
-            launch_update(w->V, vsb, N, wj, vsb, j + 1, S.hc, MAXV, 1, w->partial, nblk, nb,
-                          S.active, s);
-            hipLaunchKernelGGL(k_norm_givens, dim3(nb), dim3(256), 0, s, S, w->partial, nblk, j);
-            launch_scale(wj, vsb, N, S.scale, nb, S.active, s);
+            launch_arnoldi_step(S, w->V, vsb, N, j, w->partial, nblk, s);
         }
-        hipLaunchKernelGGL(k_solve_y, dim3((nb + 63) / 64), dim3(64), 0, s, S);
+        hipLaunchKernelGGL(k_solve_y, dim3(nb), dim3(64), 0, s, S);
         launch_xupdate(x, N, w->Z, zsb, N, S.y, MAXV, S.k, nb, S.incycle, s);
         launch_true_residual(h->kappa0, h->gamma0, h->n, h->omega, b, N, x, N, w->V, vsb,
                              w->rpartial, nblk, nb, S.incycle, s);
@@ -404,8 +316,8 @@ extern "C" int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int
         maxit = opts->maxit;
         prec = opts->prec;
     }
-    if (m < 1 || m > MAXV || !(tol > 0.0) || maxit < 0) {
-        set_error("helm_fgmres_solve: m must be in [1, 32], tol > 0, maxit >= 0");
+    if (m < 1 || m > MAXM || !(tol > 0.0) || maxit < 0) {
+        set_error("helm_fgmres_solve: m must be in [1, 30], tol > 0, maxit >= 0");
         return HELM_E_INVALID;
     }
     if (prec != HELM_PREC_SL) {

@@ -13,6 +13,8 @@
 namespace helm {
 
 void set_error(const std::string &msg);
+// Timing hook (prof.hip): event on stream s at the start/end of a family's launch.
+void prof_mark(int family, hipStream_t s, bool start);
 
 #define HELM_HIP_CHECK(call)                                                        \
     do {                                                                            \
@@ -39,18 +41,23 @@ void launch_apply(const Level &L, float shift, const float2 *x, size_t xs, float
 
 // Fused pre-relaxation from zero + residual + full-weighting restriction:
 //   v = w D^-1 f,  fc = R (f - Op v)
+// With `scale` (per batch entry, may be null) the input is read as scale[b] * f.
 void launch_down(const Level &L, float shift, float w, const float2 *f, size_t fs,
-                 float2 *fc, size_t fcs, int nb, const int *active, hipStream_t s);
+                 float2 *fc, size_t fcs, int nb, const int *active, hipStream_t s,
+                 const double *scale = nullptr);
 
 // Fused prolongation + correction + post-relaxation:
 //   v' = w D^-1 f + P vc,  v = v' + w D^-1 (f - Op v')
+// `scale` as for launch_down.
 void launch_up(const Level &L, float shift, float w, const float2 *f, size_t fs,
                const float2 *vc, size_t vcs, float2 *v, size_t vs, int nb,
-               const int *active, hipStream_t s);
+               const int *active, hipStream_t s, const double *scale = nullptr);
 
 // v = X f with the dense coarsest-level inverse X (N x N complex64, row-major).
+// `scale` as for launch_down.
 void launch_coarse_solve(const float2 *X, int N, const float2 *f, size_t fs, float2 *v,
-                         size_t vs, int nb, const int *active, hipStream_t s);
+                         size_t vs, int nb, const int *active, hipStream_t s,
+                         const double *scale = nullptr);
 
 // Level-l coefficients by injection from the fine fields, computed in double
 // and rounded once: mass = omega^2 kappa^2 (1 - i gamma) at (2^l I, 2^l J).
@@ -65,17 +72,34 @@ void launch_true_residual(const float *kappa, const float *gamma, int n, double 
                           const int *active, hipStream_t s);
 
 // ---------------------------------------------------------------- krylov
+constexpr int MAXM = 30;              // largest Krylov subspace per cycle
+constexpr int MAXV = 32;              // per-right-hand-side coefficient storage
+constexpr int MAXP = 2 * MAXM + 4;    // partial sums per block of an Arnoldi pass
+
+// Per-right-hand-side FGMRES state in device memory (struct of arrays).
+struct FgState {
+    int m, nb;
+    int *active, *incycle, *k, *its;
+    double *bnorm, *beta, *relres, *scale, *nu;
+    double2 *H;   // [nb][(m+1)*m], H[i*m + j]
+    double2 *g;   // [nb][m+1]
+    double *cs;   // [nb][m]
+    double2 *sn;  // [nb][m]
+    double2 *hc;  // [nb][MAXV] projection coefficients of the current step
+    double2 *ac;  // [nb][MAXV] delayed re-orthogonalisation coefficients
+    double2 *y;   // [nb][MAXV]
+    double tol;
+    int maxit;
+};
+
 int krylov_nblk(size_t N);
 
-// partial[b][blk][i] = sum over the block's points of conj(V_i) w, i < nv.
-void launch_dots(const float2 *V, size_t vstride_b, size_t N, const float2 *w,
-                 size_t ws, int nv, double2 *partial, int nblk, int nb, const int *active,
-                 hipStream_t s);
-// w -= sum_i h_i V_i (h from hcoef[b][i]); then partial dots conj(V_i) w (mode 0)
-// or partial |w|^2 (mode 1).
-void launch_update(const float2 *V, size_t vstride_b, size_t N, float2 *w, size_t ws,
-                   int nv, const double2 *hcoef, int hstride, int mode, double2 *partial,
-                   int nblk, int nb, const int *active, hipStream_t s);
+// One Arnoldi step j (delayed CGS2): pass A (inner products), reduction with
+// the Givens update of Hessenberg column j and the stop test, pass B (final
+// v_j and the next candidate).  V[b] holds m+1 vectors of N points; slot j
+// holds the candidate, slot j+1 holds w = A z_j.
+void launch_arnoldi_step(const FgState &S, float2 *V, size_t vsb, size_t N, int j,
+                         double2 *partial, int nblk, hipStream_t s);
 void launch_scale(float2 *w, size_t ws, size_t N, const double *scale, int nb,
                   const int *active, hipStream_t s);
 void launch_xupdate(double2 *x, size_t xs, const float2 *Z, size_t zstride_b, size_t N,

@@ -1,32 +1,60 @@
-// Arnoldi (classical Gram-Schmidt with one re-orthogonalisation, CGS2)
-// kernels of the flexible GMRES driver.  Vectors are complex64; every inner
-// product accumulates in FP64 (each complex64 product is exact in FP64), and
-// the reductions are two-stage with a fixed order, so results are
-// bit-reproducible run to run.  The FGMRES iteration itself follows Saad's
-// flexible GMRES with right preconditioning (section 3, eq. 2.5).
+// Arnoldi kernels of the flexible GMRES driver.
+//
+// Orthogonalisation is classical Gram-Schmidt with one re-orthogonalisation
+// whose second pass is delayed by one step and merged with the projection of
+// the next vector (the "delayed CGS2" low-synchronisation scheme of
+// Swirydowicz, Langou, Ananthan, Yang and Thomas, 2020).  Step j keeps
+// V_0..V_{j-1} final and slot j holding the candidate u (orthogonalised once,
+// norm nu).  With w = A z_j:
+//   pass A (one read of V_0..V_{j-1}, u, w), one fixed-order reduction:
+//       a = V^H u,  c = V^H w,  alpha = u^H u,  beta = u^H w,  gw = w^H w
+//   reduction (one block per right-hand side):
+//       nu'^2 = alpha - |a|^2,  v_j = (u - V a) / nu'
+//       h_i = c_i (i < j),  h_j = (beta - a^H c) / nu',
+//       h_{j+1,j}^2 = gw - |c|^2 - |h_j|^2,  then the Givens update of column j
+//   pass B (one read of V_0..V_{j-1}, u, w): writes v_j to slot j and the new
+//       candidate u' = w - sum_{i<=j} h_i v_i to slot j+1.
+// The preconditioner is applied to u / nu, which differs from the final v_j
+// only by the delayed re-orthogonalisation; flexible GMRES allows any
+// preconditioned direction z_j, and the Arnoldi relation A Z = V H holds for
+// the final basis.
+//
+// Vectors are complex64; every inner product accumulates in FP64 (each
+// complex64 product is exact in FP64) and is reduced in a fixed order, so
+// results are bit-reproducible.  Hessenberg column, Givens rotations and the
+// implicit residual are FP64 (section 3: FGMRES with right preconditioning,
+// eq. 2.5).
 #include "helm_internal.h"
 
 namespace helm {
 
 namespace {
 
-constexpr int MAXV = 32;  // largest Krylov subspace per cycle
-
 __device__ __forceinline__ double wave_sum(double v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
-
-// Block-level (256 threads) sum of NV complex accumulators, thread i < NV
-// writes partial i.
-template <int NV>
-__device__ __forceinline__ void block_store(double (&ar)[NV], double (&ai)[NV], double2 *out)
+__device__ __forceinline__ double2 dmul(double2 a, double2 b)
 {
-    __shared__ double sr[4][NV], si[4][NV];
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 dconj(double2 a) { return make_double2(a.x, -a.y); }
+// conj(a) * b
+__device__ __forceinline__ double2 cdot(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// Block-level (256 threads) sum of NP complex accumulators; entry i is
+// written by thread i.
+template <int NP>
+__device__ __forceinline__ void block_store(double (&ar)[NP], double (&ai)[NP], double2 *out)
+{
+    __shared__ double sr[4][NP], si[4][NP];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
+    for (int i = 0; i < NP; ++i) {
         double a = wave_sum(ar[i]), c = wave_sum(ai[i]);
         if (lane == 0) {
             sr[wv][i] = a;
@@ -34,106 +62,259 @@ __device__ __forceinline__ void block_store(double (&ar)[NV], double (&ai)[NV], 
         }
     }
     __syncthreads();
-    if (threadIdx.x < NV) {
-        int i = threadIdx.x;
+    for (int i = threadIdx.x; i < NP; i += 256)
         out[i] = make_double2((sr[0][i] + sr[1][i]) + (sr[2][i] + sr[3][i]),
                               (si[0][i] + si[1][i]) + (si[2][i] + si[3][i]));
-    }
 }
 
-// partial[b][blk][i] = sum_p conj(V_i[p]) w[p]
-template <int NV>
-__global__ __launch_bounds__(256) void k_dots(const float2 *__restrict__ V, size_t vsb,
-                                              size_t N, const float2 *__restrict__ w,
-                                              size_t ws, double2 *__restrict__ partial,
-                                              int nblk, const int *__restrict__ active)
+// Pass A of step J: partial sums of a_i = <v_i, u>, c_i = <v_i, w> (i < J),
+// alpha = <u, u>, beta = <u, w>, gw = <w, w>, stored as
+// [a_0..a_{J-1}, c_0..c_{J-1}, alpha, beta, gw].
+template <int J>
+__global__ __launch_bounds__(256) void k_arnoldi_a(FgState S, const float2 *__restrict__ V,
+                                                   size_t vsb, size_t N,
+                                                   double2 *__restrict__ partial, int nblk)
 {
+    constexpr int NP = 2 * J + 3;
+    constexpr int JV = J > 0 ? J : 1;
     const int b = blockIdx.y;
-    if (active && !active[b]) return;
-    V += (size_t)b * vsb;
-    w += (size_t)b * ws;
-    double ar[NV], ai[NV];
+    if (!S.active[b]) return;
+    const float2 *Vb = V + (size_t)b * vsb;
+    const float2 *u = Vb + (size_t)J * N;
+    const float2 *w = Vb + (size_t)(J + 1) * N;
+    constexpr int U = J <= 12 ? 2 : 1;  // points per thread per step (register budget)
+    double ar[NP], ai[NP];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) ar[i] = ai[i] = 0.0;
-    for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)nblk * 256) {
-        float2 c = w[p];
-        double cx = c.x, cy = c.y;
+    for (int i = 0; i < NP; ++i) ar[i] = ai[i] = 0.0;
+    for (size_t p0 = (size_t)blockIdx.x * 256 * U + threadIdx.x; p0 < N;
+         p0 += (size_t)nblk * 256 * U) {
+        float2 uu[U], ww[U], v[U][JV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            float2 v = V[(size_t)i * N + p];
-            ar[i] += (double)v.x * cx + (double)v.y * cy;
-            ai[i] += (double)v.x * cy - (double)v.y * cx;
+        for (int q = 0; q < U; ++q) {
+            size_t p = p0 + 256 * q;
+            bool ok = p < N;
+            uu[q] = ok ? u[p] : make_float2(0.f, 0.f);
+            ww[q] = ok ? w[p] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int i = 0; i < J; ++i) v[q][i] = ok ? Vb[(size_t)i * N + p] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            double ux = uu[q].x, uy = uu[q].y, wx = ww[q].x, wy = ww[q].y;
+#pragma unroll
+            for (int i = 0; i < J; ++i) {
+                double vx = v[q][i].x, vy = v[q][i].y;
+                ar[i] += vx * ux + vy * uy;
+                ai[i] += vx * uy - vy * ux;
+                ar[J + i] += vx * wx + vy * wy;
+                ai[J + i] += vx * wy - vy * wx;
+            }
+            ar[2 * J] += ux * ux + uy * uy;
+            ar[2 * J + 1] += ux * wx + uy * wy;
+            ai[2 * J + 1] += ux * wy - uy * wx;
+            ar[2 * J + 2] += wx * wx + wy * wy;
         }
     }
-    block_store<NV>(ar, ai, partial + ((size_t)b * nblk + blockIdx.x) * MAXV);
+    block_store<NP>(ar, ai, partial + ((size_t)b * nblk + blockIdx.x) * MAXP);
 }
 
-// w -= sum_i h_i V_i in FP64, stored complex64; then mode 0: partial
-// conj(V_i) w of the stored w, mode 1: partial |w|^2 (in component 0).
-template <int NV>
-__global__ __launch_bounds__(256) void k_update(const float2 *__restrict__ V, size_t vsb,
-                                                size_t N, float2 *__restrict__ w, size_t ws,
-                                                const double2 *__restrict__ hcoef, int hstride,
-                                                int mode, double2 *__restrict__ partial,
-                                                int nblk, const int *__restrict__ active)
+// Reduction of pass A and the Givens update of column j (one block per
+// right-hand side).  Sets S.hc = [h_0..h_j], S.ac = [a_0..a_{j-1}], S.nu =
+// nu', the Hessenberg column, rotations, g and the next candidate's scale;
+// clears the active flag when the cycle stops at this step.
+__global__ __launch_bounds__(1024) void k_arnoldi_reduce(FgState S,
+                                                         const double2 *__restrict__ partial,
+                                                         int nblk, int j)
 {
-    const int b = blockIdx.y;
-    if (active && !active[b]) return;
-    V += (size_t)b * vsb;
-    w += (size_t)b * ws;
-    hcoef += (size_t)b * hstride;
-    double hr[NV], hi[NV], ar[NV], ai[NV];
+    const int b = blockIdx.x;
+    if (!S.active[b]) return;
+    const int m = S.m;
+    const int np = 2 * j + 3;
+    __shared__ double2 part[16][MAXP];
+    __shared__ double2 red[MAXP];
+    __shared__ double2 col[MAXV + 1], sn_s[MAXV];
+    __shared__ double cs_s[MAXV];
+    __shared__ double sums[3][2];
+    const int t = threadIdx.x;
+    {
+        // fixed-order sums over blocks: 64 entries x 16 row groups
+        const double2 *pb = partial + (size_t)b * nblk * MAXP;
+        const int r0 = t >> 6, i = t & 63;
+        double sr = 0.0, si = 0.0;
+        if (i < np) {
+#pragma unroll 8
+            for (int q = r0; q < nblk; q += 16) {
+                double2 v = pb[(size_t)q * MAXP + i];
+                sr += v.x;
+                si += v.y;
+            }
+        }
+        part[r0][i] = make_double2(sr, si);
+    }
+    double *cs = S.cs + (size_t)b * m;
+    double2 *sn = S.sn + (size_t)b * m;
+    double2 *H = S.H + (size_t)b * (m + 1) * m;
+    double2 *g = S.g + (size_t)b * (m + 1);
+    if (t < j) {
+        cs_s[t] = cs[t];
+        sn_s[t] = sn[t];
+    }
+    __syncthreads();
+    if (t < np) {
+        double tr = 0.0, ti = 0.0;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        double2 h = hcoef[i];
+        for (int r = 0; r < 16; ++r) {
+            tr += part[r][t].x;
+            ti += part[r][t].y;
+        }
+        red[t] = make_double2(tr, ti);
+    }
+    __syncthreads();
+    // |a|^2, |c|^2 and a^H c over i < j, one lane per i (wave 0)
+    if (t < 64) {
+        double aa = 0.0, cc = 0.0, acr = 0.0, aci = 0.0;
+        if (t < j) {
+            double2 a = red[t], c = red[j + t];
+            aa = a.x * a.x + a.y * a.y;
+            cc = c.x * c.x + c.y * c.y;
+            double2 q = cdot(a, c);
+            acr = q.x;
+            aci = q.y;
+        }
+        aa = wave_sum(aa);
+        cc = wave_sum(cc);
+        acr = wave_sum(acr);
+        aci = wave_sum(aci);
+        if (t == 0) {
+            sums[0][0] = aa;
+            sums[1][0] = cc;
+            sums[2][0] = acr;
+            sums[2][1] = aci;
+        }
+    }
+    if (t < j) {
+        S.hc[(size_t)b * MAXV + t] = red[j + t];
+        S.ac[(size_t)b * MAXV + t] = red[t];
+        col[t] = red[j + t];
+    }
+    __syncthreads();
+    if (t == 0) {
+        double alpha = red[2 * j].x, gw = red[2 * j + 2].x;
+        double2 beta = red[2 * j + 1];
+        double aa = sums[0][0], cc = sums[1][0];
+        double2 ac = make_double2(sums[2][0], sums[2][1]);
+        double nu2 = alpha - aa;
+        double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+        double2 hj = nu > 0.0 ? make_double2((beta.x - ac.x) / nu, (beta.y - ac.y) / nu)
+                              : make_double2(0.0, 0.0);
+        double hn2 = gw - cc - (hj.x * hj.x + hj.y * hj.y);
+        double hn = hn2 > 0.0 ? sqrt(hn2) : 0.0;
+        S.hc[(size_t)b * MAXV + j] = hj;
+        S.nu[b] = nu;
+        col[j] = hj;
+        // previous rotations in order; `a` carries the running second component
+        double2 a = col[0];
+        for (int i = 0; i < j; ++i) {
+            double2 c = col[i + 1];
+            double2 t1 = dmul(sn_s[i], c);
+            col[i] = make_double2(cs_s[i] * a.x + t1.x, cs_s[i] * a.y + t1.y);
+            double2 t2 = dmul(dconj(sn_s[i]), a);
+            a = make_double2(cs_s[i] * c.x - t2.x, cs_s[i] * c.y - t2.y);
+        }
+        // new rotation [c s; -conj(s) c] zeroing hn under a
+        double am = hypot(a.x, a.y);
+        double tt = hypot(am, hn);
+        double cj;
+        double2 sj;
+        if (am == 0.0) {
+            cj = 0.0;
+            sj = make_double2(1.0, 0.0);
+            col[j] = make_double2(hn, 0.0);
+        } else {
+            double2 ph = make_double2(a.x / am, a.y / am);
+            cj = am / tt;
+            sj = make_double2(ph.x * hn / tt, ph.y * hn / tt);
+            col[j] = make_double2(ph.x * tt, ph.y * tt);
+        }
+        col[j + 1] = make_double2(0.0, 0.0);
+        cs[j] = cj;
+        sn[j] = sj;
+        double2 gj = g[j];
+        double2 t3 = dmul(dconj(sj), gj);
+        g[j + 1] = make_double2(-t3.x, -t3.y);
+        g[j] = make_double2(cj * gj.x, cj * gj.y);
+        S.k[b] = j + 1;
+        int its = ++S.its[b];
+        double res = hypot(t3.x, t3.y);
+        S.scale[b] = hn > 0.0 ? 1.0 / hn : 0.0;
+        if (nu == 0.0 || hn == 0.0 || res <= S.tol * S.bnorm[b] || its >= S.maxit || j + 1 >= m)
+            S.active[b] = 0;
+    }
+    __syncthreads();
+    if (t <= j + 1) H[t * m + j] = col[t];
+}
+
+// Pass B of step J: v_J = (u - sum a_i v_i) / nu' into slot J and the next
+// candidate u' = w - sum_{i<=J} h_i v_i into slot J+1.  Right-hand sides
+// whose cycle stopped at this step are inactive and skip it.
+template <int J>
+__global__ __launch_bounds__(256) void k_arnoldi_b(FgState S, float2 *__restrict__ V, size_t vsb,
+                                                   size_t N)
+{
+    constexpr int JV = J > 0 ? J : 1;
+    const int b = blockIdx.y;
+    if (!S.active[b]) return;
+    float2 *Vb = V + (size_t)b * vsb;
+    float2 *u = Vb + (size_t)J * N;
+    float2 *w = Vb + (size_t)(J + 1) * N;
+    double hr[J + 1], hi[J + 1], cr[JV], ci[JV];
+#pragma unroll
+    for (int i = 0; i <= J; ++i) {
+        double2 h = S.hc[(size_t)b * MAXV + i];
         hr[i] = h.x;
         hi[i] = h.y;
-        ar[i] = ai[i] = 0.0;
     }
-    double nrm = 0.0;
-    for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)nblk * 256) {
-        float2 c = w[p];
-        double cx = c.x, cy = c.y;
-        float2 v[NV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            v[i] = V[(size_t)i * N + p];
-            cx -= hr[i] * v[i].x - hi[i] * v[i].y;
-            cy -= hr[i] * v[i].y + hi[i] * v[i].x;
+    for (int i = 0; i < J; ++i) {
+        double2 a = S.ac[(size_t)b * MAXV + i];
+        cr[i] = a.x;
+        ci[i] = a.y;
+    }
+    const double inu = 1.0 / S.nu[b];
+    constexpr int U = J <= 12 ? 2 : 1;  // points per thread per step (register budget)
+    for (size_t p0 = (size_t)blockIdx.x * 256 * U + threadIdx.x; p0 < N;
+         p0 += (size_t)gridDim.x * 256 * U) {
+        float2 uu[U], ww[U], v[U][JV];
+        bool ok[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            size_t p = p0 + 256 * q;
+            ok[q] = p < N;
+            uu[q] = ok[q] ? u[p] : make_float2(0.f, 0.f);
+            ww[q] = ok[q] ? w[p] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int i = 0; i < J; ++i) v[q][i] = ok[q] ? Vb[(size_t)i * N + p] : make_float2(0.f, 0.f);
         }
-        float2 o = make_float2((float)cx, (float)cy);
-        w[p] = o;
-        double ox = o.x, oy = o.y;
-        if (mode == 0) {
 #pragma unroll
-            for (int i = 0; i < NV; ++i) {
-                ar[i] += (double)v[i].x * ox + (double)v[i].y * oy;
-                ai[i] += (double)v[i].x * oy - (double)v[i].y * ox;
+        for (int q = 0; q < U; ++q) {
+            double ux = uu[q].x, uy = uu[q].y, wx = ww[q].x, wy = ww[q].y;
+#pragma unroll
+            for (int i = 0; i < J; ++i) {
+                double vx = v[q][i].x, vy = v[q][i].y;
+                ux -= cr[i] * vx - ci[i] * vy;
+                uy -= cr[i] * vy + ci[i] * vx;
+                wx -= hr[i] * vx - hi[i] * vy;
+                wy -= hr[i] * vy + hi[i] * vx;
             }
-        } else {
-            nrm += ox * ox + oy * oy;
+            float2 vj = make_float2((float)(ux * inu), (float)(uy * inu));
+            double vx = vj.x, vy = vj.y;
+            wx -= hr[J] * vx - hi[J] * vy;
+            wy -= hr[J] * vy + hi[J] * vx;
+            if (ok[q]) {
+                u[p0 + 256 * q] = vj;
+                w[p0 + 256 * q] = make_float2((float)wx, (float)wy);
+            }
         }
-    }
-    double2 *out = partial + ((size_t)b * nblk + blockIdx.x) * MAXV;
-    if (mode == 0) {
-        block_store<NV>(ar, ai, out);
-    } else {
-        double z[1] = {nrm}, zi[1] = {0.0};
-        block_store<1>(z, zi, out);
-    }
-}
-
-__global__ __launch_bounds__(256) void k_scale(float2 *__restrict__ w, size_t ws, size_t N,
-                                               const double *__restrict__ scale,
-                                               const int *__restrict__ active)
-{
-    const int b = blockIdx.y;
-    if (active && !active[b]) return;
-    w += (size_t)b * ws;
-    const float s = (float)scale[b];
-    for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)gridDim.x * 256) {
-        float2 c = w[p];
-        w[p] = make_float2(c.x * s, c.y * s);
     }
 }
 
@@ -165,63 +346,68 @@ __global__ __launch_bounds__(256) void k_xupdate(double2 *__restrict__ x, size_t
     }
 }
 
-template <int NV>
-void dots_dispatch(const float2 *V, size_t vsb, size_t N, const float2 *w, size_t ws,
-                   double2 *partial, int nblk, int nb, const int *active, hipStream_t s)
+__global__ __launch_bounds__(256) void k_scale(float2 *__restrict__ w, size_t ws, size_t N,
+                                               const double *__restrict__ scale,
+                                               const int *__restrict__ active)
 {
-    hipLaunchKernelGGL(k_dots<NV>, dim3(nblk, nb), dim3(256), 0, s, V, vsb, N, w, ws, partial,
-                       nblk, active);
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    w += (size_t)b * ws;
+    const float s = (float)scale[b];
+    for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)gridDim.x * 256) {
+        float2 c = w[p];
+        w[p] = make_float2(c.x * s, c.y * s);
+    }
 }
 
-template <int NV>
-void update_dispatch(const float2 *V, size_t vsb, size_t N, float2 *w, size_t ws,
-                     const double2 *h, int hstride, int mode, double2 *partial, int nblk, int nb,
-                     const int *active, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_update<NV>, dim3(nblk, nb), dim3(256), 0, s, V, vsb, N, w, ws, h,
-                       hstride, mode, partial, nblk, active);
-}
+using pa_fn = void (*)(const FgState &, const float2 *, size_t, size_t, double2 *, int, hipStream_t);
+using pb_fn = void (*)(const FgState &, float2 *, size_t, size_t, int, hipStream_t);
 
-using dots_fn = void (*)(const float2 *, size_t, size_t, const float2 *, size_t, double2 *, int,
-                         int, const int *, hipStream_t);
-using update_fn = void (*)(const float2 *, size_t, size_t, float2 *, size_t, const double2 *,
-                           int, int, double2 *, int, int, const int *, hipStream_t);
+template <int J>
+void pa_dispatch(const FgState &S, const float2 *V, size_t vsb, size_t N, double2 *partial, int nblk,
+                 hipStream_t s)
+{
+    hipLaunchKernelGGL(k_arnoldi_a<J>, dim3(nblk, S.nb), dim3(256), 0, s, S, V, vsb, N, partial,
+                       nblk);
+}
+template <int J>
+void pb_dispatch(const FgState &S, float2 *V, size_t vsb, size_t N, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_arnoldi_b<J>, dim3(nblk, S.nb), dim3(256), 0, s, S, V, vsb, N);
+}
 
 template <int... I>
-constexpr auto make_dots_table(std::integer_sequence<int, I...>)
+constexpr std::array<pa_fn, sizeof...(I)> make_pa(std::integer_sequence<int, I...>)
 {
-    return std::array<dots_fn, sizeof...(I)>{&dots_dispatch<I + 1>...};
+    return {&pa_dispatch<I>...};
 }
 template <int... I>
-constexpr auto make_update_table(std::integer_sequence<int, I...>)
+constexpr std::array<pb_fn, sizeof...(I)> make_pb(std::integer_sequence<int, I...>)
 {
-    return std::array<update_fn, sizeof...(I)>{&update_dispatch<I + 1>...};
+    return {&pb_dispatch<I>...};
 }
 
-const auto kDots = make_dots_table(std::make_integer_sequence<int, MAXV>{});
-const auto kUpdate = make_update_table(std::make_integer_sequence<int, MAXV>{});
+const auto kPassA = make_pa(std::make_integer_sequence<int, MAXM>{});
+const auto kPassB = make_pb(std::make_integer_sequence<int, MAXM>{});
 
 }  // namespace
 
 int krylov_nblk(size_t N)
 {
-    size_t b = (N + 1023) / 1024;
+    size_t b = (N + 511) / 512;
     if (b < 1) b = 1;
     if (b > 1024) b = 1024;
     return (int)b;
 }
 
-void launch_dots(const float2 *V, size_t vsb, size_t N, const float2 *w, size_t ws, int nv,
-                 double2 *partial, int nblk, int nb, const int *active, hipStream_t s)
+void launch_arnoldi_step(const FgState &S, float2 *V, size_t vsb, size_t N, int j,
+                         double2 *partial, int nblk, hipStream_t s)
 {
-    kDots[nv - 1](V, vsb, N, w, ws, partial, nblk, nb, active, s);
-}
-
-void launch_update(const float2 *V, size_t vsb, size_t N, float2 *w, size_t ws, int nv,
-                   const double2 *hcoef, int hstride, int mode, double2 *partial, int nblk, int nb,
-                   const int *active, hipStream_t s)
-{
-    kUpdate[nv - 1](V, vsb, N, w, ws, hcoef, hstride, mode, partial, nblk, nb, active, s);
+    prof_mark(HELM_PROF_CGS, s, true);
+    kPassA[j](S, V, vsb, N, partial, nblk, s);
+    hipLaunchKernelGGL(k_arnoldi_reduce, dim3(S.nb), dim3(1024), 0, s, S, partial, nblk, j);
+    kPassB[j](S, V, vsb, N, nblk, s);
+    prof_mark(HELM_PROF_CGS, s, false);
 }
 
 void launch_scale(float2 *w, size_t ws, size_t N, const double *scale, int nb, const int *active,

@@ -91,30 +91,47 @@ __global__ __launch_bounds__(256) void k_down(const float2 *__restrict__ f, size
                                               float2 *__restrict__ fc, size_t fcs,
                                               const float2 *__restrict__ mass, int n,
                                               float ih2, float shift, float w,
+                                              const double *__restrict__ scale,
                                               const int *__restrict__ active)
 {
     __shared__ float2 sv[DN_VH][DN_VW + 1];
     __shared__ float2 sf[DN_VH][DN_VW + 1];
+    constexpr int NLD = (DN_VH * DN_VW + 255) / 256;
     const int b = blockIdx.z;
     if (active && !active[b]) return;
     f += (size_t)b * fs;
     fc += (size_t)b * fcs;
+    const float sc = scale ? (float)scale[b] : 1.f;
     const int nc = n / 2;
     const int I0 = blockIdx.y * DN_CH, J0 = blockIdx.x * DN_CW;
     const int fi0 = 2 * I0 - 2, fj0 = 2 * J0 - 2;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < DN_VH * DN_VW; idx += 256) {
+    float2 fl[NLD], ml[NLD];
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+        int idx = tid + 256 * q;
         int r = idx / DN_VW, c = idx - r * DN_VW;
         int i = fi0 + r, j = fj0 + c;
-        float2 fv = f2(0.f, 0.f), vv = f2(0.f, 0.f);
-        if (i >= 0 && i < n && j >= 0 && j < n) {
+        fl[q] = ml[q] = f2(0.f, 0.f);
+        if (idx < DN_VH * DN_VW && i >= 0 && i < n && j >= 0 && j < n) {
             size_t p = (size_t)i * n + j;
-            fv = f[p];
-            float2 m = op_mass(mass[p], shift);
-            vv = cdiv(w * fv, f2(4.f * ih2 - m.x, -m.y));
+            fl[q] = f[p];
+            ml[q] = mass[p];
         }
-        sf[r][c] = fv;
-        sv[r][c] = vv;
+    }
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+        int idx = tid + 256 * q;
+        if (idx < DN_VH * DN_VW) {
+            int r = idx / DN_VW, c = idx - r * DN_VW;
+            int i = fi0 + r, j = fj0 + c;
+            float2 fv = sc * fl[q];
+            float2 m = op_mass(ml[q], shift);
+            float2 vv = (i >= 0 && i < n && j >= 0 && j < n) ? cdiv(w * fv, f2(4.f * ih2 - m.x, -m.y))
+                                                             : f2(0.f, 0.f);
+            sf[r][c] = fv;
+            sv[r][c] = vv;
+        }
     }
     __syncthreads();
     // residual on rows/cols 1..size-2 of the region; zero outside the grid
@@ -149,35 +166,65 @@ __global__ __launch_bounds__(256) void k_up(const float2 *__restrict__ f, size_t
                                             const float2 *__restrict__ vc, size_t vcs,
                                             float2 *__restrict__ v, size_t vs,
                                             const float2 *__restrict__ mass, int n, float ih2,
-                                            float shift, float w, const int *__restrict__ active)
+                                            float shift, float w, const double *__restrict__ scale,
+                                            const int *__restrict__ active)
 {
     __shared__ float2 svc[UP_CH][UP_CW + 1];
     __shared__ float2 sv[UP_H + 2][UP_W + 3];
     __shared__ float2 sf[UP_H][UP_W];
     __shared__ float2 sd[UP_H][UP_W];
+    constexpr int RW = UP_W + 2, RH = UP_H + 2;
+    constexpr int NLC = (UP_CH * UP_CW + 255) / 256, NLD = (RH * RW + 255) / 256;
     const int b = blockIdx.z;
     if (active && !active[b]) return;
     f += (size_t)b * fs;
     vc += (size_t)b * vcs;
     v += (size_t)b * vs;
+    const float sc = scale ? (float)scale[b] : 1.f;
     const int nc = n / 2;
     const int i0 = blockIdx.y * UP_H, j0 = blockIdx.x * UP_W;
     const int I0 = i0 / 2 - 1, J0 = j0 / 2 - 1;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < UP_CH * UP_CW; idx += 256) {
+    float2 cl[NLC], fl[NLD], ml[NLD];
+#pragma unroll
+    for (int q = 0; q < NLC; ++q) {
+        int idx = tid + 256 * q;
         int r = idx / UP_CW, c = idx - r * UP_CW;
         int I = I0 + r, J = J0 + c;
-        svc[r][c] = (I >= 0 && I < nc && J >= 0 && J < nc) ? vc[(size_t)I * nc + J] : f2(0.f, 0.f);
+        cl[q] = (idx < UP_CH * UP_CW && I >= 0 && I < nc && J >= 0 && J < nc) ? vc[(size_t)I * nc + J]
+                                                                              : f2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+        int idx = tid + 256 * q;
+        int r = idx / RW, c = idx - r * RW;
+        int i = i0 - 1 + r, j = j0 - 1 + c;
+        fl[q] = ml[q] = f2(0.f, 0.f);
+        if (idx < RH * RW && i >= 0 && i < n && j >= 0 && j < n) {
+            size_t p = (size_t)i * n + j;
+            fl[q] = f[p];
+            ml[q] = mass[p];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NLC; ++q) {
+        int idx = tid + 256 * q;
+        if (idx < UP_CH * UP_CW) {
+            int r = idx / UP_CW, c = idx - r * UP_CW;
+            svc[r][c] = cl[q];
+        }
     }
     __syncthreads();
-    for (int idx = tid; idx < (UP_H + 2) * (UP_W + 2); idx += 256) {
-        int r = idx / (UP_W + 2), c = idx - r * (UP_W + 2);
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+        int idx = tid + 256 * q;
+        if (idx >= RH * RW) continue;
+        int r = idx / RW, c = idx - r * RW;
         int i = i0 - 1 + r, j = j0 - 1 + c;
         float2 vp = f2(0.f, 0.f);
         if (i >= 0 && i < n && j >= 0 && j < n) {
-            size_t p = (size_t)i * n + j;
-            float2 fv = f[p];
-            float2 m = op_mass(mass[p], shift);
+            float2 fv = sc * fl[q];
+            float2 m = op_mass(ml[q], shift);
             float2 d = f2(4.f * ih2 - m.x, -m.y);
             // bilinear prolongation: even index -> one coarse point (weight 1),
             // odd index -> the two neighbours (weight 1/2 each)
@@ -213,11 +260,13 @@ __global__ __launch_bounds__(256) void k_up(const float2 *__restrict__ f, size_t
 }
 
 // ------------------------------------------------------------------ coarse
-// v = X f for NB right-hand sides at once; one wavefront per row of X.
+// v = X f for NB right-hand sides at once; one wavefront per row of X, each
+// lane streaming two complex entries (16 bytes) per load.
 template <int NB>
 __global__ __launch_bounds__(256) void k_coarse(const float2 *__restrict__ X, int N,
                                                 const float2 *__restrict__ f, size_t fs,
                                                 float2 *__restrict__ v, size_t vs, int b0,
+                                                const double *__restrict__ scale,
                                                 const int *__restrict__ active)
 {
     const int lane = threadIdx.x & 63;
@@ -227,7 +276,24 @@ __global__ __launch_bounds__(256) void k_coarse(const float2 *__restrict__ X, in
 #pragma unroll
     for (int q = 0; q < NB; ++q) ar[q] = ai[q] = 0.f;
     const float2 *xr = X + (size_t)row * N;
-    for (int k = lane; k < N; k += 64) {
+    const int nvec = (N / 128) * 128;
+    // X rows start 8-byte aligned; the 16-byte path needs an even row offset
+    const bool al = (((size_t)row * N) & 1) == 0;
+    int k0 = 0;
+    if (al) {
+#pragma unroll 4
+        for (int k = 2 * lane; k < nvec; k += 128) {
+            float4 a = *reinterpret_cast<const float4 *>(xr + k);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                float4 c = *reinterpret_cast<const float4 *>(f + (size_t)(b0 + q) * fs + k);
+                ar[q] += a.x * c.x - a.y * c.y + a.z * c.z - a.w * c.w;
+                ai[q] += a.x * c.y + a.y * c.x + a.z * c.w + a.w * c.z;
+            }
+        }
+        k0 = nvec;
+    }
+    for (int k = k0 + lane; k < N; k += 64) {
         float2 a = xr[k];
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
@@ -245,7 +311,10 @@ __global__ __launch_bounds__(256) void k_coarse(const float2 *__restrict__ X, in
     if (lane == 0) {
 #pragma unroll
         for (int q = 0; q < NB; ++q)
-            if (!active || active[b0 + q]) v[(size_t)(b0 + q) * vs + row] = f2(ar[q], ai[q]);
+            if (!active || active[b0 + q]) {
+                float sc = scale ? (float)scale[b0 + q] : 1.f;
+                v[(size_t)(b0 + q) * vs + row] = f2(sc * ar[q], sc * ai[q]);
+            }
     }
 }
 
@@ -315,50 +384,58 @@ void launch_apply(const Level &L, float shift, const float2 *x, size_t xs, float
     long long waves_at_1 = (long long)strips * n * nb;
     int R = (int)std::min<long long>(32, std::max<long long>(2, waves_at_1 / 4096));
     dim3 grid(strips, (n + 4 * R - 1) / (4 * R), nb), block(64, 4);
+    prof_mark(HELM_PROF_APPLY, s, true);
     hipLaunchKernelGGL(k_apply, grid, block, 0, s, x, xs, y, ys, L.mass, n, L.ih2, shift, R,
                        active);
+    prof_mark(HELM_PROF_APPLY, s, false);
 }
 
 void launch_down(const Level &L, float shift, float w, const float2 *f, size_t fs, float2 *fc,
-                 size_t fcs, int nb, const int *active, hipStream_t s)
+                 size_t fcs, int nb, const int *active, hipStream_t s, const double *scale)
 {
     const int nc = L.n / 2;
     dim3 grid((nc + DN_CW - 1) / DN_CW, (nc + DN_CH - 1) / DN_CH, nb);
-    hipLaunchKernelGGL(k_down, grid, dim3(256), 0, s, f, fs, fc, fcs, L.mass, L.n, L.ih2, shift,
-                       w, active);
+    prof_mark(HELM_PROF_DOWN, s, true);
+    hipLaunchKernelGGL(k_down, grid, dim3(256), 0, s, f, fs, fc, fcs, L.mass,
+                       L.n, L.ih2, shift, w, scale, active);
+    prof_mark(HELM_PROF_DOWN, s, false);
 }
 
 void launch_up(const Level &L, float shift, float w, const float2 *f, size_t fs,
                const float2 *vc, size_t vcs, float2 *v, size_t vs, int nb, const int *active,
-               hipStream_t s)
+               hipStream_t s, const double *scale)
 {
     const int n = L.n;
     dim3 grid((n + UP_W - 1) / UP_W, (n + UP_H - 1) / UP_H, nb);
+    prof_mark(HELM_PROF_UP, s, true);
     hipLaunchKernelGGL(k_up, grid, dim3(256), 0, s, f, fs, vc, vcs, v, vs, L.mass, n, L.ih2,
-                       shift, w, active);
+                       shift, w, scale, active);
+    prof_mark(HELM_PROF_UP, s, false);
 }
 
 void launch_coarse_solve(const float2 *X, int N, const float2 *f, size_t fs, float2 *v,
-                         size_t vs, int nb, const int *active, hipStream_t s)
+                         size_t vs, int nb, const int *active, hipStream_t s, const double *scale)
 {
     dim3 grid((N + 3) / 4), block(256);
+    prof_mark(HELM_PROF_COARSE, s, true);
     int b0 = 0;
     while (b0 < nb) {
         int left = nb - b0;
         if (left >= 8) {
-            hipLaunchKernelGGL(k_coarse<8>, grid, block, 0, s, X, N, f, fs, v, vs, b0, active);
+            hipLaunchKernelGGL(k_coarse<8>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, active);
             b0 += 8;
         } else if (left >= 4) {
-            hipLaunchKernelGGL(k_coarse<4>, grid, block, 0, s, X, N, f, fs, v, vs, b0, active);
+            hipLaunchKernelGGL(k_coarse<4>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, active);
             b0 += 4;
         } else if (left >= 2) {
-            hipLaunchKernelGGL(k_coarse<2>, grid, block, 0, s, X, N, f, fs, v, vs, b0, active);
+            hipLaunchKernelGGL(k_coarse<2>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, active);
             b0 += 2;
         } else {
-            hipLaunchKernelGGL(k_coarse<1>, grid, block, 0, s, X, N, f, fs, v, vs, b0, active);
+            hipLaunchKernelGGL(k_coarse<1>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, active);
             b0 += 1;
         }
     }
+    prof_mark(HELM_PROF_COARSE, s, false);
 }
 
 void launch_level_mass(const float *kappa, const float *gamma, int n, int stride_pow,

@@ -23,8 +23,10 @@ PREC = {"sl": 0, "unet_cgc": 1, "unet_defl": 2}
 
 EXPORTS = [
     "helm_setup", "helm_destroy", "helm_level_size", "helm_num_levels", "helm_apply",
-    "helm_sl_vcycle", "helm_fgmres_solve", "helm_last_error",
+    "helm_sl_vcycle", "helm_fgmres_solve", "helm_last_error", "helm_profile_start",
+    "helm_profile_stop",
 ]
+PROF = {"none": 0, "coarse": 1, "down": 2, "up": 3, "cgs": 4, "apply": 5}
 
 
 class HelmError(RuntimeError):
@@ -77,6 +79,10 @@ def lib():
         L.helm_fgmres_solve.restype = ip
         L.helm_last_error.argtypes = []
         L.helm_last_error.restype = C.c_char_p
+        L.helm_profile_start.argtypes = [ip]
+        L.helm_profile_start.restype = ip
+        L.helm_profile_stop.argtypes = [C.POINTER(dp), C.POINTER(C.c_longlong)]
+        L.helm_profile_stop.restype = ip
         _lib = L
     return _lib
 
@@ -189,3 +195,16 @@ def fgmres_solve(problems, rhs, m=20, tol=1e-7, maxit=20000, prec="sl", net=None
     rc = _check(lib().helm_fgmres_solve(probs, nprob, counts, bp, xp, C.byref(opts), stats,
                                         _stream(stream)), "helm_fgmres_solve")
     return xs, [stats[i].as_dict() for i in range(total)], rc
+
+
+def profile_start(family):
+    """Start timing every launch of one kernel family with HIP events."""
+    _check(lib().helm_profile_start(PROF[family]), "helm_profile_start")
+
+
+def profile_stop():
+    """Stop timing; returns (summed device milliseconds, number of launches)."""
+    ms = C.c_double()
+    n = C.c_longlong()
+    _check(lib().helm_profile_stop(C.byref(ms), C.byref(n)), "helm_profile_stop")
+    return ms.value, n.value
