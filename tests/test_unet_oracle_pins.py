@@ -1,0 +1,121 @@
+"""Pins of the U-Net oracle: explicit loops for the layer primitives, closed
+forms for bilinear upsampling and the first Adam step, FP64 central finite
+differences for the gradients, and the homogeneity the RMS scaling implies."""
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+from oracle import helm_oracle, unet_oracle as U
+
+TINY = U.UNetCfg(in_ch=3, out_ch=2, widths=(4, 8))
+
+
+def test_config_network_parameter_count():
+    """4 levels 32/64/128/256, input (Re r, Im r, kappa): 1,945,506 parameters
+    (convolutions + BN affine + 1x1 head)."""
+    cfg = U.UNetCfg()
+    conv = sum(int(np.prod(s)) for k, s in U.param_shapes(cfg).items() if k.endswith(".w"))
+    head_b = 2
+    assert conv + head_b == 1_945_506
+    ctxcfg = U.UNetCfg(context=True)
+    assert [s[1] for s in U.layer_specs(ctxcfg)][:2] == [35, 32]
+
+
+def test_conv_matches_explicit_loop():
+    rng = np.random.default_rng(0)
+    x = torch.tensor(rng.standard_normal((1, 2, 5, 6)))
+    w = torch.tensor(rng.standard_normal((3, 2, 3, 3)))
+    y = F.conv2d(x, w, padding=1).numpy()
+    xp = np.pad(x.numpy(), ((0, 0), (0, 0), (1, 1), (1, 1)))
+    ref = np.zeros((1, 3, 5, 6))
+    for co in range(3):
+        for i in range(5):
+            for j in range(6):
+                ref[0, co, i, j] = np.sum(xp[0, :, i:i + 3, j:j + 3] * w.numpy()[co])
+    np.testing.assert_allclose(y, ref, atol=1e-12)
+
+
+def test_bilinear_up_closed_form():
+    """Half-pixel centres: [a, b] -> [a, 3a/4 + b/4, a/4 + 3b/4, b]."""
+    x = torch.tensor([[[[1.0, 5.0]]]], dtype=torch.float64).repeat(1, 1, 2, 1)
+    y = U.up2(x)[0, 0, 0].numpy()
+    np.testing.assert_allclose(y, [1.0, 2.0, 4.0, 5.0], atol=1e-14)
+
+
+def test_batchnorm_training_statistics():
+    torch.manual_seed(1)
+    p, buf = U.init_params(TINY, 3, dtype=torch.float64)
+    x = torch.randn(4, 3, 8, 8, dtype=torch.float64)
+    stats = {}
+    y = F.conv2d(x, p["enc0a.w"], padding=1)
+    U._block(x, p, buf, "enc0a", True, stats)
+    mean, var = stats["enc0a"]
+    np.testing.assert_allclose(mean.numpy(), y.numpy().mean(axis=(0, 2, 3)), atol=1e-12)
+    np.testing.assert_allclose(var.numpy(), y.numpy().var(axis=(0, 2, 3)), atol=1e-12)
+    z = (y - mean[None, :, None, None]) / torch.sqrt(var[None, :, None, None] + U.EPS)
+    np.testing.assert_allclose(z.mean(dim=(0, 2, 3)).numpy(), 0.0, atol=1e-12)
+    np.testing.assert_allclose(z.var(dim=(0, 2, 3), unbiased=False).numpy(), 1.0, atol=1e-4)
+
+
+def test_gradients_match_central_differences():
+    """Training-mode loss gradients (autograd) against FP64 central
+    differences on a tiny network, every parameter tensor sampled."""
+    p, buf = U.init_params(TINY, 5, dtype=torch.float64)
+    rng = np.random.default_rng(7)
+    x = torch.tensor(rng.standard_normal((2, 3, 8, 8)))
+    probe = torch.tensor(rng.standard_normal((2, 2, 8, 8)))
+
+    def loss_of(pp):
+        return (U.forward(TINY, pp, buf, x, training=True) * probe).sum()
+
+    pg = {k: v.clone().requires_grad_(True) for k, v in p.items()}
+    loss_of(pg).backward()
+    h = 1e-6
+    for k, v in p.items():
+        flat = v.reshape(-1)
+        for idx in rng.choice(flat.numel(), size=min(3, flat.numel()), replace=False):
+            pp = {kk: vv.clone() for kk, vv in p.items()}
+            pm = {kk: vv.clone() for kk, vv in p.items()}
+            pp[k].reshape(-1)[idx] += h
+            pm[k].reshape(-1)[idx] -= h
+            fd = (loss_of(pp) - loss_of(pm)).item() / (2 * h)
+            ad = pg[k].grad.reshape(-1)[idx].item()
+            assert abs(fd - ad) <= 1e-5 * max(1.0, abs(fd)), (k, idx, fd, ad)
+
+
+def test_adam_first_step_closed_form():
+    p = {"a": torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64)}
+    g = {"a": torch.tensor([0.3, -1e-3, 0.0], dtype=torch.float64)}
+    m = {"a": torch.zeros(3, dtype=torch.float64)}
+    v = {"a": torch.zeros(3, dtype=torch.float64)}
+    new, _, _ = U.adam_step(dict(p), g, m, v, 1, lr=1e-3)
+    expect = p["a"] - 1e-3 * g["a"] / (g["a"].abs() + 1e-8)
+    np.testing.assert_allclose(new["a"].numpy(), expect.numpy(), atol=1e-15)
+
+
+def test_prolong_torch_matches_oracle_prolongation():
+    rng = np.random.default_rng(3)
+    ec = rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))
+    a = U.prolong_torch(torch.tensor(ec)).numpy()
+    np.testing.assert_allclose(a, helm_oracle.prolong(ec), atol=1e-14)
+
+
+def test_wrapper_positively_homogeneous_and_zero():
+    cfg = U.UNetCfg(widths=(4, 8, 16))
+    p, buf = U.init_params(cfg, 11, dtype=torch.float64)
+    n = 32
+    rng = np.random.default_rng(4)
+    r = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    kc = rng.uniform(0.25, 1.0, (n // 2, n // 2))
+    e1 = U.unet_apply(cfg, p, buf, r, kc, dtype=torch.float64)
+    e2 = U.unet_apply(cfg, p, buf, 7.5 * r, kc, dtype=torch.float64)
+    np.testing.assert_allclose(e2, 7.5 * e1, rtol=1e-10, atol=1e-12 * np.abs(e2).max())
+    assert np.all(U.unet_apply(cfg, p, buf, 0 * r, kc) == 0)
+
+
+def test_maxpool_first_maximum_gradient():
+    """Ties route the gradient to the first maximum in (0,0),(0,1),(1,0),(1,1) order."""
+    x = torch.tensor([[[[1.0, 3.0], [3.0, 2.0]]]], requires_grad=True)
+    F.max_pool2d(x, 2).sum().backward()
+    np.testing.assert_array_equal(x.grad.numpy()[0, 0], [[0.0, 1.0], [0.0, 0.0]])
