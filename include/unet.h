@@ -1,0 +1,118 @@
+/*
+ * unet.h -- C ABI of the U-Net part of the MI355X Helmholtz library: the
+ * network used as error predictor inside the preconditioners of section 3.2
+ * (coarse-grid correction with Jacobi smoothing, Algorithm 2; deflation
+ * beside an SL V-cycle, eq. 3.4), its encoder-solver variant (section 3.3,
+ * eq. 3.5) and its supervised training (section 3.4, eq. 3.7-3.9) with Adam.
+ *
+ * Conventions are those of helm.h (device pointers owned by the caller,
+ * void* streams, 0 / >0 / <0 return codes, helm_last_error()).
+ *
+ * Network: L levels of widths w_0..w_{L-1}.  Level l applies twice
+ * [3x3 convolution (zero padding, no bias) -> batch normalisation ->
+ * LeakyReLU(0.2)]; 2x2 max pooling between levels; on the way up a bilinear
+ * x2 upsampling (half-pixel centres, edges clamped) concatenated as
+ * [upsampled, skip] and the same double convolution; a 1x1 convolution with
+ * bias to out_ch channels.  BN uses eps 1e-5 and momentum 0.1; inference uses
+ * the running statistics.  Weights and activations are bf16 on the device
+ * with FP32 accumulation; FP32 master weights and Adam moments are kept.
+ *
+ * Parameter order (flat FP32 arrays): for each 3x3 convolution in forward
+ * order (enc0a, enc0b, enc1a, ..., dec{L-2}a, dec{L-2}b, ..., dec0a, dec0b):
+ * weight [cout][cin][3][3], BN weight [cout], BN bias [cout]; then the head
+ * weight [out_ch][w_0] and bias [out_ch].  Buffers: for each convolution the
+ * BN running mean [cout] and running variance [cout].
+ */
+#ifndef UNET_H
+#define UNET_H
+
+#include "helm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct unet_net unet_net;
+
+typedef struct {
+    int in_ch;      /* real input channels: 3 = (Re r, Im r, kappa)           */
+    int out_ch;     /* output channels: 2 = (Re e, Im e)                       */
+    int levels;     /* resolution levels, 1..6                                  */
+    int widths[6];  /* channels per level; each a multiple of 32               */
+    int context;    /* 1: solver of an encoder-solver pair (reserved, 0 now)   */
+    int head;       /* 1: 1x1 head (required now)                               */
+} unet_cfg;
+
+/* Create a network with zero parameters (set them with unet_set_params). */
+int unet_create(const unet_cfg *cfg, unet_net **out);
+void unet_destroy(unet_net *net);
+/* Number of FP32 parameters / buffer entries in the flat orders above. */
+long long unet_num_params(const unet_net *net);
+long long unet_num_buffers(const unet_net *net);
+
+/* Copy parameters and BN buffers in (device float arrays of the sizes above);
+ * resets the Adam state and step count.  buffers may be NULL (mean 0, var 1). */
+int unet_set_params(unet_net *net, const float *params, const float *buffers, void *stream);
+/* Copy the FP32 master parameters and buffers out (either may be NULL). */
+int unet_get_params(unet_net *net, float *params, float *buffers, void *stream);
+
+/*
+ * unet_forward -- plain network application.
+ *   x   : device float [B][in_ch][H][W]; H, W divisible by 2^(levels-1)
+ *   out : device float [B][out_ch][H][W]
+ *   training = 0: BN with running statistics; 1: batch statistics (the
+ *   running statistics are not updated).
+ */
+int unet_forward(unet_net *net, const float *x, int B, int H, int W, float *out, int training,
+                 void *stream);
+
+/*
+ * unet_infer -- the network as error predictor for residuals on the fine
+ * grid of medium h (the network runs on the grid n/2):
+ *   e = P s Net(R(h^2 r) / s, kappa_c),  s = RMS over the coarse grid of
+ *   |R(h^2 r)|,  kappa_c the slowness injected at the coarse points.
+ * R, P: full-weighting restriction and bilinear prolongation (eq. 2.9); the
+ * h^2 scaling follows section 3.4; s makes the map positively homogeneous.
+ * An all-zero residual gives e = 0.
+ *   r, e : complex64 [nrhs][n][n]; must not overlap.
+ */
+int unet_infer(unet_net *net, helm_handle *h, const float *r, float *e, int nrhs, void *stream);
+
+/* One training batch of (residual, error, coarse slowness) triples. */
+typedef struct {
+    int nb;               /* samples                                             */
+    int n;                /* fine grid size (network on n/2)                     */
+    const float *r;       /* complex64 [nb][n][n] residuals                      */
+    const float *e;       /* complex64 [nb][n][n] errors (A e = r)               */
+    const float *kappa_c; /* float [nb][n/2][n/2] coarse slowness                */
+} unet_batch;
+
+typedef struct {
+    float lr;             /* default 1e-3 */
+    float beta1, beta2;   /* default 0.9, 0.999 */
+    float eps;            /* default 1e-8 */
+} unet_train_opts;
+
+/*
+ * unet_loss_grad -- loss of eq. 3.7 in the scaled form used here,
+ *   loss = mean_b || P Net(R(h^2 r_b)/s_b, kappa_c) - e_b / s_b ||^2 / n^2,
+ * with training-mode BN, and its gradient.  loss_out: host double.
+ * grads: device float [num_params] receiving the gradient (may be NULL).
+ */
+int unet_loss_grad(unet_net *net, const unet_batch *batch, double *loss_out, float *grads,
+                   void *stream);
+
+/*
+ * unet_train_step -- unet_loss_grad, one Adam step (bias-corrected, no weight
+ * decay) on the FP32 masters, bf16 weights re-rounded from them, and the BN
+ * running statistics updated.  loss_out: host double (loss before the step);
+ * opts may be NULL.  Synchronises `stream` to read the loss.
+ */
+int unet_train_step(unet_net *net, const unet_batch *batch, const unet_train_opts *opts,
+                    double *loss_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UNET_H */

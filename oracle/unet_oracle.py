@@ -124,9 +124,41 @@ def unflatten(cfg, flat, dtype=torch.float32):
     return out
 
 
+def bf16_round(t):
+    """Round to the nearest bfloat16 (ties to even), back in t's dtype."""
+    return t.to(torch.bfloat16).to(t.dtype)
+
+
+class _RoundGrad(torch.autograd.Function):
+    """Identity forward; rounds the incoming gradient to bfloat16."""
+
+    @staticmethod
+    def forward(ctx, x):
+        return x.view_as(x)
+
+    @staticmethod
+    def backward(ctx, g):
+        return bf16_round(g)
+
+
+def _ste_round(t):
+    """bfloat16 rounding in the forward pass, identity in the backward pass."""
+    return t + (bf16_round(t) - t).detach()
+
+
+# When True the forward pass rounds weights, activations and the network
+# input to bfloat16, and the backward pass rounds the gradient that reaches
+# each convolution output, at the points where a bf16 device implementation
+# does (FP32 accumulation everywhere else).  Off by default.
+EMULATE_BF16 = False
+
+
 def _block(x, p, buf, name, training, stats):
     """3x3 conv -> BN -> LeakyReLU."""
-    y = F.conv2d(x, p[name + ".w"], padding=1)
+    if EMULATE_BF16:
+        y = _RoundGrad.apply(F.conv2d(x, _ste_round(p[name + ".w"]), padding=1))
+    else:
+        y = F.conv2d(x, p[name + ".w"], padding=1)
     if training:
         mean = y.mean(dim=(0, 2, 3))
         var = y.var(dim=(0, 2, 3), unbiased=False)
@@ -137,7 +169,8 @@ def _block(x, p, buf, name, training, stats):
         z = (y - buf[name + ".rm"][None, :, None, None]) / torch.sqrt(
             buf[name + ".rv"][None, :, None, None] + EPS)
     z = z * p[name + ".g"][None, :, None, None] + p[name + ".b"][None, :, None, None]
-    return F.leaky_relu(z, SLOPE)
+    a = F.leaky_relu(z, SLOPE)
+    return _ste_round(a) if EMULATE_BF16 else a
 
 
 def up2(x):
@@ -150,7 +183,7 @@ def forward(cfg: UNetCfg, p, buf, x, ctx=None, training=False, stats=None):
     an encoder (head=False) the list of per-level context tensors."""
     L = cfg.levels
     skips = []
-    h = x
+    h = _ste_round(x) if EMULATE_BF16 else x
     for l in range(L):
         if l > 0:
             h = F.max_pool2d(h, 2)
@@ -162,7 +195,10 @@ def forward(cfg: UNetCfg, p, buf, x, ctx=None, training=False, stats=None):
     outs = [None] * L
     outs[L - 1] = h
     for l in range(L - 2, -1, -1):
-        h = torch.cat([up2(h), skips[l]], dim=1)
+        u = up2(h)
+        if EMULATE_BF16:
+            u = _ste_round(u)
+        h = torch.cat([u, skips[l]], dim=1)
         if cfg.context:
             h = torch.cat([h, ctx[l]], dim=1)
         h = _block(h, p, buf, f"dec{l}a", training, stats)

@@ -1,0 +1,1067 @@
+// U-Net kernels for gfx950: bf16 MFMA implicit-GEMM convolutions with FP32
+// accumulation, and the pointwise / pooling / resampling / loss / optimiser
+// kernels around them.  Activations are NHWC with a channel count that is a
+// multiple of 32.
+//
+// MFMA v_mfma_f32_16x16x32_bf16 operand layout (64 lanes):
+//   A (16 x 32): lane l holds row l % 16, k = 8 (l / 16) .. 8 (l / 16) + 7
+//   B (32 x 16): lane l holds col l % 16, the same k range
+//   D (16 x 16): lane l holds col l % 16, rows 4 (l / 16) .. 4 (l / 16) + 3
+#include <algorithm>
+
+#include "unet_internal.h"
+
+namespace helm {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ------------------------------------------------------------------ conv fwd
+// Block: 4 wavefronts; tile TH = 4 MF rows x 16 columns of pixels and
+// CO = 16 NF output channels.  Wavefront w owns pixel rows w MF .. w MF +
+// MF - 1 (one 16-pixel M fragment per row) and all NF channel fragments.
+// K loop: 32-channel chunks of the concatenated input; per chunk the input
+// halo tile and the chunk's weights for all 9 taps are staged in LDS.
+template <int MF, int NF>
+__global__ __launch_bounds__(256) void k_conv3x3(Srcs in, int H, int W,
+                                                 const bf16 *__restrict__ Wt, int Cout, int mode,
+                                                 float *__restrict__ out32,
+                                                 bf16 *__restrict__ out16,
+                                                 const float *__restrict__ scale,
+                                                 const float *__restrict__ shift, float slope)
+{
+    constexpr int TW = 16, TH = 4 * MF, HX = TW + 2, HY = TH + 2;
+    constexpr int PS = 40;           // LDS halves per pixel: 32 channels + pad
+    constexpr int CO = 16 * NF;
+    constexpr int WS = 9 * 32 + 8;   // LDS halves per output channel row
+    __shared__ __attribute__((aligned(16))) bf16 sx[HY * HX * PS];
+    __shared__ __attribute__((aligned(16))) bf16 sw[CO * WS];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ncob = (Cout + CO - 1) / CO;
+    const int b = blockIdx.z / ncob, co0 = (blockIdx.z % ncob) * CO;
+    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+    f32x4 acc[MF][NF];
+#pragma unroll
+    for (int i = 0; i < MF; ++i)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nch = in.Ctot / 32;
+    for (int ch = 0; ch < nch; ++ch) {
+        int coff = ch * 32, s = 0;
+        while (s < in.n - 1 && coff >= in.s[s].C) {
+            coff -= in.s[s].C;
+            ++s;
+        }
+        const bf16 *src = in.s[s].p;
+        const int Cs = in.s[s].C;
+        for (int idx = tid; idx < HY * HX * 4; idx += 256) {
+            int seg = idx & 3, pix = idx >> 2;
+            int ty = pix / HX, tx = pix - ty * HX;
+            int y = y0 + ty - 1, x = x0 + tx - 1;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (y >= 0 && y < H && x >= 0 && x < W)
+                v = *reinterpret_cast<const uint4 *>(src + (((size_t)b * H + y) * W + x) * Cs +
+                                                     coff + seg * 8);
+            *reinterpret_cast<uint4 *>(&sx[pix * PS + seg * 8]) = v;
+        }
+        for (int idx = tid; idx < CO * 36; idx += 256) {
+            int seg = idx & 3, r = idx >> 2;
+            int co = r / 9, tap = r - co * 9;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (co0 + co < Cout)
+                v = *reinterpret_cast<const uint4 *>(Wt + ((size_t)(co0 + co) * 9 + tap) * in.Ctot +
+                                                     ch * 32 + seg * 8);
+            *reinterpret_cast<uint4 *>(&sw[co * WS + tap * 32 + seg * 8]) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+            bf16x8 a[MF], bw[NF];
+#pragma unroll
+            for (int mf = 0; mf < MF; ++mf) {
+                int ty = wv * MF + mf, tx = lane & 15;
+                a[mf] = *reinterpret_cast<const bf16x8 *>(
+                    &sx[((ty + ky) * HX + tx + kx) * PS + 8 * (lane >> 4)]);
+            }
+#pragma unroll
+            for (int nf = 0; nf < NF; ++nf)
+                bw[nf] = *reinterpret_cast<const bf16x8 *>(
+                    &sw[(nf * 16 + (lane & 15)) * WS + tap * 32 + 8 * (lane >> 4)]);
+#pragma unroll
+            for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+                for (int nf = 0; nf < NF; ++nf)
+                    acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mf], bw[nf], acc[mf][nf],
+                                                                          0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+        for (int nf = 0; nf < NF; ++nf)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int y = y0 + wv * MF + mf, x = x0 + 4 * (lane >> 4) + q;
+                const int co = co0 + nf * 16 + (lane & 15);
+                if (y < H && x < W && co < Cout) {
+                    const size_t o = (((size_t)b * H + y) * W + x) * Cout + co;
+                    float v = acc[mf][nf][q];
+                    if (mode == 0) {
+                        out32[o] = v;
+                    } else {
+                        float z = v * scale[co] + shift[co];
+                        out16[o] = (bf16)(z > 0.f ? z : slope * z);
+                    }
+                }
+            }
+}
+
+// ------------------------------------------------------------------ wgrad
+// dW[co][tap][ci] over a range of pixels (split K).  Block tile: 64 output x
+// 64 input channels for one tap; K steps of 32 pixels staged transposed in
+// LDS ([channel][pixel]) so each MFMA fragment is one 16-byte LDS read.
+// Wavefront w owns output-channel rows 16 w .. 16 w + 15 and all 4 input
+// channel fragments.
+constexpr int WG_CB = 64, WG_IB = 64, WG_K = 32, WG_PAD = 40;
+
+__global__ __launch_bounds__(256) void k_wgrad(Srcs x, const bf16 *__restrict__ dy, int B, int H,
+                                               int W, int Cout, int npix_split,
+                                               float *__restrict__ part)
+{
+    __shared__ __attribute__((aligned(16))) bf16 sa[WG_CB * WG_PAD];
+    __shared__ __attribute__((aligned(16))) bf16 sb[WG_IB * WG_PAD];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ncb = (Cout + WG_CB - 1) / WG_CB, nib = (x.Ctot + WG_IB - 1) / WG_IB;
+    const int tap = blockIdx.y % 9;
+    const int cb = (blockIdx.y / 9) % ncb, ib = (blockIdx.y / 9) / ncb;
+    const int split = blockIdx.x;
+    const int dyo = tap / 3 - 1, dxo = tap % 3 - 1;
+    const size_t P = (size_t)B * H * W;
+    const size_t p_begin = (size_t)split * npix_split;
+    const size_t p_end = std::min(P, p_begin + (size_t)npix_split);
+    f32x4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // loader mapping: thread t -> pixel t / 8, 8-channel segment t % 8
+    const int lp = tid >> 3, lseg = tid & 7;
+    const int co_l = cb * WG_CB + lseg * 8, ci_l = ib * WG_IB + lseg * 8;
+    // source of this thread's input-channel segment
+    int s = 0, coff = ci_l;
+    while (s < x.n - 1 && coff >= x.s[s].C) {
+        coff -= x.s[s].C;
+        ++s;
+    }
+    const bool ci_ok = ci_l < x.Ctot;
+    for (size_t p0 = p_begin; p0 < p_end; p0 += WG_K) {
+        const size_t p = p0 + lp;
+        uint4 va = {0u, 0u, 0u, 0u}, vb = {0u, 0u, 0u, 0u};
+        if (p < p_end) {
+            if (co_l < Cout) va = *reinterpret_cast<const uint4 *>(dy + p * Cout + co_l);
+            const int xx = (int)(p % W), yy = (int)((p / W) % H);
+            const size_t bb = p / ((size_t)W * H);
+            const int ys = yy + dyo, xs = xx + dxo;
+            if (ci_ok && ys >= 0 && ys < H && xs >= 0 && xs < W)
+                vb = *reinterpret_cast<const uint4 *>(
+                    x.s[s].p + ((bb * H + ys) * W + xs) * x.s[s].C + coff);
+        }
+        const bf16 *ea = reinterpret_cast<const bf16 *>(&va);
+        const bf16 *eb = reinterpret_cast<const bf16 *>(&vb);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            sa[(lseg * 8 + q) * WG_PAD + lp] = ea[q];
+            sb[(lseg * 8 + q) * WG_PAD + lp] = eb[q];
+        }
+        __syncthreads();
+        bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sa[(wv * 16 + (lane & 15)) * WG_PAD + 8 * (lane >> 4)]);
+#pragma unroll
+        for (int nf = 0; nf < 4; ++nf) {
+            bf16x8 bw = *reinterpret_cast<const bf16x8 *>(
+                &sb[(nf * 16 + (lane & 15)) * WG_PAD + 8 * (lane >> 4)]);
+            acc[nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[nf], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // partial[split][co][tap][ci]
+    const size_t per_split = (size_t)Cout * 9 * x.Ctot;
+#pragma unroll
+    for (int nf = 0; nf < 4; ++nf)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int co = cb * WG_CB + wv * 16 + 4 * (lane >> 4) + q;
+            const int ci = ib * WG_IB + nf * 16 + (lane & 15);
+            if (co < Cout && ci < x.Ctot)
+                part[split * per_split + ((size_t)co * 9 + tap) * x.Ctot + ci] = acc[nf][q];
+        }
+}
+
+__global__ void k_sum_splits(const float *__restrict__ part, int nsplit, size_t n,
+                             float *__restrict__ out)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        float acc = 0.f;
+        for (int s = 0; s < nsplit; ++s) acc += part[(size_t)s * n + i];
+        out[i] = acc;
+    }
+}
+
+// ------------------------------------------------------------------ BN
+// per-block partial sums (FP64) of y and y^2 per channel; thread t handles
+// channel t % C and pixels t / C + k * (256 / C)
+__global__ __launch_bounds__(256) void k_bn_partial(const float *__restrict__ y, size_t P, int C,
+                                                    double *__restrict__ part, int nblk)
+{
+    const int t = threadIdx.x, c = t % C, r0 = t / C, rs = 256 / C;
+    double s1 = 0.0, s2 = 0.0;
+    if (r0 < rs)
+        for (size_t p = (size_t)blockIdx.x * rs + r0; p < P; p += (size_t)nblk * rs) {
+            double v = y[p * C + c];
+            s1 += v;
+            s2 += v * v;
+        }
+    __shared__ double sh1[256], sh2[256];
+    sh1[t] = s1;
+    sh2[t] = s2;
+    __syncthreads();
+    if (t < C) {
+        double a = 0.0, q = 0.0;
+        for (int r = 0; r < rs; ++r) {
+            a += sh1[r * C + t];
+            q += sh2[r * C + t];
+        }
+        part[((size_t)blockIdx.x * C + t) * 2] = a;
+        part[((size_t)blockIdx.x * C + t) * 2 + 1] = q;
+    }
+}
+
+__global__ void k_bn_finish(const double *__restrict__ part, int nblk, int C, size_t P,
+                            float *__restrict__ mean, float *__restrict__ rstd,
+                            float *__restrict__ var_out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    double a = 0.0, q = 0.0;
+    for (int k = 0; k < nblk; ++k) {
+        a += part[((size_t)k * C + c) * 2];
+        q += part[((size_t)k * C + c) * 2 + 1];
+    }
+    double mu = a / (double)P, var = q / (double)P - mu * mu;
+    if (var < 0.0) var = 0.0;
+    mean[c] = (float)mu;
+    rstd[c] = (float)(1.0 / sqrt(var + 1e-5));
+    if (var_out) var_out[c] = (float)var;
+}
+
+__global__ void k_bn_act_fwd(const float *__restrict__ y, size_t n, int C,
+                             const float *__restrict__ mean, const float *__restrict__ rstd,
+                             const float *__restrict__ g, const float *__restrict__ bb, float slope,
+                             bf16 *__restrict__ a)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        int c = (int)(i % C);
+        float z = g[c] * (y[i] - mean[c]) * rstd[c] + bb[c];
+        a[i] = (bf16)(z > 0.f ? z : slope * z);
+    }
+}
+
+// partial sums of dz and dz * xhat per channel
+__global__ __launch_bounds__(256) void k_bn_bwd_partial(
+    const float *__restrict__ da, const float *__restrict__ y, size_t P, int C,
+    const float *__restrict__ mean, const float *__restrict__ rstd, const float *__restrict__ g,
+    const float *__restrict__ bb, float slope, double *__restrict__ part, int nblk)
+{
+    const int t = threadIdx.x, c = t % C, r0 = t / C, rs = 256 / C;
+    double s1 = 0.0, s2 = 0.0;
+    if (r0 < rs)
+        for (size_t p = (size_t)blockIdx.x * rs + r0; p < P; p += (size_t)nblk * rs) {
+            float xh = (y[p * C + c] - mean[c]) * rstd[c];
+            float z = g[c] * xh + bb[c];
+            float dz = da[p * C + c] * (z > 0.f ? 1.f : slope);
+            s1 += dz;
+            s2 += (double)dz * xh;
+        }
+    __shared__ double sh1[256], sh2[256];
+    sh1[t] = s1;
+    sh2[t] = s2;
+    __syncthreads();
+    if (t < C) {
+        double a = 0.0, q = 0.0;
+        for (int r = 0; r < rs; ++r) {
+            a += sh1[r * C + t];
+            q += sh2[r * C + t];
+        }
+        part[((size_t)blockIdx.x * C + t) * 2] = a;
+        part[((size_t)blockIdx.x * C + t) * 2 + 1] = q;
+    }
+}
+
+__global__ void k_bn_bwd_finish(const double *__restrict__ part, int nblk, int C,
+                                float *__restrict__ dg, float *__restrict__ db,
+                                float *__restrict__ sums)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    double a = 0.0, q = 0.0;
+    for (int k = 0; k < nblk; ++k) {
+        a += part[((size_t)k * C + c) * 2];
+        q += part[((size_t)k * C + c) * 2 + 1];
+    }
+    db[c] += (float)a;
+    dg[c] += (float)q;
+    sums[2 * c] = (float)a;
+    sums[2 * c + 1] = (float)q;
+}
+
+__global__ void k_bn_bwd_apply(const float *__restrict__ da, const float *__restrict__ y, size_t n,
+                               int C, size_t P, const float *__restrict__ mean,
+                               const float *__restrict__ rstd, const float *__restrict__ g,
+                               const float *__restrict__ bb, float slope,
+                               const float *__restrict__ sums, bf16 *__restrict__ dy)
+{
+    const float invP = 1.f / (float)P;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        int c = (int)(i % C);
+        float xh = (y[i] - mean[c]) * rstd[c];
+        float z = g[c] * xh + bb[c];
+        float dz = da[i] * (z > 0.f ? 1.f : slope);
+        float v = g[c] * rstd[c] * (dz - sums[2 * c] * invP - xh * sums[2 * c + 1] * invP);
+        dy[i] = (bf16)v;
+    }
+}
+
+// ------------------------------------------------------------------ pooling
+__global__ void k_maxpool_fwd(const bf16 *__restrict__ in, int B, int H, int W, int C,
+                              bf16 *__restrict__ out, uint8_t *__restrict__ arg)
+{
+    const int Ho = H / 2, Wo = W / 2;
+    const size_t n = (size_t)B * Ho * Wo * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        int c = (int)(i % C);
+        size_t r = i / C;
+        int xo = (int)(r % Wo), yo = (int)((r / Wo) % Ho);
+        size_t b = r / ((size_t)Wo * Ho);
+        size_t base = ((b * H + 2 * yo) * W + 2 * xo) * C + c;
+        float v0 = (float)in[base], v1 = (float)in[base + C];
+        float v2 = (float)in[base + (size_t)W * C], v3 = (float)in[base + (size_t)W * C + C];
+        float best = v0;
+        uint8_t k = 0;
+        if (v1 > best) { best = v1; k = 1; }
+        if (v2 > best) { best = v2; k = 2; }
+        if (v3 > best) { best = v3; k = 3; }
+        out[i] = (bf16)best;
+        if (arg) arg[i] = k;
+    }
+}
+
+__global__ void k_maxpool_bwd(const float *__restrict__ dout, const uint8_t *__restrict__ arg,
+                              int B, int H, int W, int C, float *__restrict__ din, int din_C,
+                              int coff)
+{
+    const int Ho = H / 2, Wo = W / 2;
+    const size_t n = (size_t)B * Ho * Wo * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        int c = (int)(i % C);
+        size_t r = i / C;
+        int xo = (int)(r % Wo), yo = (int)((r / Wo) % Ho);
+        size_t b = r / ((size_t)Wo * Ho);
+        float g = dout[i];
+        int k = arg[i];
+        int yy = 2 * yo + (k >> 1), xx = 2 * xo + (k & 1);
+        din[((b * H + yy) * W + xx) * din_C + coff + c] += g;
+    }
+}
+
+// ------------------------------------------------------------------ upsampling
+__device__ __forceinline__ void up_src(int o, int n, int &i0, int &i1, float &l1)
+{
+    float src = (o + 0.5f) * 0.5f - 0.5f;
+    src = src < 0.f ? 0.f : src;
+    i0 = (int)src;
+    i1 = i0 + 1 < n ? i0 + 1 : n - 1;
+    l1 = src - (float)i0;
+}
+
+__global__ void k_up2_fwd(const bf16 *__restrict__ in, int B, int h, int w, int C,
+                          bf16 *__restrict__ out)
+{
+    const int H = 2 * h, W = 2 * w;
+    const size_t n = (size_t)B * H * W * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        int c = (int)(i % C);
+        size_t r = i / C;
+        int x = (int)(r % W), y = (int)((r / W) % H);
+        size_t b = r / ((size_t)W * H);
+        int y0, y1, x0, x1;
+        float ly, lx;
+        up_src(y, h, y0, y1, ly);
+        up_src(x, w, x0, x1, lx);
+        const bf16 *pb = in + b * h * w * C + c;
+        float v = (1.f - ly) * ((1.f - lx) * (float)pb[((size_t)y0 * w + x0) * C] +
+                                lx * (float)pb[((size_t)y0 * w + x1) * C]) +
+                  ly * ((1.f - lx) * (float)pb[((size_t)y1 * w + x0) * C] +
+                        lx * (float)pb[((size_t)y1 * w + x1) * C]);
+        out[i] = (bf16)v;
+    }
+}
+
+// 1D adjoint weights of the half-pixel x2 interpolation: coarse i receives
+// from fine 2i-1 (1/4), 2i (3/4, +1/4 at i = 0), 2i+1 (3/4, +1/4 at i = n-1),
+// 2i+2 (1/4).
+__device__ __forceinline__ void up_adj(int i, int n, int *o, float *wt)
+{
+    o[0] = 2 * i - 1; wt[0] = i >= 1 ? 0.25f : 0.f;
+    o[1] = 2 * i;     wt[1] = 0.75f + (i == 0 ? 0.25f : 0.f);
+    o[2] = 2 * i + 1; wt[2] = 0.75f + (i == n - 1 ? 0.25f : 0.f);
+    o[3] = 2 * i + 2; wt[3] = i <= n - 2 ? 0.25f : 0.f;
+}
+
+__global__ void k_up2_bwd(const float *__restrict__ dout, int cstride, int coff, int B, int h, int w,
+                          int C, float *__restrict__ din, int accumulate)
+{
+    const int H = 2 * h, W = 2 * w;
+    const size_t n = (size_t)B * h * w * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        int c = (int)(i % C);
+        size_t r = i / C;
+        int xi = (int)(r % w), yi = (int)((r / w) % h);
+        size_t b = r / ((size_t)w * h);
+        int oy[4], ox[4];
+        float wy[4], wx[4];
+        up_adj(yi, h, oy, wy);
+        up_adj(xi, w, ox, wx);
+        float acc = 0.f;
+        for (int a = 0; a < 4; ++a) {
+            if (wy[a] == 0.f) continue;
+            for (int d = 0; d < 4; ++d) {
+                if (wx[d] == 0.f) continue;
+                acc += wy[a] * wx[d] *
+                       dout[((b * H + oy[a]) * W + ox[d]) * cstride + coff + c];
+            }
+        }
+        din[i] = accumulate ? din[i] + acc : acc;
+    }
+}
+
+__global__ void k_slice_add(const float *__restrict__ src, int cstride, int coff, size_t P, int C,
+                            float *__restrict__ dst, int accumulate)
+{
+    const size_t n = P * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        size_t p = i / C;
+        int c = (int)(i % C);
+        float v = src[p * cstride + coff + c];
+        dst[i] = accumulate ? dst[i] + v : v;
+    }
+}
+
+__global__ void k_f32_to_bf16(const float *__restrict__ x, size_t n, bf16 *__restrict__ y)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        y[i] = (bf16)x[i];
+}
+
+// ------------------------------------------------------------------ head
+__global__ void k_head_fwd(const bf16 *__restrict__ a, size_t P, int C, const float *__restrict__ Wh,
+                           const float *__restrict__ bh, float *__restrict__ out)
+{
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+         p += (size_t)gridDim.x * blockDim.x) {
+        float s0 = bh[0], s1 = bh[1];
+        for (int c = 0; c < C; ++c) {
+            float v = (float)a[p * C + c];
+            s0 += Wh[c] * v;
+            s1 += Wh[C + c] * v;
+        }
+        out[2 * p] = s0;
+        out[2 * p + 1] = s1;
+    }
+}
+
+// da[p][c] = sum_k Wh[k][c] dout[p][k]; per-block partial sums of
+// dout[p][k] a[p][c] (entries 0..2C-1) and dout[p][k] (2C, 2C+1)
+__global__ __launch_bounds__(256) void k_head_bwd(const float *__restrict__ dout,
+                                                  const bf16 *__restrict__ a, size_t P, int C,
+                                                  const float *__restrict__ Wh,
+                                                  float *__restrict__ da,
+                                                  double *__restrict__ part, int nblk)
+{
+    __shared__ double sh[256][2];
+    const int t = threadIdx.x;
+    // pass 1: da (one thread per pixel)
+    for (size_t p = (size_t)blockIdx.x * 256 + t; p < P; p += (size_t)nblk * 256) {
+        float g0 = dout[2 * p], g1 = dout[2 * p + 1];
+        for (int c = 0; c < C; ++c) da[p * C + c] = Wh[c] * g0 + Wh[C + c] * g1;
+    }
+    // pass 2: sums, thread t handles column c = t % (2C+2) of the parameter gradient
+    const int ncol = 2 * C + 2;
+    const int col = t % ncol, r0 = t / ncol, rs = 256 / ncol;
+    double acc = 0.0;
+    if (r0 < rs)
+        for (size_t p = (size_t)blockIdx.x * rs + r0; p < P; p += (size_t)nblk * rs) {
+            if (col < 2 * C) {
+                int k = col / C, c = col % C;
+                acc += (double)dout[2 * p + k] * (float)a[p * C + c];
+            } else {
+                acc += dout[2 * p + (col - 2 * C)];
+            }
+        }
+    sh[t][0] = acc;
+    __syncthreads();
+    if (t < ncol) {
+        double s = 0.0;
+        for (int r = 0; r < rs; ++r) s += sh[r * ncol + t][0];
+        part[(size_t)blockIdx.x * ncol + t] = s;
+    }
+}
+
+__global__ void k_head_bwd_finish(const double *__restrict__ part, int nblk, int C,
+                                  float *__restrict__ dWh, float *__restrict__ dbh)
+{
+    const int ncol = 2 * C + 2;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ncol) return;
+    double s = 0.0;
+    for (int k = 0; k < nblk; ++k) s += part[(size_t)k * ncol + t];
+    if (t < 2 * C)
+        dWh[t] += (float)s;
+    else
+        dbh[t - 2 * C] += (float)s;
+}
+
+// ------------------------------------------------------------------ wrapper
+// rc = R(h^2 r) (full weighting, zero outside) and partial sums of |rc|^2
+__global__ __launch_bounds__(256) void k_restrict_scaled(const float2 *__restrict__ r, size_t rs,
+                                                         int n, float2 *__restrict__ rc,
+                                                         double *__restrict__ part, int nblk)
+{
+    const int b = blockIdx.y, nc = n / 2;
+    const float h2 = 1.f / ((float)n * (float)n);
+    const float2 *rb = r + (size_t)b * rs;
+    double acc = 0.0;
+    for (int idx = blockIdx.x * 256 + threadIdx.x; idx < nc * nc; idx += nblk * 256) {
+        int I = idx / nc, J = idx - I * nc;
+        float sr = 0.f, si = 0.f;
+        for (int a = -1; a <= 1; ++a)
+            for (int c = -1; c <= 1; ++c) {
+                int i = 2 * I + a, j = 2 * J + c;
+                if (i < 0 || j < 0 || i >= n || j >= n) continue;
+                float wgt = (a == 0 ? 0.5f : 0.25f) * (c == 0 ? 0.5f : 0.25f);
+                float2 v = rb[(size_t)i * n + j];
+                sr += wgt * v.x;
+                si += wgt * v.y;
+            }
+        sr *= h2;
+        si *= h2;
+        rc[(size_t)b * nc * nc + idx] = make_float2(sr, si);
+        acc += (double)sr * sr + (double)si * si;
+    }
+    acc = wave_sum(acc);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(size_t)b * nblk + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void k_rms(const double *__restrict__ part, int nblk, int nc, double *__restrict__ s)
+{
+    const int b = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    double a = 0.0;
+    for (int k = 0; k < nblk; ++k) a += part[(size_t)b * nblk + k];
+    s[b] = sqrt(a / ((double)nc * nc));
+}
+
+__global__ void k_pack_input(const float2 *__restrict__ rc, const double *__restrict__ s, int nb,
+                             int n, const float *__restrict__ kf, const float *__restrict__ kc,
+                             bf16 *__restrict__ x0)
+{
+    const int nc = n / 2;
+    const size_t total = (size_t)nb * nc * nc;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        int b = (int)(i / ((size_t)nc * nc));
+        size_t pix = i % ((size_t)nc * nc);
+        int I = (int)(pix / nc), J = (int)(pix % nc);
+        float inv = s[b] > 0.0 ? (float)(1.0 / s[b]) : 0.f;
+        float2 v = rc[i];
+        float kap = kf ? kf[(size_t)(2 * I) * n + 2 * J] : kc[i];
+        bf16 *o = x0 + i * 32;
+        o[0] = (bf16)(v.x * inv);
+        o[1] = (bf16)(v.y * inv);
+        o[2] = (bf16)kap;
+        for (int c = 3; c < 32; ++c) o[c] = (bf16)0.f;
+    }
+}
+
+// e (+)= P(s (out0 + i out1)), P bilinear prolongation (transposed stride-2
+// convolution with (1/4)[1 2 1; 2 4 2; 1 2 1])
+__global__ void k_net_output(const float *__restrict__ out, const double *__restrict__ s, int nb,
+                             int n, float2 *__restrict__ e, size_t es, int accumulate)
+{
+    const int nc = n / 2;
+    const size_t total = (size_t)nb * n * n;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        int b = (int)(idx / ((size_t)n * n));
+        size_t pix = idx % ((size_t)n * n);
+        int i = (int)(pix / n), j = (int)(pix % n);
+        const float *ob = out + (size_t)b * nc * nc * 2;
+        float sr = 0.f, si = 0.f;
+        int Ia = i >> 1, Ib = (i + 1) >> 1, Ja = j >> 1, Jb = (j + 1) >> 1;
+        float wi = (i & 1) ? 0.5f : 1.f, wj = (j & 1) ? 0.5f : 1.f;
+        for (int u = 0; u < ((i & 1) ? 2 : 1); ++u) {
+            int I = u ? Ib : Ia;
+            if (I >= nc) continue;
+            for (int v = 0; v < ((j & 1) ? 2 : 1); ++v) {
+                int J = v ? Jb : Ja;
+                if (J >= nc) continue;
+                sr += ob[((size_t)I * nc + J) * 2];
+                si += ob[((size_t)I * nc + J) * 2 + 1];
+            }
+        }
+        float sc = (float)s[b] * wi * wj;
+        float2 val = make_float2(sc * sr, sc * si);
+        float2 *pe = e + (size_t)b * es + pix;
+        if (accumulate) {
+            float2 o = *pe;
+            val.x += o.x;
+            val.y += o.y;
+        }
+        *pe = val;
+    }
+}
+
+// d = P(out_b) - e_b / s_b on the fine grid, partial sums of |d|^2
+__global__ __launch_bounds__(256) void k_loss_fine(const float *__restrict__ out,
+                                                   const double *__restrict__ s, int n,
+                                                   const float2 *__restrict__ e,
+                                                   float2 *__restrict__ d,
+                                                   double *__restrict__ part, int nblk)
+{
+    const int b = blockIdx.y, nc = n / 2;
+    const float *ob = out + (size_t)b * nc * nc * 2;
+    const float inv = s[b] > 0.0 ? (float)(1.0 / s[b]) : 0.f;
+    double acc = 0.0;
+    for (int pix = blockIdx.x * 256 + threadIdx.x; pix < n * n; pix += nblk * 256) {
+        int i = pix / n, j = pix - i * n;
+        float sr = 0.f, si = 0.f;
+        int Ia = i >> 1, Ib = (i + 1) >> 1, Ja = j >> 1, Jb = (j + 1) >> 1;
+        float wi = (i & 1) ? 0.5f : 1.f, wj = (j & 1) ? 0.5f : 1.f;
+        for (int u = 0; u < ((i & 1) ? 2 : 1); ++u) {
+            int I = u ? Ib : Ia;
+            if (I >= nc) continue;
+            for (int v = 0; v < ((j & 1) ? 2 : 1); ++v) {
+                int J = v ? Jb : Ja;
+                if (J >= nc) continue;
+                sr += ob[((size_t)I * nc + J) * 2];
+                si += ob[((size_t)I * nc + J) * 2 + 1];
+            }
+        }
+        float2 t = e[(size_t)b * n * n + pix];
+        float dr = wi * wj * sr - t.x * inv, di = wi * wj * si - t.y * inv;
+        d[(size_t)b * n * n + pix] = make_float2(dr, di);
+        acc += (double)dr * dr + (double)di * di;
+    }
+    acc = wave_sum(acc);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(size_t)b * nblk + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// dout = (2 / (B n^2)) P^T d with P^T = 4 R
+__global__ void k_loss_back(const float2 *__restrict__ d, int nb, int n, float *__restrict__ dout)
+{
+    const int nc = n / 2;
+    const float k = 8.f / ((float)nb * (float)n * (float)n);
+    const size_t total = (size_t)nb * nc * nc;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        int b = (int)(idx / ((size_t)nc * nc));
+        size_t pix = idx % ((size_t)nc * nc);
+        int I = (int)(pix / nc), J = (int)(pix % nc);
+        const float2 *db = d + (size_t)b * n * n;
+        float sr = 0.f, si = 0.f;
+        for (int a = -1; a <= 1; ++a)
+            for (int c = -1; c <= 1; ++c) {
+                int i = 2 * I + a, j = 2 * J + c;
+                if (i < 0 || j < 0 || i >= n || j >= n) continue;
+                float wgt = (a == 0 ? 0.5f : 0.25f) * (c == 0 ? 0.5f : 0.25f);
+                float2 v = db[(size_t)i * n + j];
+                sr += wgt * v.x;
+                si += wgt * v.y;
+            }
+        dout[2 * idx] = k * sr;
+        dout[2 * idx + 1] = k * si;
+    }
+}
+
+__global__ void k_loss_finish(const double *__restrict__ part, int nblk, int nb, int n,
+                              double *__restrict__ loss)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a = 0.0;
+    for (int b = 0; b < nb; ++b)
+        for (int k = 0; k < nblk; ++k) a += part[(size_t)b * nblk + k];
+    *loss = a / ((double)n * n) / nb;
+}
+
+// ------------------------------------------------------------------ params
+__global__ void k_pack_weights(const float *__restrict__ Wc, int Cout, int Cin,
+                               const int *__restrict__ map, int Cpad, bf16 *__restrict__ Wp,
+                               bf16 *__restrict__ Wd)
+{
+    const size_t total = (size_t)Cout * 9 * Cpad;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        int cp = (int)(i % Cpad);
+        int tap = (int)((i / Cpad) % 9);
+        int co = (int)(i / ((size_t)Cpad * 9));
+        int ci = map[cp];
+        float w = ci >= 0 ? Wc[((size_t)co * Cin + ci) * 9 + tap] : 0.f;
+        float wf = ci >= 0 ? Wc[((size_t)co * Cin + ci) * 9 + (8 - tap)] : 0.f;
+        Wp[i] = (bf16)w;
+        Wd[((size_t)cp * 9 + tap) * Cout + co] = (bf16)wf;
+    }
+}
+
+__global__ void k_unpack_wgrad(const float *__restrict__ dW, int Cout, int Cin,
+                               const int *__restrict__ map, int Cpad, float *__restrict__ gW)
+{
+    const size_t total = (size_t)Cout * 9 * Cpad;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        int cp = (int)(i % Cpad);
+        int tap = (int)((i / Cpad) % 9);
+        int co = (int)(i / ((size_t)Cpad * 9));
+        int ci = map[cp];
+        if (ci >= 0) gW[((size_t)co * Cin + ci) * 9 + tap] += dW[i];
+    }
+}
+
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, size_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        float gi = g[i];
+        float mi = b1 * m[i] + (1.f - b1) * gi;
+        float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+__global__ void k_bn_running(float *__restrict__ rm, float *__restrict__ rv,
+                             const float *__restrict__ mean, const float *__restrict__ var, int C,
+                             float mom, float unb)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    rm[c] = (1.f - mom) * rm[c] + mom * mean[c];
+    rv[c] = (1.f - mom) * rv[c] + mom * var[c] * unb;
+}
+
+__global__ void k_fold_bn(const float *__restrict__ g, const float *__restrict__ b,
+                          const float *__restrict__ rm, const float *__restrict__ rv, int C,
+                          float eps, float *__restrict__ scale, float *__restrict__ shift)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    float sc = g[c] / sqrtf(rv[c] + eps);
+    scale[c] = sc;
+    shift[c] = b[c] - rm[c] * sc;
+}
+
+__global__ void k_nchw_to_nhwc(const float *__restrict__ x, int B, int C, int H, int W, int Cp,
+                               bf16 *__restrict__ y)
+{
+    const size_t n = (size_t)B * H * W * Cp;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        int c = (int)(i % Cp);
+        size_t p = i / Cp;
+        int xx = (int)(p % W), yy = (int)((p / W) % H);
+        size_t b = p / ((size_t)W * H);
+        y[i] = c < C ? (bf16)x[((b * C + c) * H + yy) * W + xx] : (bf16)0.f;
+    }
+}
+
+__global__ void k_nhwc_to_nchw(const float *__restrict__ x, int B, int C, int H, int W,
+                               float *__restrict__ y)
+{
+    const size_t n = (size_t)B * H * W * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        int xx = (int)(i % W), yy = (int)((i / W) % H);
+        int c = (int)((i / ((size_t)W * H)) % C);
+        size_t b = i / ((size_t)W * H * C);
+        y[i] = x[((b * H + yy) * W + xx) * C + c];
+    }
+}
+
+inline int grid_for(size_t n, int block = 256, int cap = 8192)
+{
+    size_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > (size_t)cap) g = cap;
+    return (int)g;
+}
+
+inline int red_blocks(size_t P, int C)
+{
+    size_t rows = 256 / C;
+    size_t b = (P + rows * 64 - 1) / (rows * 64);
+    if (b < 1) b = 1;
+    if (b > 512) b = 512;
+    return (int)b;
+}
+
+}  // namespace
+
+// ================================================================== launchers
+
+void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout, int mode,
+                    float *out32, bf16 *out16, const float *scale, const float *shift,
+                    float slope, hipStream_t s)
+{
+    // wide tiles for large images, narrow channel blocks for 32-channel layers
+    const bool tall = H >= 64;
+    const int NF = Cout >= 64 ? 4 : 2;
+    const int CO = 16 * NF;
+    const int TH = tall ? 16 : 8;
+    dim3 grid((W + 15) / 16, (H + TH - 1) / TH, B * ((Cout + CO - 1) / CO));
+    if (tall && NF == 4)
+        hipLaunchKernelGGL((k_conv3x3<4, 4>), grid, dim3(256), 0, s, in, H, W, Wt, Cout, mode, out32,
+                           out16, scale, shift, slope);
+    else if (tall)
+        hipLaunchKernelGGL((k_conv3x3<4, 2>), grid, dim3(256), 0, s, in, H, W, Wt, Cout, mode, out32,
+                           out16, scale, shift, slope);
+    else if (NF == 4)
+        hipLaunchKernelGGL((k_conv3x3<2, 4>), grid, dim3(256), 0, s, in, H, W, Wt, Cout, mode, out32,
+                           out16, scale, shift, slope);
+    else
+        hipLaunchKernelGGL((k_conv3x3<2, 2>), grid, dim3(256), 0, s, in, H, W, Wt, Cout, mode, out32,
+                           out16, scale, shift, slope);
+}
+
+static int wgrad_nsplit(int B, int H, int W, int Cout, int Ctot)
+{
+    size_t P = (size_t)B * H * W;
+    int blocks = 9 * ((Cout + WG_CB - 1) / WG_CB) * ((Ctot + WG_IB - 1) / WG_IB);
+    int want = std::max(1, 2048 / blocks);
+    size_t maxs = (P + 255) / 256;  // at least 256 pixels per split
+    return (int)std::max<size_t>(1, std::min<size_t>((size_t)want, maxs));
+}
+
+size_t wgrad_scratch(int B, int H, int W, int Cout, int Ctot)
+{
+    return (size_t)wgrad_nsplit(B, H, W, Cout, Ctot) * Cout * 9 * Ctot;
+}
+
+void launch_wgrad(const Srcs &x, const bf16 *dy, int B, int H, int W, int Cout, float *dW,
+                  float *part, hipStream_t s)
+{
+    size_t P = (size_t)B * H * W;
+    int nsplit = wgrad_nsplit(B, H, W, Cout, x.Ctot);
+    int per = (int)(((P + nsplit - 1) / nsplit + WG_K - 1) / WG_K * WG_K);
+    nsplit = (int)((P + per - 1) / per);
+    dim3 grid(nsplit, 9 * ((Cout + WG_CB - 1) / WG_CB) * ((x.Ctot + WG_IB - 1) / WG_IB));
+    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, s, x, dy, B, H, W, Cout, per, part);
+    size_t n = (size_t)Cout * 9 * x.Ctot;
+    hipLaunchKernelGGL(k_sum_splits, dim3(grid_for(n)), dim3(256), 0, s, part, nsplit, n, dW);
+}
+
+void launch_bn_stats(const float *y, size_t P, int C, double *part, float *mean, float *rstd,
+                     float *var_out, hipStream_t s)
+{
+    int nblk = red_blocks(P, C);
+    hipLaunchKernelGGL(k_bn_partial, dim3(nblk), dim3(256), 0, s, y, P, C, part, nblk);
+    hipLaunchKernelGGL(k_bn_finish, dim3((C + 63) / 64), dim3(64), 0, s, part, nblk, C, P, mean, rstd,
+                       var_out);
+}
+
+void launch_bn_act_fwd(const float *y, size_t P, int C, const float *mean, const float *rstd,
+                       const float *g, const float *b, float slope, bf16 *a, hipStream_t s)
+{
+    size_t n = P * C;
+    hipLaunchKernelGGL(k_bn_act_fwd, dim3(grid_for(n)), dim3(256), 0, s, y, n, C, mean, rstd, g, b,
+                       slope, a);
+}
+
+void launch_bn_act_bwd(const float *da, const float *y, size_t P, int C, const float *mean,
+                       const float *rstd, const float *g, const float *b, float slope,
+                       double *part, float *dg, float *db, bf16 *dy, hipStream_t s)
+{
+    int nblk = red_blocks(P, C);
+    hipLaunchKernelGGL(k_bn_bwd_partial, dim3(nblk), dim3(256), 0, s, da, y, P, C, mean, rstd, g, b,
+                       slope, part, nblk);
+    // per-channel sums (dbeta, dgamma) go to the tail of `part`
+    float *sums = reinterpret_cast<float *>(part + (size_t)nblk * C * 2);
+    hipLaunchKernelGGL(k_bn_bwd_finish, dim3((C + 63) / 64), dim3(64), 0, s, part, nblk, C, dg, db,
+                       sums);
+    size_t n = P * C;
+    hipLaunchKernelGGL(k_bn_bwd_apply, dim3(grid_for(n)), dim3(256), 0, s, da, y, n, C, P, mean, rstd,
+                       g, b, slope, sums, dy);
+}
+
+void launch_maxpool_fwd(const bf16 *in, int B, int H, int W, int C, bf16 *out, uint8_t *arg,
+                        hipStream_t s)
+{
+    size_t n = (size_t)B * (H / 2) * (W / 2) * C;
+    hipLaunchKernelGGL(k_maxpool_fwd, dim3(grid_for(n)), dim3(256), 0, s, in, B, H, W, C, out, arg);
+}
+
+void launch_maxpool_bwd(const float *dout, const uint8_t *arg, int B, int H, int W, int C,
+                        int cstride_in, int coff_in, float *din, int din_C, hipStream_t s)
+{
+    (void)cstride_in;
+    size_t n = (size_t)B * (H / 2) * (W / 2) * C;
+    hipLaunchKernelGGL(k_maxpool_bwd, dim3(grid_for(n)), dim3(256), 0, s, dout, arg, B, H, W, C, din,
+                       din_C, coff_in);
+}
+
+void launch_up2_fwd(const bf16 *in, int B, int h, int w, int C, bf16 *out, hipStream_t s)
+{
+    size_t n = (size_t)B * 4 * h * w * C;
+    hipLaunchKernelGGL(k_up2_fwd, dim3(grid_for(n)), dim3(256), 0, s, in, B, h, w, C, out);
+}
+
+void launch_up2_bwd(const float *dout, int cstride, int coff, int B, int h, int w, int C,
+                    float *din, int accumulate, hipStream_t s)
+{
+    size_t n = (size_t)B * h * w * C;
+    hipLaunchKernelGGL(k_up2_bwd, dim3(grid_for(n)), dim3(256), 0, s, dout, cstride, coff, B, h, w, C,
+                       din, accumulate);
+}
+
+void launch_slice_add(const float *src, int cstride, int coff, size_t P, int C, float *dst,
+                      int accumulate, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_slice_add, dim3(grid_for(P * C)), dim3(256), 0, s, src, cstride, coff, P, C,
+                       dst, accumulate);
+}
+
+void launch_nchw_to_nhwc(const float *x, int B, int C, int H, int W, int Cp, bf16 *y, hipStream_t s)
+{
+    size_t n = (size_t)B * H * W * Cp;
+    hipLaunchKernelGGL(k_nchw_to_nhwc, dim3(grid_for(n)), dim3(256), 0, s, x, B, C, H, W, Cp, y);
+}
+
+void launch_nhwc_to_nchw(const float *x, int B, int C, int H, int W, float *y, hipStream_t s)
+{
+    size_t n = (size_t)B * H * W * C;
+    hipLaunchKernelGGL(k_nhwc_to_nchw, dim3(grid_for(n)), dim3(256), 0, s, x, B, C, H, W, y);
+}
+
+void launch_f32_to_bf16(const float *x, size_t n, bf16 *y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid_for(n)), dim3(256), 0, s, x, n, y);
+}
+
+void launch_head_fwd(const bf16 *a, size_t P, int C, const float *Wh, const float *bh, float *out,
+                     hipStream_t s)
+{
+    hipLaunchKernelGGL(k_head_fwd, dim3(grid_for(P)), dim3(256), 0, s, a, P, C, Wh, bh, out);
+}
+
+void launch_head_bwd(const float *dout, const bf16 *a, size_t P, int C, const float *Wh,
+                     float *da, double *part, float *dWh, float *dbh, hipStream_t s)
+{
+    int nblk = (int)std::min<size_t>(512, std::max<size_t>(1, (P + 1023) / 1024));
+    hipLaunchKernelGGL(k_head_bwd, dim3(nblk), dim3(256), 0, s, dout, a, P, C, Wh, da, part, nblk);
+    hipLaunchKernelGGL(k_head_bwd_finish, dim3(1), dim3(256), 0, s, part, nblk, C, dWh, dbh);
+}
+
+void launch_net_input(const float2 *r, size_t rstride, int nb, int n, const float *kappa_fine,
+                      const float *kappa_c, float2 *rc, double *part, double *s, bf16 *x0,
+                      hipStream_t st)
+{
+    int nc = n / 2;
+    int nblk = (int)std::min<size_t>(256, std::max<size_t>(1, ((size_t)nc * nc + 1023) / 1024));
+    hipLaunchKernelGGL(k_restrict_scaled, dim3(nblk, nb), dim3(256), 0, st, r, rstride, n, rc, part,
+                       nblk);
+    hipLaunchKernelGGL(k_rms, dim3(nb), dim3(64), 0, st, part, nblk, nc, s);
+    size_t tot = (size_t)nb * nc * nc;
+    hipLaunchKernelGGL(k_pack_input, dim3(grid_for(tot)), dim3(256), 0, st, rc, s, nb, n, kappa_fine,
+                       kappa_c, x0);
+}
+
+void launch_net_output(const float *out, const double *s, int nb, int n, float2 *e, size_t estride,
+                       int accumulate, hipStream_t st)
+{
+    size_t tot = (size_t)nb * n * n;
+    hipLaunchKernelGGL(k_net_output, dim3(grid_for(tot)), dim3(256), 0, st, out, s, nb, n, e, estride,
+                       accumulate);
+}
+
+void launch_loss_grad(const float *out, const double *s, int nb, int n, const float2 *e,
+                      float2 *dfine, double *part, float *dout, double *loss_out, hipStream_t st)
+{
+    int nblk = (int)std::min<size_t>(256, std::max<size_t>(1, ((size_t)n * n + 1023) / 1024));
+    hipLaunchKernelGGL(k_loss_fine, dim3(nblk, nb), dim3(256), 0, st, out, s, n, e, dfine, part, nblk);
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(64), 0, st, part, nblk, nb, n, loss_out);
+    size_t tot = (size_t)nb * (n / 2) * (n / 2);
+    hipLaunchKernelGGL(k_loss_back, dim3(grid_for(tot)), dim3(256), 0, st, dfine, nb, n, dout);
+}
+
+void launch_pack_weights(const float *W, int Cout, int Cin, const int *map, int Cpad, bf16 *Wp,
+                         bf16 *Wd, hipStream_t s)
+{
+    size_t n = (size_t)Cout * 9 * Cpad;
+    hipLaunchKernelGGL(k_pack_weights, dim3(grid_for(n)), dim3(256), 0, s, W, Cout, Cin, map, Cpad, Wp,
+                       Wd);
+}
+
+void launch_unpack_wgrad(const float *dW, int Cout, int Cin, const int *map, int Cpad, float *gW,
+                         hipStream_t s)
+{
+    size_t n = (size_t)Cout * 9 * Cpad;
+    hipLaunchKernelGGL(k_unpack_wgrad, dim3(grid_for(n)), dim3(256), 0, s, dW, Cout, Cin, map, Cpad,
+                       gW);
+}
+
+void launch_adam(float *p, const float *g, float *m, float *v, size_t n, float lr, float b1,
+                 float b2, float eps, int step, hipStream_t s)
+{
+    float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, c1,
+                       c2);
+}
+
+void launch_bn_running(float *rm, float *rv, const float *mean, const float *var, int C,
+                       float momentum, double count, hipStream_t s)
+{
+    float unb = count > 1.0 ? (float)(count / (count - 1.0)) : 1.f;
+    hipLaunchKernelGGL(k_bn_running, dim3((C + 63) / 64), dim3(64), 0, s, rm, rv, mean, var, C,
+                       momentum, unb);
+}
+
+void launch_fold_bn(const float *g, const float *b, const float *rm, const float *rv, int C,
+                    float eps, float *scale, float *shift, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fold_bn, dim3((C + 63) / 64), dim3(64), 0, s, g, b, rm, rv, C, eps, scale,
+                       shift);
+}
+
+}  // namespace helm

@@ -1,0 +1,66 @@
+// The U-Net object behind the unet_net handle of include/unet.h (internal).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/unet.h"
+#include "unet_internal.h"
+
+struct helm_handle;
+
+struct unet_net {
+    // one 3x3 convolution with its batch normalisation
+    struct Layer {
+        std::string name;
+        int level = 0, cout = 0, nsrc = 0, cin_real = 0, cin_pad = 0;
+        int src_real[3] = {0, 0, 0}, src_pad[3] = {0, 0, 0};
+        size_t w_off = 0, g_off = 0, b_off = 0, rm_off = 0, rv_off = 0, sc_off = 0;
+        helm::bf16 *Wp = nullptr, *Wd = nullptr;  // packed forward / data-gradient weights
+        int *map = nullptr;                        // padded -> canonical input channel
+        float *mean = nullptr, *rstd = nullptr, *var = nullptr;  // batch statistics
+    };
+    // per-layer activations of the current workspace
+    struct Act {
+        float *y32 = nullptr;   // raw convolution output (training)
+        helm::bf16 *a = nullptr;  // activation
+        float *g = nullptr;     // gradient w.r.t. the activation (training)
+    };
+
+    unet_cfg cfg{};
+    std::vector<Layer> L;
+    size_t nparams = 0, nbuf = 0, head_w = 0, head_b = 0;
+    float *P = nullptr, *G = nullptr, *M = nullptr, *V = nullptr, *BUF = nullptr;
+    float *scale = nullptr, *shift = nullptr;  // folded inference BN
+    int step = 0;
+
+    int wsB = 0, wsH = 0, wsW = 0;
+    bool wsTrain = false;
+    std::vector<Act> act;
+    std::vector<helm::bf16 *> pooled, up;
+    std::vector<uint8_t *> arg;
+    helm::bf16 *x0 = nullptr, *dy = nullptr;
+    float *out = nullptr, *gout = nullptr, *dX = nullptr, *dW = nullptr, *wpart = nullptr;
+    float *xin = nullptr;
+    double *red = nullptr, *s = nullptr, *dloss = nullptr;
+    float2 *rcoarse = nullptr, *dfine = nullptr;
+
+    ~unet_net();
+    int init(const unet_cfg &c);
+    int ensure_ws(int B, int H, int W, bool training);
+    void free_ws();
+    int enc_index(int level, char ab) const;
+    int dec_index(int level, char ab) const;
+    helm::Srcs layer_srcs(int i) const;
+    void run_layer(int i, const helm::Srcs &src, int B, int H, int W, bool training, hipStream_t st);
+    void forward_from_x0(int B, int H, int W, bool training, hipStream_t st);
+    void backward(int B, int H, int W, hipStream_t st);
+    void repack(hipStream_t st);
+    void refold(hipStream_t st);
+    int pack_nchw_input(const float *x, int B, int H, int W, hipStream_t st);
+    int unpack_nchw_output(float *o, int B, int H, int W, hipStream_t st);
+    // e (+)= P s Net(R(h^2 r)/s, kappa_c) for nb fields of medium h
+    int wrap_apply(helm_handle *h, const float2 *r, size_t rs, float2 *e, size_t es, int nb,
+                   int accumulate, hipStream_t st);
+    int loss_grad(const unet_batch &bt, hipStream_t st);
+};

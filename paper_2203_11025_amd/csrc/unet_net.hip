@@ -1,0 +1,572 @@
+// Host orchestration of the U-Net: parameters, forward (training and
+// inference batch normalisation), backward, loss, Adam, and the residual ->
+// error wrapper used by the preconditioners.
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/unet.h"
+#include "handle.h"
+#include "unet_internal.h"
+#include "unet_net.h"
+
+namespace helm {
+
+namespace {
+
+constexpr float SLOPE = 0.2f;
+constexpr float BN_EPS = 1e-5f;
+constexpr float BN_MOM = 0.1f;
+
+template <typename T>
+int dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc((void **)p, count * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        set_error("unet: device allocation failed");
+        return HELM_E_NOMEM;
+    }
+    return HELM_OK;
+}
+
+int pad32(int c) { return (c + 31) / 32 * 32; }
+
+}  // namespace
+}  // namespace helm
+
+using namespace helm;
+
+void unet_net::free_ws()
+{
+    for (auto &a : act) {
+        hipFree(a.y32);
+        hipFree(a.a);
+        hipFree(a.g);
+    }
+    act.clear();
+    for (auto p : pooled) hipFree(p);
+    for (auto p : arg) hipFree(p);
+    for (auto p : up) hipFree(p);
+    pooled.clear();
+    arg.clear();
+    up.clear();
+    hipFree(x0);
+    hipFree(out);
+    hipFree(gout);
+    hipFree(dX);
+    hipFree(dy);
+    hipFree(dW);
+    hipFree(wpart);
+    hipFree(red);
+    hipFree(rcoarse);
+    hipFree(s);
+    hipFree(dfine);
+    hipFree(dloss);
+    hipFree(xin);
+    x0 = nullptr;
+    out = gout = dX = dW = wpart = nullptr;
+    dy = nullptr;
+    red = nullptr;
+    rcoarse = dfine = nullptr;
+    s = dloss = nullptr;
+    xin = nullptr;
+    wsB = wsH = wsW = 0;
+    wsTrain = false;
+}
+
+unet_net::~unet_net()
+{
+    free_ws();
+    for (auto &l : L) {
+        hipFree(l.Wp);
+        hipFree(l.Wd);
+        hipFree(l.map);
+        hipFree(l.mean);
+        hipFree(l.rstd);
+        hipFree(l.var);
+    }
+    hipFree(P);
+    hipFree(G);
+    hipFree(M);
+    hipFree(V);
+    hipFree(BUF);
+    hipFree(scale);
+    hipFree(shift);
+}
+
+int unet_net::init(const unet_cfg &c)
+{
+    cfg = c;
+    const int Lv = cfg.levels;
+    auto add = [&](const std::string &name, int level, std::vector<int> real, std::vector<int> padc,
+                   int cout) {
+        Layer l;
+        l.name = name;
+        l.level = level;
+        l.cout = cout;
+        l.nsrc = (int)real.size();
+        l.cin_real = l.cin_pad = 0;
+        for (int k = 0; k < l.nsrc; ++k) {
+            l.src_real[k] = real[k];
+            l.src_pad[k] = padc[k];
+            l.cin_real += real[k];
+            l.cin_pad += padc[k];
+        }
+        L.push_back(l);
+    };
+    const int *w = cfg.widths;
+    for (int l = 0; l < Lv; ++l) {
+        if (l == 0)
+            add("enc0a", 0, {cfg.in_ch}, {pad32(cfg.in_ch)}, w[0]);
+        else
+            add("enc" + std::to_string(l) + "a", l, {w[l - 1]}, {w[l - 1]}, w[l]);
+        add("enc" + std::to_string(l) + "b", l, {w[l]}, {w[l]}, w[l]);
+    }
+    for (int l = Lv - 2; l >= 0; --l) {
+        add("dec" + std::to_string(l) + "a", l, {w[l + 1], w[l]}, {w[l + 1], w[l]}, w[l]);
+        add("dec" + std::to_string(l) + "b", l, {w[l]}, {w[l]}, w[l]);
+    }
+    // flat offsets
+    size_t off = 0, boff = 0;
+    int rc;
+    for (auto &l : L) {
+        l.w_off = off;
+        off += (size_t)l.cout * l.cin_real * 9;
+        l.g_off = off;
+        off += l.cout;
+        l.b_off = off;
+        off += l.cout;
+        l.rm_off = boff;
+        boff += l.cout;
+        l.rv_off = boff;
+        boff += l.cout;
+        // padded channel -> canonical channel map
+        std::vector<int> map(l.cin_pad, -1);
+        int cr = 0, cp = 0;
+        for (int k = 0; k < l.nsrc; ++k) {
+            for (int q = 0; q < l.src_real[k]; ++q) map[cp + q] = cr + q;
+            cr += l.src_real[k];
+            cp += l.src_pad[k];
+        }
+        if ((rc = dalloc(&l.map, map.size())) || (rc = dalloc(&l.Wp, (size_t)l.cout * 9 * l.cin_pad)) ||
+            (rc = dalloc(&l.Wd, (size_t)l.cout * 9 * l.cin_pad)) || (rc = dalloc(&l.mean, l.cout)) ||
+            (rc = dalloc(&l.rstd, l.cout)) || (rc = dalloc(&l.var, l.cout)))
+            return rc;
+        if (hipMemcpy(l.map, map.data(), map.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+            set_error("unet_create: upload failed");
+            return HELM_E_HIP;
+        }
+    }
+    head_w = off;
+    off += (size_t)cfg.out_ch * w[0];
+    head_b = off;
+    off += cfg.out_ch;
+    nparams = off;
+    nbuf = boff;
+    size_t nsc = 0;
+    for (auto &l : L) {
+        l.sc_off = nsc;
+        nsc += l.cout;
+    }
+    if ((rc = dalloc(&P, nparams)) || (rc = dalloc(&G, nparams)) || (rc = dalloc(&M, nparams)) ||
+        (rc = dalloc(&V, nparams)) || (rc = dalloc(&BUF, nbuf)) || (rc = dalloc(&scale, nsc)) ||
+        (rc = dalloc(&shift, nsc)))
+        return rc;
+    if (hipMemset(P, 0, nparams * 4) || hipMemset(M, 0, nparams * 4) || hipMemset(V, 0, nparams * 4)) {
+        set_error("unet_create: clearing parameters failed");
+        return HELM_E_HIP;
+    }
+    return HELM_OK;
+}
+
+int unet_net::ensure_ws(int B, int H, int W, bool training)
+{
+    if (B <= wsB && H == wsH && W == wsW && (!training || wsTrain)) return HELM_OK;
+    int nB = std::max(B, wsB);
+    bool tr = training || wsTrain;
+    free_ws();
+    const int Lv = cfg.levels;
+    int rc;
+    act.resize(L.size());
+    size_t maxdx = 0, maxdy = 0, maxdw = 0, maxpart = 0;
+    for (size_t i = 0; i < L.size(); ++i) {
+        const Layer &l = L[i];
+        size_t Pl = (size_t)nB * (H >> l.level) * (W >> l.level);
+        if ((rc = dalloc(&act[i].a, Pl * l.cout))) return rc;
+        if (tr) {
+            if ((rc = dalloc(&act[i].y32, Pl * l.cout)) || (rc = dalloc(&act[i].g, Pl * l.cout))) return rc;
+        }
+        maxdx = std::max(maxdx, Pl * l.cin_pad);
+        maxdy = std::max(maxdy, Pl * l.cout);
+        maxdw = std::max(maxdw, (size_t)l.cout * 9 * l.cin_pad);
+        maxpart = std::max(maxpart, wgrad_scratch(nB, H >> l.level, W >> l.level, l.cout, l.cin_pad));
+    }
+    pooled.assign(Lv, nullptr);
+    arg.assign(Lv, nullptr);
+    up.assign(Lv, nullptr);
+    for (int l = 1; l < Lv; ++l) {
+        size_t Pl = (size_t)nB * (H >> l) * (W >> l);
+        if ((rc = dalloc(&pooled[l], Pl * cfg.widths[l - 1])) || (rc = dalloc(&arg[l], Pl * cfg.widths[l - 1])))
+            return rc;
+    }
+    for (int l = 0; l < Lv - 1; ++l) {
+        size_t Pl = (size_t)nB * (H >> l) * (W >> l);
+        if ((rc = dalloc(&up[l], Pl * cfg.widths[l + 1]))) return rc;
+    }
+    size_t P0 = (size_t)nB * H * W;
+    if ((rc = dalloc(&x0, P0 * pad32(cfg.in_ch))) || (rc = dalloc(&out, P0 * cfg.out_ch)) ||
+        (rc = dalloc(&xin, P0 * cfg.out_ch)))
+        return rc;
+    if ((rc = dalloc(&red, 1 << 20))) return rc;  // reduction scratch (8 MB)
+    if (tr) {
+        if ((rc = dalloc(&gout, P0 * cfg.out_ch)) || (rc = dalloc(&dX, maxdx)) || (rc = dalloc(&dy, maxdy)) ||
+            (rc = dalloc(&dW, maxdw)) || (rc = dalloc(&wpart, maxpart)))
+            return rc;
+    }
+    // wrapper scratch: coarse residual, scales, fine residual of the loss
+    if ((rc = dalloc(&rcoarse, P0)) || (rc = dalloc(&s, nB)) || (rc = dalloc(&dloss, 1)))
+        return rc;
+    if (tr && (rc = dalloc(&dfine, (size_t)nB * 4 * H * W))) return rc;
+    wsB = nB;
+    wsH = H;
+    wsW = W;
+    wsTrain = tr;
+    return HELM_OK;
+}
+
+// One 3x3 convolution layer with BN and LeakyReLU.
+void unet_net::run_layer(int i, const Srcs &src, int B, int H, int W, bool training, hipStream_t st)
+{
+    Layer &l = L[i];
+    Act &a = act[i];
+    const size_t Pl = (size_t)B * H * W;
+    if (training) {
+        launch_conv3x3(src, B, H, W, l.Wp, l.cout, 0, a.y32, nullptr, nullptr, nullptr, SLOPE, st);
+        launch_bn_stats(a.y32, Pl, l.cout, red, l.mean, l.rstd, l.var, st);
+        launch_bn_act_fwd(a.y32, Pl, l.cout, l.mean, l.rstd, P + l.g_off, P + l.b_off, SLOPE, a.a, st);
+    } else {
+        launch_conv3x3(src, B, H, W, l.Wp, l.cout, 1, nullptr, a.a, scale + l.sc_off, shift + l.sc_off,
+                       SLOPE, st);
+    }
+}
+
+Srcs unet_net::layer_srcs(int i) const
+{
+    const Layer &l = L[i];
+    Srcs s{};
+    s.n = l.nsrc;
+    s.Ctot = l.cin_pad;
+    const std::string &nm = l.name;
+    int lev = l.level;
+    if (nm == "enc0a") {
+        s.s[0] = {x0, l.src_pad[0]};
+    } else if (nm[0] == 'e' && nm.back() == 'a') {
+        s.s[0] = {pooled[lev], l.src_pad[0]};
+    } else if (nm.back() == 'b') {
+        s.s[0] = {act[i - 1].a, l.src_pad[0]};
+    } else {  // decoder 'a': [upsampled, skip]
+        s.s[0] = {up[lev], l.src_pad[0]};
+        s.s[1] = {act[enc_index(lev, 'b')].a, l.src_pad[1]};
+    }
+    return s;
+}
+
+int unet_net::enc_index(int level, char ab) const { return 2 * level + (ab == 'b' ? 1 : 0); }
+
+int unet_net::dec_index(int level, char ab) const
+{
+    // decoders follow the 2L encoder layers, level L-2 first
+    return 2 * cfg.levels + 2 * (cfg.levels - 2 - level) + (ab == 'b' ? 1 : 0);
+}
+
+void unet_net::forward_from_x0(int B, int H, int W, bool training, hipStream_t st)
+{
+    const int Lv = cfg.levels;
+    for (int l = 0; l < Lv; ++l) {
+        int Hl = H >> l, Wl = W >> l;
+        if (l > 0)
+            launch_maxpool_fwd(act[enc_index(l - 1, 'b')].a, B, H >> (l - 1), W >> (l - 1),
+                               cfg.widths[l - 1], pooled[l], training ? arg[l] : nullptr, st);
+        run_layer(enc_index(l, 'a'), layer_srcs(enc_index(l, 'a')), B, Hl, Wl, training, st);
+        run_layer(enc_index(l, 'b'), layer_srcs(enc_index(l, 'b')), B, Hl, Wl, training, st);
+    }
+    for (int l = Lv - 2; l >= 0; --l) {
+        int Hl = H >> l, Wl = W >> l;
+        const bf16 *prev = (l == Lv - 2) ? act[enc_index(Lv - 1, 'b')].a : act[dec_index(l + 1, 'b')].a;
+        launch_up2_fwd(prev, B, Hl / 2, Wl / 2, cfg.widths[l + 1], up[l], st);
+        run_layer(dec_index(l, 'a'), layer_srcs(dec_index(l, 'a')), B, Hl, Wl, training, st);
+        run_layer(dec_index(l, 'b'), layer_srcs(dec_index(l, 'b')), B, Hl, Wl, training, st);
+    }
+    int last = Lv >= 2 ? dec_index(0, 'b') : enc_index(0, 'b');
+    launch_head_fwd(act[last].a, (size_t)B * H * W, cfg.widths[0], P + head_w, P + head_b, out, st);
+}
+
+void unet_net::backward(int B, int H, int W, hipStream_t st)
+{
+    const int Lv = cfg.levels;
+    const size_t P0 = (size_t)B * H * W;
+    for (size_t i = 0; i < L.size(); ++i) {
+        size_t Pl = (size_t)B * (H >> L[i].level) * (W >> L[i].level);
+        hipMemsetAsync(act[i].g, 0, Pl * L[i].cout * sizeof(float), st);
+    }
+    int last = Lv >= 2 ? dec_index(0, 'b') : enc_index(0, 'b');
+    launch_head_bwd(gout, act[last].a, P0, cfg.widths[0], P + head_w, act[last].g, red, G + head_w,
+                    G + head_b, st);
+    for (int i = (int)L.size() - 1; i >= 0; --i) {
+        Layer &l = L[i];
+        Act &a = act[i];
+        const int Hl = H >> l.level, Wl = W >> l.level;
+        const size_t Pl = (size_t)B * Hl * Wl;
+        launch_bn_act_bwd(a.g, a.y32, Pl, l.cout, l.mean, l.rstd, P + l.g_off, P + l.b_off, SLOPE, red,
+                          G + l.g_off, G + l.b_off, dy, st);
+        Srcs src = layer_srcs(i);
+        launch_wgrad(src, dy, B, Hl, Wl, l.cout, dW, wpart, st);
+        launch_unpack_wgrad(dW, l.cout, l.cin_real, l.map, l.cin_pad, G + l.w_off, st);
+        if (i == 0) continue;  // no gradient w.r.t. the network input
+        // data gradient: a 3x3 convolution of dy with the flipped, transposed weights
+        Srcs ds{};
+        ds.n = 1;
+        ds.Ctot = l.cout;
+        ds.s[0] = {dy, l.cout};
+        launch_conv3x3(ds, B, Hl, Wl, l.Wd, l.cin_pad, 0, dX, nullptr, nullptr, nullptr, SLOPE, st);
+        const std::string &nm = l.name;
+        if (nm.back() == 'b') {
+            launch_slice_add(dX, l.cin_pad, 0, Pl, l.cout, act[i - 1].g, 1, st);
+        } else if (nm[0] == 'e') {
+            // enc{lev}a, lev >= 1: through the max pooling into enc{lev-1}b
+            int src_layer = enc_index(l.level - 1, 'b');
+            launch_maxpool_bwd(dX, arg[l.level], B, Hl * 2, Wl * 2, cfg.widths[l.level - 1], l.cin_pad, 0,
+                               act[src_layer].g, cfg.widths[l.level - 1], st);
+        } else {
+            // dec{lev}a: [upsampled, skip]
+            int lev = l.level;
+            int prev = (lev == Lv - 2) ? enc_index(Lv - 1, 'b') : dec_index(lev + 1, 'b');
+            launch_up2_bwd(dX, l.cin_pad, 0, B, Hl / 2, Wl / 2, cfg.widths[lev + 1], act[prev].g, 1, st);
+            launch_slice_add(dX, l.cin_pad, cfg.widths[lev + 1], Pl, cfg.widths[lev],
+                             act[enc_index(lev, 'b')].g, 1, st);
+        }
+    }
+}
+
+void unet_net::repack(hipStream_t st)
+{
+    for (auto &l : L)
+        launch_pack_weights(P + l.w_off, l.cout, l.cin_real, l.map, l.cin_pad, l.Wp, l.Wd, st);
+    refold(st);
+}
+
+void unet_net::refold(hipStream_t st)
+{
+    for (auto &l : L)
+        launch_fold_bn(P + l.g_off, P + l.b_off, BUF + l.rm_off, BUF + l.rv_off, l.cout, BN_EPS,
+                       scale + l.sc_off, shift + l.sc_off, st);
+}
+
+int unet_net::wrap_apply(helm_handle *h, const float2 *r, size_t rs, float2 *e, size_t es, int nb,
+                     int accumulate, hipStream_t st)
+{
+    const int n = h->n, nc = n / 2;
+    int rc = ensure_ws(nb, nc, nc, false);
+    if (rc) return rc;
+    launch_net_input(r, rs, nb, n, h->kappa0, nullptr, rcoarse, red, s, x0, st);
+    forward_from_x0(nb, nc, nc, false, st);
+    launch_net_output(out, s, nb, n, e, es, accumulate, st);
+    return HELM_OK;
+}
+
+int unet_net::loss_grad(const unet_batch &bt, hipStream_t st)
+{
+    const int n = bt.n, nc = n / 2, nb = bt.nb;
+    int rc = ensure_ws(nb, nc, nc, true);
+    if (rc) return rc;
+    launch_net_input((const float2 *)bt.r, (size_t)n * n, nb, n, nullptr, bt.kappa_c, rcoarse, red, s,
+                     x0, st);
+    forward_from_x0(nb, nc, nc, true, st);
+    launch_loss_grad(out, s, nb, n, (const float2 *)bt.e, dfine, red, gout, dloss, st);
+    hipMemsetAsync(G, 0, nparams * sizeof(float), st);
+    backward(nb, nc, nc, st);
+    return HELM_OK;
+}
+
+int unet_net::pack_nchw_input(const float *x, int B, int H, int W, hipStream_t st)
+{
+    launch_nchw_to_nhwc(x, B, cfg.in_ch, H, W, pad32(cfg.in_ch), x0, st);
+    return HELM_OK;
+}
+
+int unet_net::unpack_nchw_output(float *o, int B, int H, int W, hipStream_t st)
+{
+    launch_nhwc_to_nchw(out, B, cfg.out_ch, H, W, o, st);
+    return HELM_OK;
+}
+
+extern "C" {
+
+int unet_create(const unet_cfg *cfg, unet_net **out)
+{
+    if (!cfg || !out) {
+        set_error("unet_create: null argument");
+        return HELM_E_INVALID;
+    }
+    *out = nullptr;
+    if (cfg->levels < 1 || cfg->levels > 6 || cfg->in_ch < 1 || cfg->in_ch > 32 || cfg->out_ch != 2 ||
+        !cfg->head || cfg->context) {
+        set_error("unet_create: unsupported configuration (levels 1..6, in_ch 1..32, out_ch 2, head 1, context 0)");
+        return HELM_E_INVALID;
+    }
+    for (int l = 0; l < cfg->levels; ++l)
+        if (cfg->widths[l] < 32 || cfg->widths[l] % 32 != 0 || cfg->widths[l] > 256) {
+            set_error("unet_create: widths must be multiples of 32 in [32, 256]");
+            return HELM_E_INVALID;
+        }
+    auto *net = new unet_net();
+    int rc = net->init(*cfg);
+    if (rc) {
+        delete net;
+        return rc;
+    }
+    *out = net;
+    return HELM_OK;
+}
+
+void unet_destroy(unet_net *net) { delete net; }
+
+long long unet_num_params(const unet_net *net) { return net ? (long long)net->nparams : -1; }
+long long unet_num_buffers(const unet_net *net) { return net ? (long long)net->nbuf : -1; }
+
+int unet_set_params(unet_net *net, const float *params, const float *buffers, void *stream)
+{
+    if (!net || !params) {
+        set_error("unet_set_params: null argument");
+        return HELM_E_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    HELM_HIP_CHECK(hipMemcpyAsync(net->P, params, net->nparams * 4, hipMemcpyDeviceToDevice, st));
+    if (buffers) {
+        HELM_HIP_CHECK(hipMemcpyAsync(net->BUF, buffers, net->nbuf * 4, hipMemcpyDeviceToDevice, st));
+    } else {
+        std::vector<float> b(net->nbuf);
+        for (auto &l : net->L) {
+            std::fill(b.begin() + l.rm_off, b.begin() + l.rm_off + l.cout, 0.f);
+            std::fill(b.begin() + l.rv_off, b.begin() + l.rv_off + l.cout, 1.f);
+        }
+        HELM_HIP_CHECK(hipMemcpyAsync(net->BUF, b.data(), net->nbuf * 4, hipMemcpyHostToDevice, st));
+        HELM_HIP_CHECK(hipStreamSynchronize(st));
+    }
+    HELM_HIP_CHECK(hipMemsetAsync(net->M, 0, net->nparams * 4, st));
+    HELM_HIP_CHECK(hipMemsetAsync(net->V, 0, net->nparams * 4, st));
+    net->step = 0;
+    net->repack(st);
+    HELM_HIP_CHECK(hipGetLastError());
+    return HELM_OK;
+}
+
+int unet_get_params(unet_net *net, float *params, float *buffers, void *stream)
+{
+    if (!net) {
+        set_error("unet_get_params: null argument");
+        return HELM_E_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (params) HELM_HIP_CHECK(hipMemcpyAsync(params, net->P, net->nparams * 4, hipMemcpyDeviceToDevice, st));
+    if (buffers) HELM_HIP_CHECK(hipMemcpyAsync(buffers, net->BUF, net->nbuf * 4, hipMemcpyDeviceToDevice, st));
+    return HELM_OK;
+}
+
+int unet_forward(unet_net *net, const float *x, int B, int H, int W, float *out, int training,
+                 void *stream)
+{
+    if (!net || !x || !out || B < 1 || H < 1 || W < 1) {
+        set_error("unet_forward: invalid argument");
+        return HELM_E_INVALID;
+    }
+    const int div = 1 << (net->cfg.levels - 1);
+    if (H % div || W % div) {
+        set_error("unet_forward: H and W must be divisible by 2^(levels-1)");
+        return HELM_E_SHAPE;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int rc = net->ensure_ws(B, H, W, training != 0);
+    if (rc) return rc;
+    rc = net->pack_nchw_input(x, B, H, W, st);
+    if (rc) return rc;
+    net->forward_from_x0(B, H, W, training != 0, st);
+    rc = net->unpack_nchw_output(out, B, H, W, st);
+    if (rc) return rc;
+    HELM_HIP_CHECK(hipGetLastError());
+    return HELM_OK;
+}
+
+int unet_infer(unet_net *net, helm_handle *h, const float *r, float *e, int nrhs, void *stream)
+{
+    if (!net || !h || !r || !e || nrhs < 0) {
+        set_error("unet_infer: invalid argument");
+        return HELM_E_INVALID;
+    }
+    if (nrhs == 0) return HELM_OK;
+    const int div = 1 << net->cfg.levels;  // the network runs on n/2
+    if (h->n % div) {
+        set_error("unet_infer: n must be divisible by 2^levels");
+        return HELM_E_SHAPE;
+    }
+    size_t N = (size_t)h->n * h->n;
+    int rc = net->wrap_apply(h, (const float2 *)r, N, (float2 *)e, N, nrhs, 0, (hipStream_t)stream);
+    if (rc) return rc;
+    HELM_HIP_CHECK(hipGetLastError());
+    return HELM_OK;
+}
+
+int unet_loss_grad(unet_net *net, const unet_batch *batch, double *loss_out, float *grads,
+                   void *stream)
+{
+    if (!net || !batch || !batch->r || !batch->e || !batch->kappa_c || batch->nb < 1) {
+        set_error("unet_loss_grad: invalid argument");
+        return HELM_E_INVALID;
+    }
+    const int div = 1 << net->cfg.levels;
+    if (batch->n % div) {
+        set_error("unet_loss_grad: n must be divisible by 2^levels");
+        return HELM_E_SHAPE;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int rc = net->loss_grad(*batch, st);
+    if (rc) return rc;
+    if (grads) HELM_HIP_CHECK(hipMemcpyAsync(grads, net->G, net->nparams * 4, hipMemcpyDeviceToDevice, st));
+    if (loss_out) {
+        HELM_HIP_CHECK(hipMemcpyAsync(loss_out, net->dloss, sizeof(double), hipMemcpyDeviceToHost, st));
+        HELM_HIP_CHECK(hipStreamSynchronize(st));
+    }
+    HELM_HIP_CHECK(hipGetLastError());
+    return HELM_OK;
+}
+
+int unet_train_step(unet_net *net, const unet_batch *batch, const unet_train_opts *opts,
+                    double *loss_out, void *stream)
+{
+    unet_train_opts o{1e-3f, 0.9f, 0.999f, 1e-8f};
+    if (opts) o = *opts;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = unet_loss_grad(net, batch, nullptr, nullptr, stream);
+    if (rc) return rc;
+    net->step += 1;
+    launch_adam(net->P, net->G, net->M, net->V, net->nparams, o.lr, o.beta1, o.beta2, o.eps, net->step, st);
+    const double count = (double)batch->nb * (batch->n / 2) * (batch->n / 2);
+    for (size_t i = 0; i < net->L.size(); ++i) {
+        auto &l = net->L[i];
+        // statistics of each layer at its own resolution
+        double cnt = count / (double)(1u << (2 * l.level));
+        launch_bn_running(net->BUF + l.rm_off, net->BUF + l.rv_off, l.mean, l.var, l.cout, BN_MOM, cnt, st);
+    }
+    net->repack(st);
+    if (loss_out) {
+        HELM_HIP_CHECK(hipMemcpyAsync(loss_out, net->dloss, sizeof(double), hipMemcpyDeviceToHost, st));
+        HELM_HIP_CHECK(hipStreamSynchronize(st));
+    }
+    HELM_HIP_CHECK(hipGetLastError());
+    return HELM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+"""ctypes binding of the U-Net entry points (include/unet.h).  Argument
+marshalling only; every step runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from .helm import HelmError, _check, _dev, _stream, lib as _helm_lib
+
+EXPORTS = ["unet_create", "unet_destroy", "unet_num_params", "unet_num_buffers",
+           "unet_set_params", "unet_get_params", "unet_forward", "unet_infer",
+           "unet_loss_grad", "unet_train_step"]
+
+
+class Cfg(C.Structure):
+    _fields_ = [("in_ch", C.c_int), ("out_ch", C.c_int), ("levels", C.c_int),
+                ("widths", C.c_int * 6), ("context", C.c_int), ("head", C.c_int)]
+
+
+class Batch(C.Structure):
+    _fields_ = [("nb", C.c_int), ("n", C.c_int), ("r", C.c_void_p), ("e", C.c_void_p),
+                ("kappa_c", C.c_void_p)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
+
+
+_done = False
+
+
+def lib():
+    global _done
+    L = _helm_lib()
+    if not _done:
+        vp, ip = C.c_void_p, C.c_int
+        L.unet_create.argtypes = [C.POINTER(Cfg), C.POINTER(vp)]
+        L.unet_create.restype = ip
+        L.unet_destroy.argtypes = [vp]
+        L.unet_destroy.restype = None
+        L.unet_num_params.argtypes = [vp]
+        L.unet_num_params.restype = C.c_longlong
+        L.unet_num_buffers.argtypes = [vp]
+        L.unet_num_buffers.restype = C.c_longlong
+        L.unet_set_params.argtypes = [vp, vp, vp, vp]
+        L.unet_set_params.restype = ip
+        L.unet_get_params.argtypes = [vp, vp, vp, vp]
+        L.unet_get_params.restype = ip
+        L.unet_forward.argtypes = [vp, vp, ip, ip, ip, vp, ip, vp]
+        L.unet_forward.restype = ip
+        L.unet_infer.argtypes = [vp, vp, vp, vp, ip, vp]
+        L.unet_infer.restype = ip
+        L.unet_loss_grad.argtypes = [vp, C.POINTER(Batch), C.POINTER(C.c_double), vp, vp]
+        L.unet_loss_grad.restype = ip
+        L.unet_train_step.argtypes = [vp, C.POINTER(Batch), C.POINTER(TrainOpts),
+                                      C.POINTER(C.c_double), vp]
+        L.unet_train_step.restype = ip
+        _done = True
+    return L
+
+
+class UNet:
+    def __init__(self, widths=(32, 64, 128, 256), in_ch=3, out_ch=2):
+        cfg = Cfg(in_ch, out_ch, len(widths), (C.c_int * 6)(*list(widths) + [0] * (6 - len(widths))),
+                  0, 1)
+        h = C.c_void_p()
+        _check(lib().unet_create(C.byref(cfg), C.byref(h)), "unet_create")
+        self._h = h
+        self.widths = tuple(widths)
+        self.in_ch, self.out_ch = in_ch, out_ch
+        self.nparams = lib().unet_num_params(h)
+        self.nbuf = lib().unet_num_buffers(h)
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().unet_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params, buffers=None, stream=None):
+        if params.numel() != self.nparams:
+            raise HelmError(f"expected {self.nparams} parameters, got {params.numel()}")
+        p = params.to(device="cuda", dtype=torch.float32).contiguous()
+        b = None
+        if buffers is not None:
+            if buffers.numel() != self.nbuf:
+                raise HelmError(f"expected {self.nbuf} buffer entries, got {buffers.numel()}")
+            b = buffers.to(device="cuda", dtype=torch.float32).contiguous()
+        _check(lib().unet_set_params(self._h, _dev(p, torch.float32, "params"),
+                                     _dev(b, torch.float32, "buffers") if b is not None else None,
+                                     _stream(stream)), "unet_set_params")
+        torch.cuda.synchronize()
+
+    def get_params(self, stream=None):
+        p = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
+        b = torch.empty(self.nbuf, dtype=torch.float32, device="cuda")
+        _check(lib().unet_get_params(self._h, _dev(p, torch.float32, "p"), _dev(b, torch.float32, "b"),
+                                     _stream(stream)), "unet_get_params")
+        torch.cuda.synchronize()
+        return p, b
+
+    def forward(self, x, training=False, stream=None):
+        B, Cin, H, W = x.shape
+        x = x.to(device="cuda", dtype=torch.float32).contiguous()
+        out = torch.empty((B, self.out_ch, H, W), dtype=torch.float32, device="cuda")
+        _check(lib().unet_forward(self._h, _dev(x, torch.float32, "x"), B, H, W,
+                                  _dev(out, torch.float32, "out"), int(training), _stream(stream)),
+               "unet_forward")
+        return out
+
+    def infer(self, handle, r, stream=None):
+        r = handle._batch(r, "r")
+        e = torch.empty_like(r)
+        _check(lib().unet_infer(self._h, handle.ptr, _dev(r, torch.complex64, "r"),
+                                _dev(e, torch.complex64, "e"), r.shape[0], _stream(stream)),
+               "unet_infer")
+        return e
+
+    @staticmethod
+    def _batch(r, e, kappa_c):
+        nb, n = r.shape[0], r.shape[-1]
+        bt = Batch(nb, n, _dev(r, torch.complex64, "r"), _dev(e, torch.complex64, "e"),
+                   _dev(kappa_c, torch.float32, "kappa_c"))
+        return bt
+
+    def loss_grad(self, r, e, kappa_c, stream=None):
+        bt = self._batch(r, e, kappa_c)
+        g = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
+        loss = C.c_double()
+        _check(lib().unet_loss_grad(self._h, C.byref(bt), C.byref(loss), _dev(g, torch.float32, "g"),
+                                    _stream(stream)), "unet_loss_grad")
+        return loss.value, g
+
+    def train_step(self, r, e, kappa_c, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        bt = self._batch(r, e, kappa_c)
+        o = TrainOpts(lr, beta1, beta2, eps)
+        loss = C.c_double()
+        _check(lib().unet_train_step(self._h, C.byref(bt), C.byref(o), C.byref(loss),
+                                     _stream(stream)), "unet_train_step")
+        return loss.value

@@ -47,8 +47,8 @@ def test_last_error_callable_without_gpu():
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libhelm.so not built")
 def test_binding_names_match_header():
-    from paper_2203_11025_amd import helm
+    from paper_2203_11025_amd import helm, unet
 
     names = declared_functions()
-    for n in helm.EXPORTS:
+    for n in helm.EXPORTS + unet.EXPORTS:
         assert n in names
