@@ -146,6 +146,21 @@ int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int *rhs_per_p
                       void *stream);
 
 /*
+ * helm_training_triples -- supervised training data (section 3.4, eq.
+ * 3.8-3.9 with a single flexible-GMRES step): for given x,
+ *   b = A x,  z = M_V(b) (one SL V-cycle),  alpha = (Az)^H b / |Az|^2,
+ *   r = b - alpha A z  (the residual of x~ = alpha z),  e = x - alpha z,
+ * so that A e = r up to rounding.  The random x is an input.
+ *   x, r, e : complex64 [nrhs][n][n]; r and e are outputs; no overlap.
+ */
+int helm_training_triples(helm_handle *h, const float *x, float *r, float *e, int nrhs,
+                          void *stream);
+
+/* Slowness injected at the coarse points (2I, 2J): float [n/2][n/2] (the
+ * network's kappa input channel). */
+int helm_coarse_slowness(helm_handle *h, float *kc, void *stream);
+
+/*
  * Kernel timing hook (measurement support, not part of the method).  While
  * active, the library records a HIP event pair on the launch stream around
  * every launch of one kernel family; helm_profile_stop synchronises on those

@@ -322,3 +322,17 @@ def adam_step(params, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         vh = v[k] / (1 - b2 ** step)
         params[k] = params[k] - lr * mh / (torch.sqrt(vh) + eps)
     return params, m, v
+
+
+def training_triple(hier, x):
+    """Training data of section 3.4 (eq. 3.8-3.9) with one flexible-GMRES
+    step from zero and the SL V-cycle as preconditioner: b = A x,
+    z = V(b), alpha = argmin ||b - alpha A z||, r = b - alpha A z,
+    e = x - alpha z."""
+    kap, gam, om = hier.kappa0, hier.gamma0, hier.omega
+    x = np.asarray(x, dtype=np.complex128)
+    b = helm_oracle.apply(kap, gam, om, x)
+    z = hier.vcycle(b)
+    w = helm_oracle.apply(kap, gam, om, z)
+    alpha = np.vdot(w, b) / np.vdot(w, w)
+    return b - alpha * w, x - alpha * z

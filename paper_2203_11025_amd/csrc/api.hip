@@ -159,11 +159,11 @@ int ensure_vcycle_ws(helm_handle *h, int nb)
 }
 
 int vcycle(helm_handle *h, const float2 *f, size_t fs, float2 *v, size_t vs, int nb,
-           const int *active, hipStream_t s, const double *scale)
+           const int *active, hipStream_t s, const double *scale, int accumulate)
 {
     const int L = h->levels;
     if (L == 1) {
-        launch_coarse_solve(h->Xc, h->Nc, f, fs, v, vs, nb, active, s, scale);
+        launch_coarse_solve(h->Xc, h->Nc, f, fs, v, vs, nb, active, s, scale, accumulate);
         return HELM_OK;
     }
     int rc = ensure_vcycle_ws(h, nb);
@@ -188,7 +188,7 @@ int vcycle(helm_handle *h, const float2 *f, size_t fs, float2 *v, size_t vs, int
         float2 *dst = l == 0 ? v : h->wv[l];
         size_t dstr = l == 0 ? vs : Nl;
         launch_up(h->lv[l], sh, w, src, ss, h->wv[l + 1], Nn, dst, dstr, nb, active, s,
-                  l == 0 ? scale : nullptr);
+                  l == 0 ? scale : nullptr, l == 0 ? accumulate : 0);
     }
     return HELM_OK;
 }

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "handle.h"
+#include "unet_net.h"
 
 namespace helm {
 
@@ -34,6 +35,8 @@ struct FgWork {
     int *h_i = nullptr;       // pinned: active flags
     double *h_d = nullptr;    // pinned: relres
     int *h_its = nullptr;     // pinned: iteration counts
+    int *h_fb = nullptr;      // pinned: fallback flags
+    float2 *t1 = nullptr, *t2 = nullptr;  // network-preconditioner scratch
     FgState S{};
 };
 
@@ -131,20 +134,24 @@ void work_free(FgWork *w)
     hipFree(w->partial);
     hipFree(w->rpartial);
     hipFree(w->state);
+    hipFree(w->t1);
+    hipFree(w->t2);
+    if (w->h_fb) hipHostFree(w->h_fb);
     if (w->h_i) hipHostFree(w->h_i);
     if (w->h_d) hipHostFree(w->h_d);
     if (w->h_its) hipHostFree(w->h_its);
     delete w;
 }
 
-int work_ensure(helm_handle *h, int nb, int m, FgWork **out)
+int work_ensure(helm_handle *h, int nb, int m, bool scratch, FgWork **out)
 {
     FgWork *w = (FgWork *)h->fg;
     size_t N = (size_t)h->n * h->n;
-    if (w && w->nb >= nb && w->m == m && w->N == N) {
+    if (w && w->nb >= nb && w->m == m && w->N == N && (!scratch || w->t1)) {
         *out = w;
         return HELM_OK;
     }
+    if (w && w->t1) scratch = true;
     work_free(w);
     h->fg = nullptr;
     w = new FgWork();
@@ -161,7 +168,7 @@ int work_ensure(helm_handle *h, int nb, int m, FgWork **out)
     }
     // state: ints, then doubles, then double2s, each section 256-byte aligned
     auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    size_t ni = 4 * (size_t)nb, nd = 5 * (size_t)nb + (size_t)nb * m;
+    size_t ni = 8 * (size_t)nb, nd = 5 * (size_t)nb + (size_t)nb * m;
     size_t nz = (size_t)nb * ((m + 1) * m + (m + 1) + m + 3 * MAXV);
     size_t off_d = align(ni * sizeof(int)), off_z = align(off_d + nd * sizeof(double));
     size_t bytes = off_z + nz * sizeof(double2);
@@ -179,6 +186,10 @@ int work_ensure(helm_handle *h, int nb, int m, FgWork **out)
     S.incycle = S.active + nb;
     S.k = S.incycle + nb;
     S.its = S.k + nb;
+    S.fallback = S.its + nb;
+    S.stall = S.fallback + nb;
+    S.mask_net = S.stall + nb;
+    S.mask_sl = S.mask_net + nb;
     S.bnorm = (double *)(p + off_d);
     S.beta = S.bnorm + nb;
     S.relres = S.beta + nb;
@@ -201,7 +212,12 @@ int work_ensure(helm_handle *h, int nb, int m, FgWork **out)
         set_error("helm_fgmres_solve: clearing the solver state failed");
         return HELM_E_HIP;
     }
-    if (hipHostMalloc((void **)&w->h_i, nb * sizeof(int)) != hipSuccess ||
+    if (scratch && (dalloc(&w->t1, (size_t)nb * N) || dalloc(&w->t2, (size_t)nb * N))) {
+        work_free(w);
+        return HELM_E_NOMEM;
+    }
+    if (hipHostMalloc((void **)&w->h_fb, nb * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void **)&w->h_i, nb * sizeof(int)) != hipSuccess ||
         hipHostMalloc((void **)&w->h_d, nb * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&w->h_its, nb * sizeof(int)) != hipSuccess) {
         work_free(w);
@@ -213,25 +229,55 @@ int work_ensure(helm_handle *h, int nb, int m, FgWork **out)
     return HELM_OK;
 }
 
+// z = Prec(v) for the network preconditioners (section 3.2).  v (slot j) is
+// normalised in place first.  Right-hand sides in fallback use M_V.
+//   M_CU (Algorithm 2 with the network coarse correction):
+//       e1 = w D_A^-1 v,  e2 = e1 + Net(v - A e1),  z = e2 + w D_A^-1 (v - A e2)
+//   M_VU (eq. 3.4):  e0 = Net(v),  z = e0 + V(0, v - A e0)
+int apply_net_prec(helm_handle *h, unet_net *net, int prec, FgWork *w, const FgState &S,
+                   float2 *v, size_t vs, float2 *z, size_t zs, int nb, hipStream_t s)
+{
+    const size_t N = w->N;
+    const Level &L0 = h->lv[0];
+    const float jw = (float)h->jacobi_w;
+    launch_scale(v, vs, N, S.scale, nb, S.active, s);
+    launch_masks(S, 1, s);
+    int rc;
+    if (prec == HELM_PREC_UNET_DEFL) {
+        if ((rc = net->wrap_apply(h, v, vs, z, zs, nb, 0, s, S.mask_net))) return rc;
+        launch_resjac(L0, 0.f, jw, 0, z, zs, v, vs, w->t2, N, nb, S.active, s);
+        return vcycle(h, w->t2, N, z, zs, nb, S.active, s, nullptr, 1);
+    }
+    // coarse-grid-correction form
+    launch_resjac(L0, 0.f, jw, 2, v, vs, v, vs, w->t1, N, nb, S.mask_net, s);
+    launch_resjac(L0, 0.f, jw, 0, w->t1, N, v, vs, w->t2, N, nb, S.mask_net, s);
+    if ((rc = net->wrap_apply(h, w->t2, N, w->t1, N, nb, 1, s, S.mask_net))) return rc;
+    launch_resjac(L0, 0.f, jw, 1, w->t1, N, v, vs, z, zs, nb, S.mask_net, s);
+    return vcycle(h, v, vs, z, zs, nb, S.mask_sl, s);
+}
+
 // One problem (medium) with nb right-hand sides.
 int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, double tol,
-                  int maxit, int prec, helm_fgmres_stats *stats, hipStream_t s)
+                  int maxit, int prec, unet_net *net, double stall_ratio,
+                  helm_fgmres_stats *stats, hipStream_t s)
 {
     FgWork *w = nullptr;
-    int rc = work_ensure(h, nb, m, &w);
+    const bool use_net = prec != HELM_PREC_SL;
+    int rc = work_ensure(h, nb, m, use_net, &w);
     if (rc) return rc;
     FgState S = w->S;
     S.tol = tol;
     S.maxit = maxit;
+    S.stall_ratio = use_net ? stall_ratio : 0.0;
     const size_t N = w->N;
     const int nblk = krylov_nblk(N);
     const size_t vsb = (size_t)(m + 1) * N, zsb = (size_t)m * N;
     const Level &L0 = h->lv[0];
-    (void)prec;
     std::vector<int> restarts(nb, 0);
     std::vector<char> done(nb, 0);
 
     HELM_HIP_CHECK(hipMemsetAsync(x, 0, (size_t)nb * N * sizeof(double2), s));
+    HELM_HIP_CHECK(hipMemsetAsync(S.fallback, 0, 2 * (size_t)nb * sizeof(int), s));
     for (int i = 0; i < nb; ++i) w->h_i[i] = 1;
     HELM_HIP_CHECK(hipMemcpyAsync(S.active, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
     HELM_HIP_CHECK(hipMemcpyAsync(S.incycle, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
@@ -254,10 +300,15 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
         for (int j = 0; j < m; ++j) {
             float2 *vj = w->V + (size_t)j * N, *zj = w->Z + (size_t)j * N;
             float2 *wj = w->V + (size_t)(j + 1) * N;
-            // slot j holds the candidate direction, unnormalised; the V-cycle
-            // reads it scaled by 1 / (its norm)
-            rc = vcycle(h, vj, vsb, zj, zsb, nb, S.active, s, S.scale);
-            if (rc) return rc;
+            if (!use_net) {
+                // slot j holds the candidate direction, unnormalised; the V-cycle
+                // reads it scaled by 1 / (its norm)
+                rc = vcycle(h, vj, vsb, zj, zsb, nb, S.active, s, S.scale);
+                if (rc) return rc;
+            } else {
+                rc = apply_net_prec(h, net, prec, w, S, vj, vsb, zj, zsb, nb, s);
+                if (rc) return rc;
+            }
             launch_apply(L0, 0.f, zj, zsb, wj, vsb, nb, S.active, s);
             launch_arnoldi_step(S, w->V, vsb, N, j, w->partial, nblk, s);
         }
@@ -270,6 +321,8 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
             if (w->h_i[i]) restarts[i]++;
         HELM_HIP_CHECK(hipGetLastError());
     }
+    HELM_HIP_CHECK(hipMemcpyAsync(w->h_fb, S.fallback, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+    HELM_HIP_CHECK(hipStreamSynchronize(s));
     int nconv = 0;
     for (int i = 0; i < nb; ++i) {
         bool conv = w->h_d[i] <= tol;
@@ -278,7 +331,7 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
             stats[i].iterations = w->h_its[i];
             stats[i].restarts = restarts[i];
             stats[i].converged = conv ? 1 : 0;
-            stats[i].fallback = 0;
+            stats[i].fallback = w->h_fb[i];
             stats[i].true_relres = w->h_d[i];
         }
     }
@@ -309,19 +362,26 @@ extern "C" int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int
         return HELM_E_INVALID;
     }
     int m = 20, maxit = 20000, prec = HELM_PREC_SL;
-    double tol = 1e-7;
+    double tol = 1e-7, stall = 0.0;
+    unet_net *net = nullptr;
     if (opts) {
         m = opts->m;
         tol = opts->tol;
         maxit = opts->maxit;
         prec = opts->prec;
+        net = (unet_net *)opts->net;
+        stall = opts->stall_ratio;
     }
     if (m < 1 || m > MAXM || !(tol > 0.0) || maxit < 0) {
         set_error("helm_fgmres_solve: m must be in [1, 30], tol > 0, maxit >= 0");
         return HELM_E_INVALID;
     }
-    if (prec != HELM_PREC_SL) {
-        set_error("helm_fgmres_solve: this preconditioner needs a network (not available)");
+    if (prec != HELM_PREC_SL && prec != HELM_PREC_UNET_CGC && prec != HELM_PREC_UNET_DEFL) {
+        set_error("helm_fgmres_solve: unknown preconditioner");
+        return HELM_E_INVALID;
+    }
+    if (prec != HELM_PREC_SL && !net) {
+        set_error("helm_fgmres_solve: the network preconditioners need opts->net");
         return HELM_E_INVALID;
     }
     int status = HELM_OK, off = 0;
@@ -331,8 +391,13 @@ extern "C" int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int
             return HELM_E_INVALID;
         }
         if (rhs_per_prob[p] == 0) continue;
+        if (net && (probs[p]->n % (2 << (net->cfg.levels - 1)) || probs[p]->n % (1 << net->cfg.levels))) {
+            set_error("helm_fgmres_solve: grid size not divisible by 2^levels of the network");
+            return HELM_E_SHAPE;
+        }
         int rc = solve_problem(probs[p], rhs_per_prob[p], (const float2 *)b[p], (double2 *)x[p], m,
-                               tol, maxit, prec, stats ? stats + off : nullptr, (hipStream_t)stream);
+                               tol, maxit, prec, net, stall, stats ? stats + off : nullptr,
+                               (hipStream_t)stream);
         if (rc < 0) return rc;
         if (rc == HELM_NOT_CONVERGED) status = HELM_NOT_CONVERGED;
         off += rhs_per_prob[p];

@@ -28,6 +28,6 @@ int ensure_vcycle_ws(helm_handle *h, int nb);
 // v = V-cycle(0, f) on M, batch of nb fields (strides in complex elements);
 // with `scale` the input is read as scale[b] * f (the cycle is linear).
 int vcycle(helm_handle *h, const float2 *f, size_t fs, float2 *v, size_t vs, int nb,
-           const int *active, hipStream_t s, const double *scale = nullptr);
+           const int *active, hipStream_t s, const double *scale = nullptr, int accumulate = 0);
 void fgmres_free(helm_handle *h);
 }  // namespace helm

@@ -48,16 +48,22 @@ void launch_down(const Level &L, float shift, float w, const float2 *f, size_t f
 
 // Fused prolongation + correction + post-relaxation:
 //   v' = w D^-1 f + P vc,  v = v' + w D^-1 (f - Op v')
-// `scale` as for launch_down.
+// `scale` as for launch_down; with `accumulate` the result is added to v.
 void launch_up(const Level &L, float shift, float w, const float2 *f, size_t fs,
                const float2 *vc, size_t vcs, float2 *v, size_t vs, int nb,
-               const int *active, hipStream_t s, const double *scale = nullptr);
+               const int *active, hipStream_t s, const double *scale = nullptr,
+               int accumulate = 0);
 
 // v = X f with the dense coarsest-level inverse X (N x N complex64, row-major).
-// `scale` as for launch_down.
+// `scale` as for launch_down; with `accumulate` the result is added to v.
 void launch_coarse_solve(const float2 *X, int N, const float2 *f, size_t fs, float2 *v,
                          size_t vs, int nb, const int *active, hipStream_t s,
-                         const double *scale = nullptr);
+                         const double *scale = nullptr, int accumulate = 0);
+
+// mode 0: y = f - Op x;  mode 1: y = x + w D^-1 (f - Op x);  mode 2: y = w D^-1 f.
+void launch_resjac(const Level &L, float shift, float w, int mode, const float2 *x, size_t xs,
+                   const float2 *f, size_t fs, float2 *y, size_t ys, int nb, const int *active,
+                   hipStream_t s);
 
 // Level-l coefficients by injection from the fine fields, computed in double
 // and rounded once: mass = omega^2 kappa^2 (1 - i gamma) at (2^l I, 2^l J).
@@ -80,6 +86,9 @@ constexpr int MAXP = 2 * MAXM + 4;    // partial sums per block of an Arnoldi pa
 struct FgState {
     int m, nb;
     int *active, *incycle, *k, *its;
+    int *fallback, *stall;     // sticky switch to the plain SL V-cycle, stall counter
+    int *mask_net, *mask_sl;   // per-step masks: network path / SL path
+    double stall_ratio;        // 0 = never fall back
     double *bnorm, *beta, *relres, *scale, *nu;
     double2 *H;   // [nb][(m+1)*m], H[i*m + j]
     double2 *g;   // [nb][m+1]
@@ -102,6 +111,8 @@ void launch_arnoldi_step(const FgState &S, float2 *V, size_t vsb, size_t N, int 
                          double2 *partial, int nblk, hipStream_t s);
 void launch_scale(float2 *w, size_t ws, size_t N, const double *scale, int nb,
                   const int *active, hipStream_t s);
+// mask_net = active && !fallback, mask_sl = active && (fallback || !use_net)
+void launch_masks(const FgState &S, int use_net, hipStream_t s);
 void launch_xupdate(double2 *x, size_t xs, const float2 *Z, size_t zstride_b, size_t N,
                     const double2 *y, int ystride, const int *kcount, int nb,
                     const int *active, hipStream_t s);

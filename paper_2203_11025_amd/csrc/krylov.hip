@@ -246,6 +246,17 @@ __global__ __launch_bounds__(1024) void k_arnoldi_reduce(FgState S,
         S.k[b] = j + 1;
         int its = ++S.its[b];
         double res = hypot(t3.x, t3.y);
+        // stall detection: residual reduction |g_{j+1}| / |g_j| above the
+        // ratio on 3 consecutive steps (not the first of a cycle) switches
+        // this right-hand side to the plain SL V-cycle for good
+        if (S.stall_ratio > 0.0 && j > 0) {
+            double prev = hypot(gj.x, gj.y);
+            if (prev > 0.0 && res > S.stall_ratio * prev) {
+                if (++S.stall[b] >= 3) S.fallback[b] = 1;
+            } else {
+                S.stall[b] = 0;
+            }
+        }
         S.scale[b] = hn > 0.0 ? 1.0 / hn : 0.0;
         if (nu == 0.0 || hn == 0.0 || res <= S.tol * S.bnorm[b] || its >= S.maxit || j + 1 >= m)
             S.active[b] = 0;
@@ -360,6 +371,15 @@ __global__ __launch_bounds__(256) void k_scale(float2 *__restrict__ w, size_t ws
     }
 }
 
+__global__ void k_masks(FgState S, int use_net)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= S.nb) return;
+    const int a = S.active[b], fb = S.fallback[b];
+    S.mask_net[b] = (a && use_net && !fb) ? 1 : 0;
+    S.mask_sl[b] = (a && (!use_net || fb)) ? 1 : 0;
+}
+
 using pa_fn = void (*)(const FgState &, const float2 *, size_t, size_t, double2 *, int, hipStream_t);
 using pb_fn = void (*)(const FgState &, float2 *, size_t, size_t, int, hipStream_t);
 
@@ -408,6 +428,11 @@ void launch_arnoldi_step(const FgState &S, float2 *V, size_t vsb, size_t N, int 
     hipLaunchKernelGGL(k_arnoldi_reduce, dim3(S.nb), dim3(1024), 0, s, S, partial, nblk, j);
     kPassB[j](S, V, vsb, N, nblk, s);
     prof_mark(HELM_PROF_CGS, s, false);
+}
+
+void launch_masks(const FgState &S, int use_net, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_masks, dim3((S.nb + 63) / 64), dim3(64), 0, s, S, use_net);
 }
 
 void launch_scale(float2 *w, size_t ws, size_t N, const double *scale, int nb, const int *active,

@@ -79,6 +79,57 @@ __global__ __launch_bounds__(256) void k_apply(const float2 *__restrict__ x, siz
     }
 }
 
+// ------------------------------------------------------------------ residual / Jacobi
+// mode 0: y = f - Op x;  mode 1: y = x + w D^-1 (f - Op x);  mode 2: y = w D^-1 f
+// (Jacobi from a zero guess).  Same register-window walk as k_apply.
+__global__ __launch_bounds__(256) void k_resjac(const float2 *__restrict__ x, size_t xs,
+                                                const float2 *__restrict__ f, size_t fs,
+                                                float2 *__restrict__ y, size_t ys,
+                                                const float2 *__restrict__ mass, int n, float ih2,
+                                                float shift, float w, int mode, int R,
+                                                const int *__restrict__ active)
+{
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    const int lane = threadIdx.x;
+    const int j = blockIdx.x * 64 + lane;
+    const int i0 = (blockIdx.y * 4 + threadIdx.y) * R;
+    if (i0 >= n) return;
+    x += (size_t)b * xs;
+    f += (size_t)b * fs;
+    y += (size_t)b * ys;
+    if (mode == 2) {
+        if (j >= n) return;
+        const int iend = min(i0 + R, n);
+        for (int i = i0; i < iend; ++i) {
+            size_t p = (size_t)i * n + j;
+            float2 m = op_mass(mass[p], shift);
+            y[p] = cdiv(w * f[p], f2(4.f * ih2 - m.x, -m.y));
+        }
+        return;
+    }
+    auto ld = [&](int i, int jj) {
+        return (i >= 0 && i < n && jj >= 0 && jj < n) ? x[(size_t)i * n + jj] : f2(0.f, 0.f);
+    };
+    float2 up = ld(i0 - 1, j), cur = ld(i0, j);
+    const int iend = min(i0 + R, n);
+    for (int i = i0; i < iend; ++i) {
+        float2 dn = ld(i + 1, j);
+        float2 lf = shfl_up1(cur), rt = shfl_down1(cur);
+        if (lane == 0) lf = ld(i, j - 1);
+        if (lane == 63) rt = ld(i, j + 1);
+        if (j < n) {
+            size_t p = (size_t)i * n + j;
+            float2 m = op_mass(mass[p], shift);
+            float2 opx = ih2 * (4.f * cur - up - dn - lf - rt) - cmul(m, cur);
+            float2 res = f[p] - opx;
+            y[p] = mode == 0 ? res : cur + cdiv(w * res, f2(4.f * ih2 - m.x, -m.y));
+        }
+        up = cur;
+        cur = dn;
+    }
+}
+
 // ------------------------------------------------------------------ down
 // Fused: v = w D^-1 f (Jacobi from a zero guess), r = f - Op v, fc = R r.
 // Since D v = w f, (Op v)(p) = w f(p) - ih2 * sum of the 4 neighbours of v,
@@ -167,7 +218,7 @@ __global__ __launch_bounds__(256) void k_up(const float2 *__restrict__ f, size_t
                                             float2 *__restrict__ v, size_t vs,
                                             const float2 *__restrict__ mass, int n, float ih2,
                                             float shift, float w, const double *__restrict__ scale,
-                                            const int *__restrict__ active)
+                                            int accumulate, const int *__restrict__ active)
 {
     __shared__ float2 svc[UP_CH][UP_CW + 1];
     __shared__ float2 sv[UP_H + 2][UP_W + 3];
@@ -254,7 +305,9 @@ __global__ __launch_bounds__(256) void k_up(const float2 *__restrict__ f, size_t
             float2 d = sd[r][c];
             float2 nb4 = sv[r][c + 1] + sv[r + 2][c + 1] + sv[r + 1][c] + sv[r + 1][c + 2];
             float2 res = sf[r][c] - (cmul(d, vp) - ih2 * nb4);
-            v[(size_t)i * n + j] = vp + cdiv(w * res, d);
+            float2 z = vp + cdiv(w * res, d);
+            if (accumulate) z = z + v[(size_t)i * n + j];
+            v[(size_t)i * n + j] = z;
         }
     }
 }
@@ -266,7 +319,7 @@ template <int NB>
 __global__ __launch_bounds__(256) void k_coarse(const float2 *__restrict__ X, int N,
                                                 const float2 *__restrict__ f, size_t fs,
                                                 float2 *__restrict__ v, size_t vs, int b0,
-                                                const double *__restrict__ scale,
+                                                const double *__restrict__ scale, int accumulate,
                                                 const int *__restrict__ active)
 {
     const int lane = threadIdx.x & 63;
@@ -313,7 +366,9 @@ __global__ __launch_bounds__(256) void k_coarse(const float2 *__restrict__ X, in
         for (int q = 0; q < NB; ++q)
             if (!active || active[b0 + q]) {
                 float sc = scale ? (float)scale[b0 + q] : 1.f;
-                v[(size_t)(b0 + q) * vs + row] = f2(sc * ar[q], sc * ai[q]);
+                float2 z = f2(sc * ar[q], sc * ai[q]);
+                if (accumulate) z = z + v[(size_t)(b0 + q) * vs + row];
+                v[(size_t)(b0 + q) * vs + row] = z;
             }
     }
 }
@@ -390,6 +445,19 @@ void launch_apply(const Level &L, float shift, const float2 *x, size_t xs, float
     prof_mark(HELM_PROF_APPLY, s, false);
 }
 
+void launch_resjac(const Level &L, float shift, float w, int mode, const float2 *x, size_t xs,
+                   const float2 *f, size_t fs, float2 *y, size_t ys, int nb, const int *active,
+                   hipStream_t s)
+{
+    const int n = L.n;
+    const int strips = (n + 63) / 64;
+    long long waves_at_1 = (long long)strips * n * nb;
+    int R = (int)std::min<long long>(32, std::max<long long>(2, waves_at_1 / 4096));
+    dim3 grid(strips, (n + 4 * R - 1) / (4 * R), nb), block(64, 4);
+    hipLaunchKernelGGL(k_resjac, grid, block, 0, s, x, xs, f, fs, y, ys, L.mass, n, L.ih2, shift, w,
+                       mode, R, active);
+}
+
 void launch_down(const Level &L, float shift, float w, const float2 *f, size_t fs, float2 *fc,
                  size_t fcs, int nb, const int *active, hipStream_t s, const double *scale)
 {
@@ -403,18 +471,19 @@ void launch_down(const Level &L, float shift, float w, const float2 *f, size_t f
 
 void launch_up(const Level &L, float shift, float w, const float2 *f, size_t fs,
                const float2 *vc, size_t vcs, float2 *v, size_t vs, int nb, const int *active,
-               hipStream_t s, const double *scale)
+               hipStream_t s, const double *scale, int accumulate)
 {
     const int n = L.n;
     dim3 grid((n + UP_W - 1) / UP_W, (n + UP_H - 1) / UP_H, nb);
     prof_mark(HELM_PROF_UP, s, true);
     hipLaunchKernelGGL(k_up, grid, dim3(256), 0, s, f, fs, vc, vcs, v, vs, L.mass, n, L.ih2,
-                       shift, w, scale, active);
+                       shift, w, scale, accumulate, active);
     prof_mark(HELM_PROF_UP, s, false);
 }
 
 void launch_coarse_solve(const float2 *X, int N, const float2 *f, size_t fs, float2 *v,
-                         size_t vs, int nb, const int *active, hipStream_t s, const double *scale)
+                         size_t vs, int nb, const int *active, hipStream_t s, const double *scale,
+                         int accumulate)
 {
     dim3 grid((N + 3) / 4), block(256);
     prof_mark(HELM_PROF_COARSE, s, true);
@@ -422,16 +491,16 @@ void launch_coarse_solve(const float2 *X, int N, const float2 *f, size_t fs, flo
     while (b0 < nb) {
         int left = nb - b0;
         if (left >= 8) {
-            hipLaunchKernelGGL(k_coarse<8>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, active);
+            hipLaunchKernelGGL(k_coarse<8>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, accumulate, active);
             b0 += 8;
         } else if (left >= 4) {
-            hipLaunchKernelGGL(k_coarse<4>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, active);
+            hipLaunchKernelGGL(k_coarse<4>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, accumulate, active);
             b0 += 4;
         } else if (left >= 2) {
-            hipLaunchKernelGGL(k_coarse<2>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, active);
+            hipLaunchKernelGGL(k_coarse<2>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, accumulate, active);
             b0 += 2;
         } else {
-            hipLaunchKernelGGL(k_coarse<1>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, active);
+            hipLaunchKernelGGL(k_coarse<1>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, accumulate, active);
             b0 += 1;
         }
     }

@@ -89,7 +89,7 @@ void launch_net_input(const float2 *r, size_t rstride, int nb, int n, const floa
                       hipStream_t s_);
 // e (+)= P (s_b (out0 + i out1)) on the fine grid; out [nb][n/2][n/2][2] FP32.
 void launch_net_output(const float *out, const double *s, int nb, int n, float2 *e,
-                       size_t estride, int accumulate, hipStream_t st);
+                       size_t estride, int accumulate, hipStream_t st, const int *mask = nullptr);
 // Loss of one batch: d = P out_b - e_b / s_b (fine), loss = mean_b |d|^2 / n^2,
 // dout = (2 / (B n^2)) 4 R(d) split into (re, im).  loss_out: device double.
 void launch_loss_grad(const float *out, const double *s, int nb, int n, const float2 *e,

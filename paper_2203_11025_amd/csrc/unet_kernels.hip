@@ -614,7 +614,8 @@ __global__ void k_pack_input(const float2 *__restrict__ rc, const double *__rest
 // e (+)= P(s (out0 + i out1)), P bilinear prolongation (transposed stride-2
 // convolution with (1/4)[1 2 1; 2 4 2; 1 2 1])
 __global__ void k_net_output(const float *__restrict__ out, const double *__restrict__ s, int nb,
-                             int n, float2 *__restrict__ e, size_t es, int accumulate)
+                             int n, float2 *__restrict__ e, size_t es, int accumulate,
+                             const int *__restrict__ mask)
 {
     const int nc = n / 2;
     const size_t total = (size_t)nb * n * n;
@@ -622,6 +623,10 @@ __global__ void k_net_output(const float *__restrict__ out, const double *__rest
          idx += (size_t)gridDim.x * blockDim.x) {
         int b = (int)(idx / ((size_t)n * n));
         size_t pix = idx % ((size_t)n * n);
+        if (mask && !mask[b]) {
+            if (!accumulate) e[(size_t)b * es + pix] = make_float2(0.f, 0.f);
+            continue;
+        }
         int i = (int)(pix / n), j = (int)(pix % n);
         const float *ob = out + (size_t)b * nc * nc * 2;
         float sr = 0.f, si = 0.f;
@@ -1008,11 +1013,11 @@ void launch_net_input(const float2 *r, size_t rstride, int nb, int n, const floa
 }
 
 void launch_net_output(const float *out, const double *s, int nb, int n, float2 *e, size_t estride,
-                       int accumulate, hipStream_t st)
+                       int accumulate, hipStream_t st, const int *mask)
 {
     size_t tot = (size_t)nb * n * n;
     hipLaunchKernelGGL(k_net_output, dim3(grid_for(tot)), dim3(256), 0, st, out, s, nb, n, e, estride,
-                       accumulate);
+                       accumulate, mask);
 }
 
 void launch_loss_grad(const float *out, const double *s, int nb, int n, const float2 *e,

@@ -366,14 +366,14 @@ void unet_net::refold(hipStream_t st)
 }
 
 int unet_net::wrap_apply(helm_handle *h, const float2 *r, size_t rs, float2 *e, size_t es, int nb,
-                     int accumulate, hipStream_t st)
+                     int accumulate, hipStream_t st, const int *mask)
 {
     const int n = h->n, nc = n / 2;
     int rc = ensure_ws(nb, nc, nc, false);
     if (rc) return rc;
     launch_net_input(r, rs, nb, n, h->kappa0, nullptr, rcoarse, red, s, x0, st);
     forward_from_x0(nb, nc, nc, false, st);
-    launch_net_output(out, s, nb, n, e, es, accumulate, st);
+    launch_net_output(out, s, nb, n, e, es, accumulate, st, mask);
     return HELM_OK;
 }
 

@@ -24,7 +24,7 @@ PREC = {"sl": 0, "unet_cgc": 1, "unet_defl": 2}
 EXPORTS = [
     "helm_setup", "helm_destroy", "helm_level_size", "helm_num_levels", "helm_apply",
     "helm_sl_vcycle", "helm_fgmres_solve", "helm_last_error", "helm_profile_start",
-    "helm_profile_stop",
+    "helm_profile_stop", "helm_training_triples", "helm_coarse_slowness",
 ]
 PROF = {"none": 0, "coarse": 1, "down": 2, "up": 3, "cgs": 4, "apply": 5}
 
@@ -79,6 +79,10 @@ def lib():
         L.helm_fgmres_solve.restype = ip
         L.helm_last_error.argtypes = []
         L.helm_last_error.restype = C.c_char_p
+        L.helm_training_triples.argtypes = [vp, vp, vp, vp, ip, vp]
+        L.helm_training_triples.restype = ip
+        L.helm_coarse_slowness.argtypes = [vp, vp, vp]
+        L.helm_coarse_slowness.restype = ip
         L.helm_profile_start.argtypes = [ip]
         L.helm_profile_start.restype = ip
         L.helm_profile_stop.argtypes = [C.POINTER(dp), C.POINTER(C.c_longlong)]
@@ -161,6 +165,23 @@ class Handle:
                                 _dev(y, torch.complex64, "y"), x.shape[0], _stream(stream)),
                "helm_apply")
         return y
+
+    def training_triples(self, x, stream=None):
+        """(r, e) with one SL-FGMRES step from zero on b = A x (eq. 3.8-3.9)."""
+        x = self._batch(x, "x")
+        r = torch.empty_like(x)
+        e = torch.empty_like(x)
+        _check(lib().helm_training_triples(self._h, _dev(x, torch.complex64, "x"),
+                                           _dev(r, torch.complex64, "r"),
+                                           _dev(e, torch.complex64, "e"), x.shape[0],
+                                           _stream(stream)), "helm_training_triples")
+        return r, e
+
+    def coarse_slowness(self, stream=None):
+        kc = torch.empty((self.n // 2, self.n // 2), dtype=torch.float32, device="cuda")
+        _check(lib().helm_coarse_slowness(self._h, _dev(kc, torch.float32, "kc"), _stream(stream)),
+               "helm_coarse_slowness")
+        return kc
 
     def vcycle(self, f, out=None, stream=None):
         f = self._batch(f, "f")

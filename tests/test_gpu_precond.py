@@ -1,0 +1,149 @@
+"""GPU parity of the network preconditioners (M_CU, M_VU), the training
+triples and the learned part end to end, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import helm_oracle, unet_oracle as U
+from paper_2203_11025_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = (32, 64, 128)
+
+
+@pytest.fixture(scope="module")
+def mods():
+    from paper_2203_11025_amd import helm, train, unet
+
+    assert torch.cuda.is_available()
+    unet.lib()
+    return helm, unet, train
+
+
+def medium(n, seed):
+    kap = inputs.smooth_medium(n, max(2.0, n / 16), seed=seed)
+    gam = inputs.sponge_gamma(n, width=min(16, n // 8))
+    return kap, gam, inputs.omega_for_ppw(n)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def net_from_oracle(unet, seed, widths=WIDTHS):
+    cfg = U.UNetCfg(widths=widths)
+    p, buf = U.init_params(cfg, seed)
+    net = unet.UNet(widths=widths)
+    net.set_params(U.flatten(cfg, p), torch.cat([buf[k].reshape(-1) for k in U.buffer_shapes(cfg)]))
+    return cfg, p, buf, net
+
+
+def test_training_triples_parity(mods, oracle):
+    helm, unet, _ = mods
+    n = 64
+    kap, gam, om = medium(n, 3)
+    h = helm.Handle(torch.from_numpy(kap).cuda(), torch.from_numpy(gam).cuda(), om, levels=2)
+    H = oracle.Hierarchy(kap, gam, om, 2)
+    rng = np.random.default_rng(1)
+    x = (rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n))).astype(np.complex64)
+    r, e = h.training_triples(torch.from_numpy(x).cuda())
+    r, e = r.cpu().numpy(), e.cpu().numpy()
+    for k in range(2):
+        ro, eo = U.training_triple(H, x[k])
+        assert rel(r[k], ro) <= 1e-5 and rel(e[k], eo) <= 1e-5
+    kc = h.coarse_slowness().cpu().numpy()
+    np.testing.assert_array_equal(kc, kap[::2, ::2])
+
+
+@pytest.mark.parametrize("prec", ["unet_defl", "unet_cgc"])
+def test_first_preconditioned_step_matches_oracle(mods, oracle, prec):
+    """One FGMRES step with the network preconditioner: x_1 = y z_0 with
+    z_0 = Prec(b / |b|); compared with the oracle's preconditioner."""
+    helm, unet, _ = mods
+    n = 64
+    kap, gam, om = medium(n, 5)
+    h = helm.Handle(torch.from_numpy(kap).cuda(), torch.from_numpy(gam).cuda(), om, levels=2)
+    cfg, p, buf, net = net_from_oracle(unet, 13)
+    b = inputs.point_sources(n, 1, seed=2, margin=8)
+    xs, st, rc = helm.fgmres_solve([h], [torch.from_numpy(b).cuda()], m=5, tol=1e-12, maxit=1,
+                                   prec=prec, net=net)
+    x1 = xs[0].cpu().numpy()[0]
+    H = oracle.Hierarchy(kap, gam, om, 2)
+    kc = kap.astype(np.float64)[::2, ::2]
+    if prec == "unet_defl":
+        f = lambda v: U.precond_defl(H, cfg, p, buf, v, kc)
+    else:
+        f = lambda v: U.precond_cgc(H, cfg, p, buf, v, kc)
+    xo, sto = H.fgmres(b[0], m=5, tol=1e-12, maxit=1, prec=f)
+    assert st[0]["iterations"] == 1 and sto["iterations"] == 1
+    assert rel(x1, xo) <= 2e-2, rel(x1, xo)
+
+
+def test_defl_converges_with_untrained_network(mods, oracle):
+    """M_VU with a random network still converges to the FP64 tolerance
+    (FGMRES is flexible; the V-cycle stabilises the step)."""
+    helm, unet, _ = mods
+    n = 128
+    kap, gam, om = medium(n, 7)
+    h = helm.Handle(torch.from_numpy(kap).cuda(), torch.from_numpy(gam).cuda(), om, levels=3)
+    _, _, _, net = net_from_oracle(unet, 17)
+    b = inputs.point_sources(n, 2, seed=4)
+    xs, st, rc = helm.fgmres_solve([h], [torch.from_numpy(b).cuda()], m=10, tol=1e-7,
+                                   prec="unet_defl", net=net)
+    assert rc == 0
+    x = xs[0].cpu().numpy()
+    for k in range(2):
+        r = b[k].astype(complex) - oracle.apply(kap, gam, om, x[k])
+        assert np.linalg.norm(r) / np.linalg.norm(b[k]) <= 1e-7 and st[k]["converged"]
+
+
+def test_stall_fallback_switches_to_sl(mods, oracle):
+    """A network whose output ignores the residual (zero convolutions, BN
+    bias 1: a constant field) makes M_CU stall; with stall_ratio the solve
+    falls back to the plain SL V-cycle and still converges."""
+    helm, unet, _ = mods
+    n = 64
+    kap, gam, om = medium(n, 9)
+    h = helm.Handle(torch.from_numpy(kap).cuda(), torch.from_numpy(gam).cuda(), om, levels=2)
+    cfg = U.UNetCfg(widths=WIDTHS)
+    p, buf = U.init_params(cfg, 23)
+    for k in p:
+        p[k] = torch.zeros_like(p[k]) if k.endswith(".w") else torch.ones_like(p[k])
+    p["head.b"] = torch.zeros_like(p["head.b"])
+    net = unet.UNet(widths=WIDTHS)
+    net.set_params(U.flatten(cfg, p))
+    b = inputs.point_sources(n, 1, seed=6, margin=8)
+    xs, st, rc = helm.fgmres_solve([h], [torch.from_numpy(b).cuda()], m=10, tol=1e-7,
+                                   prec="unet_cgc", net=net, stall_ratio=0.95, maxit=3000)
+    assert st[0]["fallback"] == 1
+    assert rc == 0 and st[0]["converged"]
+    x = xs[0].cpu().numpy()[0]
+    r = b[0].astype(complex) - oracle.apply(kap, gam, om, x)
+    assert np.linalg.norm(r) / np.linalg.norm(b[0]) <= 1e-7
+
+
+def test_trained_network_beats_untrained_and_plain_sl(mods, oracle):
+    """The learned part pays: after training on triples of the medium (the
+    mini-retraining setting), M_VU needs fewer FGMRES iterations than with
+    the untrained network and than the plain SL V-cycle."""
+    helm, unet, train = mods
+    n = 128
+    kap, gam, om = medium(n, 11)
+    h = helm.Handle(torch.from_numpy(kap).cuda(), torch.from_numpy(gam).cuda(), om, levels=3)
+    _, _, _, net = net_from_oracle(unet, 29)
+    b = torch.from_numpy(inputs.point_sources(n, 4, seed=8)).cuda()
+
+    def iters(prec, nt=None):
+        xs, st, rc = helm.fgmres_solve([h], [b], m=10, tol=1e-7, prec=prec, net=nt)
+        assert rc == 0 and all(s["converged"] for s in st)
+        return float(np.mean([s["iterations"] for s in st]))
+
+    it_sl = iters("sl")
+    it_untrained = iters("unet_defl", net)
+    losses = train.train(net, [h], steps=400, batch=16, lr=1e-3, seed=1)
+    it_trained = iters("unet_defl", net)
+    print(f"iterations: SL {it_sl}, untrained M_VU {it_untrained}, trained M_VU {it_trained}; "
+          f"loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    assert losses[-1] < 0.5 * losses[0]
+    assert it_trained < it_untrained and it_trained < it_sl

@@ -119,3 +119,21 @@ def test_maxpool_first_maximum_gradient():
     x = torch.tensor([[[[1.0, 3.0], [3.0, 2.0]]]], requires_grad=True)
     F.max_pool2d(x, 2).sum().backward()
     np.testing.assert_array_equal(x.grad.numpy()[0, 0], [[0.0, 1.0], [0.0, 0.0]])
+
+
+def test_training_triple_residual_and_one_step_minimiser(oracle):
+    """A e = r, and x~ = x - e is the one-step FGMRES(SL) iterate from zero."""
+    n = 32
+    kap = np.full((n, n), 0.8)
+    kap[10:20, 5:25] = 0.5
+    from paper_2203_11025_amd import inputs
+    gam = inputs.sponge_gamma(n, width=4).astype(np.float64)
+    om = inputs.omega_for_ppw(n)
+    H = oracle.Hierarchy(kap, gam, om, 2)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    r, e = U.training_triple(H, x)
+    np.testing.assert_allclose(oracle.apply(kap, gam, om, e), r, atol=1e-9 * np.abs(r).max())
+    b = oracle.apply(kap, gam, om, x)
+    x1, st = H.fgmres(b, m=5, tol=1e-14, maxit=1)
+    np.testing.assert_allclose(x - e, x1, atol=1e-10 * np.abs(x1).max())
