@@ -24,6 +24,28 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// 8 bf16 channels <-> 8 floats (16-byte vectors)
+struct f8 {
+    float v[8];
+};
+__device__ __forceinline__ f8 ld8(const bf16 *p)
+{
+    uint4 u = *reinterpret_cast<const uint4 *>(p);
+    const bf16 *e = reinterpret_cast<const bf16 *>(&u);
+    f8 r;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r.v[q] = (float)e[q];
+    return r;
+}
+__device__ __forceinline__ void st8(bf16 *p, const f8 &r)
+{
+    uint4 u;
+    bf16 *e = reinterpret_cast<bf16 *>(&u);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) e[q] = (bf16)r.v[q];
+    *reinterpret_cast<uint4 *>(p) = u;
+}
+
 // ------------------------------------------------------------------ conv fwd
 // Block: 4 wavefronts; tile TH = 4 MF rows x 16 columns of pixels and
 // CO = 16 NF output channels.  Wavefront w owns pixel rows w MF .. w MF +
@@ -127,81 +149,112 @@ __global__ __launch_bounds__(256) void k_conv3x3(Srcs in, int H, int W,
 }
 
 // ------------------------------------------------------------------ wgrad
-// dW[co][tap][ci] over a range of pixels (split K).  Block tile: 64 output x
-// 64 input channels for one tap; K steps of 32 pixels staged transposed in
-// LDS ([channel][pixel]) so each MFMA fragment is one 16-byte LDS read.
-// Wavefront w owns output-channel rows 16 w .. 16 w + 15 and all 4 input
-// channel fragments.
-constexpr int WG_CB = 64, WG_IB = 64, WG_K = 32, WG_PAD = 40;
+// dW[co][tap][ci] = sum_p dy[p][co] X[p + tap offset][ci] over a range of
+// K steps (split K).  One workgroup owns a block of up to 64 output and 64
+// input channels for all 9 taps.  A K step is one image-row segment of 32
+// pixels: dy for the segment and X for the three rows around it are staged
+// transposed ([channel][pixel]) in LDS, X as three copies shifted by kx so
+// every MFMA fragment is an aligned 16-byte LDS read.  Wavefront w owns
+// output-channel fragment w % NCF and the taps tg, tg + 4/NCF, ... with
+// tg = w / NCF.
+constexpr int WG_CB = 64, WG_IB = 64, WG_SEG = 32, WG_PAD = 40;
 
+template <int NCF>
 __global__ __launch_bounds__(256) void k_wgrad(Srcs x, const bf16 *__restrict__ dy, int B, int H,
-                                               int W, int Cout, int npix_split,
+                                               int W, int Cout, int steps_per_split,
                                                float *__restrict__ part)
 {
+    constexpr int TS = 4 / NCF;                 // tap stride between a wave's taps
+    constexpr int NT = (9 + TS - 1) / TS;       // taps per wave (upper bound)
     __shared__ __attribute__((aligned(16))) bf16 sa[WG_CB * WG_PAD];
-    __shared__ __attribute__((aligned(16))) bf16 sb[WG_IB * WG_PAD];
+    __shared__ __attribute__((aligned(16))) bf16 sb[3][3][WG_IB * WG_PAD];  // [kx][ky][ci][px]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int ncb = (Cout + WG_CB - 1) / WG_CB, nib = (x.Ctot + WG_IB - 1) / WG_IB;
-    const int tap = blockIdx.y % 9;
-    const int cb = (blockIdx.y / 9) % ncb, ib = (blockIdx.y / 9) / ncb;
-    const int split = blockIdx.x;
-    const int dyo = tap / 3 - 1, dxo = tap % 3 - 1;
-    const size_t P = (size_t)B * H * W;
-    const size_t p_begin = (size_t)split * npix_split;
-    const size_t p_end = std::min(P, p_begin + (size_t)npix_split);
-    f32x4 acc[4];
+    const int ncb = (Cout + WG_CB - 1) / WG_CB;
+    const int cb = blockIdx.y % ncb, ib = blockIdx.y / ncb;
+    const int cf = wv % NCF, tg = wv / NCF;
+    const int nseg_row = (W + WG_SEG - 1) / WG_SEG;
+    const int total_steps = B * H * nseg_row;
+    const int s_begin = blockIdx.x * steps_per_split;
+    const int s_end = min(total_steps, s_begin + steps_per_split);
+    f32x4 acc[NT][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // loader mapping: thread t -> pixel t / 8, 8-channel segment t % 8
-    const int lp = tid >> 3, lseg = tid & 7;
-    const int co_l = cb * WG_CB + lseg * 8, ci_l = ib * WG_IB + lseg * 8;
-    // source of this thread's input-channel segment
-    int s = 0, coff = ci_l;
-    while (s < x.n - 1 && coff >= x.s[s].C) {
-        coff -= x.s[s].C;
-        ++s;
-    }
-    const bool ci_ok = ci_l < x.Ctot;
-    for (size_t p0 = p_begin; p0 < p_end; p0 += WG_K) {
-        const size_t p = p0 + lp;
-        uint4 va = {0u, 0u, 0u, 0u}, vb = {0u, 0u, 0u, 0u};
-        if (p < p_end) {
-            if (co_l < Cout) va = *reinterpret_cast<const uint4 *>(dy + p * Cout + co_l);
-            const int xx = (int)(p % W), yy = (int)((p / W) % H);
-            const size_t bb = p / ((size_t)W * H);
-            const int ys = yy + dyo, xs = xx + dxo;
-            if (ci_ok && ys >= 0 && ys < H && xs >= 0 && xs < W)
-                vb = *reinterpret_cast<const uint4 *>(
-                    x.s[s].p + ((bb * H + ys) * W + xs) * x.s[s].C + coff);
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // dy loader: thread -> pixel tid / 8, 8-channel group tid % 8
+    const int lp = tid >> 3, lg = tid & 7;
+    const int co_l = cb * WG_CB + lg * 8;
+    for (int st = s_begin; st < s_end; ++st) {
+        const int seg = st % nseg_row, rowi = st / nseg_row;
+        const int y = rowi % H, b = rowi / H;
+        const int x0 = seg * WG_SEG;
+        {
+            uint4 va = {0u, 0u, 0u, 0u};
+            const int xx = x0 + lp;
+            if (xx < W && co_l < Cout)
+                va = *reinterpret_cast<const uint4 *>(dy + (((size_t)b * H + y) * W + xx) * Cout + co_l);
+            const bf16 *ea = reinterpret_cast<const bf16 *>(&va);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sa[(lg * 8 + q) * WG_PAD + lp] = ea[q];
         }
-        const bf16 *ea = reinterpret_cast<const bf16 *>(&va);
-        const bf16 *eb = reinterpret_cast<const bf16 *>(&vb);
+        // X: rows y-1..y+1, pixels x0-1 .. x0+32, 8 input-channel groups
+        for (int idx = tid; idx < 3 * (WG_SEG + 2) * 8; idx += 256) {
+            const int g = idx & 7, r = idx >> 3;
+            const int ky = r / (WG_SEG + 2), px = r % (WG_SEG + 2);  // px = pixel x0 - 1 + px
+            const int ys = y + ky - 1, xs = x0 + px - 1;
+            const int ci_l = ib * WG_IB + g * 8;
+            uint4 vb = {0u, 0u, 0u, 0u};
+            if (ci_l < x.Ctot && ys >= 0 && ys < H && xs >= 0 && xs < W) {
+                int s = 0, coff = ci_l;
+                while (s < x.n - 1 && coff >= x.s[s].C) {
+                    coff -= x.s[s].C;
+                    ++s;
+                }
+                vb = *reinterpret_cast<const uint4 *>(x.s[s].p + (((size_t)b * H + ys) * W + xs) * x.s[s].C +
+                                                      coff);
+            }
+            const bf16 *eb = reinterpret_cast<const bf16 *>(&vb);
+            // copy kx holds X at pixel (segment pixel k) + kx - 1, i.e. px = k + kx
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            sa[(lseg * 8 + q) * WG_PAD + lp] = ea[q];
-            sb[(lseg * 8 + q) * WG_PAD + lp] = eb[q];
+            for (int kx = 0; kx < 3; ++kx) {
+                const int k = px - kx;
+                if (k >= 0 && k < WG_SEG)
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) sb[kx][ky][(g * 8 + q) * WG_PAD + k] = eb[q];
+            }
         }
         __syncthreads();
-        bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sa[(wv * 16 + (lane & 15)) * WG_PAD + 8 * (lane >> 4)]);
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sa[(cf * 16 + (lane & 15)) * WG_PAD + 8 * (lane >> 4)]);
 #pragma unroll
-        for (int nf = 0; nf < 4; ++nf) {
-            bf16x8 bw = *reinterpret_cast<const bf16x8 *>(
-                &sb[(nf * 16 + (lane & 15)) * WG_PAD + 8 * (lane >> 4)]);
-            acc[nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[nf], 0, 0, 0);
+        for (int t = 0; t < NT; ++t) {
+            const int tap = tg + t * TS;
+            if (tap < 9) {
+                const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+#pragma unroll
+                for (int nf = 0; nf < 4; ++nf) {
+                    const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(
+                        &sb[kx][ky][(nf * 16 + (lane & 15)) * WG_PAD + 8 * (lane >> 4)]);
+                    acc[t][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[t][nf], 0, 0, 0);
+                }
+            }
         }
         __syncthreads();
     }
-    // partial[split][co][tap][ci]
     const size_t per_split = (size_t)Cout * 9 * x.Ctot;
 #pragma unroll
-    for (int nf = 0; nf < 4; ++nf)
+    for (int t = 0; t < NT; ++t) {
+        const int tap = tg + t * TS;
+        if (tap >= 9) continue;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int co = cb * WG_CB + wv * 16 + 4 * (lane >> 4) + q;
-            const int ci = ib * WG_IB + nf * 16 + (lane & 15);
-            if (co < Cout && ci < x.Ctot)
-                part[split * per_split + ((size_t)co * 9 + tap) * x.Ctot + ci] = acc[nf][q];
-        }
+        for (int nf = 0; nf < 4; ++nf)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int co = cb * WG_CB + cf * 16 + 4 * (lane >> 4) + q;
+                const int ci = ib * WG_IB + nf * 16 + (lane & 15);
+                if (co < Cout && ci < x.Ctot)
+                    part[blockIdx.x * per_split + ((size_t)co * 9 + tap) * x.Ctot + ci] = acc[t][nf][q];
+            }
+    }
 }
 
 __global__ void k_sum_splits(const float *__restrict__ part, int nsplit, size_t n,
@@ -244,17 +297,20 @@ __global__ __launch_bounds__(256) void k_bn_partial(const float *__restrict__ y,
     }
 }
 
+// one wavefront per channel; fixed-order sums over the partials
 __global__ void k_bn_finish(const double *__restrict__ part, int nblk, int C, size_t P,
                             float *__restrict__ mean, float *__restrict__ rstd,
                             float *__restrict__ var_out)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
+    const int c = blockIdx.x;
     double a = 0.0, q = 0.0;
-    for (int k = 0; k < nblk; ++k) {
+    for (int k = threadIdx.x; k < nblk; k += 64) {
         a += part[((size_t)k * C + c) * 2];
         q += part[((size_t)k * C + c) * 2 + 1];
     }
+    a = wave_sum(a);
+    q = wave_sum(q);
+    if (threadIdx.x != 0) return;
     double mu = a / (double)P, var = q / (double)P - mu * mu;
     if (var < 0.0) var = 0.0;
     mean[c] = (float)mu;
@@ -267,11 +323,21 @@ __global__ void k_bn_act_fwd(const float *__restrict__ y, size_t n, int C,
                              const float *__restrict__ g, const float *__restrict__ bb, float slope,
                              bf16 *__restrict__ a)
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        int c = (int)(i % C);
-        float z = g[c] * (y[i] - mean[c]) * rstd[c] + bb[c];
-        a[i] = (bf16)(z > 0.f ? z : slope * z);
+    const int G = C / 8;
+    const int nv = (int)(n / 8);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
+        int c0 = (i % G) * 8;
+        float4 u0 = *reinterpret_cast<const float4 *>(y + (size_t)i * 8);
+        float4 u1 = *reinterpret_cast<const float4 *>(y + (size_t)i * 8 + 4);
+        float yv[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+        f8 o;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int c = c0 + q;
+            float z = g[c] * (yv[q] - mean[c]) * rstd[c] + bb[c];
+            o.v[q] = z > 0.f ? z : slope * z;
+        }
+        st8(a + (size_t)i * 8, o);
     }
 }
 
@@ -310,13 +376,15 @@ __global__ void k_bn_bwd_finish(const double *__restrict__ part, int nblk, int C
                                 float *__restrict__ dg, float *__restrict__ db,
                                 float *__restrict__ sums)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
+    const int c = blockIdx.x;
     double a = 0.0, q = 0.0;
-    for (int k = 0; k < nblk; ++k) {
+    for (int k = threadIdx.x; k < nblk; k += 64) {
         a += part[((size_t)k * C + c) * 2];
         q += part[((size_t)k * C + c) * 2 + 1];
     }
+    a = wave_sum(a);
+    q = wave_sum(q);
+    if (threadIdx.x != 0) return;
     db[c] += (float)a;
     dg[c] += (float)q;
     sums[2 * c] = (float)a;
@@ -330,39 +398,62 @@ __global__ void k_bn_bwd_apply(const float *__restrict__ da, const float *__rest
                                const float *__restrict__ sums, bf16 *__restrict__ dy)
 {
     const float invP = 1.f / (float)P;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        int c = (int)(i % C);
-        float xh = (y[i] - mean[c]) * rstd[c];
-        float z = g[c] * xh + bb[c];
-        float dz = da[i] * (z > 0.f ? 1.f : slope);
-        float v = g[c] * rstd[c] * (dz - sums[2 * c] * invP - xh * sums[2 * c + 1] * invP);
-        dy[i] = (bf16)v;
+    const int G = C / 8;
+    const int nv = (int)(n / 8);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
+        int c0 = (i % G) * 8;
+        float4 u0 = *reinterpret_cast<const float4 *>(y + (size_t)i * 8);
+        float4 u1 = *reinterpret_cast<const float4 *>(y + (size_t)i * 8 + 4);
+        float4 d0 = *reinterpret_cast<const float4 *>(da + (size_t)i * 8);
+        float4 d1 = *reinterpret_cast<const float4 *>(da + (size_t)i * 8 + 4);
+        float yv[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+        float dv[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+        f8 o;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int c = c0 + q;
+            float xh = (yv[q] - mean[c]) * rstd[c];
+            float z = g[c] * xh + bb[c];
+            float dz = dv[q] * (z > 0.f ? 1.f : slope);
+            o.v[q] = g[c] * rstd[c] * (dz - sums[2 * c] * invP - xh * sums[2 * c + 1] * invP);
+        }
+        st8(dy + (size_t)i * 8, o);
     }
 }
 
 // ------------------------------------------------------------------ pooling
+// thread per (output pixel, 8-channel group)
 __global__ void k_maxpool_fwd(const bf16 *__restrict__ in, int B, int H, int W, int C,
                               bf16 *__restrict__ out, uint8_t *__restrict__ arg)
 {
-    const int Ho = H / 2, Wo = W / 2;
-    const size_t n = (size_t)B * Ho * Wo * C;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        int c = (int)(i % C);
-        size_t r = i / C;
-        int xo = (int)(r % Wo), yo = (int)((r / Wo) % Ho);
-        size_t b = r / ((size_t)Wo * Ho);
-        size_t base = ((b * H + 2 * yo) * W + 2 * xo) * C + c;
-        float v0 = (float)in[base], v1 = (float)in[base + C];
-        float v2 = (float)in[base + (size_t)W * C], v3 = (float)in[base + (size_t)W * C + C];
-        float best = v0;
-        uint8_t k = 0;
-        if (v1 > best) { best = v1; k = 1; }
-        if (v2 > best) { best = v2; k = 2; }
-        if (v3 > best) { best = v3; k = 3; }
-        out[i] = (bf16)best;
-        if (arg) arg[i] = k;
+    const int Ho = H / 2, Wo = W / 2, G = C / 8;
+    const int n = B * Ho * Wo * G;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int g = i % G, pix = i / G;
+        int xo = pix % Wo, r = pix / Wo;
+        int yo = r % Ho, b = r / Ho;
+        size_t base = (((size_t)b * H + 2 * yo) * W + 2 * xo) * C + 8 * g;
+        f8 v0 = ld8(in + base), v1 = ld8(in + base + C);
+        f8 v2 = ld8(in + base + (size_t)W * C), v3 = ld8(in + base + (size_t)W * C + C);
+        f8 o;
+        uint8_t k8[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            float best = v0.v[q];
+            uint8_t k = 0;
+            if (v1.v[q] > best) { best = v1.v[q]; k = 1; }
+            if (v2.v[q] > best) { best = v2.v[q]; k = 2; }
+            if (v3.v[q] > best) { best = v3.v[q]; k = 3; }
+            o.v[q] = best;
+            k8[q] = k;
+        }
+        st8(out + (size_t)pix * C + 8 * g, o);
+        if (arg) {
+            uint2 packed;
+            packed.x = k8[0] | (k8[1] << 8) | (k8[2] << 16) | ((uint32_t)k8[3] << 24);
+            packed.y = k8[4] | (k8[5] << 8) | (k8[6] << 16) | ((uint32_t)k8[7] << 24);
+            *reinterpret_cast<uint2 *>(arg + (size_t)pix * C + 8 * g) = packed;
+        }
     }
 }
 
@@ -371,17 +462,14 @@ __global__ void k_maxpool_bwd(const float *__restrict__ dout, const uint8_t *__r
                               int coff)
 {
     const int Ho = H / 2, Wo = W / 2;
-    const size_t n = (size_t)B * Ho * Wo * C;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        int c = (int)(i % C);
-        size_t r = i / C;
-        int xo = (int)(r % Wo), yo = (int)((r / Wo) % Ho);
-        size_t b = r / ((size_t)Wo * Ho);
-        float g = dout[i];
+    const int n = B * Ho * Wo * C;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int c = i % C, pix = i / C;
+        int xo = pix % Wo, r = pix / Wo;
+        int yo = r % Ho, b = r / Ho;
         int k = arg[i];
         int yy = 2 * yo + (k >> 1), xx = 2 * xo + (k & 1);
-        din[((b * H + yy) * W + xx) * din_C + coff + c] += g;
+        din[(((size_t)b * H + yy) * W + xx) * din_C + coff + c] += dout[i];
     }
 }
 
@@ -398,24 +486,25 @@ __device__ __forceinline__ void up_src(int o, int n, int &i0, int &i1, float &l1
 __global__ void k_up2_fwd(const bf16 *__restrict__ in, int B, int h, int w, int C,
                           bf16 *__restrict__ out)
 {
-    const int H = 2 * h, W = 2 * w;
-    const size_t n = (size_t)B * H * W * C;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        int c = (int)(i % C);
-        size_t r = i / C;
-        int x = (int)(r % W), y = (int)((r / W) % H);
-        size_t b = r / ((size_t)W * H);
+    const int H = 2 * h, W = 2 * w, G = C / 8;
+    const int n = B * H * W * G;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int g = i % G, pix = i / G;
+        int x = pix % W, r = pix / W;
+        int y = r % H, b = r / H;
         int y0, y1, x0, x1;
         float ly, lx;
         up_src(y, h, y0, y1, ly);
         up_src(x, w, x0, x1, lx);
-        const bf16 *pb = in + b * h * w * C + c;
-        float v = (1.f - ly) * ((1.f - lx) * (float)pb[((size_t)y0 * w + x0) * C] +
-                                lx * (float)pb[((size_t)y0 * w + x1) * C]) +
-                  ly * ((1.f - lx) * (float)pb[((size_t)y1 * w + x0) * C] +
-                        lx * (float)pb[((size_t)y1 * w + x1) * C]);
-        out[i] = (bf16)v;
+        const bf16 *pb = in + (size_t)b * h * w * C + 8 * g;
+        f8 a00 = ld8(pb + ((size_t)y0 * w + x0) * C), a01 = ld8(pb + ((size_t)y0 * w + x1) * C);
+        f8 a10 = ld8(pb + ((size_t)y1 * w + x0) * C), a11 = ld8(pb + ((size_t)y1 * w + x1) * C);
+        f8 o;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            o.v[q] = (1.f - ly) * ((1.f - lx) * a00.v[q] + lx * a01.v[q]) +
+                     ly * ((1.f - lx) * a10.v[q] + lx * a11.v[q]);
+        st8(out + (size_t)pix * C + 8 * g, o);
     }
 }
 
@@ -434,13 +523,11 @@ __global__ void k_up2_bwd(const float *__restrict__ dout, int cstride, int coff,
                           int C, float *__restrict__ din, int accumulate)
 {
     const int H = 2 * h, W = 2 * w;
-    const size_t n = (size_t)B * h * w * C;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        int c = (int)(i % C);
-        size_t r = i / C;
-        int xi = (int)(r % w), yi = (int)((r / w) % h);
-        size_t b = r / ((size_t)w * h);
+    const int n = B * h * w * C;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int c = i % C, r = i / C;
+        int xi = r % w, r2 = r / w;
+        int yi = r2 % h, b = r2 / h;
         int oy[4], ox[4];
         float wy[4], wx[4];
         up_adj(yi, h, oy, wy);
@@ -451,7 +538,7 @@ __global__ void k_up2_bwd(const float *__restrict__ dout, int cstride, int coff,
             for (int d = 0; d < 4; ++d) {
                 if (wx[d] == 0.f) continue;
                 acc += wy[a] * wx[d] *
-                       dout[((b * H + oy[a]) * W + ox[d]) * cstride + coff + c];
+                       dout[(((size_t)b * H + oy[a]) * W + ox[d]) * cstride + coff + c];
             }
         }
         din[i] = accumulate ? din[i] + acc : acc;
@@ -461,12 +548,10 @@ __global__ void k_up2_bwd(const float *__restrict__ dout, int cstride, int coff,
 __global__ void k_slice_add(const float *__restrict__ src, int cstride, int coff, size_t P, int C,
                             float *__restrict__ dst, int accumulate)
 {
-    const size_t n = P * C;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        size_t p = i / C;
-        int c = (int)(i % C);
-        float v = src[p * cstride + coff + c];
+    const int n = (int)(P * C);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int p = i / C, c = i % C;
+        float v = src[(size_t)p * cstride + coff + c];
         dst[i] = accumulate ? dst[i] + v : v;
     }
 }
@@ -482,53 +567,82 @@ __global__ void k_f32_to_bf16(const float *__restrict__ x, size_t n, bf16 *__res
 __global__ void k_head_fwd(const bf16 *__restrict__ a, size_t P, int C, const float *__restrict__ Wh,
                            const float *__restrict__ bh, float *__restrict__ out)
 {
-    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
-         p += (size_t)gridDim.x * blockDim.x) {
+    __shared__ float w[2 * 256];
+    for (int t = threadIdx.x; t < 2 * C; t += blockDim.x) w[t] = Wh[t];
+    __syncthreads();
+    const int np = (int)P;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
         float s0 = bh[0], s1 = bh[1];
-        for (int c = 0; c < C; ++c) {
-            float v = (float)a[p * C + c];
-            s0 += Wh[c] * v;
-            s1 += Wh[C + c] * v;
+        const bf16 *ap = a + (size_t)p * C;
+        for (int c0 = 0; c0 < C; c0 += 8) {
+            f8 v = ld8(ap + c0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                s0 += w[c0 + q] * v.v[q];
+                s1 += w[C + c0 + q] * v.v[q];
+            }
         }
-        out[2 * p] = s0;
-        out[2 * p + 1] = s1;
+        *reinterpret_cast<float2 *>(out + 2 * (size_t)p) = make_float2(s0, s1);
     }
 }
 
-// da[p][c] = sum_k Wh[k][c] dout[p][k]; per-block partial sums of
-// dout[p][k] a[p][c] (entries 0..2C-1) and dout[p][k] (2C, 2C+1)
+// da[p][c] = sum_k Wh[k][c] dout[p][k] (thread per pixel and 8-channel group)
+__global__ void k_head_bwd_da(const float *__restrict__ dout, int P, int C,
+                              const float *__restrict__ Wh, float *__restrict__ da)
+{
+    const int G = C / 8, n = P * G;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int g = i % G, p = i / G;
+        float2 d = *reinterpret_cast<const float2 *>(dout + 2 * (size_t)p);
+        float o[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o[q] = Wh[8 * g + q] * d.x + Wh[C + 8 * g + q] * d.y;
+        float4 *dst = reinterpret_cast<float4 *>(da + (size_t)p * C + 8 * g);
+        dst[0] = make_float4(o[0], o[1], o[2], o[3]);
+        dst[1] = make_float4(o[4], o[5], o[6], o[7]);
+    }
+}
+
+// per-block partial sums: entries k*C + c = sum_p dout[p][k] a[p][c], and
+// 2C + k = sum_p dout[p][k]; thread t handles channel t % C
 __global__ __launch_bounds__(256) void k_head_bwd(const float *__restrict__ dout,
                                                   const bf16 *__restrict__ a, size_t P, int C,
                                                   const float *__restrict__ Wh,
                                                   float *__restrict__ da,
                                                   double *__restrict__ part, int nblk)
 {
-    __shared__ double sh[256][2];
-    const int t = threadIdx.x;
-    // pass 1: da (one thread per pixel)
-    for (size_t p = (size_t)blockIdx.x * 256 + t; p < P; p += (size_t)nblk * 256) {
-        float g0 = dout[2 * p], g1 = dout[2 * p + 1];
-        for (int c = 0; c < C; ++c) da[p * C + c] = Wh[c] * g0 + Wh[C + c] * g1;
-    }
-    // pass 2: sums, thread t handles column c = t % (2C+2) of the parameter gradient
-    const int ncol = 2 * C + 2;
-    const int col = t % ncol, r0 = t / ncol, rs = 256 / ncol;
-    double acc = 0.0;
+    (void)Wh;
+    (void)da;
+    const int t = threadIdx.x, c = t % C, r0 = t / C, rs = 256 / C;
+    double s0 = 0.0, s1 = 0.0, b0 = 0.0, b1 = 0.0;
     if (r0 < rs)
         for (size_t p = (size_t)blockIdx.x * rs + r0; p < P; p += (size_t)nblk * rs) {
-            if (col < 2 * C) {
-                int k = col / C, c = col % C;
-                acc += (double)dout[2 * p + k] * (float)a[p * C + c];
-            } else {
-                acc += dout[2 * p + (col - 2 * C)];
+            float2 d = *reinterpret_cast<const float2 *>(dout + 2 * p);
+            float v = (float)a[p * C + c];
+            s0 += (double)d.x * v;
+            s1 += (double)d.y * v;
+            if (c == 0) {
+                b0 += d.x;
+                b1 += d.y;
             }
         }
-    sh[t][0] = acc;
+    __shared__ double sh[4][256];
+    sh[0][t] = s0;
+    sh[1][t] = s1;
+    sh[2][t] = b0;
+    sh[3][t] = b1;
     __syncthreads();
-    if (t < ncol) {
-        double s = 0.0;
-        for (int r = 0; r < rs; ++r) s += sh[r * ncol + t][0];
-        part[(size_t)blockIdx.x * ncol + t] = s;
+    const int ncol = 2 * C + 2;
+    for (int col = t; col < ncol; col += 256) {
+        double acc = 0.0;
+        if (col < 2 * C) {
+            int k = col / C, cc = col % C;
+            for (int r = 0; r < rs; ++r) acc += sh[k][r * C + cc];
+        } else {
+            int k = col - 2 * C;
+            for (int r = 0; r < rs; ++r) acc += sh[2 + k][r * C];
+        }
+        part[(size_t)blockIdx.x * ncol + col] = acc;
     }
 }
 
@@ -536,10 +650,12 @@ __global__ void k_head_bwd_finish(const double *__restrict__ part, int nblk, int
                                   float *__restrict__ dWh, float *__restrict__ dbh)
 {
     const int ncol = 2 * C + 2;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x;
     if (t >= ncol) return;
     double s = 0.0;
-    for (int k = 0; k < nblk; ++k) s += part[(size_t)k * ncol + t];
+    for (int k = threadIdx.x; k < nblk; k += 64) s += part[(size_t)k * ncol + t];
+    s = wave_sum(s);
+    if (threadIdx.x != 0) return;
     if (t < 2 * C)
         dWh[t] += (float)s;
     else
@@ -594,20 +710,25 @@ __global__ void k_pack_input(const float2 *__restrict__ rc, const double *__rest
                              bf16 *__restrict__ x0)
 {
     const int nc = n / 2;
-    const size_t total = (size_t)nb * nc * nc;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * blockDim.x) {
-        int b = (int)(i / ((size_t)nc * nc));
-        size_t pix = i % ((size_t)nc * nc);
-        int I = (int)(pix / nc), J = (int)(pix % nc);
+    const int total = nb * nc * nc;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        int b = i / (nc * nc), pix = i - b * nc * nc;
+        int I = pix / nc, J = pix - I * nc;
         float inv = s[b] > 0.0 ? (float)(1.0 / s[b]) : 0.f;
         float2 v = rc[i];
         float kap = kf ? kf[(size_t)(2 * I) * n + 2 * J] : kc[i];
-        bf16 *o = x0 + i * 32;
-        o[0] = (bf16)(v.x * inv);
-        o[1] = (bf16)(v.y * inv);
-        o[2] = (bf16)kap;
-        for (int c = 3; c < 32; ++c) o[c] = (bf16)0.f;
+        f8 head;
+        head.v[0] = v.x * inv;
+        head.v[1] = v.y * inv;
+        head.v[2] = kap;
+#pragma unroll
+        for (int q = 3; q < 8; ++q) head.v[q] = 0.f;
+        bf16 *o = x0 + (size_t)i * 32;
+        st8(o, head);
+        const uint4 z = {0u, 0u, 0u, 0u};
+        *reinterpret_cast<uint4 *>(o + 8) = z;
+        *reinterpret_cast<uint4 *>(o + 16) = z;
+        *reinterpret_cast<uint4 *>(o + 24) = z;
     }
 }
 
@@ -722,11 +843,10 @@ __global__ void k_loss_back(const float2 *__restrict__ d, int nb, int n, float *
 __global__ void k_loss_finish(const double *__restrict__ part, int nblk, int nb, int n,
                               double *__restrict__ loss)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double a = 0.0;
-    for (int b = 0; b < nb; ++b)
-        for (int k = 0; k < nblk; ++k) a += part[(size_t)b * nblk + k];
-    *loss = a / ((double)n * n) / nb;
+    for (int k = threadIdx.x; k < nb * nblk; k += 64) a += part[k];
+    a = wave_sum(a);
+    if (threadIdx.x == 0) *loss = a / ((double)n * n) / nb;
 }
 
 // ------------------------------------------------------------------ params
@@ -872,11 +992,10 @@ void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
 
 static int wgrad_nsplit(int B, int H, int W, int Cout, int Ctot)
 {
-    size_t P = (size_t)B * H * W;
-    int blocks = 9 * ((Cout + WG_CB - 1) / WG_CB) * ((Ctot + WG_IB - 1) / WG_IB);
-    int want = std::max(1, 2048 / blocks);
-    size_t maxs = (P + 255) / 256;  // at least 256 pixels per split
-    return (int)std::max<size_t>(1, std::min<size_t>((size_t)want, maxs));
+    const int steps = B * H * ((W + WG_SEG - 1) / WG_SEG);
+    const int blocks = ((Cout + WG_CB - 1) / WG_CB) * ((Ctot + WG_IB - 1) / WG_IB);
+    int want = std::max(1, 1024 / blocks);
+    return std::max(1, std::min(want, (steps + 7) / 8));  // at least 8 steps per split
 }
 
 size_t wgrad_scratch(int B, int H, int W, int Cout, int Ctot)
@@ -887,12 +1006,18 @@ size_t wgrad_scratch(int B, int H, int W, int Cout, int Ctot)
 void launch_wgrad(const Srcs &x, const bf16 *dy, int B, int H, int W, int Cout, float *dW,
                   float *part, hipStream_t s)
 {
-    size_t P = (size_t)B * H * W;
+    const int steps = B * H * ((W + WG_SEG - 1) / WG_SEG);
     int nsplit = wgrad_nsplit(B, H, W, Cout, x.Ctot);
-    int per = (int)(((P + nsplit - 1) / nsplit + WG_K - 1) / WG_K * WG_K);
-    nsplit = (int)((P + per - 1) / per);
-    dim3 grid(nsplit, 9 * ((Cout + WG_CB - 1) / WG_CB) * ((x.Ctot + WG_IB - 1) / WG_IB));
-    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, s, x, dy, B, H, W, Cout, per, part);
+    const int per = (steps + nsplit - 1) / nsplit;
+    nsplit = (steps + per - 1) / per;
+    dim3 grid(nsplit, ((Cout + WG_CB - 1) / WG_CB) * ((x.Ctot + WG_IB - 1) / WG_IB));
+    const int ncf = std::min(4, (Cout + 15) / 16);
+    if (ncf >= 4)
+        hipLaunchKernelGGL(k_wgrad<4>, grid, dim3(256), 0, s, x, dy, B, H, W, Cout, per, part);
+    else if (ncf >= 2)
+        hipLaunchKernelGGL(k_wgrad<2>, grid, dim3(256), 0, s, x, dy, B, H, W, Cout, per, part);
+    else
+        hipLaunchKernelGGL(k_wgrad<1>, grid, dim3(256), 0, s, x, dy, B, H, W, Cout, per, part);
     size_t n = (size_t)Cout * 9 * x.Ctot;
     hipLaunchKernelGGL(k_sum_splits, dim3(grid_for(n)), dim3(256), 0, s, part, nsplit, n, dW);
 }
@@ -902,15 +1027,14 @@ void launch_bn_stats(const float *y, size_t P, int C, double *part, float *mean,
 {
     int nblk = red_blocks(P, C);
     hipLaunchKernelGGL(k_bn_partial, dim3(nblk), dim3(256), 0, s, y, P, C, part, nblk);
-    hipLaunchKernelGGL(k_bn_finish, dim3((C + 63) / 64), dim3(64), 0, s, part, nblk, C, P, mean, rstd,
-                       var_out);
+    hipLaunchKernelGGL(k_bn_finish, dim3(C), dim3(64), 0, s, part, nblk, C, P, mean, rstd, var_out);
 }
 
 void launch_bn_act_fwd(const float *y, size_t P, int C, const float *mean, const float *rstd,
                        const float *g, const float *b, float slope, bf16 *a, hipStream_t s)
 {
     size_t n = P * C;
-    hipLaunchKernelGGL(k_bn_act_fwd, dim3(grid_for(n)), dim3(256), 0, s, y, n, C, mean, rstd, g, b,
+    hipLaunchKernelGGL(k_bn_act_fwd, dim3(grid_for(n / 8)), dim3(256), 0, s, y, n, C, mean, rstd, g, b,
                        slope, a);
 }
 
@@ -923,17 +1047,16 @@ void launch_bn_act_bwd(const float *da, const float *y, size_t P, int C, const f
                        slope, part, nblk);
     // per-channel sums (dbeta, dgamma) go to the tail of `part`
     float *sums = reinterpret_cast<float *>(part + (size_t)nblk * C * 2);
-    hipLaunchKernelGGL(k_bn_bwd_finish, dim3((C + 63) / 64), dim3(64), 0, s, part, nblk, C, dg, db,
-                       sums);
+    hipLaunchKernelGGL(k_bn_bwd_finish, dim3(C), dim3(64), 0, s, part, nblk, C, dg, db, sums);
     size_t n = P * C;
-    hipLaunchKernelGGL(k_bn_bwd_apply, dim3(grid_for(n)), dim3(256), 0, s, da, y, n, C, P, mean, rstd,
+    hipLaunchKernelGGL(k_bn_bwd_apply, dim3(grid_for(n / 8)), dim3(256), 0, s, da, y, n, C, P, mean, rstd,
                        g, b, slope, sums, dy);
 }
 
 void launch_maxpool_fwd(const bf16 *in, int B, int H, int W, int C, bf16 *out, uint8_t *arg,
                         hipStream_t s)
 {
-    size_t n = (size_t)B * (H / 2) * (W / 2) * C;
+    size_t n = (size_t)B * (H / 2) * (W / 2) * (C / 8);
     hipLaunchKernelGGL(k_maxpool_fwd, dim3(grid_for(n)), dim3(256), 0, s, in, B, H, W, C, out, arg);
 }
 
@@ -948,7 +1071,7 @@ void launch_maxpool_bwd(const float *dout, const uint8_t *arg, int B, int H, int
 
 void launch_up2_fwd(const bf16 *in, int B, int h, int w, int C, bf16 *out, hipStream_t s)
 {
-    size_t n = (size_t)B * 4 * h * w * C;
+    size_t n = (size_t)B * 4 * h * w * (C / 8);
     hipLaunchKernelGGL(k_up2_fwd, dim3(grid_for(n)), dim3(256), 0, s, in, B, h, w, C, out);
 }
 
@@ -993,9 +1116,10 @@ void launch_head_fwd(const bf16 *a, size_t P, int C, const float *Wh, const floa
 void launch_head_bwd(const float *dout, const bf16 *a, size_t P, int C, const float *Wh,
                      float *da, double *part, float *dWh, float *dbh, hipStream_t s)
 {
-    int nblk = (int)std::min<size_t>(512, std::max<size_t>(1, (P + 1023) / 1024));
+    hipLaunchKernelGGL(k_head_bwd_da, dim3(grid_for(P * C / 8)), dim3(256), 0, s, dout, (int)P, C, Wh, da);
+    int nblk = red_blocks(P, C);
     hipLaunchKernelGGL(k_head_bwd, dim3(nblk), dim3(256), 0, s, dout, a, P, C, Wh, da, part, nblk);
-    hipLaunchKernelGGL(k_head_bwd_finish, dim3(1), dim3(256), 0, s, part, nblk, C, dWh, dbh);
+    hipLaunchKernelGGL(k_head_bwd_finish, dim3(2 * C + 2), dim3(64), 0, s, part, nblk, C, dWh, dbh);
 }
 
 void launch_net_input(const float2 *r, size_t rstride, int nb, int n, const float *kappa_fine,
