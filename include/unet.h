@@ -20,8 +20,10 @@
  * Parameter order (flat FP32 arrays): for each 3x3 convolution in forward
  * order (enc0a, enc0b, enc1a, ..., dec{L-2}a, dec{L-2}b, ..., dec0a, dec0b):
  * weight [cout][cin][3][3], BN weight [cout], BN bias [cout]; then the head
- * weight [out_ch][w_0] and bias [out_ch].  Buffers: for each convolution the
- * BN running mean [cout] and running variance [cout].
+ * weight [out_ch][w_0] and bias [out_ch] (absent for an encoder).  Buffers:
+ * for each convolution the BN running mean [cout] and running variance [cout].
+ * cin counts the concatenated inputs in order: [input (+ context)] for the
+ * down convolutions, [upsampled, skip (+ context)] for the up convolutions.
  */
 #ifndef UNET_H
 #define UNET_H
@@ -39,8 +41,11 @@ typedef struct {
     int out_ch;     /* output channels: 2 = (Re e, Im e)                       */
     int levels;     /* resolution levels, 1..6                                  */
     int widths[6];  /* channels per level; each a multiple of 32               */
-    int context;    /* 1: solver of an encoder-solver pair (reserved, 0 now)   */
-    int head;       /* 1: 1x1 head (required now)                               */
+    int context;    /* 1: solver of an encoder-solver pair: level l's context
+                       (w_l channels) is the last input of its first down
+                       convolution and of its first up convolution           */
+    int head;       /* 1: 1x1 head; 0: encoder (in_ch 1, context 0) whose
+                       outputs are the per-level contexts                    */
 } unet_cfg;
 
 /* Create a network with zero parameters (set them with unet_set_params). */
@@ -110,6 +115,41 @@ int unet_loss_grad(unet_net *net, const unet_batch *batch, double *loss_out, flo
  */
 int unet_train_step(unet_net *net, const unet_batch *batch, const unet_train_opts *opts,
                     double *loss_out, void *stream);
+
+/*
+ * Encoder-solver pair (section 3.3, eq. 3.5).  The encoder is the same
+ * skeleton without a head, applied to the coarse slowness kappa_c (one input
+ * channel); its output at level l (the up-path output, the bottleneck output
+ * at the last level) is the context f^(l), [nb][nc >> l][nc >> l][w_l].
+ * The solver (context = 1) concatenates f^(l) to the input of its first down
+ * convolution and of its first up convolution at level l.
+ */
+
+/*
+ * unet_pair_encode -- run the encoder (inference BN) on kappa_c, device float
+ * [nb][nc][nc], and store the contexts in the solver (a copy the solver owns:
+ * the encoder may then be reused or destroyed).  With nb = 1 the context is
+ * shared by every sample of later solver calls (one medium, many right-hand
+ * sides: the encoder runs once per medium); with nb > 1, sample b of a
+ * unet_forward batch of size nb uses context b.  helm_fgmres_solve and
+ * unet_infer need the nb = 1 form for the problem's medium (nc = n/2).
+ */
+int unet_pair_encode(unet_net *encoder, unet_net *solver, const float *kappa_c, int nb, int nc,
+                     void *stream);
+
+/*
+ * unet_pair_loss_grad -- the loss of unet_loss_grad with the solver fed
+ * the contexts the encoder computes (training-mode BN in both) from each
+ * sample's batch->kappa_c; gradients of both networks (joint training).
+ * enc_grads / sol_grads: device float arrays of each network's num_params (may
+ * be NULL).  Leaves the solver without a context (encode again before use).
+ */
+int unet_pair_loss_grad(unet_net *encoder, unet_net *solver, const unet_batch *batch,
+                        double *loss_out, float *enc_grads, float *sol_grads, void *stream);
+
+/* unet_pair_loss_grad, then one Adam step of each network (as unet_train_step). */
+int unet_pair_train_step(unet_net *encoder, unet_net *solver, const unet_batch *batch,
+                         const unet_train_opts *opts, double *loss_out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -217,6 +217,17 @@ def update_running_stats(buf, stats, count):
         buf[name + ".rv"].mul_(1 - MOMENTUM).add_(MOMENTUM * unb)
 
 
+def encode(cfg_enc: UNetCfg, p, buf, kappa_c, training=False, stats=None, dtype=torch.float32):
+    """Encoder of an encoder-solver pair (section 3.3, eq. 3.5): the headless
+    network on the coarse slowness [B, n, n] (or [n, n]); returns the
+    per-level contexts f^(l) (the up-path output at level l, the bottleneck
+    output at the last level)."""
+    k = torch.as_tensor(np.asarray(kappa_c), dtype=dtype)
+    if k.dim() == 2:
+        k = k[None]
+    return forward(cfg_enc, p, buf, k[:, None], training=training, stats=stats)
+
+
 # ----------------------------------------------------------------- wrapper
 
 def _restrict_c(x):
@@ -336,3 +347,13 @@ def training_triple(hier, x):
     w = helm_oracle.apply(kap, gam, om, z)
     alpha = np.vdot(w, b) / np.vdot(w, w)
     return b - alpha * w, x - alpha * z
+
+
+def pair_training_loss(cfg_enc, pe, bufe, cfg_sol, ps, bufs, r_batch, e_batch, kappa_c_batch,
+                       stats_e=None, stats_s=None, dtype=torch.float32):
+    """Joint loss of an encoder-solver pair: the solver's training loss with
+    each sample's contexts computed by the encoder from its own medium (both
+    networks with training-mode BN; trained together as in section 4.3.2)."""
+    ctx = encode(cfg_enc, pe, bufe, kappa_c_batch, training=True, stats=stats_e, dtype=dtype)
+    return training_loss(cfg_sol, ps, bufs, r_batch, e_batch, kappa_c_batch, ctx=ctx, stats=stats_s,
+                         dtype=dtype)

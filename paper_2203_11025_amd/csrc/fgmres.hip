@@ -384,6 +384,12 @@ extern "C" int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int
         set_error("helm_fgmres_solve: the network preconditioners need opts->net");
         return HELM_E_INVALID;
     }
+    if (net && (!net->cfg.head || (net->cfg.context && (nprob != 1 || !net->ctx_valid || !net->ctx_shared)))) {
+        // a solver's context belongs to one medium: encode it first
+        set_error("helm_fgmres_solve: a network with a head is needed; an encoder-solver's solver takes "
+                  "one problem whose medium was encoded with unet_pair_encode (nb = 1)");
+        return HELM_E_INVALID;
+    }
     int status = HELM_OK, off = 0;
     for (int p = 0; p < nprob; ++p) {
         if (!probs[p] || rhs_per_prob[p] < 0 || (rhs_per_prob[p] > 0 && (!b[p] || !x[p]))) {
@@ -391,7 +397,7 @@ extern "C" int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int
             return HELM_E_INVALID;
         }
         if (rhs_per_prob[p] == 0) continue;
-        if (net && (probs[p]->n % (2 << (net->cfg.levels - 1)) || probs[p]->n % (1 << net->cfg.levels))) {
+        if (net && (probs[p]->n % (1 << net->cfg.levels) || (net->cfg.context && net->ctx_H != probs[p]->n / 2))) {
             set_error("helm_fgmres_solve: grid size not divisible by 2^levels of the network");
             return HELM_E_SHAPE;
         }

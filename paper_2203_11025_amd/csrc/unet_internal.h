@@ -12,10 +12,13 @@ namespace helm {
 
 using bf16 = __bf16;
 
-// One input source of a convolution: NHWC bf16, channel count a multiple of 32.
+// One input source of a convolution: NHWC bf16, channel count a multiple of
+// 32; `shared` = 1 when every batch entry reads batch entry 0 (a context
+// tensor computed once per medium).
 struct Src {
     const bf16 *p;
     int C;
+    int shared;
 };
 // Up to three sources concatenated along channels (by addressing only).
 struct Srcs {
@@ -54,7 +57,8 @@ void launch_bn_act_bwd(const float *da, const float *y, size_t P, int C, const f
 
 void launch_maxpool_fwd(const bf16 *in, int B, int H, int W, int C, bf16 *out, uint8_t *arg,
                         hipStream_t s);
-// din[argmax position] += dout (din FP32 [B][H][W][C], dout [B][H/2][W/2][C])
+// din[argmax position] += dout (din FP32 [B][H][W][din_C], dout channels
+// [coff_in, coff_in + C) of a [B][H/2][W/2][cstride_in] tensor)
 void launch_maxpool_bwd(const float *dout, const uint8_t *arg, int B, int H, int W, int C,
                         int cstride_in, int coff_in, float *din, int din_C, hipStream_t s);
 // bilinear x2 upsampling (half-pixel centres, edge clamped)

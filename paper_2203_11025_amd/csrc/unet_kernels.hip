@@ -84,13 +84,14 @@ __global__ __launch_bounds__(256) void k_conv3x3(Srcs in, int H, int W,
         }
         const bf16 *src = in.s[s].p;
         const int Cs = in.s[s].C;
+        const int bsrc = in.s[s].shared ? 0 : b;
         for (int idx = tid; idx < HY * HX * 4; idx += 256) {
             int seg = idx & 3, pix = idx >> 2;
             int ty = pix / HX, tx = pix - ty * HX;
             int y = y0 + ty - 1, x = x0 + tx - 1;
             uint4 v = {0u, 0u, 0u, 0u};
             if (y >= 0 && y < H && x >= 0 && x < W)
-                v = *reinterpret_cast<const uint4 *>(src + (((size_t)b * H + y) * W + x) * Cs +
+                v = *reinterpret_cast<const uint4 *>(src + (((size_t)bsrc * H + y) * W + x) * Cs +
                                                      coff + seg * 8);
             *reinterpret_cast<uint4 *>(&sx[pix * PS + seg * 8]) = v;
         }
@@ -210,7 +211,8 @@ __global__ __launch_bounds__(256) void k_wgrad(Srcs x, const bf16 *__restrict__ 
                     coff -= x.s[s].C;
                     ++s;
                 }
-                vb = *reinterpret_cast<const uint4 *>(x.s[s].p + (((size_t)b * H + ys) * W + xs) * x.s[s].C +
+                const int bsrc = x.s[s].shared ? 0 : b;
+                vb = *reinterpret_cast<const uint4 *>(x.s[s].p + (((size_t)bsrc * H + ys) * W + xs) * x.s[s].C +
                                                       coff);
             }
             const bf16 *eb = reinterpret_cast<const bf16 *>(&vb);
@@ -457,9 +459,9 @@ __global__ void k_maxpool_fwd(const bf16 *__restrict__ in, int B, int H, int W, 
     }
 }
 
-__global__ void k_maxpool_bwd(const float *__restrict__ dout, const uint8_t *__restrict__ arg,
-                              int B, int H, int W, int C, float *__restrict__ din, int din_C,
-                              int coff)
+__global__ void k_maxpool_bwd(const float *__restrict__ dout, int cstride, int coff,
+                              const uint8_t *__restrict__ arg, int B, int H, int W, int C,
+                              float *__restrict__ din, int din_C)
 {
     const int Ho = H / 2, Wo = W / 2;
     const int n = B * Ho * Wo * C;
@@ -469,7 +471,7 @@ __global__ void k_maxpool_bwd(const float *__restrict__ dout, const uint8_t *__r
         int yo = r % Ho, b = r / Ho;
         int k = arg[i];
         int yy = 2 * yo + (k >> 1), xx = 2 * xo + (k & 1);
-        din[(((size_t)b * H + yy) * W + xx) * din_C + coff + c] += dout[i];
+        din[(((size_t)b * H + yy) * W + xx) * din_C + c] += dout[(size_t)pix * cstride + coff + c];
     }
 }
 
@@ -1063,10 +1065,9 @@ void launch_maxpool_fwd(const bf16 *in, int B, int H, int W, int C, bf16 *out, u
 void launch_maxpool_bwd(const float *dout, const uint8_t *arg, int B, int H, int W, int C,
                         int cstride_in, int coff_in, float *din, int din_C, hipStream_t s)
 {
-    (void)cstride_in;
     size_t n = (size_t)B * (H / 2) * (W / 2) * C;
-    hipLaunchKernelGGL(k_maxpool_bwd, dim3(grid_for(n)), dim3(256), 0, s, dout, arg, B, H, W, C, din,
-                       din_C, coff_in);
+    hipLaunchKernelGGL(k_maxpool_bwd, dim3(grid_for(n)), dim3(256), 0, s, dout, cstride_in, coff_in, arg,
+                       B, H, W, C, din, din_C);
 }
 
 void launch_up2_fwd(const bf16 *in, int B, int h, int w, int C, bf16 *out, hipStream_t s)

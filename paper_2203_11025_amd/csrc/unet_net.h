@@ -44,6 +44,15 @@ struct unet_net {
     float *xin = nullptr;
     double *red = nullptr, *s = nullptr, *dloss = nullptr;
     float2 *rcoarse = nullptr, *dfine = nullptr;
+    // encoder-solver: context tensors per level (solver), their gradients
+    // (solver-owned copies of the encoder outputs), their gradients
+    std::vector<const helm::bf16 *> ctxp;
+    std::vector<helm::bf16 *> ctxbuf;
+    int ctx_shared = 0, ctx_B = 0, ctx_H = 0, ctx_valid = 0;
+    std::vector<float *> gctx;
+    int attach_context(const unet_net &enc, int nb, int H, int W, hipStream_t st);
+    void clear_context();
+    void adam_update(const unet_train_opts &o, double count, hipStream_t st);
 
     ~unet_net();
     int init(const unet_cfg &c);
@@ -54,7 +63,10 @@ struct unet_net {
     helm::Srcs layer_srcs(int i) const;
     void run_layer(int i, const helm::Srcs &src, int B, int H, int W, bool training, hipStream_t st);
     void forward_from_x0(int B, int H, int W, bool training, hipStream_t st);
-    void backward(int B, int H, int W, hipStream_t st);
+    void backward(int B, int H, int W, hipStream_t st);  // zero, head, layers
+    void zero_act_grads(int B, int H, int W, hipStream_t st);
+    void layers_backward(int B, int H, int W, hipStream_t st);
+    int output_layer(int level) const;  // layer whose activation is level's output
     void repack(hipStream_t st);
     void refold(hipStream_t st);
     int pack_nchw_input(const float *x, int B, int H, int W, hipStream_t st);

@@ -50,6 +50,8 @@ void unet_net::free_ws()
     for (auto p : pooled) hipFree(p);
     for (auto p : arg) hipFree(p);
     for (auto p : up) hipFree(p);
+    for (auto p : gctx) hipFree(p);
+    gctx.clear();
     pooled.clear();
     arg.clear();
     up.clear();
@@ -80,6 +82,7 @@ void unet_net::free_ws()
 unet_net::~unet_net()
 {
     free_ws();
+    for (auto p : ctxbuf) hipFree(p);
     for (auto &l : L) {
         hipFree(l.Wp);
         hipFree(l.Wd);
@@ -118,17 +121,24 @@ int unet_net::init(const unet_cfg &c)
         L.push_back(l);
     };
     const int *w = cfg.widths;
+    // with an encoder context, level l's context (w_l channels) is the last
+    // source of enc{l}a and dec{l}a (eq. 3.5)
+    auto cx = [&](std::vector<int> v, int l) {
+        if (cfg.context) v.push_back(w[l]);
+        return v;
+    };
     for (int l = 0; l < Lv; ++l) {
         if (l == 0)
-            add("enc0a", 0, {cfg.in_ch}, {pad32(cfg.in_ch)}, w[0]);
+            add("enc0a", 0, cx({cfg.in_ch}, 0), cx({pad32(cfg.in_ch)}, 0), w[0]);
         else
-            add("enc" + std::to_string(l) + "a", l, {w[l - 1]}, {w[l - 1]}, w[l]);
+            add("enc" + std::to_string(l) + "a", l, cx({w[l - 1]}, l), cx({w[l - 1]}, l), w[l]);
         add("enc" + std::to_string(l) + "b", l, {w[l]}, {w[l]}, w[l]);
     }
     for (int l = Lv - 2; l >= 0; --l) {
-        add("dec" + std::to_string(l) + "a", l, {w[l + 1], w[l]}, {w[l + 1], w[l]}, w[l]);
+        add("dec" + std::to_string(l) + "a", l, cx({w[l + 1], w[l]}, l), cx({w[l + 1], w[l]}, l), w[l]);
         add("dec" + std::to_string(l) + "b", l, {w[l]}, {w[l]}, w[l]);
     }
+    ctxp.assign(Lv, nullptr);
     // flat offsets
     size_t off = 0, boff = 0;
     int rc;
@@ -161,9 +171,9 @@ int unet_net::init(const unet_cfg &c)
         }
     }
     head_w = off;
-    off += (size_t)cfg.out_ch * w[0];
+    if (cfg.head) off += (size_t)cfg.out_ch * w[0];
     head_b = off;
-    off += cfg.out_ch;
+    if (cfg.head) off += cfg.out_ch;
     nparams = off;
     nbuf = boff;
     size_t nsc = 0;
@@ -216,6 +226,11 @@ int unet_net::ensure_ws(int B, int H, int W, bool training)
         size_t Pl = (size_t)nB * (H >> l) * (W >> l);
         if ((rc = dalloc(&up[l], Pl * cfg.widths[l + 1]))) return rc;
     }
+    if (cfg.context && tr) {
+        gctx.assign(Lv, nullptr);
+        for (int l = 0; l < Lv; ++l)
+            if ((rc = dalloc(&gctx[l], (size_t)nB * (H >> l) * (W >> l) * cfg.widths[l]))) return rc;
+    }
     size_t P0 = (size_t)nB * H * W;
     if ((rc = dalloc(&x0, P0 * pad32(cfg.in_ch))) || (rc = dalloc(&out, P0 * cfg.out_ch)) ||
         (rc = dalloc(&xin, P0 * cfg.out_ch)))
@@ -262,19 +277,25 @@ Srcs unet_net::layer_srcs(int i) const
     const std::string &nm = l.name;
     int lev = l.level;
     if (nm == "enc0a") {
-        s.s[0] = {x0, l.src_pad[0]};
+        s.s[0] = {x0, l.src_pad[0], 0};
     } else if (nm[0] == 'e' && nm.back() == 'a') {
-        s.s[0] = {pooled[lev], l.src_pad[0]};
+        s.s[0] = {pooled[lev], l.src_pad[0], 0};
     } else if (nm.back() == 'b') {
-        s.s[0] = {act[i - 1].a, l.src_pad[0]};
+        s.s[0] = {act[i - 1].a, l.src_pad[0], 0};
     } else {  // decoder 'a': [upsampled, skip]
-        s.s[0] = {up[lev], l.src_pad[0]};
-        s.s[1] = {act[enc_index(lev, 'b')].a, l.src_pad[1]};
+        s.s[0] = {up[lev], l.src_pad[0], 0};
+        s.s[1] = {act[enc_index(lev, 'b')].a, l.src_pad[1], 0};
     }
+    if (cfg.context && nm.back() == 'a') s.s[l.nsrc - 1] = {ctxp[lev], l.src_pad[l.nsrc - 1], ctx_shared};
     return s;
 }
 
 int unet_net::enc_index(int level, char ab) const { return 2 * level + (ab == 'b' ? 1 : 0); }
+
+int unet_net::output_layer(int level) const
+{
+    return level == cfg.levels - 1 ? enc_index(level, 'b') : dec_index(level, 'b');
+}
 
 int unet_net::dec_index(int level, char ab) const
 {
@@ -300,21 +321,35 @@ void unet_net::forward_from_x0(int B, int H, int W, bool training, hipStream_t s
         run_layer(dec_index(l, 'a'), layer_srcs(dec_index(l, 'a')), B, Hl, Wl, training, st);
         run_layer(dec_index(l, 'b'), layer_srcs(dec_index(l, 'b')), B, Hl, Wl, training, st);
     }
+    if (!cfg.head) return;
     int last = Lv >= 2 ? dec_index(0, 'b') : enc_index(0, 'b');
     launch_head_fwd(act[last].a, (size_t)B * H * W, cfg.widths[0], P + head_w, P + head_b, out, st);
+}
+
+void unet_net::zero_act_grads(int B, int H, int W, hipStream_t st)
+{
+    for (size_t i = 0; i < L.size(); ++i) {
+        size_t Pl = (size_t)B * (H >> L[i].level) * (W >> L[i].level);
+        hipMemsetAsync(act[i].g, 0, Pl * L[i].cout * sizeof(float), st);
+    }
+    if (cfg.context)
+        for (int l = 0; l < cfg.levels; ++l)
+            hipMemsetAsync(gctx[l], 0, (size_t)B * (H >> l) * (W >> l) * cfg.widths[l] * sizeof(float), st);
 }
 
 void unet_net::backward(int B, int H, int W, hipStream_t st)
 {
     const int Lv = cfg.levels;
-    const size_t P0 = (size_t)B * H * W;
-    for (size_t i = 0; i < L.size(); ++i) {
-        size_t Pl = (size_t)B * (H >> L[i].level) * (W >> L[i].level);
-        hipMemsetAsync(act[i].g, 0, Pl * L[i].cout * sizeof(float), st);
-    }
+    zero_act_grads(B, H, W, st);
     int last = Lv >= 2 ? dec_index(0, 'b') : enc_index(0, 'b');
-    launch_head_bwd(gout, act[last].a, P0, cfg.widths[0], P + head_w, act[last].g, red, G + head_w,
-                    G + head_b, st);
+    launch_head_bwd(gout, act[last].a, (size_t)B * H * W, cfg.widths[0], P + head_w, act[last].g, red,
+                    G + head_w, G + head_b, st);
+    layers_backward(B, H, W, st);
+}
+
+void unet_net::layers_backward(int B, int H, int W, hipStream_t st)
+{
+    const int Lv = cfg.levels;
     for (int i = (int)L.size() - 1; i >= 0; --i) {
         Layer &l = L[i];
         Act &a = act[i];
@@ -325,30 +360,87 @@ void unet_net::backward(int B, int H, int W, hipStream_t st)
         Srcs src = layer_srcs(i);
         launch_wgrad(src, dy, B, Hl, Wl, l.cout, dW, wpart, st);
         launch_unpack_wgrad(dW, l.cout, l.cin_real, l.map, l.cin_pad, G + l.w_off, st);
-        if (i == 0) continue;  // no gradient w.r.t. the network input
+        const bool has_ctx = cfg.context && l.name.back() == 'a';
+        if (i == 0 && !has_ctx) continue;  // no gradient w.r.t. the network input
         // data gradient: a 3x3 convolution of dy with the flipped, transposed weights
         Srcs ds{};
         ds.n = 1;
         ds.Ctot = l.cout;
-        ds.s[0] = {dy, l.cout};
+        ds.s[0] = {dy, l.cout, 0};
         launch_conv3x3(ds, B, Hl, Wl, l.Wd, l.cin_pad, 0, dX, nullptr, nullptr, nullptr, SLOPE, st);
         const std::string &nm = l.name;
+        const int lev = l.level;
+        if (has_ctx)  // the context is the last source
+            launch_slice_add(dX, l.cin_pad, l.cin_pad - cfg.widths[lev], Pl, cfg.widths[lev], gctx[lev], 1,
+                             st);
+        if (i == 0) continue;
         if (nm.back() == 'b') {
             launch_slice_add(dX, l.cin_pad, 0, Pl, l.cout, act[i - 1].g, 1, st);
         } else if (nm[0] == 'e') {
             // enc{lev}a, lev >= 1: through the max pooling into enc{lev-1}b
-            int src_layer = enc_index(l.level - 1, 'b');
-            launch_maxpool_bwd(dX, arg[l.level], B, Hl * 2, Wl * 2, cfg.widths[l.level - 1], l.cin_pad, 0,
-                               act[src_layer].g, cfg.widths[l.level - 1], st);
+            int src_layer = enc_index(lev - 1, 'b');
+            launch_maxpool_bwd(dX, arg[lev], B, Hl * 2, Wl * 2, cfg.widths[lev - 1], l.cin_pad, 0,
+                               act[src_layer].g, cfg.widths[lev - 1], st);
         } else {
-            // dec{lev}a: [upsampled, skip]
-            int lev = l.level;
+            // dec{lev}a: [upsampled, skip (, context)]
             int prev = (lev == Lv - 2) ? enc_index(Lv - 1, 'b') : dec_index(lev + 1, 'b');
             launch_up2_bwd(dX, l.cin_pad, 0, B, Hl / 2, Wl / 2, cfg.widths[lev + 1], act[prev].g, 1, st);
             launch_slice_add(dX, l.cin_pad, cfg.widths[lev + 1], Pl, cfg.widths[lev],
                              act[enc_index(lev, 'b')].g, 1, st);
         }
     }
+}
+
+// Copies the encoder's per-level outputs f^(l) (eq. 3.5) into storage the
+// solver owns, so the encoder may be run again or destroyed afterwards.
+int unet_net::attach_context(const unet_net &enc, int nb, int H, int W, hipStream_t st)
+{
+    const int Lv = cfg.levels;
+    if (ctxbuf.empty() || ctx_B != nb || ctx_H != H) {
+        for (auto p : ctxbuf) hipFree(p);
+        ctxbuf.assign(Lv, nullptr);
+        ctx_valid = 0;
+        for (int l = 0; l < Lv; ++l)
+            if (hipMalloc(&ctxbuf[l], (size_t)nb * (H >> l) * (W >> l) * cfg.widths[l] * sizeof(bf16)) !=
+                hipSuccess) {
+                set_error("unet_pair_encode: out of device memory for the context");
+                return HELM_E_NOMEM;
+            }
+    }
+    for (int l = 0; l < Lv; ++l) {
+        size_t bytes = (size_t)nb * (H >> l) * (W >> l) * cfg.widths[l] * sizeof(bf16);
+        if (hipMemcpyAsync(ctxbuf[l], enc.act[enc.output_layer(l)].a, bytes, hipMemcpyDeviceToDevice, st) !=
+            hipSuccess) {
+            set_error("unet_pair_encode: context copy failed");
+            return HELM_E_HIP;
+        }
+        ctxp[l] = ctxbuf[l];
+    }
+    ctx_B = nb;
+    ctx_H = H;
+    ctx_shared = nb == 1;
+    ctx_valid = 1;
+    return HELM_OK;
+}
+
+void unet_net::clear_context()
+{
+    ctx_valid = 0;
+    for (auto &p : ctxp) p = nullptr;
+}
+
+// Adam on the FP32 masters, BN running statistics, bf16 repack; count is the
+// number of level-0 pixels in the batch.
+void unet_net::adam_update(const unet_train_opts &o, double count, hipStream_t st)
+{
+    step += 1;
+    launch_adam(P, G, M, V, nparams, o.lr, o.beta1, o.beta2, o.eps, step, st);
+    for (auto &l : L) {
+        // statistics of each layer at its own resolution
+        double cnt = count / (double)(1u << (2 * l.level));
+        launch_bn_running(BUF + l.rm_off, BUF + l.rv_off, l.mean, l.var, l.cout, BN_MOM, cnt, st);
+    }
+    repack(st);
 }
 
 void unet_net::repack(hipStream_t st)
@@ -412,9 +504,10 @@ int unet_create(const unet_cfg *cfg, unet_net **out)
         return HELM_E_INVALID;
     }
     *out = nullptr;
-    if (cfg->levels < 1 || cfg->levels > 6 || cfg->in_ch < 1 || cfg->in_ch > 32 || cfg->out_ch != 2 ||
-        !cfg->head || cfg->context) {
-        set_error("unet_create: unsupported configuration (levels 1..6, in_ch 1..32, out_ch 2, head 1, context 0)");
+    if (cfg->levels < 1 || cfg->levels > 6 || cfg->in_ch < 1 || cfg->in_ch > 32 ||
+        (cfg->head && cfg->out_ch != 2) || (!cfg->head && cfg->context)) {
+        set_error("unet_create: unsupported configuration (levels 1..6, in_ch 1..32, out_ch 2 with a "
+                  "head; an encoder (head 0) takes no context)");
         return HELM_E_INVALID;
     }
     for (int l = 0; l < cfg->levels; ++l)
@@ -489,6 +582,14 @@ int unet_forward(unet_net *net, const float *x, int B, int H, int W, float *out,
         return HELM_E_SHAPE;
     }
     hipStream_t st = (hipStream_t)stream;
+    if (!net->cfg.head) {
+        set_error("unet_forward: an encoder has no head output (use unet_pair_encode)");
+        return HELM_E_INVALID;
+    }
+    if (net->cfg.context && (!net->ctx_valid || net->ctx_H != H || (!net->ctx_shared && net->ctx_B != B))) {
+        set_error("unet_forward: attach a matching encoder context first (unet_pair_encode)");
+        return HELM_E_INVALID;
+    }
     int rc = net->ensure_ws(B, H, W, training != 0);
     if (rc) return rc;
     rc = net->pack_nchw_input(x, B, H, W, st);
@@ -512,6 +613,11 @@ int unet_infer(unet_net *net, helm_handle *h, const float *r, float *e, int nrhs
         set_error("unet_infer: n must be divisible by 2^levels");
         return HELM_E_SHAPE;
     }
+    if (!net->cfg.head || (net->cfg.context && (!net->ctx_valid || !net->ctx_shared || net->ctx_H != h->n / 2))) {
+        set_error("unet_infer: needs a network with a head and, for a solver, the medium's context "
+                  "(unet_pair_encode with nb = 1)");
+        return HELM_E_INVALID;
+    }
     size_t N = (size_t)h->n * h->n;
     int rc = net->wrap_apply(h, (const float2 *)r, N, (float2 *)e, N, nrhs, 0, (hipStream_t)stream);
     if (rc) return rc;
@@ -524,6 +630,10 @@ int unet_loss_grad(unet_net *net, const unet_batch *batch, double *loss_out, flo
 {
     if (!net || !batch || !batch->r || !batch->e || !batch->kappa_c || batch->nb < 1) {
         set_error("unet_loss_grad: invalid argument");
+        return HELM_E_INVALID;
+    }
+    if (!net->cfg.head || net->cfg.context) {
+        set_error("unet_loss_grad: encoder-solver pairs train through unet_pair_loss_grad");
         return HELM_E_INVALID;
     }
     const int div = 1 << net->cfg.levels;
@@ -551,18 +661,102 @@ int unet_train_step(unet_net *net, const unet_batch *batch, const unet_train_opt
     hipStream_t st = (hipStream_t)stream;
     int rc = unet_loss_grad(net, batch, nullptr, nullptr, stream);
     if (rc) return rc;
-    net->step += 1;
-    launch_adam(net->P, net->G, net->M, net->V, net->nparams, o.lr, o.beta1, o.beta2, o.eps, net->step, st);
-    const double count = (double)batch->nb * (batch->n / 2) * (batch->n / 2);
-    for (size_t i = 0; i < net->L.size(); ++i) {
-        auto &l = net->L[i];
-        // statistics of each layer at its own resolution
-        double cnt = count / (double)(1u << (2 * l.level));
-        launch_bn_running(net->BUF + l.rm_off, net->BUF + l.rv_off, l.mean, l.var, l.cout, BN_MOM, cnt, st);
-    }
-    net->repack(st);
+    net->adam_update(o, (double)batch->nb * (batch->n / 2) * (batch->n / 2), st);
     if (loss_out) {
         HELM_HIP_CHECK(hipMemcpyAsync(loss_out, net->dloss, sizeof(double), hipMemcpyDeviceToHost, st));
+        HELM_HIP_CHECK(hipStreamSynchronize(st));
+    }
+    HELM_HIP_CHECK(hipGetLastError());
+    return HELM_OK;
+}
+
+static int check_pair(const unet_net *enc, const unet_net *sol, const char *who)
+{
+    if (!enc || !sol || enc->cfg.head || enc->cfg.in_ch != 1 || !sol->cfg.context || !sol->cfg.head ||
+        enc->cfg.levels != sol->cfg.levels) {
+        set_error(std::string(who) + ": needs an encoder (head 0, in_ch 1) and a solver (context 1) "
+                                     "with the same levels");
+        return HELM_E_INVALID;
+    }
+    for (int l = 0; l < enc->cfg.levels; ++l)
+        if (enc->cfg.widths[l] != sol->cfg.widths[l]) {
+            set_error(std::string(who) + ": encoder and solver widths differ");
+            return HELM_E_INVALID;
+        }
+    return HELM_OK;
+}
+
+int unet_pair_encode(unet_net *enc, unet_net *sol, const float *kappa_c, int nb, int nc, void *stream)
+{
+    int rc = check_pair(enc, sol, "unet_pair_encode");
+    if (rc) return rc;
+    if (!kappa_c || nb < 1 || nc < 1 || nc % (1 << (enc->cfg.levels - 1))) {
+        set_error("unet_pair_encode: invalid kappa_c, nb or nc (nc divisible by 2^(levels-1))");
+        return HELM_E_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = enc->ensure_ws(nb, nc, nc, false))) return rc;
+    enc->pack_nchw_input(kappa_c, nb, nc, nc, st);
+    enc->forward_from_x0(nb, nc, nc, false, st);
+    if ((rc = sol->attach_context(*enc, nb, nc, nc, st))) return rc;
+    HELM_HIP_CHECK(hipGetLastError());
+    return HELM_OK;
+}
+
+int unet_pair_loss_grad(unet_net *enc, unet_net *sol, const unet_batch *batch, double *loss_out,
+                        float *enc_grads, float *sol_grads, void *stream)
+{
+    int rc = check_pair(enc, sol, "unet_pair_loss_grad");
+    if (rc) return rc;
+    if (!batch || !batch->r || !batch->e || !batch->kappa_c || batch->nb < 1 ||
+        batch->n % (1 << sol->cfg.levels)) {
+        set_error("unet_pair_loss_grad: invalid batch (n divisible by 2^levels)");
+        return HELM_E_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int nb = batch->nb, nc = batch->n / 2;
+    // encoder in training mode on each sample's medium; per-sample contexts
+    if ((rc = enc->ensure_ws(nb, nc, nc, true))) return rc;
+    enc->pack_nchw_input(batch->kappa_c, nb, nc, nc, st);
+    enc->forward_from_x0(nb, nc, nc, true, st);
+    if ((rc = sol->attach_context(*enc, nb, nc, nc, st))) return rc;
+    sol->ctx_shared = 0;
+    rc = sol->loss_grad(*batch, st);
+    if (rc) return rc;
+    // the gradient reaching each context flows back through the encoder
+    HELM_HIP_CHECK(hipMemsetAsync(enc->G, 0, enc->nparams * sizeof(float), st));
+    enc->zero_act_grads(nb, nc, nc, st);
+    for (int l = 0; l < enc->cfg.levels; ++l)
+        launch_slice_add(sol->gctx[l], enc->cfg.widths[l], 0, (size_t)nb * (nc >> l) * (nc >> l),
+                         enc->cfg.widths[l], enc->act[enc->output_layer(l)].g, 1, st);
+    enc->layers_backward(nb, nc, nc, st);
+    // the training-mode context is not the medium's inference context
+    sol->clear_context();
+    if (enc_grads)
+        HELM_HIP_CHECK(hipMemcpyAsync(enc_grads, enc->G, enc->nparams * 4, hipMemcpyDeviceToDevice, st));
+    if (sol_grads)
+        HELM_HIP_CHECK(hipMemcpyAsync(sol_grads, sol->G, sol->nparams * 4, hipMemcpyDeviceToDevice, st));
+    if (loss_out) {
+        HELM_HIP_CHECK(hipMemcpyAsync(loss_out, sol->dloss, sizeof(double), hipMemcpyDeviceToHost, st));
+        HELM_HIP_CHECK(hipStreamSynchronize(st));
+    }
+    HELM_HIP_CHECK(hipGetLastError());
+    return HELM_OK;
+}
+
+int unet_pair_train_step(unet_net *enc, unet_net *sol, const unet_batch *batch,
+                         const unet_train_opts *opts, double *loss_out, void *stream)
+{
+    unet_train_opts o{1e-3f, 0.9f, 0.999f, 1e-8f};
+    if (opts) o = *opts;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = unet_pair_loss_grad(enc, sol, batch, nullptr, nullptr, nullptr, stream);
+    if (rc) return rc;
+    const double count = (double)batch->nb * (batch->n / 2) * (batch->n / 2);
+    sol->adam_update(o, count, st);
+    enc->adam_update(o, count, st);
+    if (loss_out) {
+        HELM_HIP_CHECK(hipMemcpyAsync(loss_out, sol->dloss, sizeof(double), hipMemcpyDeviceToHost, st));
         HELM_HIP_CHECK(hipStreamSynchronize(st));
     }
     HELM_HIP_CHECK(hipGetLastError());

@@ -10,7 +10,8 @@ from .helm import HelmError, _check, _dev, _stream, lib as _helm_lib
 
 EXPORTS = ["unet_create", "unet_destroy", "unet_num_params", "unet_num_buffers",
            "unet_set_params", "unet_get_params", "unet_forward", "unet_infer",
-           "unet_loss_grad", "unet_train_step"]
+           "unet_loss_grad", "unet_train_step", "unet_pair_encode", "unet_pair_loss_grad",
+           "unet_pair_train_step"]
 
 
 class Cfg(C.Structure):
@@ -57,19 +58,32 @@ def lib():
         L.unet_train_step.argtypes = [vp, C.POINTER(Batch), C.POINTER(TrainOpts),
                                       C.POINTER(C.c_double), vp]
         L.unet_train_step.restype = ip
+        L.unet_pair_encode.argtypes = [vp, vp, vp, ip, ip, vp]
+        L.unet_pair_encode.restype = ip
+        L.unet_pair_loss_grad.argtypes = [vp, vp, C.POINTER(Batch), C.POINTER(C.c_double), vp, vp, vp]
+        L.unet_pair_loss_grad.restype = ip
+        L.unet_pair_train_step.argtypes = [vp, vp, C.POINTER(Batch), C.POINTER(TrainOpts),
+                                           C.POINTER(C.c_double), vp]
+        L.unet_pair_train_step.restype = ip
         _done = True
     return L
 
 
 class UNet:
-    def __init__(self, widths=(32, 64, 128, 256), in_ch=3, out_ch=2):
+    """context=True: the solver of an encoder-solver pair; head=False: an
+    encoder (in_ch 1), whose per-level outputs are the solver's contexts."""
+
+    def __init__(self, widths=(32, 64, 128, 256), in_ch=3, out_ch=2, context=False, head=True):
+        if not head:
+            in_ch = 1
         cfg = Cfg(in_ch, out_ch, len(widths), (C.c_int * 6)(*list(widths) + [0] * (6 - len(widths))),
-                  0, 1)
+                  int(context), int(head))
         h = C.c_void_p()
         _check(lib().unet_create(C.byref(cfg), C.byref(h)), "unet_create")
         self._h = h
         self.widths = tuple(widths)
         self.in_ch, self.out_ch = in_ch, out_ch
+        self.context, self.head = bool(context), bool(head)
         self.nparams = lib().unet_num_params(h)
         self.nbuf = lib().unet_num_buffers(h)
 
@@ -149,3 +163,34 @@ class UNet:
         _check(lib().unet_train_step(self._h, C.byref(bt), C.byref(o), C.byref(loss),
                                      _stream(stream)), "unet_train_step")
         return loss.value
+
+
+def pair_encode(encoder, solver, kappa_c, stream=None):
+    """Run the encoder on kappa_c ([nc, nc] for one medium, or [nb, nc, nc])
+    and store the per-level contexts in the solver."""
+    k = kappa_c.to(device="cuda", dtype=torch.float32).contiguous()
+    if k.dim() == 2:
+        k = k[None]
+    _check(lib().unet_pair_encode(encoder.ptr, solver.ptr, _dev(k, torch.float32, "kappa_c"),
+                                  k.shape[0], k.shape[-1], _stream(stream)), "unet_pair_encode")
+
+
+def pair_loss_grad(encoder, solver, r, e, kappa_c, stream=None):
+    bt = UNet._batch(r, e, kappa_c)
+    ge = torch.empty(encoder.nparams, dtype=torch.float32, device="cuda")
+    gs = torch.empty(solver.nparams, dtype=torch.float32, device="cuda")
+    loss = C.c_double()
+    _check(lib().unet_pair_loss_grad(encoder.ptr, solver.ptr, C.byref(bt), C.byref(loss),
+                                     _dev(ge, torch.float32, "ge"), _dev(gs, torch.float32, "gs"),
+                                     _stream(stream)), "unet_pair_loss_grad")
+    return loss.value, ge, gs
+
+
+def pair_train_step(encoder, solver, r, e, kappa_c, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                    stream=None):
+    bt = UNet._batch(r, e, kappa_c)
+    o = TrainOpts(lr, beta1, beta2, eps)
+    loss = C.c_double()
+    _check(lib().unet_pair_train_step(encoder.ptr, solver.ptr, C.byref(bt), C.byref(o), C.byref(loss),
+                                      _stream(stream)), "unet_pair_train_step")
+    return loss.value

@@ -1,0 +1,184 @@
+"""GPU parity of the encoder-solver pair (section 3.3, eq. 3.5) against the
+CPU oracle, through the C ABI: contexts, solver output, joint gradients, the
+pair inside FGMRES, and the error paths of a pair used the wrong way."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import unet_oracle as U
+from paper_2203_11025_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = (32, 64, 128)
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_2203_11025_amd import unet
+
+    assert torch.cuda.is_available()
+    unet.lib()
+    return unet
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def make_pair(N, seed, widths=WIDTHS, perturb=True):
+    ce = U.UNetCfg(in_ch=1, widths=widths, head=False)
+    cs = U.UNetCfg(in_ch=3, widths=widths, context=True)
+    pe, be = U.init_params(ce, seed)
+    ps, bs = U.init_params(cs, seed + 1)
+    rng = np.random.default_rng(seed + 2)
+    if perturb:
+        for p, b in ((pe, be), (ps, bs)):
+            for k in p:
+                if k.endswith(".g"):
+                    p[k] = torch.tensor(rng.uniform(0.5, 1.5, p[k].shape), dtype=torch.float32)
+                elif k.endswith(".b"):
+                    p[k] = torch.tensor(rng.normal(0, 0.1, p[k].shape), dtype=torch.float32)
+            for k in b:
+                b[k] = torch.tensor(rng.uniform(-0.2, 0.2, b[k].shape) if k.endswith(".rm")
+                                    else rng.uniform(0.5, 2.0, b[k].shape), dtype=torch.float32)
+    enc = N.UNet(widths=widths, head=False)
+    sol = N.UNet(widths=widths, context=True)
+    for net, cfg, p, b in ((enc, ce, pe, be), (sol, cs, ps, bs)):
+        net.set_params(U.flatten(cfg, p), torch.cat([b[k].reshape(-1) for k in U.buffer_shapes(cfg)]))
+    return ce, pe, be, cs, ps, bs, enc, sol
+
+
+@pytest.mark.parametrize("nb,B,H", [(2, 2, 32), (1, 3, 40)])
+def test_pair_forward_parity(N, nb, B, H):
+    """Per-sample contexts (nb = B) and one shared medium (nb = 1)."""
+    ce, pe, be, cs, ps, bs, enc, sol = make_pair(N, 3)
+    rng = np.random.default_rng(7)
+    kc = rng.uniform(0.25, 1.0, (nb, H, H)).astype(np.float32)
+    x = rng.standard_normal((B, 3, H, H)).astype(np.float32)
+    N.pair_encode(enc, sol, torch.from_numpy(kc))
+    out = sol.forward(torch.from_numpy(x)).cpu().numpy()
+    ctx = U.encode(ce, pe, be, kc)
+    if nb == 1:
+        ctx = [c.expand(B, -1, -1, -1) for c in ctx]
+    ref = U.forward(cs, ps, bs, torch.from_numpy(x), ctx=ctx).numpy()
+    assert rel(out, ref) <= 2e-2, rel(out, ref)
+
+
+def test_pair_loss_and_gradient_parity(N):
+    """Joint loss and both networks' gradients against the oracle's autograd
+    with bf16 emulation (same rounding points as the device)."""
+    ce, pe, be, cs, ps, bs, enc, sol = make_pair(N, 11, perturb=False)
+    n, nb = 64, 3
+    rng = np.random.default_rng(4)
+    r = (rng.standard_normal((nb, n, n)) + 1j * rng.standard_normal((nb, n, n))).astype(np.complex64)
+    e = (rng.standard_normal((nb, n, n)) + 1j * rng.standard_normal((nb, n, n))).astype(np.complex64) * 1e-4
+    kc = rng.uniform(0.25, 1.0, (nb, n // 2, n // 2)).astype(np.float32)
+    loss, ge, gs = N.pair_loss_grad(enc, sol, torch.from_numpy(r).cuda(), torch.from_numpy(e).cuda(),
+                                    torch.from_numpy(kc).cuda())
+    ga = {k: v.clone().requires_grad_(True) for k, v in pe.items()}
+    gb = {k: v.clone().requires_grad_(True) for k, v in ps.items()}
+    U.EMULATE_BF16 = True
+    try:
+        lo = U.pair_training_loss(ce, ga, be, cs, gb, bs, r, e, kc)
+        lo.backward()
+    finally:
+        U.EMULATE_BF16 = False
+    assert abs(loss - lo.item()) <= 2e-3 * abs(lo.item()), (loss, lo.item())
+    # what remains after emulation is bf16 rounding decisions that flip under
+    # a different FP32 accumulation order, amplified by every BN backward on
+    # the way; the bound grows with the number of BN layers between a tensor
+    # and the loss.  Encoder gradients come through the whole solver first.
+    sol_names = [nm for nm, _, _ in U.layer_specs(cs)]
+    enc_names = [nm for nm, _, _ in U.layer_specs(ce)]
+    bad = []
+    for cfg, g, pg in ((ce, ge.cpu().numpy(), ga), (cs, gs.cpu().numpy(), gb)):
+        off = 0
+        for k, shape in U.param_shapes(cfg).items():
+            cnt = int(np.prod(shape))
+            gg, ref = g[off:off + cnt], pg[k].grad.reshape(-1).numpy()
+            off += cnt
+            cos = float(np.dot(gg, ref) / (np.linalg.norm(gg) * np.linalg.norm(ref) + 1e-30))
+            layer = k.split(".")[0]
+            if not cfg.head:
+                depth = len(sol_names) + len(enc_names) - enc_names.index(layer)
+            else:
+                depth = 0 if layer == "head" else len(sol_names) - sol_names.index(layer)
+            r_ = float(rel(gg, ref))
+            print(f"{'sol' if cfg.head else 'enc'} {k:12s} depth={depth:2d} rel={r_:.3e} cos={cos:.6f}")
+            # BN bias gradients (batch sums of dy) cancel most, hence the floor
+            if r_ > 0.03 + 0.015 * (1 + depth) or cos < 1 - 1.5e-3 * (1 + depth):
+                bad.append((cfg.head, k, r_, cos))
+    assert not bad, bad
+
+
+def test_pair_in_fgmres_matches_oracle_and_converges(N, oracle):
+    """M_VU with an encoder-solver: the first preconditioned step against the
+    oracle's preconditioner, then a full solve to the FP64 tolerance."""
+    from paper_2203_11025_amd import helm
+
+    n = 64
+    kap = inputs.smooth_medium(n, 4.0, seed=5)
+    gam = inputs.sponge_gamma(n, width=8)
+    om = inputs.omega_for_ppw(n)
+    h = helm.Handle(torch.from_numpy(kap).cuda(), torch.from_numpy(gam).cuda(), om, levels=2)
+    ce, pe, be, cs, ps, bs, enc, sol = make_pair(N, 21)
+    kc = kap[::2, ::2].copy()
+    N.pair_encode(enc, sol, torch.from_numpy(kc))
+    b = inputs.point_sources(n, 1, seed=2, margin=8)
+    xs, st, rc = helm.fgmres_solve([h], [torch.from_numpy(b).cuda()], m=5, tol=1e-12, maxit=1,
+                                   prec="unet_defl", net=sol)
+    H = oracle.Hierarchy(kap, gam, om, 2)
+    ctx = U.encode(ce, pe, be, kc)
+    f = lambda v: U.precond_defl(H, cs, ps, bs, v, kc.astype(np.float64), ctx=ctx)
+    xo, sto = H.fgmres(b[0], m=5, tol=1e-12, maxit=1, prec=f)
+    assert rel(xs[0].cpu().numpy()[0], xo) <= 2e-2
+    xs, st, rc = helm.fgmres_solve([h], [torch.from_numpy(b).cuda()], m=10, tol=1e-7,
+                                   prec="unet_defl", net=sol)
+    assert rc == 0 and st[0]["converged"]
+    r = b[0].astype(complex) - oracle.apply(kap, gam, om, xs[0].cpu().numpy()[0])
+    assert np.linalg.norm(r) / np.linalg.norm(b[0]) <= 1e-7
+
+
+def test_pair_training_reduces_loss(N):
+    ce, pe, be, cs, ps, bs, enc, sol = make_pair(N, 31, widths=(32, 64), perturb=False)
+    n, nb = 32, 4
+    rng = np.random.default_rng(9)
+    r = (rng.standard_normal((nb, n, n)) + 1j * rng.standard_normal((nb, n, n))).astype(np.complex64)
+    e = (rng.standard_normal((nb, n, n)) + 1j * rng.standard_normal((nb, n, n))).astype(np.complex64) * 1e-4
+    kc = rng.uniform(0.25, 1.0, (nb, n // 2, n // 2)).astype(np.float32)
+    args = (torch.from_numpy(r).cuda(), torch.from_numpy(e).cuda(), torch.from_numpy(kc).cuda())
+    p0e, _ = enc.get_params()
+    losses = [N.pair_train_step(enc, sol, *args, lr=1e-3) for _ in range(30)]
+    p1e, _ = enc.get_params()
+    assert losses[-1] < 0.8 * losses[0], losses[::5]
+    assert not torch.equal(p0e, p1e)  # the encoder is trained too
+
+
+def test_pair_misuse_is_rejected(N):
+    """A solver without a context, an encoder used as a network, and a stale
+    context after training are errors, not silent results."""
+    from paper_2203_11025_amd import helm
+
+    n = 32
+    kap = inputs.constant_medium(n, 1.0)
+    gam = inputs.sponge_gamma(n, width=4)
+    h = helm.Handle(torch.from_numpy(kap).cuda(), torch.from_numpy(gam).cuda(),
+                    inputs.omega_for_ppw(n), levels=2)
+    _, _, _, _, _, _, enc, sol = make_pair(N, 41, widths=(32, 64), perturb=False)
+    b = torch.from_numpy(inputs.point_sources(n, 1, seed=1, margin=4)).cuda()
+    with pytest.raises(helm.HelmError):
+        helm.fgmres_solve([h], [b], m=5, tol=1e-7, prec="unet_defl", net=sol)
+    with pytest.raises(helm.HelmError):
+        enc.forward(torch.zeros(1, 1, 16, 16))
+    with pytest.raises(helm.HelmError):
+        helm.fgmres_solve([h], [b], m=5, tol=1e-7, prec="unet_defl", net=enc)
+    kc = torch.from_numpy(kap[::2, ::2].copy())
+    N.pair_encode(enc, sol, kc)
+    xs, st, rc = helm.fgmres_solve([h], [b], m=5, tol=1e-7, prec="unet_defl", net=sol)
+    assert rc == 0
+    rr = torch.zeros(1, n, n, dtype=torch.complex64, device="cuda")
+    N.pair_train_step(enc, sol, rr + 1, rr + 1e-4, kc[None].cuda())
+    with pytest.raises(helm.HelmError):
+        helm.fgmres_solve([h], [b], m=5, tol=1e-7, prec="unet_defl", net=sol)

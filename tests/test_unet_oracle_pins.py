@@ -137,3 +137,68 @@ def test_training_triple_residual_and_one_step_minimiser(oracle):
     b = oracle.apply(kap, gam, om, x)
     x1, st = H.fgmres(b, m=5, tol=1e-14, maxit=1)
     np.testing.assert_allclose(x - e, x1, atol=1e-10 * np.abs(x1).max())
+
+
+TINY_ENC = U.UNetCfg(in_ch=1, widths=(4, 8), head=False)
+TINY_SOL = U.UNetCfg(in_ch=3, widths=(4, 8), context=True)
+
+
+def test_pair_context_shapes_and_zero_context_weights():
+    """The encoder yields one context per level (w_l channels at the level's
+    resolution); a solver whose context weight columns are zero computes the
+    plain network with the remaining columns (the context is the last input
+    of enc{l}a and dec{l}a)."""
+    pe, be = U.init_params(TINY_ENC, 1, dtype=torch.float64)
+    ps, bs = U.init_params(TINY_SOL, 2, dtype=torch.float64)
+    rng = np.random.default_rng(3)
+    kc = rng.uniform(0.25, 1.0, (2, 8, 8))
+    ctx = U.encode(TINY_ENC, pe, be, kc, dtype=torch.float64)
+    assert [tuple(c.shape) for c in ctx] == [(2, 4, 8, 8), (2, 8, 4, 4)]
+    plain = U.UNetCfg(in_ch=3, widths=(4, 8))
+    pp = {}
+    for k, v in ps.items():
+        pp[k] = v.clone()
+    for name, cin, cout in U.layer_specs(TINY_SOL):
+        if name.endswith("a"):
+            lev = int(name[3])
+            wctx = TINY_SOL.widths[lev]
+            ps[name + ".w"][:, cin - wctx:] = 0
+            pp[name + ".w"] = ps[name + ".w"][:, :cin - wctx].clone()
+    x = torch.tensor(rng.standard_normal((2, 3, 8, 8)))
+    y_pair = U.forward(TINY_SOL, ps, bs, x, ctx=ctx)
+    y_plain = U.forward(plain, pp, bs, x)
+    np.testing.assert_allclose(y_pair.numpy(), y_plain.numpy(), atol=1e-12)
+
+
+def test_pair_gradients_match_central_differences():
+    """Joint encoder-solver gradients (autograd through the contexts) against
+    FP64 central differences, sampled in every parameter tensor of both."""
+    pe, be = U.init_params(TINY_ENC, 4, dtype=torch.float64)
+    ps, bs = U.init_params(TINY_SOL, 5, dtype=torch.float64)
+    rng = np.random.default_rng(8)
+    kc = rng.uniform(0.25, 1.0, (2, 8, 8))
+    x = torch.tensor(rng.standard_normal((2, 3, 8, 8)))
+    probe = torch.tensor(rng.standard_normal((2, 2, 8, 8)))
+
+    def loss_of(a, b):
+        ctx = U.encode(TINY_ENC, a, be, kc, training=True, dtype=torch.float64)
+        return (U.forward(TINY_SOL, b, bs, x, ctx=ctx, training=True) * probe).sum()
+
+    ga = {k: v.clone().requires_grad_(True) for k, v in pe.items()}
+    gb = {k: v.clone().requires_grad_(True) for k, v in ps.items()}
+    loss_of(ga, gb).backward()
+    h = 1e-6
+    for which, base, grads in (("enc", pe, ga), ("sol", ps, gb)):
+        for k, v in base.items():
+            flat = v.reshape(-1)
+            for idx in rng.choice(flat.numel(), size=min(2, flat.numel()), replace=False):
+                plus = {kk: vv.clone() for kk, vv in base.items()}
+                minus = {kk: vv.clone() for kk, vv in base.items()}
+                plus[k].reshape(-1)[idx] += h
+                minus[k].reshape(-1)[idx] -= h
+                if which == "enc":
+                    fd = (loss_of(plus, ps) - loss_of(minus, ps)).item() / (2 * h)
+                else:
+                    fd = (loss_of(pe, plus) - loss_of(pe, minus)).item() / (2 * h)
+                ad = grads[k].grad.reshape(-1)[idx].item()
+                assert abs(fd - ad) <= 1e-5 * max(1.0, abs(fd)), (which, k, idx, fd, ad)
