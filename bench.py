@@ -1,11 +1,21 @@
 #!/usr/bin/env python3
-"""Benchmark: FGMRES wall seconds per right-hand side to a true relative
-residual of 1e-7 on one MI355X.
+"""Benchmark: FGMRES wall seconds per right-hand side to a true (FP64)
+relative residual of 1e-7 on one MI355X, U-Net + SL against plain SL.
 
-Default workload: 512^2 smooth random medium (sigma 16 cells, slowness in
-[0.25, 1]), 10 points per wavelength, quadratic sponge, one centre point
-source, SL V(1,1) with 4 levels (coarsest 64^2 solved exactly), FGMRES(20).
-One step = one complete solve of the batch, inputs already resident in HBM.
+Default workload (multi1024): 1024^2 smooth random medium (sigma 32 cells,
+slowness in [0.25, 1]), 10 points per wavelength, quadratic 16-cell sponge,
+32 point sources at seeded positions solved in one batched launch, FGMRES(20),
+SL V(1,1) with 5 levels (coarsest 64^2 solved exactly).  The learned
+preconditioner is the encoder-solver pair used as deflation beside the SL
+V-cycle (M_VU, eq. 3.4 with the context of eq. 3.5), starting from the
+pretrained weights when they are present (else seeded initial weights), after
+200 mini-retraining Adam steps on triples of this medium (batch 16).
+
+One timed step = the encoder pass on the medium plus the complete batched
+solve of all right-hand sides, inputs resident in HBM.  The plain-SL solve of
+the same right-hand sides is timed the same way.  `value` is the U-Net + SL
+seconds per right-hand side; the mini-retraining is timed separately and also
+reported amortised over the batch.
 
 Prints one JSON line.  Runs on one GPU only.
 """
@@ -19,45 +29,82 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2203_11025_amd", "weights", "pair_base.safetensors")
+
+PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0
+FAMILIES = ("conv", "cgs", "down", "up", "apply", "coarse")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="plain512")
+    ap.add_argument("--workload", default="multi1024")
+    ap.add_argument("--prec", default="unet_defl", choices=["unet_defl", "unet_cgc"])
+    ap.add_argument("--retrain", type=int, default=200, help="mini-retraining Adam steps")
+    ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--stall-ratio", type=float, default=0.95)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the CPU oracle sample")
     return ap.parse_args()
 
 
-def cpu_baseline(P, gpu_iterations, budget_s):
-    """The FP64 C oracle on this host: a bounded sample of the same solve
-    (the first K FGMRES iterations), scaled to seconds per right-hand side
-    with the iteration count of the full solve."""
-    from oracle import helm_oracle
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+
+def cpu_baseline(P, enc, sol, prec, gpu_iterations, budget_s):
+    """The oracle on this host: the first K iterations of the same U-Net + SL
+    FGMRES solve of the first right-hand side (FP64 C sweeps and Krylov
+    method, FP32 PyTorch CPU network with the GPU's current weights), scaled
+    to seconds per right-hand side by the GPU solve's iteration count."""
+    import numpy as np
+    import torch
+
+    from oracle import helm_oracle
+    from oracle import unet_oracle as U
+
+    ce = U.UNetCfg(in_ch=1, widths=enc.widths, head=False)
+    cs = U.UNetCfg(in_ch=3, widths=sol.widths, context=True)
+    pe, be = enc.get_params()
+    ps, bs = sol.get_params()
+    pe, ps = U.unflatten(ce, pe.cpu()), U.unflatten(cs, ps.cpu())
+    def bufs(cfg, flat):
+        out, off = {}, 0
+        for k, shape in U.buffer_shapes(cfg).items():
+            cnt = int(np.prod(shape))
+            out[k] = flat[off:off + cnt].reshape(shape).clone()
+            off += cnt
+        return out
+    be, bs = bufs(ce, be.cpu()), bufs(cs, bs.cpu())
+    t_all = time.perf_counter()
     H = helm_oracle.Hierarchy(P["kappa"], P["gamma"], P["omega"], P["levels"])
+    kc = P["kappa"].astype(np.float64)[::2, ::2]
+    ctx = U.encode(ce, pe, be, kc)
+    if prec == "unet_defl":
+        f = lambda v: U.precond_defl(H, cs, ps, bs, v, kc, ctx=ctx)
+    else:
+        f = lambda v: U.precond_cgc(H, cs, ps, bs, v, kc, ctx=ctx)
     b = P["b"][0]
-    # calibrate: a short run, then a run sized to the budget
     t0 = time.perf_counter()
-    H.fgmres(b, m=P["m"], tol=1e-30, maxit=P["m"])
-    t_per_it = (time.perf_counter() - t0) / P["m"]
-    k = max(P["m"], int(budget_s / max(t_per_it, 1e-6)) // P["m"] * P["m"])
-    k = min(k, max(gpu_iterations, P["m"]))
+    H.fgmres(b, m=P["m"], tol=1e-30, maxit=1, prec=f)
+    t1 = time.perf_counter() - t0
+    k = int(max(1, min(gpu_iterations, (budget_s - (time.perf_counter() - t_all)) / max(t1, 1e-6))))
     t0 = time.perf_counter()
-    H.fgmres(b, m=P["m"], tol=1e-30, maxit=k)
+    H.fgmres(b, m=P["m"], tol=1e-30, maxit=k, prec=f)
     dt = time.perf_counter() - t0
-    per_it = dt / k
     return {
-        "value": per_it * gpu_iterations,
+        "value": dt / k * gpu_iterations,
         "unit": "s/RHS",
-        "cores": 1,
+        "cores": torch.get_num_threads(),
         "kind": "oracle",
-        "sample": f"first {k} FGMRES({P['m']}) iterations of the same {P['n']}^2 solve "
-                  f"({dt:.1f} s), scaled by the full solve's {gpu_iterations} iterations",
+        "sample": f"first {k} FGMRES({P['m']}) iterations of the same {P['n']}^2 {prec} solve of one "
+                  f"right-hand side ({dt:.1f} s; FP64 C sweeps on one core, FP32 PyTorch CPU network "
+                  f"on {torch.get_num_threads()} threads), scaled by the GPU solve's "
+                  f"{gpu_iterations} iterations",
     }
 
 
@@ -71,41 +118,127 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2203_11025_amd import helm, inputs
+    from paper_2203_11025_amd import helm, inputs, train, unet
+
+    def sync():
+        torch.cuda.synchronize()
 
     P = inputs.config_problem(a.workload)
     dev = torch.device("cuda:0")
+    t_setup = time.perf_counter()
     kap = torch.from_numpy(P["kappa"]).to(dev)
     gam = torch.from_numpy(P["gamma"]).to(dev)
     b = torch.from_numpy(P["b"]).to(dev)
     nrhs = b.shape[0]
     h = helm.Handle(kap, gam, P["omega"], levels=P["levels"])
-    x = torch.empty(b.shape, dtype=torch.complex128, device=dev)
-    print(f"[bench] setup done n={P['n']} levels={h.levels} nrhs={nrhs}", file=sys.stderr, flush=True)
+    sync()
+    t_setup = time.perf_counter() - t_setup
+    log(f"setup n={P['n']} levels={h.levels} nrhs={nrhs} ({t_setup:.2f} s)")
 
-    stats = None
-    for i in range(a.warmup):
-        _, stats, rc = helm.fgmres_solve([h], [b], m=P["m"], tol=P["tol"], xs=[x])
-        print(f"[bench] warmup {i} its={stats[0]['iterations']}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    # the dominant kernel (dense coarsest-level solve) is timed live with HIP
-    # events on its launch stream throughout the timed region
-    helm.profile_start("coarse")
+    enc = unet.UNet(head=False)
+    sol = unet.UNet(context=True)
+    pretrained = os.path.exists(a.weights)
+    if pretrained:
+        unet.load(a.weights, encoder=enc, solver=sol)
+    else:
+        enc.init(1)
+        sol.init(2)
+    log(f"network: {'pretrained ' + os.path.basename(a.weights) if pretrained else 'seeded init'}")
+
+    # mini-retraining on the medium (section 3.4), timed on its own
+    sync()
     t0 = time.perf_counter()
-    for i in range(a.steps):
-        _, stats, rc = helm.fgmres_solve([h], [b], m=P["m"], tol=P["tol"], xs=[x])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    k_ms, k_launches = helm.profile_stop()
-    ms_per_step = dt * 1000.0 / a.steps
-    its = [s["iterations"] for s in stats]
-    relres = max(s["true_relres"] for s in stats)
-    print(f"[bench] timed {a.steps} steps: {ms_per_step:.3f} ms/step its={its} relres={relres:.2e}",
-          file=sys.stderr, flush=True)
+    losses = train.train_pair(enc, sol, [h], steps=a.retrain, batch=16, lr=1e-3, seed=11)
+    sync()
+    t_retrain = time.perf_counter() - t0
+    if losses:
+        log(f"retrain {a.retrain} steps {t_retrain:.1f} s loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    kc = h.coarse_slowness()
+    x = torch.empty(b.shape, dtype=torch.complex128, device=dev)
 
+    def solve_net():
+        unet.pair_encode(enc, sol, kc)
+        return helm.fgmres_solve([h], [b], m=P["m"], tol=P["tol"], prec=a.prec, net=sol,
+                                 stall_ratio=a.stall_ratio, xs=[x])
+
+    def solve_sl():
+        return helm.fgmres_solve([h], [b], m=P["m"], tol=P["tol"], xs=[x])
+
+    # warmup; the first U-Net + SL pass also profiles every kernel family to
+    # find the dominant one
+    for i in range(a.warmup):
+        if i == 0:
+            helm.profile_start(*FAMILIES)
+        _, st, _ = solve_net()
+        if i == 0:
+            fam = {f: helm.profile_read(f) for f in FAMILIES}
+            helm.profile_stop()
+        log(f"warmup {i} U-Net+SL its mean {np.mean([s['iterations'] for s in st]):.1f}")
+        _, st, _ = solve_sl()
+        log(f"warmup {i} SL its mean {np.mean([s['iterations'] for s in st]):.1f}")
+    sync()
+    if a.warmup == 0:
+        fam = {"conv": (1.0, 1, 0.0)}
+    dominant = max(fam, key=lambda f: fam[f][0])
+
+    # timed: U-Net + SL, the dominant kernel family timed live with HIP events
+    helm.profile_start(dominant)
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        _, st_net, rc_net = solve_net()
+    sync()
+    dt_net = time.perf_counter() - t0
+    d_ms, d_launches, d_work = helm.profile_read(dominant)
+    helm.profile_stop()
+    its_net = [s["iterations"] for s in st_net]
+    relres_net = max(s["true_relres"] for s in st_net)
+    log(f"timed U-Net+SL: {dt_net / a.steps * 1e3:.1f} ms/step its mean {np.mean(its_net):.1f} "
+        f"relres {relres_net:.2e}")
+
+    # timed: plain SL on the same right-hand sides
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        _, st_sl, rc_sl = solve_sl()
+    sync()
+    dt_sl = time.perf_counter() - t0
+    its_sl = [s["iterations"] for s in st_sl]
+    relres_sl = max(s["true_relres"] for s in st_sl)
+    log(f"timed SL: {dt_sl / a.steps * 1e3:.1f} ms/step its mean {np.mean(its_sl):.1f} "
+        f"relres {relres_sl:.2e}")
+
+    # the SL sweep families, profiled over one extra plain-SL solve
+    helm.profile_start(*FAMILIES[1:])
+    solve_sl()
+    sweeps = {}
+    for f in FAMILIES[1:]:
+        ms, n_l, work = helm.profile_read(f)
+        if n_l:
+            gbs = work / (ms / 1e3) / 1e9
+            sweeps[f] = {"achieved_GBs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 3),
+                         "avg_launch_us": round(ms * 1e3 / n_l, 2), "launches": n_l}
+    helm.profile_stop()
+
+    ms_per_step = dt_net * 1000.0 / a.steps
+    value = ms_per_step / 1000.0 / nrhs
+    sl_value = dt_sl / a.steps / nrhs
+    unit_is_flops = dominant in ("conv", "wgrad")
+    avg_s = d_ms / 1e3 / max(d_launches, 1)
+    if unit_is_flops:
+        achieved = d_work / max(d_launches, 1) / avg_s / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_BF16_TFLOPS}
+    else:
+        achieved = d_work / max(d_launches, 1) / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS}
+    roof.update({"traffic": None, "kernel": dominant, "avg_launch_us": avg_s * 1e6,
+                 "launches": d_launches, "work_per_launch": d_work / max(d_launches, 1),
+                 "time_share_warmup": round(fam[dominant][0] / sum(v[0] for v in fam.values()), 3)})
     out = {
-        "metric": "FGMRES secs to rel-res 1e-7 per RHS (plain SL)",
-        "value": ms_per_step / 1000.0 / nrhs,
+        "metric": "FGMRES secs to rel-res 1e-7 per RHS: U-Net+SL vs plain SL",
+        "value": value,
         "unit": "s/RHS",
         "n_gpus": 1,
         "steps": a.steps,
@@ -114,26 +247,34 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64",
+        "dtype": "c64+bf16",
         "data": "synthetic",
-        "config": {"workload": f"{P['n']}^2 smooth medium, {nrhs} point source(s), "
-                               f"SL V(1,1) {P['levels']} levels, FGMRES({P['m']}), tol 1e-7",
-                   "n": P["n"], "nrhs": nrhs, "iterations": its, "true_relres": relres},
+        "config": {
+            "workload": f"{P['n']}^2 smooth medium (sigma {P.get('sigma', '-')}), {nrhs} point sources "
+                        f"in one batch, FGMRES({P['m']}) to true relres {P['tol']:g}; U-Net+SL = "
+                        f"{a.prec} with the encoder-solver pair; SL = V(1,1) {h.levels} levels",
+            "n": P["n"], "nrhs": nrhs, "prec": a.prec,
+            "network": "pretrained" if pretrained else "seeded init",
+            "retrain_steps": a.retrain,
+        },
+        "unet_sl": {"s_per_rhs": value, "iterations_mean": float(np.mean(its_net)),
+                    "iterations_max": int(max(its_net)), "true_relres_max": relres_net,
+                    "fallbacks": int(sum(s["fallback"] for s in st_net)), "status": rc_net},
+        "plain_sl": {"s_per_rhs": sl_value, "iterations_mean": float(np.mean(its_sl)),
+                     "iterations_max": int(max(its_sl)), "true_relres_max": relres_sl,
+                     "status": rc_sl},
+        "speedup_vs_plain_sl": sl_value / value,
+        "retrain": {"steps": a.retrain, "seconds": t_retrain,
+                    "loss_first": losses[0] if losses else None,
+                    "loss_last": losses[-1] if losses else None},
+        "value_amortized": value + (t_retrain + t_setup) / nrhs,
+        "setup_s": t_setup,
+        "roofline": roof,
+        "sweeps": sweeps,
     }
-    # algorithmic bytes of one coarse-solve launch: the dense complex64 inverse
-    # (Nc^2 entries) plus the right-hand sides read and the solutions written
-    nc = h.level_size(h.levels - 1)
-    Nc = nc * nc
-    bytes_per_launch = 8.0 * Nc * Nc + 16.0 * Nc * nrhs
-    avg_s = k_ms / 1000.0 / max(k_launches, 1)
-    achieved = bytes_per_launch / avg_s / 1e9
-    out["roofline"] = {"bound": "hbm", "kernel": "k_coarse (dense coarsest-level solve)",
-                       "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                       "frac": achieved / 8000.0, "traffic": None,
-                       "avg_launch_us": avg_s * 1e6, "launches": k_launches,
-                       "bytes_per_launch": bytes_per_launch}
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(P, its[0], a.cpu_seconds)
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(P, enc, sol, a.prec, its_net[0], a.cpu_seconds)
     print(json.dumps(out))
 
 

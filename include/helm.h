@@ -163,18 +163,28 @@ int helm_coarse_slowness(helm_handle *h, float *kc, void *stream);
 /*
  * Kernel timing hook (measurement support, not part of the method).  While
  * active, the library records a HIP event pair on the launch stream around
- * every launch of one kernel family; helm_profile_stop synchronises on those
- * events and returns the summed device time and the number of launches.
- * The hook is process-wide; concurrent solves on several threads share it.
+ * every launch of the kernel families in the mask (bit 1 << family), and sums
+ * the algorithmic work of each launch: the bytes the operation must move
+ * once (sweeps, Gram-Schmidt, coarse solve) or its FLOPs counted as 2 per
+ * multiply-add over the real (unpadded) channels (convolutions).  Work of
+ * kernels that skip converged right-hand sides counts the right-hand sides
+ * active at the start of the current restart cycle.
+ * helm_profile_read synchronises on a family's events and returns its summed
+ * device time, launch count and work; the records stay until the next
+ * helm_profile_start.  helm_profile_stop ends recording.  The hook is
+ * process-wide; concurrent solves on several threads share it.
  */
 #define HELM_PROF_NONE 0
-#define HELM_PROF_COARSE 1 /* dense coarsest-level solve (one per V-cycle)   */
-#define HELM_PROF_DOWN 2   /* fused pre-smooth + residual + restriction      */
-#define HELM_PROF_UP 3     /* fused prolongation + post-smooth               */
-#define HELM_PROF_CGS 4    /* the three Gram-Schmidt passes of an Arnoldi step */
-#define HELM_PROF_APPLY 5  /* stencil apply                                   */
-int helm_profile_start(int family);
-int helm_profile_stop(double *total_ms, long long *launches);
+#define HELM_PROF_COARSE 1 /* dense coarsest-level solve (bytes)              */
+#define HELM_PROF_DOWN 2   /* fused pre-smooth + residual + restriction (bytes) */
+#define HELM_PROF_UP 3     /* fused prolongation + post-smooth (bytes)        */
+#define HELM_PROF_CGS 4    /* the Gram-Schmidt passes of an Arnoldi step (bytes) */
+#define HELM_PROF_APPLY 5  /* stencil apply (bytes)                           */
+#define HELM_PROF_CONV 6   /* 3x3 convolutions, forward and data gradient (FLOPs) */
+#define HELM_PROF_WGRAD 7  /* 3x3 convolution weight gradients (FLOPs)        */
+int helm_profile_start(unsigned family_mask);
+int helm_profile_read(int family, double *total_ms, long long *launches, double *work);
+int helm_profile_stop(void);
 
 /* Thread-local text describing the last error of this thread ("" if none). */
 const char *helm_last_error(void);

@@ -58,6 +58,14 @@ long long unet_num_buffers(const unet_net *net);
 /* Copy parameters and BN buffers in (device float arrays of the sizes above);
  * resets the Adam state and step count.  buffers may be NULL (mean 0, var 1). */
 int unet_set_params(unet_net *net, const float *params, const float *buffers, void *stream);
+/*
+ * Seeded initial parameters: 3x3 weights Kaiming-normal over the real input
+ * fan-in with the LeakyReLU(0.2) gain (std sqrt(2 / (1 + 0.2^2) / (9 cin))),
+ * BN weight 1 and bias 0, head weight normal with std sqrt(1 / w_0), head
+ * bias 0; running statistics mean 0, variance 1; Adam state reset.  Normals
+ * from splitmix64 and the Box-Muller transform.  Synchronises `stream`.
+ */
+int unet_init(unet_net *net, unsigned long long seed, void *stream);
 /* Copy the FP32 master parameters and buffers out (either may be NULL). */
 int unet_get_params(unet_net *net, float *params, float *buffers, void *stream);
 

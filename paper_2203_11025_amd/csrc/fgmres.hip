@@ -36,6 +36,8 @@ struct FgWork {
     double *h_d = nullptr;    // pinned: relres
     int *h_its = nullptr;     // pinned: iteration counts
     int *h_fb = nullptr;      // pinned: fallback flags
+    int *h_net = nullptr;     // pinned: network batch [idx | pos]
+    int *d_net = nullptr;     // device copy of h_net
     float2 *t1 = nullptr, *t2 = nullptr;  // network-preconditioner scratch
     FgState S{};
 };
@@ -136,6 +138,8 @@ void work_free(FgWork *w)
     hipFree(w->state);
     hipFree(w->t1);
     hipFree(w->t2);
+    hipFree(w->d_net);
+    if (w->h_net) hipHostFree(w->h_net);
     if (w->h_fb) hipHostFree(w->h_fb);
     if (w->h_i) hipHostFree(w->h_i);
     if (w->h_d) hipHostFree(w->h_d);
@@ -212,11 +216,14 @@ int work_ensure(helm_handle *h, int nb, int m, bool scratch, FgWork **out)
         set_error("helm_fgmres_solve: clearing the solver state failed");
         return HELM_E_HIP;
     }
-    if (scratch && (dalloc(&w->t1, (size_t)nb * N) || dalloc(&w->t2, (size_t)nb * N))) {
+    if (scratch && (dalloc(&w->t1, (size_t)nb * N) || dalloc(&w->t2, (size_t)nb * N) ||
+                    hipMalloc(&w->d_net, 2 * nb * sizeof(int)) != hipSuccess)) {
         work_free(w);
+        set_error("helm_fgmres_solve: device allocation failed");
         return HELM_E_NOMEM;
     }
-    if (hipHostMalloc((void **)&w->h_fb, nb * sizeof(int)) != hipSuccess ||
+    if (hipHostMalloc((void **)&w->h_net, 2 * nb * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void **)&w->h_fb, nb * sizeof(int)) != hipSuccess ||
         hipHostMalloc((void **)&w->h_i, nb * sizeof(int)) != hipSuccess ||
         hipHostMalloc((void **)&w->h_d, nb * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&w->h_its, nb * sizeof(int)) != hipSuccess) {
@@ -235,8 +242,11 @@ int work_ensure(helm_handle *h, int nb, int m, bool scratch, FgWork **out)
 //       e1 = w D_A^-1 v,  e2 = e1 + Net(v - A e1),  z = e2 + w D_A^-1 (v - A e2)
 //   M_VU (eq. 3.4):  e0 = Net(v),  z = e0 + V(0, v - A e0)
 int apply_net_prec(helm_handle *h, unet_net *net, int prec, FgWork *w, const FgState &S,
-                   float2 *v, size_t vs, float2 *z, size_t zs, int nb, hipStream_t s)
+                   float2 *v, size_t vs, float2 *z, size_t zs, int nb, int nnet, hipStream_t s)
 {
+    // the network runs on the nnet right-hand sides that used it at the start
+    // of the restart cycle (w->d_net: their indices, then the inverse map)
+    const int *idx = w->d_net, *pos = w->d_net + nb;
     const size_t N = w->N;
     const Level &L0 = h->lv[0];
     const float jw = (float)h->jacobi_w;
@@ -244,14 +254,14 @@ int apply_net_prec(helm_handle *h, unet_net *net, int prec, FgWork *w, const FgS
     launch_masks(S, 1, s);
     int rc;
     if (prec == HELM_PREC_UNET_DEFL) {
-        if ((rc = net->wrap_apply(h, v, vs, z, zs, nb, 0, s, S.mask_net))) return rc;
+        if ((rc = net->wrap_apply(h, v, vs, z, zs, nb, 0, s, S.mask_net, nnet, idx, pos))) return rc;
         launch_resjac(L0, 0.f, jw, 0, z, zs, v, vs, w->t2, N, nb, S.active, s);
         return vcycle(h, w->t2, N, z, zs, nb, S.active, s, nullptr, 1);
     }
     // coarse-grid-correction form
     launch_resjac(L0, 0.f, jw, 2, v, vs, v, vs, w->t1, N, nb, S.mask_net, s);
     launch_resjac(L0, 0.f, jw, 0, w->t1, N, v, vs, w->t2, N, nb, S.mask_net, s);
-    if ((rc = net->wrap_apply(h, w->t2, N, w->t1, N, nb, 1, s, S.mask_net))) return rc;
+    if ((rc = net->wrap_apply(h, w->t2, N, w->t1, N, nb, 1, s, S.mask_net, nnet, idx, pos))) return rc;
     launch_resjac(L0, 0.f, jw, 1, w->t1, N, v, vs, z, zs, nb, S.mask_net, s);
     return vcycle(h, v, vs, z, zs, nb, S.mask_sl, s);
 }
@@ -287,6 +297,8 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
     for (;;) {
         HELM_HIP_CHECK(hipMemcpyAsync(w->h_d, S.relres, nb * sizeof(double), hipMemcpyDeviceToHost, s));
         HELM_HIP_CHECK(hipMemcpyAsync(w->h_its, S.its, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+        if (use_net)
+            HELM_HIP_CHECK(hipMemcpyAsync(w->h_fb, S.fallback, nb * sizeof(int), hipMemcpyDeviceToHost, s));
         HELM_HIP_CHECK(hipStreamSynchronize(s));
         int nact = 0;
         for (int i = 0; i < nb; ++i) {
@@ -295,6 +307,18 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
             nact += w->h_i[i];
         }
         if (nact == 0) break;
+        prof_set_active(nact);
+        int nnet = 0;
+        if (use_net) {
+            // gather the right-hand sides still using the network
+            for (int i = 0; i < nb; ++i) w->h_net[nb + i] = -1;
+            for (int i = 0; i < nb; ++i)
+                if (w->h_i[i] && !w->h_fb[i]) {
+                    w->h_net[nnet] = i;
+                    w->h_net[nb + i] = nnet++;
+                }
+            HELM_HIP_CHECK(hipMemcpyAsync(w->d_net, w->h_net, 2 * nb * sizeof(int), hipMemcpyHostToDevice, s));
+        }
         HELM_HIP_CHECK(hipMemcpyAsync(S.active, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
         HELM_HIP_CHECK(hipMemcpyAsync(S.incycle, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
         for (int j = 0; j < m; ++j) {
@@ -306,7 +330,7 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
                 rc = vcycle(h, vj, vsb, zj, zsb, nb, S.active, s, S.scale);
                 if (rc) return rc;
             } else {
-                rc = apply_net_prec(h, net, prec, w, S, vj, vsb, zj, zsb, nb, s);
+                rc = apply_net_prec(h, net, prec, w, S, vj, vsb, zj, zsb, nb, nnet, s);
                 if (rc) return rc;
             }
             launch_apply(L0, 0.f, zj, zsb, wj, vsb, nb, S.active, s);
@@ -321,6 +345,7 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
             if (w->h_i[i]) restarts[i]++;
         HELM_HIP_CHECK(hipGetLastError());
     }
+    prof_set_active(-1);
     HELM_HIP_CHECK(hipMemcpyAsync(w->h_fb, S.fallback, nb * sizeof(int), hipMemcpyDeviceToHost, s));
     HELM_HIP_CHECK(hipStreamSynchronize(s));
     int nconv = 0;

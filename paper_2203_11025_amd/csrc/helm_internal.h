@@ -14,7 +14,11 @@ namespace helm {
 
 void set_error(const std::string &msg);
 // Timing hook (prof.hip): event on stream s at the start/end of a family's launch.
-void prof_mark(int family, hipStream_t s, bool start);
+// work_per_rhs x nb (or x the active right-hand sides when masked) is added
+// to the family's algorithmic work when the stop mark is recorded
+void prof_mark(int family, hipStream_t s, bool start, double work_per_rhs = 0.0, int nb = 1,
+               bool masked = false);
+void prof_set_active(int nact);
 
 #define HELM_HIP_CHECK(call)                                                        \
     do {                                                                            \

@@ -427,7 +427,9 @@ void launch_arnoldi_step(const FgState &S, float2 *V, size_t vsb, size_t N, int 
     kPassA[j](S, V, vsb, N, partial, nblk, s);
     hipLaunchKernelGGL(k_arnoldi_reduce, dim3(S.nb), dim3(1024), 0, s, S, partial, nblk, j);
     kPassB[j](S, V, vsb, N, nblk, s);
-    prof_mark(HELM_PROF_CGS, s, false);
+    // both passes read v_0..v_j and the candidate; the second writes it:
+    // 16 (j + 2) + 8 B per point
+    prof_mark(HELM_PROF_CGS, s, false, (16.0 * (j + 2) + 8.0) * N, S.nb, true);
 }
 
 void launch_masks(const FgState &S, int use_net, hipStream_t s)

@@ -1,5 +1,6 @@
 // Kernel timing hook: HIP event pairs recorded on the launch stream around
-// every launch of one selected kernel family, summed on demand.
+// every launch of the selected kernel families, with the algorithmic work
+// (bytes or FLOPs) of each launch, summed on demand.
 #include <mutex>
 #include <vector>
 
@@ -8,29 +9,50 @@
 namespace helm {
 
 namespace {
-struct Prof {
-    std::mutex mu;
-    int family = HELM_PROF_NONE;
+constexpr int NFAM = HELM_PROF_WGRAD + 1;
+struct Family {
     std::vector<hipEvent_t> ev;  // start/stop pairs
     size_t used = 0;             // events recorded so far
     bool open = false;           // a start without its stop
+    double work = 0.0;           // summed algorithmic work of the closed pairs
+};
+struct Prof {
+    std::mutex mu;
+    unsigned mask = 0;
+    int active_rhs = -1;  // right-hand sides still iterating (set by the solver)
+    Family f[NFAM];
 };
 Prof g_prof;
 }  // namespace
 
-void prof_mark(int family, hipStream_t s, bool start)
+void prof_set_active(int nact)
 {
-    if (g_prof.family != family) return;
+    if (!g_prof.mask) return;
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    if (start == g_prof.open) return;  // unbalanced call: ignore
-    if (g_prof.used == g_prof.ev.size()) {
+    g_prof.active_rhs = nact;
+}
+
+void prof_mark(int family, hipStream_t s, bool start, double work_per_rhs, int nb, bool masked)
+{
+    if (!(g_prof.mask & (1u << family))) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    Family &F = g_prof.f[family];
+    if (start == F.open) return;  // unbalanced call: ignore
+    if (F.used == F.ev.size()) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return;
-        g_prof.ev.push_back(e);
+        F.ev.push_back(e);
     }
-    if (hipEventRecord(g_prof.ev[g_prof.used], s) == hipSuccess) {
-        ++g_prof.used;
-        g_prof.open = start;
+    if (hipEventRecord(F.ev[F.used], s) == hipSuccess) {
+        ++F.used;
+        F.open = start;
+        if (!start) {
+            // kernels that skip finished right-hand sides do the work of the
+            // active ones only
+            int cnt = nb;
+            if (masked && g_prof.active_rhs >= 0 && g_prof.active_rhs < nb) cnt = g_prof.active_rhs;
+            F.work += work_per_rhs * cnt;
+        }
     }
 }
 
@@ -38,38 +60,52 @@ void prof_mark(int family, hipStream_t s, bool start)
 
 using namespace helm;
 
-extern "C" int helm_profile_start(int family)
+extern "C" int helm_profile_start(unsigned family_mask)
 {
-    if (family < HELM_PROF_NONE || family > HELM_PROF_APPLY) {
-        set_error("helm_profile_start: unknown kernel family");
+    if (family_mask >> NFAM) {
+        set_error("helm_profile_start: unknown kernel family in the mask");
         return HELM_E_INVALID;
     }
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    g_prof.family = family;
-    g_prof.used = 0;
-    g_prof.open = false;
+    g_prof.mask = family_mask;
+    g_prof.active_rhs = -1;
+    for (auto &F : g_prof.f) {
+        F.used = 0;
+        F.open = false;
+        F.work = 0.0;
+    }
     return HELM_OK;
 }
 
-extern "C" int helm_profile_stop(double *total_ms, long long *launches)
+extern "C" int helm_profile_read(int family, double *total_ms, long long *launches, double *work)
 {
+    if (family <= HELM_PROF_NONE || family >= NFAM) {
+        set_error("helm_profile_read: unknown kernel family");
+        return HELM_E_INVALID;
+    }
     std::lock_guard<std::mutex> lk(g_prof.mu);
+    Family &F = g_prof.f[family];
     double tot = 0.0;
-    size_t pairs = g_prof.used / 2;
+    size_t pairs = F.used / 2;
     for (size_t i = 0; i < pairs; ++i) {
         float ms = 0.f;
-        if (hipEventSynchronize(g_prof.ev[2 * i + 1]) != hipSuccess ||
-            hipEventElapsedTime(&ms, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]) != hipSuccess) {
-            set_error("helm_profile_stop: reading the timing events failed");
-            g_prof.family = HELM_PROF_NONE;
+        if (hipEventSynchronize(F.ev[2 * i + 1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, F.ev[2 * i], F.ev[2 * i + 1]) != hipSuccess) {
+            set_error("helm_profile_read: reading the timing events failed");
             return HELM_E_HIP;
         }
         tot += ms;
     }
     if (total_ms) *total_ms = tot;
     if (launches) *launches = (long long)pairs;
-    g_prof.family = HELM_PROF_NONE;
-    g_prof.used = 0;
-    g_prof.open = false;
+    if (work) *work = F.work;
+    return HELM_OK;
+}
+
+extern "C" int helm_profile_stop(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.mask = 0;
+    g_prof.active_rhs = -1;
     return HELM_OK;
 }

@@ -442,7 +442,8 @@ void launch_apply(const Level &L, float shift, const float2 *x, size_t xs, float
     prof_mark(HELM_PROF_APPLY, s, true);
     hipLaunchKernelGGL(k_apply, grid, block, 0, s, x, xs, y, ys, L.mass, n, L.ih2, shift, R,
                        active);
-    prof_mark(HELM_PROF_APPLY, s, false);
+    // x read, y written, medium read: 24 B per point
+    prof_mark(HELM_PROF_APPLY, s, false, 24.0 * n * n, nb, active != nullptr);
 }
 
 void launch_resjac(const Level &L, float shift, float w, int mode, const float2 *x, size_t xs,
@@ -466,7 +467,10 @@ void launch_down(const Level &L, float shift, float w, const float2 *f, size_t f
     prof_mark(HELM_PROF_DOWN, s, true);
     hipLaunchKernelGGL(k_down, grid, dim3(256), 0, s, f, fs, fc, fcs, L.mass,
                        L.n, L.ih2, shift, w, scale, active);
-    prof_mark(HELM_PROF_DOWN, s, false);
+    // f and the medium read, the coarse residual written (the pre-smoothed
+    // iterate is recomputed by the prolongation sweep, never stored): 18 B
+    // per fine point
+    prof_mark(HELM_PROF_DOWN, s, false, 18.0 * L.n * L.n, nb, active != nullptr);
 }
 
 void launch_up(const Level &L, float shift, float w, const float2 *f, size_t fs,
@@ -478,7 +482,9 @@ void launch_up(const Level &L, float shift, float w, const float2 *f, size_t fs,
     prof_mark(HELM_PROF_UP, s, true);
     hipLaunchKernelGGL(k_up, grid, dim3(256), 0, s, f, fs, vc, vcs, v, vs, L.mass, n, L.ih2,
                        shift, w, scale, accumulate, active);
-    prof_mark(HELM_PROF_UP, s, false);
+    // f, the medium and the coarse correction read, v written (and read when
+    // accumulating): 26 (34) B per fine point
+    prof_mark(HELM_PROF_UP, s, false, (accumulate ? 34.0 : 26.0) * n * n, nb, active != nullptr);
 }
 
 void launch_coarse_solve(const float2 *X, int N, const float2 *f, size_t fs, float2 *v,
@@ -504,7 +510,8 @@ void launch_coarse_solve(const float2 *X, int N, const float2 *f, size_t fs, flo
             b0 += 1;
         }
     }
-    prof_mark(HELM_PROF_COARSE, s, false);
+    // the dense inverse read once, each right-hand side read and written
+    prof_mark(HELM_PROF_COARSE, s, false, 8.0 * N * N + (accumulate ? 24.0 : 16.0) * N * nb, 1, false);
 }
 
 void launch_level_mass(const float *kappa, const float *gamma, int n, int stride_pow,

@@ -88,12 +88,17 @@ void launch_head_bwd(const float *dout, const bf16 *a, size_t P, int C, const fl
 // x0[b][I][J][0..31] = (Re rc / s, Im rc / s, kappa_c, 0, ...), kappa_c either
 // injected from the fine slowness (kappa_fine != null) or given on the coarse
 // grid.  s[b] = 0 marks an all-zero residual.
+// Sample b of the network batch reads right-hand side idx[b] (b if idx is null).
 void launch_net_input(const float2 *r, size_t rstride, int nb, int n, const float *kappa_fine,
                       const float *kappa_c, float2 *rc, double *part, double *s, bf16 *x0,
-                      hipStream_t s_);
-// e (+)= P (s_b (out0 + i out1)) on the fine grid; out [nb][n/2][n/2][2] FP32.
+                      hipStream_t s_, const int *idx = nullptr);
+// e (+)= P (s_q (out0 + i out1)) on the fine grid for each of the nb
+// right-hand sides, q = pos[b] its sample in the network batch (b if pos is
+// null); q < 0 or mask[b] == 0: e_b = 0 (untouched when accumulating).
+// out [batch][n/2][n/2][2] FP32.
 void launch_net_output(const float *out, const double *s, int nb, int n, float2 *e,
-                       size_t estride, int accumulate, hipStream_t st, const int *mask = nullptr);
+                       size_t estride, int accumulate, hipStream_t st, const int *mask = nullptr,
+                       const int *pos = nullptr);
 // Loss of one batch: d = P out_b - e_b / s_b (fine), loss = mean_b |d|^2 / n^2,
 // dout = (2 / (B n^2)) 4 R(d) split into (re, im).  loss_out: device double.
 void launch_loss_grad(const float *out, const double *s, int nb, int n, const float2 *e,

@@ -668,11 +668,12 @@ __global__ void k_head_bwd_finish(const double *__restrict__ part, int nblk, int
 // rc = R(h^2 r) (full weighting, zero outside) and partial sums of |rc|^2
 __global__ __launch_bounds__(256) void k_restrict_scaled(const float2 *__restrict__ r, size_t rs,
                                                          int n, float2 *__restrict__ rc,
-                                                         double *__restrict__ part, int nblk)
+                                                         double *__restrict__ part, int nblk,
+                                                         const int *__restrict__ idx)
 {
     const int b = blockIdx.y, nc = n / 2;
     const float h2 = 1.f / ((float)n * (float)n);
-    const float2 *rb = r + (size_t)b * rs;
+    const float2 *rb = r + (size_t)(idx ? idx[b] : b) * rs;
     double acc = 0.0;
     for (int idx = blockIdx.x * 256 + threadIdx.x; idx < nc * nc; idx += nblk * 256) {
         int I = idx / nc, J = idx - I * nc;
@@ -738,7 +739,7 @@ __global__ void k_pack_input(const float2 *__restrict__ rc, const double *__rest
 // convolution with (1/4)[1 2 1; 2 4 2; 1 2 1])
 __global__ void k_net_output(const float *__restrict__ out, const double *__restrict__ s, int nb,
                              int n, float2 *__restrict__ e, size_t es, int accumulate,
-                             const int *__restrict__ mask)
+                             const int *__restrict__ mask, const int *__restrict__ pos)
 {
     const int nc = n / 2;
     const size_t total = (size_t)nb * n * n;
@@ -746,12 +747,13 @@ __global__ void k_net_output(const float *__restrict__ out, const double *__rest
          idx += (size_t)gridDim.x * blockDim.x) {
         int b = (int)(idx / ((size_t)n * n));
         size_t pix = idx % ((size_t)n * n);
-        if (mask && !mask[b]) {
+        const int q = pos ? pos[b] : b;  // the right-hand side's sample in the network batch
+        if (q < 0 || (mask && !mask[b])) {
             if (!accumulate) e[(size_t)b * es + pix] = make_float2(0.f, 0.f);
             continue;
         }
         int i = (int)(pix / n), j = (int)(pix % n);
-        const float *ob = out + (size_t)b * nc * nc * 2;
+        const float *ob = out + (size_t)q * nc * nc * 2;
         float sr = 0.f, si = 0.f;
         int Ia = i >> 1, Ib = (i + 1) >> 1, Ja = j >> 1, Jb = (j + 1) >> 1;
         float wi = (i & 1) ? 0.5f : 1.f, wj = (j & 1) ? 0.5f : 1.f;
@@ -765,7 +767,7 @@ __global__ void k_net_output(const float *__restrict__ out, const double *__rest
                 si += ob[((size_t)I * nc + J) * 2 + 1];
             }
         }
-        float sc = (float)s[b] * wi * wj;
+        float sc = (float)s[q] * wi * wj;
         float2 val = make_float2(sc * sr, sc * si);
         float2 *pe = e + (size_t)b * es + pix;
         if (accumulate) {
@@ -1125,12 +1127,12 @@ void launch_head_bwd(const float *dout, const bf16 *a, size_t P, int C, const fl
 
 void launch_net_input(const float2 *r, size_t rstride, int nb, int n, const float *kappa_fine,
                       const float *kappa_c, float2 *rc, double *part, double *s, bf16 *x0,
-                      hipStream_t st)
+                      hipStream_t st, const int *idx)
 {
     int nc = n / 2;
     int nblk = (int)std::min<size_t>(256, std::max<size_t>(1, ((size_t)nc * nc + 1023) / 1024));
     hipLaunchKernelGGL(k_restrict_scaled, dim3(nblk, nb), dim3(256), 0, st, r, rstride, n, rc, part,
-                       nblk);
+                       nblk, idx);
     hipLaunchKernelGGL(k_rms, dim3(nb), dim3(64), 0, st, part, nblk, nc, s);
     size_t tot = (size_t)nb * nc * nc;
     hipLaunchKernelGGL(k_pack_input, dim3(grid_for(tot)), dim3(256), 0, st, rc, s, nb, n, kappa_fine,
@@ -1138,11 +1140,11 @@ void launch_net_input(const float2 *r, size_t rstride, int nb, int n, const floa
 }
 
 void launch_net_output(const float *out, const double *s, int nb, int n, float2 *e, size_t estride,
-                       int accumulate, hipStream_t st, const int *mask)
+                       int accumulate, hipStream_t st, const int *mask, const int *pos)
 {
     size_t tot = (size_t)nb * n * n;
     hipLaunchKernelGGL(k_net_output, dim3(grid_for(tot)), dim3(256), 0, st, out, s, nb, n, e, estride,
-                       accumulate, mask);
+                       accumulate, mask, pos);
 }
 
 void launch_loss_grad(const float *out, const double *s, int nb, int n, const float2 *e,

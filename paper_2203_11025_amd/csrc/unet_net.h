@@ -71,10 +71,13 @@ struct unet_net {
     void refold(hipStream_t st);
     int pack_nchw_input(const float *x, int B, int H, int W, hipStream_t st);
     int unpack_nchw_output(float *o, int B, int H, int W, hipStream_t st);
-    // e (+)= P s Net(R(h^2 r)/s, kappa_c) for nb fields of medium h
-    // (mask, may be null: entries b with mask[b] == 0 are left unchanged, or
-    // set to zero when not accumulating)
+    // e (+)= P s Net(R(h^2 r)/s, kappa_c) for nb fields of medium h (mask,
+    // may be null: entries b with mask[b] == 0 are left unchanged, or set to
+    // zero when not accumulating).  With idx/pos the network runs on the nnet
+    // right-hand sides idx[0..nnet) only (pos: the inverse map, -1 for the
+    // others, which are treated as masked).
     int wrap_apply(helm_handle *h, const float2 *r, size_t rs, float2 *e, size_t es, int nb,
-                   int accumulate, hipStream_t st, const int *mask = nullptr);
+                   int accumulate, hipStream_t st, const int *mask = nullptr, int nnet = -1,
+                   const int *idx = nullptr, const int *pos = nullptr);
     int loss_grad(const unet_batch &bt, hipStream_t st);
 };

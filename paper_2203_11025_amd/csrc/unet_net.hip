@@ -3,6 +3,7 @@
 // error wrapper used by the preconditioners.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <string>
 #include <vector>
 
@@ -258,13 +259,18 @@ void unet_net::run_layer(int i, const Srcs &src, int B, int H, int W, bool train
     Layer &l = L[i];
     Act &a = act[i];
     const size_t Pl = (size_t)B * H * W;
+    // 2 FLOPs per multiply-add over the real input channels
+    const double flops = 18.0 * l.cin_real * l.cout * (double)Pl;
+    prof_mark(HELM_PROF_CONV, st, true);
     if (training) {
         launch_conv3x3(src, B, H, W, l.Wp, l.cout, 0, a.y32, nullptr, nullptr, nullptr, SLOPE, st);
+        prof_mark(HELM_PROF_CONV, st, false, flops);
         launch_bn_stats(a.y32, Pl, l.cout, red, l.mean, l.rstd, l.var, st);
         launch_bn_act_fwd(a.y32, Pl, l.cout, l.mean, l.rstd, P + l.g_off, P + l.b_off, SLOPE, a.a, st);
     } else {
         launch_conv3x3(src, B, H, W, l.Wp, l.cout, 1, nullptr, a.a, scale + l.sc_off, shift + l.sc_off,
                        SLOPE, st);
+        prof_mark(HELM_PROF_CONV, st, false, flops);
     }
 }
 
@@ -358,7 +364,10 @@ void unet_net::layers_backward(int B, int H, int W, hipStream_t st)
         launch_bn_act_bwd(a.g, a.y32, Pl, l.cout, l.mean, l.rstd, P + l.g_off, P + l.b_off, SLOPE, red,
                           G + l.g_off, G + l.b_off, dy, st);
         Srcs src = layer_srcs(i);
+        const double flops = 18.0 * l.cin_real * l.cout * (double)Pl;
+        prof_mark(HELM_PROF_WGRAD, st, true);
         launch_wgrad(src, dy, B, Hl, Wl, l.cout, dW, wpart, st);
+        prof_mark(HELM_PROF_WGRAD, st, false, flops);
         launch_unpack_wgrad(dW, l.cout, l.cin_real, l.map, l.cin_pad, G + l.w_off, st);
         const bool has_ctx = cfg.context && l.name.back() == 'a';
         if (i == 0 && !has_ctx) continue;  // no gradient w.r.t. the network input
@@ -367,7 +376,9 @@ void unet_net::layers_backward(int B, int H, int W, hipStream_t st)
         ds.n = 1;
         ds.Ctot = l.cout;
         ds.s[0] = {dy, l.cout, 0};
+        prof_mark(HELM_PROF_CONV, st, true);
         launch_conv3x3(ds, B, Hl, Wl, l.Wd, l.cin_pad, 0, dX, nullptr, nullptr, nullptr, SLOPE, st);
+        prof_mark(HELM_PROF_CONV, st, false, flops);
         const std::string &nm = l.name;
         const int lev = l.level;
         if (has_ctx)  // the context is the last source
@@ -458,14 +469,21 @@ void unet_net::refold(hipStream_t st)
 }
 
 int unet_net::wrap_apply(helm_handle *h, const float2 *r, size_t rs, float2 *e, size_t es, int nb,
-                     int accumulate, hipStream_t st, const int *mask)
+                         int accumulate, hipStream_t st, const int *mask, int nnet, const int *idx,
+                         const int *pos)
 {
     const int n = h->n, nc = n / 2;
-    int rc = ensure_ws(nb, nc, nc, false);
-    if (rc) return rc;
-    launch_net_input(r, rs, nb, n, h->kappa0, nullptr, rcoarse, red, s, x0, st);
-    forward_from_x0(nb, nc, nc, false, st);
-    launch_net_output(out, s, nb, n, e, es, accumulate, st, mask);
+    if (nnet < 0) {
+        nnet = nb;
+        idx = pos = nullptr;
+    }
+    if (nnet > 0) {
+        int rc = ensure_ws(nnet, nc, nc, false);
+        if (rc) return rc;
+        launch_net_input(r, rs, nnet, n, h->kappa0, nullptr, rcoarse, red, s, x0, st, idx);
+        forward_from_x0(nnet, nc, nc, false, st);
+    }
+    launch_net_output(out, s, nb, n, e, es, accumulate, st, mask, pos);
     return HELM_OK;
 }
 
@@ -555,6 +573,62 @@ int unet_set_params(unet_net *net, const float *params, const float *buffers, vo
     net->repack(st);
     HELM_HIP_CHECK(hipGetLastError());
     return HELM_OK;
+}
+
+// splitmix64 (Steele, Lea and Flood 2014) for the initial weights
+static uint64_t splitmix64(uint64_t &state)
+{
+    uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// standard normal by the Box-Muller transform of two uniforms in (0, 1]
+static double normal01(uint64_t &state)
+{
+    double u1 = ((splitmix64(state) >> 11) + 1.0) * 0x1.0p-53;
+    double u2 = ((splitmix64(state) >> 11) + 1.0) * 0x1.0p-53;
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+}
+
+int unet_init(unet_net *net, unsigned long long seed, void *stream)
+{
+    if (!net) {
+        set_error("unet_init: null network");
+        return HELM_E_INVALID;
+    }
+    std::vector<float> p(net->nparams, 0.f);
+    uint64_t st = seed * 0x2545F4914F6CDD1Dull + 1;
+    const double gain2 = 2.0 / (1.0 + SLOPE * SLOPE);  // LeakyReLU(0.2) gain squared
+    for (auto &l : net->L) {
+        const double sd = std::sqrt(gain2 / (9.0 * l.cin_real));
+        for (size_t i = 0; i < (size_t)l.cout * l.cin_real * 9; ++i) p[l.w_off + i] = (float)(sd * normal01(st));
+        for (int c = 0; c < l.cout; ++c) p[l.g_off + c] = 1.f;
+    }
+    if (net->cfg.head) {
+        const double sd = std::sqrt(1.0 / net->cfg.widths[0]);
+        for (size_t i = 0; i < (size_t)net->cfg.out_ch * net->cfg.widths[0]; ++i)
+            p[net->head_w + i] = (float)(sd * normal01(st));
+    }
+    float *dp = nullptr;
+    if (hipMalloc(&dp, net->nparams * sizeof(float)) != hipSuccess) {
+        set_error("unet_init: out of device memory");
+        return HELM_E_NOMEM;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int rc = HELM_OK;
+    if (hipMemcpyAsync(dp, p.data(), net->nparams * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess) {
+        set_error("unet_init: copy failed");
+        rc = HELM_E_HIP;
+    }
+    if (!rc) rc = unet_set_params(net, dp, nullptr, stream);
+    if (hipStreamSynchronize(s) != hipSuccess && !rc) {
+        set_error("unet_init: synchronisation failed");
+        rc = HELM_E_HIP;
+    }
+    hipFree(dp);
+    return rc;
 }
 
 int unet_get_params(unet_net *net, float *params, float *buffers, void *stream)

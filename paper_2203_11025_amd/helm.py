@@ -24,9 +24,9 @@ PREC = {"sl": 0, "unet_cgc": 1, "unet_defl": 2}
 EXPORTS = [
     "helm_setup", "helm_destroy", "helm_level_size", "helm_num_levels", "helm_apply",
     "helm_sl_vcycle", "helm_fgmres_solve", "helm_last_error", "helm_profile_start",
-    "helm_profile_stop", "helm_training_triples", "helm_coarse_slowness",
+    "helm_profile_read", "helm_profile_stop", "helm_training_triples", "helm_coarse_slowness",
 ]
-PROF = {"none": 0, "coarse": 1, "down": 2, "up": 3, "cgs": 4, "apply": 5}
+PROF = {"none": 0, "coarse": 1, "down": 2, "up": 3, "cgs": 4, "apply": 5, "conv": 6, "wgrad": 7}
 
 
 class HelmError(RuntimeError):
@@ -83,9 +83,11 @@ def lib():
         L.helm_training_triples.restype = ip
         L.helm_coarse_slowness.argtypes = [vp, vp, vp]
         L.helm_coarse_slowness.restype = ip
-        L.helm_profile_start.argtypes = [ip]
+        L.helm_profile_start.argtypes = [C.c_uint]
         L.helm_profile_start.restype = ip
-        L.helm_profile_stop.argtypes = [C.POINTER(dp), C.POINTER(C.c_longlong)]
+        L.helm_profile_read.argtypes = [ip, C.POINTER(dp), C.POINTER(C.c_longlong), C.POINTER(dp)]
+        L.helm_profile_read.restype = ip
+        L.helm_profile_stop.argtypes = []
         L.helm_profile_stop.restype = ip
         _lib = L
     return _lib
@@ -218,14 +220,26 @@ def fgmres_solve(problems, rhs, m=20, tol=1e-7, maxit=20000, prec="sl", net=None
     return xs, [stats[i].as_dict() for i in range(total)], rc
 
 
-def profile_start(family):
-    """Start timing every launch of one kernel family with HIP events."""
-    _check(lib().helm_profile_start(PROF[family]), "helm_profile_start")
+def profile_start(*families):
+    """Start timing every launch of the given kernel families with HIP events
+    on their launch streams, summing each launch's algorithmic work."""
+    mask = 0
+    for f in families:
+        mask |= 1 << PROF[f]
+    _check(lib().helm_profile_start(mask), "helm_profile_start")
+
+
+def profile_read(family):
+    """(summed device milliseconds, launches, algorithmic work) of one family
+    since profile_start (bytes for sweeps, FLOPs for convolutions)."""
+    ms = C.c_double()
+    n = C.c_longlong()
+    w = C.c_double()
+    _check(lib().helm_profile_read(PROF[family], C.byref(ms), C.byref(n), C.byref(w)),
+           "helm_profile_read")
+    return ms.value, n.value, w.value
 
 
 def profile_stop():
-    """Stop timing; returns (summed device milliseconds, number of launches)."""
-    ms = C.c_double()
-    n = C.c_longlong()
-    _check(lib().helm_profile_stop(C.byref(ms), C.byref(n)), "helm_profile_stop")
-    return ms.value, n.value
+    _check(lib().helm_profile_stop(), "helm_profile_stop")
+

@@ -151,6 +151,7 @@ def config_problem(name: str) -> dict:
     multi1024  : 1024^2, smooth medium (sigma 32 cells, seed 2), 32 point
                  sources (seed 3), 5 levels, FGMRES(20)
     """
+    sigma = None
     if name == "plain128":
         n = 128
         kappa = constant_medium(n)
@@ -158,15 +159,17 @@ def config_problem(name: str) -> dict:
         levels, m = 3, 10
     elif name == "plain512":
         n = 512
-        kappa = smooth_medium(n, 16.0, seed=1)
+        sigma = 16.0
+        kappa = smooth_medium(n, sigma, seed=1)
         b = point_source(n)[None]
         levels, m = 4, 20
     elif name == "multi1024":
         n = 1024
-        kappa = smooth_medium(n, 32.0, seed=2)
+        sigma = 32.0
+        kappa = smooth_medium(n, sigma, seed=2)
         b = point_sources(n, 32, seed=3)
         levels, m = 5, 20
     else:
         raise ValueError(f"unknown workload {name!r}")
     return dict(n=n, kappa=kappa, gamma=sponge_gamma(n), omega=omega_for_ppw(n),
-                b=b, levels=levels, m=m, tol=1e-7)
+                b=b, levels=levels, m=m, tol=1e-7, sigma=sigma)

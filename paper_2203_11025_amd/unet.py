@@ -8,7 +8,7 @@ import torch
 
 from .helm import HelmError, _check, _dev, _stream, lib as _helm_lib
 
-EXPORTS = ["unet_create", "unet_destroy", "unet_num_params", "unet_num_buffers",
+EXPORTS = ["unet_create", "unet_destroy", "unet_num_params", "unet_num_buffers", "unet_init",
            "unet_set_params", "unet_get_params", "unet_forward", "unet_infer",
            "unet_loss_grad", "unet_train_step", "unet_pair_encode", "unet_pair_loss_grad",
            "unet_pair_train_step"]
@@ -45,6 +45,8 @@ def lib():
         L.unet_num_params.restype = C.c_longlong
         L.unet_num_buffers.argtypes = [vp]
         L.unet_num_buffers.restype = C.c_longlong
+        L.unet_init.argtypes = [vp, C.c_ulonglong, vp]
+        L.unet_init.restype = ip
         L.unet_set_params.argtypes = [vp, vp, vp, vp]
         L.unet_set_params.restype = ip
         L.unet_get_params.argtypes = [vp, vp, vp, vp]
@@ -101,6 +103,10 @@ class UNet:
             self.close()
         except Exception:
             pass
+
+    def init(self, seed, stream=None):
+        """Seeded Kaiming-normal initial parameters (in the library)."""
+        _check(lib().unet_init(self._h, seed, _stream(stream)), "unet_init")
 
     def set_params(self, params, buffers=None, stream=None):
         if params.numel() != self.nparams:
@@ -194,3 +200,28 @@ def pair_train_step(encoder, solver, r, e, kappa_c, lr=1e-3, beta1=0.9, beta2=0.
     _check(lib().unet_pair_train_step(encoder.ptr, solver.ptr, C.byref(bt), C.byref(o), C.byref(loss),
                                       _stream(stream)), "unet_pair_train_step")
     return loss.value
+
+
+def save(path, **nets):
+    """Write the FP32 parameters and BN buffers of named networks to a
+    safetensors file (keys <name>.params, <name>.buffers, <name>.widths)."""
+    from safetensors.torch import save_file
+
+    out = {}
+    for name, net in nets.items():
+        p, b = net.get_params()
+        out[f"{name}.params"] = p.cpu()
+        out[f"{name}.buffers"] = b.cpu()
+        out[f"{name}.widths"] = torch.tensor(net.widths, dtype=torch.int32)
+    save_file(out, path)
+
+
+def load(path, **nets):
+    """Read parameters written by save() into networks of the same shape."""
+    from safetensors.torch import load_file
+
+    d = load_file(path)
+    for name, net in nets.items():
+        if tuple(d[f"{name}.widths"].tolist()) != net.widths:
+            raise HelmError(f"{path}: widths of {name} differ")
+        net.set_params(d[f"{name}.params"], d[f"{name}.buffers"])
