@@ -47,13 +47,20 @@ __device__ __forceinline__ void st8(bf16 *p, const f8 &r)
 }
 
 // ------------------------------------------------------------------ conv fwd
-// Block: 4 wavefronts; tile TH = 4 MF rows x 16 columns of pixels and
-// CO = 16 NF output channels.  Wavefront w owns pixel rows w MF .. w MF +
-// MF - 1 (one 16-pixel M fragment per row) and all NF channel fragments.
-// K loop: 32-channel chunks of the concatenated input; per chunk the input
-// halo tile and the chunk's weights for all 9 taps are staged in LDS.
+// Implicit GEMM, computed transposed: D[co][pixel] = sum_k W[co][k] X[k][pixel]
+// with K = 9 taps x input channels, so that each lane of an MFMA result holds
+// four consecutive output channels of one pixel (one 8- or 16-byte store).
+// A workgroup (4 wavefronts) owns CO = 16 NF output channels and walks a
+// list of pixel tiles (TH = 4 MF rows x 16 columns each); wavefront w owns
+// rows w MF .. w MF + MF - 1 of a tile (one 16-pixel fragment per row) and
+// all NF channel fragments.  The work is a sequence of stages (tile,
+// 32-channel chunk of the concatenated input).  While the MFMAs of one stage
+// run from LDS, the next stage's input halo (and its weights, when they
+// change) are loaded into registers; they go to LDS after a barrier.  With a
+// single chunk the weights stay in LDS for every tile.  For each kx the
+// MF + 2 halo rows a wavefront touches are read once and serve all three ky.
 template <int MF, int NF>
-__global__ __launch_bounds__(256) void k_conv3x3(Srcs in, int H, int W,
+__global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B, int H, int W,
                                                  const bf16 *__restrict__ Wt, int Cout, int mode,
                                                  float *__restrict__ out32,
                                                  bf16 *__restrict__ out16,
@@ -64,89 +71,196 @@ __global__ __launch_bounds__(256) void k_conv3x3(Srcs in, int H, int W,
     constexpr int PS = 40;           // LDS halves per pixel: 32 channels + pad
     constexpr int CO = 16 * NF;
     constexpr int WS = 9 * 32 + 8;   // LDS halves per output channel row
+    constexpr int NH = (HY * HX * 4 + 255) / 256;  // halo 16-byte pieces per thread
+    constexpr int NW = (CO * 36 + 255) / 256;      // weight 16-byte pieces per thread
     __shared__ __attribute__((aligned(16))) bf16 sx[HY * HX * PS];
     __shared__ __attribute__((aligned(16))) bf16 sw[CO * WS];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int ncob = (Cout + CO - 1) / CO;
-    const int b = blockIdx.z / ncob, co0 = (blockIdx.z % ncob) * CO;
-    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
-    f32x4 acc[MF][NF];
-#pragma unroll
-    for (int i = 0; i < MF; ++i)
-#pragma unroll
-        for (int j = 0; j < NF; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int co0 = blockIdx.y * CO;
     const int nch = in.Ctot / 32;
-    for (int ch = 0; ch < nch; ++ch) {
+    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
+    const int ntiles = B * tiles_x * tiles_y;
+    const int gx = gridDim.x;
+    // this workgroup's tiles: blockIdx.x, blockIdx.x + gx, ...
+    const int my_tiles = ntiles > (int)blockIdx.x ? (ntiles - 1 - blockIdx.x) / gx + 1 : 0;
+    const int nstage = my_tiles * nch;
+    if (nstage == 0) return;
+    // tile coordinates advance by gx tiles: (dtx, dty, db) with carries
+    const int dtx = gx % tiles_x, dty = (gx / tiles_x) % tiles_y, db = gx / (tiles_x * tiles_y);
+    auto advance = [&](int &tx, int &ty, int &b) {
+        tx += dtx;
+        if (tx >= tiles_x) {
+            tx -= tiles_x;
+            ++ty;
+        }
+        ty += dty;
+        if (ty >= tiles_y) {
+            ty -= tiles_y;
+            ++b;
+        }
+        b += db;
+    };
+
+    uint4 hreg[NH], wreg[NW];
+    auto load_stage = [&](int tx, int ty, int b, int ch, bool with_w) {
+        const int x0 = tx * TW - 1, y0 = ty * TH - 1;
         int coff = ch * 32, s = 0;
         while (s < in.n - 1 && coff >= in.s[s].C) {
             coff -= in.s[s].C;
             ++s;
         }
-        const bf16 *src = in.s[s].p;
         const int Cs = in.s[s].C;
-        const int bsrc = in.s[s].shared ? 0 : b;
-        for (int idx = tid; idx < HY * HX * 4; idx += 256) {
-            int seg = idx & 3, pix = idx >> 2;
-            int ty = pix / HX, tx = pix - ty * HX;
-            int y = y0 + ty - 1, x = x0 + tx - 1;
-            uint4 v = {0u, 0u, 0u, 0u};
-            if (y >= 0 && y < H && x >= 0 && x < W)
-                v = *reinterpret_cast<const uint4 *>(src + (((size_t)bsrc * H + y) * W + x) * Cs +
-                                                     coff + seg * 8);
-            *reinterpret_cast<uint4 *>(&sx[pix * PS + seg * 8]) = v;
-        }
-        for (int idx = tid; idx < CO * 36; idx += 256) {
-            int seg = idx & 3, r = idx >> 2;
-            int co = r / 9, tap = r - co * 9;
-            uint4 v = {0u, 0u, 0u, 0u};
-            if (co0 + co < Cout)
-                v = *reinterpret_cast<const uint4 *>(Wt + ((size_t)(co0 + co) * 9 + tap) * in.Ctot +
-                                                     ch * 32 + seg * 8);
-            *reinterpret_cast<uint4 *>(&sw[co * WS + tap * 32 + seg * 8]) = v;
-        }
-        __syncthreads();
+        const bf16 *src = in.s[s].p + ((size_t)(in.s[s].shared ? 0 : b) * H * W) * Cs + coff +
+                          (tid & 3) * 8;
+        const bool inside = x0 >= 0 && y0 >= 0 && x0 + HX <= W && y0 + HY <= H;
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int ky = tap / 3, kx = tap - 3 * (tap / 3);
-            bf16x8 a[MF], bw[NF];
+        for (int k = 0; k < NH; ++k) {
+            // this thread's piece: halo pixel (hy, hx), 8-channel segment tid % 4
+            const int idx = tid + 256 * k, pix = idx >> 2, hy = pix / HX;
+            const int y = y0 + hy, x = x0 + pix - hy * HX;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (idx < HY * HX * 4 && (inside || (y >= 0 && y < H && x >= 0 && x < W)))
+                v = *reinterpret_cast<const uint4 *>(src + (size_t)(y * W + x) * Cs);
+            hreg[k] = v;
+        }
+        if (with_w) {
 #pragma unroll
-            for (int mf = 0; mf < MF; ++mf) {
-                int ty = wv * MF + mf, tx = lane & 15;
-                a[mf] = *reinterpret_cast<const bf16x8 *>(
-                    &sx[((ty + ky) * HX + tx + kx) * PS + 8 * (lane >> 4)]);
+            for (int k = 0; k < NW; ++k) {
+                const int idx = tid + 256 * k;
+                const int rr = idx >> 2, co = rr / 9, tap = rr - co * 9;
+                uint4 v = {0u, 0u, 0u, 0u};
+                if (idx < CO * 36 && co0 + co < Cout)
+                    v = *reinterpret_cast<const uint4 *>(Wt + ((size_t)(co0 + co) * 9 + tap) * in.Ctot +
+                                                         ch * 32 + (idx & 3) * 8);
+                wreg[k] = v;
             }
-#pragma unroll
-            for (int nf = 0; nf < NF; ++nf)
-                bw[nf] = *reinterpret_cast<const bf16x8 *>(
-                    &sw[(nf * 16 + (lane & 15)) * WS + tap * 32 + 8 * (lane >> 4)]);
-#pragma unroll
-            for (int mf = 0; mf < MF; ++mf)
-#pragma unroll
-                for (int nf = 0; nf < NF; ++nf)
-                    acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mf], bw[nf], acc[mf][nf],
-                                                                          0, 0, 0);
         }
-        __syncthreads();
-    }
+    };
+    auto store_stage = [&](bool with_w) {
 #pragma unroll
-    for (int mf = 0; mf < MF; ++mf)
+        for (int k = 0; k < NH; ++k) {
+            const int idx = tid + 256 * k;
+            if (idx < HY * HX * 4)
+                *reinterpret_cast<uint4 *>(&sx[(idx >> 2) * PS + (idx & 3) * 8]) = hreg[k];
+        }
+        if (with_w) {
 #pragma unroll
-        for (int nf = 0; nf < NF; ++nf)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int y = y0 + wv * MF + mf, x = x0 + 4 * (lane >> 4) + q;
-                const int co = co0 + nf * 16 + (lane & 15);
-                if (y < H && x < W && co < Cout) {
-                    const size_t o = (((size_t)b * H + y) * W + x) * Cout + co;
-                    float v = acc[mf][nf][q];
-                    if (mode == 0) {
-                        out32[o] = v;
-                    } else {
-                        float z = v * scale[co] + shift[co];
-                        out16[o] = (bf16)(z > 0.f ? z : slope * z);
-                    }
+            for (int k = 0; k < NW; ++k) {
+                const int idx = tid + 256 * k;
+                if (idx < CO * 36) {
+                    const int rr = idx >> 2, co = rr / 9, tap = rr - co * 9;
+                    *reinterpret_cast<uint4 *>(&sw[co * WS + tap * 32 + (idx & 3) * 8]) = wreg[k];
                 }
             }
+        }
+    };
+
+    f32x4 acc[MF][NF];
+#pragma unroll
+    for (int i = 0; i < MF; ++i)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // current tile and the tile of the next stage to load
+    int tx = blockIdx.x % tiles_x, ty = (blockIdx.x / tiles_x) % tiles_y, b = blockIdx.x / (tiles_x * tiles_y);
+    int ntx = tx, nty = ty, nbb = b, nchk = 0;
+    load_stage(ntx, nty, nbb, 0, true);
+    store_stage(true);
+    __syncthreads();
+    const bool reload_w = nch > 1;
+    for (int st = 0; st < nstage; ++st) {
+        const bool more = st + 1 < nstage;
+        if (more) {
+            if (++nchk == nch) {
+                nchk = 0;
+                advance(ntx, nty, nbb);
+            }
+            load_stage(ntx, nty, nbb, nchk, reload_w);
+        }
+        // rows in groups of RG pixel fragments (RG + 2 halo rows live at once)
+        constexpr int RG = MF > 4 ? MF / 2 : MF;
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+#pragma unroll
+            for (int g = 0; g < MF; g += RG) {
+                bf16x8 a[RG + 2];
+#pragma unroll
+                for (int r = 0; r < RG + 2; ++r)
+                    a[r] = *reinterpret_cast<const bf16x8 *>(
+                        &sx[((wv * MF + g + r) * HX + (lane & 15) + kx) * PS + 8 * (lane >> 4)]);
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky) {
+                    const int tap = ky * 3 + kx;
+                    bf16x8 bw[NF];
+#pragma unroll
+                    for (int nf = 0; nf < NF; ++nf)
+                        bw[nf] = *reinterpret_cast<const bf16x8 *>(
+                            &sw[(nf * 16 + (lane & 15)) * WS + tap * 32 + 8 * (lane >> 4)]);
+#pragma unroll
+                    for (int mf = 0; mf < RG; ++mf)
+#pragma unroll
+                        for (int nf = 0; nf < NF; ++nf)
+                            acc[g + mf][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                bw[nf], a[mf + ky], acc[g + mf][nf], 0, 0, 0);
+                }
+                // keep the next group's LDS reads after these MFMAs (bounds
+                // the live fragments)
+                if (MF > 4) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if (st % nch == nch - 1) {
+            // the tile is complete: lane (l % 16, l / 16) holds pixel x0 + l % 16
+            // of each row and channels 4 (l / 16) .. + 3 of each fragment
+            const int x = tx * TW + (lane & 15);
+            const bool full_co = co0 + CO <= Cout;
+            // folded BN of the four output channels each lane stores (Cout is
+            // a multiple of 32, so the four are in range together)
+            float4 sc[NF], sh[NF];
+#pragma unroll
+            for (int nf = 0; nf < NF; ++nf) {
+                const int co = co0 + nf * 16 + 4 * (lane >> 4);
+                sc[nf] = make_float4(0.f, 0.f, 0.f, 0.f);
+                sh[nf] = sc[nf];
+                if (mode == 1 && co < Cout) {
+                    sc[nf] = *reinterpret_cast<const float4 *>(scale + co);
+                    sh[nf] = *reinterpret_cast<const float4 *>(shift + co);
+                }
+            }
+#pragma unroll
+            for (int mf = 0; mf < MF; ++mf) {
+                const int y = ty * TH + wv * MF + mf;
+                const bool pix_ok = y < H && x < W;
+                const size_t base = (((size_t)b * H + y) * W + x) * Cout + co0 + 4 * (lane >> 4);
+#pragma unroll
+                for (int nf = 0; nf < NF; ++nf) {
+                    if (pix_ok && (full_co || co0 + nf * 16 + 4 * (lane >> 4) < Cout)) {
+                        const f32x4 v = acc[mf][nf];
+                        if (mode == 0) {
+                            *reinterpret_cast<float4 *>(out32 + base + nf * 16) =
+                                make_float4(v[0], v[1], v[2], v[3]);
+                        } else {
+                            float z0 = v[0] * sc[nf].x + sh[nf].x, z1 = v[1] * sc[nf].y + sh[nf].y;
+                            float z2 = v[2] * sc[nf].z + sh[nf].z, z3 = v[3] * sc[nf].w + sh[nf].w;
+                            z0 = z0 > 0.f ? z0 : slope * z0;
+                            z1 = z1 > 0.f ? z1 : slope * z1;
+                            z2 = z2 > 0.f ? z2 : slope * z2;
+                            z3 = z3 > 0.f ? z3 : slope * z3;
+                            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                            bf16x4 o = {(bf16)z0, (bf16)z1, (bf16)z2, (bf16)z3};
+                            *reinterpret_cast<bf16x4 *>(out16 + base + nf * 16) = o;
+                        }
+                    }
+                    acc[mf][nf] = f32x4{0.f, 0.f, 0.f, 0.f};
+                }
+            }
+            advance(tx, ty, b);
+        }
+        if (more) {
+            __syncthreads();  // every wavefront is done with this stage's LDS
+            store_stage(reload_w);
+            __syncthreads();
+        }
+    }
 }
 
 // ------------------------------------------------------------------ wgrad
@@ -273,29 +387,51 @@ __global__ void k_sum_splits(const float *__restrict__ part, int nsplit, size_t 
 // ------------------------------------------------------------------ BN
 // per-block partial sums (FP64) of y and y^2 per channel; thread t handles
 // channel t % C and pixels t / C + k * (256 / C)
+// Per-block partial sums over pixels of 4-channel groups: thread t owns
+// channel group t % (C / 4) and pixel rows t / (C / 4) + k rs, four rows in
+// flight at a time.  part[blk][c][0..1] = (sum v, sum v^2).
 __global__ __launch_bounds__(256) void k_bn_partial(const float *__restrict__ y, size_t P, int C,
                                                     double *__restrict__ part, int nblk)
 {
-    const int t = threadIdx.x, c = t % C, r0 = t / C, rs = 256 / C;
-    double s1 = 0.0, s2 = 0.0;
-    if (r0 < rs)
-        for (size_t p = (size_t)blockIdx.x * rs + r0; p < P; p += (size_t)nblk * rs) {
-            double v = y[p * C + c];
-            s1 += v;
-            s2 += v * v;
+    const int G4 = C / 4, t = threadIdx.x, cg = t % G4, r0 = t / G4, rs = 256 / G4;
+    double s1[4] = {0.0, 0.0, 0.0, 0.0}, s2[4] = {0.0, 0.0, 0.0, 0.0};
+    if (r0 < rs) {
+        const size_t stride = (size_t)nblk * rs;
+        for (size_t p = (size_t)blockIdx.x * rs + r0; p < P; p += 4 * stride) {
+            float4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const size_t pu = p + u * stride;
+                v[u] = pu < P ? *reinterpret_cast<const float4 *>(y + pu * C + cg * 4)
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float e[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    s1[q] += e[q];
+                    s2[q] += (double)e[q] * e[q];
+                }
+            }
         }
-    __shared__ double sh1[256], sh2[256];
-    sh1[t] = s1;
-    sh2[t] = s2;
+    }
+    __shared__ double sh[2][256][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        sh[0][t][q] = s1[q];
+        sh[1][t][q] = s2[q];
+    }
     __syncthreads();
     if (t < C) {
-        double a = 0.0, q = 0.0;
+        const int g = t / 4, q = t % 4;
+        double a = 0.0, qq = 0.0;
         for (int r = 0; r < rs; ++r) {
-            a += sh1[r * C + t];
-            q += sh2[r * C + t];
+            a += sh[0][r * G4 + g][q];
+            qq += sh[1][r * G4 + g][q];
         }
         part[((size_t)blockIdx.x * C + t) * 2] = a;
-        part[((size_t)blockIdx.x * C + t) * 2 + 1] = q;
+        part[((size_t)blockIdx.x * C + t) * 2 + 1] = qq;
     }
 }
 
@@ -343,34 +479,64 @@ __global__ void k_bn_act_fwd(const float *__restrict__ y, size_t n, int C,
     }
 }
 
-// partial sums of dz and dz * xhat per channel
+// partial sums of dz and dz * xhat per channel (layout as k_bn_partial)
 __global__ __launch_bounds__(256) void k_bn_bwd_partial(
     const float *__restrict__ da, const float *__restrict__ y, size_t P, int C,
     const float *__restrict__ mean, const float *__restrict__ rstd, const float *__restrict__ g,
     const float *__restrict__ bb, float slope, double *__restrict__ part, int nblk)
 {
-    const int t = threadIdx.x, c = t % C, r0 = t / C, rs = 256 / C;
-    double s1 = 0.0, s2 = 0.0;
-    if (r0 < rs)
-        for (size_t p = (size_t)blockIdx.x * rs + r0; p < P; p += (size_t)nblk * rs) {
-            float xh = (y[p * C + c] - mean[c]) * rstd[c];
-            float z = g[c] * xh + bb[c];
-            float dz = da[p * C + c] * (z > 0.f ? 1.f : slope);
-            s1 += dz;
-            s2 += (double)dz * xh;
+    const int G4 = C / 4, t = threadIdx.x, cg = t % G4, r0 = t / G4, rs = 256 / G4;
+    double s1[4] = {0.0, 0.0, 0.0, 0.0}, s2[4] = {0.0, 0.0, 0.0, 0.0};
+    if (r0 < rs) {
+        const float4 mu = *reinterpret_cast<const float4 *>(mean + cg * 4);
+        const float4 rs4 = *reinterpret_cast<const float4 *>(rstd + cg * 4);
+        const float4 g4 = *reinterpret_cast<const float4 *>(g + cg * 4);
+        const float4 b4 = *reinterpret_cast<const float4 *>(bb + cg * 4);
+        const float m_[4] = {mu.x, mu.y, mu.z, mu.w}, r_[4] = {rs4.x, rs4.y, rs4.z, rs4.w};
+        const float g_[4] = {g4.x, g4.y, g4.z, g4.w}, b_[4] = {b4.x, b4.y, b4.z, b4.w};
+        const size_t stride = (size_t)nblk * rs;
+        for (size_t p = (size_t)blockIdx.x * rs + r0; p < P; p += 4 * stride) {
+            float4 yv[4], dv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const size_t pu = p + u * stride;
+                const bool ok = pu < P;
+                yv[u] = ok ? *reinterpret_cast<const float4 *>(y + pu * C + cg * 4)
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+                dv[u] = ok ? *reinterpret_cast<const float4 *>(da + pu * C + cg * 4)
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float ye[4] = {yv[u].x, yv[u].y, yv[u].z, yv[u].w};
+                const float de[4] = {dv[u].x, dv[u].y, dv[u].z, dv[u].w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float xh = (ye[q] - m_[q]) * r_[q];
+                    const float z = g_[q] * xh + b_[q];
+                    const float dz = de[q] * (z > 0.f ? 1.f : slope);
+                    s1[q] += dz;
+                    s2[q] += (double)dz * xh;
+                }
+            }
         }
-    __shared__ double sh1[256], sh2[256];
-    sh1[t] = s1;
-    sh2[t] = s2;
+    }
+    __shared__ double sh[2][256][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        sh[0][t][q] = s1[q];
+        sh[1][t][q] = s2[q];
+    }
     __syncthreads();
     if (t < C) {
-        double a = 0.0, q = 0.0;
+        const int gi = t / 4, q = t % 4;
+        double a = 0.0, qq = 0.0;
         for (int r = 0; r < rs; ++r) {
-            a += sh1[r * C + t];
-            q += sh2[r * C + t];
+            a += sh[0][r * G4 + gi][q];
+            qq += sh[1][r * G4 + gi][q];
         }
         part[((size_t)blockIdx.x * C + t) * 2] = a;
-        part[((size_t)blockIdx.x * C + t) * 2 + 1] = q;
+        part[((size_t)blockIdx.x * C + t) * 2 + 1] = qq;
     }
 }
 
@@ -957,12 +1123,15 @@ inline int grid_for(size_t n, int block = 256, int cap = 8192)
     return (int)g;
 }
 
+// blocks of the BN partial-sum kernels: about 16 rows per thread, at most
+// as many as the 8 MB reduction scratch holds (2 nblk C doubles + C floats)
 inline int red_blocks(size_t P, int C)
 {
-    size_t rows = 256 / C;
-    size_t b = (P + rows * 64 - 1) / (rows * 64);
+    size_t rows = 256 / (C / 4);
+    size_t b = (P + rows * 16 - 1) / (rows * 16);
+    size_t cap = std::min<size_t>(4096, ((size_t)1 << 19) / C - 1);
     if (b < 1) b = 1;
-    if (b > 512) b = 512;
+    if (b > cap) b = cap;
     return (int)b;
 }
 
@@ -974,24 +1143,30 @@ void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
                     float *out32, bf16 *out16, const float *scale, const float *shift,
                     float slope, hipStream_t s)
 {
-    // wide tiles for large images, narrow channel blocks for 32-channel layers
-    const bool tall = H >= 64;
+    // 16-row tiles for large images, 8-row tiles for small ones; narrow
+    // channel blocks for 32-channel layers
+    const int MF = H >= 64 ? 4 : 2;
     const int NF = Cout >= 64 ? 4 : 2;
     const int CO = 16 * NF;
-    const int TH = tall ? 16 : 8;
-    dim3 grid((W + 15) / 16, (H + TH - 1) / TH, B * ((Cout + CO - 1) / CO));
-    if (tall && NF == 4)
-        hipLaunchKernelGGL((k_conv3x3<4, 4>), grid, dim3(256), 0, s, in, H, W, Wt, Cout, mode, out32,
-                           out16, scale, shift, slope);
-    else if (tall)
-        hipLaunchKernelGGL((k_conv3x3<4, 2>), grid, dim3(256), 0, s, in, H, W, Wt, Cout, mode, out32,
-                           out16, scale, shift, slope);
+    const int TH = 4 * MF;
+    const int ncob = (Cout + CO - 1) / CO;
+    const long long ntiles = (long long)B * ((H + TH - 1) / TH) * ((W + 15) / 16);
+    // about eight workgroups per compute unit in total, each walking
+    // ntiles / gridDim.x tiles
+    const long long want = std::max<long long>(1, 2048 / ncob);
+    dim3 grid((unsigned)std::min<long long>(ntiles, want), ncob);
+#define CONV_LAUNCH(mf, nf)                                                                         \
+    hipLaunchKernelGGL((k_conv3x3<mf, nf>), grid, dim3(256), 0, s, in, B, H, W, Wt, Cout, mode, out32, \
+                       out16, scale, shift, slope)
+    if (MF == 4 && NF == 4)
+        CONV_LAUNCH(4, 4);
+    else if (MF == 4)
+        CONV_LAUNCH(4, 2);
     else if (NF == 4)
-        hipLaunchKernelGGL((k_conv3x3<2, 4>), grid, dim3(256), 0, s, in, H, W, Wt, Cout, mode, out32,
-                           out16, scale, shift, slope);
+        CONV_LAUNCH(2, 4);
     else
-        hipLaunchKernelGGL((k_conv3x3<2, 2>), grid, dim3(256), 0, s, in, H, W, Wt, Cout, mode, out32,
-                           out16, scale, shift, slope);
+        CONV_LAUNCH(2, 2);
+#undef CONV_LAUNCH
 }
 
 static int wgrad_nsplit(int B, int H, int W, int Cout, int Ctot)

@@ -140,8 +140,9 @@ def test_loss_and_gradient_parity(N, emulate):
         layer = k.split(".")[0]
         depth = 0 if layer == "head" else len(names) - names.index(layer)
         # emulated: what remains is bf16 rounding decisions that flip under a
-        # different FP32 accumulation order, amplified by BN backward
-        tol = 0.12 if emulate else 0.025 * (1 + depth)
+        # different FP32 accumulation order, amplified by BN backward; BN bias
+        # gradients (batch sums of dy) cancel most, hence the floor
+        tol = 0.12 if emulate else 0.03 + 0.025 * (1 + depth)
         ctol = 5e-3 if emulate else 2.5e-3 * (1 + depth)
         if r_ > tol or c < 1 - ctol:
             bad.append((k, r_, c))
