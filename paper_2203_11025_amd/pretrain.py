@@ -1,0 +1,112 @@
+"""Pretraining of the encoder-solver pair (section 3.4 with the encoder of
+section 3.3) on triples the method generates (eq. 3.8-3.9) from many smooth
+random media, all in the library's kernels.
+
+    python -m paper_2203_11025_amd.pretrain --minutes 15 --out PATH
+
+Media: n^2 grids (default 512, network on 256^2), slowness from seeded white
+noise smoothed by a Gaussian of sigma n/32 cells mapped to [0.25, 1], seeds
+10000 + i; 10 points per wavelength; the quadratic sponge.  Each Adam step
+(lr 1e-3, batch 16) takes `per_medium` samples from consecutive media.  The
+weights are saved every `--save-every` seconds and at the end; a short
+evaluation compares FGMRES iterations of M_VU and plain SL on a held-out
+medium.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import helm, inputs, train, unet
+
+DEFAULT_OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                           "pair_base.safetensors")
+
+
+def make_medium(n, seed, dev):
+    kap = inputs.smooth_medium(n, n / 32.0, seed=seed)
+    gam = inputs.sponge_gamma(n)
+    levels = max(2, int(np.log2(n // 64)) + 1)  # coarsest 64^2
+    return helm.Handle(torch.from_numpy(kap).to(dev), torch.from_numpy(gam).to(dev),
+                       inputs.omega_for_ppw(n), levels=levels)
+
+
+def evaluate(enc, sol, n, seed, nrhs, dev):
+    """Mean FGMRES(20) iterations to 1e-7: M_VU with the pair, plain SL."""
+    h = make_medium(n, seed, dev)
+    b = torch.from_numpy(inputs.point_sources(n, nrhs, seed=seed + 1)).to(dev)
+    unet.pair_encode(enc, sol, h.coarse_slowness())
+    _, st_net, _ = helm.fgmres_solve([h], [b], m=20, tol=1e-7, prec="unet_defl", net=sol)
+    _, st_sl, _ = helm.fgmres_solve([h], [b], m=20, tol=1e-7)
+    return (float(np.mean([s["iterations"] for s in st_net])),
+            float(np.mean([s["iterations"] for s in st_sl])))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--media", type=int, default=32)
+    ap.add_argument("--minutes", type=float, default=15.0)
+    ap.add_argument("--max-steps", type=int, default=10 ** 9)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--per-medium", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--resume", default=None)
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--save-every", type=float, default=120.0)
+    ap.add_argument("--log-every", type=int, default=500)
+    a = ap.parse_args(argv)
+    dev = torch.device("cuda:0")
+    t_start = time.perf_counter()
+    handles = [make_medium(a.n, 10000 + i, dev) for i in range(a.media)]
+    torch.cuda.synchronize()
+    print(f"[pretrain] {a.media} media of {a.n}^2 ready ({time.perf_counter() - t_start:.1f} s)", flush=True)
+    enc = unet.UNet(head=False)
+    sol = unet.UNet(context=True)
+    if a.resume:
+        unet.load(a.resume, encoder=enc, solver=sol)
+    else:
+        enc.init(a.seed)
+        sol.init(a.seed + 1)
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+
+    def save():
+        tmp = a.out + ".tmp"
+        unet.save(tmp, encoder=enc, solver=sol)
+        os.replace(tmp, a.out)
+
+    budget = a.minutes * 60.0
+    t0 = time.perf_counter()
+    last_save = t0
+    step, chunk, hist = 0, 200, []
+    while step < a.max_steps and time.perf_counter() - t0 < budget:
+        k = min(chunk, a.max_steps - step)
+        losses = train.train_pair(enc, sol, handles, steps=k, batch=a.batch, lr=a.lr,
+                                  seed=a.seed * 100003 + step, per_medium=a.per_medium)
+        # rotate the starting medium so consecutive chunks see every medium
+        handles = handles[k * a.batch // a.per_medium % len(handles):] + \
+            handles[:k * a.batch // a.per_medium % len(handles)]
+        step += len(losses)
+        hist.extend(losses)
+        if step % a.log_every < chunk:
+            print(f"[pretrain] step {step} loss {np.mean(hist[-chunk:]):.4e} "
+                  f"({time.perf_counter() - t0:.0f} s)", flush=True)
+        if time.perf_counter() - last_save > a.save_every:
+            save()
+            last_save = time.perf_counter()
+    save()
+    torch.cuda.synchronize()
+    print(f"[pretrain] {step} steps in {time.perf_counter() - t0:.0f} s; saved {a.out}", flush=True)
+    it_net, it_sl = evaluate(enc, sol, a.n, 90000, 4, dev)
+    print(f"[pretrain] held-out {a.n}^2 medium: M_VU {it_net:.1f} iterations, SL {it_sl:.1f}", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
