@@ -45,8 +45,17 @@ def parse():
     ap.add_argument("--prec", default="unet_defl", choices=["unet_defl", "unet_cgc"])
     ap.add_argument("--retrain", type=int, default=200, help="mini-retraining Adam steps")
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
-    ap.add_argument("--stall-ratio", type=float, default=0.95)
+    ap.add_argument("--stall-ratio", type=float, default=0.0,
+                    help="fall back to M_V on stalls (0 = never; the uneven-batch setting uses 0.95)")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay captured restart cycles (the timed region then cannot time the "
+                         "dominant kernel family with events, so the roofline object is omitted)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the built-in convolution launch shapes instead of tuning them")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device copy of this many MiB (a reference "
+                         "kernel of known traffic for hardware-counter runs)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the CPU oracle sample")
     return ap.parse_args()
@@ -125,6 +134,12 @@ def main():
 
     P = inputs.config_problem(a.workload)
     dev = torch.device("cuda:0")
+    if a.copy_probe:
+        src = torch.ones(a.copy_probe << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        sync()
+        del src, dst
     t_setup = time.perf_counter()
     kap = torch.from_numpy(P["kappa"]).to(dev)
     gam = torch.from_numpy(P["gamma"]).to(dev)
@@ -135,6 +150,8 @@ def main():
     t_setup = time.perf_counter() - t_setup
     log(f"setup n={P['n']} levels={h.levels} nrhs={nrhs} ({t_setup:.2f} s)")
 
+    if not a.no_autotune:
+        helm.autotune(1)
     enc = unet.UNet(head=False)
     sol = unet.UNet(context=True)
     pretrained = os.path.exists(a.weights)
@@ -156,13 +173,15 @@ def main():
     kc = h.coarse_slowness()
     x = torch.empty(b.shape, dtype=torch.complex128, device=dev)
 
+    graph = a.graph
+
     def solve_net():
         unet.pair_encode(enc, sol, kc)
         return helm.fgmres_solve([h], [b], m=P["m"], tol=P["tol"], prec=a.prec, net=sol,
-                                 stall_ratio=a.stall_ratio, xs=[x])
+                                 stall_ratio=a.stall_ratio, xs=[x], graph=graph)
 
     def solve_sl():
-        return helm.fgmres_solve([h], [b], m=P["m"], tol=P["tol"], xs=[x])
+        return helm.fgmres_solve([h], [b], m=P["m"], tol=P["tol"], xs=[x], graph=graph)
 
     # warmup; the first U-Net + SL pass also profiles every kernel family to
     # find the dominant one
@@ -182,14 +201,16 @@ def main():
     dominant = max(fam, key=lambda f: fam[f][0])
 
     # timed: U-Net + SL, the dominant kernel family timed live with HIP events
-    helm.profile_start(dominant)
+    # (not with graph replay: the events cannot be re-recorded inside a graph)
+    if not graph:
+        helm.profile_start(dominant)
     sync()
     t0 = time.perf_counter()
     for _ in range(a.steps):
         _, st_net, rc_net = solve_net()
     sync()
     dt_net = time.perf_counter() - t0
-    d_ms, d_launches, d_work = helm.profile_read(dominant)
+    d_ms, d_launches, d_work = helm.profile_read(dominant) if not graph else (0.0, 0, 0.0)
     helm.profile_stop()
     its_net = [s["iterations"] for s in st_net]
     relres_net = max(s["true_relres"] for s in st_net)
@@ -224,7 +245,7 @@ def main():
     value = ms_per_step / 1000.0 / nrhs
     sl_value = dt_sl / a.steps / nrhs
     unit_is_flops = dominant in ("conv", "wgrad")
-    avg_s = d_ms / 1e3 / max(d_launches, 1)
+    avg_s = max(d_ms / 1e3 / max(d_launches, 1), 1e-12)
     if unit_is_flops:
         achieved = d_work / max(d_launches, 1) / avg_s / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
@@ -255,7 +276,7 @@ def main():
                         f"{a.prec} with the encoder-solver pair; SL = V(1,1) {h.levels} levels",
             "n": P["n"], "nrhs": nrhs, "prec": a.prec,
             "network": "pretrained" if pretrained else "seeded init",
-            "retrain_steps": a.retrain,
+            "retrain_steps": a.retrain, "graph": graph, "autotune": not a.no_autotune,
         },
         "unet_sl": {"s_per_rhs": value, "iterations_mean": float(np.mean(its_net)),
                     "iterations_max": int(max(its_net)), "true_relres_max": relres_net,
@@ -269,7 +290,7 @@ def main():
                     "loss_last": losses[-1] if losses else None},
         "value_amortized": value + (t_retrain + t_setup) / nrhs,
         "setup_s": t_setup,
-        "roofline": roof,
+        "roofline": roof if d_launches else None,
         "sweeps": sweeps,
     }
     if not a.no_cpu_baseline:

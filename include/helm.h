@@ -113,6 +113,11 @@ typedef struct {
     void *net;           /* unet_net* for the U-Net preconditioners, else NULL   */
     double stall_ratio;  /* fall back to M_V when |g_{j+1}|/|g_j| exceeds this on
                             3 consecutive steps (0 = never); default 0           */
+    int graph;           /* 1: capture each restart cycle (m Arnoldi steps with
+                            their preconditioner applications, the update of x
+                            and the true residual) into a HIP graph once and
+                            replay it; default 0.  Ignored while the profiling
+                            hook is active.                                      */
 } helm_fgmres_opts;
 
 typedef struct {
@@ -138,6 +143,12 @@ typedef struct {
  * the Hessenberg least-squares problem, the solution and the true residual
  * b - A x that starts each cycle are FP64.  The iteration stops when that
  * true relative residual is <= tol.  The host synchronises once per cycle.
+ * Problems with distinct handles run concurrently on internal streams (one
+ * host thread each, up to 8), which fills the GPU when the batch holds many
+ * small or uneven grids; the call waits on `stream` first and `stream` waits
+ * on all of them before the call returns.  Problems are solved one after
+ * another when a network preconditioner is used (the network's workspace is
+ * shared) or while the profiling hook is active.
  * Returns HELM_NOT_CONVERGED if some right-hand side reached maxit first.
  */
 int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int *rhs_per_prob,
@@ -185,6 +196,18 @@ int helm_coarse_slowness(helm_handle *h, float *kc, void *stream);
 int helm_profile_start(unsigned family_mask);
 int helm_profile_read(int family, double *total_ms, long long *launches, double *work);
 int helm_profile_stop(void);
+
+/*
+ * Launch-shape autotuner of the network convolutions.  With enable = 1, the
+ * first convolution of each new shape (batch, height, width, input and output
+ * channels, epilogue) times the candidate tile heights and workgroup counts
+ * with HIP events on its stream and keeps the fastest for later calls of that
+ * shape (calls under graph capture use the table or the built-in heuristic).
+ * 0 returns to the heuristic, keeping the table; -1 also clears it.
+ * Returns the previous setting.  helm_autotune_entries: shapes tuned so far.
+ */
+int helm_autotune(int enable);
+int helm_autotune_entries(void);
 
 /* Thread-local text describing the last error of this thread ("" if none). */
 const char *helm_last_error(void);

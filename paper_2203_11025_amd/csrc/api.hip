@@ -150,6 +150,7 @@ int ensure_vcycle_ws(helm_handle *h, int nb)
     h->wf.assign(h->levels, nullptr);
     h->wv.assign(h->levels, nullptr);
     h->ws_nb = 0;
+    ++h->ws_gen;
     for (int l = 1; l < h->levels; ++l) {
         size_t Nl = (size_t)h->lv[l].n * h->lv[l].n;
         if (dmalloc(&h->wf[l], Nl * nb) || dmalloc(&h->wv[l], Nl * nb)) return HELM_E_NOMEM;

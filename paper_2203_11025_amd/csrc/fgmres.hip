@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "handle.h"
@@ -40,6 +42,16 @@ struct FgWork {
     int *d_net = nullptr;     // device copy of h_net
     float2 *t1 = nullptr, *t2 = nullptr;  // network-preconditioner scratch
     FgState S{};
+    // captured restart cycles, replayed while the key matches
+    struct Graph {
+        const void *b = nullptr, *x = nullptr, *net = nullptr;
+        int nb = 0, nnet = 0, prec = 0, hgen = 0, ngen = 0;
+        double tol = 0.0, stall = 0.0;
+        int maxit = 0;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<Graph> graphs;
+    hipStream_t cap = nullptr;  // capture stream (capture needs a non-null stream)
 };
 
 __device__ __forceinline__ double2 dmul(double2 a, double2 b)
@@ -139,6 +151,8 @@ void work_free(FgWork *w)
     hipFree(w->t1);
     hipFree(w->t2);
     hipFree(w->d_net);
+    for (auto &g : w->graphs) hipGraphExecDestroy(g.exec);
+    if (w->cap) hipStreamDestroy(w->cap);
     if (w->h_net) hipHostFree(w->h_net);
     if (w->h_fb) hipHostFree(w->h_fb);
     if (w->h_i) hipHostFree(w->h_i);
@@ -266,10 +280,69 @@ int apply_net_prec(helm_handle *h, unet_net *net, int prec, FgWork *w, const FgS
     return vcycle(h, v, vs, z, zs, nb, S.mask_sl, s);
 }
 
+// Replays the captured restart cycle for this key, capturing it first.  The
+// workspaces the cycle touches are allocated before capture.
+template <class F>
+int replay_cycle(FgWork *w, const FgState &S, int nnet, const float2 *b, const double2 *x, int prec,
+                 unet_net *net, int hgen, hipStream_t s, F &&cycle)
+{
+    const int ngen = net ? net->gen : 0;
+    FgWork::Graph *g = nullptr;
+    for (auto &e : w->graphs)
+        if (e.b == b && e.x == x && e.net == net && e.nb == S.nb && e.nnet == nnet && e.prec == prec &&
+            e.tol == S.tol && e.stall == S.stall_ratio && e.maxit == S.maxit && e.hgen == hgen &&
+            e.ngen == ngen)
+            g = &e;
+    if (!g) {
+        if (!w->cap && hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking) != hipSuccess) {
+            set_error("helm_fgmres_solve: creating the capture stream failed");
+            return HELM_E_HIP;
+        }
+        if (w->graphs.size() >= 8) {  // bounded cache
+            hipGraphExecDestroy(w->graphs.front().exec);
+            w->graphs.erase(w->graphs.begin());
+        }
+        hipGraph_t graph = nullptr;
+        HELM_HIP_CHECK(hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal));
+        int rc = cycle(w->cap);
+        hipError_t e = hipStreamEndCapture(w->cap, &graph);
+        if (rc) {
+            if (graph) hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) {
+            set_error(std::string("helm_fgmres_solve: graph capture failed: ") + hipGetErrorString(e));
+            return HELM_E_HIP;
+        }
+        FgWork::Graph ng;
+        ng.b = b;
+        ng.x = x;
+        ng.net = net;
+        ng.nb = S.nb;
+        ng.nnet = nnet;
+        ng.prec = prec;
+        ng.tol = S.tol;
+        ng.stall = S.stall_ratio;
+        ng.maxit = S.maxit;
+        ng.hgen = hgen;
+        ng.ngen = ngen;
+        e = hipGraphInstantiate(&ng.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            set_error(std::string("helm_fgmres_solve: graph instantiation failed: ") + hipGetErrorString(e));
+            return HELM_E_HIP;
+        }
+        w->graphs.push_back(ng);
+        g = &w->graphs.back();
+    }
+    HELM_HIP_CHECK(hipGraphLaunch(g->exec, s));
+    return HELM_OK;
+}
+
 // One problem (medium) with nb right-hand sides.
 int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, double tol,
                   int maxit, int prec, unet_net *net, double stall_ratio,
-                  helm_fgmres_stats *stats, hipStream_t s)
+                  helm_fgmres_stats *stats, hipStream_t s, bool use_graph)
 {
     FgWork *w = nullptr;
     const bool use_net = prec != HELM_PREC_SL;
@@ -294,6 +367,32 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
     launch_true_residual(h->kappa0, h->gamma0, h->n, h->omega, b, N, x, N, w->V, vsb, w->rpartial,
                          nblk, nb, nullptr, s);
     hipLaunchKernelGGL(k_restart, dim3(nb), dim3(256), 0, s, S, w->rpartial, nblk, 1);
+    int nnet = 0;
+    // one restart cycle: m Arnoldi steps, the least-squares update of x and the
+    // true residual that starts the next cycle; kernels only (capturable)
+    auto cycle = [&](hipStream_t cs) -> int {
+        int rc2;
+        for (int j = 0; j < m; ++j) {
+            float2 *vj = w->V + (size_t)j * N, *zj = w->Z + (size_t)j * N;
+            float2 *wj = w->V + (size_t)(j + 1) * N;
+            if (!use_net) {
+                // slot j holds the candidate direction, unnormalised; the V-cycle
+                // reads it scaled by 1 / (its norm)
+                rc2 = vcycle(h, vj, vsb, zj, zsb, nb, S.active, cs, S.scale);
+            } else {
+                rc2 = apply_net_prec(h, net, prec, w, S, vj, vsb, zj, zsb, nb, nnet, cs);
+            }
+            if (rc2) return rc2;
+            launch_apply(L0, 0.f, zj, zsb, wj, vsb, nb, S.active, cs);
+            launch_arnoldi_step(S, w->V, vsb, N, j, w->partial, nblk, cs);
+        }
+        hipLaunchKernelGGL(k_solve_y, dim3(nb), dim3(64), 0, cs, S);
+        launch_xupdate(x, N, w->Z, zsb, N, S.y, MAXV, S.k, nb, S.incycle, cs);
+        launch_true_residual(h->kappa0, h->gamma0, h->n, h->omega, b, N, x, N, w->V, vsb,
+                             w->rpartial, nblk, nb, S.incycle, cs);
+        hipLaunchKernelGGL(k_restart, dim3(nb), dim3(256), 0, cs, S, w->rpartial, nblk, 0);
+        return HELM_OK;
+    };
     for (;;) {
         HELM_HIP_CHECK(hipMemcpyAsync(w->h_d, S.relres, nb * sizeof(double), hipMemcpyDeviceToHost, s));
         HELM_HIP_CHECK(hipMemcpyAsync(w->h_its, S.its, nb * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -308,7 +407,7 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
         }
         if (nact == 0) break;
         prof_set_active(nact);
-        int nnet = 0;
+        nnet = 0;
         if (use_net) {
             // gather the right-hand sides still using the network
             for (int i = 0; i < nb; ++i) w->h_net[nb + i] = -1;
@@ -321,26 +420,16 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
         }
         HELM_HIP_CHECK(hipMemcpyAsync(S.active, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
         HELM_HIP_CHECK(hipMemcpyAsync(S.incycle, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
-        for (int j = 0; j < m; ++j) {
-            float2 *vj = w->V + (size_t)j * N, *zj = w->Z + (size_t)j * N;
-            float2 *wj = w->V + (size_t)(j + 1) * N;
-            if (!use_net) {
-                // slot j holds the candidate direction, unnormalised; the V-cycle
-                // reads it scaled by 1 / (its norm)
-                rc = vcycle(h, vj, vsb, zj, zsb, nb, S.active, s, S.scale);
-                if (rc) return rc;
-            } else {
-                rc = apply_net_prec(h, net, prec, w, S, vj, vsb, zj, zsb, nb, nnet, s);
-                if (rc) return rc;
-            }
-            launch_apply(L0, 0.f, zj, zsb, wj, vsb, nb, S.active, s);
-            launch_arnoldi_step(S, w->V, vsb, N, j, w->partial, nblk, s);
+        if (use_graph) {
+            // everything the cycle touches is allocated before capture
+            if ((rc = ensure_vcycle_ws(h, nb))) return rc;
+            if (use_net && nnet > 0 && (rc = net->ensure_ws(nnet, h->n / 2, h->n / 2, false))) return rc;
+            rc = replay_cycle(w, S, nnet, b, x, prec, net, h->ws_gen, s,
+                              [&](hipStream_t cs) { return cycle(cs); });
+        } else {
+            rc = cycle(s);
         }
-        hipLaunchKernelGGL(k_solve_y, dim3(nb), dim3(64), 0, s, S);
-        launch_xupdate(x, N, w->Z, zsb, N, S.y, MAXV, S.k, nb, S.incycle, s);
-        launch_true_residual(h->kappa0, h->gamma0, h->n, h->omega, b, N, x, N, w->V, vsb,
-                             w->rpartial, nblk, nb, S.incycle, s);
-        hipLaunchKernelGGL(k_restart, dim3(nb), dim3(256), 0, s, S, w->rpartial, nblk, 0);
+        if (rc) return rc;
         for (int i = 0; i < nb; ++i)
             if (w->h_i[i]) restarts[i]++;
         HELM_HIP_CHECK(hipGetLastError());
@@ -386,10 +475,11 @@ extern "C" int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int
         set_error("helm_fgmres_solve: invalid argument");
         return HELM_E_INVALID;
     }
-    int m = 20, maxit = 20000, prec = HELM_PREC_SL;
+    int m = 20, maxit = 20000, prec = HELM_PREC_SL, graph = 0;
     double tol = 1e-7, stall = 0.0;
     unet_net *net = nullptr;
     if (opts) {
+        graph = opts->graph;
         m = opts->m;
         tol = opts->tol;
         maxit = opts->maxit;
@@ -415,23 +505,89 @@ extern "C" int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int
                   "one problem whose medium was encoded with unet_pair_encode (nb = 1)");
         return HELM_E_INVALID;
     }
-    int status = HELM_OK, off = 0;
+    std::vector<int> offs(nprob + 1, 0);
     for (int p = 0; p < nprob; ++p) {
         if (!probs[p] || rhs_per_prob[p] < 0 || (rhs_per_prob[p] > 0 && (!b[p] || !x[p]))) {
             set_error("helm_fgmres_solve: invalid problem entry");
             return HELM_E_INVALID;
         }
-        if (rhs_per_prob[p] == 0) continue;
-        if (net && (probs[p]->n % (1 << net->cfg.levels) || (net->cfg.context && net->ctx_H != probs[p]->n / 2))) {
+        if (rhs_per_prob[p] > 0 && net &&
+            (probs[p]->n % (1 << net->cfg.levels) || (net->cfg.context && net->ctx_H != probs[p]->n / 2))) {
             set_error("helm_fgmres_solve: grid size not divisible by 2^levels of the network");
             return HELM_E_SHAPE;
         }
-        int rc = solve_problem(probs[p], rhs_per_prob[p], (const float2 *)b[p], (double2 *)x[p], m,
-                               tol, maxit, prec, net, stall, stats ? stats + off : nullptr,
-                               (hipStream_t)stream);
-        if (rc < 0) return rc;
-        if (rc == HELM_NOT_CONVERGED) status = HELM_NOT_CONVERGED;
-        off += rhs_per_prob[p];
+        offs[p + 1] = offs[p] + rhs_per_prob[p];
     }
+    hipStream_t s = (hipStream_t)stream;
+    const bool use_graph = graph && !prof_enabled();
+    std::vector<int> rcs(nprob, HELM_OK);
+    std::vector<std::string> errs(nprob);
+    auto run = [&](int p, hipStream_t st) {
+        if (rhs_per_prob[p] == 0) return;
+        rcs[p] = solve_problem(probs[p], rhs_per_prob[p], (const float2 *)b[p], (double2 *)x[p], m, tol,
+                               maxit, prec, net, stall, stats ? stats + offs[p] : nullptr, st, use_graph);
+        if (rcs[p] < 0) errs[p] = helm_last_error();
+    };
+    // group problems by handle: one handle's workspaces serve one solve at a time
+    std::vector<std::vector<int>> groups;
+    for (int p = 0; p < nprob; ++p) {
+        bool placed = false;
+        for (auto &g : groups)
+            if (probs[g[0]] == probs[p]) {
+                g.push_back(p);
+                placed = true;
+                break;
+            }
+        if (!placed) groups.push_back({p});
+    }
+    const int T = (int)std::min<size_t>(8, groups.size());
+    if (T <= 1 || net || prof_enabled()) {
+        for (int p = 0; p < nprob; ++p) {
+            run(p, s);
+            if (rcs[p] < 0) return rcs[p];
+        }
+    } else {
+        std::vector<hipStream_t> st(T, nullptr);
+        std::vector<hipEvent_t> ev(T + 1, nullptr);
+        int rc = HELM_OK;
+        for (int t = 0; t < T && !rc; ++t)
+            if (hipStreamCreateWithFlags(&st[t], hipStreamNonBlocking) != hipSuccess) rc = HELM_E_HIP;
+        for (int t = 0; t <= T && !rc; ++t)
+            if (hipEventCreateWithFlags(&ev[t], hipEventDisableTiming) != hipSuccess) rc = HELM_E_HIP;
+        if (!rc && hipEventRecord(ev[T], s) != hipSuccess) rc = HELM_E_HIP;
+        for (int t = 0; t < T && !rc; ++t)
+            if (hipStreamWaitEvent(st[t], ev[T], 0) != hipSuccess) rc = HELM_E_HIP;
+        if (!rc) {
+            std::vector<std::thread> th;
+            for (int t = 0; t < T; ++t)
+                th.emplace_back([&, t]() {
+                    for (size_t g = t; g < groups.size(); g += T)
+                        for (int p : groups[g]) {
+                            run(p, st[t]);
+                            if (rcs[p] < 0) return;
+                        }
+                });
+            for (auto &t : th) t.join();
+            for (int t = 0; t < T; ++t)
+                if (hipEventRecord(ev[t], st[t]) != hipSuccess || hipStreamWaitEvent(s, ev[t], 0) != hipSuccess)
+                    rc = HELM_E_HIP;
+        }
+        for (auto e : ev)
+            if (e) hipEventDestroy(e);
+        for (auto q : st)
+            if (q) hipStreamDestroy(q);
+        if (rc) {
+            set_error("helm_fgmres_solve: internal stream set-up failed");
+            return rc;
+        }
+        for (int p = 0; p < nprob; ++p)
+            if (rcs[p] < 0) {
+                set_error(errs[p]);
+                return rcs[p];
+            }
+    }
+    int status = HELM_OK;
+    for (int p = 0; p < nprob; ++p)
+        if (rcs[p] == HELM_NOT_CONVERGED) status = HELM_NOT_CONVERGED;
     return status;
 }

@@ -18,6 +18,7 @@ struct helm_handle {
     int Nc = 0;                // coarsest unknowns
     // V-cycle workspace: per level l >= 1, f_l and v_l for `ws_nb` fields
     int ws_nb = 0;
+    int ws_gen = 0;  // bumped on every reallocation (captured graphs hold the pointers)
     std::vector<float2 *> wf, wv;
     // FGMRES workspace (see fgmres.hip)
     void *fg = nullptr;

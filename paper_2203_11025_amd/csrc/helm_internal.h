@@ -19,6 +19,7 @@ void set_error(const std::string &msg);
 void prof_mark(int family, hipStream_t s, bool start, double work_per_rhs = 0.0, int nb = 1,
                bool masked = false);
 void prof_set_active(int nact);
+bool prof_enabled();
 
 #define HELM_HIP_CHECK(call)                                                        \
     do {                                                                            \

@@ -25,6 +25,8 @@ struct Prof {
 Prof g_prof;
 }  // namespace
 
+bool prof_enabled() { return g_prof.mask != 0; }
+
 void prof_set_active(int nact)
 {
     if (!g_prof.mask) return;

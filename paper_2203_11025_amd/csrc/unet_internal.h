@@ -35,6 +35,11 @@ struct Srcs {
 void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout, int mode,
                     float *out32, bf16 *out16, const float *scale, const float *shift,
                     float slope, hipStream_t s);
+// Launch-shape autotuner of launch_conv3x3: enable = 1 tunes each new shape
+// on first use, 0 uses the heuristic, -1 also forgets the table.  Returns
+// the previous setting.
+int conv_autotune(int enable);
+int conv_autotune_entries();
 // Weight gradient: dW[co][tap][ci] = sum_p dy[p][co] * X[p + tap offset][ci],
 // X the concatenated sources; written (not accumulated) as FP32 [Cout][9][Ctot].
 // `part` is scratch of launch_wgrad_scratch(...) floats.

@@ -8,6 +8,9 @@
 //   B (32 x 16): lane l holds col l % 16, the same k range
 //   D (16 x 16): lane l holds col l % 16, rows 4 (l / 16) .. 4 (l / 16) + 3
 #include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
 
 #include "unet_internal.h"
 
@@ -264,122 +267,186 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
 }
 
 // ------------------------------------------------------------------ wgrad
-// dW[co][tap][ci] = sum_p dy[p][co] X[p + tap offset][ci] over a range of
-// K steps (split K).  One workgroup owns a block of up to 64 output and 64
-// input channels for all 9 taps.  A K step is one image-row segment of 32
-// pixels: dy for the segment and X for the three rows around it are staged
-// transposed ([channel][pixel]) in LDS, X as three copies shifted by kx so
-// every MFMA fragment is an aligned 16-byte LDS read.  Wavefront w owns
-// output-channel fragment w % NCF and the taps tg, tg + 4/NCF, ... with
-// tg = w / NCF.
-constexpr int WG_CB = 64, WG_IB = 64, WG_SEG = 32, WG_PAD = 40;
+// dW[co][tap][ci] = sum_p dy[p][co] X[p + tap offset][ci] over a range of K
+// steps (split K).  MFMA operands: A = dy^T (16 output channels x 32
+// pixels), B = X^T (32 pixels x 16 input channels).  A workgroup owns CB =
+// 16 NCF output and IB = 16 NIF input channels for all 9 taps.  A K step is
+// row y of one 32-pixel column strip (b, x0); consecutive steps walk down the
+// strip.  LDS holds dy^T of the row and X^T of rows y-1, y, y+1 in a ring of
+// three slots, each slot as three copies shifted by kx so every fragment is
+// an aligned 16-byte read; a step inside a strip stages one new X row.
+// Staging transposes blocks of 8 pixels x 8 channels in registers and
+// writes 16-byte LDS rows.  Wavefront w owns input-channel fragment w % NIF
+// and the taps tg, tg + 4 / NIF, ... with tg = w / NIF.
+constexpr int WG_SEG = 32, WG_PADP = 40;
 
-template <int NCF>
+// transposes 8 pixels x 8 bf16 channels: p[i] holds channels 0..7 of pixel
+// i; o[q] receives pixels 0..7 of channel q
+__device__ __forceinline__ void transpose8(const uint4 p[8], uint4 o[8])
+{
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {  // channel pair (2m, 2m + 1) sits in dword m
+        uint32_t ev[4], od[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t A = reinterpret_cast<const uint32_t *>(&p[2 * k])[m];
+            const uint32_t Bv = reinterpret_cast<const uint32_t *>(&p[2 * k + 1])[m];
+            ev[k] = (A & 0xFFFFu) | (Bv << 16);
+            od[k] = (A >> 16) | (Bv & 0xFFFF0000u);
+        }
+        o[2 * m] = make_uint4(ev[0], ev[1], ev[2], ev[3]);
+        o[2 * m + 1] = make_uint4(od[0], od[1], od[2], od[3]);
+    }
+}
+
+template <int NCF, int NIF>
 __global__ __launch_bounds__(256) void k_wgrad(Srcs x, const bf16 *__restrict__ dy, int B, int H,
                                                int W, int Cout, int steps_per_split,
                                                float *__restrict__ part)
 {
-    constexpr int TS = 4 / NCF;                 // tap stride between a wave's taps
-    constexpr int NT = (9 + TS - 1) / TS;       // taps per wave (upper bound)
-    __shared__ __attribute__((aligned(16))) bf16 sa[WG_CB * WG_PAD];
-    __shared__ __attribute__((aligned(16))) bf16 sb[3][3][WG_IB * WG_PAD];  // [kx][ky][ci][px]
+    constexpr int CB = 16 * NCF, IB = 16 * NIF;
+    constexpr int TG = 4 / NIF;               // tap stride between a wave's taps
+    constexpr int NT = (9 + TG - 1) / TG;     // taps per wave (upper bound)
+    constexpr int NDY = 4 * (CB / 8);         // dy staging tasks per row
+    constexpr int NXR = 3 * 4 * (IB / 8);     // X staging tasks per row (3 shifted copies)
+    __shared__ __attribute__((aligned(16))) bf16 sa[CB * WG_PADP];
+    __shared__ __attribute__((aligned(16))) bf16 sb[3][3][IB * WG_PADP];  // [slot][kx][ci][px]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int ncb = (Cout + WG_CB - 1) / WG_CB;
+    const int ncb = (Cout + CB - 1) / CB;
     const int cb = blockIdx.y % ncb, ib = blockIdx.y / ncb;
-    const int cf = wv % NCF, tg = wv / NCF;
-    const int nseg_row = (W + WG_SEG - 1) / WG_SEG;
-    const int total_steps = B * H * nseg_row;
+    const int co0 = cb * CB, ci0 = ib * IB;
+    const int fi = wv % NIF, tg = wv / NIF;
+    const int nseg = (W + WG_SEG - 1) / WG_SEG;
+    const int total_steps = B * nseg * H;
     const int s_begin = blockIdx.x * steps_per_split;
     const int s_end = min(total_steps, s_begin + steps_per_split);
-    f32x4 acc[NT][4];
+    f32x4 acc[NT][NCF];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // dy loader: thread -> pixel tid / 8, 8-channel group tid % 8
-    const int lp = tid >> 3, lg = tid & 7;
-    const int co_l = cb * WG_CB + lg * 8;
-    for (int st = s_begin; st < s_end; ++st) {
-        const int seg = st % nseg_row, rowi = st / nseg_row;
-        const int y = rowi % H, b = rowi / H;
-        const int x0 = seg * WG_SEG;
-        {
-            uint4 va = {0u, 0u, 0u, 0u};
-            const int xx = x0 + lp;
-            if (xx < W && co_l < Cout)
-                va = *reinterpret_cast<const uint4 *>(dy + (((size_t)b * H + y) * W + xx) * Cout + co_l);
-            const bf16 *ea = reinterpret_cast<const bf16 *>(&va);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) sa[(lg * 8 + q) * WG_PAD + lp] = ea[q];
-        }
-        // X: rows y-1..y+1, pixels x0-1 .. x0+32, 8 input-channel groups
-        for (int idx = tid; idx < 3 * (WG_SEG + 2) * 8; idx += 256) {
-            const int g = idx & 7, r = idx >> 3;
-            const int ky = r / (WG_SEG + 2), px = r % (WG_SEG + 2);  // px = pixel x0 - 1 + px
-            const int ys = y + ky - 1, xs = x0 + px - 1;
-            const int ci_l = ib * WG_IB + g * 8;
-            uint4 vb = {0u, 0u, 0u, 0u};
-            if (ci_l < x.Ctot && ys >= 0 && ys < H && xs >= 0 && xs < W) {
-                int s = 0, coff = ci_l;
-                while (s < x.n - 1 && coff >= x.s[s].C) {
-                    coff -= x.s[s].C;
-                    ++s;
-                }
-                const int bsrc = x.s[s].shared ? 0 : b;
-                vb = *reinterpret_cast<const uint4 *>(x.s[s].p + (((size_t)bsrc * H + ys) * W + xs) * x.s[s].C +
-                                                      coff);
+        for (int j = 0; j < NCF; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // stages the X^T copies of image row yr (zero outside the image) into its slot
+    auto stage_x = [&](int task, int b, int x0, int yr) {
+        const int g = task % (IB / 8), r = task / (IB / 8), j = r % 4, kx = r / 4;
+        const int c = ci0 + g * 8;
+        uint4 pv[8];
+        const bool rowok = yr >= 0 && yr < H && c < x.Ctot;
+        int s = 0, coff = c;
+        if (rowok)
+            while (s < x.n - 1 && coff >= x.s[s].C) {
+                coff -= x.s[s].C;
+                ++s;
             }
-            const bf16 *eb = reinterpret_cast<const bf16 *>(&vb);
-            // copy kx holds X at pixel (segment pixel k) + kx - 1, i.e. px = k + kx
+        const bf16 *src = x.s[s].p;
+        const int Cs = x.s[s].C;
+        const size_t rowbase = ((size_t)(x.s[s].shared ? 0 : b) * H + (rowok ? yr : 0)) * W;
 #pragma unroll
-            for (int kx = 0; kx < 3; ++kx) {
-                const int k = px - kx;
-                if (k >= 0 && k < WG_SEG)
+        for (int i = 0; i < 8; ++i) {
+            const int xs = x0 - 1 + 8 * j + kx + i;
+            pv[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (rowok && xs >= 0 && xs < W)
+                pv[i] = *reinterpret_cast<const uint4 *>(src + (rowbase + xs) * Cs + coff);
+        }
+        uint4 o[8];
+        transpose8(pv, o);
+        const int slot = (yr + 3) % 3;
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) sb[kx][ky][(g * 8 + q) * WG_PAD + k] = eb[q];
+        for (int q = 0; q < 8; ++q)
+            *reinterpret_cast<uint4 *>(&sb[slot][kx][(g * 8 + q) * WG_PADP + 8 * j]) = o[q];
+    };
+    auto stage_dy = [&](int task, int b, int x0, int y) {
+        const int g = task % (CB / 8), j = task / (CB / 8);
+        const int c = co0 + g * 8;
+        uint4 pv[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int xs = x0 + 8 * j + i;
+            pv[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (c < Cout && xs < W)
+                pv[i] = *reinterpret_cast<const uint4 *>(dy + (((size_t)b * H + y) * W + xs) * Cout + c);
+        }
+        uint4 o[8];
+        transpose8(pv, o);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            *reinterpret_cast<uint4 *>(&sa[(g * 8 + q) * WG_PADP + 8 * j]) = o[q];
+    };
+
+    for (int st = s_begin; st < s_end; ++st) {
+        const int y = st % H, r = st / H, seg = r % nseg, b = r / nseg;
+        const int x0 = seg * WG_SEG;
+        // a new strip (or the split's first step) stages all three X rows
+        const bool fresh = st == s_begin || y == 0;
+        const int nx = fresh ? 3 * NXR : NXR;
+        for (int task = tid; task < NDY + nx; task += 256) {
+            if (task < NDY) {
+                stage_dy(task, b, x0, y);
+            } else {
+                const int t2 = task - NDY;
+                const int yr = fresh ? y - 1 + t2 / NXR : y + 1;
+                stage_x(t2 % NXR, b, x0, yr);
             }
         }
         __syncthreads();
-        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sa[(cf * 16 + (lane & 15)) * WG_PAD + 8 * (lane >> 4)]);
+        bf16x8 a[NCF];
+#pragma unroll
+        for (int cf = 0; cf < NCF; ++cf)
+            a[cf] = *reinterpret_cast<const bf16x8 *>(&sa[(cf * 16 + (lane & 15)) * WG_PADP + 8 * (lane >> 4)]);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int tap = tg + t * TS;
+            const int tap = tg + t * TG;
             if (tap < 9) {
                 const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+                const int slot = (y + ky - 1 + 3) % 3;
+                const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(
+                    &sb[slot][kx][(fi * 16 + (lane & 15)) * WG_PADP + 8 * (lane >> 4)]);
 #pragma unroll
-                for (int nf = 0; nf < 4; ++nf) {
-                    const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(
-                        &sb[kx][ky][(nf * 16 + (lane & 15)) * WG_PAD + 8 * (lane >> 4)]);
-                    acc[t][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[t][nf], 0, 0, 0);
-                }
+                for (int cf = 0; cf < NCF; ++cf)
+                    acc[t][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cf], bw, acc[t][cf], 0, 0, 0);
             }
         }
         __syncthreads();
     }
+    // D[co][ci]: lane holds input channel l % 16 and output channels 4 (l / 16) .. + 3
     const size_t per_split = (size_t)Cout * 9 * x.Ctot;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        const int tap = tg + t * TS;
+        const int tap = tg + t * TG;
         if (tap >= 9) continue;
 #pragma unroll
-        for (int nf = 0; nf < 4; ++nf)
+        for (int cf = 0; cf < NCF; ++cf)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int co = cb * WG_CB + cf * 16 + 4 * (lane >> 4) + q;
-                const int ci = ib * WG_IB + nf * 16 + (lane & 15);
+                const int co = co0 + cf * 16 + 4 * (lane >> 4) + q;
+                const int ci = ci0 + fi * 16 + (lane & 15);
                 if (co < Cout && ci < x.Ctot)
-                    part[blockIdx.x * per_split + ((size_t)co * 9 + tap) * x.Ctot + ci] = acc[t][nf][q];
+                    part[blockIdx.x * per_split + ((size_t)co * 9 + tap) * x.Ctot + ci] = acc[t][cf][q];
             }
     }
 }
 
+// out[i] = sum over splits of part[split][i], in two fixed-order passes:
+// groups of 32 splits into tmp, then the groups
 __global__ void k_sum_splits(const float *__restrict__ part, int nsplit, size_t n,
-                             float *__restrict__ out)
+                             float *__restrict__ tmp, int ngroup)
+{
+    const int g = blockIdx.y;
+    const int s0 = g * 32, s1 = min(nsplit, s0 + 32);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        float acc = 0.f;
+        for (int s = s0; s < s1; ++s) acc += part[(size_t)s * n + i];
+        tmp[(size_t)g * n + i] = acc;
+    }
+}
+
+__global__ void k_sum_groups(const float *__restrict__ tmp, int ngroup, size_t n, float *__restrict__ out)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         float acc = 0.f;
-        for (int s = 0; s < nsplit; ++s) acc += part[(size_t)s * n + i];
+        for (int g = 0; g < ngroup; ++g) acc += tmp[(size_t)g * n + i];
         out[i] = acc;
     }
 }
@@ -1139,28 +1206,29 @@ inline int red_blocks(size_t P, int C)
 
 // ================================================================== launchers
 
-void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout, int mode,
-                    float *out32, bf16 *out16, const float *scale, const float *shift,
-                    float slope, hipStream_t s)
+namespace {
+
+// launch shape of one convolution: pixel rows per wavefront fragment group
+// (tile height 4 MF) and the number of workgroups walking the tiles
+struct ConvShape {
+    int mf, blocks;
+};
+
+void conv_dispatch(const ConvShape &c, const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout,
+                   int mode, float *out32, bf16 *out16, const float *scale, const float *shift,
+                   float slope, hipStream_t s)
 {
-    // 16-row tiles for large images, 8-row tiles for small ones; narrow
-    // channel blocks for 32-channel layers
-    const int MF = H >= 64 ? 4 : 2;
     const int NF = Cout >= 64 ? 4 : 2;
     const int CO = 16 * NF;
-    const int TH = 4 * MF;
     const int ncob = (Cout + CO - 1) / CO;
-    const long long ntiles = (long long)B * ((H + TH - 1) / TH) * ((W + 15) / 16);
-    // about eight workgroups per compute unit in total, each walking
-    // ntiles / gridDim.x tiles
-    const long long want = std::max<long long>(1, 2048 / ncob);
-    dim3 grid((unsigned)std::min<long long>(ntiles, want), ncob);
+    const long long ntiles = (long long)B * ((H + 4 * c.mf - 1) / (4 * c.mf)) * ((W + 15) / 16);
+    dim3 grid((unsigned)std::max<long long>(1, std::min<long long>(ntiles, c.blocks)), ncob);
 #define CONV_LAUNCH(mf, nf)                                                                         \
     hipLaunchKernelGGL((k_conv3x3<mf, nf>), grid, dim3(256), 0, s, in, B, H, W, Wt, Cout, mode, out32, \
                        out16, scale, shift, slope)
-    if (MF == 4 && NF == 4)
+    if (c.mf == 4 && NF == 4)
         CONV_LAUNCH(4, 4);
-    else if (MF == 4)
+    else if (c.mf == 4)
         CONV_LAUNCH(4, 2);
     else if (NF == 4)
         CONV_LAUNCH(2, 4);
@@ -1169,17 +1237,112 @@ void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
 #undef CONV_LAUNCH
 }
 
+// Heuristic: 16-row tiles for large images, 8-row tiles for small ones;
+// about eight workgroups per compute unit in total.
+ConvShape conv_default(int H, int Cout)
+{
+    const int ncob = (Cout + (Cout >= 64 ? 63 : 31)) / (Cout >= 64 ? 64 : 32);
+    return ConvShape{H >= 64 ? 4 : 2, std::max(1, 2048 / ncob)};
+}
+
+struct Tuner {
+    std::mutex mu;
+    int enabled = 0;
+    std::map<std::array<int, 6>, ConvShape> table;
+};
+Tuner g_tune;
+
+// Times every candidate launch shape for this convolution (three runs each,
+// HIP events on the caller's stream) and keeps the fastest.  Each run
+// recomputes the same output, so tuning leaves the result unchanged.
+ConvShape conv_tune(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout, int mode, float *out32,
+                    bf16 *out16, const float *scale, const float *shift, float slope, hipStream_t s)
+{
+    const int ncob = (Cout + (Cout >= 64 ? 63 : 31)) / (Cout >= 64 ? 64 : 32);
+    ConvShape best = conv_default(H, Cout);
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return best;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return best;
+    }
+    for (int mf : {2, 4})
+        for (int per_cu : {2, 4, 8, 16}) {
+            ConvShape c{mf, std::max(1, 256 * per_cu / ncob)};
+            conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s);  // warm
+            hipEventRecord(e0, s);
+            for (int r = 0; r < 3; ++r)
+                conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s);
+            hipEventRecord(e1, s);
+            float ms = 0.f;
+            if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+                ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return best;
+}
+
+}  // namespace
+
+void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout, int mode,
+                    float *out32, bf16 *out16, const float *scale, const float *shift,
+                    float slope, hipStream_t s)
+{
+    ConvShape c = conv_default(H, Cout);
+    if (g_tune.enabled) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+            const std::array<int, 6> key{B, H, W, in.Ctot, Cout, mode};
+            std::lock_guard<std::mutex> lk(g_tune.mu);
+            auto it = g_tune.table.find(key);
+            if (it == g_tune.table.end())
+                it = g_tune.table.emplace(key, conv_tune(in, B, H, W, Wt, Cout, mode, out32, out16, scale,
+                                                          shift, slope, s)).first;
+            c = it->second;
+        } else {
+            std::lock_guard<std::mutex> lk(g_tune.mu);
+            auto it = g_tune.table.find({B, H, W, in.Ctot, Cout, mode});
+            if (it != g_tune.table.end()) c = it->second;
+        }
+    }
+    conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s);
+}
+
+int conv_autotune(int enable)
+{
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    const int prev = g_tune.enabled;
+    g_tune.enabled = enable ? 1 : 0;
+    if (enable < 0) g_tune.table.clear();
+    return prev;
+}
+
+int conv_autotune_entries()
+{
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    return (int)g_tune.table.size();
+}
+
 static int wgrad_nsplit(int B, int H, int W, int Cout, int Ctot)
 {
     const int steps = B * H * ((W + WG_SEG - 1) / WG_SEG);
-    const int blocks = ((Cout + WG_CB - 1) / WG_CB) * ((Ctot + WG_IB - 1) / WG_IB);
+    const int CB = Cout >= 64 ? 64 : 32, IB = Ctot >= 64 ? 64 : 32;
+    const int blocks = ((Cout + CB - 1) / CB) * ((Ctot + IB - 1) / IB);
     int want = std::max(1, 1024 / blocks);
-    return std::max(1, std::min(want, (steps + 7) / 8));  // at least 8 steps per split
+    return std::max(1, std::min(want, (steps + 31) / 32));  // at least 32 steps per split
 }
 
 size_t wgrad_scratch(int B, int H, int W, int Cout, int Ctot)
 {
-    return (size_t)wgrad_nsplit(B, H, W, Cout, Ctot) * Cout * 9 * Ctot;
+    // the partials, then the 32-split group sums
+    const size_t n = (size_t)Cout * 9 * Ctot;
+    const size_t ns = (size_t)wgrad_nsplit(B, H, W, Cout, Ctot);
+    return ns * n + ((ns + 31) / 32) * n;
 }
 
 void launch_wgrad(const Srcs &x, const bf16 *dy, int B, int H, int W, int Cout, float *dW,
@@ -1189,16 +1352,21 @@ void launch_wgrad(const Srcs &x, const bf16 *dy, int B, int H, int W, int Cout, 
     int nsplit = wgrad_nsplit(B, H, W, Cout, x.Ctot);
     const int per = (steps + nsplit - 1) / nsplit;
     nsplit = (steps + per - 1) / per;
-    dim3 grid(nsplit, ((Cout + WG_CB - 1) / WG_CB) * ((x.Ctot + WG_IB - 1) / WG_IB));
-    const int ncf = std::min(4, (Cout + 15) / 16);
-    if (ncf >= 4)
-        hipLaunchKernelGGL(k_wgrad<4>, grid, dim3(256), 0, s, x, dy, B, H, W, Cout, per, part);
-    else if (ncf >= 2)
-        hipLaunchKernelGGL(k_wgrad<2>, grid, dim3(256), 0, s, x, dy, B, H, W, Cout, per, part);
+    const int CB = Cout >= 64 ? 64 : 32, IB = x.Ctot >= 64 ? 64 : 32;
+    dim3 grid(nsplit, ((Cout + CB - 1) / CB) * ((x.Ctot + IB - 1) / IB));
+    if (CB == 64 && IB == 64)
+        hipLaunchKernelGGL((k_wgrad<4, 4>), grid, dim3(256), 0, s, x, dy, B, H, W, Cout, per, part);
+    else if (CB == 64)
+        hipLaunchKernelGGL((k_wgrad<4, 2>), grid, dim3(256), 0, s, x, dy, B, H, W, Cout, per, part);
+    else if (IB == 64)
+        hipLaunchKernelGGL((k_wgrad<2, 4>), grid, dim3(256), 0, s, x, dy, B, H, W, Cout, per, part);
     else
-        hipLaunchKernelGGL(k_wgrad<1>, grid, dim3(256), 0, s, x, dy, B, H, W, Cout, per, part);
-    size_t n = (size_t)Cout * 9 * x.Ctot;
-    hipLaunchKernelGGL(k_sum_splits, dim3(grid_for(n)), dim3(256), 0, s, part, nsplit, n, dW);
+        hipLaunchKernelGGL((k_wgrad<2, 2>), grid, dim3(256), 0, s, x, dy, B, H, W, Cout, per, part);
+    const size_t n = (size_t)Cout * 9 * x.Ctot;
+    const int ngroup = (nsplit + 31) / 32;
+    float *tmp = part + (size_t)nsplit * n;
+    hipLaunchKernelGGL(k_sum_splits, dim3(grid_for(n), ngroup), dim3(256), 0, s, part, nsplit, n, tmp, ngroup);
+    hipLaunchKernelGGL(k_sum_groups, dim3(grid_for(n)), dim3(256), 0, s, tmp, ngroup, n, dW);
 }
 
 void launch_bn_stats(const float *y, size_t P, int C, double *part, float *mean, float *rstd,

@@ -49,6 +49,7 @@ struct unet_net {
     std::vector<const helm::bf16 *> ctxp;
     std::vector<helm::bf16 *> ctxbuf;
     int ctx_shared = 0, ctx_B = 0, ctx_H = 0, ctx_valid = 0;
+    int gen = 0;  // bumped when workspace or context storage moves (captured graphs hold pointers)
     std::vector<float *> gctx;
     int attach_context(const unet_net &enc, int nb, int H, int W, hipStream_t st);
     void clear_context();

@@ -199,6 +199,7 @@ int unet_net::ensure_ws(int B, int H, int W, bool training)
     int nB = std::max(B, wsB);
     bool tr = training || wsTrain;
     free_ws();
+    ++gen;
     const int Lv = cfg.levels;
     int rc;
     act.resize(L.size());
@@ -408,6 +409,7 @@ int unet_net::attach_context(const unet_net &enc, int nb, int H, int W, hipStrea
 {
     const int Lv = cfg.levels;
     if (ctxbuf.empty() || ctx_B != nb || ctx_H != H) {
+        ++gen;
         for (auto p : ctxbuf) hipFree(p);
         ctxbuf.assign(Lv, nullptr);
         ctx_valid = 0;
@@ -514,6 +516,10 @@ int unet_net::unpack_nchw_output(float *o, int B, int H, int W, hipStream_t st)
 }
 
 extern "C" {
+
+int helm_autotune(int enable) { return helm::conv_autotune(enable); }
+
+int helm_autotune_entries(void) { return helm::conv_autotune_entries(); }
 
 int unet_create(const unet_cfg *cfg, unet_net **out)
 {

@@ -24,7 +24,7 @@ PREC = {"sl": 0, "unet_cgc": 1, "unet_defl": 2}
 EXPORTS = [
     "helm_setup", "helm_destroy", "helm_level_size", "helm_num_levels", "helm_apply",
     "helm_sl_vcycle", "helm_fgmres_solve", "helm_last_error", "helm_profile_start",
-    "helm_profile_read", "helm_profile_stop", "helm_training_triples", "helm_coarse_slowness",
+    "helm_profile_read", "helm_profile_stop", "helm_autotune", "helm_autotune_entries", "helm_training_triples", "helm_coarse_slowness",
 ]
 PROF = {"none": 0, "coarse": 1, "down": 2, "up": 3, "cgs": 4, "apply": 5, "conv": 6, "wgrad": 7}
 
@@ -39,7 +39,7 @@ class _Opts(C.Structure):
 
 class FgmresOpts(C.Structure):
     _fields_ = [("m", C.c_int), ("tol", C.c_double), ("maxit", C.c_int), ("prec", C.c_int),
-                ("net", C.c_void_p), ("stall_ratio", C.c_double)]
+                ("net", C.c_void_p), ("stall_ratio", C.c_double), ("graph", C.c_int)]
 
 
 class FgmresStats(C.Structure):
@@ -89,6 +89,10 @@ def lib():
         L.helm_profile_read.restype = ip
         L.helm_profile_stop.argtypes = []
         L.helm_profile_stop.restype = ip
+        L.helm_autotune.argtypes = [ip]
+        L.helm_autotune.restype = ip
+        L.helm_autotune_entries.argtypes = []
+        L.helm_autotune_entries.restype = ip
         _lib = L
     return _lib
 
@@ -195,7 +199,7 @@ class Handle:
 
 
 def fgmres_solve(problems, rhs, m=20, tol=1e-7, maxit=20000, prec="sl", net=None,
-                 stall_ratio=0.0, xs=None, stream=None):
+                 stall_ratio=0.0, xs=None, stream=None, graph=False):
     """Solve A x = b for every right-hand side of every problem.
 
     problems: list of Handle; rhs: list of complex64 tensors [nrhs_p, n_p, n_p].
@@ -214,7 +218,7 @@ def fgmres_solve(problems, rhs, m=20, tol=1e-7, maxit=20000, prec="sl", net=None
     total = sum(b.shape[0] for b in rhs)
     stats = (FgmresStats * max(total, 1))()
     opts = FgmresOpts(m, tol, maxit, PREC[prec] if isinstance(prec, str) else int(prec),
-                      C.c_void_p(net.ptr.value if net is not None else 0), stall_ratio)
+                      C.c_void_p(net.ptr.value if net is not None else 0), stall_ratio, int(graph))
     rc = _check(lib().helm_fgmres_solve(probs, nprob, counts, bp, xp, C.byref(opts), stats,
                                         _stream(stream)), "helm_fgmres_solve")
     return xs, [stats[i].as_dict() for i in range(total)], rc
@@ -242,4 +246,14 @@ def profile_read(family):
 
 def profile_stop():
     _check(lib().helm_profile_stop(), "helm_profile_stop")
+
+
+def autotune(enable=1):
+    """Switch the convolution launch-shape autotuner (1 on, 0 off, -1 off and
+    forget); returns the previous setting."""
+    return lib().helm_autotune(int(enable))
+
+
+def autotune_entries():
+    return lib().helm_autotune_entries()
 
