@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -282,6 +283,11 @@ int apply_net_prec(helm_handle *h, unet_net *net, int prec, FgWork *w, const FgS
 
 // Replays the captured restart cycle for this key, capturing it first.  The
 // workspaces the cycle touches are allocated before capture.
+// Capture and instantiation run one at a time across threads (replays run
+// concurrently): a capture must not overlap calls that are unsafe during
+// capture, such as allocations, on other threads.
+std::mutex g_capture_mu;
+
 template <class F>
 int replay_cycle(FgWork *w, const FgState &S, int nnet, const float2 *b, const double2 *x, int prec,
                  unet_net *net, int hgen, hipStream_t s, F &&cycle)
@@ -302,6 +308,7 @@ int replay_cycle(FgWork *w, const FgState &S, int nnet, const float2 *b, const d
             hipGraphExecDestroy(w->graphs.front().exec);
             w->graphs.erase(w->graphs.begin());
         }
+        std::lock_guard<std::mutex> lk(g_capture_mu);
         hipGraph_t graph = nullptr;
         HELM_HIP_CHECK(hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal));
         int rc = cycle(w->cap);
@@ -554,6 +561,16 @@ extern "C" int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int
             if (hipStreamCreateWithFlags(&st[t], hipStreamNonBlocking) != hipSuccess) rc = HELM_E_HIP;
         for (int t = 0; t <= T && !rc; ++t)
             if (hipEventCreateWithFlags(&ev[t], hipEventDisableTiming) != hipSuccess) rc = HELM_E_HIP;
+        // every workspace (and capture stream) exists before the workers
+        // start, so no allocation overlaps a capture on another thread
+        for (int p = 0; p < nprob && !rc; ++p) {
+            if (rhs_per_prob[p] == 0) continue;
+            FgWork *w = nullptr;
+            if ((rc = work_ensure(probs[p], rhs_per_prob[p], m, false, &w))) break;
+            if ((rc = ensure_vcycle_ws(probs[p], rhs_per_prob[p]))) break;
+            if (use_graph && !w->cap && hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking) != hipSuccess)
+                rc = HELM_E_HIP;
+        }
         if (!rc && hipEventRecord(ev[T], s) != hipSuccess) rc = HELM_E_HIP;
         for (int t = 0; t < T && !rc; ++t)
             if (hipStreamWaitEvent(st[t], ev[T], 0) != hipSuccess) rc = HELM_E_HIP;

@@ -18,7 +18,7 @@ using bf16 = __bf16;
 struct Src {
     const bf16 *p;
     int C;
-    int shared;
+    int shared;  // one tensor for the whole batch (read as sample 0)
 };
 // Up to three sources concatenated along channels (by addressing only).
 struct Srcs {
@@ -32,9 +32,18 @@ struct Srcs {
 // accumulation.  Wt: bf16 [Cout][9][Ctot] (tap = ky*3 + kx).
 //   mode 0: out32[p][co] = conv (raw, FP32)
 //   mode 1: out16[p][co] = bf16(LeakyReLU(conv * scale[co] + shift[co]))
+// Optional epilogue work of an inference (mode 1) convolution:
+//   pool     : also write the 2x2 max-pooled activation [B][H/2][W/2][Cout]
+//   head_out : apply the 1x1 head (head_w [2][Cout], head_b [2]) and write
+//              [B][H][W][2] FP32 instead of the activation (needs Cout <= 64)
+struct ConvEpi {
+    bf16 *pool = nullptr;
+    const float *head_w = nullptr, *head_b = nullptr;
+    float *head_out = nullptr;
+};
 void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout, int mode,
                     float *out32, bf16 *out16, const float *scale, const float *shift,
-                    float slope, hipStream_t s);
+                    float slope, hipStream_t s, const ConvEpi &epi = ConvEpi());
 // Launch-shape autotuner of launch_conv3x3: enable = 1 tunes each new shape
 // on first use, 0 uses the heuristic, -1 also forgets the table.  Returns
 // the previous setting.

@@ -49,6 +49,28 @@ __device__ __forceinline__ void st8(bf16 *p, const f8 &r)
     *reinterpret_cast<uint4 *>(p) = u;
 }
 
+// Bilinear x2 upsampling with half-pixel centres: fine index o of a line of
+// n coarse samples reads coarse i0 and i1 with weights 1 - l1 and l1 (edges
+// clamped); up_blend8 blends eight channels of the four coarse samples.
+__device__ __forceinline__ void up_src(int o, int n, int &i0, int &i1, float &l1)
+{
+    float src = (o + 0.5f) * 0.5f - 0.5f;
+    src = src < 0.f ? 0.f : src;
+    i0 = (int)src;
+    i1 = i0 + 1 < n ? i0 + 1 : n - 1;
+    l1 = src - (float)i0;
+}
+
+__device__ __forceinline__ f8 up_blend8(const f8 &a00, const f8 &a01, const f8 &a10, const f8 &a11, float ly,
+                                        float lx)
+{
+    f8 o;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        o.v[q] = (1.f - ly) * ((1.f - lx) * a00.v[q] + lx * a01.v[q]) + ly * ((1.f - lx) * a10.v[q] + lx * a11.v[q]);
+    return o;
+}
+
 // ------------------------------------------------------------------ conv fwd
 // Implicit GEMM, computed transposed: D[co][pixel] = sum_k W[co][k] X[k][pixel]
 // with K = 9 taps x input channels, so that each lane of an MFMA result holds
@@ -62,13 +84,14 @@ __device__ __forceinline__ void st8(bf16 *p, const f8 &r)
 // change) are loaded into registers; they go to LDS after a barrier.  With a
 // single chunk the weights stay in LDS for every tile.  For each kx the
 // MF + 2 halo rows a wavefront touches are read once and serve all three ky.
-template <int MF, int NF>
+template <int MF, int NF, int EPI>  // EPI: 0 store, 1 store and pool, 2 head
 __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B, int H, int W,
                                                  const bf16 *__restrict__ Wt, int Cout, int mode,
                                                  float *__restrict__ out32,
                                                  bf16 *__restrict__ out16,
                                                  const float *__restrict__ scale,
-                                                 const float *__restrict__ shift, float slope)
+                                                 const float *__restrict__ shift, float slope,
+                                                 ConvEpi epi)
 {
     constexpr int TW = 16, TH = 4 * MF, HX = TW + 2, HY = TH + 2;
     constexpr int PS = 40;           // LDS halves per pixel: 32 channels + pad
@@ -211,7 +234,7 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
                 if (MF > 4) __builtin_amdgcn_sched_barrier(0);
             }
         }
-        if (st % nch == nch - 1) {
+        if (EPI == 0 && st % nch == nch - 1) {
             // the tile is complete: lane (l % 16, l / 16) holds pixel x0 + l % 16
             // of each row and channels 4 (l / 16) .. + 3 of each fragment
             const int x = tx * TW + (lane & 15);
@@ -256,6 +279,102 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
                     acc[mf][nf] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
             }
+            advance(tx, ty, b);
+        }
+        if (EPI != 0 && st % nch == nch - 1) {
+            // inference epilogue with pooling (EPI 1) or the 1x1 head (EPI 2):
+            // lane (l % 16, l / 16) holds pixel x0 + l % 16 of each row and
+            // channels 4 (l / 16) .. + 3 of each fragment
+            const int x = tx * TW + (lane & 15);
+            const int cl = 4 * (lane >> 4);
+            const bool full_co = co0 + CO <= Cout;
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            float s0[MF], s1[MF];  // head partial sums per row
+#pragma unroll
+            for (int mf = 0; mf < MF; ++mf) s0[mf] = s1[mf] = 0.f;
+            // one channel fragment at a time (bounds the live registers)
+#pragma unroll
+            for (int nf = 0; nf < NF; ++nf) {
+                const int co = co0 + nf * 16 + cl;
+                const bool co_ok = full_co || co < Cout;
+                float4 sc = make_float4(0.f, 0.f, 0.f, 0.f), sh = sc;
+                if (co_ok) {
+                    sc = *reinterpret_cast<const float4 *>(scale + co);
+                    sh = *reinterpret_cast<const float4 *>(shift + co);
+                }
+                const float scv[4] = {sc.x, sc.y, sc.z, sc.w}, shv[4] = {sh.x, sh.y, sh.z, sh.w};
+                // folded BN and LeakyReLU, rounded to bf16 (kept as floats)
+#pragma unroll
+                for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        float z = acc[mf][nf][q] * scv[q] + shv[q];
+                        z = z > 0.f ? z : slope * z;
+                        acc[mf][nf][q] = (float)(bf16)z;
+                    }
+                if (EPI != 2) {
+#pragma unroll
+                    for (int mf = 0; mf < MF; ++mf) {
+                        const int y = ty * TH + wv * MF + mf;
+                        if (y < H && x < W && co_ok) {
+                            const f32x4 v = acc[mf][nf];
+                            bf16x4 o = {(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
+                            *reinterpret_cast<bf16x4 *>(out16 + (((size_t)b * H + y) * W + x) * Cout + co) = o;
+                        }
+                    }
+                }
+                if (EPI == 1) {
+                    // 2x2 max pooling: rows mf, mf + 1 of this wavefront, pixels
+                    // x, x + 1 in lanes l, l ^ 1 (H and W are even)
+#pragma unroll
+                    for (int mf = 0; mf < MF; mf += 2) {
+                        const int y = ty * TH + wv * MF + mf;
+                        float m[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            m[q] = fmaxf(acc[mf][nf][q], acc[mf + 1][nf][q]);
+                            m[q] = fmaxf(m[q], __shfl_xor(m[q], 1));
+                        }
+                        if ((x & 1) == 0 && y < H && x < W && co_ok) {
+                            bf16x4 o = {(bf16)m[0], (bf16)m[1], (bf16)m[2], (bf16)m[3]};
+                            *reinterpret_cast<bf16x4 *>(
+                                epi.pool + (((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * Cout + co) = o;
+                        }
+                    }
+                }
+                if (EPI == 2 && co_ok) {
+                    const float4 u0 = *reinterpret_cast<const float4 *>(epi.head_w + co);
+                    const float4 u1 = *reinterpret_cast<const float4 *>(epi.head_w + Cout + co);
+#pragma unroll
+                    for (int mf = 0; mf < MF; ++mf) {
+                        s0[mf] += u0.x * acc[mf][nf][0] + u0.y * acc[mf][nf][1] + u0.z * acc[mf][nf][2] +
+                                  u0.w * acc[mf][nf][3];
+                        s1[mf] += u1.x * acc[mf][nf][0] + u1.y * acc[mf][nf][1] + u1.z * acc[mf][nf][2] +
+                                  u1.w * acc[mf][nf][3];
+                    }
+                }
+            }
+            if (EPI == 2) {
+                // 1x1 head over all Cout channels of the pixel: the four lanes
+                // l, l ^ 16, l ^ 32, l ^ 48 hold its channels
+                const float hb0 = epi.head_b[0], hb1 = epi.head_b[1];
+#pragma unroll
+                for (int mf = 0; mf < MF; ++mf) {
+                    const int y = ty * TH + wv * MF + mf;
+                    float a0 = s0[mf], a1 = s1[mf];
+                    a0 += __shfl_xor(a0, 16);
+                    a1 += __shfl_xor(a1, 16);
+                    a0 += __shfl_xor(a0, 32);
+                    a1 += __shfl_xor(a1, 32);
+                    if (lane < 16 && y < H && x < W)
+                        *reinterpret_cast<float2 *>(epi.head_out + (((size_t)b * H + y) * W + x) * 2) =
+                            make_float2(a0 + hb0, a1 + hb1);
+                }
+            }
+#pragma unroll
+            for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+                for (int nf = 0; nf < NF; ++nf) acc[mf][nf] = f32x4{0.f, 0.f, 0.f, 0.f};
             advance(tx, ty, b);
         }
         if (more) {
@@ -709,15 +828,8 @@ __global__ void k_maxpool_bwd(const float *__restrict__ dout, int cstride, int c
 }
 
 // ------------------------------------------------------------------ upsampling
-__device__ __forceinline__ void up_src(int o, int n, int &i0, int &i1, float &l1)
-{
-    float src = (o + 0.5f) * 0.5f - 0.5f;
-    src = src < 0.f ? 0.f : src;
-    i0 = (int)src;
-    i1 = i0 + 1 < n ? i0 + 1 : n - 1;
-    l1 = src - (float)i0;
-}
 
+// thread per (fine pixel, 8-channel group)
 __global__ void k_up2_fwd(const bf16 *__restrict__ in, int B, int h, int w, int C,
                           bf16 *__restrict__ out)
 {
@@ -734,12 +846,7 @@ __global__ void k_up2_fwd(const bf16 *__restrict__ in, int B, int h, int w, int 
         const bf16 *pb = in + (size_t)b * h * w * C + 8 * g;
         f8 a00 = ld8(pb + ((size_t)y0 * w + x0) * C), a01 = ld8(pb + ((size_t)y0 * w + x1) * C);
         f8 a10 = ld8(pb + ((size_t)y1 * w + x0) * C), a11 = ld8(pb + ((size_t)y1 * w + x1) * C);
-        f8 o;
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            o.v[q] = (1.f - ly) * ((1.f - lx) * a00.v[q] + lx * a01.v[q]) +
-                     ly * ((1.f - lx) * a10.v[q] + lx * a11.v[q]);
-        st8(out + (size_t)pix * C + 8 * g, o);
+        st8(out + (size_t)pix * C + 8 * g, up_blend8(a00, a01, a10, a11, ly, lx));
     }
 }
 
@@ -898,32 +1005,43 @@ __global__ void k_head_bwd_finish(const double *__restrict__ part, int nblk, int
 }
 
 // ------------------------------------------------------------------ wrapper
-// rc = R(h^2 r) (full weighting, zero outside) and partial sums of |rc|^2
+// rc = R(h^2 r) (full weighting, zero outside) and partial sums of |rc|^2.
+// Thread per pair of coarse points (I, 2K), (I, 2K + 1): fine rows 2I - 1 ..
+// 2I + 1, columns 4K - 1 .. 4K + 3 (one float2 and two float4 loads a row).
 __global__ __launch_bounds__(256) void k_restrict_scaled(const float2 *__restrict__ r, size_t rs,
                                                          int n, float2 *__restrict__ rc,
                                                          double *__restrict__ part, int nblk,
                                                          const int *__restrict__ idx)
 {
-    const int b = blockIdx.y, nc = n / 2;
+    const int b = blockIdx.y, nc = n / 2, hp = nc / 2;
     const float h2 = 1.f / ((float)n * (float)n);
     const float2 *rb = r + (size_t)(idx ? idx[b] : b) * rs;
     double acc = 0.0;
-    for (int idx = blockIdx.x * 256 + threadIdx.x; idx < nc * nc; idx += nblk * 256) {
-        int I = idx / nc, J = idx - I * nc;
-        float sr = 0.f, si = 0.f;
-        for (int a = -1; a <= 1; ++a)
-            for (int c = -1; c <= 1; ++c) {
-                int i = 2 * I + a, j = 2 * J + c;
-                if (i < 0 || j < 0 || i >= n || j >= n) continue;
-                float wgt = (a == 0 ? 0.5f : 0.25f) * (c == 0 ? 0.5f : 0.25f);
-                float2 v = rb[(size_t)i * n + j];
-                sr += wgt * v.x;
-                si += wgt * v.y;
-            }
-        sr *= h2;
-        si *= h2;
-        rc[(size_t)b * nc * nc + idx] = make_float2(sr, si);
-        acc += (double)sr * sr + (double)si * si;
+    for (int t = blockIdx.x * 256 + threadIdx.x; t < nc * hp; t += nblk * 256) {
+        const int I = t / hp, K = t - I * hp;
+        float s0r = 0.f, s0i = 0.f, s1r = 0.f, s1i = 0.f;
+#pragma unroll
+        for (int a = -1; a <= 1; ++a) {
+            const int i = 2 * I + a;
+            if (i < 0 || i >= n) continue;
+            const float wr = a == 0 ? 0.5f : 0.25f;
+            const float2 *row = rb + (size_t)i * n + 4 * K;
+            const float2 m1 = K > 0 ? row[-1] : make_float2(0.f, 0.f);
+            const float4 p01 = *reinterpret_cast<const float4 *>(row);
+            const float4 p23 = *reinterpret_cast<const float4 *>(row + 2);
+            // coarse 2K: columns 4K - 1, 4K, 4K + 1; coarse 2K + 1: 4K + 1, 4K + 2, 4K + 3
+            s0r += wr * (0.25f * m1.x + 0.5f * p01.x + 0.25f * p01.z);
+            s0i += wr * (0.25f * m1.y + 0.5f * p01.y + 0.25f * p01.w);
+            s1r += wr * (0.25f * p01.z + 0.5f * p23.x + 0.25f * p23.z);
+            s1i += wr * (0.25f * p01.w + 0.5f * p23.y + 0.25f * p23.w);
+        }
+        s0r *= h2;
+        s0i *= h2;
+        s1r *= h2;
+        s1i *= h2;
+        *reinterpret_cast<float4 *>(rc + (size_t)b * nc * nc + (size_t)I * nc + 2 * K) =
+            make_float4(s0r, s0i, s1r, s1i);
+        acc += (double)s0r * s0r + (double)s0i * s0i + (double)s1r * s1r + (double)s1i * s1i;
     }
     acc = wave_sum(acc);
     __shared__ double red[4];
@@ -959,54 +1077,57 @@ __global__ void k_pack_input(const float2 *__restrict__ rc, const double *__rest
         head.v[2] = kap;
 #pragma unroll
         for (int q = 3; q < 8; ++q) head.v[q] = 0.f;
-        bf16 *o = x0 + (size_t)i * 32;
-        st8(o, head);
-        const uint4 z = {0u, 0u, 0u, 0u};
-        *reinterpret_cast<uint4 *>(o + 8) = z;
-        *reinterpret_cast<uint4 *>(o + 16) = z;
-        *reinterpret_cast<uint4 *>(o + 24) = z;
+        // channels 8..31 of x0 are zero from allocation on and never written
+        st8(x0 + (size_t)i * 32, head);
     }
 }
 
 // e (+)= P(s (out0 + i out1)), P bilinear prolongation (transposed stride-2
-// convolution with (1/4)[1 2 1; 2 4 2; 1 2 1])
+// convolution with (1/4)[1 2 1; 2 4 2; 1 2 1]).  Thread per fine row i and
+// coarse column J: fine pixels (i, 2J) (coarse column J, weight 1) and
+// (i, 2J + 1) (columns J, J + 1, weight 1/2 each); fine row i reads coarse
+// row i / 2 (even i, weight 1) or rows (i - 1) / 2 and (i + 1) / 2 (odd i,
+// weight 1/2 each), zero outside.
 __global__ void k_net_output(const float *__restrict__ out, const double *__restrict__ s, int nb,
                              int n, float2 *__restrict__ e, size_t es, int accumulate,
                              const int *__restrict__ mask, const int *__restrict__ pos)
 {
     const int nc = n / 2;
-    const size_t total = (size_t)nb * n * n;
+    const size_t total = (size_t)nb * n * nc;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
-        int b = (int)(idx / ((size_t)n * n));
-        size_t pix = idx % ((size_t)n * n);
+        const int J = (int)(idx % nc);
+        const size_t r = idx / nc;
+        const int i = (int)(r % n), b = (int)(r / n);
+        float4 *pe = reinterpret_cast<float4 *>(e + (size_t)b * es + (size_t)i * n + 2 * J);
         const int q = pos ? pos[b] : b;  // the right-hand side's sample in the network batch
         if (q < 0 || (mask && !mask[b])) {
-            if (!accumulate) e[(size_t)b * es + pix] = make_float2(0.f, 0.f);
+            if (!accumulate) *pe = make_float4(0.f, 0.f, 0.f, 0.f);
             continue;
         }
-        int i = (int)(pix / n), j = (int)(pix % n);
-        const float *ob = out + (size_t)q * nc * nc * 2;
-        float sr = 0.f, si = 0.f;
-        int Ia = i >> 1, Ib = (i + 1) >> 1, Ja = j >> 1, Jb = (j + 1) >> 1;
-        float wi = (i & 1) ? 0.5f : 1.f, wj = (j & 1) ? 0.5f : 1.f;
-        for (int u = 0; u < ((i & 1) ? 2 : 1); ++u) {
-            int I = u ? Ib : Ia;
+        const float2 *ob = reinterpret_cast<const float2 *>(out + (size_t)q * nc * nc * 2);
+        float2 c0 = make_float2(0.f, 0.f), c1 = c0;  // rows blended at columns J and J + 1
+        const int Ia = i >> 1, Ib = (i + 1) >> 1;
+        const int nrow = (i & 1) ? 2 : 1;
+        for (int u = 0; u < nrow; ++u) {
+            const int I = u ? Ib : Ia;
             if (I >= nc) continue;
-            for (int v = 0; v < ((j & 1) ? 2 : 1); ++v) {
-                int J = v ? Jb : Ja;
-                if (J >= nc) continue;
-                sr += ob[((size_t)I * nc + J) * 2];
-                si += ob[((size_t)I * nc + J) * 2 + 1];
-            }
+            const float2 v0 = ob[(size_t)I * nc + J];
+            const float2 v1 = J + 1 < nc ? ob[(size_t)I * nc + J + 1] : make_float2(0.f, 0.f);
+            c0.x += v0.x;
+            c0.y += v0.y;
+            c1.x += v1.x;
+            c1.y += v1.y;
         }
-        float sc = (float)s[q] * wi * wj;
-        float2 val = make_float2(sc * sr, sc * si);
-        float2 *pe = e + (size_t)b * es + pix;
+        const float wi = (i & 1) ? 0.5f : 1.f;
+        const float sc = (float)s[q] * wi;
+        float4 val = make_float4(sc * c0.x, sc * c0.y, 0.5f * sc * (c0.x + c1.x), 0.5f * sc * (c0.y + c1.y));
         if (accumulate) {
-            float2 o = *pe;
+            const float4 o = *pe;
             val.x += o.x;
             val.y += o.y;
+            val.z += o.z;
+            val.w += o.w;
         }
         *pe = val;
     }
@@ -1216,16 +1337,26 @@ struct ConvShape {
 
 void conv_dispatch(const ConvShape &c, const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout,
                    int mode, float *out32, bf16 *out16, const float *scale, const float *shift,
-                   float slope, hipStream_t s)
+                   float slope, hipStream_t s, const ConvEpi &epi)
 {
     const int NF = Cout >= 64 ? 4 : 2;
     const int CO = 16 * NF;
     const int ncob = (Cout + CO - 1) / CO;
     const long long ntiles = (long long)B * ((H + 4 * c.mf - 1) / (4 * c.mf)) * ((W + 15) / 16);
     dim3 grid((unsigned)std::max<long long>(1, std::min<long long>(ntiles, c.blocks)), ncob);
-#define CONV_LAUNCH(mf, nf)                                                                         \
-    hipLaunchKernelGGL((k_conv3x3<mf, nf>), grid, dim3(256), 0, s, in, B, H, W, Wt, Cout, mode, out32, \
-                       out16, scale, shift, slope)
+    const int ep = epi.head_out ? 2 : (epi.pool ? 1 : 0);
+#define CONV_LAUNCH(mf, nf)                                                                                 \
+    do {                                                                                                    \
+        if (ep == 2)                                                                                        \
+            hipLaunchKernelGGL((k_conv3x3<mf, nf, 2>), grid, dim3(256), 0, s, in, B, H, W, Wt, Cout, mode,    \
+                               out32, out16, scale, shift, slope, epi);                                      \
+        else if (ep == 1)                                                                                   \
+            hipLaunchKernelGGL((k_conv3x3<mf, nf, 1>), grid, dim3(256), 0, s, in, B, H, W, Wt, Cout, mode,    \
+                               out32, out16, scale, shift, slope, epi);                                      \
+        else                                                                                                \
+            hipLaunchKernelGGL((k_conv3x3<mf, nf, 0>), grid, dim3(256), 0, s, in, B, H, W, Wt, Cout, mode,    \
+                               out32, out16, scale, shift, slope, epi);                                      \
+    } while (0)
     if (c.mf == 4 && NF == 4)
         CONV_LAUNCH(4, 4);
     else if (c.mf == 4)
@@ -1245,6 +1376,13 @@ ConvShape conv_default(int H, int Cout)
     return ConvShape{H >= 64 ? 4 : 2, std::max(1, 2048 / ncob)};
 }
 
+// epilogue and source variant of a convolution (part of the tuning key)
+int conv_variant(const Srcs &in, int mode, const ConvEpi &epi)
+{
+    (void)in;
+    return mode | ((epi.pool != nullptr) << 1) | ((epi.head_out != nullptr) << 2);
+}
+
 struct Tuner {
     std::mutex mu;
     int enabled = 0;
@@ -1256,7 +1394,8 @@ Tuner g_tune;
 // HIP events on the caller's stream) and keeps the fastest.  Each run
 // recomputes the same output, so tuning leaves the result unchanged.
 ConvShape conv_tune(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout, int mode, float *out32,
-                    bf16 *out16, const float *scale, const float *shift, float slope, hipStream_t s)
+                    bf16 *out16, const float *scale, const float *shift, float slope, hipStream_t s,
+                    const ConvEpi &epi)
 {
     const int ncob = (Cout + (Cout >= 64 ? 63 : 31)) / (Cout >= 64 ? 64 : 32);
     ConvShape best = conv_default(H, Cout);
@@ -1270,10 +1409,10 @@ ConvShape conv_tune(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
     for (int mf : {2, 4})
         for (int per_cu : {2, 4, 8, 16}) {
             ConvShape c{mf, std::max(1, 256 * per_cu / ncob)};
-            conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s);  // warm
+            conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s, epi);  // warm
             hipEventRecord(e0, s);
             for (int r = 0; r < 3; ++r)
-                conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s);
+                conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s, epi);
             hipEventRecord(e1, s);
             float ms = 0.f;
             if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
@@ -1291,26 +1430,26 @@ ConvShape conv_tune(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
 
 void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout, int mode,
                     float *out32, bf16 *out16, const float *scale, const float *shift,
-                    float slope, hipStream_t s)
+                    float slope, hipStream_t s, const ConvEpi &epi)
 {
     ConvShape c = conv_default(H, Cout);
     if (g_tune.enabled) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
-            const std::array<int, 6> key{B, H, W, in.Ctot, Cout, mode};
+            const std::array<int, 6> key{B, H, W, in.Ctot, Cout, conv_variant(in, mode, epi)};
             std::lock_guard<std::mutex> lk(g_tune.mu);
             auto it = g_tune.table.find(key);
             if (it == g_tune.table.end())
                 it = g_tune.table.emplace(key, conv_tune(in, B, H, W, Wt, Cout, mode, out32, out16, scale,
-                                                          shift, slope, s)).first;
+                                                          shift, slope, s, epi)).first;
             c = it->second;
         } else {
             std::lock_guard<std::mutex> lk(g_tune.mu);
-            auto it = g_tune.table.find({B, H, W, in.Ctot, Cout, mode});
+            auto it = g_tune.table.find({B, H, W, in.Ctot, Cout, conv_variant(in, mode, epi)});
             if (it != g_tune.table.end()) c = it->second;
         }
     }
-    conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s);
+    conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s, epi);
 }
 
 int conv_autotune(int enable)
@@ -1473,7 +1612,7 @@ void launch_net_input(const float2 *r, size_t rstride, int nb, int n, const floa
                       hipStream_t st, const int *idx)
 {
     int nc = n / 2;
-    int nblk = (int)std::min<size_t>(256, std::max<size_t>(1, ((size_t)nc * nc + 1023) / 1024));
+    int nblk = (int)std::min<size_t>(256, std::max<size_t>(1, ((size_t)nc * nc / 2 + 511) / 512));
     hipLaunchKernelGGL(k_restrict_scaled, dim3(nblk, nb), dim3(256), 0, st, r, rstride, n, rc, part,
                        nblk, idx);
     hipLaunchKernelGGL(k_rms, dim3(nb), dim3(64), 0, st, part, nblk, nc, s);
@@ -1485,7 +1624,7 @@ void launch_net_input(const float2 *r, size_t rstride, int nb, int n, const floa
 void launch_net_output(const float *out, const double *s, int nb, int n, float2 *e, size_t estride,
                        int accumulate, hipStream_t st, const int *mask, const int *pos)
 {
-    size_t tot = (size_t)nb * n * n;
+    size_t tot = (size_t)nb * n * (n / 2);
     hipLaunchKernelGGL(k_net_output, dim3(grid_for(tot)), dim3(256), 0, st, out, s, nb, n, e, estride,
                        accumulate, mask, pos);
 }

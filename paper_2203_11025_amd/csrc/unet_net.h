@@ -62,7 +62,8 @@ struct unet_net {
     int enc_index(int level, char ab) const;
     int dec_index(int level, char ab) const;
     helm::Srcs layer_srcs(int i) const;
-    void run_layer(int i, const helm::Srcs &src, int B, int H, int W, bool training, hipStream_t st);
+    void run_layer(int i, const helm::Srcs &src, int B, int H, int W, bool training, hipStream_t st,
+                   const helm::ConvEpi &epi = helm::ConvEpi());
     void forward_from_x0(int B, int H, int W, bool training, hipStream_t st);
     void backward(int B, int H, int W, hipStream_t st);  // zero, head, layers
     void zero_act_grads(int B, int H, int W, hipStream_t st);

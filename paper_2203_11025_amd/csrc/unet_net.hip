@@ -237,6 +237,12 @@ int unet_net::ensure_ws(int B, int H, int W, bool training)
     if ((rc = dalloc(&x0, P0 * pad32(cfg.in_ch))) || (rc = dalloc(&out, P0 * cfg.out_ch)) ||
         (rc = dalloc(&xin, P0 * cfg.out_ch)))
         return rc;
+    // the padding channels of the network input stay zero: input packing
+    // writes only the first eight channels of each pixel
+    if (hipMemset(x0, 0, P0 * pad32(cfg.in_ch) * sizeof(bf16)) != hipSuccess) {
+        set_error("unet: clearing the input workspace failed");
+        return HELM_E_HIP;
+    }
     if ((rc = dalloc(&red, 1 << 20))) return rc;  // reduction scratch (8 MB)
     if (tr) {
         if ((rc = dalloc(&gout, P0 * cfg.out_ch)) || (rc = dalloc(&dX, maxdx)) || (rc = dalloc(&dy, maxdy)) ||
@@ -255,7 +261,8 @@ int unet_net::ensure_ws(int B, int H, int W, bool training)
 }
 
 // One 3x3 convolution layer with BN and LeakyReLU.
-void unet_net::run_layer(int i, const Srcs &src, int B, int H, int W, bool training, hipStream_t st)
+void unet_net::run_layer(int i, const Srcs &src, int B, int H, int W, bool training, hipStream_t st,
+                         const ConvEpi &epi)
 {
     Layer &l = L[i];
     Act &a = act[i];
@@ -270,7 +277,7 @@ void unet_net::run_layer(int i, const Srcs &src, int B, int H, int W, bool train
         launch_bn_act_fwd(a.y32, Pl, l.cout, l.mean, l.rstd, P + l.g_off, P + l.b_off, SLOPE, a.a, st);
     } else {
         launch_conv3x3(src, B, H, W, l.Wp, l.cout, 1, nullptr, a.a, scale + l.sc_off, shift + l.sc_off,
-                       SLOPE, st);
+                       SLOPE, st, epi);
         prof_mark(HELM_PROF_CONV, st, false, flops);
     }
 }
@@ -310,26 +317,46 @@ int unet_net::dec_index(int level, char ab) const
     return 2 * cfg.levels + 2 * (cfg.levels - 2 - level) + (ab == 'b' ? 1 : 0);
 }
 
+// Training keeps every intermediate tensor the backward pass reads (pooling
+// arguments, the last activation) and runs pooling and the head on their own.
+// In inference the second convolution of a 32-channel encoder level also
+// writes the pooled tensor, and a 32-channel last convolution applies the head.
 void unet_net::forward_from_x0(int B, int H, int W, bool training, hipStream_t st)
 {
     const int Lv = cfg.levels;
+    const int last = Lv >= 2 ? dec_index(0, 'b') : enc_index(0, 'b');
+    const bool fuse_head = !training && cfg.head && cfg.widths[0] == 32;
     for (int l = 0; l < Lv; ++l) {
         int Hl = H >> l, Wl = W >> l;
-        if (l > 0)
+        if (l > 0 && (training || cfg.widths[l - 1] != 32))
             launch_maxpool_fwd(act[enc_index(l - 1, 'b')].a, B, H >> (l - 1), W >> (l - 1),
                                cfg.widths[l - 1], pooled[l], training ? arg[l] : nullptr, st);
         run_layer(enc_index(l, 'a'), layer_srcs(enc_index(l, 'a')), B, Hl, Wl, training, st);
-        run_layer(enc_index(l, 'b'), layer_srcs(enc_index(l, 'b')), B, Hl, Wl, training, st);
+        ConvEpi epi;
+        // pooling in the epilogue pays for 32-channel layers only (wider
+        // channel blocks run out of registers)
+        if (!training && l < Lv - 1 && cfg.widths[l] == 32) epi.pool = pooled[l + 1];
+        if (fuse_head && enc_index(l, 'b') == last) {
+            epi.head_w = P + head_w;
+            epi.head_b = P + head_b;
+            epi.head_out = out;
+        }
+        run_layer(enc_index(l, 'b'), layer_srcs(enc_index(l, 'b')), B, Hl, Wl, training, st, epi);
     }
     for (int l = Lv - 2; l >= 0; --l) {
         int Hl = H >> l, Wl = W >> l;
         const bf16 *prev = (l == Lv - 2) ? act[enc_index(Lv - 1, 'b')].a : act[dec_index(l + 1, 'b')].a;
         launch_up2_fwd(prev, B, Hl / 2, Wl / 2, cfg.widths[l + 1], up[l], st);
         run_layer(dec_index(l, 'a'), layer_srcs(dec_index(l, 'a')), B, Hl, Wl, training, st);
-        run_layer(dec_index(l, 'b'), layer_srcs(dec_index(l, 'b')), B, Hl, Wl, training, st);
+        ConvEpi epi;
+        if (fuse_head && dec_index(l, 'b') == last) {
+            epi.head_w = P + head_w;
+            epi.head_b = P + head_b;
+            epi.head_out = out;
+        }
+        run_layer(dec_index(l, 'b'), layer_srcs(dec_index(l, 'b')), B, Hl, Wl, training, st, epi);
     }
-    if (!cfg.head) return;
-    int last = Lv >= 2 ? dec_index(0, 'b') : enc_index(0, 'b');
+    if (!cfg.head || fuse_head) return;
     launch_head_fwd(act[last].a, (size_t)B * H * W, cfg.widths[0], P + head_w, P + head_b, out, st);
 }
 
