@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_2203_11025_amd", "weights", "pair_base.safetensors")
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv_multi1024_traffic.md")
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0
 FAMILIES = ("conv", "cgs", "down", "up", "apply", "coarse")
@@ -59,6 +60,25 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the CPU oracle sample")
     return ap.parse_args()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of the convolutions from the committed counter
+    runs, or None when the kernel source changed since they were taken."""
+    import hashlib
+    import re
+
+    if kernel != "conv" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    m1 = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", text)
+    m2 = re.search(r"kernel_source_sha256: ([0-9a-f]+)", text)
+    src = os.path.join(ROOT, "paper_2203_11025_amd", "csrc", "unet_kernels.hip")
+    if not (m1 and m2 and os.path.exists(src)):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m2.group(1):
+        return None
+    return float(m1.group(1))
 
 
 def log(msg):
@@ -254,7 +274,7 @@ def main():
         achieved = d_work / max(d_launches, 1) / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS}
-    roof.update({"traffic": None, "kernel": dominant, "avg_launch_us": avg_s * 1e6,
+    roof.update({"traffic": measured_traffic(dominant), "kernel": dominant, "avg_launch_us": avg_s * 1e6,
                  "launches": d_launches, "work_per_launch": d_work / max(d_launches, 1),
                  "time_share_warmup": round(fam[dominant][0] / sum(v[0] for v in fam.values()), 3)})
     out = {
