@@ -147,6 +147,8 @@ int ensure_vcycle_ws(helm_handle *h, int nb)
     if (nb <= h->ws_nb) return HELM_OK;
     for (auto p : h->wf) hipFree(p);
     for (auto p : h->wv) hipFree(p);
+    hipFree(h->cpart);
+    h->cpart = nullptr;
     h->wf.assign(h->levels, nullptr);
     h->wv.assign(h->levels, nullptr);
     h->ws_nb = 0;
@@ -155,6 +157,7 @@ int ensure_vcycle_ws(helm_handle *h, int nb)
         size_t Nl = (size_t)h->lv[l].n * h->lv[l].n;
         if (dmalloc(&h->wf[l], Nl * nb) || dmalloc(&h->wv[l], Nl * nb)) return HELM_E_NOMEM;
     }
+    if (dmalloc(&h->cpart, coarse_scratch(h->Nc, nb))) return HELM_E_NOMEM;
     h->ws_nb = nb;
     return HELM_OK;
 }
@@ -163,12 +166,12 @@ int vcycle(helm_handle *h, const float2 *f, size_t fs, float2 *v, size_t vs, int
            const int *active, hipStream_t s, const double *scale, int accumulate)
 {
     const int L = h->levels;
-    if (L == 1) {
-        launch_coarse_solve(h->Xc, h->Nc, f, fs, v, vs, nb, active, s, scale, accumulate);
-        return HELM_OK;
-    }
     int rc = ensure_vcycle_ws(h, nb);
     if (rc) return rc;
+    if (L == 1) {
+        launch_coarse_solve(h->Xc, h->Nc, f, fs, v, vs, nb, active, s, scale, accumulate, h->cpart);
+        return HELM_OK;
+    }
     const float sh = (float)h->beta, w = (float)h->jacobi_w;
     // restrict down to the coarsest level
     for (int l = 0; l < L - 1; ++l) {
@@ -179,7 +182,8 @@ int vcycle(helm_handle *h, const float2 *f, size_t fs, float2 *v, size_t vs, int
                     l == 0 ? scale : nullptr);
     }
     size_t Nc = (size_t)h->Nc;
-    launch_coarse_solve(h->Xc, h->Nc, h->wf[L - 1], Nc, h->wv[L - 1], Nc, nb, active, s);
+    launch_coarse_solve(h->Xc, h->Nc, h->wf[L - 1], Nc, h->wv[L - 1], Nc, nb, active, s, nullptr, 0,
+                        h->cpart);
     // prolongate and post-relax up to the finest level
     for (int l = L - 2; l >= 0; --l) {
         size_t Nl = (size_t)h->lv[l].n * h->lv[l].n;
@@ -318,6 +322,7 @@ void helm_destroy(helm_handle *h)
     for (auto p : h->wv) hipFree(p);
     for (auto &L : h->lv) hipFree(L.mass);
     hipFree(h->Xc);
+    hipFree(h->cpart);
     hipFree(h->kappa0);
     hipFree(h->gamma0);
     delete h;

@@ -20,6 +20,7 @@ struct helm_handle {
     int ws_nb = 0;
     int ws_gen = 0;  // bumped on every reallocation (captured graphs hold the pointers)
     std::vector<float2 *> wf, wv;
+    float2 *cpart = nullptr;   // partial sums of the coarsest-level GEMM
     // FGMRES workspace (see fgmres.hip)
     void *fg = nullptr;
 };

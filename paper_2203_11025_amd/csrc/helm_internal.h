@@ -61,9 +61,12 @@ void launch_up(const Level &L, float shift, float w, const float2 *f, size_t fs,
 
 // v = X f with the dense coarsest-level inverse X (N x N complex64, row-major).
 // `scale` as for launch_down; with `accumulate` the result is added to v.
+// `scratch` (coarse_scratch(N, nb) complex, may be null): with four or more
+// right-hand sides the product runs as a tiled GEMM reading X once.
+size_t coarse_scratch(int N, int nb);
 void launch_coarse_solve(const float2 *X, int N, const float2 *f, size_t fs, float2 *v,
                          size_t vs, int nb, const int *active, hipStream_t s,
-                         const double *scale = nullptr, int accumulate = 0);
+                         const double *scale = nullptr, int accumulate = 0, float2 *scratch = nullptr);
 
 // mode 0: y = f - Op x;  mode 1: y = x + w D^-1 (f - Op x);  mode 2: y = w D^-1 f.
 void launch_resjac(const Level &L, float shift, float w, int mode, const float2 *x, size_t xs,

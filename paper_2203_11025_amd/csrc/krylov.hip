@@ -79,41 +79,47 @@ __global__ __launch_bounds__(256) void k_arnoldi_a(FgState S, const float2 *__re
     constexpr int JV = J > 0 ? J : 1;
     const int b = blockIdx.y;
     if (!S.active[b]) return;
-    const float2 *Vb = V + (size_t)b * vsb;
-    const float2 *u = Vb + (size_t)J * N;
-    const float2 *w = Vb + (size_t)(J + 1) * N;
-    constexpr int U = J <= 12 ? 2 : 1;  // points per thread per step (register budget)
+    // two consecutive points per lane (16-byte loads; N is even)
+    const float4 *Vb = reinterpret_cast<const float4 *>(V + (size_t)b * vsb);
+    const size_t N2 = N / 2;
+    const float4 *u = Vb + (size_t)J * N2;
+    const float4 *w = Vb + (size_t)(J + 1) * N2;
+    constexpr int U = J <= 8 ? 2 : 1;  // point pairs per thread per step (register budget)
     double ar[NP], ai[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) ar[i] = ai[i] = 0.0;
-    for (size_t p0 = (size_t)blockIdx.x * 256 * U + threadIdx.x; p0 < N;
+    for (size_t p0 = (size_t)blockIdx.x * 256 * U + threadIdx.x; p0 < N2;
          p0 += (size_t)nblk * 256 * U) {
-        float2 uu[U], ww[U], v[U][JV];
+        float4 uu[U], ww[U], v[U][JV];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             size_t p = p0 + 256 * q;
-            bool ok = p < N;
-            uu[q] = ok ? u[p] : make_float2(0.f, 0.f);
-            ww[q] = ok ? w[p] : make_float2(0.f, 0.f);
+            bool ok = p < N2;
+            const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+            uu[q] = ok ? u[p] : z;
+            ww[q] = ok ? w[p] : z;
 #pragma unroll
-            for (int i = 0; i < J; ++i) v[q][i] = ok ? Vb[(size_t)i * N + p] : make_float2(0.f, 0.f);
+            for (int i = 0; i < J; ++i) v[q][i] = ok ? Vb[(size_t)i * N2 + p] : z;
         }
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-            double ux = uu[q].x, uy = uu[q].y, wx = ww[q].x, wy = ww[q].y;
+        for (int q = 0; q < U; ++q)
 #pragma unroll
-            for (int i = 0; i < J; ++i) {
-                double vx = v[q][i].x, vy = v[q][i].y;
-                ar[i] += vx * ux + vy * uy;
-                ai[i] += vx * uy - vy * ux;
-                ar[J + i] += vx * wx + vy * wy;
-                ai[J + i] += vx * wy - vy * wx;
+            for (int h = 0; h < 2; ++h) {
+                const double ux = h ? uu[q].z : uu[q].x, uy = h ? uu[q].w : uu[q].y;
+                const double wx = h ? ww[q].z : ww[q].x, wy = h ? ww[q].w : ww[q].y;
+#pragma unroll
+                for (int i = 0; i < J; ++i) {
+                    const double vx = h ? v[q][i].z : v[q][i].x, vy = h ? v[q][i].w : v[q][i].y;
+                    ar[i] += vx * ux + vy * uy;
+                    ai[i] += vx * uy - vy * ux;
+                    ar[J + i] += vx * wx + vy * wy;
+                    ai[J + i] += vx * wy - vy * wx;
+                }
+                ar[2 * J] += ux * ux + uy * uy;
+                ar[2 * J + 1] += ux * wx + uy * wy;
+                ai[2 * J + 1] += ux * wy - uy * wx;
+                ar[2 * J + 2] += wx * wx + wy * wy;
             }
-            ar[2 * J] += ux * ux + uy * uy;
-            ar[2 * J + 1] += ux * wx + uy * wy;
-            ai[2 * J + 1] += ux * wy - uy * wx;
-            ar[2 * J + 2] += wx * wx + wy * wy;
-        }
     }
     block_store<NP>(ar, ai, partial + ((size_t)b * nblk + blockIdx.x) * MAXP);
 }
@@ -275,9 +281,11 @@ __global__ __launch_bounds__(256) void k_arnoldi_b(FgState S, float2 *__restrict
     constexpr int JV = J > 0 ? J : 1;
     const int b = blockIdx.y;
     if (!S.active[b]) return;
-    float2 *Vb = V + (size_t)b * vsb;
-    float2 *u = Vb + (size_t)J * N;
-    float2 *w = Vb + (size_t)(J + 1) * N;
+    // two consecutive points per lane (16-byte loads and stores; N is even)
+    float4 *Vb = reinterpret_cast<float4 *>(V + (size_t)b * vsb);
+    const size_t N2 = N / 2;
+    float4 *u = Vb + (size_t)J * N2;
+    float4 *w = Vb + (size_t)(J + 1) * N2;
     double hr[J + 1], hi[J + 1], cr[JV], ci[JV];
 #pragma unroll
     for (int i = 0; i <= J; ++i) {
@@ -292,38 +300,48 @@ __global__ __launch_bounds__(256) void k_arnoldi_b(FgState S, float2 *__restrict
         ci[i] = a.y;
     }
     const double inu = 1.0 / S.nu[b];
-    constexpr int U = J <= 12 ? 2 : 1;  // points per thread per step (register budget)
-    for (size_t p0 = (size_t)blockIdx.x * 256 * U + threadIdx.x; p0 < N;
+    constexpr int U = J <= 8 ? 2 : 1;  // point pairs per thread per step (register budget)
+    for (size_t p0 = (size_t)blockIdx.x * 256 * U + threadIdx.x; p0 < N2;
          p0 += (size_t)gridDim.x * 256 * U) {
-        float2 uu[U], ww[U], v[U][JV];
+        float4 uu[U], ww[U], v[U][JV];
         bool ok[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             size_t p = p0 + 256 * q;
-            ok[q] = p < N;
-            uu[q] = ok[q] ? u[p] : make_float2(0.f, 0.f);
-            ww[q] = ok[q] ? w[p] : make_float2(0.f, 0.f);
+            ok[q] = p < N2;
+            const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+            uu[q] = ok[q] ? u[p] : z;
+            ww[q] = ok[q] ? w[p] : z;
 #pragma unroll
-            for (int i = 0; i < J; ++i) v[q][i] = ok[q] ? Vb[(size_t)i * N + p] : make_float2(0.f, 0.f);
+            for (int i = 0; i < J; ++i) v[q][i] = ok[q] ? Vb[(size_t)i * N2 + p] : z;
         }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            double ux = uu[q].x, uy = uu[q].y, wx = ww[q].x, wy = ww[q].y;
+            float ov[4], ow[4];
 #pragma unroll
-            for (int i = 0; i < J; ++i) {
-                double vx = v[q][i].x, vy = v[q][i].y;
-                ux -= cr[i] * vx - ci[i] * vy;
-                uy -= cr[i] * vy + ci[i] * vx;
-                wx -= hr[i] * vx - hi[i] * vy;
-                wy -= hr[i] * vy + hi[i] * vx;
+            for (int h = 0; h < 2; ++h) {
+                double ux = h ? uu[q].z : uu[q].x, uy = h ? uu[q].w : uu[q].y;
+                double wx = h ? ww[q].z : ww[q].x, wy = h ? ww[q].w : ww[q].y;
+#pragma unroll
+                for (int i = 0; i < J; ++i) {
+                    const double vx = h ? v[q][i].z : v[q][i].x, vy = h ? v[q][i].w : v[q][i].y;
+                    ux -= cr[i] * vx - ci[i] * vy;
+                    uy -= cr[i] * vy + ci[i] * vx;
+                    wx -= hr[i] * vx - hi[i] * vy;
+                    wy -= hr[i] * vy + hi[i] * vx;
+                }
+                const float vjx = (float)(ux * inu), vjy = (float)(uy * inu);
+                const double vx = vjx, vy = vjy;
+                wx -= hr[J] * vx - hi[J] * vy;
+                wy -= hr[J] * vy + hi[J] * vx;
+                ov[2 * h] = vjx;
+                ov[2 * h + 1] = vjy;
+                ow[2 * h] = (float)wx;
+                ow[2 * h + 1] = (float)wy;
             }
-            float2 vj = make_float2((float)(ux * inu), (float)(uy * inu));
-            double vx = vj.x, vy = vj.y;
-            wx -= hr[J] * vx - hi[J] * vy;
-            wy -= hr[J] * vy + hi[J] * vx;
             if (ok[q]) {
-                u[p0 + 256 * q] = vj;
-                w[p0 + 256 * q] = make_float2((float)wx, (float)wy);
+                u[p0 + 256 * q] = make_float4(ov[0], ov[1], ov[2], ov[3]);
+                w[p0 + 256 * q] = make_float4(ow[0], ow[1], ow[2], ow[3]);
             }
         }
     }
@@ -427,9 +445,9 @@ void launch_arnoldi_step(const FgState &S, float2 *V, size_t vsb, size_t N, int 
     kPassA[j](S, V, vsb, N, partial, nblk, s);
     hipLaunchKernelGGL(k_arnoldi_reduce, dim3(S.nb), dim3(1024), 0, s, S, partial, nblk, j);
     kPassB[j](S, V, vsb, N, nblk, s);
-    // both passes read v_0..v_j and the candidate; the second writes it:
-    // 16 (j + 2) + 8 B per point
-    prof_mark(HELM_PROF_CGS, s, false, (16.0 * (j + 2) + 8.0) * N, S.nb, true);
+    // both passes read v_0..v_{j-1}, the candidate and w; the second writes
+    // v_j and the next candidate: 16 (j + 2) + 16 B per point
+    prof_mark(HELM_PROF_CGS, s, false, (16.0 * (j + 2) + 16.0) * N, S.nb, true);
 }
 
 void launch_masks(const FgState &S, int use_net, hipStream_t s)

@@ -373,6 +373,85 @@ __global__ __launch_bounds__(256) void k_coarse(const float2 *__restrict__ X, in
     }
 }
 
+// Many right-hand sides: V = X F as a tiled complex GEMM, so X is read once
+// and each right-hand side is reused across CG_BM rows from LDS.  A
+// workgroup owns CG_BM rows, CG_BN right-hand sides and one of CG_SPLIT
+// ranges of the sum; k_coarse_finish adds the ranges in order and applies
+// scale / accumulate / the active mask.
+constexpr int CG_BM = 32, CG_BN = 32, CG_BK = 64, CG_SPLIT = 4;
+
+// c + a b (complex)
+__device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c)
+{
+    return f2(c.x + a.x * b.x - a.y * b.y, c.y + a.x * b.y + a.y * b.x);
+}
+
+__global__ __launch_bounds__(256) void k_coarse_gemm(const float2 *__restrict__ X, int N,
+                                                     const float2 *__restrict__ f, size_t fs, int nb,
+                                                     float2 *__restrict__ part)
+{
+    __shared__ float2 xs[CG_BM][CG_BK + 1];
+    __shared__ float2 fsh[CG_BK][CG_BN + 1];
+    const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+    const int r0 = blockIdx.x * CG_BM, sp = blockIdx.y, c0 = blockIdx.z * CG_BN;
+    const int kper = (N + CG_SPLIT - 1) / CG_SPLIT;
+    const int kb = sp * kper, ke = min(N, kb + kper);
+    float2 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f2(0.f, 0.f);
+    for (int k0 = kb; k0 < ke; k0 += CG_BK) {
+        for (int i = tid; i < CG_BM * CG_BK; i += 256) {
+            const int r = i / CG_BK, kk = i % CG_BK;
+            const int row = r0 + r, k = k0 + kk;
+            xs[r][kk] = (row < N && k < ke) ? X[(size_t)row * N + k] : f2(0.f, 0.f);
+        }
+        for (int i = tid; i < CG_BN * CG_BK; i += 256) {
+            const int c = i / CG_BK, kk = i % CG_BK;
+            const int k = k0 + kk;
+            fsh[kk][c] = (c0 + c < nb && k < ke) ? f[(size_t)(c0 + c) * fs + k] : f2(0.f, 0.f);
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < CG_BK; ++kk) {
+            const float2 x0 = xs[2 * tr][kk], x1 = xs[2 * tr + 1][kk];
+            const float2 g0 = fsh[kk][2 * tc], g1 = fsh[kk][2 * tc + 1];
+            acc[0][0] = cfma(x0, g0, acc[0][0]);
+            acc[0][1] = cfma(x0, g1, acc[0][1]);
+            acc[1][0] = cfma(x1, g0, acc[1][0]);
+            acc[1][1] = cfma(x1, g1, acc[1][1]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int row = r0 + 2 * tr + i, c = c0 + 2 * tc + j;
+            if (row < N && c < nb) part[((size_t)sp * nb + c) * N + row] = acc[i][j];
+        }
+}
+
+__global__ void k_coarse_finish(const float2 *__restrict__ part, int N, int nb, float2 *__restrict__ v,
+                                size_t vs, const double *__restrict__ scale, int accumulate,
+                                const int *__restrict__ active)
+{
+    const size_t total = (size_t)nb * N;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i / N), row = (int)(i % N);
+        if (active && !active[c]) continue;
+        float2 z = part[(size_t)c * N + row];
+#pragma unroll
+        for (int sp = 1; sp < CG_SPLIT; ++sp) z = z + part[((size_t)sp * nb + c) * N + row];
+        const float sc = scale ? (float)scale[c] : 1.f;
+        z = f2(sc * z.x, sc * z.y);
+        if (accumulate) z = z + v[(size_t)c * vs + row];
+        v[(size_t)c * vs + row] = z;
+    }
+}
+
 // ------------------------------------------------------------------ setup
 __global__ void k_level_mass(const float *__restrict__ kappa, const float *__restrict__ gamma,
                              int n, int sp, double omega, float2 *__restrict__ mass, int nl)
@@ -487,30 +566,36 @@ void launch_up(const Level &L, float shift, float w, const float2 *f, size_t fs,
     prof_mark(HELM_PROF_UP, s, false, (accumulate ? 34.0 : 26.0) * n * n, nb, active != nullptr);
 }
 
+size_t coarse_scratch(int N, int nb) { return (size_t)CG_SPLIT * nb * N; }
+
 void launch_coarse_solve(const float2 *X, int N, const float2 *f, size_t fs, float2 *v,
                          size_t vs, int nb, const int *active, hipStream_t s, const double *scale,
-                         int accumulate)
+                         int accumulate, float2 *scratch)
 {
     dim3 grid((N + 3) / 4), block(256);
     prof_mark(HELM_PROF_COARSE, s, true);
-    int b0 = 0;
-    while (b0 < nb) {
-        int left = nb - b0;
-        if (left >= 8) {
-            hipLaunchKernelGGL(k_coarse<8>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, accumulate, active);
-            b0 += 8;
-        } else if (left >= 4) {
-            hipLaunchKernelGGL(k_coarse<4>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, accumulate, active);
-            b0 += 4;
-        } else if (left >= 2) {
-            hipLaunchKernelGGL(k_coarse<2>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, accumulate, active);
-            b0 += 2;
-        } else {
-            hipLaunchKernelGGL(k_coarse<1>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, accumulate, active);
-            b0 += 1;
+    if (nb >= 4 && scratch) {
+        // X read once for all right-hand sides
+        dim3 g((N + CG_BM - 1) / CG_BM, CG_SPLIT, (nb + CG_BN - 1) / CG_BN);
+        hipLaunchKernelGGL(k_coarse_gemm, g, dim3(256), 0, s, X, N, f, fs, nb, scratch);
+        size_t tot = (size_t)nb * N;
+        hipLaunchKernelGGL(k_coarse_finish, dim3((unsigned)std::min<size_t>(8192, (tot + 255) / 256)),
+                           dim3(256), 0, s, scratch, N, nb, v, vs, scale, accumulate, active);
+    } else {
+        int b0 = 0;
+        while (b0 < nb) {
+            int left = nb - b0;
+            if (left >= 2) {
+                hipLaunchKernelGGL(k_coarse<2>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, accumulate,
+                                   active);
+                b0 += 2;
+            } else {
+                hipLaunchKernelGGL(k_coarse<1>, grid, block, 0, s, X, N, f, fs, v, vs, b0, scale, accumulate,
+                                   active);
+                b0 += 1;
+            }
         }
     }
-    // the dense inverse read once, each right-hand side read and written
     prof_mark(HELM_PROF_COARSE, s, false, 8.0 * N * N + (accumulate ? 24.0 : 16.0) * N * nb, 1, false);
 }
 

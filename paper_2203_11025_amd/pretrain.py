@@ -7,7 +7,9 @@ random media, all in the library's kernels.
 Media: n^2 grids (default 512, network on 256^2), slowness from seeded white
 noise smoothed by a Gaussian of sigma n/32 cells mapped to [0.25, 1], seeds
 10000 + i; 10 points per wavelength; the quadratic sponge.  Each Adam step
-(lr 1e-3, batch 16) takes `per_medium` samples from consecutive media.  The
+(lr 1e-3 by default, optionally decayed linearly in time, batch 16) takes
+`per_medium` samples from consecutive media.  `--resume` continues from
+saved weights (e.g. fine-tuning at a larger grid).  The
 weights are saved every `--save-every` seconds and at the end; a short
 evaluation compares FGMRES iterations of M_VU and plain SL on a held-out
 medium.
@@ -56,6 +58,8 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--per-medium", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-final", type=float, default=None,
+                    help="decay the learning rate linearly (in time) to this value; default constant")
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--resume", default=None)
     ap.add_argument("--out", default=DEFAULT_OUT)
@@ -87,7 +91,11 @@ def main(argv=None):
     step, chunk, hist = 0, 200, []
     while step < a.max_steps and time.perf_counter() - t0 < budget:
         k = min(chunk, a.max_steps - step)
-        losses = train.train_pair(enc, sol, handles, steps=k, batch=a.batch, lr=a.lr,
+        lr = a.lr
+        if a.lr_final is not None:
+            f = min(1.0, (time.perf_counter() - t0) / budget)
+            lr = a.lr + (a.lr_final - a.lr) * f
+        losses = train.train_pair(enc, sol, handles, steps=k, batch=a.batch, lr=lr,
                                   seed=a.seed * 100003 + step, per_medium=a.per_medium)
         # rotate the starting medium so consecutive chunks see every medium
         handles = handles[k * a.batch // a.per_medium % len(handles):] + \

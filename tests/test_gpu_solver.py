@@ -64,6 +64,25 @@ def test_vcycle_parity(H, oracle, n, levels):
         assert relerr(v[k], ref) <= 1e-5, (n, levels, k, relerr(v[k], ref))
 
 
+@pytest.mark.parametrize("nb", [5, 37])
+def test_vcycle_many_rhs_parity(H, oracle, nb):
+    """Four or more right-hand sides take the tiled GEMM for the coarsest
+    solve (37: two right-hand-side tiles, the second partial); every one is
+    compared with the oracle, with a zero field in the batch."""
+    n, levels = 64, 2
+    kap, gam, om = medium(n, 300 + nb)
+    h = handle(H, kap, gam, om, levels=levels)
+    ho = oracle.Hierarchy(kap, gam, om, levels)
+    f = crandn(nb, n, n)
+    f[3] = 0
+    v = h.vcycle(torch.from_numpy(f).cuda()).cpu().numpy()
+    assert np.all(v[3] == 0)
+    for k in range(nb):
+        if k != 3:
+            ref = ho.vcycle(f[k])
+            assert relerr(v[k], ref) <= 1e-5, (nb, k, relerr(v[k], ref))
+
+
 def test_vcycle_point_source_and_zero(H, oracle):
     n = 128
     kap, gam, om = medium(n, 7)
