@@ -12,19 +12,26 @@ namespace helm {
 
 using bf16 = __bf16;
 
-// One input source of a convolution: NHWC bf16, channel count a multiple of
-// 32; `shared` = 1 when every batch entry reads batch entry 0 (a context
-// tensor computed once per medium).
+// One input source of a convolution: NHWC bf16 taking C channels (a
+// multiple of 32) of the concatenated input; `shared` = 1 when every batch
+// entry reads batch entry 0 (a context tensor computed once per medium).
+// The tensor itself may hold fewer channels per pixel (`stride`, a multiple
+// of 8; 0 means C): the channels from `stride` to C read as zero.
 struct Src {
     const bf16 *p;
     int C;
     int shared;  // one tensor for the whole batch (read as sample 0)
+    int stride = 0;
 };
 // Up to three sources concatenated along channels (by addressing only).
+// The convolution weights of these Ctot channels start at channel woff of
+// rows of wstride channels (0: Ctot, i.e. the weights cover exactly these
+// sources); a subset of a layer's inputs is convolved with its weight slice.
 struct Srcs {
     Src s[3];
     int n;
     int Ctot;
+    int wstride = 0, woff = 0;
 };
 
 // ---------------------------------------------------------------- convolution
@@ -36,10 +43,18 @@ struct Srcs {
 //   pool     : also write the 2x2 max-pooled activation [B][H/2][W/2][Cout]
 //   head_out : apply the 1x1 head (head_w [2][Cout], head_b [2]) and write
 //              [B][H][W][2] FP32 instead of the activation (needs Cout <= 64)
+//   cmap     : FP16 [H][W][Cout] added to the raw convolution before the
+//              folded BN, the same for every batch entry (the part of the
+//              convolution over a context shared by the batch)
+// and of a raw (mode 0) convolution:
+//   raw16    : write the raw output as FP16 [B][H][W][Cout] here instead
+//              of out32
 struct ConvEpi {
     bf16 *pool = nullptr;
     const float *head_w = nullptr, *head_b = nullptr;
     float *head_out = nullptr;
+    const _Float16 *cmap = nullptr;
+    _Float16 *raw16 = nullptr;
 };
 void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout, int mode,
                     float *out32, bf16 *out16, const float *scale, const float *shift,
@@ -99,13 +114,14 @@ void launch_head_bwd(const float *dout, const bf16 *a, size_t P, int C, const fl
 
 // ---------------------------------------------------------------- wrapper
 // rc = R(h^2 r) per right-hand side (fine n -> coarse n/2), s_b = RMS |rc|,
-// x0[b][I][J][0..31] = (Re rc / s, Im rc / s, kappa_c, 0, ...), kappa_c either
+// x0[b][I][J][0..7] = (Re rc / s, Im rc / s, kappa_c, 0, ...) (x0_stride
+// channels per pixel, a multiple of 8; the others untouched), kappa_c either
 // injected from the fine slowness (kappa_fine != null) or given on the coarse
 // grid.  s[b] = 0 marks an all-zero residual.
 // Sample b of the network batch reads right-hand side idx[b] (b if idx is null).
 void launch_net_input(const float2 *r, size_t rstride, int nb, int n, const float *kappa_fine,
                       const float *kappa_c, float2 *rc, double *part, double *s, bf16 *x0,
-                      hipStream_t s_, const int *idx = nullptr);
+                      int x0_stride, hipStream_t s_, const int *idx = nullptr);
 // e (+)= P (s_q (out0 + i out1)) on the fine grid for each of the nb
 // right-hand sides, q = pos[b] its sample in the network batch (b if pos is
 // null); q < 0 or mask[b] == 0: e_b = 0 (untouched when accumulating).

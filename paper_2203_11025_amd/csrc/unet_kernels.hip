@@ -20,6 +20,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -84,7 +85,13 @@ __device__ __forceinline__ f8 up_blend8(const f8 &a00, const f8 &a01, const f8 &
 // change) are loaded into registers; they go to LDS after a barrier.  With a
 // single chunk the weights stay in LDS for every tile.  For each kx the
 // MF + 2 halo rows a wavefront touches are read once and serve all three ky.
-template <int MF, int NF, int EPI>  // EPI: 0 store, 1 store and pool, 2 head
+//
+// IN8: a single source with 8 channels per pixel (the network input).  A K
+// step of 32 then spans four taps of 8 channels (lane group l / 16 takes tap
+// 4 s + l / 16 of step s), so the nine taps take three steps instead of nine;
+// the halo holds 8 channels per pixel and the weights 12 tap slots (the last
+// three zero).
+template <int MF, int NF, int EPI, bool IN8 = false>  // EPI: 0 store, 1 store and pool, 2 head
 __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B, int H, int W,
                                                  const bf16 *__restrict__ Wt, int Cout, int mode,
                                                  float *__restrict__ out32,
@@ -99,11 +106,14 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
     constexpr int WS = 9 * 32 + 8;   // LDS halves per output channel row
     constexpr int NH = (HY * HX * 4 + 255) / 256;  // halo 16-byte pieces per thread
     constexpr int NW = (CO * 36 + 255) / 256;      // weight 16-byte pieces per thread
+    constexpr int WS8 = 12 * 8 + 8;                // IN8: LDS halves per output channel row
+    constexpr int NH8 = (HY * HX + 255) / 256, NW8 = (CO * 12 + 255) / 256;
     __shared__ __attribute__((aligned(16))) bf16 sx[HY * HX * PS];
     __shared__ __attribute__((aligned(16))) bf16 sw[CO * WS];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int co0 = blockIdx.y * CO;
     const int nch = in.Ctot / 32;
+    const int wst = in.wstride ? in.wstride : in.Ctot;  // weight row length
     const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
     const int ntiles = B * tiles_x * tiles_y;
     const int gx = gridDim.x;
@@ -130,22 +140,47 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
     uint4 hreg[NH], wreg[NW];
     auto load_stage = [&](int tx, int ty, int b, int ch, bool with_w) {
         const int x0 = tx * TW - 1, y0 = ty * TH - 1;
+        if constexpr (IN8) {
+            const bf16 *src = in.s[0].p + ((size_t)(in.s[0].shared ? 0 : b) * H * W) * 8;
+            const bool inside = x0 >= 0 && y0 >= 0 && x0 + HX <= W && y0 + HY <= H;
+#pragma unroll
+            for (int k = 0; k < NH8; ++k) {
+                const int pix = tid + 256 * k, hy = pix / HX;
+                const int y = y0 + hy, x = x0 + pix - hy * HX;
+                uint4 v = {0u, 0u, 0u, 0u};
+                if (pix < HY * HX && (inside || (y >= 0 && y < H && x >= 0 && x < W)))
+                    v = *reinterpret_cast<const uint4 *>(src + (size_t)(y * W + x) * 8);
+                hreg[k] = v;
+            }
+            if (with_w) {
+#pragma unroll
+                for (int k = 0; k < NW8; ++k) {
+                    const int idx = tid + 256 * k, co = idx / 12, tap = idx - co * 12;
+                    uint4 v = {0u, 0u, 0u, 0u};
+                    if (idx < CO * 12 && tap < 9 && co0 + co < Cout)
+                        v = *reinterpret_cast<const uint4 *>(Wt + ((size_t)(co0 + co) * 9 + tap) * wst + in.woff);
+                    wreg[k] = v;
+                }
+            }
+            return;
+        }
         int coff = ch * 32, s = 0;
         while (s < in.n - 1 && coff >= in.s[s].C) {
             coff -= in.s[s].C;
             ++s;
         }
-        const int Cs = in.s[s].C;
+        const int Cs = in.s[s].stride ? in.s[s].stride : in.s[s].C;  // channels per pixel in memory
         const bf16 *src = in.s[s].p + ((size_t)(in.s[s].shared ? 0 : b) * H * W) * Cs + coff +
                           (tid & 3) * 8;
         const bool inside = x0 >= 0 && y0 >= 0 && x0 + HX <= W && y0 + HY <= H;
+        const bool seg_ok = coff + (tid & 3) * 8 < Cs;  // this thread's 8 channels exist
 #pragma unroll
         for (int k = 0; k < NH; ++k) {
             // this thread's piece: halo pixel (hy, hx), 8-channel segment tid % 4
             const int idx = tid + 256 * k, pix = idx >> 2, hy = pix / HX;
             const int y = y0 + hy, x = x0 + pix - hy * HX;
             uint4 v = {0u, 0u, 0u, 0u};
-            if (idx < HY * HX * 4 && (inside || (y >= 0 && y < H && x >= 0 && x < W)))
+            if (idx < HY * HX * 4 && seg_ok && (inside || (y >= 0 && y < H && x >= 0 && x < W)))
                 v = *reinterpret_cast<const uint4 *>(src + (size_t)(y * W + x) * Cs);
             hreg[k] = v;
         }
@@ -156,13 +191,28 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
                 const int rr = idx >> 2, co = rr / 9, tap = rr - co * 9;
                 uint4 v = {0u, 0u, 0u, 0u};
                 if (idx < CO * 36 && co0 + co < Cout)
-                    v = *reinterpret_cast<const uint4 *>(Wt + ((size_t)(co0 + co) * 9 + tap) * in.Ctot +
+                    v = *reinterpret_cast<const uint4 *>(Wt + ((size_t)(co0 + co) * 9 + tap) * wst + in.woff +
                                                          ch * 32 + (idx & 3) * 8);
                 wreg[k] = v;
             }
         }
     };
     auto store_stage = [&](bool with_w) {
+        if constexpr (IN8) {
+#pragma unroll
+            for (int k = 0; k < NH8; ++k) {
+                const int pix = tid + 256 * k;
+                if (pix < HY * HX) *reinterpret_cast<uint4 *>(&sx[pix * 8]) = hreg[k];
+            }
+            if (with_w) {
+#pragma unroll
+                for (int k = 0; k < NW8; ++k) {
+                    const int idx = tid + 256 * k, co = idx / 12;
+                    if (idx < CO * 12) *reinterpret_cast<uint4 *>(&sw[co * WS8 + (idx - co * 12) * 8]) = wreg[k];
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < NH; ++k) {
             const int idx = tid + 256 * k;
@@ -203,6 +253,29 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
             }
             load_stage(ntx, nty, nbb, nchk, reload_w);
         }
+        if constexpr (IN8) {
+            // step s: this lane's tap 4 s + l / 16 (none for 9..11)
+            bf16x8 wa[3][NF];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int nf = 0; nf < NF; ++nf)
+                    wa[k][nf] = *reinterpret_cast<const bf16x8 *>(
+                        &sw[(nf * 16 + (lane & 15)) * WS8 + (4 * k + (lane >> 4)) * 8]);
+#pragma unroll
+            for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int t = 4 * k + (lane >> 4), tc = t < 9 ? t : 8;
+                    const int ky = tc / 3, kx = tc - 3 * ky;
+                    bf16x8 xb = *reinterpret_cast<const bf16x8 *>(
+                        &sx[((wv * MF + mf + ky) * HX + (lane & 15) + kx) * 8]);
+                    if (t >= 9) xb = bf16x8{};
+#pragma unroll
+                    for (int nf = 0; nf < NF; ++nf)
+                        acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[k][nf], xb, acc[mf][nf], 0, 0, 0);
+                }
+        } else {
         // rows in groups of RG pixel fragments (RG + 2 halo rows live at once)
         constexpr int RG = MF > 4 ? MF / 2 : MF;
 #pragma unroll
@@ -234,6 +307,7 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
                 if (MF > 4) __builtin_amdgcn_sched_barrier(0);
             }
         }
+        }
         if (EPI == 0 && st % nch == nch - 1) {
             // the tile is complete: lane (l % 16, l / 16) holds pixel x0 + l % 16
             // of each row and channels 4 (l / 16) .. + 3 of each fragment
@@ -262,11 +336,21 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
                     if (pix_ok && (full_co || co0 + nf * 16 + 4 * (lane >> 4) < Cout)) {
                         const f32x4 v = acc[mf][nf];
                         if (mode == 0) {
-                            *reinterpret_cast<float4 *>(out32 + base + nf * 16) =
-                                make_float4(v[0], v[1], v[2], v[3]);
+                            if (epi.raw16)
+                                *reinterpret_cast<f16x4 *>(epi.raw16 + base + nf * 16) =
+                                    f16x4{(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
+                            else
+                                *reinterpret_cast<float4 *>(out32 + base + nf * 16) =
+                                    make_float4(v[0], v[1], v[2], v[3]);
                         } else {
-                            float z0 = v[0] * sc[nf].x + sh[nf].x, z1 = v[1] * sc[nf].y + sh[nf].y;
-                            float z2 = v[2] * sc[nf].z + sh[nf].z, z3 = v[3] * sc[nf].w + sh[nf].w;
+                            f16x4 m = f16x4{};
+                            if (epi.cmap)
+                                m = *reinterpret_cast<const f16x4 *>(
+                                    epi.cmap + ((size_t)y * W + x) * Cout + co0 + 4 * (lane >> 4) + nf * 16);
+                            float z0 = (v[0] + (float)m[0]) * sc[nf].x + sh[nf].x;
+                            float z1 = (v[1] + (float)m[1]) * sc[nf].y + sh[nf].y;
+                            float z2 = (v[2] + (float)m[2]) * sc[nf].z + sh[nf].z;
+                            float z3 = (v[3] + (float)m[3]) * sc[nf].w + sh[nf].w;
                             z0 = z0 > 0.f ? z0 : slope * z0;
                             z1 = z1 > 0.f ? z1 : slope * z1;
                             z2 = z2 > 0.f ? z2 : slope * z2;
@@ -305,13 +389,21 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
                 const float scv[4] = {sc.x, sc.y, sc.z, sc.w}, shv[4] = {sh.x, sh.y, sh.z, sh.w};
                 // folded BN and LeakyReLU, rounded to bf16 (kept as floats)
 #pragma unroll
-                for (int mf = 0; mf < MF; ++mf)
+                for (int mf = 0; mf < MF; ++mf) {
+                    const int y = ty * TH + wv * MF + mf;
+                    float mv[4] = {0.f, 0.f, 0.f, 0.f};
+                    if (epi.cmap && y < H && x < W && co_ok) {
+                        const f16x4 m = *reinterpret_cast<const f16x4 *>(epi.cmap + ((size_t)y * W + x) * Cout + co);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) mv[q] = (float)m[q];
+                    }
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        float z = acc[mf][nf][q] * scv[q] + shv[q];
+                        float z = (acc[mf][nf][q] + mv[q]) * scv[q] + shv[q];
                         z = z > 0.f ? z : slope * z;
                         acc[mf][nf][q] = (float)(bf16)z;
                     }
+                }
                 if (EPI != 2) {
 #pragma unroll
                     for (int mf = 0; mf < MF; ++mf) {
@@ -458,13 +550,14 @@ __global__ __launch_bounds__(256) void k_wgrad(Srcs x, const bf16 *__restrict__ 
                 ++s;
             }
         const bf16 *src = x.s[s].p;
-        const int Cs = x.s[s].C;
+        const int Cs = x.s[s].stride ? x.s[s].stride : x.s[s].C;  // channels per pixel in memory
         const size_t rowbase = ((size_t)(x.s[s].shared ? 0 : b) * H + (rowok ? yr : 0)) * W;
+        const bool seg_ok = coff < Cs;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int xs = x0 - 1 + 8 * j + kx + i;
             pv[i] = make_uint4(0u, 0u, 0u, 0u);
-            if (rowok && xs >= 0 && xs < W)
+            if (rowok && seg_ok && xs >= 0 && xs < W)
                 pv[i] = *reinterpret_cast<const uint4 *>(src + (rowbase + xs) * Cs + coff);
         }
         uint4 o[8];
@@ -777,37 +870,37 @@ __global__ void k_bn_bwd_apply(const float *__restrict__ da, const float *__rest
 
 // ------------------------------------------------------------------ pooling
 // thread per (output pixel, 8-channel group)
-__global__ void k_maxpool_fwd(const bf16 *__restrict__ in, int B, int H, int W, int C,
-                              bf16 *__restrict__ out, uint8_t *__restrict__ arg)
+// grid (pixels x channel groups of an output row, output rows, batch)
+__global__ void k_maxpool_fwd(const bf16 *__restrict__ in, int H, int W, int C, bf16 *__restrict__ out,
+                              uint8_t *__restrict__ arg)
 {
-    const int Ho = H / 2, Wo = W / 2, G = C / 8;
-    const int n = B * Ho * Wo * G;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        int g = i % G, pix = i / G;
-        int xo = pix % Wo, r = pix / Wo;
-        int yo = r % Ho, b = r / Ho;
-        size_t base = (((size_t)b * H + 2 * yo) * W + 2 * xo) * C + 8 * g;
-        f8 v0 = ld8(in + base), v1 = ld8(in + base + C);
-        f8 v2 = ld8(in + base + (size_t)W * C), v3 = ld8(in + base + (size_t)W * C + C);
-        f8 o;
-        uint8_t k8[8];
+    const int Wo = W / 2, G = C / 8;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Wo * G) return;
+    const int yo = blockIdx.y, b = blockIdx.z;
+    const int xo = t / G, g = t - xo * G;
+    const size_t base = (((size_t)b * H + 2 * yo) * W + 2 * xo) * C + 8 * g;
+    const f8 v0 = ld8(in + base), v1 = ld8(in + base + C);
+    const f8 v2 = ld8(in + base + (size_t)W * C), v3 = ld8(in + base + (size_t)W * C + C);
+    f8 o;
+    uint8_t k8[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            float best = v0.v[q];
-            uint8_t k = 0;
-            if (v1.v[q] > best) { best = v1.v[q]; k = 1; }
-            if (v2.v[q] > best) { best = v2.v[q]; k = 2; }
-            if (v3.v[q] > best) { best = v3.v[q]; k = 3; }
-            o.v[q] = best;
-            k8[q] = k;
-        }
-        st8(out + (size_t)pix * C + 8 * g, o);
-        if (arg) {
-            uint2 packed;
-            packed.x = k8[0] | (k8[1] << 8) | (k8[2] << 16) | ((uint32_t)k8[3] << 24);
-            packed.y = k8[4] | (k8[5] << 8) | (k8[6] << 16) | ((uint32_t)k8[7] << 24);
-            *reinterpret_cast<uint2 *>(arg + (size_t)pix * C + 8 * g) = packed;
-        }
+    for (int q = 0; q < 8; ++q) {
+        float best = v0.v[q];
+        uint8_t k = 0;
+        if (v1.v[q] > best) { best = v1.v[q]; k = 1; }
+        if (v2.v[q] > best) { best = v2.v[q]; k = 2; }
+        if (v3.v[q] > best) { best = v3.v[q]; k = 3; }
+        o.v[q] = best;
+        k8[q] = k;
+    }
+    const size_t pix = ((size_t)b * (H / 2) + yo) * Wo + xo;
+    st8(out + pix * C + 8 * g, o);
+    if (arg) {
+        uint2 packed;
+        packed.x = k8[0] | (k8[1] << 8) | (k8[2] << 16) | ((uint32_t)k8[3] << 24);
+        packed.y = k8[4] | (k8[5] << 8) | (k8[6] << 16) | ((uint32_t)k8[7] << 24);
+        *reinterpret_cast<uint2 *>(arg + pix * C + 8 * g) = packed;
     }
 }
 
@@ -830,24 +923,24 @@ __global__ void k_maxpool_bwd(const float *__restrict__ dout, int cstride, int c
 // ------------------------------------------------------------------ upsampling
 
 // thread per (fine pixel, 8-channel group)
-__global__ void k_up2_fwd(const bf16 *__restrict__ in, int B, int h, int w, int C,
-                          bf16 *__restrict__ out)
+// grid (pixels x channel groups of a fine row, fine rows, batch): the row's
+// coarse rows and weights are uniform per block
+__global__ void k_up2_fwd(const bf16 *__restrict__ in, int h, int w, int C, bf16 *__restrict__ out)
 {
-    const int H = 2 * h, W = 2 * w, G = C / 8;
-    const int n = B * H * W * G;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        int g = i % G, pix = i / G;
-        int x = pix % W, r = pix / W;
-        int y = r % H, b = r / H;
-        int y0, y1, x0, x1;
-        float ly, lx;
-        up_src(y, h, y0, y1, ly);
-        up_src(x, w, x0, x1, lx);
-        const bf16 *pb = in + (size_t)b * h * w * C + 8 * g;
-        f8 a00 = ld8(pb + ((size_t)y0 * w + x0) * C), a01 = ld8(pb + ((size_t)y0 * w + x1) * C);
-        f8 a10 = ld8(pb + ((size_t)y1 * w + x0) * C), a11 = ld8(pb + ((size_t)y1 * w + x1) * C);
-        st8(out + (size_t)pix * C + 8 * g, up_blend8(a00, a01, a10, a11, ly, lx));
-    }
+    const int W = 2 * w, G = C / 8;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= W * G) return;
+    const int y = blockIdx.y, b = blockIdx.z;
+    const int x = t / G, g = t - x * G;
+    int y0, y1, x0, x1;
+    float ly, lx;
+    up_src(y, h, y0, y1, ly);
+    up_src(x, w, x0, x1, lx);
+    const bf16 *pb = in + (size_t)b * h * w * C + 8 * g;
+    const bf16 *r0 = pb + (size_t)y0 * w * C, *r1 = pb + (size_t)y1 * w * C;
+    const f8 a00 = ld8(r0 + x0 * C), a01 = ld8(r0 + x1 * C);
+    const f8 a10 = ld8(r1 + x0 * C), a11 = ld8(r1 + x1 * C);
+    st8(out + (((size_t)b * 2 * h + y) * W + x) * C + 8 * g, up_blend8(a00, a01, a10, a11, ly, lx));
 }
 
 // 1D adjoint weights of the half-pixel x2 interpolation: coarse i receives
@@ -1059,27 +1152,28 @@ __global__ void k_rms(const double *__restrict__ part, int nblk, int nc, double 
     s[b] = sqrt(a / ((double)nc * nc));
 }
 
-__global__ void k_pack_input(const float2 *__restrict__ rc, const double *__restrict__ s, int nb,
-                             int n, const float *__restrict__ kf, const float *__restrict__ kc,
-                             bf16 *__restrict__ x0)
+// grid (coarse columns, coarse rows, batch)
+__global__ void k_pack_input(const float2 *__restrict__ rc, const double *__restrict__ s, int n,
+                             const float *__restrict__ kf, const float *__restrict__ kc,
+                             bf16 *__restrict__ x0, int xs)
 {
     const int nc = n / 2;
-    const int total = nb * nc * nc;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-        int b = i / (nc * nc), pix = i - b * nc * nc;
-        int I = pix / nc, J = pix - I * nc;
-        float inv = s[b] > 0.0 ? (float)(1.0 / s[b]) : 0.f;
-        float2 v = rc[i];
-        float kap = kf ? kf[(size_t)(2 * I) * n + 2 * J] : kc[i];
-        f8 head;
-        head.v[0] = v.x * inv;
-        head.v[1] = v.y * inv;
-        head.v[2] = kap;
+    const int J = blockIdx.x * blockDim.x + threadIdx.x;
+    if (J >= nc) return;
+    const int I = blockIdx.y, b = blockIdx.z;
+    const size_t i = ((size_t)b * nc + I) * nc + J;
+    const double sb = s[b];
+    const float inv = sb > 0.0 ? (float)(1.0 / sb) : 0.f;
+    const float2 v = rc[i];
+    const float kap = kf ? kf[(size_t)(2 * I) * n + 2 * J] : kc[i];
+    f8 head;
+    head.v[0] = v.x * inv;
+    head.v[1] = v.y * inv;
+    head.v[2] = kap;
 #pragma unroll
-        for (int q = 3; q < 8; ++q) head.v[q] = 0.f;
-        // channels 8..31 of x0 are zero from allocation on and never written
-        st8(x0 + (size_t)i * 32, head);
-    }
+    for (int q = 3; q < 8; ++q) head.v[q] = 0.f;
+    // channels 8 .. xs - 1 (if any) are zero from allocation on
+    st8(x0 + i * xs, head);
 }
 
 // e (+)= P(s (out0 + i out1)), P bilinear prolongation (transposed stride-2
@@ -1088,22 +1182,21 @@ __global__ void k_pack_input(const float2 *__restrict__ rc, const double *__rest
 // (i, 2J + 1) (columns J, J + 1, weight 1/2 each); fine row i reads coarse
 // row i / 2 (even i, weight 1) or rows (i - 1) / 2 and (i + 1) / 2 (odd i,
 // weight 1/2 each), zero outside.
-__global__ void k_net_output(const float *__restrict__ out, const double *__restrict__ s, int nb,
-                             int n, float2 *__restrict__ e, size_t es, int accumulate,
+// grid (coarse columns, fine rows, right-hand sides)
+__global__ void k_net_output(const float *__restrict__ out, const double *__restrict__ s, int n,
+                             float2 *__restrict__ e, size_t es, int accumulate,
                              const int *__restrict__ mask, const int *__restrict__ pos)
 {
     const int nc = n / 2;
-    const size_t total = (size_t)nb * n * nc;
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (size_t)gridDim.x * blockDim.x) {
-        const int J = (int)(idx % nc);
-        const size_t r = idx / nc;
-        const int i = (int)(r % n), b = (int)(r / n);
+    const int J = blockIdx.x * blockDim.x + threadIdx.x;
+    if (J >= nc) return;
+    const int i = blockIdx.y, b = blockIdx.z;
+    {
         float4 *pe = reinterpret_cast<float4 *>(e + (size_t)b * es + (size_t)i * n + 2 * J);
         const int q = pos ? pos[b] : b;  // the right-hand side's sample in the network batch
         if (q < 0 || (mask && !mask[b])) {
             if (!accumulate) *pe = make_float4(0.f, 0.f, 0.f, 0.f);
-            continue;
+            return;
         }
         const float2 *ob = reinterpret_cast<const float2 *>(out + (size_t)q * nc * nc * 2);
         float2 c0 = make_float2(0.f, 0.f), c1 = c0;  // rows blended at columns J and J + 1
@@ -1329,6 +1422,13 @@ inline int red_blocks(size_t P, int C)
 
 namespace {
 
+// one source of 8 channels per pixel padded to a 32-channel block: the
+// three-step form of k_conv3x3
+bool conv_in8(const Srcs &in)
+{
+    return in.n == 1 && in.Ctot == 32 && in.s[0].stride == 8;
+}
+
 // launch shape of one convolution: pixel rows per wavefront fragment group
 // (tile height 4 MF) and the number of workgroups walking the tiles
 struct ConvShape {
@@ -1345,6 +1445,21 @@ void conv_dispatch(const ConvShape &c, const Srcs &in, int B, int H, int W, cons
     const long long ntiles = (long long)B * ((H + 4 * c.mf - 1) / (4 * c.mf)) * ((W + 15) / 16);
     dim3 grid((unsigned)std::max<long long>(1, std::min<long long>(ntiles, c.blocks)), ncob);
     const int ep = epi.head_out ? 2 : (epi.pool ? 1 : 0);
+    if (conv_in8(in) && ep == 0) {
+        if (c.mf == 4 && NF == 4)
+            hipLaunchKernelGGL((k_conv3x3<4, 4, 0, true>), grid, dim3(256), 0, s, in, B, H, W, Wt, Cout, mode,
+                               out32, out16, scale, shift, slope, epi);
+        else if (c.mf == 4)
+            hipLaunchKernelGGL((k_conv3x3<4, 2, 0, true>), grid, dim3(256), 0, s, in, B, H, W, Wt, Cout, mode,
+                               out32, out16, scale, shift, slope, epi);
+        else if (NF == 4)
+            hipLaunchKernelGGL((k_conv3x3<2, 4, 0, true>), grid, dim3(256), 0, s, in, B, H, W, Wt, Cout, mode,
+                               out32, out16, scale, shift, slope, epi);
+        else
+            hipLaunchKernelGGL((k_conv3x3<2, 2, 0, true>), grid, dim3(256), 0, s, in, B, H, W, Wt, Cout, mode,
+                               out32, out16, scale, shift, slope, epi);
+        return;
+    }
 #define CONV_LAUNCH(mf, nf)                                                                                 \
     do {                                                                                                    \
         if (ep == 2)                                                                                        \
@@ -1379,8 +1494,9 @@ ConvShape conv_default(int H, int Cout)
 // epilogue and source variant of a convolution (part of the tuning key)
 int conv_variant(const Srcs &in, int mode, const ConvEpi &epi)
 {
-    (void)in;
-    return mode | ((epi.pool != nullptr) << 1) | ((epi.head_out != nullptr) << 2);
+    return mode | ((epi.pool != nullptr) << 1) | ((epi.head_out != nullptr) << 2) |
+           ((epi.cmap != nullptr) << 3) | ((in.wstride != 0 && in.wstride != in.Ctot) << 4) |
+           (conv_in8(in) << 5) | ((epi.raw16 != nullptr) << 6);
 }
 
 struct Tuner {
@@ -1434,9 +1550,13 @@ void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
 {
     ConvShape c = conv_default(H, Cout);
     if (g_tune.enabled) {
+        // batch sizes share an entry per power-of-two bucket: a batch that
+        // shrinks as right-hand sides converge is not tuned again each time
+        int Bk = 1;
+        while (Bk < B) Bk *= 2;
+        const std::array<int, 6> key{Bk, H, W, in.Ctot, Cout, conv_variant(in, mode, epi)};
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
-            const std::array<int, 6> key{B, H, W, in.Ctot, Cout, conv_variant(in, mode, epi)};
             std::lock_guard<std::mutex> lk(g_tune.mu);
             auto it = g_tune.table.find(key);
             if (it == g_tune.table.end())
@@ -1445,7 +1565,7 @@ void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
             c = it->second;
         } else {
             std::lock_guard<std::mutex> lk(g_tune.mu);
-            auto it = g_tune.table.find({B, H, W, in.Ctot, Cout, conv_variant(in, mode, epi)});
+            auto it = g_tune.table.find(key);
             if (it != g_tune.table.end()) c = it->second;
         }
     }
@@ -1542,8 +1662,9 @@ void launch_bn_act_bwd(const float *da, const float *y, size_t P, int C, const f
 void launch_maxpool_fwd(const bf16 *in, int B, int H, int W, int C, bf16 *out, uint8_t *arg,
                         hipStream_t s)
 {
-    size_t n = (size_t)B * (H / 2) * (W / 2) * (C / 8);
-    hipLaunchKernelGGL(k_maxpool_fwd, dim3(grid_for(n)), dim3(256), 0, s, in, B, H, W, C, out, arg);
+    const int row = (W / 2) * (C / 8);
+    hipLaunchKernelGGL(k_maxpool_fwd, dim3((row + 255) / 256, H / 2, B), dim3(256), 0, s, in, H, W, C, out,
+                       arg);
 }
 
 void launch_maxpool_bwd(const float *dout, const uint8_t *arg, int B, int H, int W, int C,
@@ -1556,8 +1677,8 @@ void launch_maxpool_bwd(const float *dout, const uint8_t *arg, int B, int H, int
 
 void launch_up2_fwd(const bf16 *in, int B, int h, int w, int C, bf16 *out, hipStream_t s)
 {
-    size_t n = (size_t)B * 4 * h * w * (C / 8);
-    hipLaunchKernelGGL(k_up2_fwd, dim3(grid_for(n)), dim3(256), 0, s, in, B, h, w, C, out);
+    const int row = 2 * w * (C / 8);
+    hipLaunchKernelGGL(k_up2_fwd, dim3((row + 255) / 256, 2 * h, B), dim3(256), 0, s, in, h, w, C, out);
 }
 
 void launch_up2_bwd(const float *dout, int cstride, int coff, int B, int h, int w, int C,
@@ -1608,7 +1729,7 @@ void launch_head_bwd(const float *dout, const bf16 *a, size_t P, int C, const fl
 }
 
 void launch_net_input(const float2 *r, size_t rstride, int nb, int n, const float *kappa_fine,
-                      const float *kappa_c, float2 *rc, double *part, double *s, bf16 *x0,
+                      const float *kappa_c, float2 *rc, double *part, double *s, bf16 *x0, int x0_stride,
                       hipStream_t st, const int *idx)
 {
     int nc = n / 2;
@@ -1616,16 +1737,15 @@ void launch_net_input(const float2 *r, size_t rstride, int nb, int n, const floa
     hipLaunchKernelGGL(k_restrict_scaled, dim3(nblk, nb), dim3(256), 0, st, r, rstride, n, rc, part,
                        nblk, idx);
     hipLaunchKernelGGL(k_rms, dim3(nb), dim3(64), 0, st, part, nblk, nc, s);
-    size_t tot = (size_t)nb * nc * nc;
-    hipLaunchKernelGGL(k_pack_input, dim3(grid_for(tot)), dim3(256), 0, st, rc, s, nb, n, kappa_fine,
-                       kappa_c, x0);
+    hipLaunchKernelGGL(k_pack_input, dim3((nc + 255) / 256, nc, nb), dim3(256), 0, st, rc, s, n, kappa_fine,
+                       kappa_c, x0, x0_stride);
 }
 
 void launch_net_output(const float *out, const double *s, int nb, int n, float2 *e, size_t estride,
                        int accumulate, hipStream_t st, const int *mask, const int *pos)
 {
-    size_t tot = (size_t)nb * n * (n / 2);
-    hipLaunchKernelGGL(k_net_output, dim3(grid_for(tot)), dim3(256), 0, st, out, s, nb, n, e, estride,
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_net_output, dim3((n / 2 + 255) / 256, n, nb), dim3(256), 0, st, out, s, n, e, estride,
                        accumulate, mask, pos);
 }
 

@@ -40,6 +40,8 @@ struct unet_net {
     std::vector<helm::bf16 *> pooled, up;
     std::vector<uint8_t *> arg;
     helm::bf16 *x0 = nullptr, *dy = nullptr;
+    // channels per pixel of the network input x0: in_ch rounded up to 8
+    int x0_stride() const { return (cfg.in_ch + 7) / 8 * 8; }
     float *out = nullptr, *gout = nullptr, *dX = nullptr, *dW = nullptr, *wpart = nullptr;
     float *xin = nullptr;
     double *red = nullptr, *s = nullptr, *dloss = nullptr;
@@ -49,6 +51,18 @@ struct unet_net {
     std::vector<const helm::bf16 *> ctxp;
     std::vector<helm::bf16 *> ctxbuf;
     int ctx_shared = 0, ctx_B = 0, ctx_H = 0, ctx_valid = 0;
+    // With a context shared by the batch, the part of each context-taking
+    // convolution over the context is the same for every sample: cmap[i]
+    // (FP16 [H_l][W_l][cout], layer i) holds it, computed when the context is
+    // attached; inference adds it in the epilogue instead of convolving the
+    // context again.  Invalid once the weights change.
+    std::vector<_Float16 *> cmap;
+    int cmap_valid = 0;
+    bool use_cmap(bool training, int H) const
+    {
+        return !training && cfg.context && ctx_valid && ctx_shared && cmap_valid && H == ctx_H;
+    }
+    void compute_cmaps(hipStream_t st);
     int gen = 0;  // bumped when workspace or context storage moves (captured graphs hold pointers)
     std::vector<float *> gctx;
     int attach_context(const unet_net &enc, int nb, int H, int W, hipStream_t st);
@@ -61,7 +75,8 @@ struct unet_net {
     void free_ws();
     int enc_index(int level, char ab) const;
     int dec_index(int level, char ab) const;
-    helm::Srcs layer_srcs(int i) const;
+    // sources of layer i; without_ctx drops the context (weights sliced)
+    helm::Srcs layer_srcs(int i, bool without_ctx = false) const;
     void run_layer(int i, const helm::Srcs &src, int B, int H, int W, bool training, hipStream_t st,
                    const helm::ConvEpi &epi = helm::ConvEpi());
     void forward_from_x0(int B, int H, int W, bool training, hipStream_t st);

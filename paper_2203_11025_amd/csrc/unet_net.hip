@@ -84,6 +84,7 @@ unet_net::~unet_net()
 {
     free_ws();
     for (auto p : ctxbuf) hipFree(p);
+    for (auto p : cmap) hipFree(p);
     for (auto &l : L) {
         hipFree(l.Wp);
         hipFree(l.Wd);
@@ -234,12 +235,10 @@ int unet_net::ensure_ws(int B, int H, int W, bool training)
             if ((rc = dalloc(&gctx[l], (size_t)nB * (H >> l) * (W >> l) * cfg.widths[l]))) return rc;
     }
     size_t P0 = (size_t)nB * H * W;
-    if ((rc = dalloc(&x0, P0 * pad32(cfg.in_ch))) || (rc = dalloc(&out, P0 * cfg.out_ch)) ||
+    if ((rc = dalloc(&x0, P0 * x0_stride())) || (rc = dalloc(&out, P0 * cfg.out_ch)) ||
         (rc = dalloc(&xin, P0 * cfg.out_ch)))
         return rc;
-    // the padding channels of the network input stay zero: input packing
-    // writes only the first eight channels of each pixel
-    if (hipMemset(x0, 0, P0 * pad32(cfg.in_ch) * sizeof(bf16)) != hipSuccess) {
+    if (hipMemset(x0, 0, P0 * x0_stride() * sizeof(bf16)) != hipSuccess) {
         set_error("unet: clearing the input workspace failed");
         return HELM_E_HIP;
     }
@@ -267,8 +266,10 @@ void unet_net::run_layer(int i, const Srcs &src, int B, int H, int W, bool train
     Layer &l = L[i];
     Act &a = act[i];
     const size_t Pl = (size_t)B * H * W;
-    // 2 FLOPs per multiply-add over the real input channels
-    const double flops = 18.0 * l.cin_real * l.cout * (double)Pl;
+    // 2 FLOPs per multiply-add over the real input channels (without the
+    // context when its part comes from the context map)
+    const int cin = epi.cmap ? l.cin_real - l.src_real[l.nsrc - 1] : l.cin_real;
+    const double flops = 18.0 * cin * l.cout * (double)Pl;
     prof_mark(HELM_PROF_CONV, st, true);
     if (training) {
         launch_conv3x3(src, B, H, W, l.Wp, l.cout, 0, a.y32, nullptr, nullptr, nullptr, SLOPE, st);
@@ -282,16 +283,17 @@ void unet_net::run_layer(int i, const Srcs &src, int B, int H, int W, bool train
     }
 }
 
-Srcs unet_net::layer_srcs(int i) const
+Srcs unet_net::layer_srcs(int i, bool without_ctx) const
 {
     const Layer &l = L[i];
     Srcs s{};
     s.n = l.nsrc;
     s.Ctot = l.cin_pad;
+    s.wstride = l.cin_pad;
     const std::string &nm = l.name;
     int lev = l.level;
     if (nm == "enc0a") {
-        s.s[0] = {x0, l.src_pad[0], 0};
+        s.s[0] = {x0, l.src_pad[0], 0, x0_stride()};
     } else if (nm[0] == 'e' && nm.back() == 'a') {
         s.s[0] = {pooled[lev], l.src_pad[0], 0};
     } else if (nm.back() == 'b') {
@@ -300,8 +302,39 @@ Srcs unet_net::layer_srcs(int i) const
         s.s[0] = {up[lev], l.src_pad[0], 0};
         s.s[1] = {act[enc_index(lev, 'b')].a, l.src_pad[1], 0};
     }
-    if (cfg.context && nm.back() == 'a') s.s[l.nsrc - 1] = {ctxp[lev], l.src_pad[l.nsrc - 1], ctx_shared};
+    if (cfg.context && nm.back() == 'a') {
+        if (without_ctx) {  // the context is the last source and the last weight columns
+            s.n = l.nsrc - 1;
+            s.Ctot = l.cin_pad - l.src_pad[l.nsrc - 1];
+        } else {
+            s.s[l.nsrc - 1] = {ctxp[lev], l.src_pad[l.nsrc - 1], ctx_shared};
+        }
+    }
     return s;
+}
+
+// cmap[i] = the convolution of layer i over the context alone (raw, rounded
+// to FP16, one sample): the context columns of the packed weights applied
+// to it.
+void unet_net::compute_cmaps(hipStream_t st)
+{
+    for (size_t i = 0; i < L.size(); ++i) {
+        const Layer &l = L[i];
+        if (!cmap[i]) continue;
+        const int lev = l.level, cc = l.src_pad[l.nsrc - 1];
+        Srcs s{};
+        s.n = 1;
+        s.Ctot = cc;
+        s.wstride = l.cin_pad;
+        s.woff = l.cin_pad - cc;
+        s.s[0] = {ctxp[lev], cc, 1};
+        ConvEpi e;
+        e.raw16 = cmap[i];
+        launch_conv3x3(s, 1, ctx_H >> lev, ctx_H >> lev, l.Wp, l.cout, 0, nullptr, nullptr, nullptr, nullptr,
+                       SLOPE, st, e);
+    }
+    if (!cmap_valid) ++gen;  // captured graphs that convolve the context are stale
+    cmap_valid = 1;
 }
 
 int unet_net::enc_index(int level, char ab) const { return 2 * level + (ab == 'b' ? 1 : 0); }
@@ -326,12 +359,19 @@ void unet_net::forward_from_x0(int B, int H, int W, bool training, hipStream_t s
     const int Lv = cfg.levels;
     const int last = Lv >= 2 ? dec_index(0, 'b') : enc_index(0, 'b');
     const bool fuse_head = !training && cfg.head && cfg.widths[0] == 32;
+    const bool maps = use_cmap(training, H);
+    // a context-taking layer: its sources, and the context map when used
+    auto run_a = [&](int i, int Hl, int Wl) {
+        ConvEpi e;
+        if (maps) e.cmap = cmap[i];
+        run_layer(i, layer_srcs(i, maps), B, Hl, Wl, training, st, e);
+    };
     for (int l = 0; l < Lv; ++l) {
         int Hl = H >> l, Wl = W >> l;
         if (l > 0 && (training || cfg.widths[l - 1] != 32))
             launch_maxpool_fwd(act[enc_index(l - 1, 'b')].a, B, H >> (l - 1), W >> (l - 1),
                                cfg.widths[l - 1], pooled[l], training ? arg[l] : nullptr, st);
-        run_layer(enc_index(l, 'a'), layer_srcs(enc_index(l, 'a')), B, Hl, Wl, training, st);
+        run_a(enc_index(l, 'a'), Hl, Wl);
         ConvEpi epi;
         // pooling in the epilogue pays for 32-channel layers only (wider
         // channel blocks run out of registers)
@@ -347,7 +387,7 @@ void unet_net::forward_from_x0(int B, int H, int W, bool training, hipStream_t s
         int Hl = H >> l, Wl = W >> l;
         const bf16 *prev = (l == Lv - 2) ? act[enc_index(Lv - 1, 'b')].a : act[dec_index(l + 1, 'b')].a;
         launch_up2_fwd(prev, B, Hl / 2, Wl / 2, cfg.widths[l + 1], up[l], st);
-        run_layer(dec_index(l, 'a'), layer_srcs(dec_index(l, 'a')), B, Hl, Wl, training, st);
+        run_a(dec_index(l, 'a'), Hl, Wl);
         ConvEpi epi;
         if (fuse_head && dec_index(l, 'b') == last) {
             epi.head_w = P + head_w;
@@ -437,9 +477,19 @@ int unet_net::attach_context(const unet_net &enc, int nb, int H, int W, hipStrea
     const int Lv = cfg.levels;
     if (ctxbuf.empty() || ctx_B != nb || ctx_H != H) {
         ++gen;
+        cmap_valid = 0;
         for (auto p : ctxbuf) hipFree(p);
+        for (auto p : cmap) hipFree(p);
         ctxbuf.assign(Lv, nullptr);
+        cmap.assign(L.size(), nullptr);
         ctx_valid = 0;
+        for (size_t i = 0; i < L.size() && nb == 1 && H == W; ++i)
+            if (L[i].name.back() == 'a' &&
+                hipMalloc(&cmap[i], (size_t)(H >> L[i].level) * (W >> L[i].level) * L[i].cout * sizeof(_Float16)) !=
+                    hipSuccess) {
+                set_error("unet_pair_encode: out of device memory for the context maps");
+                return HELM_E_NOMEM;
+            }
         for (int l = 0; l < Lv; ++l)
             if (hipMalloc(&ctxbuf[l], (size_t)nb * (H >> l) * (W >> l) * cfg.widths[l] * sizeof(bf16)) !=
                 hipSuccess) {
@@ -460,12 +510,20 @@ int unet_net::attach_context(const unet_net &enc, int nb, int H, int W, hipStrea
     ctx_H = H;
     ctx_shared = nb == 1;
     ctx_valid = 1;
+    if (ctx_shared && H == W) {
+        compute_cmaps(st);
+    } else if (cmap_valid) {
+        cmap_valid = 0;
+        ++gen;
+    }
     return HELM_OK;
 }
 
 void unet_net::clear_context()
 {
     ctx_valid = 0;
+    if (cmap_valid) ++gen;
+    cmap_valid = 0;
     for (auto &p : ctxp) p = nullptr;
 }
 
@@ -485,6 +543,10 @@ void unet_net::adam_update(const unet_train_opts &o, double count, hipStream_t s
 
 void unet_net::repack(hipStream_t st)
 {
+    if (cmap_valid) {  // the context maps hold the previous weights
+        cmap_valid = 0;
+        ++gen;  // captured graphs that add the maps are stale
+    }
     for (auto &l : L)
         launch_pack_weights(P + l.w_off, l.cout, l.cin_real, l.map, l.cin_pad, l.Wp, l.Wd, st);
     refold(st);
@@ -509,7 +571,7 @@ int unet_net::wrap_apply(helm_handle *h, const float2 *r, size_t rs, float2 *e, 
     if (nnet > 0) {
         int rc = ensure_ws(nnet, nc, nc, false);
         if (rc) return rc;
-        launch_net_input(r, rs, nnet, n, h->kappa0, nullptr, rcoarse, red, s, x0, st, idx);
+        launch_net_input(r, rs, nnet, n, h->kappa0, nullptr, rcoarse, red, s, x0, x0_stride(), st, idx);
         forward_from_x0(nnet, nc, nc, false, st);
     }
     launch_net_output(out, s, nb, n, e, es, accumulate, st, mask, pos);
@@ -522,7 +584,7 @@ int unet_net::loss_grad(const unet_batch &bt, hipStream_t st)
     int rc = ensure_ws(nb, nc, nc, true);
     if (rc) return rc;
     launch_net_input((const float2 *)bt.r, (size_t)n * n, nb, n, nullptr, bt.kappa_c, rcoarse, red, s,
-                     x0, st);
+                     x0, x0_stride(), st);
     forward_from_x0(nb, nc, nc, true, st);
     launch_loss_grad(out, s, nb, n, (const float2 *)bt.e, dfine, red, gout, dloss, st);
     hipMemsetAsync(G, 0, nparams * sizeof(float), st);
@@ -532,7 +594,7 @@ int unet_net::loss_grad(const unet_batch &bt, hipStream_t st)
 
 int unet_net::pack_nchw_input(const float *x, int B, int H, int W, hipStream_t st)
 {
-    launch_nchw_to_nhwc(x, B, cfg.in_ch, H, W, pad32(cfg.in_ch), x0, st);
+    launch_nchw_to_nhwc(x, B, cfg.in_ch, H, W, x0_stride(), x0, st);
     return HELM_OK;
 }
 

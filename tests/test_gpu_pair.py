@@ -66,6 +66,39 @@ def test_pair_forward_parity(N, nb, B, H):
     assert rel(out, ref) <= 2e-2, rel(out, ref)
 
 
+def test_shared_context_maps(N):
+    """With one medium for the whole batch, inference adds each layer's
+    convolution over the context from a map computed at encode time.  The
+    map path, the path that convolves the context again (taken once the
+    weights change without a new encode), and the oracle agree; a new encode
+    brings the maps back with the new weights."""
+    widths = (32, 64, 128, 256)
+    ce, pe, be, cs, ps, bs, enc, sol = make_pair(N, 13, widths=widths)
+    rng = np.random.default_rng(17)
+    H, B = 64, 3
+    kc = rng.uniform(0.25, 1.0, (1, H, H)).astype(np.float32)
+    x = torch.from_numpy(rng.standard_normal((B, 3, H, H)).astype(np.float32))
+    N.pair_encode(enc, sol, torch.from_numpy(kc))
+    out_map = sol.forward(x).cpu().numpy()
+    ctx = [c.expand(B, -1, -1, -1) for c in U.encode(ce, pe, be, kc)]
+    ref = U.forward(cs, ps, bs, x, ctx=ctx).numpy()
+    assert rel(out_map, ref) <= 2e-2, rel(out_map, ref)
+    # same weights set again: the maps are dropped, the context is convolved
+    sol.set_params(U.flatten(cs, ps), torch.cat([bs[k].reshape(-1) for k in U.buffer_shapes(cs)]))
+    out_cat = sol.forward(x).cpu().numpy()
+    assert rel(out_map, out_cat) <= 5e-3, rel(out_map, out_cat)
+    # new solver weights, old context: no stale maps
+    ps2 = {k: v * 1.1 if k.endswith(".w") else v for k, v in ps.items()}
+    sol.set_params(U.flatten(cs, ps2), torch.cat([bs[k].reshape(-1) for k in U.buffer_shapes(cs)]))
+    ref2 = U.forward(cs, ps2, bs, x, ctx=ctx).numpy()
+    out2 = sol.forward(x).cpu().numpy()
+    assert rel(out2, ref2) <= 2e-2, rel(out2, ref2)
+    N.pair_encode(enc, sol, torch.from_numpy(kc))
+    out3 = sol.forward(x).cpu().numpy()
+    assert rel(out3, ref2) <= 2e-2, rel(out3, ref2)
+    assert rel(out3, out2) <= 5e-3, rel(out3, out2)
+
+
 def test_pair_loss_and_gradient_parity(N):
     """Joint loss and both networks' gradients against the oracle's autograd
     with bf16 emulation (same rounding points as the device)."""
