@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--workload", default="multi1024")
     ap.add_argument("--prec", default="unet_defl", choices=["unet_defl", "unet_cgc"])
     ap.add_argument("--retrain", type=int, default=200, help="mini-retraining Adam steps")
-    ap.add_argument("--retrain-lr", type=float, default=1e-3, help="mini-retraining learning rate")
+    ap.add_argument("--retrain-lr", type=float, default=1e-4,
+                    help="mini-retraining learning rate (the pretraining ended at 1e-4)")
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--stall-ratio", type=float, default=0.0,
                     help="fall back to M_V on stalls (0 = never; the uneven-batch setting uses 0.95)")

@@ -177,7 +177,7 @@ int work_ensure(helm_handle *h, int nb, int m, bool scratch, FgWork **out)
     w->nb = nb;
     w->m = m;
     w->N = N;
-    int nblk = krylov_nblk(N);
+    int nblk = krylov_nblk(N, 1);  // the most any batch uses
     int rc;
     if ((rc = dalloc(&w->V, (size_t)nb * (m + 1) * N)) || (rc = dalloc(&w->Z, (size_t)nb * m * N)) ||
         (rc = dalloc(&w->partial, (size_t)nb * nblk * MAXP)) ||
@@ -360,7 +360,7 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
     S.maxit = maxit;
     S.stall_ratio = use_net ? stall_ratio : 0.0;
     const size_t N = w->N;
-    const int nblk = krylov_nblk(N);
+    const int nblk = krylov_nblk(N, nb);
     const size_t vsb = (size_t)(m + 1) * N, zsb = (size_t)m * N;
     const Level &L0 = h->lv[0];
     std::vector<int> restarts(nb, 0);

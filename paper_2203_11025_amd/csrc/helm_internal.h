@@ -109,7 +109,9 @@ struct FgState {
     int maxit;
 };
 
-int krylov_nblk(size_t N);
+// Workgroups per right-hand side of the Krylov reductions for nb
+// right-hand sides of N points (never more than for nb = 1).
+int krylov_nblk(size_t N, int nb);
 
 // One Arnoldi step j (delayed CGS2): pass A (inner products), reduction with
 // the Givens update of Hessenberg column j and the stop test, pass B (final

@@ -24,6 +24,8 @@
 // results are bit-reproducible.  Hessenberg column, Givens rotations and the
 // implicit residual are FP64 (section 3: FGMRES with right preconditioning,
 // eq. 2.5).
+#include <algorithm>
+
 #include "helm_internal.h"
 
 namespace helm {
@@ -430,11 +432,14 @@ const auto kPassB = make_pb(std::make_integer_sequence<int, MAXM>{});
 
 }  // namespace
 
-int krylov_nblk(size_t N)
+int krylov_nblk(size_t N, int nb)
 {
+    // at least two point pairs per thread; about 8192 workgroups over the
+    // batch (fewer, longer blocks amortise the FP64 block reductions)
     size_t b = (N + 511) / 512;
+    const size_t cap = std::min<size_t>(1024, std::max<size_t>(128, 8192 / (size_t)std::max(1, nb)));
     if (b < 1) b = 1;
-    if (b > 1024) b = 1024;
+    if (b > cap) b = cap;
     return (int)b;
 }
 
