@@ -22,6 +22,18 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 
+// Raw buffer loads (descriptor word 3 of the gfx9 family: 32-bit data
+// format, no swizzle).  An offset at or past num_records returns zero
+// without touching memory; BUF_NONE is such an offset for every buffer
+// below 2 GB.
+constexpr int BUF_DWORD3 = 0x00020000;
+constexpr int BUF_NONE = 0x7fffffff;
+__device__ __forceinline__ uint4 ld_buf16(__amdgpu_buffer_rsrc_t r, int off)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -110,8 +122,17 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
     constexpr int NH8 = (HY * HX + 255) / 256, NW8 = (CO * 12 + 255) / 256;
     __shared__ __attribute__((aligned(16))) bf16 sx[HY * HX * PS];
     __shared__ __attribute__((aligned(16))) bf16 sw[CO * WS];
+    // folded BN of this block's channels, read by the epilogues from LDS (a
+    // global load there would stay in flight across the loop and make the
+    // next stage's prefetch wait)
+    __shared__ __attribute__((aligned(16))) float ssc[CO], ssh[CO];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int co0 = blockIdx.y * CO;
+    if (tid < CO) {
+        const bool ok = mode == 1 && co0 + tid < Cout;
+        ssc[tid] = ok ? scale[co0 + tid] : 0.f;
+        ssh[tid] = ok ? shift[co0 + tid] : 0.f;
+    }
     const int nch = in.Ctot / 32;
     const int wst = in.wstride ? in.wstride : in.Ctot;  // weight row length
     const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
@@ -169,9 +190,28 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
             coff -= in.s[s].C;
             ++s;
         }
+        // weights first: their address registers may be reloaded from
+        // scratch, and the wait for that reload should not cover the halo
+        // loads
+        // Buffer loads from uniform descriptors with 32-bit byte offsets; a
+        // piece outside the image, the tensor's channels or the weight rows
+        // gets an offset past the descriptor's range and reads as zero.
+        if (with_w) {
+            const size_t w0 = (size_t)co0 * 9 * wst + in.woff + ch * 32;
+            const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(Wt + w0), 0, (int)(((size_t)Cout * 9 * wst - w0) * 2), BUF_DWORD3);
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                const int idx = tid + 256 * k;
+                const int rr = idx >> 2, co = rr / 9, tap = rr - co * 9;
+                const int off = idx < CO * 36 ? ((co * 9 + tap) * wst + (idx & 3) * 8) * 2 : BUF_NONE;
+                wreg[k] = ld_buf16(wr, off);
+            }
+        }
         const int Cs = in.s[s].stride ? in.s[s].stride : in.s[s].C;  // channels per pixel in memory
-        const bf16 *src = in.s[s].p + ((size_t)(in.s[s].shared ? 0 : b) * H * W) * Cs + coff +
-                          (tid & 3) * 8;
+        const size_t h0 = ((size_t)(in.s[s].shared ? 0 : b) * H * W) * Cs + coff;
+        const __amdgpu_buffer_rsrc_t hr = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(in.s[s].p + h0), 0, (int)(((size_t)H * W * Cs - coff) * 2), BUF_DWORD3);
         const bool inside = x0 >= 0 && y0 >= 0 && x0 + HX <= W && y0 + HY <= H;
         const bool seg_ok = coff + (tid & 3) * 8 < Cs;  // this thread's 8 channels exist
 #pragma unroll
@@ -179,22 +219,8 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
             // this thread's piece: halo pixel (hy, hx), 8-channel segment tid % 4
             const int idx = tid + 256 * k, pix = idx >> 2, hy = pix / HX;
             const int y = y0 + hy, x = x0 + pix - hy * HX;
-            uint4 v = {0u, 0u, 0u, 0u};
-            if (idx < HY * HX * 4 && seg_ok && (inside || (y >= 0 && y < H && x >= 0 && x < W)))
-                v = *reinterpret_cast<const uint4 *>(src + (size_t)(y * W + x) * Cs);
-            hreg[k] = v;
-        }
-        if (with_w) {
-#pragma unroll
-            for (int k = 0; k < NW; ++k) {
-                const int idx = tid + 256 * k;
-                const int rr = idx >> 2, co = rr / 9, tap = rr - co * 9;
-                uint4 v = {0u, 0u, 0u, 0u};
-                if (idx < CO * 36 && co0 + co < Cout)
-                    v = *reinterpret_cast<const uint4 *>(Wt + ((size_t)(co0 + co) * 9 + tap) * wst + in.woff +
-                                                         ch * 32 + (idx & 3) * 8);
-                wreg[k] = v;
-            }
+            const bool ok = idx < HY * HX * 4 && seg_ok && (inside || (y >= 0 && y < H && x >= 0 && x < W));
+            hreg[k] = ld_buf16(hr, ok ? ((y * W + x) * Cs + (tid & 3) * 8) * 2 : BUF_NONE);
         }
     };
     auto store_stage = [&](bool with_w) {
@@ -318,13 +344,8 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
             float4 sc[NF], sh[NF];
 #pragma unroll
             for (int nf = 0; nf < NF; ++nf) {
-                const int co = co0 + nf * 16 + 4 * (lane >> 4);
-                sc[nf] = make_float4(0.f, 0.f, 0.f, 0.f);
-                sh[nf] = sc[nf];
-                if (mode == 1 && co < Cout) {
-                    sc[nf] = *reinterpret_cast<const float4 *>(scale + co);
-                    sh[nf] = *reinterpret_cast<const float4 *>(shift + co);
-                }
+                sc[nf] = *reinterpret_cast<const float4 *>(&ssc[nf * 16 + 4 * (lane >> 4)]);
+                sh[nf] = *reinterpret_cast<const float4 *>(&ssh[nf * 16 + 4 * (lane >> 4)]);
             }
 #pragma unroll
             for (int mf = 0; mf < MF; ++mf) {
@@ -381,11 +402,8 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
             for (int nf = 0; nf < NF; ++nf) {
                 const int co = co0 + nf * 16 + cl;
                 const bool co_ok = full_co || co < Cout;
-                float4 sc = make_float4(0.f, 0.f, 0.f, 0.f), sh = sc;
-                if (co_ok) {
-                    sc = *reinterpret_cast<const float4 *>(scale + co);
-                    sh = *reinterpret_cast<const float4 *>(shift + co);
-                }
+                const float4 sc = *reinterpret_cast<const float4 *>(&ssc[nf * 16 + cl]);
+                const float4 sh = *reinterpret_cast<const float4 *>(&ssh[nf * 16 + cl]);
                 const float scv[4] = {sc.x, sc.y, sc.z, sc.w}, shv[4] = {sh.x, sh.y, sh.z, sh.w};
                 // folded BN and LeakyReLU, rounded to bf16 (kept as floats)
 #pragma unroll
