@@ -84,6 +84,172 @@ __device__ __forceinline__ f8 up_blend8(const f8 &a00, const f8 &a01, const f8 &
     return o;
 }
 
+// Epilogue of a finished tile: rows y0 .. y0 + MF - 1 of this wavefront,
+// pixel x = lane % 16 column of the tile, channels co0 + 16 nf + 4 (lane /
+// 16) .. + 3 of fragment nf.  bn(c, sc, sh) gives the folded BN of block
+// channels c .. c + 3.  Clears acc.
+template <int MF, int NF, int EPI, class BN>
+__device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[MF][NF], int lane, int b, int y0, int x, int H, int W,
+                                              int Cout, int co0, int mode, float *__restrict__ out32,
+                                              bf16 *__restrict__ out16, float slope, const ConvEpi &epi, BN bn)
+{
+    constexpr int CO = 16 * NF;
+    if constexpr (EPI == 0) {
+        // the tile is complete: lane (l % 16, l / 16) holds pixel x0 + l % 16
+        // of each row and channels 4 (l / 16) .. + 3 of each fragment
+        const bool full_co = co0 + CO <= Cout;
+        // folded BN of the four output channels each lane stores (Cout is
+        // a multiple of 32, so the four are in range together)
+        float4 sc[NF], sh[NF];
+#pragma unroll
+        for (int nf = 0; nf < NF; ++nf) bn(nf * 16 + 4 * (lane >> 4), sc[nf], sh[nf]);
+        // the context map of the whole tile first (one wait for all loads)
+        f16x4 mp[MF][NF];
+#pragma unroll
+        for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+            for (int nf = 0; nf < NF; ++nf) {
+                mp[mf][nf] = f16x4{};
+                const int y = y0 + mf;
+                if (mode == 1 && epi.cmap && y < H && x < W && (full_co || co0 + nf * 16 + 4 * (lane >> 4) < Cout))
+                    mp[mf][nf] = *reinterpret_cast<const f16x4 *>(epi.cmap + ((size_t)y * W + x) * Cout + co0 +
+                                                                  4 * (lane >> 4) + nf * 16);
+            }
+#pragma unroll
+        for (int mf = 0; mf < MF; ++mf) {
+            const int y = y0 + mf;
+            const bool pix_ok = y < H && x < W;
+            const size_t base = (((size_t)b * H + y) * W + x) * Cout + co0 + 4 * (lane >> 4);
+#pragma unroll
+            for (int nf = 0; nf < NF; ++nf) {
+                if (pix_ok && (full_co || co0 + nf * 16 + 4 * (lane >> 4) < Cout)) {
+                    const f32x4 v = acc[mf][nf];
+                    if (mode == 0) {
+                        if (epi.raw16)
+                            *reinterpret_cast<f16x4 *>(epi.raw16 + base + nf * 16) =
+                                f16x4{(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
+                        else
+                            *reinterpret_cast<float4 *>(out32 + base + nf * 16) =
+                                make_float4(v[0], v[1], v[2], v[3]);
+                    } else {
+                        const f16x4 m = mp[mf][nf];
+                        float z0 = (v[0] + (float)m[0]) * sc[nf].x + sh[nf].x;
+                        float z1 = (v[1] + (float)m[1]) * sc[nf].y + sh[nf].y;
+                        float z2 = (v[2] + (float)m[2]) * sc[nf].z + sh[nf].z;
+                        float z3 = (v[3] + (float)m[3]) * sc[nf].w + sh[nf].w;
+                        z0 = z0 > 0.f ? z0 : slope * z0;
+                        z1 = z1 > 0.f ? z1 : slope * z1;
+                        z2 = z2 > 0.f ? z2 : slope * z2;
+                        z3 = z3 > 0.f ? z3 : slope * z3;
+                        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                        bf16x4 o = {(bf16)z0, (bf16)z1, (bf16)z2, (bf16)z3};
+                        *reinterpret_cast<bf16x4 *>(out16 + base + nf * 16) = o;
+                    }
+                }
+                acc[mf][nf] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+    } else {
+        // inference epilogue with pooling (EPI 1) or the 1x1 head (EPI 2):
+        // lane (l % 16, l / 16) holds pixel x0 + l % 16 of each row and
+        // channels 4 (l / 16) .. + 3 of each fragment
+        const int cl = 4 * (lane >> 4);
+        const bool full_co = co0 + CO <= Cout;
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        float s0[MF], s1[MF];  // head partial sums per row
+#pragma unroll
+        for (int mf = 0; mf < MF; ++mf) s0[mf] = s1[mf] = 0.f;
+        // one channel fragment at a time (bounds the live registers)
+#pragma unroll
+        for (int nf = 0; nf < NF; ++nf) {
+            const int co = co0 + nf * 16 + cl;
+            const bool co_ok = full_co || co < Cout;
+            float4 sc, sh;
+            bn(nf * 16 + cl, sc, sh);
+            const float scv[4] = {sc.x, sc.y, sc.z, sc.w}, shv[4] = {sh.x, sh.y, sh.z, sh.w};
+            // folded BN and LeakyReLU, rounded to bf16 (kept as floats)
+#pragma unroll
+            for (int mf = 0; mf < MF; ++mf) {
+                const int y = y0 + mf;
+                float mv[4] = {0.f, 0.f, 0.f, 0.f};
+                if (epi.cmap && y < H && x < W && co_ok) {
+                    const f16x4 m = *reinterpret_cast<const f16x4 *>(epi.cmap + ((size_t)y * W + x) * Cout + co);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) mv[q] = (float)m[q];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float z = (acc[mf][nf][q] + mv[q]) * scv[q] + shv[q];
+                    z = z > 0.f ? z : slope * z;
+                    acc[mf][nf][q] = (float)(bf16)z;
+                }
+            }
+            if (EPI != 2) {
+#pragma unroll
+                for (int mf = 0; mf < MF; ++mf) {
+                    const int y = y0 + mf;
+                    if (y < H && x < W && co_ok) {
+                        const f32x4 v = acc[mf][nf];
+                        bf16x4 o = {(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
+                        *reinterpret_cast<bf16x4 *>(out16 + (((size_t)b * H + y) * W + x) * Cout + co) = o;
+                    }
+                }
+            }
+            if (EPI == 1) {
+                // 2x2 max pooling: rows mf, mf + 1 of this wavefront, pixels
+                // x, x + 1 in lanes l, l ^ 1 (H and W are even)
+#pragma unroll
+                for (int mf = 0; mf < MF; mf += 2) {
+                    const int y = y0 + mf;
+                    float m[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        m[q] = fmaxf(acc[mf][nf][q], acc[mf + 1][nf][q]);
+                        m[q] = fmaxf(m[q], __shfl_xor(m[q], 1));
+                    }
+                    if ((x & 1) == 0 && y < H && x < W && co_ok) {
+                        bf16x4 o = {(bf16)m[0], (bf16)m[1], (bf16)m[2], (bf16)m[3]};
+                        *reinterpret_cast<bf16x4 *>(
+                            epi.pool + (((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * Cout + co) = o;
+                    }
+                }
+            }
+            if (EPI == 2 && co_ok) {
+                const float4 u0 = *reinterpret_cast<const float4 *>(epi.head_w + co);
+                const float4 u1 = *reinterpret_cast<const float4 *>(epi.head_w + Cout + co);
+#pragma unroll
+                for (int mf = 0; mf < MF; ++mf) {
+                    s0[mf] += u0.x * acc[mf][nf][0] + u0.y * acc[mf][nf][1] + u0.z * acc[mf][nf][2] +
+                              u0.w * acc[mf][nf][3];
+                    s1[mf] += u1.x * acc[mf][nf][0] + u1.y * acc[mf][nf][1] + u1.z * acc[mf][nf][2] +
+                              u1.w * acc[mf][nf][3];
+                }
+            }
+        }
+        if (EPI == 2) {
+            // 1x1 head over all Cout channels of the pixel: the four lanes
+            // l, l ^ 16, l ^ 32, l ^ 48 hold its channels
+            const float hb0 = epi.head_b[0], hb1 = epi.head_b[1];
+#pragma unroll
+            for (int mf = 0; mf < MF; ++mf) {
+                const int y = y0 + mf;
+                float a0 = s0[mf], a1 = s1[mf];
+                a0 += __shfl_xor(a0, 16);
+                a1 += __shfl_xor(a1, 16);
+                a0 += __shfl_xor(a0, 32);
+                a1 += __shfl_xor(a1, 32);
+                if (lane < 16 && y < H && x < W)
+                    *reinterpret_cast<float2 *>(epi.head_out + (((size_t)b * H + y) * W + x) * 2) =
+                        make_float2(a0 + hb0, a1 + hb1);
+            }
+        }
+#pragma unroll
+        for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+            for (int nf = 0; nf < NF; ++nf) acc[mf][nf] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
 // ------------------------------------------------------------------ conv fwd
 // Implicit GEMM, computed transposed: D[co][pixel] = sum_k W[co][k] X[k][pixel]
 // with K = 9 taps x input channels, so that each lane of an MFMA result holds
@@ -334,157 +500,13 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
             }
         }
         }
-        if (EPI == 0 && st % nch == nch - 1) {
-            // the tile is complete: lane (l % 16, l / 16) holds pixel x0 + l % 16
-            // of each row and channels 4 (l / 16) .. + 3 of each fragment
-            const int x = tx * TW + (lane & 15);
-            const bool full_co = co0 + CO <= Cout;
-            // folded BN of the four output channels each lane stores (Cout is
-            // a multiple of 32, so the four are in range together)
-            float4 sc[NF], sh[NF];
-#pragma unroll
-            for (int nf = 0; nf < NF; ++nf) {
-                sc[nf] = *reinterpret_cast<const float4 *>(&ssc[nf * 16 + 4 * (lane >> 4)]);
-                sh[nf] = *reinterpret_cast<const float4 *>(&ssh[nf * 16 + 4 * (lane >> 4)]);
-            }
-#pragma unroll
-            for (int mf = 0; mf < MF; ++mf) {
-                const int y = ty * TH + wv * MF + mf;
-                const bool pix_ok = y < H && x < W;
-                const size_t base = (((size_t)b * H + y) * W + x) * Cout + co0 + 4 * (lane >> 4);
-#pragma unroll
-                for (int nf = 0; nf < NF; ++nf) {
-                    if (pix_ok && (full_co || co0 + nf * 16 + 4 * (lane >> 4) < Cout)) {
-                        const f32x4 v = acc[mf][nf];
-                        if (mode == 0) {
-                            if (epi.raw16)
-                                *reinterpret_cast<f16x4 *>(epi.raw16 + base + nf * 16) =
-                                    f16x4{(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
-                            else
-                                *reinterpret_cast<float4 *>(out32 + base + nf * 16) =
-                                    make_float4(v[0], v[1], v[2], v[3]);
-                        } else {
-                            f16x4 m = f16x4{};
-                            if (epi.cmap)
-                                m = *reinterpret_cast<const f16x4 *>(
-                                    epi.cmap + ((size_t)y * W + x) * Cout + co0 + 4 * (lane >> 4) + nf * 16);
-                            float z0 = (v[0] + (float)m[0]) * sc[nf].x + sh[nf].x;
-                            float z1 = (v[1] + (float)m[1]) * sc[nf].y + sh[nf].y;
-                            float z2 = (v[2] + (float)m[2]) * sc[nf].z + sh[nf].z;
-                            float z3 = (v[3] + (float)m[3]) * sc[nf].w + sh[nf].w;
-                            z0 = z0 > 0.f ? z0 : slope * z0;
-                            z1 = z1 > 0.f ? z1 : slope * z1;
-                            z2 = z2 > 0.f ? z2 : slope * z2;
-                            z3 = z3 > 0.f ? z3 : slope * z3;
-                            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-                            bf16x4 o = {(bf16)z0, (bf16)z1, (bf16)z2, (bf16)z3};
-                            *reinterpret_cast<bf16x4 *>(out16 + base + nf * 16) = o;
-                        }
-                    }
-                    acc[mf][nf] = f32x4{0.f, 0.f, 0.f, 0.f};
-                }
-            }
-            advance(tx, ty, b);
-        }
-        if (EPI != 0 && st % nch == nch - 1) {
-            // inference epilogue with pooling (EPI 1) or the 1x1 head (EPI 2):
-            // lane (l % 16, l / 16) holds pixel x0 + l % 16 of each row and
-            // channels 4 (l / 16) .. + 3 of each fragment
-            const int x = tx * TW + (lane & 15);
-            const int cl = 4 * (lane >> 4);
-            const bool full_co = co0 + CO <= Cout;
-            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-            float s0[MF], s1[MF];  // head partial sums per row
-#pragma unroll
-            for (int mf = 0; mf < MF; ++mf) s0[mf] = s1[mf] = 0.f;
-            // one channel fragment at a time (bounds the live registers)
-#pragma unroll
-            for (int nf = 0; nf < NF; ++nf) {
-                const int co = co0 + nf * 16 + cl;
-                const bool co_ok = full_co || co < Cout;
-                const float4 sc = *reinterpret_cast<const float4 *>(&ssc[nf * 16 + cl]);
-                const float4 sh = *reinterpret_cast<const float4 *>(&ssh[nf * 16 + cl]);
-                const float scv[4] = {sc.x, sc.y, sc.z, sc.w}, shv[4] = {sh.x, sh.y, sh.z, sh.w};
-                // folded BN and LeakyReLU, rounded to bf16 (kept as floats)
-#pragma unroll
-                for (int mf = 0; mf < MF; ++mf) {
-                    const int y = ty * TH + wv * MF + mf;
-                    float mv[4] = {0.f, 0.f, 0.f, 0.f};
-                    if (epi.cmap && y < H && x < W && co_ok) {
-                        const f16x4 m = *reinterpret_cast<const f16x4 *>(epi.cmap + ((size_t)y * W + x) * Cout + co);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) mv[q] = (float)m[q];
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        float z = (acc[mf][nf][q] + mv[q]) * scv[q] + shv[q];
-                        z = z > 0.f ? z : slope * z;
-                        acc[mf][nf][q] = (float)(bf16)z;
-                    }
-                }
-                if (EPI != 2) {
-#pragma unroll
-                    for (int mf = 0; mf < MF; ++mf) {
-                        const int y = ty * TH + wv * MF + mf;
-                        if (y < H && x < W && co_ok) {
-                            const f32x4 v = acc[mf][nf];
-                            bf16x4 o = {(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
-                            *reinterpret_cast<bf16x4 *>(out16 + (((size_t)b * H + y) * W + x) * Cout + co) = o;
-                        }
-                    }
-                }
-                if (EPI == 1) {
-                    // 2x2 max pooling: rows mf, mf + 1 of this wavefront, pixels
-                    // x, x + 1 in lanes l, l ^ 1 (H and W are even)
-#pragma unroll
-                    for (int mf = 0; mf < MF; mf += 2) {
-                        const int y = ty * TH + wv * MF + mf;
-                        float m[4];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            m[q] = fmaxf(acc[mf][nf][q], acc[mf + 1][nf][q]);
-                            m[q] = fmaxf(m[q], __shfl_xor(m[q], 1));
-                        }
-                        if ((x & 1) == 0 && y < H && x < W && co_ok) {
-                            bf16x4 o = {(bf16)m[0], (bf16)m[1], (bf16)m[2], (bf16)m[3]};
-                            *reinterpret_cast<bf16x4 *>(
-                                epi.pool + (((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * Cout + co) = o;
-                        }
-                    }
-                }
-                if (EPI == 2 && co_ok) {
-                    const float4 u0 = *reinterpret_cast<const float4 *>(epi.head_w + co);
-                    const float4 u1 = *reinterpret_cast<const float4 *>(epi.head_w + Cout + co);
-#pragma unroll
-                    for (int mf = 0; mf < MF; ++mf) {
-                        s0[mf] += u0.x * acc[mf][nf][0] + u0.y * acc[mf][nf][1] + u0.z * acc[mf][nf][2] +
-                                  u0.w * acc[mf][nf][3];
-                        s1[mf] += u1.x * acc[mf][nf][0] + u1.y * acc[mf][nf][1] + u1.z * acc[mf][nf][2] +
-                                  u1.w * acc[mf][nf][3];
-                    }
-                }
-            }
-            if (EPI == 2) {
-                // 1x1 head over all Cout channels of the pixel: the four lanes
-                // l, l ^ 16, l ^ 32, l ^ 48 hold its channels
-                const float hb0 = epi.head_b[0], hb1 = epi.head_b[1];
-#pragma unroll
-                for (int mf = 0; mf < MF; ++mf) {
-                    const int y = ty * TH + wv * MF + mf;
-                    float a0 = s0[mf], a1 = s1[mf];
-                    a0 += __shfl_xor(a0, 16);
-                    a1 += __shfl_xor(a1, 16);
-                    a0 += __shfl_xor(a0, 32);
-                    a1 += __shfl_xor(a1, 32);
-                    if (lane < 16 && y < H && x < W)
-                        *reinterpret_cast<float2 *>(epi.head_out + (((size_t)b * H + y) * W + x) * 2) =
-                            make_float2(a0 + hb0, a1 + hb1);
-                }
-            }
-#pragma unroll
-            for (int mf = 0; mf < MF; ++mf)
-#pragma unroll
-                for (int nf = 0; nf < NF; ++nf) acc[mf][nf] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (st % nch == nch - 1) {
+            // the tile is complete
+            conv_epilogue<MF, NF, EPI>(acc, lane, b, ty * TH + wv * MF, tx * TW + (lane & 15), H, W, Cout, co0,
+                                       mode, out32, out16, slope, epi, [&](int c, float4 &sc, float4 &sh) {
+                                           sc = *reinterpret_cast<const float4 *>(&ssc[c]);
+                                           sh = *reinterpret_cast<const float4 *>(&ssh[c]);
+                                       });
             advance(tx, ty, b);
         }
         if (more) {
@@ -492,6 +514,211 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
             store_stage(reload_w);
             __syncthreads();
         }
+    }
+}
+
+// Direct-to-LDS form of the same convolution for 512-thread workgroups.
+// Eight wavefronts share one copy of the weights; the tile is 8 MF rows x
+// 16 columns.  Halo and weights reach LDS by buffer loads that write LDS
+// directly (lane l of an instruction fills 16-byte slot base + l), into two
+// buffers: while the MFMAs read one stage, the next stage's copy is in
+// flight into the other buffer, and no registers stage it.  Slots are
+// XOR-swizzled so fragment reads spread over all banks: halo piece (pixel p,
+// 8-channel segment s) sits in slot 4 p + (s ^ ((p / 4) % 4)), weight piece
+// (channel c, tap t, segment s) in slot 4 (9 c + t) + (s ^ ((c / 4) % 4)).
+// Pieces outside the image, the source's channels or Cout read as zero.
+// RW: the weights change per stage (more than one 32-channel chunk).
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(3))) uint4 luint4;
+typedef __attribute__((address_space(3))) bf16x8 lbf16x8;
+
+// The builtins sit in plain device functions: called from a lambda in a
+// kernel template, they keep the host pass from emitting the launch stub.
+// 16-byte direct-to-LDS buffer load: lane l fills slot dst + l
+__device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t r, luint4 *dst, int off)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void *)dst, 16, off, 0, 0, 0);
+}
+__device__ __forceinline__ void wg_barrier() { __builtin_amdgcn_s_barrier(); }
+// s_waitcnt with vmcnt = N (< 64) and the other counters left alone
+#define WAIT_VM(N) __builtin_amdgcn_s_waitcnt(((N) & 15) | (((N) >> 4) << 14) | (7 << 4) | (15 << 8))
+
+template <int MF, int NF, int EPI, bool RW>
+__global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int W, const bf16 *__restrict__ Wt,
+                                                     int Cout, int mode, float *__restrict__ out32,
+                                                     bf16 *__restrict__ out16, const float *__restrict__ scale,
+                                                     const float *__restrict__ shift, float slope, ConvEpi epi)
+{
+    constexpr int NWV = 8;
+    constexpr int TW = 16, TH = NWV * MF, HX = TW + 2, HY = TH + 2;
+    constexpr int CO = 16 * NF;
+    constexpr int HSL = HY * HX * 4, HIN = (HSL + 511) / 512;  // halo slots, DMA instructions per wave
+    constexpr int WSL = CO * 36, WIN = (WSL + 511) / 512;       // weight slots, instructions
+    constexpr int NISS = HIN + (RW ? WIN : 0);                  // instructions per stage and wave
+    __shared__ __attribute__((aligned(16))) uint4 hA_[HIN * 512], hB_[HIN * 512];
+    __shared__ __attribute__((aligned(16))) uint4 wA_[WIN * 512], wB_[WIN * 512];
+    // LDS-typed pointers keep each buffer's identity visible to the
+    // compiler, so a read of one buffer does not wait for copies into the
+    // other
+    luint4 *hA = (luint4 *)hA_, *hB = (luint4 *)hB_, *wA = (luint4 *)wA_, *wB = (luint4 *)wB_;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int co0 = blockIdx.y * CO;
+    const int nch = in.Ctot / 32;
+    const int wst = in.wstride ? in.wstride : in.Ctot;
+    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
+    const int ntiles = B * tiles_x * tiles_y;
+    const int gx = gridDim.x;
+    const int my_tiles = ntiles > (int)blockIdx.x ? (ntiles - 1 - blockIdx.x) / gx + 1 : 0;
+    const int nstage = my_tiles * nch;
+    if (nstage == 0) return;
+    const int dtx = gx % tiles_x, dty = (gx / tiles_x) % tiles_y, db = gx / (tiles_x * tiles_y);
+    auto advance = [&](int &tx, int &ty, int &b) {
+        tx += dtx;
+        if (tx >= tiles_x) {
+            tx -= tiles_x;
+            ++ty;
+        }
+        ty += dty;
+        if (ty >= tiles_y) {
+            ty -= tiles_y;
+            ++b;
+        }
+        b += db;
+    };
+
+    // DMA of one stage's halo (and weights) into the given buffers.  The
+    // byte offsets stay in hoff/woff until after the MFMAs of the stage:
+    // were their registers reused as fragment destinations, the compiler
+    // would wait for these copies before the first fragment read.
+    int hoff[HIN], woff[WIN];
+    auto issue_halo = [&](luint4 *hbuf, int tx, int ty, int b, int ch, bool real) {
+        const int x0 = tx * TW - 1, y0 = ty * TH - 1;
+        int coff = ch * 32, s = 0;
+        while (s < in.n - 1 && coff >= in.s[s].C) {
+            coff -= in.s[s].C;
+            ++s;
+        }
+        const int Cs = in.s[s].stride ? in.s[s].stride : in.s[s].C;
+        const size_t h0 = ((size_t)(in.s[s].shared ? 0 : b) * H * W) * Cs + coff;
+        const __amdgpu_buffer_rsrc_t hr = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(in.s[s].p + h0), 0, (int)(((size_t)H * W * Cs - coff) * 2), BUF_DWORD3);
+#pragma unroll
+        for (int k = 0; k < HIN; ++k) {
+            const int blk = k * NWV + wv, q = blk * 64 + lane;
+            const int pix = q >> 2, seg = (q & 3) ^ ((pix >> 2) & 3);
+            const int hy = pix / HX, y = y0 + hy, x = x0 + pix - hy * HX;
+            const bool ok = real && q < HSL && coff + seg * 8 < Cs && y >= 0 && y < H && x >= 0 && x < W;
+            hoff[k] = ok ? ((y * W + x) * Cs + seg * 8) * 2 : BUF_NONE;
+            dma16(hr, hbuf + blk * 64, hoff[k]);
+        }
+    };
+    auto issue_w = [&](luint4 *wbuf, int ch, bool real) {
+        const size_t w0 = (size_t)co0 * 9 * wst + in.woff + ch * 32;
+        const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(Wt + w0), 0, (int)(((size_t)Cout * 9 * wst - w0) * 2), BUF_DWORD3);
+#pragma unroll
+        for (int k = 0; k < WIN; ++k) {
+            const int blk = k * NWV + wv, q = blk * 64 + lane;
+            const int co = q / 36, r = q - co * 36, tap = r >> 2, seg = (r & 3) ^ ((co >> 2) & 3);
+            woff[k] = real && q < WSL ? ((co * 9 + tap) * wst + seg * 8) * 2 : BUF_NONE;
+            dma16(wr, wbuf + blk * 64, woff[k]);
+        }
+    };
+
+    f32x4 acc[MF][NF];
+#pragma unroll
+    for (int i = 0; i < MF; ++i)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // folded BN of the lane's output channels, kept in registers (no global
+    // loads in the loop besides the copies and the context map)
+    float4 bsc[NF], bsh[NF];
+#pragma unroll
+    for (int nf = 0; nf < NF; ++nf) {
+        const int co = co0 + nf * 16 + 4 * (lane >> 4);
+        bsc[nf] = bsh[nf] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (mode == 1 && co < Cout) {
+            bsc[nf] = *reinterpret_cast<const float4 *>(scale + co);
+            bsh[nf] = *reinterpret_cast<const float4 *>(shift + co);
+        }
+    }
+
+    // MFMAs of one stage from the given buffers
+    auto compute = [&](const luint4 *hbuf, const luint4 *wbuf) {
+        const int seg = lane >> 4;
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+            bf16x8 a[MF + 2];
+#pragma unroll
+            for (int r = 0; r < MF + 2; ++r) {
+                const int p = (wv * MF + r) * HX + (lane & 15) + kx;
+                a[r] = *reinterpret_cast<const lbf16x8 *>(hbuf + p * 4 + (seg ^ ((p >> 2) & 3)));
+            }
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky) {
+                const int tap = ky * 3 + kx;
+                bf16x8 bw[NF];
+#pragma unroll
+                for (int nf = 0; nf < NF; ++nf) {
+                    const int co = nf * 16 + (lane & 15);
+                    bw[nf] = *reinterpret_cast<const lbf16x8 *>(wbuf + (co * 9 + tap) * 4 + (seg ^ ((co >> 2) & 3)));
+                }
+#pragma unroll
+                for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+                    for (int nf = 0; nf < NF; ++nf)
+                        acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[nf], a[mf + ky], acc[mf][nf], 0, 0, 0);
+            }
+        }
+    };
+
+    int tx = blockIdx.x % tiles_x, ty = (blockIdx.x / tiles_x) % tiles_y, b = blockIdx.x / (tiles_x * tiles_y);
+    int ntx = tx, nty = ty, nbb = b, nchk = 0;
+    issue_halo(hA, tx, ty, b, 0, true);
+    issue_w(wA, 0, true);
+    if (!RW) issue_w(wB, 0, true);  // one chunk: both weight buffers hold it for the whole kernel
+
+    // one stage: issue the next stage's copy, wait for this one, MFMAs,
+    // epilogue when the tile is complete
+    auto step = [&](luint4 *__restrict__ ch_, luint4 *__restrict__ cw_, luint4 *__restrict__ nh_,
+                    luint4 *__restrict__ nw_, int st) {
+        // The next stage's copy is issued on every step (all pieces out of
+        // range after the last stage): copies issued under a branch would
+        // make the compiler wait for all of them before the fragment reads.
+        const bool more = st + 1 < nstage;
+        if (more && ++nchk == nch) {
+            nchk = 0;
+            advance(ntx, nty, nbb);
+        }
+        issue_halo(nh_, ntx, nty, nbb, nchk, more);
+        if (RW) issue_w(nw_, nchk, more);
+        WAIT_VM(NISS);  // this stage's copies (issued a step earlier) have landed
+        wg_barrier();   // ... for every wavefront
+        compute(ch_, cw_);
+        // (no instructions: keeps the offset registers allocated until here;
+        // the constraint names a GPU register class, so the host pass skips it)
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+        for (int q = 0; q < HIN; ++q) asm volatile("" ::"v"(hoff[q]));
+        if (RW) {
+#pragma unroll
+            for (int q = 0; q < WIN; ++q) asm volatile("" ::"v"(woff[q]));
+        }
+#endif
+        if (st % nch == nch - 1) {
+            conv_epilogue<MF, NF, EPI>(acc, lane, b, ty * TH + wv * MF, tx * TW + (lane & 15), H, W, Cout, co0,
+                                       mode, out32, out16, slope, epi, [&](int c, float4 &sc, float4 &sh) {
+                                           // c = 16 nf + 4 (lane / 16) (+ 0): fragment nf's registers
+                                           sc = bsc[c >> 4];
+                                           sh = bsh[c >> 4];
+                                       });
+            advance(tx, ty, b);
+        }
+        wg_barrier();  // every wavefront is done with these buffers
+    };
+    for (int st = 0; st < nstage; st += 2) {
+        step(hA, wA, hB, wB, st);
+        if (st + 1 < nstage) step(hB, wB, hA, wA, st + 1);
     }
 }
 
@@ -1447,10 +1674,11 @@ bool conv_in8(const Srcs &in)
     return in.n == 1 && in.Ctot == 32 && in.s[0].stride == 8;
 }
 
-// launch shape of one convolution: pixel rows per wavefront fragment group
-// (tile height 4 MF) and the number of workgroups walking the tiles
+// launch shape of one convolution: the kernel (0: k_conv3x3, 256 threads,
+// tile height 4 MF; 1: k_conv3x3d, 512 threads, tile height 8 MF), pixel
+// rows per wavefront and the number of workgroups walking the tiles
 struct ConvShape {
-    int mf, blocks;
+    int mf, blocks, kind = 1;
 };
 
 void conv_dispatch(const ConvShape &c, const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout,
@@ -1460,9 +1688,47 @@ void conv_dispatch(const ConvShape &c, const Srcs &in, int B, int H, int W, cons
     const int NF = Cout >= 64 ? 4 : 2;
     const int CO = 16 * NF;
     const int ncob = (Cout + CO - 1) / CO;
-    const long long ntiles = (long long)B * ((H + 4 * c.mf - 1) / (4 * c.mf)) * ((W + 15) / 16);
-    dim3 grid((unsigned)std::max<long long>(1, std::min<long long>(ntiles, c.blocks)), ncob);
     const int ep = epi.head_out ? 2 : (epi.pool ? 1 : 0);
+    if (c.kind == 1 && !conv_in8(in)) {
+        const long long ntiles = (long long)B * ((H + 8 * c.mf - 1) / (8 * c.mf)) * ((W + 15) / 16);
+        dim3 grid((unsigned)std::max<long long>(1, std::min<long long>(ntiles, c.blocks)), ncob);
+        const bool rw = in.Ctot > 32;
+#define CONVD1(mf, nf, rw)                                                                                    \
+    do {                                                                                                     \
+        if (ep == 2)                                                                                         \
+            hipLaunchKernelGGL((k_conv3x3d<mf, nf, 2, rw>), grid, dim3(512), 0, s, in, B, H, W, Wt, Cout, mode, \
+                               out32, out16, scale, shift, slope, epi);                                       \
+        else if (ep == 1)                                                                                    \
+            hipLaunchKernelGGL((k_conv3x3d<mf, nf, 1, rw>), grid, dim3(512), 0, s, in, B, H, W, Wt, Cout, mode, \
+                               out32, out16, scale, shift, slope, epi);                                       \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_conv3x3d<mf, nf, 0, rw>), grid, dim3(512), 0, s, in, B, H, W, Wt, Cout, mode, \
+                               out32, out16, scale, shift, slope, epi);                                       \
+    } while (0)
+#define CONVD(mf, nf)            \
+    do {                         \
+        if (rw)                  \
+            CONVD1(mf, nf, true);  \
+        else                     \
+            CONVD1(mf, nf, false); \
+    } while (0)
+        if (c.mf == 4 && NF == 4)
+            CONVD(4, 4);
+        else if (c.mf == 4)
+            CONVD(4, 2);
+        else if (NF == 4)
+            CONVD(2, 4);
+        else
+            CONVD(2, 2);
+#undef CONVD
+#undef CONVD1
+        return;
+    }
+    const long long ntiles = (long long)B * ((H + 4 * c.mf - 1) / (4 * c.mf)) * ((W + 15) / 16);
+    // (shapes chosen for the 512-thread kernel count half-size workgroups
+    // four times: about the same number of threads in flight)
+    const int blocks = c.kind == 1 ? 4 * c.blocks : c.blocks;
+    dim3 grid((unsigned)std::max<long long>(1, std::min<long long>(ntiles, blocks)), ncob);
     if (conv_in8(in) && ep == 0) {
         if (c.mf == 4 && NF == 4)
             hipLaunchKernelGGL((k_conv3x3<4, 4, 0, true>), grid, dim3(256), 0, s, in, B, H, W, Wt, Cout, mode,
@@ -1506,7 +1772,7 @@ void conv_dispatch(const ConvShape &c, const Srcs &in, int B, int H, int W, cons
 ConvShape conv_default(int H, int Cout)
 {
     const int ncob = (Cout + (Cout >= 64 ? 63 : 31)) / (Cout >= 64 ? 64 : 32);
-    return ConvShape{H >= 64 ? 4 : 2, std::max(1, 2048 / ncob)};
+    return ConvShape{H >= 128 ? 4 : 2, std::max(1, 512 / ncob), 1};
 }
 
 // epilogue and source variant of a convolution (part of the tuning key)
@@ -1540,9 +1806,10 @@ ConvShape conv_tune(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
         hipEventDestroy(e0);
         return best;
     }
+    for (int kind : {0, 1})
     for (int mf : {2, 4})
-        for (int per_cu : {2, 4, 8, 16}) {
-            ConvShape c{mf, std::max(1, 256 * per_cu / ncob)};
+        for (int per_cu : {1, 2, 4, 8}) {
+            ConvShape c{mf, std::max(1, 256 * per_cu * (kind ? 1 : 2) / ncob), kind};
             conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s, epi);  // warm
             hipEventRecord(e0, s);
             for (int r = 0; r < 3; ++r)
