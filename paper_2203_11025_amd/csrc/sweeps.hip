@@ -23,10 +23,12 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 {
     return f2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ float2 cdiv(float2 a, float2 b)
+// 1 / b through the hardware reciprocal (1 ulp): the sweeps are partly
+// bound by arithmetic, and IEEE divisions cost about ten instructions each
+__device__ __forceinline__ float2 cinv(float2 b)
 {
-    float den = b.x * b.x + b.y * b.y;
-    return f2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+    const float r = __builtin_amdgcn_rcpf(b.x * b.x + b.y * b.y);
+    return f2(b.x * r, -b.y * r);
 }
 __device__ __forceinline__ float2 op_mass(float2 m, float shift) { return f2(m.x, m.y - shift * m.x); }
 
@@ -104,7 +106,7 @@ __global__ __launch_bounds__(256) void k_resjac(const float2 *__restrict__ x, si
         for (int i = i0; i < iend; ++i) {
             size_t p = (size_t)i * n + j;
             float2 m = op_mass(mass[p], shift);
-            y[p] = cdiv(w * f[p], f2(4.f * ih2 - m.x, -m.y));
+            y[p] = w * cmul(f[p], cinv(f2(4.f * ih2 - m.x, -m.y)));
         }
         return;
     }
@@ -123,7 +125,7 @@ __global__ __launch_bounds__(256) void k_resjac(const float2 *__restrict__ x, si
             float2 m = op_mass(mass[p], shift);
             float2 opx = ih2 * (4.f * cur - up - dn - lf - rt) - cmul(m, cur);
             float2 res = f[p] - opx;
-            y[p] = mode == 0 ? res : cur + cdiv(w * res, f2(4.f * ih2 - m.x, -m.y));
+            y[p] = mode == 0 ? res : cur + w * cmul(res, cinv(f2(4.f * ih2 - m.x, -m.y)));
         }
         up = cur;
         cur = dn;
@@ -178,7 +180,7 @@ __global__ __launch_bounds__(256) void k_down(const float2 *__restrict__ f, size
             int i = fi0 + r, j = fj0 + c;
             float2 fv = sc * fl[q];
             float2 m = op_mass(ml[q], shift);
-            float2 vv = (i >= 0 && i < n && j >= 0 && j < n) ? cdiv(w * fv, f2(4.f * ih2 - m.x, -m.y))
+            float2 vv = (i >= 0 && i < n && j >= 0 && j < n) ? w * cmul(fv, cinv(f2(4.f * ih2 - m.x, -m.y)))
                                                              : f2(0.f, 0.f);
             sf[r][c] = fv;
             sv[r][c] = vv;
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(256) void k_up(const float2 *__restrict__ f, size_t
                 pv = pv + svc[rb][ca];
                 if (j & 1) pv = pv + svc[rb][cb];
             }
-            vp = cdiv(w * fv, d) + (wr * wc) * pv;
+            vp = w * cmul(fv, cinv(d)) + (wr * wc) * pv;
             if (r >= 1 && r <= UP_H && c >= 1 && c <= UP_W) {
                 sf[r - 1][c - 1] = fv;
                 sd[r - 1][c - 1] = d;
@@ -305,7 +307,7 @@ __global__ __launch_bounds__(256) void k_up(const float2 *__restrict__ f, size_t
             float2 d = sd[r][c];
             float2 nb4 = sv[r][c + 1] + sv[r + 2][c + 1] + sv[r + 1][c] + sv[r + 1][c + 2];
             float2 res = sf[r][c] - (cmul(d, vp) - ih2 * nb4);
-            float2 z = vp + cdiv(w * res, d);
+            float2 z = vp + w * cmul(res, cinv(d));
             if (accumulate) z = z + v[(size_t)i * n + j];
             v[(size_t)i * n + j] = z;
         }
