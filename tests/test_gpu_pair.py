@@ -66,7 +66,8 @@ def test_pair_forward_parity(N, nb, B, H):
     assert rel(out, ref) <= 2e-2, rel(out, ref)
 
 
-def test_shared_context_maps(N):
+@pytest.mark.parametrize("H", [64, 144])
+def test_shared_context_maps(N, H):
     """With one medium for the whole batch, inference adds each layer's
     convolution over the context from a map computed at encode time.  The
     map path, the path that convolves the context again (taken once the
@@ -75,7 +76,7 @@ def test_shared_context_maps(N):
     widths = (32, 64, 128, 256)
     ce, pe, be, cs, ps, bs, enc, sol = make_pair(N, 13, widths=widths)
     rng = np.random.default_rng(17)
-    H, B = 64, 3
+    B = 3
     kc = rng.uniform(0.25, 1.0, (1, H, H)).astype(np.float32)
     x = torch.from_numpy(rng.standard_normal((B, 3, H, H)).astype(np.float32))
     N.pair_encode(enc, sol, torch.from_numpy(kc))

@@ -47,8 +47,10 @@ def make(N, widths, seed, random_stats=True):
     return cfg, p, buf, net
 
 
+# 144: 32-row tiles (images of 128 and more) with a ragged last tile at
+# every level
 @pytest.mark.parametrize("widths,B,H", [((32, 64), 2, 16), ((32, 64, 128), 1, 40),
-                                         ((32, 64, 128, 256), 2, 64)])
+                                         ((32, 64, 128, 256), 2, 64), ((32, 64, 128, 256), 2, 144)])
 @pytest.mark.parametrize("training", [False, True])
 def test_forward_parity(N, widths, B, H, training):
     cfg, p, buf, net = make(N, widths, 3)
