@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_a(FgState S, const float2 *__re
     const size_t N2 = N / 2;
     const float4 *u = Vb + (size_t)J * N2;
     const float4 *w = Vb + (size_t)(J + 1) * N2;
-    constexpr int U = J <= 8 ? 2 : 1;  // point pairs per thread per step (register budget)
+    constexpr int U = 1;  // point pairs per thread per step (two measured slower at every j)
     double ar[NP], ai[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) ar[i] = ai[i] = 0.0;

@@ -376,62 +376,89 @@ __global__ __launch_bounds__(256) void k_coarse(const float2 *__restrict__ X, in
 }
 
 // Many right-hand sides: V = X F as a tiled complex GEMM, so X is read once
-// and each right-hand side is reused across CG_BM rows from LDS.  A
-// workgroup owns CG_BM rows, CG_BN right-hand sides and one of CG_SPLIT
-// ranges of the sum; k_coarse_finish adds the ranges in order and applies
-// scale / accumulate / the active mask.
-constexpr int CG_BM = 32, CG_BN = 32, CG_BK = 64, CG_SPLIT = 4;
+// for up to 32 right-hand sides; k_coarse_finish adds the split ranges in
+// order and applies scale / accumulate / the active mask.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-// c + a b (complex)
-__device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c)
-{
-    return f2(c.x + a.x * b.x - a.y * b.y, c.y + a.x * b.y + a.y * b.x);
-}
-
+// Complex GEMM on FP32 MFMA (16x16x4), computed transposed so that each
+// lane's four accumulator rows are four right-hand sides:
+//   X^T[c][row] = sum_k F^T[c][k] M^-1^T[k][row],
+// complex as four real products per step (re += Fr Mr - Fi Mi, im += Fr Mi
+// + Fi Mr).  MFMA operand layout (64 lanes): A (16 x 4) lane l holds row
+// l % 16, k = l / 16; B (4 x 16) lane l holds k = l / 16, column l % 16;
+// D (16 x 16) lane l holds rows 4 (l / 16) .. + 3 of column l % 16.  A
+// workgroup (4 wavefronts) owns CG_ROWS rows of M^-1 (16 per wavefront), up
+// to 32 right-hand sides (two 16-wide tiles) and one of CG_SPLIT ranges of
+// the sum.  CG_BK-deep slices of M^-1 and F are staged in LDS with k
+// contiguous (coalesced global reads, contiguous LDS writes) in rows padded
+// to CG_KP entries: a fragment read (16 rows x 4 k) then touches 64
+// distinct banks.  k_coarse_finish adds the ranges in order and applies the
+// scale.
+constexpr int CG_ROWS = 64, CG_BK = 64, CG_SPLIT = 8, CG_KP = CG_BK + 2;
 __global__ __launch_bounds__(256) void k_coarse_gemm(const float2 *__restrict__ X, int N,
                                                      const float2 *__restrict__ f, size_t fs, int nb,
                                                      float2 *__restrict__ part)
 {
-    __shared__ float2 xs[CG_BM][CG_BK + 1];
-    __shared__ float2 fsh[CG_BK][CG_BN + 1];
-    const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
-    const int r0 = blockIdx.x * CG_BM, sp = blockIdx.y, c0 = blockIdx.z * CG_BN;
-    const int kper = (N + CG_SPLIT - 1) / CG_SPLIT;
+    __shared__ float2 xs[CG_ROWS][CG_KP];
+    __shared__ float2 fsh[32][CG_KP];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int r0 = blockIdx.x * CG_ROWS, sp = blockIdx.y, c0 = blockIdx.z * 32;
+    const int kper = ((N + CG_SPLIT - 1) / CG_SPLIT + CG_BK - 1) / CG_BK * CG_BK;
     const int kb = sp * kper, ke = min(N, kb + kper);
-    float2 acc[2][2];
+    f32x4_t accr[2], acci[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f2(0.f, 0.f);
+    for (int t = 0; t < 2; ++t) accr[t] = acci[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    const int lr = lane & 15, lk = lane >> 4;
+    constexpr int NXL = CG_ROWS * CG_BK / 256, NFL = 32 * CG_BK / 256;  // loads per thread
     for (int k0 = kb; k0 < ke; k0 += CG_BK) {
-        for (int i = tid; i < CG_BM * CG_BK; i += 256) {
-            const int r = i / CG_BK, kk = i % CG_BK;
+        // M^-1 slice (rows r0 .. + 63, k k0 .. + 63, coalesced along k) and
+        // F slice (right-hand sides c0 .. + 31): all loads issued before the
+        // LDS stores
+        float2 xv[NXL], fv[NFL];
+#pragma unroll
+        for (int q = 0; q < NXL; ++q) {
+            const int i = tid + 256 * q, r = i / CG_BK, kk = i - r * CG_BK;
             const int row = r0 + r, k = k0 + kk;
-            xs[r][kk] = (row < N && k < ke) ? X[(size_t)row * N + k] : f2(0.f, 0.f);
+            xv[q] = (row < N && k < ke) ? X[(size_t)row * N + k] : f2(0.f, 0.f);
         }
-        for (int i = tid; i < CG_BN * CG_BK; i += 256) {
-            const int c = i / CG_BK, kk = i % CG_BK;
+#pragma unroll
+        for (int q = 0; q < NFL; ++q) {
+            const int i = tid + 256 * q, c = i / CG_BK, kk = i - c * CG_BK;
             const int k = k0 + kk;
-            fsh[kk][c] = (c0 + c < nb && k < ke) ? f[(size_t)(c0 + c) * fs + k] : f2(0.f, 0.f);
+            fv[q] = (c0 + c < nb && k < ke) ? f[(size_t)(c0 + c) * fs + k] : f2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < NXL; ++q) {
+            const int i = tid + 256 * q;
+            xs[i / CG_BK][i % CG_BK] = xv[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NFL; ++q) {
+            const int i = tid + 256 * q;
+            fsh[i / CG_BK][i % CG_BK] = fv[q];
         }
         __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < CG_BK; ++kk) {
-            const float2 x0 = xs[2 * tr][kk], x1 = xs[2 * tr + 1][kk];
-            const float2 g0 = fsh[kk][2 * tc], g1 = fsh[kk][2 * tc + 1];
-            acc[0][0] = cfma(x0, g0, acc[0][0]);
-            acc[0][1] = cfma(x0, g1, acc[0][1]);
-            acc[1][0] = cfma(x1, g0, acc[1][0]);
-            acc[1][1] = cfma(x1, g1, acc[1][1]);
+#pragma unroll 4
+        for (int kq = 0; kq < CG_BK; kq += 4) {
+            const float2 b = xs[wv * 16 + lr][kq + lk];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const float2 a = fsh[t * 16 + lr][kq + lk];
+                accr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, accr[t], 0, 0, 0);
+                accr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, accr[t], 0, 0, 0);
+                acci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, acci[t], 0, 0, 0);
+                acci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, acci[t], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
+    const int row = r0 + wv * 16 + lr;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int row = r0 + 2 * tr + i, c = c0 + 2 * tc + j;
-            if (row < N && c < nb) part[((size_t)sp * nb + c) * N + row] = acc[i][j];
+        for (int q = 0; q < 4; ++q) {
+            const int c = c0 + t * 16 + 4 * lk + q;
+            if (row < N && c < nb) part[((size_t)sp * nb + c) * N + row] = f2(accr[t][q], acci[t][q]);
         }
 }
 
@@ -578,7 +605,7 @@ void launch_coarse_solve(const float2 *X, int N, const float2 *f, size_t fs, flo
     prof_mark(HELM_PROF_COARSE, s, true);
     if (nb >= 4 && scratch) {
         // X read once for all right-hand sides
-        dim3 g((N + CG_BM - 1) / CG_BM, CG_SPLIT, (nb + CG_BN - 1) / CG_BN);
+        dim3 g((N + CG_ROWS - 1) / CG_ROWS, CG_SPLIT, (nb + 31) / 32);
         hipLaunchKernelGGL(k_coarse_gemm, g, dim3(256), 0, s, X, N, f, fs, nb, scratch);
         size_t tot = (size_t)nb * N;
         hipLaunchKernelGGL(k_coarse_finish, dim3((unsigned)std::min<size_t>(8192, (tot + 255) / 256)),
