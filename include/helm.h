@@ -20,6 +20,8 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *    work is enqueued on it; entry points do not synchronise the device
  *    unless their comment says so.
+ *  - A batch of zero fields (nrhs = 0) is a no-op that returns 0; its array
+ *    pointers may then be NULL.
  *  - Return value: 0 = success, > 0 = completed with a warning
  *    (HELM_NOT_CONVERGED), < 0 = error; helm_last_error() then holds a
  *    message for the calling thread.  On error no output is guaranteed.

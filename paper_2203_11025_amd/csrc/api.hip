@@ -338,7 +338,7 @@ int helm_num_levels(const helm_handle *h) { return h ? h->levels : -1; }
 
 int helm_apply(helm_handle *h, int op, const float *x, float *y, int nrhs, void *stream)
 {
-    if (!h || !x || !y || nrhs < 0 || (op != HELM_OP_A && op != HELM_OP_M)) {
+    if (!h || nrhs < 0 || (nrhs > 0 && (!x || !y)) || (op != HELM_OP_A && op != HELM_OP_M)) {
         set_error("helm_apply: invalid argument");
         return HELM_E_INVALID;
     }
@@ -353,7 +353,7 @@ int helm_apply(helm_handle *h, int op, const float *x, float *y, int nrhs, void 
 
 int helm_sl_vcycle(helm_handle *h, const float *f, float *v, int nrhs, void *stream)
 {
-    if (!h || !f || !v || nrhs < 0) {
+    if (!h || nrhs < 0 || (nrhs > 0 && (!f || !v))) {
         set_error("helm_sl_vcycle: invalid argument");
         return HELM_E_INVALID;
     }

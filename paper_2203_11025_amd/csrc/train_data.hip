@@ -97,7 +97,7 @@ using namespace helm;
 extern "C" int helm_training_triples(helm_handle *h, const float *x, float *r, float *e, int nrhs,
                                      void *stream)
 {
-    if (!h || !x || !r || !e || nrhs < 0) {
+    if (!h || nrhs < 0 || (nrhs > 0 && (!x || !r || !e))) {
         set_error("helm_training_triples: invalid argument");
         return HELM_E_INVALID;
     }

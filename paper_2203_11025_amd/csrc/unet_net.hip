@@ -772,7 +772,7 @@ int unet_forward(unet_net *net, const float *x, int B, int H, int W, float *out,
 
 int unet_infer(unet_net *net, helm_handle *h, const float *r, float *e, int nrhs, void *stream)
 {
-    if (!net || !h || !r || !e || nrhs < 0) {
+    if (!net || !h || nrhs < 0 || (nrhs > 0 && (!r || !e))) {
         set_error("unet_infer: invalid argument");
         return HELM_E_INVALID;
     }
