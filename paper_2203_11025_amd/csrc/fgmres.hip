@@ -251,8 +251,10 @@ int work_ensure(helm_handle *h, int nb, int m, bool scratch, FgWork **out)
     return HELM_OK;
 }
 
-// z = Prec(v) for the network preconditioners (section 3.2).  v (slot j) is
-// normalised in place first.  Right-hand sides in fallback use M_V.
+// z = Prec(v) for the network preconditioners (section 3.2).  Slot j holds
+// the candidate unnormalised, as for M_V: every kernel that reads it as the
+// preconditioner's input multiplies by S.scale (1 / its norm) on load.
+// Right-hand sides in fallback use M_V.
 //   M_CU (Algorithm 2 with the network coarse correction):
 //       e1 = w D_A^-1 v,  e2 = e1 + Net(v - A e1),  z = e2 + w D_A^-1 (v - A e2)
 //   M_VU (eq. 3.4):  e0 = Net(v),  z = e0 + V(0, v - A e0)
@@ -265,20 +267,20 @@ int apply_net_prec(helm_handle *h, unet_net *net, int prec, FgWork *w, const FgS
     const size_t N = w->N;
     const Level &L0 = h->lv[0];
     const float jw = (float)h->jacobi_w;
-    launch_scale(v, vs, N, S.scale, nb, S.active, s);
+    const double *sc = S.scale;
     launch_masks(S, 1, s);
     int rc;
     if (prec == HELM_PREC_UNET_DEFL) {
-        if ((rc = net->wrap_apply(h, v, vs, z, zs, nb, 0, s, S.mask_net, nnet, idx, pos))) return rc;
-        launch_resjac(L0, 0.f, jw, 0, z, zs, v, vs, w->t2, N, nb, S.active, s);
+        if ((rc = net->wrap_apply(h, v, vs, z, zs, nb, 0, s, S.mask_net, nnet, idx, pos, sc))) return rc;
+        launch_resjac(L0, 0.f, jw, 0, z, zs, v, vs, w->t2, N, nb, S.active, s, sc);
         return vcycle(h, w->t2, N, z, zs, nb, S.active, s, nullptr, 1);
     }
     // coarse-grid-correction form
-    launch_resjac(L0, 0.f, jw, 2, v, vs, v, vs, w->t1, N, nb, S.mask_net, s);
-    launch_resjac(L0, 0.f, jw, 0, w->t1, N, v, vs, w->t2, N, nb, S.mask_net, s);
+    launch_resjac(L0, 0.f, jw, 2, v, vs, v, vs, w->t1, N, nb, S.mask_net, s, sc);
+    launch_resjac(L0, 0.f, jw, 0, w->t1, N, v, vs, w->t2, N, nb, S.mask_net, s, sc);
     if ((rc = net->wrap_apply(h, w->t2, N, w->t1, N, nb, 1, s, S.mask_net, nnet, idx, pos))) return rc;
-    launch_resjac(L0, 0.f, jw, 1, w->t1, N, v, vs, z, zs, nb, S.mask_net, s);
-    return vcycle(h, v, vs, z, zs, nb, S.mask_sl, s);
+    launch_resjac(L0, 0.f, jw, 1, w->t1, N, v, vs, z, zs, nb, S.mask_net, s, sc);
+    return vcycle(h, v, vs, z, zs, nb, S.mask_sl, s, sc);
 }
 
 // Replays the captured restart cycle for this key, capturing it first.  The

@@ -69,9 +69,10 @@ void launch_coarse_solve(const float2 *X, int N, const float2 *f, size_t fs, flo
                          const double *scale = nullptr, int accumulate = 0, float2 *scratch = nullptr);
 
 // mode 0: y = f - Op x;  mode 1: y = x + w D^-1 (f - Op x);  mode 2: y = w D^-1 f.
+// With fscale, field b of f is read as fscale[b] f_b.
 void launch_resjac(const Level &L, float shift, float w, int mode, const float2 *x, size_t xs,
                    const float2 *f, size_t fs, float2 *y, size_t ys, int nb, const int *active,
-                   hipStream_t s);
+                   hipStream_t s, const double *fscale = nullptr);
 
 // Level-l coefficients by injection from the fine fields, computed in double
 // and rounded once: mass = omega^2 kappa^2 (1 - i gamma) at (2^l I, 2^l J).
@@ -119,8 +120,6 @@ int krylov_nblk(size_t N, int nb);
 // holds the candidate, slot j+1 holds w = A z_j.
 void launch_arnoldi_step(const FgState &S, float2 *V, size_t vsb, size_t N, int j,
                          double2 *partial, int nblk, hipStream_t s);
-void launch_scale(float2 *w, size_t ws, size_t N, const double *scale, int nb,
-                  const int *active, hipStream_t s);
 // mask_net = active && !fallback, mask_sl = active && (fallback || !use_net)
 void launch_masks(const FgState &S, int use_net, hipStream_t s);
 void launch_xupdate(double2 *x, size_t xs, const float2 *Z, size_t zstride_b, size_t N,

@@ -377,20 +377,6 @@ __global__ __launch_bounds__(256) void k_xupdate(double2 *__restrict__ x, size_t
     }
 }
 
-__global__ __launch_bounds__(256) void k_scale(float2 *__restrict__ w, size_t ws, size_t N,
-                                               const double *__restrict__ scale,
-                                               const int *__restrict__ active)
-{
-    const int b = blockIdx.y;
-    if (active && !active[b]) return;
-    w += (size_t)b * ws;
-    const float s = (float)scale[b];
-    for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)gridDim.x * 256) {
-        float2 c = w[p];
-        w[p] = make_float2(c.x * s, c.y * s);
-    }
-}
-
 __global__ void k_masks(FgState S, int use_net)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -458,13 +444,6 @@ void launch_arnoldi_step(const FgState &S, float2 *V, size_t vsb, size_t N, int 
 void launch_masks(const FgState &S, int use_net, hipStream_t s)
 {
     hipLaunchKernelGGL(k_masks, dim3((S.nb + 63) / 64), dim3(64), 0, s, S, use_net);
-}
-
-void launch_scale(float2 *w, size_t ws, size_t N, const double *scale, int nb, const int *active,
-                  hipStream_t s)
-{
-    int g = (int)std::min<size_t>(1024, (N + 1023) / 1024);
-    hipLaunchKernelGGL(k_scale, dim3(g, nb), dim3(256), 0, s, w, ws, N, scale, active);
 }
 
 void launch_xupdate(double2 *x, size_t xs, const float2 *Z, size_t zsb, size_t N,

@@ -83,16 +83,19 @@ __global__ __launch_bounds__(256) void k_apply(const float2 *__restrict__ x, siz
 
 // ------------------------------------------------------------------ residual / Jacobi
 // mode 0: y = f - Op x;  mode 1: y = x + w D^-1 (f - Op x);  mode 2: y = w D^-1 f
-// (Jacobi from a zero guess).  Same register-window walk as k_apply.
+// (Jacobi from a zero guess).  f is read as fscale[b] f when fscale is given.
+// Same register-window walk as k_apply.
 __global__ __launch_bounds__(256) void k_resjac(const float2 *__restrict__ x, size_t xs,
                                                 const float2 *__restrict__ f, size_t fs,
                                                 float2 *__restrict__ y, size_t ys,
                                                 const float2 *__restrict__ mass, int n, float ih2,
                                                 float shift, float w, int mode, int R,
-                                                const int *__restrict__ active)
+                                                const int *__restrict__ active,
+                                                const double *__restrict__ fscale)
 {
     const int b = blockIdx.z;
     if (active && !active[b]) return;
+    const float fsc = fscale ? (float)fscale[b] : 1.f;
     const int lane = threadIdx.x;
     const int j = blockIdx.x * 64 + lane;
     const int i0 = (blockIdx.y * 4 + threadIdx.y) * R;
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(256) void k_resjac(const float2 *__restrict__ x, si
         for (int i = i0; i < iend; ++i) {
             size_t p = (size_t)i * n + j;
             float2 m = op_mass(mass[p], shift);
-            y[p] = w * cmul(f[p], cinv(f2(4.f * ih2 - m.x, -m.y)));
+            y[p] = w * cmul(fsc * f[p], cinv(f2(4.f * ih2 - m.x, -m.y)));
         }
         return;
     }
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(256) void k_resjac(const float2 *__restrict__ x, si
             size_t p = (size_t)i * n + j;
             float2 m = op_mass(mass[p], shift);
             float2 opx = ih2 * (4.f * cur - up - dn - lf - rt) - cmul(m, cur);
-            float2 res = f[p] - opx;
+            float2 res = fsc * f[p] - opx;
             y[p] = mode == 0 ? res : cur + w * cmul(res, cinv(f2(4.f * ih2 - m.x, -m.y)));
         }
         up = cur;
@@ -556,7 +559,7 @@ void launch_apply(const Level &L, float shift, const float2 *x, size_t xs, float
 
 void launch_resjac(const Level &L, float shift, float w, int mode, const float2 *x, size_t xs,
                    const float2 *f, size_t fs, float2 *y, size_t ys, int nb, const int *active,
-                   hipStream_t s)
+                   hipStream_t s, const double *fscale)
 {
     const int n = L.n;
     const int strips = (n + 63) / 64;
@@ -564,7 +567,7 @@ void launch_resjac(const Level &L, float shift, float w, int mode, const float2 
     int R = (int)std::min<long long>(32, std::max<long long>(2, waves_at_1 / 4096));
     dim3 grid(strips, (n + 4 * R - 1) / (4 * R), nb), block(64, 4);
     hipLaunchKernelGGL(k_resjac, grid, block, 0, s, x, xs, f, fs, y, ys, L.mass, n, L.ih2, shift, w,
-                       mode, R, active);
+                       mode, R, active, fscale);
 }
 
 void launch_down(const Level &L, float shift, float w, const float2 *f, size_t fs, float2 *fc,

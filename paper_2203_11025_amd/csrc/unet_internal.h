@@ -22,6 +22,12 @@ struct Src {
     int C;
     int shared;  // one tensor for the whole batch (read as sample 0)
     int stride = 0;
+    // up = 1: the tensor is stored at half resolution (H/2 x W/2) and read
+    // through the x2 bilinear upsampling (half-pixel centres, edges clamped),
+    // each upsampled value rounded to bf16 as a stored upsampled tensor
+    // would be.  Only the first source of an inference convolution with
+    // H and W even may set it.
+    int up = 0;
 };
 // Up to three sources concatenated along channels (by addressing only).
 // The convolution weights of these Ctot channels start at channel woff of
@@ -118,10 +124,12 @@ void launch_head_bwd(const float *dout, const bf16 *a, size_t P, int C, const fl
 // channels per pixel, a multiple of 8; the others untouched), kappa_c either
 // injected from the fine slowness (kappa_fine != null) or given on the coarse
 // grid.  s[b] = 0 marks an all-zero residual.
-// Sample b of the network batch reads right-hand side idx[b] (b if idx is null).
+// Sample b of the network batch reads right-hand side q = idx[b] (b if idx is
+// null), multiplied by fscale[q] when fscale is given.
 void launch_net_input(const float2 *r, size_t rstride, int nb, int n, const float *kappa_fine,
                       const float *kappa_c, float2 *rc, double *part, double *s, bf16 *x0,
-                      int x0_stride, hipStream_t s_, const int *idx = nullptr);
+                      int x0_stride, hipStream_t s_, const int *idx = nullptr,
+                      const double *fscale = nullptr);
 // e (+)= P (s_q (out0 + i out1)) on the fine grid for each of the nb
 // right-hand sides, q = pos[b] its sample in the network batch (b if pos is
 // null); q < 0 or mask[b] == 0: e_b = 0 (untouched when accumulating).

@@ -53,6 +53,14 @@ __device__ __forceinline__ f8 ld8(const bf16 *p)
     for (int q = 0; q < 8; ++q) r.v[q] = (float)e[q];
     return r;
 }
+__device__ __forceinline__ f8 u4_to_f8(const uint4 &u)
+{
+    const bf16 *e = reinterpret_cast<const bf16 *>(&u);
+    f8 r;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r.v[q] = (float)e[q];
+    return r;
+}
 __device__ __forceinline__ void st8(bf16 *p, const f8 &r)
 {
     uint4 u;
@@ -531,6 +539,19 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(3))) uint4 luint4;
 typedef __attribute__((address_space(3))) bf16x8 lbf16x8;
+// plain 16-byte LDS words (HIP's vector classes cannot be assigned through
+// LDS-qualified pointers in the host pass)
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) u32x4 lu32x4;
+__device__ __forceinline__ uint4 lds_ld16(const luint4 *p)
+{
+    const u32x4 v = *reinterpret_cast<const lu32x4 *>(p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void lds_st16(luint4 *p, const uint4 &v)
+{
+    *reinterpret_cast<lu32x4 *>(p) = u32x4{v.x, v.y, v.z, v.w};
+}
 
 // The builtins sit in plain device functions: called from a lambda in a
 // kernel template, they keep the host pass from emitting the launch stub.
@@ -542,8 +563,17 @@ __device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t r, luint4 *dst, int
 __device__ __forceinline__ void wg_barrier() { __builtin_amdgcn_s_barrier(); }
 // s_waitcnt with vmcnt = N (< 64) and the other counters left alone
 #define WAIT_VM(N) __builtin_amdgcn_s_waitcnt(((N) & 15) | (((N) >> 4) << 14) | (7 << 4) | (15 << 8))
+// s_waitcnt lgkmcnt(0), the other counters left alone
+#define WAIT_LGKM0() __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4))
 
-template <int MF, int NF, int EPI, bool RW>
+// UP: the first source is read through the x2 bilinear upsampling (Src::up).
+// A stage of one of its chunks copies the coarse window under the tile into
+// the halo buffer; the workgroup then expands it in place to the fine halo
+// (bf16, the values a stored upsampled tensor would hold) before the MFMAs.
+// The fine halo pairs rows (and columns) as (odd, even) fine indices 2c + 1,
+// 2c + 2, which read coarse c and c + 1 only, so each 2 x 2 fine block needs
+// a 2 x 2 coarse window.
+template <int MF, int NF, int EPI, bool RW, bool UP = false>
 __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int W, const bf16 *__restrict__ Wt,
                                                      int Cout, int mode, float *__restrict__ out32,
                                                      bf16 *__restrict__ out16, const float *__restrict__ scale,
@@ -555,6 +585,14 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
     constexpr int HSL = HY * HX * 4, HIN = (HSL + 511) / 512;  // halo slots, DMA instructions per wave
     constexpr int WSL = CO * 36, WIN = (WSL + 511) / 512;       // weight slots, instructions
     constexpr int NISS = HIN + (RW ? WIN : 0);                  // instructions per stage and wave
+    // one chunk of at most 32 output channels: each wavefront keeps all the
+    // weight fragments in registers (9 NF x 4 VGPRs) and reads only the
+    // halo from LDS
+    constexpr bool WREG = !RW && NF <= 2;
+    // fused upsampling: fine halo row / column pairs, coarse window
+    constexpr int NPY = TH / 2 + 1, NPX = TW / 2 + 1, CWY = NPY + 1, CWX = NPX + 1;
+    static_assert(!UP || CWY * CWX * 4 <= HIN * 512, "coarse window fits the halo buffer");
+    static_assert(!UP || RW, "an upsampled source comes with a second source");
     __shared__ __attribute__((aligned(16))) uint4 hA_[HIN * 512], hB_[HIN * 512];
     __shared__ __attribute__((aligned(16))) uint4 wA_[WIN * 512], wB_[WIN * 512];
     // LDS-typed pointers keep each buffer's identity visible to the
@@ -599,18 +637,99 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
             ++s;
         }
         const int Cs = in.s[s].stride ? in.s[s].stride : in.s[s].C;
-        const size_t h0 = ((size_t)(in.s[s].shared ? 0 : b) * H * W) * Cs + coff;
+        // an upsampled chunk copies its coarse window (rows and columns
+        // clamped to the image: the clamped samples are the ones the
+        // interpolation reads) to slots 4 (row * CWX + column) + segment
+        const bool upc = UP && s == 0 && in.s[0].up;
+        const int hh = upc ? H / 2 : H, ww = upc ? W / 2 : W;
+        const size_t h0 = ((size_t)(in.s[s].shared ? 0 : b) * hh * ww) * Cs + coff;
         const __amdgpu_buffer_rsrc_t hr = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(in.s[s].p + h0), 0, (int)(((size_t)H * W * Cs - coff) * 2), BUF_DWORD3);
+            (void *)(in.s[s].p + h0), 0, (int)(((size_t)hh * ww * Cs - coff) * 2), BUF_DWORD3);
 #pragma unroll
         for (int k = 0; k < HIN; ++k) {
             const int blk = k * NWV + wv, q = blk * 64 + lane;
             const int pix = q >> 2, seg = (q & 3) ^ ((pix >> 2) & 3);
             const int hy = pix / HX, y = y0 + hy, x = x0 + pix - hy * HX;
             const bool ok = real && q < HSL && coff + seg * 8 < Cs && y >= 0 && y < H && x >= 0 && x < W;
-            hoff[k] = ok ? ((y * W + x) * Cs + seg * 8) * 2 : BUF_NONE;
+            int off = ok ? ((y * W + x) * Cs + seg * 8) * 2 : BUF_NONE;
+            if constexpr (UP) {
+                const int cp = q >> 2, cs = q & 3, cr = cp / CWX;
+                int gy = (y0 + 1) / 2 - 1 + cr, gx = (x0 + 1) / 2 - 1 + (cp - cr * CWX);
+                gy = gy < 0 ? 0 : (gy >= hh ? hh - 1 : gy);
+                gx = gx < 0 ? 0 : (gx >= ww ? ww - 1 : gx);
+                const bool cok = real && q < CWY * CWX * 4 && coff + cs * 8 < Cs;
+                const int coffs = cok ? ((gy * ww + gx) * Cs + cs * 8) * 2 : BUF_NONE;
+                off = upc ? coffs : off;
+            }
+            hoff[k] = off;
             dma16(hr, hbuf + blk * 64, hoff[k]);
         }
+    };
+    // expands the coarse window in hb to the fine halo of tile (tx, ty):
+    // thread per (row pair k, column pair m, segment); fine halo pixel
+    // (2k + p, 2m + q) blends window rows k, k + 1 and columns m, m + 1.  Its
+    // weights are up_src's (1 - l, l) on those slots; at the first image row
+    // (column) up_src's first sample is the second slot and its weight l is
+    // zero, so the weights become (l, 1 - l) = (0, 1).  The blend has the
+    // form of up_blend8, and each value equals a direct evaluation.
+    auto build_up = [&](luint4 *hb, int tx, int ty) {
+        constexpr int NIT = NPY * NPX * 4, NR = (NIT + 511) / 512;
+        const int hc = H / 2, wc = W / 2;
+        uint4 w00[NR], w01[NR], w10[NR], w11[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int it = r * 512 + tid, pr = it >> 2, k = pr / NPX, m = pr - k * NPX;
+            if (it < NIT) {
+                const luint4 *c0 = hb + (k * CWX + m) * 4 + (it & 3);
+                w00[r] = lds_ld16(c0);
+                w01[r] = lds_ld16(c0 + 4);
+                w10[r] = lds_ld16(c0 + CWX * 4);
+                w11[r] = lds_ld16(c0 + CWX * 4 + 4);
+            }
+        }
+        WAIT_LGKM0();
+        wg_barrier();  // every window read is done before the halo overwrites it
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int it = r * 512 + tid, seg = it & 3, pr = it >> 2, k = pr / NPX, m = pr - k * NPX;
+            if (it < NIT) {
+                const f8 a00 = u4_to_f8(w00[r]), a01 = u4_to_f8(w01[r]);
+                const f8 a10 = u4_to_f8(w10[r]), a11 = u4_to_f8(w11[r]);
+                const int c = ty * (TH / 2) - 1 + k, d = tx * (TW / 2) - 1 + m;
+                float wy[2][2], wx[2][2];
+                bool iny[2], inx[2];
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    const int fy = ty * TH - 1 + 2 * k + p, fx = tx * TW - 1 + 2 * m + p;
+                    int i0, i1;
+                    float l;
+                    up_src(fy, hc, i0, i1, l);
+                    wy[p][0] = i0 > c ? l : 1.f - l;
+                    wy[p][1] = i0 > c ? 1.f - l : l;
+                    iny[p] = fy >= 0 && fy < H;
+                    up_src(fx, wc, i0, i1, l);
+                    wx[p][0] = i0 > d ? l : 1.f - l;
+                    wx[p][1] = i0 > d ? 1.f - l : l;
+                    inx[p] = fx >= 0 && fx < W;
+                }
+#pragma unroll
+                for (int pq = 0; pq < 4; ++pq) {
+                    const int p = pq >> 1, q = pq & 1;
+                    uint4 o = make_uint4(0u, 0u, 0u, 0u);
+                    if (iny[p] && inx[q]) {
+                        const float y0 = wy[p][0], y1 = wy[p][1], x0 = wx[q][0], x1 = wx[q][1];
+                        bf16 *e = reinterpret_cast<bf16 *>(&o);
+#pragma unroll
+                        for (int z = 0; z < 8; ++z)
+                            e[z] = (bf16)(y0 * (x0 * a00.v[z] + x1 * a01.v[z]) + y1 * (x0 * a10.v[z] + x1 * a11.v[z]));
+                    }
+                    const int pix = (2 * k + p) * HX + 2 * m + q;
+                    lds_st16(hb + pix * 4 + (seg ^ ((pix >> 2) & 3)), o);
+                }
+            }
+        }
+        WAIT_LGKM0();
+        wg_barrier();  // the fine halo is complete
     };
     auto issue_w = [&](luint4 *wbuf, int ch, bool real) {
         const size_t w0 = (size_t)co0 * 9 * wst + in.woff + ch * 32;
@@ -643,6 +762,7 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
         }
     }
 
+    bf16x8 wreg[WREG ? 9 : 1][WREG ? NF : 1];
     // MFMAs of one stage from the given buffers
     auto compute = [&](const luint4 *hbuf, const luint4 *wbuf) {
         const int seg = lane >> 4;
@@ -661,7 +781,11 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
 #pragma unroll
                 for (int nf = 0; nf < NF; ++nf) {
                     const int co = nf * 16 + (lane & 15);
-                    bw[nf] = *reinterpret_cast<const lbf16x8 *>(wbuf + (co * 9 + tap) * 4 + (seg ^ ((co >> 2) & 3)));
+                    if constexpr (WREG)
+                        bw[nf] = wreg[tap][nf];
+                    else
+                        bw[nf] = *reinterpret_cast<const lbf16x8 *>(wbuf + (co * 9 + tap) * 4 +
+                                                                    (seg ^ ((co >> 2) & 3)));
                 }
 #pragma unroll
                 for (int mf = 0; mf < MF; ++mf)
@@ -676,7 +800,22 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
     int ntx = tx, nty = ty, nbb = b, nchk = 0;
     issue_halo(hA, tx, ty, b, 0, true);
     issue_w(wA, 0, true);
-    if (!RW) issue_w(wB, 0, true);  // one chunk: both weight buffers hold it for the whole kernel
+    if constexpr (WREG) {
+        // the weights (and the first halo) land; every wavefront copies its
+        // fragments to registers
+        WAIT_VM(0);
+        wg_barrier();
+        const int seg = lane >> 4;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+            for (int nf = 0; nf < NF; ++nf) {
+                const int co = nf * 16 + (lane & 15);
+                wreg[tap][nf] = *reinterpret_cast<const lbf16x8 *>(wA + (co * 9 + tap) * 4 + (seg ^ ((co >> 2) & 3)));
+            }
+    } else if (!RW) {
+        issue_w(wB, 0, true);  // one chunk: both weight buffers hold it for the whole kernel
+    }
 
     // one stage: issue the next stage's copy, wait for this one, MFMAs,
     // epilogue when the tile is complete
@@ -694,6 +833,9 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
         if (RW) issue_w(nw_, nchk, more);
         WAIT_VM(NISS);  // this stage's copies (issued a step earlier) have landed
         wg_barrier();   // ... for every wavefront
+        if constexpr (UP) {
+            if (in.s[0].up && (st % nch) * 32 < in.s[0].C) build_up(ch_, tx, ty);
+        }
         compute(ch_, cw_);
         // (no instructions: keeps the offset registers allocated until here;
         // the constraint names a GPU register class, so the host pass skips it)
@@ -1167,25 +1309,77 @@ __global__ void k_maxpool_bwd(const float *__restrict__ dout, int cstride, int c
 
 // ------------------------------------------------------------------ upsampling
 
-// thread per (fine pixel, 8-channel group)
-// grid (pixels x channel groups of a fine row, fine rows, batch): the row's
-// coarse rows and weights are uniform per block
+// Thread per (coarse column j, 8-channel group, UP_R coarse rows): it writes
+// the 2 UP_R x 2 fine pixels of those rows and columns.  Fine index 2i + a
+// reads coarse i - 1 .. i + 1 only, so a window of three coarse columns rolls
+// down the rows and each coarse sample is loaded about (UP_R + 2) / UP_R
+// times instead of four.  Every fine pixel blends the same samples with the
+// same weights as a direct evaluation of up_src.
+// grid (columns x channel groups, h / UP_R row blocks, batch)
+constexpr int UP_R = 4;
+__device__ __forceinline__ uint4 up_pick(int slot, const uint4 &v0, const uint4 &v1, const uint4 &v2)
+{
+    return slot == 0 ? v0 : slot == 1 ? v1 : v2;
+}
 __global__ void k_up2_fwd(const bf16 *__restrict__ in, int h, int w, int C, bf16 *__restrict__ out)
 {
     const int W = 2 * w, G = C / 8;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= W * G) return;
-    const int y = blockIdx.y, b = blockIdx.z;
-    const int x = t / G, g = t - x * G;
-    int y0, y1, x0, x1;
-    float ly, lx;
-    up_src(y, h, y0, y1, ly);
-    up_src(x, w, x0, x1, lx);
+    if (t >= w * G) return;
+    const int j = t / G, g = t - j * G, b = blockIdx.z;
+    const int i0 = blockIdx.y * UP_R, i1 = i0 + UP_R < h ? i0 + UP_R : h;
+    // fine columns 2j, 2j + 1: coarse columns as slots of the window j - 1 .. j + 1
+    int cs[2][2];
+    float lx[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        int x0, x1;
+        up_src(2 * j + a, w, x0, x1, lx[a]);
+        cs[a][0] = x0 - j + 1;
+        cs[a][1] = x1 - j + 1;
+    }
+    const int cm = j > 0 ? j - 1 : 0, cp = j + 1 < w ? j + 1 : w - 1;
     const bf16 *pb = in + (size_t)b * h * w * C + 8 * g;
-    const bf16 *r0 = pb + (size_t)y0 * w * C, *r1 = pb + (size_t)y1 * w * C;
-    const f8 a00 = ld8(r0 + x0 * C), a01 = ld8(r0 + x1 * C);
-    const f8 a10 = ld8(r1 + x0 * C), a11 = ld8(r1 + x1 * C);
-    st8(out + (((size_t)b * 2 * h + y) * W + x) * C + 8 * g, up_blend8(a00, a01, a10, a11, ly, lx));
+    auto ldrow = [&](int r, uint4 (&v)[3]) {
+        r = r < 0 ? 0 : (r >= h ? h - 1 : r);
+        const bf16 *pr = pb + (size_t)r * w * C;
+        v[0] = *reinterpret_cast<const uint4 *>(pr + (size_t)cm * C);
+        v[1] = *reinterpret_cast<const uint4 *>(pr + (size_t)j * C);
+        v[2] = *reinterpret_cast<const uint4 *>(pr + (size_t)cp * C);
+    };
+    uint4 win[3][3];  // coarse rows i - 1, i, i + 1
+    ldrow(i0 - 1, win[0]);
+    ldrow(i0, win[1]);
+    for (int i = i0; i < i1; ++i) {
+        ldrow(i + 1, win[2]);
+#pragma unroll
+        for (int ar = 0; ar < 2; ++ar) {
+            int y0, y1;
+            float ly;
+            up_src(2 * i + ar, h, y0, y1, ly);
+            const int r0 = y0 - i + 1, r1 = y1 - i + 1;
+            uint4 row0[3], row1[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                row0[q] = up_pick(r0, win[0][q], win[1][q], win[2][q]);
+                row1[q] = up_pick(r1, win[0][q], win[1][q], win[2][q]);
+            }
+            bf16 *po = out + (((size_t)b * 2 * h + 2 * i + ar) * W + 2 * j) * C + 8 * g;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const f8 a00 = u4_to_f8(up_pick(cs[a][0], row0[0], row0[1], row0[2]));
+                const f8 a01 = u4_to_f8(up_pick(cs[a][1], row0[0], row0[1], row0[2]));
+                const f8 a10 = u4_to_f8(up_pick(cs[a][0], row1[0], row1[1], row1[2]));
+                const f8 a11 = u4_to_f8(up_pick(cs[a][1], row1[0], row1[1], row1[2]));
+                st8(po + (size_t)a * C, up_blend8(a00, a01, a10, a11, ly, lx[a]));
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            win[0][q] = win[1][q];
+            win[1][q] = win[2][q];
+        }
+    }
 }
 
 // 1D adjoint weights of the half-pixel x2 interpolation: coarse i receives
@@ -1343,17 +1537,22 @@ __global__ void k_head_bwd_finish(const double *__restrict__ part, int nblk, int
 }
 
 // ------------------------------------------------------------------ wrapper
-// rc = R(h^2 r) (full weighting, zero outside) and partial sums of |rc|^2.
-// Thread per pair of coarse points (I, 2K), (I, 2K + 1): fine rows 2I - 1 ..
-// 2I + 1, columns 4K - 1 .. 4K + 3 (one float2 and two float4 loads a row).
+// rc = R(h^2 f r) (full weighting, zero outside) and partial sums of
+// |rc|^2, with f = fscale[rhs] (1 without fscale) applied to each sample of r
+// as it is loaded.  Thread per pair of coarse points (I, 2K), (I, 2K + 1):
+// fine rows 2I - 1 .. 2I + 1, columns 4K - 1 .. 4K + 3 (one float2 and two
+// float4 loads a row).
 __global__ __launch_bounds__(256) void k_restrict_scaled(const float2 *__restrict__ r, size_t rs,
                                                          int n, float2 *__restrict__ rc,
                                                          double *__restrict__ part, int nblk,
-                                                         const int *__restrict__ idx)
+                                                         const int *__restrict__ idx,
+                                                         const double *__restrict__ fscale)
 {
     const int b = blockIdx.y, nc = n / 2, hp = nc / 2;
     const float h2 = 1.f / ((float)n * (float)n);
-    const float2 *rb = r + (size_t)(idx ? idx[b] : b) * rs;
+    const int ib = idx ? idx[b] : b;
+    const float f = fscale ? (float)fscale[ib] : 1.f;
+    const float2 *rb = r + (size_t)ib * rs;
     double acc = 0.0;
     for (int t = blockIdx.x * 256 + threadIdx.x; t < nc * hp; t += nblk * 256) {
         const int I = t / hp, K = t - I * hp;
@@ -1364,9 +1563,12 @@ __global__ __launch_bounds__(256) void k_restrict_scaled(const float2 *__restric
             if (i < 0 || i >= n) continue;
             const float wr = a == 0 ? 0.5f : 0.25f;
             const float2 *row = rb + (size_t)i * n + 4 * K;
-            const float2 m1 = K > 0 ? row[-1] : make_float2(0.f, 0.f);
-            const float4 p01 = *reinterpret_cast<const float4 *>(row);
-            const float4 p23 = *reinterpret_cast<const float4 *>(row + 2);
+            float2 m1 = K > 0 ? row[-1] : make_float2(0.f, 0.f);
+            float4 p01 = *reinterpret_cast<const float4 *>(row);
+            float4 p23 = *reinterpret_cast<const float4 *>(row + 2);
+            m1 = make_float2(m1.x * f, m1.y * f);
+            p01 = make_float4(p01.x * f, p01.y * f, p01.z * f, p01.w * f);
+            p23 = make_float4(p23.x * f, p23.y * f, p23.z * f, p23.w * f);
             // coarse 2K: columns 4K - 1, 4K, 4K + 1; coarse 2K + 1: 4K + 1, 4K + 2, 4K + 3
             s0r += wr * (0.25f * m1.x + 0.5f * p01.x + 0.25f * p01.z);
             s0i += wr * (0.25f * m1.y + 0.5f * p01.y + 0.25f * p01.w);
@@ -1689,10 +1891,28 @@ void conv_dispatch(const ConvShape &c, const Srcs &in, int B, int H, int W, cons
     const int CO = 16 * NF;
     const int ncob = (Cout + CO - 1) / CO;
     const int ep = epi.head_out ? 2 : (epi.pool ? 1 : 0);
-    if (c.kind == 1 && !conv_in8(in)) {
+    // an upsampled first source (plain epilogue, more than one chunk) runs
+    // on k_conv3x3d only
+    const bool upsrc = in.s[0].up != 0;
+    if ((c.kind == 1 || upsrc) && !conv_in8(in)) {
         const long long ntiles = (long long)B * ((H + 8 * c.mf - 1) / (8 * c.mf)) * ((W + 15) / 16);
         dim3 grid((unsigned)std::max<long long>(1, std::min<long long>(ntiles, c.blocks)), ncob);
         const bool rw = in.Ctot > 32;
+#define CONVUP(mf, nf)                                                                                         \
+    hipLaunchKernelGGL((k_conv3x3d<mf, nf, 0, true, true>), grid, dim3(512), 0, s, in, B, H, W, Wt, Cout, mode, \
+                       out32, out16, scale, shift, slope, epi)
+        if (upsrc) {
+            if (c.mf == 4 && NF == 4)
+                CONVUP(4, 4);
+            else if (c.mf == 4)
+                CONVUP(4, 2);
+            else if (NF == 4)
+                CONVUP(2, 4);
+            else
+                CONVUP(2, 2);
+            return;
+        }
+#undef CONVUP
 #define CONVD1(mf, nf, rw)                                                                                    \
     do {                                                                                                     \
         if (ep == 2)                                                                                         \
@@ -1780,7 +2000,7 @@ int conv_variant(const Srcs &in, int mode, const ConvEpi &epi)
 {
     return mode | ((epi.pool != nullptr) << 1) | ((epi.head_out != nullptr) << 2) |
            ((epi.cmap != nullptr) << 3) | ((in.wstride != 0 && in.wstride != in.Ctot) << 4) |
-           (conv_in8(in) << 5) | ((epi.raw16 != nullptr) << 6);
+           (conv_in8(in) << 5) | ((epi.raw16 != nullptr) << 6) | ((in.s[0].up != 0) << 7);
 }
 
 struct Tuner {
@@ -1809,6 +2029,7 @@ ConvShape conv_tune(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
     for (int kind : {0, 1})
     for (int mf : {2, 4})
         for (int per_cu : {1, 2, 4, 8}) {
+            if (kind == 0 && in.s[0].up) continue;  // runs on k_conv3x3d only
             ConvShape c{mf, std::max(1, 256 * per_cu * (kind ? 1 : 2) / ncob), kind};
             conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s, epi);  // warm
             hipEventRecord(e0, s);
@@ -1962,8 +2183,9 @@ void launch_maxpool_bwd(const float *dout, const uint8_t *arg, int B, int H, int
 
 void launch_up2_fwd(const bf16 *in, int B, int h, int w, int C, bf16 *out, hipStream_t s)
 {
-    const int row = 2 * w * (C / 8);
-    hipLaunchKernelGGL(k_up2_fwd, dim3((row + 255) / 256, 2 * h, B), dim3(256), 0, s, in, h, w, C, out);
+    const int row = w * (C / 8);
+    hipLaunchKernelGGL(k_up2_fwd, dim3((row + 255) / 256, (h + UP_R - 1) / UP_R, B), dim3(256), 0, s, in, h, w,
+                       C, out);
 }
 
 void launch_up2_bwd(const float *dout, int cstride, int coff, int B, int h, int w, int C,
@@ -2015,12 +2237,12 @@ void launch_head_bwd(const float *dout, const bf16 *a, size_t P, int C, const fl
 
 void launch_net_input(const float2 *r, size_t rstride, int nb, int n, const float *kappa_fine,
                       const float *kappa_c, float2 *rc, double *part, double *s, bf16 *x0, int x0_stride,
-                      hipStream_t st, const int *idx)
+                      hipStream_t st, const int *idx, const double *fscale)
 {
     int nc = n / 2;
     int nblk = (int)std::min<size_t>(256, std::max<size_t>(1, ((size_t)nc * nc / 2 + 511) / 512));
     hipLaunchKernelGGL(k_restrict_scaled, dim3(nblk, nb), dim3(256), 0, st, r, rstride, n, rc, part,
-                       nblk, idx);
+                       nblk, idx, fscale);
     hipLaunchKernelGGL(k_rms, dim3(nb), dim3(64), 0, st, part, nblk, nc, s);
     hipLaunchKernelGGL(k_pack_input, dim3((nc + 255) / 256, nc, nb), dim3(256), 0, st, rc, s, n, kappa_fine,
                        kappa_c, x0, x0_stride);

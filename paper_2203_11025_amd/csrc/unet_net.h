@@ -92,9 +92,10 @@ struct unet_net {
     // may be null: entries b with mask[b] == 0 are left unchanged, or set to
     // zero when not accumulating).  With idx/pos the network runs on the nnet
     // right-hand sides idx[0..nnet) only (pos: the inverse map, -1 for the
-    // others, which are treated as masked).
+    // others, which are treated as masked).  fscale (may be null): field b
+    // is read as fscale[b] r_b.
     int wrap_apply(helm_handle *h, const float2 *r, size_t rs, float2 *e, size_t es, int nb,
                    int accumulate, hipStream_t st, const int *mask = nullptr, int nnet = -1,
-                   const int *idx = nullptr, const int *pos = nullptr);
+                   const int *idx = nullptr, const int *pos = nullptr, const double *fscale = nullptr);
     int loss_grad(const unet_batch &bt, hipStream_t st);
 };

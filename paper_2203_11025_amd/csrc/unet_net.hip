@@ -360,11 +360,18 @@ void unet_net::forward_from_x0(int B, int H, int W, bool training, hipStream_t s
     const int last = Lv >= 2 ? dec_index(0, 'b') : enc_index(0, 'b');
     const bool fuse_head = !training && cfg.head && cfg.widths[0] == 32;
     const bool maps = use_cmap(training, H);
-    // a context-taking layer: its sources, and the context map when used
-    auto run_a = [&](int i, int Hl, int Wl) {
+    // a context-taking layer: its sources, and the context map when used;
+    // up (inference decoders): the first source is the coarse activation,
+    // upsampled inside the convolution
+    auto run_a = [&](int i, int Hl, int Wl, const bf16 *up = nullptr) {
         ConvEpi e;
         if (maps) e.cmap = cmap[i];
-        run_layer(i, layer_srcs(i, maps), B, Hl, Wl, training, st, e);
+        Srcs src = layer_srcs(i, maps);
+        if (up) {
+            src.s[0].p = up;
+            src.s[0].up = 1;
+        }
+        run_layer(i, src, B, Hl, Wl, training, st, e);
     };
     for (int l = 0; l < Lv; ++l) {
         int Hl = H >> l, Wl = W >> l;
@@ -386,8 +393,19 @@ void unet_net::forward_from_x0(int B, int H, int W, bool training, hipStream_t s
     for (int l = Lv - 2; l >= 0; --l) {
         int Hl = H >> l, Wl = W >> l;
         const bf16 *prev = (l == Lv - 2) ? act[enc_index(Lv - 1, 'b')].a : act[dec_index(l + 1, 'b')].a;
-        launch_up2_fwd(prev, B, Hl / 2, Wl / 2, cfg.widths[l + 1], up[l], st);
-        run_a(dec_index(l, 'a'), Hl, Wl);
+        // Upsampling inside the convolution saves writing and re-reading
+        // the upsampled tensor, but its in-LDS expansion is VALU work that
+        // the workgroup's barriers serialise with the MFMAs: it pays for
+        // 32-channel outputs only (on MI355X: 0.86 ms against 0.99 ms for
+        // upsampling plus convolution at 512^2 x 32 samples, while 64- and
+        // 128-channel outputs lose 12-25%).  Training keeps the upsampled
+        // tensor for the backward pass.
+        if (!training && cfg.widths[l] == 32) {
+            run_a(dec_index(l, 'a'), Hl, Wl, prev);
+        } else {
+            launch_up2_fwd(prev, B, Hl / 2, Wl / 2, cfg.widths[l + 1], up[l], st);
+            run_a(dec_index(l, 'a'), Hl, Wl);
+        }
         ConvEpi epi;
         if (fuse_head && dec_index(l, 'b') == last) {
             epi.head_w = P + head_w;
@@ -561,7 +579,7 @@ void unet_net::refold(hipStream_t st)
 
 int unet_net::wrap_apply(helm_handle *h, const float2 *r, size_t rs, float2 *e, size_t es, int nb,
                          int accumulate, hipStream_t st, const int *mask, int nnet, const int *idx,
-                         const int *pos)
+                         const int *pos, const double *fscale)
 {
     const int n = h->n, nc = n / 2;
     if (nnet < 0) {
@@ -571,7 +589,8 @@ int unet_net::wrap_apply(helm_handle *h, const float2 *r, size_t rs, float2 *e, 
     if (nnet > 0) {
         int rc = ensure_ws(nnet, nc, nc, false);
         if (rc) return rc;
-        launch_net_input(r, rs, nnet, n, h->kappa0, nullptr, rcoarse, red, s, x0, x0_stride(), st, idx);
+        launch_net_input(r, rs, nnet, n, h->kappa0, nullptr, rcoarse, red, s, x0, x0_stride(), st, idx,
+                         fscale);
         forward_from_x0(nnet, nc, nc, false, st);
     }
     launch_net_output(out, s, nb, n, e, es, accumulate, st, mask, pos);

@@ -60,6 +60,14 @@ def test_forward_parity(N, widths, B, H, training):
     out = net.forward(torch.from_numpy(x), training=training).cpu().numpy()
     ref = U.forward(cfg, p, buf, torch.from_numpy(x), training=training).numpy()
     assert rel(out, ref) <= 2e-2, rel(out, ref)
+    # the image frame alone (clamped upsampling and zero padding meet
+    # there), and the rows and columns at every 16-pixel tile seam
+    frame = np.zeros((H, H), bool)
+    frame[[0, -1], :] = frame[:, [0, -1]] = True
+    seams = np.zeros((H, H), bool)
+    seams[15::16, :] = seams[16::16, :] = seams[:, 15::16] = seams[:, 16::16] = True
+    for sel in (frame, seams):
+        assert rel(out[..., sel], ref[..., sel]) <= 2e-2, rel(out[..., sel], ref[..., sel])
 
 
 def test_params_roundtrip(N):
