@@ -186,6 +186,13 @@ int helm_coarse_slowness(helm_handle *h, float *kc, void *stream);
  * device time, launch count and work; the records stay until the next
  * helm_profile_start.  helm_profile_stop ends recording.  The hook is
  * process-wide; concurrent solves on several threads share it.
+ * helm_profile_sample(k), k >= 1 (default 1): only about one launch in k
+ * of each family is timed, chosen by a fixed hash of the launch's index
+ * since helm_profile_start (so that the subset does not alias with a
+ * repeated sequence of launches), and the launch count and work cover those
+ * launches only (each event costs a few microseconds of queue time between
+ * kernels).  The events carry no system-scope fence:
+ * they serve timing only.
  */
 #define HELM_PROF_NONE 0
 #define HELM_PROF_COARSE 1 /* dense coarsest-level solve (bytes)              */
@@ -198,6 +205,7 @@ int helm_coarse_slowness(helm_handle *h, float *kc, void *stream);
 int helm_profile_start(unsigned family_mask);
 int helm_profile_read(int family, double *total_ms, long long *launches, double *work);
 int helm_profile_stop(void);
+int helm_profile_sample(int every);
 
 /*
  * Launch-shape autotuner of the network convolutions.  With enable = 1, the

@@ -14,11 +14,14 @@ struct Family {
     std::vector<hipEvent_t> ev;  // start/stop pairs
     size_t used = 0;             // events recorded so far
     bool open = false;           // a start without its stop
+    long long seen = 0;          // launches since the start (timed or not)
+    bool skip = false;           // the open launch is not timed
     double work = 0.0;           // summed algorithmic work of the closed pairs
 };
 struct Prof {
     std::mutex mu;
     unsigned mask = 0;
+    int every = 1;        // time one launch in `every` of each family
     int active_rhs = -1;  // right-hand sides still iterating (set by the solver)
     Family f[NFAM];
 };
@@ -40,9 +43,27 @@ void prof_mark(int family, hipStream_t s, bool start, double work_per_rhs, int n
     std::lock_guard<std::mutex> lk(g_prof.mu);
     Family &F = g_prof.f[family];
     if (start == F.open) return;  // unbalanced call: ignore
+    if (start) {
+        // launch i is timed when a hash of i is divisible by the stride: a
+        // fixed subset of about 1 / every of the launches that does not
+        // alias with the period of a repeated launch sequence (the layers of
+        // a network pass)
+        unsigned long long z = (unsigned long long)F.seen++ * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 31)) * 0xBF58476D1CE4E5B9ull;
+        F.skip = g_prof.every > 1 && ((z ^ (z >> 29)) % (unsigned long long)g_prof.every) != 0;
+        if (F.skip) {
+            F.open = true;
+            return;
+        }
+    } else if (F.skip) {
+        F.open = false;
+        return;
+    }
     if (F.used == F.ev.size()) {
+        // timing only (read after the caller synchronises): no system-scope
+        // fence, whose cache writeback would stall and cool the next kernel
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return;
         F.ev.push_back(e);
     }
     if (hipEventRecord(F.ev[F.used], s) == hipSuccess) {
@@ -74,8 +95,21 @@ extern "C" int helm_profile_start(unsigned family_mask)
     for (auto &F : g_prof.f) {
         F.used = 0;
         F.open = false;
+        F.seen = 0;
+        F.skip = false;
         F.work = 0.0;
     }
+    return HELM_OK;
+}
+
+extern "C" int helm_profile_sample(int every)
+{
+    if (every < 1) {
+        set_error("helm_profile_sample: the stride must be at least 1");
+        return HELM_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.every = every;
     return HELM_OK;
 }
 

@@ -26,7 +26,8 @@ struct Src {
     // through the x2 bilinear upsampling (half-pixel centres, edges clamped),
     // each upsampled value rounded to bf16 as a stored upsampled tensor
     // would be.  Only the first source of an inference convolution with
-    // H and W even may set it.
+    // H and W even, a second source and at most 32 output channels may set
+    // it.
     int up = 0;
 };
 // Up to three sources concatenated along channels (by addressing only).

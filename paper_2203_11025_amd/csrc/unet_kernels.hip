@@ -568,11 +568,12 @@ __device__ __forceinline__ void wg_barrier() { __builtin_amdgcn_s_barrier(); }
 
 // UP: the first source is read through the x2 bilinear upsampling (Src::up).
 // A stage of one of its chunks copies the coarse window under the tile into
-// the halo buffer; the workgroup then expands it in place to the fine halo
-// (bf16, the values a stored upsampled tensor would hold) before the MFMAs.
-// The fine halo pairs rows (and columns) as (odd, even) fine indices 2c + 1,
-// 2c + 2, which read coarse c and c + 1 only, so each 2 x 2 fine block needs
-// a 2 x 2 coarse window.
+// an area of the halo buffer past the fine halo; the workgroup then expands
+// it to the fine halo (bf16, the values a stored upsampled tensor would
+// hold) before the MFMAs.  The fine halo pairs rows (and columns) as (odd,
+// even) fine indices 2c + 1, 2c + 2, which read coarse c and c + 1 only, so
+// each 2 x 2 fine block needs a 2 x 2 coarse window.  (32 output channels:
+// the larger halo buffers leave no LDS for wider weight blocks.)
 template <int MF, int NF, int EPI, bool RW, bool UP = false>
 __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int W, const bf16 *__restrict__ Wt,
                                                      int Cout, int mode, float *__restrict__ out32,
@@ -584,16 +585,17 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
     constexpr int CO = 16 * NF;
     constexpr int HSL = HY * HX * 4, HIN = (HSL + 511) / 512;  // halo slots, DMA instructions per wave
     constexpr int WSL = CO * 36, WIN = (WSL + 511) / 512;       // weight slots, instructions
-    constexpr int NISS = HIN + (RW ? WIN : 0);                  // instructions per stage and wave
+    // fused upsampling: fine halo row / column pairs, coarse window (CWN
+    // slots after the HIN * 512 of the fine halo, HINC more instructions)
+    constexpr int NPY = TH / 2 + 1, NPX = TW / 2 + 1, CWY = NPY + 1, CWX = NPX + 1;
+    constexpr int CWN = UP ? CWY * CWX * 4 : 0, HINC = (CWN + 511) / 512, HINT = HIN + HINC;
+    constexpr int NISS = HINT + (RW ? WIN : 0);                 // instructions per stage and wave
     // one chunk of at most 32 output channels: each wavefront keeps all the
     // weight fragments in registers (9 NF x 4 VGPRs) and reads only the
     // halo from LDS
     constexpr bool WREG = !RW && NF <= 2;
-    // fused upsampling: fine halo row / column pairs, coarse window
-    constexpr int NPY = TH / 2 + 1, NPX = TW / 2 + 1, CWY = NPY + 1, CWX = NPX + 1;
-    static_assert(!UP || CWY * CWX * 4 <= HIN * 512, "coarse window fits the halo buffer");
-    static_assert(!UP || RW, "an upsampled source comes with a second source");
-    __shared__ __attribute__((aligned(16))) uint4 hA_[HIN * 512], hB_[HIN * 512];
+    static_assert(!UP || (RW && NF == 2), "an upsampled source: a second source, 32 output channels");
+    __shared__ __attribute__((aligned(16))) uint4 hA_[HINT * 512], hB_[HINT * 512];
     __shared__ __attribute__((aligned(16))) uint4 wA_[WIN * 512], wB_[WIN * 512];
     // LDS-typed pointers keep each buffer's identity visible to the
     // compiler, so a read of one buffer does not wait for copies into the
@@ -628,7 +630,7 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
     // byte offsets stay in hoff/woff until after the MFMAs of the stage:
     // were their registers reused as fragment destinations, the compiler
     // would wait for these copies before the first fragment read.
-    int hoff[HIN], woff[WIN];
+    int hoff[HINT], woff[WIN];
     auto issue_halo = [&](luint4 *hbuf, int tx, int ty, int b, int ch, bool real) {
         const int x0 = tx * TW - 1, y0 = ty * TH - 1;
         int coff = ch * 32, s = 0;
@@ -639,27 +641,30 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
         const int Cs = in.s[s].stride ? in.s[s].stride : in.s[s].C;
         // an upsampled chunk copies its coarse window (rows and columns
         // clamped to the image: the clamped samples are the ones the
-        // interpolation reads) to slots 4 (row * CWX + column) + segment
+        // interpolation reads) to slots HIN * 512 + 4 (row * CWX + column) +
+        // segment; the fine halo slots stay untouched until the expansion
         const bool upc = UP && s == 0 && in.s[0].up;
         const int hh = upc ? H / 2 : H, ww = upc ? W / 2 : W;
         const size_t h0 = ((size_t)(in.s[s].shared ? 0 : b) * hh * ww) * Cs + coff;
         const __amdgpu_buffer_rsrc_t hr = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(in.s[s].p + h0), 0, (int)(((size_t)hh * ww * Cs - coff) * 2), BUF_DWORD3);
 #pragma unroll
-        for (int k = 0; k < HIN; ++k) {
+        for (int k = 0; k < HINT; ++k) {
             const int blk = k * NWV + wv, q = blk * 64 + lane;
-            const int pix = q >> 2, seg = (q & 3) ^ ((pix >> 2) & 3);
-            const int hy = pix / HX, y = y0 + hy, x = x0 + pix - hy * HX;
-            const bool ok = real && q < HSL && coff + seg * 8 < Cs && y >= 0 && y < H && x >= 0 && x < W;
-            int off = ok ? ((y * W + x) * Cs + seg * 8) * 2 : BUF_NONE;
-            if constexpr (UP) {
-                const int cp = q >> 2, cs = q & 3, cr = cp / CWX;
+            int off;
+            if (k < HIN) {
+                const int pix = q >> 2, seg = (q & 3) ^ ((pix >> 2) & 3);
+                const int hy = pix / HX, y = y0 + hy, x = x0 + pix - hy * HX;
+                const bool ok = real && !upc && q < HSL && coff + seg * 8 < Cs && y >= 0 && y < H && x >= 0 &&
+                                x < W;
+                off = ok ? ((y * W + x) * Cs + seg * 8) * 2 : BUF_NONE;
+            } else {
+                const int cq = q - HIN * 512, cp = cq >> 2, cs = cq & 3, cr = cp / CWX;
                 int gy = (y0 + 1) / 2 - 1 + cr, gx = (x0 + 1) / 2 - 1 + (cp - cr * CWX);
                 gy = gy < 0 ? 0 : (gy >= hh ? hh - 1 : gy);
                 gx = gx < 0 ? 0 : (gx >= ww ? ww - 1 : gx);
-                const bool cok = real && q < CWY * CWX * 4 && coff + cs * 8 < Cs;
-                const int coffs = cok ? ((gy * ww + gx) * Cs + cs * 8) * 2 : BUF_NONE;
-                off = upc ? coffs : off;
+                const bool cok = real && upc && cq < CWN && coff + cs * 8 < Cs;
+                off = cok ? ((gy * ww + gx) * Cs + cs * 8) * 2 : BUF_NONE;
             }
             hoff[k] = off;
             dma16(hr, hbuf + blk * 64, hoff[k]);
@@ -670,31 +675,20 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
     // (2k + p, 2m + q) blends window rows k, k + 1 and columns m, m + 1.  Its
     // weights are up_src's (1 - l, l) on those slots; at the first image row
     // (column) up_src's first sample is the second slot and its weight l is
-    // zero, so the weights become (l, 1 - l) = (0, 1).  The blend has the
-    // form of up_blend8, and each value equals a direct evaluation.
+    // zero, so the weights become (l, 1 - l) = (0, 1).  Each value is formed
+    // as up_blend8 forms it (the two horizontal blends of a fine column are
+    // shared by the pair's two rows) and equals a direct evaluation.
     auto build_up = [&](luint4 *hb, int tx, int ty) {
         constexpr int NIT = NPY * NPX * 4, NR = (NIT + 511) / 512;
         const int hc = H / 2, wc = W / 2;
-        uint4 w00[NR], w01[NR], w10[NR], w11[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int it = r * 512 + tid, pr = it >> 2, k = pr / NPX, m = pr - k * NPX;
-            if (it < NIT) {
-                const luint4 *c0 = hb + (k * CWX + m) * 4 + (it & 3);
-                w00[r] = lds_ld16(c0);
-                w01[r] = lds_ld16(c0 + 4);
-                w10[r] = lds_ld16(c0 + CWX * 4);
-                w11[r] = lds_ld16(c0 + CWX * 4 + 4);
-            }
-        }
-        WAIT_LGKM0();
-        wg_barrier();  // every window read is done before the halo overwrites it
+        const luint4 *cw = hb + HIN * 512;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const int it = r * 512 + tid, seg = it & 3, pr = it >> 2, k = pr / NPX, m = pr - k * NPX;
             if (it < NIT) {
-                const f8 a00 = u4_to_f8(w00[r]), a01 = u4_to_f8(w01[r]);
-                const f8 a10 = u4_to_f8(w10[r]), a11 = u4_to_f8(w11[r]);
+                const luint4 *c0 = cw + (k * CWX + m) * 4 + seg;
+                const f8 a00 = u4_to_f8(lds_ld16(c0)), a01 = u4_to_f8(lds_ld16(c0 + 4));
+                const f8 a10 = u4_to_f8(lds_ld16(c0 + CWX * 4)), a11 = u4_to_f8(lds_ld16(c0 + CWX * 4 + 4));
                 const int c = ty * (TH / 2) - 1 + k, d = tx * (TW / 2) - 1 + m;
                 float wy[2][2], wx[2][2];
                 bool iny[2], inx[2];
@@ -713,18 +707,24 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
                     inx[p] = fx >= 0 && fx < W;
                 }
 #pragma unroll
-                for (int pq = 0; pq < 4; ++pq) {
-                    const int p = pq >> 1, q = pq & 1;
-                    uint4 o = make_uint4(0u, 0u, 0u, 0u);
-                    if (iny[p] && inx[q]) {
-                        const float y0 = wy[p][0], y1 = wy[p][1], x0 = wx[q][0], x1 = wx[q][1];
-                        bf16 *e = reinterpret_cast<bf16 *>(&o);
+                for (int q = 0; q < 2; ++q) {
+                    f8 h0, h1;  // horizontal blends of window rows k and k + 1 at fine column q
 #pragma unroll
-                        for (int z = 0; z < 8; ++z)
-                            e[z] = (bf16)(y0 * (x0 * a00.v[z] + x1 * a01.v[z]) + y1 * (x0 * a10.v[z] + x1 * a11.v[z]));
+                    for (int z = 0; z < 8; ++z) {
+                        h0.v[z] = wx[q][0] * a00.v[z] + wx[q][1] * a01.v[z];
+                        h1.v[z] = wx[q][0] * a10.v[z] + wx[q][1] * a11.v[z];
                     }
-                    const int pix = (2 * k + p) * HX + 2 * m + q;
-                    lds_st16(hb + pix * 4 + (seg ^ ((pix >> 2) & 3)), o);
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        uint4 o = make_uint4(0u, 0u, 0u, 0u);
+                        if (iny[p] && inx[q]) {
+                            bf16 *e = reinterpret_cast<bf16 *>(&o);
+#pragma unroll
+                            for (int z = 0; z < 8; ++z) e[z] = (bf16)(wy[p][0] * h0.v[z] + wy[p][1] * h1.v[z]);
+                        }
+                        const int pix = (2 * k + p) * HX + 2 * m + q;
+                        lds_st16(hb + pix * 4 + (seg ^ ((pix >> 2) & 3)), o);
+                    }
                 }
             }
         }
@@ -841,7 +841,7 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
         // the constraint names a GPU register class, so the host pass skips it)
 #if defined(__HIP_DEVICE_COMPILE__)
 #pragma unroll
-        for (int q = 0; q < HIN; ++q) asm volatile("" ::"v"(hoff[q]));
+        for (int q = 0; q < HINT; ++q) asm volatile("" ::"v"(hoff[q]));
         if (RW) {
 #pragma unroll
             for (int q = 0; q < WIN; ++q) asm volatile("" ::"v"(woff[q]));
@@ -1891,8 +1891,8 @@ void conv_dispatch(const ConvShape &c, const Srcs &in, int B, int H, int W, cons
     const int CO = 16 * NF;
     const int ncob = (Cout + CO - 1) / CO;
     const int ep = epi.head_out ? 2 : (epi.pool ? 1 : 0);
-    // an upsampled first source (plain epilogue, more than one chunk) runs
-    // on k_conv3x3d only
+    // an upsampled first source (plain epilogue, more than one chunk, at
+    // most 32 output channels) runs on k_conv3x3d only
     const bool upsrc = in.s[0].up != 0;
     if ((c.kind == 1 || upsrc) && !conv_in8(in)) {
         const long long ntiles = (long long)B * ((H + 8 * c.mf - 1) / (8 * c.mf)) * ((W + 15) / 16);
@@ -1901,13 +1901,9 @@ void conv_dispatch(const ConvShape &c, const Srcs &in, int B, int H, int W, cons
 #define CONVUP(mf, nf)                                                                                         \
     hipLaunchKernelGGL((k_conv3x3d<mf, nf, 0, true, true>), grid, dim3(512), 0, s, in, B, H, W, Wt, Cout, mode, \
                        out32, out16, scale, shift, slope, epi)
-        if (upsrc) {
-            if (c.mf == 4 && NF == 4)
-                CONVUP(4, 4);
-            else if (c.mf == 4)
+        if (upsrc) {  // 32 output channels (NF == 2) only
+            if (c.mf == 4)
                 CONVUP(4, 2);
-            else if (NF == 4)
-                CONVUP(2, 4);
             else
                 CONVUP(2, 2);
             return;

@@ -24,7 +24,7 @@ PREC = {"sl": 0, "unet_cgc": 1, "unet_defl": 2}
 EXPORTS = [
     "helm_setup", "helm_destroy", "helm_level_size", "helm_num_levels", "helm_apply",
     "helm_sl_vcycle", "helm_fgmres_solve", "helm_last_error", "helm_profile_start",
-    "helm_profile_read", "helm_profile_stop", "helm_autotune", "helm_autotune_entries", "helm_training_triples", "helm_coarse_slowness",
+    "helm_profile_read", "helm_profile_stop", "helm_profile_sample", "helm_autotune", "helm_autotune_entries", "helm_training_triples", "helm_coarse_slowness",
 ]
 PROF = {"none": 0, "coarse": 1, "down": 2, "up": 3, "cgs": 4, "apply": 5, "conv": 6, "wgrad": 7}
 
@@ -89,6 +89,8 @@ def lib():
         L.helm_profile_read.restype = ip
         L.helm_profile_stop.argtypes = []
         L.helm_profile_stop.restype = ip
+        L.helm_profile_sample.argtypes = [ip]
+        L.helm_profile_sample.restype = ip
         L.helm_autotune.argtypes = [ip]
         L.helm_autotune.restype = ip
         L.helm_autotune_entries.argtypes = []
@@ -224,12 +226,14 @@ def fgmres_solve(problems, rhs, m=20, tol=1e-7, maxit=20000, prec="sl", net=None
     return xs, [stats[i].as_dict() for i in range(total)], rc
 
 
-def profile_start(*families):
-    """Start timing every launch of the given kernel families with HIP events
-    on their launch streams, summing each launch's algorithmic work."""
+def profile_start(*families, every=1):
+    """Start timing the launches of the given kernel families with HIP events
+    on their launch streams (every `every`-th launch of each family), summing
+    the timed launches' algorithmic work."""
     mask = 0
     for f in families:
         mask |= 1 << PROF[f]
+    _check(lib().helm_profile_sample(int(every)), "helm_profile_sample")
     _check(lib().helm_profile_start(mask), "helm_profile_start")
 
 

@@ -220,3 +220,24 @@ def test_fgmres_2048_largest_grid(H, oracle):
     x = xs[0].cpu().numpy()
     for k in range(2):
         assert _true_relres(oracle, kap, gam, om, b[k], x[k]) <= 1e-7
+
+
+def test_profile_sampling(H):
+    """Live kernel timing: every launch, then about one in four (a fixed
+    hashed subset: 11 of the first 40), with the same work per launch."""
+    n = 64
+    kap, gam, om = medium(n, 61)
+    h = handle(H, kap, gam, om, levels=2)
+    x = torch.from_numpy(crandn(2, n, n)).cuda()
+    counts = {}
+    for every in (1, 4):
+        H.profile_start("apply", every=every)
+        for _ in range(40):
+            h.apply(x)
+        torch.cuda.synchronize()
+        ms, launches, work = H.profile_read("apply")
+        assert ms > 0.0
+        counts[every] = (launches, work / launches)
+    H.profile_stop()
+    assert counts[1][0] == 40 and counts[4][0] == 11
+    assert counts[4][1] == counts[1][1] == 24.0 * n * n * 2
