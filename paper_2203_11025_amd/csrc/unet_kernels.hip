@@ -111,18 +111,29 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[MF][NF], int lane, in
         float4 sc[NF], sh[NF];
 #pragma unroll
         for (int nf = 0; nf < NF; ++nf) bn(nf * 16 + 4 * (lane >> 4), sc[nf], sh[nf]);
-        // the context map of the whole tile first (one wait for all loads)
+        // the context map of the whole tile first: branch-free buffer loads
+        // (pieces outside the image or Cout read as zero), so that they all
+        // issue before the first wait
         f16x4 mp[MF][NF];
+        if (mode == 1 && epi.cmap) {
+            const __amdgpu_buffer_rsrc_t mr = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)epi.cmap, 0, (int)((size_t)H * W * Cout * 2), BUF_DWORD3);
 #pragma unroll
-        for (int mf = 0; mf < MF; ++mf)
+            for (int mf = 0; mf < MF; ++mf)
 #pragma unroll
-            for (int nf = 0; nf < NF; ++nf) {
-                mp[mf][nf] = f16x4{};
-                const int y = y0 + mf;
-                if (mode == 1 && epi.cmap && y < H && x < W && (full_co || co0 + nf * 16 + 4 * (lane >> 4) < Cout))
-                    mp[mf][nf] = *reinterpret_cast<const f16x4 *>(epi.cmap + ((size_t)y * W + x) * Cout + co0 +
-                                                                  4 * (lane >> 4) + nf * 16);
-            }
+                for (int nf = 0; nf < NF; ++nf) {
+                    const int y = y0 + mf, c = co0 + 4 * (lane >> 4) + nf * 16;
+                    const bool ok = y < H && x < W && (full_co || c < Cout);
+                    mp[mf][nf] = __builtin_bit_cast(
+                        f16x4, __builtin_amdgcn_raw_buffer_load_b64(mr, ok ? ((y * W + x) * Cout + c) * 2 : BUF_NONE,
+                                                                   0, 0));
+                }
+        } else {
+#pragma unroll
+            for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+                for (int nf = 0; nf < NF; ++nf) mp[mf][nf] = f16x4{};
+        }
 #pragma unroll
         for (int mf = 0; mf < MF; ++mf) {
             const int y = y0 + mf;
