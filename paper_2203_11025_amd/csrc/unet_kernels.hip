@@ -128,6 +128,11 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[MF][NF], int lane, in
                         f16x4, __builtin_amdgcn_raw_buffer_load_b64(mr, ok ? ((y * W + x) * Cout + c) * 2 : BUF_NONE,
                                                                    0, 0));
                 }
+            // one wait here, on every lane: waits left inside the divergent
+            // store branches below would make the compiler wait for all
+            // memory operations at the next write of these registers (the
+            // next stage's copy issue)
+            __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0); expcnt, lgkmcnt untouched
         } else {
 #pragma unroll
             for (int mf = 0; mf < MF; ++mf)
