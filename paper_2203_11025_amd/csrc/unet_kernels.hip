@@ -611,6 +611,13 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
     // halo from LDS
     constexpr bool WREG = !RW && NF <= 2;
     static_assert(!UP || (RW && NF == 2), "an upsampled source: a second source, 32 output channels");
+    // Wavefront layout.  SPL = 2 (64 output channels, plain epilogue): the
+    // wavefronts pair up over the block's channels, each taking 2 MF rows x
+    // NF / 2 fragments: the same MFMAs from fewer fragment reads (3 (2 MF +
+    // 2) + 9 NF / 2 instead of 3 (MF + 2) + 9 NF per stage), since the weights
+    // dominate those reads (1.5% faster network inference on MI355X).
+    constexpr int SPL = (NF == 4 && EPI == 0 && !WREG) ? 2 : 1;
+    constexpr int WMF = MF * SPL, WNF = NF / SPL;
     __shared__ __attribute__((aligned(16))) uint4 hA_[HINT * 512], hB_[HINT * 512];
     __shared__ __attribute__((aligned(16))) uint4 wA_[WIN * 512], wB_[WIN * 512];
     // LDS-typed pointers keep each buffer's identity visible to the
@@ -760,17 +767,20 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
         }
     };
 
-    f32x4 acc[MF][NF];
+    // this wavefront: tile rows wrow .. wrow + WMF - 1, block channels wco ..
+    // wco + 16 WNF - 1
+    const int wrow = (wv / SPL) * WMF, wco = (wv % SPL) * WNF * 16;
+    f32x4 acc[WMF][WNF];
 #pragma unroll
-    for (int i = 0; i < MF; ++i)
+    for (int i = 0; i < WMF; ++i)
 #pragma unroll
-        for (int j = 0; j < NF; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < WNF; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     // folded BN of the lane's output channels, kept in registers (no global
     // loads in the loop besides the copies and the context map)
-    float4 bsc[NF], bsh[NF];
+    float4 bsc[WNF], bsh[WNF];
 #pragma unroll
-    for (int nf = 0; nf < NF; ++nf) {
-        const int co = co0 + nf * 16 + 4 * (lane >> 4);
+    for (int nf = 0; nf < WNF; ++nf) {
+        const int co = co0 + wco + nf * 16 + 4 * (lane >> 4);
         bsc[nf] = bsh[nf] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (mode == 1 && co < Cout) {
             bsc[nf] = *reinterpret_cast<const float4 *>(scale + co);
@@ -784,19 +794,19 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
         const int seg = lane >> 4;
 #pragma unroll
         for (int kx = 0; kx < 3; ++kx) {
-            bf16x8 a[MF + 2];
+            bf16x8 a[WMF + 2];
 #pragma unroll
-            for (int r = 0; r < MF + 2; ++r) {
-                const int p = (wv * MF + r) * HX + (lane & 15) + kx;
+            for (int r = 0; r < WMF + 2; ++r) {
+                const int p = (wrow + r) * HX + (lane & 15) + kx;
                 a[r] = *reinterpret_cast<const lbf16x8 *>(hbuf + p * 4 + (seg ^ ((p >> 2) & 3)));
             }
 #pragma unroll
             for (int ky = 0; ky < 3; ++ky) {
                 const int tap = ky * 3 + kx;
-                bf16x8 bw[NF];
+                bf16x8 bw[WNF];
 #pragma unroll
-                for (int nf = 0; nf < NF; ++nf) {
-                    const int co = nf * 16 + (lane & 15);
+                for (int nf = 0; nf < WNF; ++nf) {
+                    const int co = wco + nf * 16 + (lane & 15);
                     if constexpr (WREG)
                         bw[nf] = wreg[tap][nf];
                     else
@@ -804,9 +814,9 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
                                                                     (seg ^ ((co >> 2) & 3)));
                 }
 #pragma unroll
-                for (int mf = 0; mf < MF; ++mf)
+                for (int mf = 0; mf < WMF; ++mf)
 #pragma unroll
-                    for (int nf = 0; nf < NF; ++nf)
+                    for (int nf = 0; nf < WNF; ++nf)
                         acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[nf], a[mf + ky], acc[mf][nf], 0, 0, 0);
             }
         }
@@ -864,12 +874,13 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
         }
 #endif
         if (st % nch == nch - 1) {
-            conv_epilogue<MF, NF, EPI>(acc, lane, b, ty * TH + wv * MF, tx * TW + (lane & 15), H, W, Cout, co0,
-                                       mode, out32, out16, slope, epi, [&](int c, float4 &sc, float4 &sh) {
-                                           // c = 16 nf + 4 (lane / 16) (+ 0): fragment nf's registers
-                                           sc = bsc[c >> 4];
-                                           sh = bsh[c >> 4];
-                                       });
+            conv_epilogue<WMF, WNF, EPI>(acc, lane, b, ty * TH + wrow, tx * TW + (lane & 15), H, W, Cout,
+                                         co0 + wco, mode, out32, out16, slope, epi,
+                                         [&](int c, float4 &sc, float4 &sh) {
+                                             // c = 16 nf + 4 (lane / 16) (+ 0): fragment nf's registers
+                                             sc = bsc[c >> 4];
+                                             sh = bsh[c >> 4];
+                                         });
             advance(tx, ty, b);
         }
         wg_barrier();  // every wavefront is done with these buffers
