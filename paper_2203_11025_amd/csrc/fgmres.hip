@@ -39,6 +39,7 @@ struct FgWork {
     double *h_d = nullptr;    // pinned: relres
     int *h_its = nullptr;     // pinned: iteration counts
     int *h_fb = nullptr;      // pinned: fallback flags
+    int *h_a = nullptr;       // pinned: active flags read inside a restart cycle
     int *h_net = nullptr;     // pinned: network batch [idx | pos]
     int *d_net = nullptr;     // device copy of h_net
     float2 *t1 = nullptr, *t2 = nullptr;  // network-preconditioner scratch
@@ -156,6 +157,7 @@ void work_free(FgWork *w)
     if (w->cap) hipStreamDestroy(w->cap);
     if (w->h_net) hipHostFree(w->h_net);
     if (w->h_fb) hipHostFree(w->h_fb);
+    if (w->h_a) hipHostFree(w->h_a);
     if (w->h_i) hipHostFree(w->h_i);
     if (w->h_d) hipHostFree(w->h_d);
     if (w->h_its) hipHostFree(w->h_its);
@@ -239,6 +241,7 @@ int work_ensure(helm_handle *h, int nb, int m, bool scratch, FgWork **out)
     }
     if (hipHostMalloc((void **)&w->h_net, 2 * nb * sizeof(int)) != hipSuccess ||
         hipHostMalloc((void **)&w->h_fb, nb * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void **)&w->h_a, nb * sizeof(int)) != hipSuccess ||
         hipHostMalloc((void **)&w->h_i, nb * sizeof(int)) != hipSuccess ||
         hipHostMalloc((void **)&w->h_d, nb * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&w->h_its, nb * sizeof(int)) != hipSuccess) {
@@ -348,6 +351,9 @@ int replay_cycle(FgWork *w, const FgState &S, int nnet, const float2 *b, const d
     return HELM_OK;
 }
 
+// Arnoldi steps between refreshes of the network batch in an eager solve
+constexpr int NET_SEG = 5;
+
 // One problem (medium) with nb right-hand sides.
 int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, double tol,
                   int maxit, int prec, unet_net *net, double stall_ratio,
@@ -377,11 +383,12 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
                          nblk, nb, nullptr, s);
     hipLaunchKernelGGL(k_restart, dim3(nb), dim3(256), 0, s, S, w->rpartial, nblk, 1);
     int nnet = 0;
-    // one restart cycle: m Arnoldi steps, the least-squares update of x and the
-    // true residual that starts the next cycle; kernels only (capturable)
-    auto cycle = [&](hipStream_t cs) -> int {
+    // Arnoldi steps j0 .. j1 - 1 of a restart cycle, then (last) the
+    // least-squares update of x and the true residual that starts the next
+    // cycle; kernels only (capturable)
+    auto cycle = [&](hipStream_t cs, int j0, int j1, bool last) -> int {
         int rc2;
-        for (int j = 0; j < m; ++j) {
+        for (int j = j0; j < j1; ++j) {
             float2 *vj = w->V + (size_t)j * N, *zj = w->Z + (size_t)j * N;
             float2 *wj = w->V + (size_t)(j + 1) * N;
             if (!use_net) {
@@ -395,12 +402,25 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
             launch_apply(L0, 0.f, zj, zsb, wj, vsb, nb, S.active, cs);
             launch_arnoldi_step(S, w->V, vsb, N, j, w->partial, nblk, cs);
         }
+        if (!last) return HELM_OK;
         hipLaunchKernelGGL(k_solve_y, dim3(nb), dim3(64), 0, cs, S);
         launch_xupdate(x, N, w->Z, zsb, N, S.y, MAXV, S.k, nb, S.incycle, cs);
         launch_true_residual(h->kappa0, h->gamma0, h->n, h->omega, b, N, x, N, w->V, vsb,
                              w->rpartial, nblk, nb, S.incycle, cs);
         hipLaunchKernelGGL(k_restart, dim3(nb), dim3(256), 0, cs, S, w->rpartial, nblk, 0);
         return HELM_OK;
+    };
+    // the network batch: right-hand sides that are active and not in
+    // fallback (flags in act and fb), written to d_net; returns its size
+    auto set_net_batch = [&](const int *act, const int *fb) -> int {
+        int cnt = 0;
+        for (int i = 0; i < nb; ++i) w->h_net[nb + i] = -1;
+        for (int i = 0; i < nb; ++i)
+            if (act[i] && !fb[i]) {
+                w->h_net[cnt] = i;
+                w->h_net[nb + i] = cnt++;
+            }
+        return cnt;
     };
     for (;;) {
         HELM_HIP_CHECK(hipMemcpyAsync(w->h_d, S.relres, nb * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -419,12 +439,7 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
         nnet = 0;
         if (use_net) {
             // gather the right-hand sides still using the network
-            for (int i = 0; i < nb; ++i) w->h_net[nb + i] = -1;
-            for (int i = 0; i < nb; ++i)
-                if (w->h_i[i] && !w->h_fb[i]) {
-                    w->h_net[nnet] = i;
-                    w->h_net[nb + i] = nnet++;
-                }
+            nnet = set_net_batch(w->h_i, w->h_fb);
             HELM_HIP_CHECK(hipMemcpyAsync(w->d_net, w->h_net, 2 * nb * sizeof(int), hipMemcpyHostToDevice, s));
         }
         HELM_HIP_CHECK(hipMemcpyAsync(S.active, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
@@ -434,9 +449,27 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
             if ((rc = ensure_vcycle_ws(h, nb))) return rc;
             if (use_net && nnet > 0 && (rc = net->ensure_ws(nnet, h->n / 2, h->n / 2, false))) return rc;
             rc = replay_cycle(w, S, nnet, b, x, prec, net, h->ws_gen, s,
-                              [&](hipStream_t cs) { return cycle(cs); });
+                              [&](hipStream_t cs) { return cycle(cs, 0, m, true); });
+        } else if (!use_net) {
+            rc = cycle(s, 0, m, true);
         } else {
-            rc = cycle(s);
+            // Right-hand sides that converge (or fall back) inside the cycle
+            // leave the network batch at the next segment boundary instead of
+            // at the cycle's end: the network is most of an M_VU step, and a
+            // host round trip every NET_SEG steps costs little next to it.
+            for (int j0 = 0; j0 < m && !rc; j0 += NET_SEG) {
+                const int j1 = std::min(m, j0 + NET_SEG);
+                rc = cycle(s, j0, j1, j1 == m);
+                if (rc || j1 == m || nnet == 0) continue;
+                HELM_HIP_CHECK(hipMemcpyAsync(w->h_a, S.active, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+                HELM_HIP_CHECK(hipMemcpyAsync(w->h_fb, S.fallback, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+                HELM_HIP_CHECK(hipStreamSynchronize(s));
+                int cnt = 0;
+                for (int i = 0; i < nb; ++i) cnt += w->h_a[i] && !w->h_fb[i];
+                if (cnt == nnet) continue;  // nobody left the batch
+                nnet = set_net_batch(w->h_a, w->h_fb);
+                HELM_HIP_CHECK(hipMemcpyAsync(w->d_net, w->h_net, 2 * nb * sizeof(int), hipMemcpyHostToDevice, s));
+            }
         }
         if (rc) return rc;
         for (int i = 0; i < nb; ++i)
