@@ -352,7 +352,7 @@ int replay_cycle(FgWork *w, const FgState &S, int nnet, const float2 *b, const d
 }
 
 // Arnoldi steps between refreshes of the network batch in an eager solve
-constexpr int NET_SEG = 5;
+constexpr int NET_SEG = 2;
 
 // One problem (medium) with nb right-hand sides.
 int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, double tol,
