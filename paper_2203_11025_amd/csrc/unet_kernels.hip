@@ -1336,13 +1336,14 @@ __global__ void k_maxpool_bwd(const float *__restrict__ dout, int cstride, int c
 
 // ------------------------------------------------------------------ upsampling
 
-// Thread per (coarse column j, 8-channel group, UP_R coarse rows): it writes
-// the 2 UP_R x 2 fine pixels of those rows and columns.  Fine index 2i + a
-// reads coarse i - 1 .. i + 1 only, so a window of three coarse columns rolls
-// down the rows and each coarse sample is loaded about (UP_R + 2) / UP_R
-// times instead of four.  Every fine pixel blends the same samples with the
-// same weights as a direct evaluation of up_src.
-// grid (columns x channel groups, h / UP_R row blocks, batch)
+// Thread per (fine column, 8-channel group, UP_R coarse rows): it writes the
+// 2 UP_R fine pixels of that column over those rows.  Fine row 2i + a reads
+// coarse rows i - 1 .. i + 1 only, so a window of three coarse rows (at the
+// column's two coarse columns) rolls down, and each coarse sample is loaded
+// about (UP_R + 2) / UP_R times per fine column instead of twice per row.
+// Every fine pixel blends the same samples with the same weights as a direct
+// evaluation of up_src.
+// grid (fine columns x channel groups, h / UP_R row blocks, batch)
 constexpr int UP_R = 4;
 __device__ __forceinline__ uint4 up_pick(int slot, const uint4 &v0, const uint4 &v1, const uint4 &v2)
 {
@@ -1352,29 +1353,22 @@ __global__ void k_up2_fwd(const bf16 *__restrict__ in, int h, int w, int C, bf16
 {
     const int W = 2 * w, G = C / 8;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= w * G) return;
-    const int j = t / G, g = t - j * G, b = blockIdx.z;
+    if (t >= W * G) return;
+    // fine column x = 2j + a, channel group g (fastest: a wavefront's stores
+    // cover whole consecutive pixels)
+    const int x = t / G, g = t - x * G, b = blockIdx.z;
     const int i0 = blockIdx.y * UP_R, i1 = i0 + UP_R < h ? i0 + UP_R : h;
-    // fine columns 2j, 2j + 1: coarse columns as slots of the window j - 1 .. j + 1
-    int cs[2][2];
-    float lx[2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        int x0, x1;
-        up_src(2 * j + a, w, x0, x1, lx[a]);
-        cs[a][0] = x0 - j + 1;
-        cs[a][1] = x1 - j + 1;
-    }
-    const int cm = j > 0 ? j - 1 : 0, cp = j + 1 < w ? j + 1 : w - 1;
+    int x0, x1;
+    float lx;
+    up_src(x, w, x0, x1, lx);
     const bf16 *pb = in + (size_t)b * h * w * C + 8 * g;
-    auto ldrow = [&](int r, uint4 (&v)[3]) {
+    auto ldrow = [&](int r, uint4 (&v)[2]) {
         r = r < 0 ? 0 : (r >= h ? h - 1 : r);
         const bf16 *pr = pb + (size_t)r * w * C;
-        v[0] = *reinterpret_cast<const uint4 *>(pr + (size_t)cm * C);
-        v[1] = *reinterpret_cast<const uint4 *>(pr + (size_t)j * C);
-        v[2] = *reinterpret_cast<const uint4 *>(pr + (size_t)cp * C);
+        v[0] = *reinterpret_cast<const uint4 *>(pr + (size_t)x0 * C);
+        v[1] = *reinterpret_cast<const uint4 *>(pr + (size_t)x1 * C);
     };
-    uint4 win[3][3];  // coarse rows i - 1, i, i + 1
+    uint4 win[3][2];  // coarse rows i - 1, i, i + 1 at columns x0, x1
     ldrow(i0 - 1, win[0]);
     ldrow(i0, win[1]);
     for (int i = i0; i < i1; ++i) {
@@ -1385,24 +1379,15 @@ __global__ void k_up2_fwd(const bf16 *__restrict__ in, int h, int w, int C, bf16
             float ly;
             up_src(2 * i + ar, h, y0, y1, ly);
             const int r0 = y0 - i + 1, r1 = y1 - i + 1;
-            uint4 row0[3], row1[3];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                row0[q] = up_pick(r0, win[0][q], win[1][q], win[2][q]);
-                row1[q] = up_pick(r1, win[0][q], win[1][q], win[2][q]);
-            }
-            bf16 *po = out + (((size_t)b * 2 * h + 2 * i + ar) * W + 2 * j) * C + 8 * g;
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const f8 a00 = u4_to_f8(up_pick(cs[a][0], row0[0], row0[1], row0[2]));
-                const f8 a01 = u4_to_f8(up_pick(cs[a][1], row0[0], row0[1], row0[2]));
-                const f8 a10 = u4_to_f8(up_pick(cs[a][0], row1[0], row1[1], row1[2]));
-                const f8 a11 = u4_to_f8(up_pick(cs[a][1], row1[0], row1[1], row1[2]));
-                st8(po + (size_t)a * C, up_blend8(a00, a01, a10, a11, ly, lx[a]));
-            }
+            const f8 a00 = u4_to_f8(up_pick(r0, win[0][0], win[1][0], win[2][0]));
+            const f8 a01 = u4_to_f8(up_pick(r0, win[0][1], win[1][1], win[2][1]));
+            const f8 a10 = u4_to_f8(up_pick(r1, win[0][0], win[1][0], win[2][0]));
+            const f8 a11 = u4_to_f8(up_pick(r1, win[0][1], win[1][1], win[2][1]));
+            st8(out + (((size_t)b * 2 * h + 2 * i + ar) * W + x) * C + 8 * g,
+                up_blend8(a00, a01, a10, a11, ly, lx));
         }
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
+        for (int q = 0; q < 2; ++q) {
             win[0][q] = win[1][q];
             win[1][q] = win[2][q];
         }
@@ -2206,7 +2191,7 @@ void launch_maxpool_bwd(const float *dout, const uint8_t *arg, int B, int H, int
 
 void launch_up2_fwd(const bf16 *in, int B, int h, int w, int C, bf16 *out, hipStream_t s)
 {
-    const int row = w * (C / 8);
+    const int row = 2 * w * (C / 8);
     hipLaunchKernelGGL(k_up2_fwd, dim3((row + 255) / 256, (h + UP_R - 1) / UP_R, B), dim3(256), 0, s, in, h, w,
                        C, out);
 }
