@@ -420,10 +420,12 @@ const auto kPassB = make_pb(std::make_integer_sequence<int, MAXM>{});
 
 int krylov_nblk(size_t N, int nb)
 {
-    // at least two point pairs per thread; about 8192 workgroups over the
-    // batch (fewer, longer blocks amortise the FP64 block reductions)
+    // at least two point pairs per thread; about 2048 workgroups over the
+    // batch, at least 64 per right-hand side (fewer, longer blocks amortise
+    // the FP64 block reductions: on MI355X, 1024^2 x 32, the passes stream
+    // 2% faster than with 8192 workgroups and 5% faster than with 16384)
     size_t b = (N + 511) / 512;
-    const size_t cap = std::min<size_t>(1024, std::max<size_t>(128, 8192 / (size_t)std::max(1, nb)));
+    const size_t cap = std::min<size_t>(1024, std::max<size_t>(64, 2048 / (size_t)std::max(1, nb)));
     if (b < 1) b = 1;
     if (b > cap) b = cap;
     return (int)b;
