@@ -144,8 +144,8 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are "
-                          "not part of this build (the path shards by medium and right-hand "
-                          "side with no exchange)"}))
+                          "not implemented (the path shards by medium and right-hand side "
+                          "with no exchange)"}))
         sys.exit(2)
     import numpy as np
     import torch

@@ -9,8 +9,8 @@ max_pool2d, interpolate) in the precision of the tensors passed in (float32
 for parity, float64 for finite-difference checks); gradients come from
 torch.autograd over these operations.
 
-Network (section 3.1 gives the U-Net idea; the layer recipe here is the one
-fixed for this build): L levels of widths w_0..w_{L-1}; level l applies twice
+Network (section 3.1 gives the U-Net idea; the layer recipe here is the
+configured network's): L levels of widths w_0..w_{L-1}; level l applies twice
 [3x3 convolution (zero padding 1, no bias) -> batch normalisation ->
 LeakyReLU(0.2)]; 2x2 max pooling between levels; on the way up a bilinear x2
 upsampling (half-pixel centres) concatenated as [upsampled, skip] and the
