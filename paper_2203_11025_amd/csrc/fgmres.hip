@@ -60,8 +60,6 @@ __device__ __forceinline__ double2 dmul(double2 a, double2 b)
 {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ double2 dconj(double2 a) { return make_double2(a.x, -a.y); }
-__device__ __forceinline__ double dabs(double2 a) { return hypot(a.x, a.y); }
 
 __device__ __forceinline__ double wave_sum(double v)
 {
