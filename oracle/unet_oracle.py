@@ -266,22 +266,37 @@ def unet_apply(cfg, p, buf, r, kappa_c, ctx=None, dtype=torch.float32):
     return _prolong_c(ec)
 
 
-def precond_cgc(hier, cfg, p, buf, r, kappa_c, weight=0.8, ctx=None):
-    """M_CU: Jacobi on A, network coarse correction of the new residual,
-    Jacobi on A (Algorithm 2 with the network's coarse-grid correction)."""
+def cgc_compose(hier, net_fn, r, weight=0.8):
+    """Algorithm 2 with a coarse-grid correction given as a map net_fn from a
+    fine residual to a fine error estimate: a damped Jacobi sweep on A from
+    zero, the correction of the new residual, a damped Jacobi sweep on A.
+        e1 = w D_A^-1 r,  e2 = e1 + net_fn(r - A e1),  e = e2 + w D_A^-1 (r - A e2)"""
     kap, gam, om = hier.kappa0, hier.gamma0, hier.omega
     e1 = helm_oracle.jacobi(kap, gam, om, r, np.zeros_like(r), shift=0.0, weight=weight)
     r1 = helm_oracle.residual(kap, gam, om, r, e1)
-    e2 = e1 + unet_apply(cfg, p, buf, r1, kappa_c, ctx=ctx)
+    e2 = e1 + net_fn(r1)
     return helm_oracle.jacobi(kap, gam, om, r, e2, shift=0.0, weight=weight)
+
+
+def defl_compose(hier, net_fn, r):
+    """Eq. 3.4 with the error estimate given as a map net_fn: e0 = net_fn(r),
+    then an SL V-cycle from zero on the remaining residual,
+        e = e0 + V(0, r - A e0)."""
+    e0 = net_fn(r)
+    r1 = hier.residual_A(r, e0)
+    return e0 + hier.vcycle(r1)
+
+
+def precond_cgc(hier, cfg, p, buf, r, kappa_c, weight=0.8, ctx=None):
+    """M_CU: Jacobi on A, network coarse correction of the new residual,
+    Jacobi on A (Algorithm 2 with the network's coarse-grid correction)."""
+    return cgc_compose(hier, lambda v: unet_apply(cfg, p, buf, v, kappa_c, ctx=ctx), r, weight)
 
 
 def precond_defl(hier, cfg, p, buf, r, kappa_c, ctx=None):
     """M_VU (eq. 3.4): e0 = network(r), then an SL V-cycle on the remaining
     residual: e = e0 + V(0, r - A e0)."""
-    e0 = unet_apply(cfg, p, buf, r, kappa_c, ctx=ctx)
-    r1 = hier.residual_A(r, e0)
-    return e0 + hier.vcycle(r1)
+    return defl_compose(hier, lambda v: unet_apply(cfg, p, buf, v, kappa_c, ctx=ctx), r)
 
 
 # ----------------------------------------------------------------- training

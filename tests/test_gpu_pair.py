@@ -101,8 +101,13 @@ def test_shared_context_maps(N, H):
 
 
 def test_pair_loss_and_gradient_parity(N):
-    """Joint loss and both networks' gradients against the oracle's autograd
-    with bf16 emulation (same rounding points as the device)."""
+    """Joint loss and both networks' gradients against the oracle's autograd,
+    the plain FP32 oracle and the bf16-emulating one, within twice the
+    rounding spread the oracle shows on this pair and batch
+    (tests/grad_bounds.py).  Encoder gradients come through the whole solver
+    first, so their spread is the largest."""
+    from tests import grad_bounds as GB
+
     ce, pe, be, cs, ps, bs, enc, sol = make_pair(N, 11, perturb=False)
     n, nb = 64, 3
     rng = np.random.default_rng(4)
@@ -111,39 +116,20 @@ def test_pair_loss_and_gradient_parity(N):
     kc = rng.uniform(0.25, 1.0, (nb, n // 2, n // 2)).astype(np.float32)
     loss, ge, gs = N.pair_loss_grad(enc, sol, torch.from_numpy(r).cuda(), torch.from_numpy(e).cuda(),
                                     torch.from_numpy(kc).cuda())
-    ga = {k: v.clone().requires_grad_(True) for k, v in pe.items()}
-    gb = {k: v.clone().requires_grad_(True) for k, v in ps.items()}
-    U.EMULATE_BF16 = True
-    try:
-        lo = U.pair_training_loss(ce, ga, be, cs, gb, bs, r, e, kc)
-        lo.backward()
-    finally:
-        U.EMULATE_BF16 = False
-    assert abs(loss - lo.item()) <= 2e-3 * abs(lo.item()), (loss, lo.item())
-    # what remains after emulation is bf16 rounding decisions that flip under
-    # a different FP32 accumulation order, amplified by every BN backward on
-    # the way; the bound grows with the number of BN layers between a tensor
-    # and the loss.  Encoder gradients come through the whole solver first.
-    sol_names = [nm for nm, _, _ in U.layer_specs(cs)]
-    enc_names = [nm for nm, _, _ in U.layer_specs(ce)]
+
+    def loss_fn(pgs, rr, dtype):
+        bbe = {k: v.to(dtype) for k, v in be.items()}
+        bbs = {k: v.to(dtype) for k, v in bs.items()}
+        return U.pair_training_loss(ce, pgs[0], bbe, cs, pgs[1], bbs, rr, e, kc, dtype=dtype)
+
+    M = GB.measure(loss_fn, [pe, ps], r)
+    assert abs(loss - M["lossE"]) <= 2e-3 * abs(M["lossE"]), (loss, M["lossE"])
+    assert abs(loss - M["loss32"]) <= 2e-2 * abs(M["loss32"]), (loss, M["loss32"])
     bad = []
-    for cfg, g, pg in ((ce, ge.cpu().numpy(), ga), (cs, gs.cpu().numpy(), gb)):
-        off = 0
-        for k, shape in U.param_shapes(cfg).items():
-            cnt = int(np.prod(shape))
-            gg, ref = g[off:off + cnt], pg[k].grad.reshape(-1).numpy()
-            off += cnt
-            cos = float(np.dot(gg, ref) / (np.linalg.norm(gg) * np.linalg.norm(ref) + 1e-30))
-            layer = k.split(".")[0]
-            if not cfg.head:
-                depth = len(sol_names) + len(enc_names) - enc_names.index(layer)
-            else:
-                depth = 0 if layer == "head" else len(sol_names) - sol_names.index(layer)
-            r_ = float(rel(gg, ref))
-            print(f"{'sol' if cfg.head else 'enc'} {k:12s} depth={depth:2d} rel={r_:.3e} cos={cos:.6f}")
-            # BN bias gradients (batch sums of dy) cancel most, hence the floor
-            if r_ > 0.03 + 0.015 * (1 + depth) or cos < 1 - 1.5e-3 * (1 + depth):
-                bad.append((cfg.head, k, r_, cos))
+    for i, (cfg, g) in enumerate(((ce, ge.cpu().numpy()), (cs, gs.cpu().numpy()))):
+        tag = "enc" if i == 0 else "sol"
+        bad += GB.check(g, cfg, M["g32"][i], M["spread32"][i], tag + "-fp32")
+        bad += GB.check(g, cfg, M["gE"][i], M["spreadE"][i], tag + "-bf16e")
     assert not bad, bad
 
 
