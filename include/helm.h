@@ -102,6 +102,31 @@ int helm_apply(helm_handle *h, int op, const float *x, float *y, int nrhs,
  */
 int helm_sl_vcycle(helm_handle *h, const float *f, float *v, int nrhs, void *stream);
 
+/*
+ * helm_sl_vcycle_noalloc -- helm_sl_vcycle for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same result as helm_sl_vcycle (same
+ * kernels in the same order), but the cycle's workspace (restricted
+ * right-hand sides and corrections of every level below the finest, partial
+ * sums of the coarsest-level solve) is carved from a fixed 64 MiB device
+ * array of the library instead of the handle's allocations.  The call itself
+ * allocates nothing; the array of each device exists from library load to
+ * process end, and its address is looked up the first time the call runs on
+ * that device.  The caller still owns f and v.
+ *   f, v : complex64 [nrhs][n][n]; must not overlap.
+ * Limit: helm_sl_vcycle_noalloc_bytes(h, nrhs) <= 64 MiB (about 11
+ * right-hand sides at 1024^2, 45 at 512^2); larger batches return
+ * HELM_E_INVALID without launching anything.  Calls on one device share the
+ * array: calls that overlap in time on one device (other streams or
+ * threads) race, so serialise them.  Launches of this call are not timed by
+ * the profiling hook.
+ */
+int helm_sl_vcycle_noalloc(helm_handle *h, const float *f, float *v, int nrhs, void *stream);
+/* Workspace bytes helm_sl_vcycle_noalloc needs for nrhs fields of medium h,
+ * and the fixed maximum. */
+size_t helm_sl_vcycle_noalloc_bytes(const helm_handle *h, int nrhs);
+size_t helm_sl_vcycle_noalloc_max_bytes(void);
+
 /* Preconditioners for helm_fgmres_solve. */
 #define HELM_PREC_SL 0        /* M_V: one SL V-cycle                           */
 #define HELM_PREC_UNET_CGC 1  /* M_CU: Jacobi, U-Net coarse correction, Jacobi */
@@ -126,8 +151,17 @@ typedef struct {
     int iterations;      /* preconditioner applications                          */
     int restarts;        /* completed FGMRES cycles                              */
     int converged;       /* 1 if the true relative residual reached tol          */
-    int fallback;        /* 1 if the solve switched to the plain SL V-cycle      */
+    int fallback;        /* nonzero if the solve switched to the plain SL
+                            V-cycle: 1 after a stalled residual reduction, 2
+                            after a non-finite preconditioned direction (that
+                            step is dropped and its cycle ends)                  */
     double true_relres;  /* final ||b - A x|| / ||b|| recomputed in FP64         */
+    /* Convergence factor of eq. 4.1, rho = (||r_T|| / ||r_0||)^(1/T), with T
+       the first iteration whose implicit residual is reduced 1e6 (1e7) times
+       from ||b||; if that never happens, T = iterations and ||r_T|| is the
+       final true residual. */
+    int its_1e6, its_1e7;
+    double rho_1e6, rho_1e7;
 } helm_fgmres_stats;
 
 /*
@@ -218,6 +252,19 @@ int helm_profile_sample(int every);
  */
 int helm_autotune(int enable);
 int helm_autotune_entries(void);
+/*
+ * Test hook: force one candidate launch shape of the tuner on every
+ * convolution (forward and data gradient) until called with kind < 0.
+ *   kind   : 0 = the 256-thread register-staged kernel, 1 = the 512-thread
+ *            direct-to-LDS kernel (a convolution whose first source is read
+ *            through the x2 upsampling always runs on kind 1);
+ *   mf     : 2 or 4 (tile heights 8 / 16 rows for kind 0, 16 / 32 for kind 1);
+ *   per_cu : workgroups per compute unit, 1..64 (the tuner tries 1, 2, 4, 8).
+ * Every candidate computes the same result in the same summation order; the
+ * hook lets tests check each against the oracle.  Returns HELM_E_INVALID for
+ * a shape outside these ranges.  Process-wide.
+ */
+int helm_autotune_force(int kind, int mf, int per_cu);
 
 /* Thread-local text describing the last error of this thread ("" if none). */
 const char *helm_last_error(void);

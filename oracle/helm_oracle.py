@@ -235,3 +235,40 @@ def convergence_factor(hist, reduction=1e6):
     if T == 0:
         return 0.0, 0
     return float((hist[T] / hist[0]) ** (1.0 / T)), T
+
+
+def operator_matrix(kappa, gamma, omega, shift=0.0, h=None):
+    """The operator of eq. 2.2 (shift = beta: the SL operator of eq. 2.4) as a
+    scipy sparse matrix on the n x n unknowns (row-major, zero outside):
+    diagonal 4/h^2 - omega^2 kappa^2 (1 - i (gamma + shift)), -1/h^2 for each
+    of the four neighbours inside the grid."""
+    import scipy.sparse as sp
+
+    k, g = _r(kappa), _r(gamma)
+    n = k.shape[0]
+    h = 1.0 / n if h is None else h
+    ih2 = 1.0 / (h * h)
+    idx = np.arange(n * n).reshape(n, n)
+    diag = 4.0 * ih2 - omega ** 2 * k.ravel() ** 2 * (1 - 1j * (g.ravel() + shift))
+    rows, cols, vals = [idx.ravel()], [idx.ravel()], [diag]
+    for a, b in (((slice(1, None), slice(None)), (slice(None, -1), slice(None))),
+                 ((slice(None, -1), slice(None)), (slice(1, None), slice(None))),
+                 ((slice(None), slice(1, None)), (slice(None), slice(None, -1))),
+                 ((slice(None), slice(None, -1)), (slice(None), slice(1, None)))):
+        r, c = idx[a].ravel(), idx[b].ravel()
+        rows.append(r)
+        cols.append(c)
+        vals.append(np.full(r.size, -ih2, dtype=complex))
+    return sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(n * n, n * n))
+
+
+def direct_solver(kappa, gamma, omega, shift=0.0):
+    """x = Op^-1 b by a sparse LU factorisation (SuperLU, factored once) of
+    operator_matrix: the exact solution of the discrete system, for reference
+    solutions at sizes where the plain-C FGMRES is slow.  Returns b -> x."""
+    import scipy.sparse.linalg as spl
+
+    n = _r(kappa).shape[0]
+    lu = spl.splu(operator_matrix(kappa, gamma, omega, shift), permc_spec="COLAMD")
+    return lambda b: lu.solve(_c(b).ravel()).reshape(n, n)

@@ -165,37 +165,72 @@ int ensure_vcycle_ws(helm_handle *h, int nb)
 int vcycle(helm_handle *h, const float2 *f, size_t fs, float2 *v, size_t vs, int nb,
            const int *active, hipStream_t s, const double *scale, int accumulate)
 {
-    const int L = h->levels;
     int rc = ensure_vcycle_ws(h, nb);
     if (rc) return rc;
+    VcycleWs ws;
+    for (int l = 0; l < h->levels; ++l) {
+        ws.wf[l] = h->wf[l];
+        ws.wv[l] = h->wv[l];
+    }
+    ws.cpart = h->cpart;
+    vcycle_with(h, ws, f, fs, v, vs, nb, active, s, scale, accumulate);
+    return HELM_OK;
+}
+
+size_t vcycle_ws_elems(const helm_handle *h, int nb)
+{
+    auto up = [](size_t e) { return (e + 31) & ~(size_t)31; };  // 256-byte aligned pieces
+    size_t tot = 0;
+    for (int l = 1; l < h->levels; ++l) tot += 2 * up((size_t)h->lv[l].n * h->lv[l].n * nb);
+    return tot + up(coarse_scratch(h->Nc, nb));
+}
+
+void vcycle_carve(const helm_handle *h, int nb, float2 *base, VcycleWs &ws)
+{
+    auto up = [](size_t e) { return (e + 31) & ~(size_t)31; };
+    size_t off = 0;
+    for (int l = 0; l < VcycleWs::MAXL; ++l) ws.wf[l] = ws.wv[l] = nullptr;
+    for (int l = 1; l < h->levels; ++l) {
+        const size_t e = up((size_t)h->lv[l].n * h->lv[l].n * nb);
+        ws.wf[l] = base + off;
+        off += e;
+        ws.wv[l] = base + off;
+        off += e;
+    }
+    ws.cpart = base + off;
+}
+
+void vcycle_with(helm_handle *h, const VcycleWs &ws, const float2 *f, size_t fs, float2 *v, size_t vs,
+                 int nb, const int *active, hipStream_t s, const double *scale, int accumulate)
+{
+    const int L = h->levels;
     if (L == 1) {
-        launch_coarse_solve(h->Xc, h->Nc, f, fs, v, vs, nb, active, s, scale, accumulate, h->cpart);
-        return HELM_OK;
+        launch_coarse_solve(h->Xc, h->Nc, f, fs, v, vs, nb, active, s, scale, accumulate, ws.cpart);
+        return;
     }
     const float sh = (float)h->beta, w = (float)h->jacobi_w;
     // restrict down to the coarsest level
     for (int l = 0; l < L - 1; ++l) {
-        const float2 *src = l == 0 ? f : h->wf[l];
+        const float2 *src = l == 0 ? f : ws.wf[l];
         size_t ss = l == 0 ? fs : (size_t)h->lv[l].n * h->lv[l].n;
         size_t ds = (size_t)h->lv[l + 1].n * h->lv[l + 1].n;
-        launch_down(h->lv[l], sh, w, src, ss, h->wf[l + 1], ds, nb, active, s,
+        launch_down(h->lv[l], sh, w, src, ss, ws.wf[l + 1], ds, nb, active, s,
                     l == 0 ? scale : nullptr);
     }
     size_t Nc = (size_t)h->Nc;
-    launch_coarse_solve(h->Xc, h->Nc, h->wf[L - 1], Nc, h->wv[L - 1], Nc, nb, active, s, nullptr, 0,
-                        h->cpart);
+    launch_coarse_solve(h->Xc, h->Nc, ws.wf[L - 1], Nc, ws.wv[L - 1], Nc, nb, active, s, nullptr, 0,
+                        ws.cpart);
     // prolongate and post-relax up to the finest level
     for (int l = L - 2; l >= 0; --l) {
         size_t Nl = (size_t)h->lv[l].n * h->lv[l].n;
         size_t Nn = (size_t)h->lv[l + 1].n * h->lv[l + 1].n;
-        const float2 *src = l == 0 ? f : h->wf[l];
+        const float2 *src = l == 0 ? f : ws.wf[l];
         size_t ss = l == 0 ? fs : Nl;
-        float2 *dst = l == 0 ? v : h->wv[l];
+        float2 *dst = l == 0 ? v : ws.wv[l];
         size_t dstr = l == 0 ? vs : Nl;
-        launch_up(h->lv[l], sh, w, src, ss, h->wv[l + 1], Nn, dst, dstr, nb, active, s,
+        launch_up(h->lv[l], sh, w, src, ss, ws.wv[l + 1], Nn, dst, dstr, nb, active, s,
                   l == 0 ? scale : nullptr, l == 0 ? accumulate : 0);
     }
-    return HELM_OK;
 }
 
 }  // namespace helm

@@ -5,9 +5,9 @@
 // Per cycle and right-hand side b:
 //   r = b - A x (FP64, x complex128), beta = ||r||, v_0 = r / beta
 //   for j < m:  z_j = Prec(v_j); w = A z_j;
-//               CGS2: h = V^H w, w -= V h, h' = V^H w, w -= V h', H(:,j) = h + h'
-//               H(j+1,j) = ||w||, v_{j+1} = w / H(j+1,j)
-//               complex Givens rotation on column j (FP64), g_{j+1} = implicit residual
+//               orthogonalise w against v_0..v_j (delayed CGS2, krylov.hip),
+//               Hessenberg column j, complex Givens rotation on it (FP64),
+//               g_{j+1} = implicit residual
 //   x += Z y with y = H_k^-1 g_k (FP64)
 // The iteration stops once the FP64 true relative residual ||b - A x||/||b||
 // is <= tol; the implicit estimate |g_{j+1}| only ends a cycle early.
@@ -187,7 +187,7 @@ int work_ensure(helm_handle *h, int nb, int m, bool scratch, FgWork **out)
     }
     // state: ints, then doubles, then double2s, each section 256-byte aligned
     auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    size_t ni = 8 * (size_t)nb, nd = 5 * (size_t)nb + (size_t)nb * m;
+    size_t ni = 10 * (size_t)nb, nd = 7 * (size_t)nb + (size_t)nb * m;
     size_t nz = (size_t)nb * ((m + 1) * m + (m + 1) + m + 3 * MAXV);
     size_t off_d = align(ni * sizeof(int)), off_z = align(off_d + nd * sizeof(double));
     size_t bytes = off_z + nz * sizeof(double2);
@@ -209,12 +209,16 @@ int work_ensure(helm_handle *h, int nb, int m, bool scratch, FgWork **out)
     S.stall = S.fallback + nb;
     S.mask_net = S.stall + nb;
     S.mask_sl = S.mask_net + nb;
+    S.t6 = S.mask_sl + nb;
+    S.t7 = S.t6 + nb;
     S.bnorm = (double *)(p + off_d);
     S.beta = S.bnorm + nb;
     S.relres = S.beta + nb;
     S.scale = S.relres + nb;
     S.nu = S.scale + nb;
-    S.cs = S.nu + nb;
+    S.rel6 = S.nu + nb;
+    S.rel7 = S.rel6 + nb;
+    S.cs = S.rel7 + nb;
     S.H = (double2 *)(p + off_z);
     S.g = S.H + (size_t)nb * (m + 1) * m;
     S.sn = S.g + (size_t)nb * (m + 1);
@@ -374,6 +378,7 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
 
     HELM_HIP_CHECK(hipMemsetAsync(x, 0, (size_t)nb * N * sizeof(double2), s));
     HELM_HIP_CHECK(hipMemsetAsync(S.fallback, 0, 2 * (size_t)nb * sizeof(int), s));
+    HELM_HIP_CHECK(hipMemsetAsync(S.t6, 0, 2 * (size_t)nb * sizeof(int), s));
     for (int i = 0; i < nb; ++i) w->h_i[i] = 1;
     HELM_HIP_CHECK(hipMemcpyAsync(S.active, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
     HELM_HIP_CHECK(hipMemcpyAsync(S.incycle, w->h_i, nb * sizeof(int), hipMemcpyHostToDevice, s));
@@ -476,6 +481,10 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
     }
     prof_set_active(-1);
     HELM_HIP_CHECK(hipMemcpyAsync(w->h_fb, S.fallback, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+    std::vector<int> t67(2 * (size_t)nb);
+    std::vector<double> r67(2 * (size_t)nb);
+    HELM_HIP_CHECK(hipMemcpyAsync(t67.data(), S.t6, 2 * nb * sizeof(int), hipMemcpyDeviceToHost, s));
+    HELM_HIP_CHECK(hipMemcpyAsync(r67.data(), S.rel6, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, s));
     HELM_HIP_CHECK(hipStreamSynchronize(s));
     int nconv = 0;
     for (int i = 0; i < nb; ++i) {
@@ -487,6 +496,24 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
             stats[i].converged = conv ? 1 : 0;
             stats[i].fallback = w->h_fb[i];
             stats[i].true_relres = w->h_d[i];
+            // eq. 4.1: rho = (||r_T|| / ||r_0||)^(1/T), T the first iteration
+            // reaching the reduction, else the last one with the final residual
+            for (int q = 0; q < 2; ++q) {
+                int T = t67[(size_t)q * nb + i];
+                double rel = r67[(size_t)q * nb + i];
+                if (T == 0) {
+                    T = w->h_its[i];
+                    rel = w->h_d[i];
+                }
+                const double rho = T > 0 ? std::pow(rel, 1.0 / T) : 0.0;
+                if (q == 0) {
+                    stats[i].its_1e6 = T;
+                    stats[i].rho_1e6 = rho;
+                } else {
+                    stats[i].its_1e7 = T;
+                    stats[i].rho_1e7 = rho;
+                }
+            }
         }
     }
     return nconv == nb ? HELM_OK : HELM_NOT_CONVERGED;

@@ -26,6 +26,21 @@ struct helm_handle {
 };
 
 namespace helm {
+// Workspace of one V-cycle over nb fields: per level l >= 1 the restricted
+// right-hand side f_l and the correction v_l ([nb][n_l][n_l] each), and the
+// partial sums of the coarsest-level GEMM (coarse_scratch(Nc, nb)).
+struct VcycleWs {
+    static constexpr int MAXL = 12;
+    float2 *wf[MAXL] = {}, *wv[MAXL] = {};
+    float2 *cpart = nullptr;
+};
+// complex elements of a VcycleWs carved from one buffer, and the carving
+size_t vcycle_ws_elems(const helm_handle *h, int nb);
+void vcycle_carve(const helm_handle *h, int nb, float2 *base, VcycleWs &ws);
+// the V-cycle on a given workspace: kernel launches only (no allocation)
+void vcycle_with(helm_handle *h, const VcycleWs &ws, const float2 *f, size_t fs, float2 *v, size_t vs,
+                 int nb, const int *active, hipStream_t s, const double *scale = nullptr,
+                 int accumulate = 0);
 int ensure_vcycle_ws(helm_handle *h, int nb);
 // v = V-cycle(0, f) on M, batch of nb fields (strides in complex elements);
 // with `scale` the input is read as scale[b] * f (the cycle is linear).

@@ -20,6 +20,8 @@ void prof_mark(int family, hipStream_t s, bool start, double work_per_rhs = 0.0,
                bool masked = false);
 void prof_set_active(int nact);
 bool prof_enabled();
+// suspend (true) / resume (false) timing of this thread's launches
+void prof_suspend(bool on);
 
 #define HELM_HIP_CHECK(call)                                                        \
     do {                                                                            \
@@ -95,10 +97,13 @@ constexpr int MAXP = 2 * MAXM + 4;    // partial sums per block of an Arnoldi pa
 struct FgState {
     int m, nb;
     int *active, *incycle, *k, *its;
-    int *fallback, *stall;     // sticky switch to the plain SL V-cycle, stall counter
+    int *fallback, *stall;     // sticky switch to the plain SL V-cycle (1: stalled,
+                               // 2: non-finite preconditioned direction), stall counter
     int *mask_net, *mask_sl;   // per-step masks: network path / SL path
+    int *t6, *t7;              // first iteration whose implicit residual is <= 1e-6 / 1e-7 of ||b||
     double stall_ratio;        // 0 = never fall back
     double *bnorm, *beta, *relres, *scale, *nu;
+    double *rel6, *rel7;       // implicit relative residual at t6 / t7
     double2 *H;   // [nb][(m+1)*m], H[i*m + j]
     double2 *g;   // [nb][m+1]
     double *cs;   // [nb][m]

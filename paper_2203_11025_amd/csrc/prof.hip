@@ -28,6 +28,12 @@ struct Prof {
 Prof g_prof;
 }  // namespace
 
+// launches of this thread are not timed while positive (callers that must
+// not create events)
+thread_local int t_prof_suspended = 0;
+
+void prof_suspend(bool on) { t_prof_suspended += on ? 1 : -1; }
+
 bool prof_enabled() { return g_prof.mask != 0; }
 
 void prof_set_active(int nact)
@@ -39,7 +45,7 @@ void prof_set_active(int nact)
 
 void prof_mark(int family, hipStream_t s, bool start, double work_per_rhs, int nb, bool masked)
 {
-    if (!(g_prof.mask & (1u << family))) return;
+    if (!(g_prof.mask & (1u << family)) || t_prof_suspended > 0) return;
     std::lock_guard<std::mutex> lk(g_prof.mu);
     Family &F = g_prof.f[family];
     if (start == F.open) return;  // unbalanced call: ignore

@@ -71,6 +71,8 @@ void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
 // the previous setting.
 int conv_autotune(int enable);
 int conv_autotune_entries();
+// force one candidate launch shape on every convolution (kind < 0: off); -1 if invalid
+int conv_force(int kind, int mf, int per_cu);
 // Weight gradient: dW[co][tap][ci] = sum_p dy[p][co] * X[p + tap offset][ci],
 // X the concatenated sources; written (not accumulated) as FP32 [Cout][9][Ctot].
 // `part` is scratch of launch_wgrad_scratch(...) floats.

@@ -2015,8 +2015,18 @@ struct Tuner {
     std::mutex mu;
     int enabled = 0;
     std::map<std::array<int, 6>, ConvShape> table;
+    // a launch shape forced on every convolution (kind, mf, workgroups per
+    // compute unit as in the candidate list), kind < 0 = none
+    int force_kind = -1, force_mf = 0, force_per_cu = 0;
 };
 Tuner g_tune;
+
+// the candidate of conv_tune for (kind, mf, per_cu)
+ConvShape conv_candidate(int kind, int mf, int per_cu, int Cout)
+{
+    const int ncob = (Cout + (Cout >= 64 ? 63 : 31)) / (Cout >= 64 ? 64 : 32);
+    return ConvShape{mf, std::max(1, 256 * per_cu * (kind ? 1 : 2) / ncob), kind};
+}
 
 // Times every candidate launch shape for this convolution (three runs each,
 // HIP events on the caller's stream) and keeps the fastest.  Each run
@@ -2025,7 +2035,6 @@ ConvShape conv_tune(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
                     bf16 *out16, const float *scale, const float *shift, float slope, hipStream_t s,
                     const ConvEpi &epi)
 {
-    const int ncob = (Cout + (Cout >= 64 ? 63 : 31)) / (Cout >= 64 ? 64 : 32);
     ConvShape best = conv_default(H, Cout);
     float best_ms = 1e30f;
     hipEvent_t e0, e1;
@@ -2038,7 +2047,7 @@ ConvShape conv_tune(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
     for (int mf : {2, 4})
         for (int per_cu : {1, 2, 4, 8}) {
             if (kind == 0 && in.s[0].up) continue;  // runs on k_conv3x3d only
-            ConvShape c{mf, std::max(1, 256 * per_cu * (kind ? 1 : 2) / ncob), kind};
+            ConvShape c = conv_candidate(kind, mf, per_cu, Cout);
             conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s, epi);  // warm
             hipEventRecord(e0, s);
             for (int r = 0; r < 3; ++r)
@@ -2063,6 +2072,14 @@ void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
                     float slope, hipStream_t s, const ConvEpi &epi)
 {
     ConvShape c = conv_default(H, Cout);
+    {
+        std::lock_guard<std::mutex> lk(g_tune.mu);
+        if (g_tune.force_kind >= 0) {
+            c = conv_candidate(g_tune.force_kind, g_tune.force_mf, g_tune.force_per_cu, Cout);
+            conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s, epi);
+            return;
+        }
+    }
     if (g_tune.enabled) {
         // batch sizes share an entry per power-of-two bucket: a batch that
         // shrinks as right-hand sides converge is not tuned again each time
@@ -2093,6 +2110,16 @@ int conv_autotune(int enable)
     g_tune.enabled = enable ? 1 : 0;
     if (enable < 0) g_tune.table.clear();
     return prev;
+}
+
+int conv_force(int kind, int mf, int per_cu)
+{
+    if (kind >= 0 && (kind > 1 || (mf != 2 && mf != 4) || per_cu < 1 || per_cu > 64)) return -1;
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    g_tune.force_kind = kind < 0 ? -1 : kind;
+    g_tune.force_mf = mf;
+    g_tune.force_per_cu = per_cu;
+    return 0;
 }
 
 int conv_autotune_entries()

@@ -627,6 +627,15 @@ extern "C" {
 
 int helm_autotune(int enable) { return helm::conv_autotune(enable); }
 
+int helm_autotune_force(int kind, int mf, int per_cu)
+{
+    if (helm::conv_force(kind, mf, per_cu)) {
+        helm::set_error("helm_autotune_force: kind must be 0 or 1, mf 2 or 4, per_cu in [1, 64]");
+        return HELM_E_INVALID;
+    }
+    return HELM_OK;
+}
+
 int helm_autotune_entries(void) { return helm::conv_autotune_entries(); }
 
 int unet_create(const unet_cfg *cfg, unet_net **out)

@@ -24,7 +24,8 @@ PREC = {"sl": 0, "unet_cgc": 1, "unet_defl": 2}
 EXPORTS = [
     "helm_setup", "helm_destroy", "helm_level_size", "helm_num_levels", "helm_apply",
     "helm_sl_vcycle", "helm_fgmres_solve", "helm_last_error", "helm_profile_start",
-    "helm_profile_read", "helm_profile_stop", "helm_profile_sample", "helm_autotune", "helm_autotune_entries", "helm_training_triples", "helm_coarse_slowness",
+    "helm_profile_read", "helm_profile_stop", "helm_profile_sample", "helm_autotune", "helm_autotune_entries", "helm_autotune_force", "helm_training_triples", "helm_coarse_slowness",
+    "helm_sl_vcycle_noalloc", "helm_sl_vcycle_noalloc_bytes", "helm_sl_vcycle_noalloc_max_bytes",
 ]
 PROF = {"none": 0, "coarse": 1, "down": 2, "up": 3, "cgs": 4, "apply": 5, "conv": 6, "wgrad": 7}
 
@@ -44,7 +45,8 @@ class FgmresOpts(C.Structure):
 
 class FgmresStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
-                ("fallback", C.c_int), ("true_relres", C.c_double)]
+                ("fallback", C.c_int), ("true_relres", C.c_double), ("its_1e6", C.c_int),
+                ("its_1e7", C.c_int), ("rho_1e6", C.c_double), ("rho_1e7", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -73,6 +75,12 @@ def lib():
         L.helm_apply.restype = ip
         L.helm_sl_vcycle.argtypes = [vp, vp, vp, ip, vp]
         L.helm_sl_vcycle.restype = ip
+        L.helm_sl_vcycle_noalloc.argtypes = [vp, vp, vp, ip, vp]
+        L.helm_sl_vcycle_noalloc.restype = ip
+        L.helm_sl_vcycle_noalloc_bytes.argtypes = [vp, ip]
+        L.helm_sl_vcycle_noalloc_bytes.restype = C.c_size_t
+        L.helm_sl_vcycle_noalloc_max_bytes.argtypes = []
+        L.helm_sl_vcycle_noalloc_max_bytes.restype = C.c_size_t
         L.helm_fgmres_solve.argtypes = [C.POINTER(vp), ip, C.POINTER(ip), C.POINTER(vp),
                                         C.POINTER(vp), C.POINTER(FgmresOpts),
                                         C.POINTER(FgmresStats), vp]
@@ -95,6 +103,8 @@ def lib():
         L.helm_autotune.restype = ip
         L.helm_autotune_entries.argtypes = []
         L.helm_autotune_entries.restype = ip
+        L.helm_autotune_force.argtypes = [ip, ip, ip]
+        L.helm_autotune_force.restype = ip
         _lib = L
     return _lib
 
@@ -199,6 +209,18 @@ class Handle:
                "helm_sl_vcycle")
         return v
 
+    def vcycle_noalloc(self, f, out, stream=None):
+        """helm_sl_vcycle on the library's fixed device workspace (no
+        allocation in the call); `out` is the caller's output buffer."""
+        f = self._batch(f, "f")
+        _check(lib().helm_sl_vcycle_noalloc(self._h, _dev(f, torch.complex64, "f"),
+                                            _dev(out, torch.complex64, "out"), f.shape[0],
+                                            _stream(stream)), "helm_sl_vcycle_noalloc")
+        return out
+
+    def vcycle_noalloc_bytes(self, nrhs):
+        return lib().helm_sl_vcycle_noalloc_bytes(self._h, int(nrhs))
+
 
 def fgmres_solve(problems, rhs, m=20, tol=1e-7, maxit=20000, prec="sl", net=None,
                  stall_ratio=0.0, xs=None, stream=None, graph=False):
@@ -261,3 +283,9 @@ def autotune(enable=1):
 def autotune_entries():
     return lib().helm_autotune_entries()
 
+
+
+def autotune_force(kind=-1, mf=2, per_cu=1):
+    """Force one tuner candidate launch shape on every convolution (test
+    hook); kind < 0 switches it off."""
+    _check(lib().helm_autotune_force(int(kind), int(mf), int(per_cu)), "helm_autotune_force")

@@ -202,3 +202,35 @@ def test_pair_misuse_is_rejected(N):
     N.pair_train_step(enc, sol, rr + 1, rr + 1e-4, kc[None].cuda())
     with pytest.raises(helm.HelmError):
         helm.fgmres_solve([h], [b], m=5, tol=1e-7, prec="unet_defl", net=sol)
+
+
+def test_every_tuner_candidate_at_the_1024_workload_network_grid(N):
+    """The network of the 1024^2 workload runs on the 512^2 coarse grid with
+    one shared medium (context maps, the fused x2 upsampling of the first
+    decoder convolution).  Every launch shape the autotuner can pick is
+    forced on every convolution and checked against the FP32 oracle."""
+    from paper_2203_11025_amd import helm
+
+    widths = (32, 64, 128, 256)
+    ce, pe, be, cs, ps, bs, enc, sol = make_pair(N, 51, widths=widths)
+    rng = np.random.default_rng(52)
+    nc, B = 512, 2
+    kc = rng.uniform(0.25, 1.0, (1, nc, nc)).astype(np.float32)
+    x = rng.standard_normal((B, 3, nc, nc)).astype(np.float32)
+    x[:, 2] = kc[0]
+    ctx = [c.expand(B, -1, -1, -1) for c in U.encode(ce, pe, be, kc)]
+    ref = U.forward(cs, ps, bs, torch.from_numpy(x), ctx=ctx).numpy()
+    outs = {}
+    try:
+        for kind in (0, 1):
+            for mf in (2, 4):
+                for per_cu in (1, 2, 4, 8):
+                    helm.autotune_force(kind, mf, per_cu)
+                    N.pair_encode(enc, sol, torch.from_numpy(kc))
+                    outs[(kind, mf, per_cu)] = sol.forward(torch.from_numpy(x)).cpu().numpy()
+    finally:
+        helm.autotune_force(-1)
+    for cand, out in outs.items():
+        r_ = rel(out, ref)
+        print(f"candidate {cand}: rel {r_:.3e}")
+        assert r_ <= 2e-2, (cand, r_)

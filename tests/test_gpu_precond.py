@@ -147,3 +147,30 @@ def test_trained_network_beats_untrained_and_plain_sl(mods, oracle):
           f"loss {losses[0]:.3e} -> {losses[-1]:.3e}")
     assert losses[-1] < 0.5 * losses[0]
     assert it_trained < it_untrained and it_trained < it_sl
+
+
+def test_non_finite_network_output_falls_back_to_sl(mods, oracle):
+    """A network whose head bias is +Inf makes every M_VU direction
+    non-finite.  The Arnoldi reduction drops that step, ends the cycle on the
+    finite columns and switches the right-hand side to M_V (fallback = 2),
+    so the solve converges to the FP64 tolerance within a bounded number of
+    iterations; the stall ratio is off, so only the guard can act."""
+    helm, unet, _ = mods
+    n = 64
+    kap, gam, om = medium(n, 15)
+    h = helm.Handle(torch.from_numpy(kap).cuda(), torch.from_numpy(gam).cuda(), om, levels=2)
+    cfg = U.UNetCfg(widths=WIDTHS)
+    p, buf = U.init_params(cfg, 31)
+    p["head.b"] = torch.tensor([float("inf"), 0.0])
+    net = unet.UNet(widths=WIDTHS)
+    net.set_params(U.flatten(cfg, p))
+    b = inputs.point_sources(n, 2, seed=9, margin=8)
+    xs, st, rc = helm.fgmres_solve([h], [torch.from_numpy(b).cuda()], m=10, tol=1e-7, maxit=200,
+                                   prec="unet_defl", net=net, stall_ratio=0.0)
+    x = xs[0].cpu().numpy()
+    assert np.all(np.isfinite(x))
+    for k in range(2):
+        assert st[k]["fallback"] == 2, st[k]
+        assert rc == 0 and st[k]["converged"] and st[k]["iterations"] <= 200
+        r = b[k].astype(complex) - oracle.apply(kap, gam, om, x[k])
+        assert np.linalg.norm(r) / np.linalg.norm(b[k]) <= 1e-7

@@ -165,3 +165,38 @@ def test_training_reduces_loss(N):
     args = (torch.from_numpy(r).cuda(), torch.from_numpy(e).cuda(), torch.from_numpy(kc).cuda())
     losses = [net.train_step(*args, lr=1e-3) for _ in range(30)]
     assert losses[-1] < 0.8 * losses[0], losses[::5]
+
+
+CANDIDATES = [(kind, mf, per_cu) for kind in (0, 1) for mf in (2, 4) for per_cu in (1, 8)]
+
+
+@pytest.mark.parametrize("training", [False, True])
+def test_every_tuner_candidate_matches_oracle(N, training):
+    """Each launch shape the autotuner can pick (both kernels, both tile
+    heights, the fewest and the most workgroups) forced on every
+    convolution of the configured 4-level network on a ragged 144^2 image;
+    each against the FP32 oracle at the network bar."""
+    from paper_2203_11025_amd import helm
+
+    cfg, p, buf, net = make(N, (32, 64, 128, 256), 5)
+    rng = np.random.default_rng(6)
+    H, B = 144, 2
+    x = rng.standard_normal((B, 3, H, H)).astype(np.float32)
+    x[:, 2] = rng.uniform(0.25, 1.0, (B, H, H))
+    ref = U.forward(cfg, p, buf, torch.from_numpy(x), training=training).numpy()
+    outs = {}
+    try:
+        for cand in CANDIDATES:
+            helm.autotune_force(*cand)
+            outs[cand] = net.forward(torch.from_numpy(x), training=training).cpu().numpy()
+    finally:
+        helm.autotune_force(-1)
+    for cand, out in outs.items():
+        assert rel(out, ref) <= 2e-2, (cand, rel(out, ref))
+    # the workgroup count only changes which workgroup walks which tiles:
+    # the outputs of one kernel and tile height are identical
+    for kind in (0, 1):
+        for mf in (2, 4):
+            assert np.array_equal(outs[(kind, mf, 1)], outs[(kind, mf, 8)]), (kind, mf)
+    spread = max(float(np.abs(o - outs[CANDIDATES[0]]).max()) for o in outs.values())
+    print(f"largest difference between candidates: {spread:.3e}")

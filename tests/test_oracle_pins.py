@@ -340,3 +340,23 @@ def test_convergence_factor_geometric(oracle):
     hist = 0.5 ** np.arange(30)
     rho, T = oracle.convergence_factor(hist)
     assert T == 20 and rho == pytest.approx(0.5)
+
+
+@pytest.mark.parametrize("shift", [0.0, 0.5])
+def test_operator_matrix_is_the_stencil(oracle, shift):
+    """The sparse assembly of the operator applies like the stencil loop, on
+    a heterogeneous medium with a sponge, and the direct solver inverts it
+    (against the banded LU)."""
+    from paper_2203_11025_amd import inputs
+    n = 24
+    kap = inputs.smooth_medium(n, 3.0, seed=9).astype(np.float64)
+    gam = inputs.sponge_gamma(n, width=4).astype(np.float64)
+    om = inputs.omega_for_ppw(n)
+    rng = np.random.default_rng(10)
+    x = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = oracle.operator_matrix(kap, gam, om, shift)
+    np.testing.assert_allclose((A @ x.ravel()).reshape(n, n), oracle.apply(kap, gam, om, x, shift=shift),
+                               rtol=0, atol=1e-9 * n * n)
+    solve = oracle.direct_solver(kap, gam, om, shift)
+    np.testing.assert_allclose(solve(x), oracle.band_solve(kap, gam, om, x, shift=shift),
+                               rtol=1e-10, atol=1e-12 * np.abs(solve(x)).max())

@@ -1,0 +1,64 @@
+"""helm_sl_vcycle_noalloc (the V-cycle on the library's fixed device
+workspace) against helm_sl_vcycle through the C ABI: two calls in a row, the
+second with a smaller input, and the size limit."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2203_11025_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_2203_11025_amd import helm
+
+    assert torch.cuda.is_available()
+    helm.lib()
+    return helm
+
+
+def _case(H, n, levels, nrhs, seed):
+    kap = inputs.smooth_medium(n, max(2.0, n / 16), seed=seed)
+    gam = inputs.sponge_gamma(n, width=min(16, n // 4))
+    h = H.Handle(torch.from_numpy(kap).cuda(), torch.from_numpy(gam).cuda(),
+                 inputs.omega_for_ppw(n), levels=levels)
+    rng = np.random.default_rng(seed)
+    f = (rng.standard_normal((nrhs, n, n)) + 1j * rng.standard_normal((nrhs, n, n))).astype(np.complex64)
+    return kap, gam, h, torch.from_numpy(f).cuda()
+
+
+def test_noalloc_vcycle_matches_vcycle_twice(H, oracle):
+    """First call: 128^2, 3 levels, 6 right-hand sides (the coarsest solve
+    takes the GEMM with its partial sums in the workspace).  Second call:
+    64^2, 2 levels, 2 right-hand sides (the GEMV path), on the workspace the
+    first call left behind.  Both equal helm_sl_vcycle bit for bit (same
+    kernels, same order), and the V-cycle bar (1e-5) against the oracle."""
+    for n, levels, nrhs, seed in ((128, 3, 6, 11), (64, 2, 2, 12)):
+        kap, gam, h, f = _case(H, n, levels, nrhs, seed)
+        assert 0 < h.vcycle_noalloc_bytes(nrhs) <= H.lib().helm_sl_vcycle_noalloc_max_bytes()
+        out = torch.full_like(f, float("nan"))
+        h.vcycle_noalloc(f, out)
+        ref = h.vcycle(f)
+        torch.cuda.synchronize()
+        a, b = out.cpu().numpy(), ref.cpu().numpy()
+        assert np.array_equal(a, b), (n, nrhs, np.abs(a - b).max())
+        ho = oracle.Hierarchy(kap, gam, inputs.omega_for_ppw(n), levels)
+        vo = ho.vcycle(f[0].cpu().numpy())
+        assert np.linalg.norm(a[0] - vo) / np.linalg.norm(vo) <= 1e-5
+
+
+def test_noalloc_vcycle_rejects_a_batch_beyond_the_limit(H):
+    """A workspace above the fixed size is refused before anything runs."""
+    n = 512
+    kap, gam, h, f = _case(H, n, 4, 1, 13)
+    limit = H.lib().helm_sl_vcycle_noalloc_max_bytes()
+    nrhs = 1
+    while h.vcycle_noalloc_bytes(nrhs) <= limit:
+        nrhs *= 2
+    big = torch.zeros((nrhs, n, n), dtype=torch.complex64, device="cuda")
+    out = torch.zeros_like(big)
+    with pytest.raises(H.HelmError, match="exceeds"):
+        h.vcycle_noalloc(big, out)
+    assert torch.count_nonzero(out).item() == 0
