@@ -152,11 +152,26 @@ def _ste_round(t):
 # does (FP32 accumulation everywhere else).  Off by default.
 EMULATE_BF16 = False
 
+# Spread measurement only (off by default, no effect on the arithmetic when
+# None): a (torch.Generator, rel) pair.  With EMULATE_BF16 on, every
+# convolution output is multiplied by (1 + rel * N(0, 1)) before its bf16
+# rounding, which models another FP32 summation order inside every layer (a
+# sum of K terms in FP32 carries a relative error of order sqrt(K) 2^-24).
+JITTER = None
+
+
+def _jitter(y):
+    if JITTER is None:
+        return y
+    gen, rel_ = JITTER
+    f = 1.0 + rel_ * torch.randn(y.shape, generator=gen, dtype=torch.float64).to(y.dtype)
+    return y * f
+
 
 def _block(x, p, buf, name, training, stats):
     """3x3 conv -> BN -> LeakyReLU."""
     if EMULATE_BF16:
-        y = _RoundGrad.apply(F.conv2d(x, _ste_round(p[name + ".w"]), padding=1))
+        y = _RoundGrad.apply(_jitter(F.conv2d(x, _ste_round(p[name + ".w"]), padding=1)))
     else:
         y = F.conv2d(x, p[name + ".w"], padding=1)
     if training:
