@@ -203,6 +203,49 @@ int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int *rhs_per_p
 int helm_training_triples(helm_handle *h, const float *x, float *r, float *e, int nrhs,
                           void *stream);
 
+/*
+ * helm_training_triples_seeded -- training triples with the random x
+ * drawn on the device from (seed, sample index), so that a training run is
+ * reproducible from its seed and the index of its next sample (section 3.4
+ * draws x at random; eq. 3.8), and a chosen number of smoothing steps.
+ * Sample b of the call has index index0 + b.
+ * Its point p takes the Philox4x32-10 block (Salmon et al., SC 2011) of
+ * counter (p, index_lo, index_hi, 0) under key (seed_lo, seed_hi); the
+ * first two 32-bit words a, c give u1 = (a + 1) 2^-32 and u2 = c 2^-32, and
+ * the Box-Muller transform in double precision gives
+ *   Re x = sqrt(-2 ln u1) cos(2 pi u2),  Im x = sqrt(-2 ln u1) sin(2 pi u2),
+ * each rounded once to float: iid N(0, 1) real and imaginary parts.
+ *   ksteps : k, the number of FGMRES steps of eq. 3.8 (the paper draws k from
+ *          1..10 per sample; here one k per call), in [1, 30].  k = 1 is the
+ *          closed form of helm_training_triples.  k > 1: FGMRES(max(k, 10))
+ *          with M_V from zero on b = A x, stopped after k steps (no restart
+ *          for k <= 10), the iterate x~ in FP64; r = b - A x~ evaluated in
+ *          FP64, e = x - x~, both rounded once.  This uses the handle's FGMRES
+ *          workspace (a later solve with another restart length reallocates
+ *          it) and synchronises `stream` once.
+ *   x    : complex64 [nrhs][n][n] receiving the drawn x, or NULL (kept in the
+ *          handle's workspace only).
+ *   r, e : as for helm_training_triples.
+ * The handle keeps a workspace of 4 nrhs complex64 fields for these calls
+ * (grown on demand, released by helm_destroy); calls on one handle must not
+ * overlap.
+ */
+int helm_training_triples_seeded(helm_handle *h, unsigned long long seed, unsigned long long index0,
+                                 int ksteps, float *x, float *r, float *e, int nrhs, void *stream);
+
+/*
+ * helm_triples_mix -- augmentation by linear combinations of triples
+ * (section 3.4): for nin triples (r_j, e_j) of ONE medium (A e_j = r_j),
+ *   r'_b = sum_j c[b][j] r_j,   e'_b = sum_j c[b][j] e_j,   b < nout,
+ * which again satisfy A e'_b = r'_b.  FP32 arithmetic, sums in j order.
+ *   r, e         : complex64 [nin][npts] inputs;
+ *   coef         : device float [nout][nin] real coefficients;
+ *   r_out, e_out : complex64 [nout][npts]; must not overlap the inputs.
+ * nin, nout <= 32.
+ */
+int helm_triples_mix(const float *r, const float *e, int nin, long long npts, const float *coef, int nout,
+                     float *r_out, float *e_out, void *stream);
+
 /* Slowness injected at the coarse points (2I, 2J): float [n/2][n/2] (the
  * network's kappa input channel). */
 int helm_coarse_slowness(helm_handle *h, float *kc, void *stream);
@@ -265,6 +308,29 @@ int helm_autotune_entries(void);
  * a shape outside these ranges.  Process-wide.
  */
 int helm_autotune_force(int kind, int mf, int per_cu);
+
+/*
+ * Allocator hook.  Every device workspace the library owns (handles, FGMRES
+ * solves, networks, the training-triple generator) is obtained from
+ *   alloc(bytes, ctx)            -> device pointer, NULL on failure
+ * and returned through
+ *   release(ptr, bytes, ctx)
+ * (for example a caching allocator of the host framework), instead of
+ * hipMalloc / hipFree.  Both functions, or neither (NULL, NULL: back to
+ * hipMalloc / hipFree), must be given; ctx is passed through.  A block goes
+ * back to the allocator it came from even after the registration changes.
+ * The library synchronises the device before handing a block to `release`
+ * (its kernels may still read it on internal streams).  The functions may be
+ * called from the library's internal host threads (concurrent problems of
+ * helm_fgmres_solve), one at a time per call site.  Process-wide; register
+ * before creating handles or networks.  The fixed array of
+ * helm_sl_vcycle_noalloc is not covered (it is never allocated).
+ */
+typedef void *(*helm_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*helm_free_fn)(void *ptr, size_t bytes, void *ctx);
+int helm_set_allocator(helm_alloc_fn alloc, helm_free_fn release, void *ctx);
+/* Bytes of device memory the library currently holds (all allocators). */
+size_t helm_allocated_bytes(void);
 
 /* Thread-local text describing the last error of this thread ("" if none). */
 const char *helm_last_error(void);

@@ -159,6 +159,26 @@ int unet_pair_loss_grad(unet_net *encoder, unet_net *solver, const unet_batch *b
 int unet_pair_train_step(unet_net *encoder, unet_net *solver, const unet_batch *batch,
                          const unet_train_opts *opts, double *loss_out, void *stream);
 
+/*
+ * Training state.  unet_save writes, and unet_load restores, everything a
+ * training run needs to continue bit for bit: the FP32 master parameters, the
+ * BN running statistics, the Adam moments and step count (section 3.4 trains
+ * with Adam) and the training-data cursor (the seed and the next sample index
+ * of helm_training_triples_seeded).  The file is a host file at `path`
+ * (written to path + ".tmp", then renamed): the 8-byte tag "HELMUNT1", int32
+ * in_ch, out_ch, levels, widths[6] (0 past levels), context, head; int64
+ * num_params, num_buffers; int32 Adam step; uint64 data seed, next sample
+ * index; FP32 parameters, buffers, first moments, second moments, all
+ * little-endian.  unet_load requires a network of the same configuration
+ * (else HELM_E_INVALID, nothing changed), re-rounds the bf16 weights and
+ * drops the solver's context maps (encode again).  Both synchronise `stream`.
+ */
+int unet_save(unet_net *net, const char *path, void *stream);
+int unet_load(unet_net *net, const char *path, void *stream);
+/* The training-data cursor kept with the state (0, 0 after unet_create). */
+int unet_set_cursor(unet_net *net, unsigned long long seed, unsigned long long next_index);
+int unet_get_cursor(const unet_net *net, unsigned long long *seed, unsigned long long *next_index);
+
 #ifdef __cplusplus
 }
 #endif

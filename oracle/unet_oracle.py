@@ -379,6 +379,27 @@ def training_triple(hier, x):
     return b - alpha * w, x - alpha * z
 
 
+def training_triple_k(hier, x, k):
+    """Training data of eq. 3.8-3.9 with k flexible-GMRES steps: b = A x,
+    x~ = k steps of FGMRES(max(k, 10)) with the SL V-cycle from zero (fewer
+    if the solve ends exactly earlier), r = b - A x~, e = x - x~."""
+    kap, gam, om = hier.kappa0, hier.gamma0, hier.omega
+    x = np.asarray(x, dtype=np.complex128)
+    b = helm_oracle.apply(kap, gam, om, x)
+    xt, st = hier.fgmres(b, m=max(k, 10), tol=1e-300, maxit=k)
+    return b - helm_oracle.apply(kap, gam, om, xt), x - xt, st["iterations"]
+
+
+def mix_triples(r, e, coef):
+    """Augmentation by linear combinations (section 3.4): r'_b = sum_j
+    coef[b, j] r_j and e'_b = sum_j coef[b, j] e_j for triples of one
+    medium."""
+    c = np.asarray(coef, dtype=np.float64)
+    r = np.asarray(r, dtype=np.complex128)
+    e = np.asarray(e, dtype=np.complex128)
+    return np.tensordot(c, r, axes=(1, 0)), np.tensordot(c, e, axes=(1, 0))
+
+
 def pair_training_loss(cfg_enc, pe, bufe, cfg_sol, ps, bufs, r_batch, e_batch, kappa_c_batch,
                        stats_e=None, stats_s=None, dtype=torch.float32):
     """Joint loss of an encoder-solver pair: the solver's training loss with

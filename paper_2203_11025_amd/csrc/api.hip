@@ -131,7 +131,7 @@ bool coarse_inverse(int nl, double ih2, const std::vector<cd> &mass, std::vector
 template <typename T>
 int dmalloc(T **p, size_t count)
 {
-    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    hipError_t e = dev_malloc((void **)p, count * sizeof(T));
     if (e != hipSuccess) {
         set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
         *p = nullptr;
@@ -145,9 +145,9 @@ int dmalloc(T **p, size_t count)
 int ensure_vcycle_ws(helm_handle *h, int nb)
 {
     if (nb <= h->ws_nb) return HELM_OK;
-    for (auto p : h->wf) hipFree(p);
-    for (auto p : h->wv) hipFree(p);
-    hipFree(h->cpart);
+    for (auto p : h->wf) dev_free(p);
+    for (auto p : h->wv) dev_free(p);
+    dev_free(h->cpart);
     h->cpart = nullptr;
     h->wf.assign(h->levels, nullptr);
     h->wv.assign(h->levels, nullptr);
@@ -353,13 +353,17 @@ void helm_destroy(helm_handle *h)
 {
     if (!h) return;
     fgmres_free(h);
-    for (auto p : h->wf) hipFree(p);
-    for (auto p : h->wv) hipFree(p);
-    for (auto &L : h->lv) hipFree(L.mass);
-    hipFree(h->Xc);
-    hipFree(h->cpart);
-    hipFree(h->kappa0);
-    hipFree(h->gamma0);
+    dev_free(h->tw);
+    dev_free(h->tx);
+    dev_free(h->tpart);
+    dev_free(h->txt);
+    for (auto p : h->wf) dev_free(p);
+    for (auto p : h->wv) dev_free(p);
+    for (auto &L : h->lv) dev_free(L.mass);
+    dev_free(h->Xc);
+    dev_free(h->cpart);
+    dev_free(h->kappa0);
+    dev_free(h->gamma0);
     delete h;
 }
 

@@ -132,7 +132,7 @@ __global__ void k_restart(FgState S, const double *__restrict__ rpartial, int nb
 template <typename T>
 int dalloc(T **p, size_t count)
 {
-    if (hipMalloc((void **)p, count * sizeof(T)) != hipSuccess) {
+    if (dev_malloc((void **)p, count * sizeof(T)) != hipSuccess) {
         *p = nullptr;
         set_error("helm_fgmres_solve: device allocation failed");
         return HELM_E_NOMEM;
@@ -143,14 +143,14 @@ int dalloc(T **p, size_t count)
 void work_free(FgWork *w)
 {
     if (!w) return;
-    hipFree(w->V);
-    hipFree(w->Z);
-    hipFree(w->partial);
-    hipFree(w->rpartial);
-    hipFree(w->state);
-    hipFree(w->t1);
-    hipFree(w->t2);
-    hipFree(w->d_net);
+    dev_free(w->V);
+    dev_free(w->Z);
+    dev_free(w->partial);
+    dev_free(w->rpartial);
+    dev_free(w->state);
+    dev_free(w->t1);
+    dev_free(w->t2);
+    dev_free(w->d_net);
     for (auto &g : w->graphs) hipGraphExecDestroy(g.exec);
     if (w->cap) hipStreamDestroy(w->cap);
     if (w->h_net) hipHostFree(w->h_net);
@@ -191,7 +191,7 @@ int work_ensure(helm_handle *h, int nb, int m, bool scratch, FgWork **out)
     size_t nz = (size_t)nb * ((m + 1) * m + (m + 1) + m + 3 * MAXV);
     size_t off_d = align(ni * sizeof(int)), off_z = align(off_d + nd * sizeof(double));
     size_t bytes = off_z + nz * sizeof(double2);
-    if (hipMalloc(&w->state, bytes) != hipSuccess) {
+    if (dev_malloc(&w->state, bytes) != hipSuccess) {
         work_free(w);
         set_error("helm_fgmres_solve: device allocation failed");
         return HELM_E_NOMEM;
@@ -236,7 +236,7 @@ int work_ensure(helm_handle *h, int nb, int m, bool scratch, FgWork **out)
         return HELM_E_HIP;
     }
     if (scratch && (dalloc(&w->t1, (size_t)nb * N) || dalloc(&w->t2, (size_t)nb * N) ||
-                    hipMalloc(&w->d_net, 2 * nb * sizeof(int)) != hipSuccess)) {
+                    dev_malloc(&w->d_net, 2 * nb * sizeof(int)) != hipSuccess)) {
         work_free(w);
         set_error("helm_fgmres_solve: device allocation failed");
         return HELM_E_NOMEM;
@@ -520,6 +520,12 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
 }
 
 }  // namespace
+
+int fgmres_one(helm_handle *h, int nb, const float2 *b, double2 *x, int m, double tol, int maxit, int prec,
+               unet_net *net, double stall_ratio, helm_fgmres_stats *stats, hipStream_t s, bool use_graph)
+{
+    return solve_problem(h, nb, b, x, m, tol, maxit, prec, net, stall_ratio, stats, s, use_graph);
+}
 
 void fgmres_free(helm_handle *h)
 {

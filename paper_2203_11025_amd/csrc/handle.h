@@ -5,6 +5,8 @@
 
 #include "helm_internal.h"
 
+struct unet_net;
+
 struct helm_handle {
     int n = 0;
     int levels = 0;
@@ -23,6 +25,12 @@ struct helm_handle {
     float2 *cpart = nullptr;   // partial sums of the coarsest-level GEMM
     // FGMRES workspace (see fgmres.hip)
     void *fg = nullptr;
+    // training-triple workspace (train_data.hip): A z and the x drawn by the
+    // seeded generator for `tw_nb` fields, FP64 partial sums
+    int tw_nb = 0;
+    float2 *tw = nullptr, *tx = nullptr;
+    double *tpart = nullptr;
+    double2 *txt = nullptr;  // the k-step FGMRES iterate x~ (complex128)
 };
 
 namespace helm {
@@ -47,4 +55,8 @@ int ensure_vcycle_ws(helm_handle *h, int nb);
 int vcycle(helm_handle *h, const float2 *f, size_t fs, float2 *v, size_t vs, int nb,
            const int *active, hipStream_t s, const double *scale = nullptr, int accumulate = 0);
 void fgmres_free(helm_handle *h);
+// FGMRES(m) of one problem with nb right-hand sides (fgmres.hip); x is
+// complex128 [nb][n][n] and starts from zero.
+int fgmres_one(helm_handle *h, int nb, const float2 *b, double2 *x, int m, double tol, int maxit, int prec,
+               unet_net *net, double stall_ratio, helm_fgmres_stats *stats, hipStream_t s, bool use_graph);
 }  // namespace helm

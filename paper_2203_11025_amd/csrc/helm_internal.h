@@ -13,6 +13,15 @@
 namespace helm {
 
 void set_error(const std::string &msg);
+// Device memory of the library's workspaces (alloc.hip): through the
+// allocator registered with helm_set_allocator, else hipMalloc / hipFree.
+hipError_t dev_malloc(void **p, size_t bytes);
+hipError_t dev_free(void *p);
+template <typename T>
+inline hipError_t dev_malloc(T **p, size_t bytes)
+{
+    return dev_malloc(reinterpret_cast<void **>(p), bytes);
+}
 // Timing hook (prof.hip): event on stream s at the start/end of a family's launch.
 // work_per_rhs x nb (or x the active right-hand sides when masked) is added
 // to the family's algorithmic work when the stop mark is recorded

@@ -33,6 +33,9 @@ struct unet_net {
     float *P = nullptr, *G = nullptr, *M = nullptr, *V = nullptr, *BUF = nullptr;
     float *scale = nullptr, *shift = nullptr;  // folded inference BN
     int step = 0;
+    // training-data cursor saved with the state: the seed of the sample
+    // generator and the index of the next sample to draw
+    uint64_t data_seed = 0, data_next = 0;
 
     int wsB = 0, wsH = 0, wsW = 0;
     bool wsTrain = false;

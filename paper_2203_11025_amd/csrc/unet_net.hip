@@ -25,7 +25,7 @@ int dalloc(T **p, size_t count)
 {
     *p = nullptr;
     if (count == 0) count = 1;
-    if (hipMalloc((void **)p, count * sizeof(T)) != hipSuccess) {
+    if (dev_malloc((void **)p, count * sizeof(T)) != hipSuccess) {
         *p = nullptr;
         set_error("unet: device allocation failed");
         return HELM_E_NOMEM;
@@ -43,32 +43,32 @@ using namespace helm;
 void unet_net::free_ws()
 {
     for (auto &a : act) {
-        hipFree(a.y32);
-        hipFree(a.a);
-        hipFree(a.g);
+        dev_free(a.y32);
+        dev_free(a.a);
+        dev_free(a.g);
     }
     act.clear();
-    for (auto p : pooled) hipFree(p);
-    for (auto p : arg) hipFree(p);
-    for (auto p : up) hipFree(p);
-    for (auto p : gctx) hipFree(p);
+    for (auto p : pooled) dev_free(p);
+    for (auto p : arg) dev_free(p);
+    for (auto p : up) dev_free(p);
+    for (auto p : gctx) dev_free(p);
     gctx.clear();
     pooled.clear();
     arg.clear();
     up.clear();
-    hipFree(x0);
-    hipFree(out);
-    hipFree(gout);
-    hipFree(dX);
-    hipFree(dy);
-    hipFree(dW);
-    hipFree(wpart);
-    hipFree(red);
-    hipFree(rcoarse);
-    hipFree(s);
-    hipFree(dfine);
-    hipFree(dloss);
-    hipFree(xin);
+    dev_free(x0);
+    dev_free(out);
+    dev_free(gout);
+    dev_free(dX);
+    dev_free(dy);
+    dev_free(dW);
+    dev_free(wpart);
+    dev_free(red);
+    dev_free(rcoarse);
+    dev_free(s);
+    dev_free(dfine);
+    dev_free(dloss);
+    dev_free(xin);
     x0 = nullptr;
     out = gout = dX = dW = wpart = nullptr;
     dy = nullptr;
@@ -83,23 +83,23 @@ void unet_net::free_ws()
 unet_net::~unet_net()
 {
     free_ws();
-    for (auto p : ctxbuf) hipFree(p);
-    for (auto p : cmap) hipFree(p);
+    for (auto p : ctxbuf) dev_free(p);
+    for (auto p : cmap) dev_free(p);
     for (auto &l : L) {
-        hipFree(l.Wp);
-        hipFree(l.Wd);
-        hipFree(l.map);
-        hipFree(l.mean);
-        hipFree(l.rstd);
-        hipFree(l.var);
+        dev_free(l.Wp);
+        dev_free(l.Wd);
+        dev_free(l.map);
+        dev_free(l.mean);
+        dev_free(l.rstd);
+        dev_free(l.var);
     }
-    hipFree(P);
-    hipFree(G);
-    hipFree(M);
-    hipFree(V);
-    hipFree(BUF);
-    hipFree(scale);
-    hipFree(shift);
+    dev_free(P);
+    dev_free(G);
+    dev_free(M);
+    dev_free(V);
+    dev_free(BUF);
+    dev_free(scale);
+    dev_free(shift);
 }
 
 int unet_net::init(const unet_cfg &c)
@@ -496,20 +496,20 @@ int unet_net::attach_context(const unet_net &enc, int nb, int H, int W, hipStrea
     if (ctxbuf.empty() || ctx_B != nb || ctx_H != H) {
         ++gen;
         cmap_valid = 0;
-        for (auto p : ctxbuf) hipFree(p);
-        for (auto p : cmap) hipFree(p);
+        for (auto p : ctxbuf) dev_free(p);
+        for (auto p : cmap) dev_free(p);
         ctxbuf.assign(Lv, nullptr);
         cmap.assign(L.size(), nullptr);
         ctx_valid = 0;
         for (size_t i = 0; i < L.size() && nb == 1 && H == W; ++i)
             if (L[i].name.back() == 'a' &&
-                hipMalloc(&cmap[i], (size_t)(H >> L[i].level) * (W >> L[i].level) * L[i].cout * sizeof(_Float16)) !=
+                dev_malloc(&cmap[i], (size_t)(H >> L[i].level) * (W >> L[i].level) * L[i].cout * sizeof(_Float16)) !=
                     hipSuccess) {
                 set_error("unet_pair_encode: out of device memory for the context maps");
                 return HELM_E_NOMEM;
             }
         for (int l = 0; l < Lv; ++l)
-            if (hipMalloc(&ctxbuf[l], (size_t)nb * (H >> l) * (W >> l) * cfg.widths[l] * sizeof(bf16)) !=
+            if (dev_malloc(&ctxbuf[l], (size_t)nb * (H >> l) * (W >> l) * cfg.widths[l] * sizeof(bf16)) !=
                 hipSuccess) {
                 set_error("unet_pair_encode: out of device memory for the context");
                 return HELM_E_NOMEM;
@@ -698,6 +698,137 @@ int unet_set_params(unet_net *net, const float *params, const float *buffers, vo
     return HELM_OK;
 }
 
+// ---------------------------------------------------------------- state files
+// Layout (little-endian): the 8-byte tag "HELMUNT1", then int32 in_ch,
+// out_ch, levels, widths[6], context, head; int64 nparams, nbuf; int32 Adam
+// step; uint64 data seed, next sample index; then FP32 arrays: parameters
+// [nparams], BN buffers [nbuf], Adam first moments [nparams], second moments
+// [nparams].
+static const char STATE_TAG[8] = {'H', 'E', 'L', 'M', 'U', 'N', 'T', '1'};
+
+struct StateHead {
+    int32_t cfg[11];
+    int64_t np, nb;
+    int32_t step;
+    uint64_t seed, next;
+};
+
+static void state_head(const unet_net *net, StateHead &h)
+{
+    const unet_cfg &c = net->cfg;
+    int32_t v[11] = {c.in_ch, c.out_ch, c.levels, 0, 0, 0, 0, 0, 0, c.context, c.head};
+    for (int l = 0; l < 6; ++l) v[3 + l] = l < c.levels ? c.widths[l] : 0;
+    std::copy(v, v + 11, h.cfg);
+    h.np = (int64_t)net->nparams;
+    h.nb = (int64_t)net->nbuf;
+    h.step = net->step;
+    h.seed = net->data_seed;
+    h.next = net->data_next;
+}
+
+static bool write_all(FILE *f, const void *p, size_t bytes) { return fwrite(p, 1, bytes, f) == bytes; }
+static bool read_all(FILE *f, void *p, size_t bytes) { return fread(p, 1, bytes, f) == bytes; }
+
+int unet_save(unet_net *net, const char *path, void *stream)
+{
+    if (!net || !path) {
+        set_error("unet_save: null argument");
+        return HELM_E_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<float> buf(3 * net->nparams + net->nbuf);
+    float *p = buf.data(), *b = p + net->nparams, *m = b + net->nbuf, *v = m + net->nparams;
+    HELM_HIP_CHECK(hipMemcpyAsync(p, net->P, net->nparams * 4, hipMemcpyDeviceToHost, st));
+    HELM_HIP_CHECK(hipMemcpyAsync(b, net->BUF, net->nbuf * 4, hipMemcpyDeviceToHost, st));
+    HELM_HIP_CHECK(hipMemcpyAsync(m, net->M, net->nparams * 4, hipMemcpyDeviceToHost, st));
+    HELM_HIP_CHECK(hipMemcpyAsync(v, net->V, net->nparams * 4, hipMemcpyDeviceToHost, st));
+    HELM_HIP_CHECK(hipStreamSynchronize(st));
+    StateHead h;
+    state_head(net, h);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "wb");
+    if (!f) {
+        set_error(std::string("unet_save: cannot open ") + tmp);
+        return HELM_E_INVALID;
+    }
+    bool ok = write_all(f, STATE_TAG, 8) && write_all(f, h.cfg, sizeof h.cfg) && write_all(f, &h.np, 8) &&
+              write_all(f, &h.nb, 8) && write_all(f, &h.step, 4) && write_all(f, &h.seed, 8) &&
+              write_all(f, &h.next, 8) && write_all(f, buf.data(), buf.size() * 4);
+    ok = (fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        set_error(std::string("unet_save: writing ") + path + " failed");
+        return HELM_E_INVALID;
+    }
+    return HELM_OK;
+}
+
+int unet_load(unet_net *net, const char *path, void *stream)
+{
+    if (!net || !path) {
+        set_error("unet_load: null argument");
+        return HELM_E_INVALID;
+    }
+    FILE *f = fopen(path, "rb");
+    if (!f) {
+        set_error(std::string("unet_load: cannot open ") + path);
+        return HELM_E_INVALID;
+    }
+    char tag[8];
+    StateHead h, mine;
+    state_head(net, mine);
+    bool ok = read_all(f, tag, 8) && std::equal(tag, tag + 8, STATE_TAG) && read_all(f, h.cfg, sizeof h.cfg) &&
+              read_all(f, &h.np, 8) && read_all(f, &h.nb, 8) && read_all(f, &h.step, 4) &&
+              read_all(f, &h.seed, 8) && read_all(f, &h.next, 8);
+    if (!ok || !std::equal(h.cfg, h.cfg + 11, mine.cfg) || h.np != mine.np || h.nb != mine.nb || h.step < 0) {
+        fclose(f);
+        set_error(std::string("unet_load: ") + path + " is not a state file of a network of this configuration");
+        return HELM_E_INVALID;
+    }
+    std::vector<float> buf(3 * net->nparams + net->nbuf);
+    ok = read_all(f, buf.data(), buf.size() * 4);
+    fclose(f);
+    if (!ok) {
+        set_error(std::string("unet_load: ") + path + " is truncated");
+        return HELM_E_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    float *p = buf.data(), *b = p + net->nparams, *m = b + net->nbuf, *v = m + net->nparams;
+    HELM_HIP_CHECK(hipMemcpyAsync(net->P, p, net->nparams * 4, hipMemcpyHostToDevice, st));
+    HELM_HIP_CHECK(hipMemcpyAsync(net->BUF, b, net->nbuf * 4, hipMemcpyHostToDevice, st));
+    HELM_HIP_CHECK(hipMemcpyAsync(net->M, m, net->nparams * 4, hipMemcpyHostToDevice, st));
+    HELM_HIP_CHECK(hipMemcpyAsync(net->V, v, net->nparams * 4, hipMemcpyHostToDevice, st));
+    net->repack(st);
+    HELM_HIP_CHECK(hipStreamSynchronize(st));  // the host copy is released on return
+    net->step = h.step;
+    net->data_seed = h.seed;
+    net->data_next = h.next;
+    HELM_HIP_CHECK(hipGetLastError());
+    return HELM_OK;
+}
+
+int unet_set_cursor(unet_net *net, unsigned long long seed, unsigned long long next)
+{
+    if (!net) {
+        set_error("unet_set_cursor: null network");
+        return HELM_E_INVALID;
+    }
+    net->data_seed = seed;
+    net->data_next = next;
+    return HELM_OK;
+}
+
+int unet_get_cursor(const unet_net *net, unsigned long long *seed, unsigned long long *next)
+{
+    if (!net || !seed || !next) {
+        set_error("unet_get_cursor: null argument");
+        return HELM_E_INVALID;
+    }
+    *seed = net->data_seed;
+    *next = net->data_next;
+    return HELM_OK;
+}
+
 // splitmix64 (Steele, Lea and Flood 2014) for the initial weights
 static uint64_t splitmix64(uint64_t &state)
 {
@@ -735,7 +866,7 @@ int unet_init(unet_net *net, unsigned long long seed, void *stream)
             p[net->head_w + i] = (float)(sd * normal01(st));
     }
     float *dp = nullptr;
-    if (hipMalloc(&dp, net->nparams * sizeof(float)) != hipSuccess) {
+    if (dev_malloc(&dp, net->nparams * sizeof(float)) != hipSuccess) {
         set_error("unet_init: out of device memory");
         return HELM_E_NOMEM;
     }
@@ -750,7 +881,7 @@ int unet_init(unet_net *net, unsigned long long seed, void *stream)
         set_error("unet_init: synchronisation failed");
         rc = HELM_E_HIP;
     }
-    hipFree(dp);
+    dev_free(dp);
     return rc;
 }
 

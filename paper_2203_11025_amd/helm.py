@@ -26,7 +26,10 @@ EXPORTS = [
     "helm_sl_vcycle", "helm_fgmres_solve", "helm_last_error", "helm_profile_start",
     "helm_profile_read", "helm_profile_stop", "helm_profile_sample", "helm_autotune", "helm_autotune_entries", "helm_autotune_force", "helm_training_triples", "helm_coarse_slowness",
     "helm_sl_vcycle_noalloc", "helm_sl_vcycle_noalloc_bytes", "helm_sl_vcycle_noalloc_max_bytes",
+    "helm_training_triples_seeded", "helm_set_allocator", "helm_allocated_bytes", "helm_triples_mix",
 ]
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
 PROF = {"none": 0, "coarse": 1, "down": 2, "up": 3, "cgs": 4, "apply": 5, "conv": 6, "wgrad": 7}
 
 
@@ -89,6 +92,14 @@ def lib():
         L.helm_last_error.restype = C.c_char_p
         L.helm_training_triples.argtypes = [vp, vp, vp, vp, ip, vp]
         L.helm_training_triples.restype = ip
+        L.helm_training_triples_seeded.argtypes = [vp, C.c_ulonglong, C.c_ulonglong, ip, vp, vp, vp, ip, vp]
+        L.helm_triples_mix.argtypes = [vp, vp, ip, C.c_longlong, vp, ip, vp, vp, vp]
+        L.helm_triples_mix.restype = ip
+        L.helm_training_triples_seeded.restype = ip
+        L.helm_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
+        L.helm_set_allocator.restype = ip
+        L.helm_allocated_bytes.argtypes = []
+        L.helm_allocated_bytes.restype = C.c_size_t
         L.helm_coarse_slowness.argtypes = [vp, vp, vp]
         L.helm_coarse_slowness.restype = ip
         L.helm_profile_start.argtypes = [C.c_uint]
@@ -195,7 +206,27 @@ class Handle:
                                            _stream(stream)), "helm_training_triples")
         return r, e
 
-    def coarse_slowness(self, stream=None):
+    def training_triples_seeded(self, seed, index0, r, e, x=None, ksteps=1, stream=None):
+        """Triples of samples index0 .. index0 + len(r) - 1 with x drawn on
+        the device from (seed, index) and k = ksteps FGMRES(M_V) steps
+        (helm_training_triples_seeded), written into the given complex64
+        [nrhs, n, n] views r and e (and x if given)."""
+        r = self._batch(r, "r")
+        e = self._batch(e, "e")
+        xp = C.c_void_p(0) if x is None else _dev(self._batch(x, "x"), torch.complex64, "x")
+        _check(lib().helm_training_triples_seeded(self._h, int(seed), int(index0), int(ksteps), xp,
+                                                  _dev(r, torch.complex64, "r"),
+                                                  _dev(e, torch.complex64, "e"), r.shape[0],
+                                                  _stream(stream)), "helm_training_triples_seeded")
+        return r, e
+
+    def coarse_slowness(self, out=None, stream=None):
+        """Slowness at the coarse points, float [n/2, n/2] (into `out`, a
+        contiguous view, if given)."""
+        if out is not None:
+            _check(lib().helm_coarse_slowness(self._h, _dev(out, torch.float32, "kc"), _stream(stream)),
+                   "helm_coarse_slowness")
+            return out
         kc = torch.empty((self.n // 2, self.n // 2), dtype=torch.float32, device="cuda")
         _check(lib().helm_coarse_slowness(self._h, _dev(kc, torch.float32, "kc"), _stream(stream)),
                "helm_coarse_slowness")
@@ -289,3 +320,53 @@ def autotune_force(kind=-1, mf=2, per_cu=1):
     """Force one tuner candidate launch shape on every convolution (test
     hook); kind < 0 switches it off."""
     _check(lib().helm_autotune_force(int(kind), int(mf), int(per_cu)), "helm_autotune_force")
+
+
+_alloc_keep = None
+
+
+def set_allocator(alloc=None, release=None):
+    """Register Python callables alloc(bytes) -> device address and
+    release(address, bytes) for the library's workspaces (helm_set_allocator);
+    no arguments restore hipMalloc / hipFree."""
+    global _alloc_keep
+    if alloc is None:
+        _check(lib().helm_set_allocator(ALLOC_FN(), FREE_FN(), None), "helm_set_allocator")
+        _alloc_keep = None
+        return
+    a = ALLOC_FN(lambda nbytes, ctx: alloc(int(nbytes)) or None)
+    f = FREE_FN(lambda ptr, nbytes, ctx: release(int(ptr), int(nbytes)))
+    _check(lib().helm_set_allocator(a, f, None), "helm_set_allocator")
+    _alloc_keep = (a, f, alloc, release)
+
+
+def use_torch_allocator(device=None):
+    """Back the library's workspaces by torch's caching allocator (blocks on
+    the given device, default the current one)."""
+    dev = torch.cuda.current_device() if device is None else int(device)
+
+    def alloc(nbytes):
+        return torch.cuda.caching_allocator_alloc(nbytes, device=dev)
+
+    def release(ptr, nbytes):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    set_allocator(alloc, release)
+
+
+def triples_mix(r, e, coef, r_out, e_out, stream=None):
+    """r_out[b] = sum_j coef[b, j] r[j] (and e) for triples of one medium
+    (helm_triples_mix); coef: device float [nout, nin]."""
+    nin, nout = r.shape[0], coef.shape[0]
+    if tuple(coef.shape) != (nout, nin) or e.shape != r.shape or r_out.shape[0] != nout or e_out.shape != r_out.shape:
+        raise HelmError("triples_mix: shapes do not match")
+    npts = r[0].numel()
+    _check(lib().helm_triples_mix(_dev(r, torch.complex64, "r"), _dev(e, torch.complex64, "e"), nin, npts,
+                                  _dev(coef, torch.float32, "coef"), nout, _dev(r_out, torch.complex64, "r_out"),
+                                  _dev(e_out, torch.complex64, "e_out"), _stream(stream)), "helm_triples_mix")
+    return r_out, e_out
+
+
+def allocated_bytes():
+    """Device bytes the library currently holds."""
+    return lib().helm_allocated_bytes()

@@ -11,7 +11,7 @@ from .helm import HelmError, _check, _dev, _stream, lib as _helm_lib
 EXPORTS = ["unet_create", "unet_destroy", "unet_num_params", "unet_num_buffers", "unet_init",
            "unet_set_params", "unet_get_params", "unet_forward", "unet_infer",
            "unet_loss_grad", "unet_train_step", "unet_pair_encode", "unet_pair_loss_grad",
-           "unet_pair_train_step"]
+           "unet_pair_train_step", "unet_save", "unet_load", "unet_set_cursor", "unet_get_cursor"]
 
 
 class Cfg(C.Structure):
@@ -67,6 +67,14 @@ def lib():
         L.unet_pair_train_step.argtypes = [vp, vp, C.POINTER(Batch), C.POINTER(TrainOpts),
                                            C.POINTER(C.c_double), vp]
         L.unet_pair_train_step.restype = ip
+        L.unet_save.argtypes = [vp, C.c_char_p, vp]
+        L.unet_save.restype = ip
+        L.unet_load.argtypes = [vp, C.c_char_p, vp]
+        L.unet_load.restype = ip
+        L.unet_set_cursor.argtypes = [vp, C.c_ulonglong, C.c_ulonglong]
+        L.unet_set_cursor.restype = ip
+        L.unet_get_cursor.argtypes = [vp, C.POINTER(C.c_ulonglong), C.POINTER(C.c_ulonglong)]
+        L.unet_get_cursor.restype = ip
         _done = True
     return L
 
@@ -103,6 +111,22 @@ class UNet:
             self.close()
         except Exception:
             pass
+
+    def save_state(self, path, stream=None):
+        """Parameters, BN statistics, Adam state and data cursor (unet_save)."""
+        _check(lib().unet_save(self._h, str(path).encode(), _stream(stream)), "unet_save")
+
+    def load_state(self, path, stream=None):
+        _check(lib().unet_load(self._h, str(path).encode(), _stream(stream)), "unet_load")
+
+    def set_cursor(self, seed, next_index):
+        _check(lib().unet_set_cursor(self._h, int(seed), int(next_index)), "unet_set_cursor")
+
+    def cursor(self):
+        """(seed, next sample index) of the training data."""
+        a, b = C.c_ulonglong(), C.c_ulonglong()
+        _check(lib().unet_get_cursor(self._h, C.byref(a), C.byref(b)), "unet_get_cursor")
+        return a.value, b.value
 
     def init(self, seed, stream=None):
         """Seeded Kaiming-normal initial parameters (in the library)."""

@@ -17,6 +17,7 @@ def declared_functions():
     for h in HEADERS:
         text = open(h).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"^typedef[^;]*;", "", text, flags=re.M | re.S)  # function-pointer types
         for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(\w+)\s*\(", text, flags=re.M):
             name = m.group(1)
             if name not in ("if", "for", "while", "return", "sizeof", "defined"):
