@@ -54,6 +54,11 @@ typedef struct {
     double jacobi_weight; /* damped-Jacobi weight (section 4); default 0.8       */
     int levels;           /* V-cycle levels; 0 = coarsest level 64^2, or n^2 if
                              n <= 64 (default)                                   */
+    int coarse_gmres;     /* coarsest-level solver: 0 = exact (dense inverse,
+                             default); k in [1, 30] = k GMRES steps with the
+                             Jacobi (diagonal) right preconditioner from zero,
+                             then one damped Jacobi post-relaxation (the
+                             setting of section 4; needs levels >= 2)          */
 } helm_opts;
 
 /*

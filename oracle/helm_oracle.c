@@ -268,6 +268,7 @@ typedef struct {
     double h[16];
     double *kappa[16], *gamma[16];
     band_lu *coarse;
+    int coarse_gmres;  /* 0: exact coarsest solve; k > 0: GMRES(k) + Jacobi */
 } orc_hier;
 
 orc_hier *orc_hier_create(int n, int levels, double omega, const double *kappa,
@@ -319,6 +320,141 @@ int orc_hier_level_n(const orc_hier *H, int l) { return H->n[l]; }
 const double *orc_hier_level_kappa(const orc_hier *H, int l) { return H->kappa[l]; }
 const double *orc_hier_level_gamma(const orc_hier *H, int l) { return H->gamma[l]; }
 
+/* Plain inner products for the coarse GMRES (defined again below for FGMRES). */
+static double cg_norm(const cplx *v, size_t N)
+{
+    double s = 0.0;
+    for (size_t p = 0; p < N; p++)
+        s += creal(v[p]) * creal(v[p]) + cimag(v[p]) * cimag(v[p]);
+    return sqrt(s);
+}
+
+static cplx cg_dot(const cplx *u, const cplx *v, size_t N)
+{
+    cplx s = 0.0;
+    for (size_t p = 0; p < N; p++)
+        s += conj(u[p]) * v[p];
+    return s;
+}
+
+/*
+ * Coarsest-level solve of section 4's setting: k steps of GMRES on
+ * M_L x = f with the diagonal (Jacobi) right preconditioner D^-1,
+ * D = diag(M_L), from x = 0, one cycle (no restart).  Plain definition:
+ * x = D^-1 V y with V an orthonormal basis (modified Gram-Schmidt) of the
+ * Krylov space K_k(M_L D^-1, f) and y minimising ||f - M_L D^-1 V y||,
+ * found from the Hessenberg matrix by a dense least-squares solve (normal
+ * equations are avoided: the (k+1) x k system is solved by Householder QR
+ * written out below).  The iteration stops early on an exact breakdown.
+ */
+static void coarse_gmres(const orc_hier *H, int l, int k, const cplx *f, cplx *x)
+{
+    int n = H->n[l];
+    size_t N = (size_t)n * n;
+    double h = H->h[l], om = H->omega, sh = H->beta;
+    cplx *V = calloc((size_t)(k + 1) * N, sizeof(cplx));
+    cplx *z = malloc(N * sizeof(cplx)), *w = malloc(N * sizeof(cplx));
+    cplx *Dinv = malloc(N * sizeof(cplx));
+    cplx *Hm = calloc((size_t)(k + 1) * k, sizeof(cplx)); /* Hm[i*k + j] */
+    for (size_t p = 0; p < N; p++)
+        Dinv[p] = 1.0 / (4.0 / (h * h) - mass_coef(om, H->kappa[l][p], H->gamma[l][p], sh));
+    memset(x, 0, N * sizeof(cplx));
+    double beta = cg_norm(f, N);
+    if (beta == 0.0)
+        goto out;
+    for (size_t p = 0; p < N; p++)
+        V[p] = f[p] / beta;
+    int kk = 0;
+    for (int j = 0; j < k; j++) {
+        cplx *vj = V + (size_t)j * N;
+        for (size_t p = 0; p < N; p++)
+            z[p] = Dinv[p] * vj[p];
+        orc_apply(n, h, om, H->kappa[l], H->gamma[l], sh, z, w);
+        for (int i = 0; i <= j; i++) {
+            cplx *vi = V + (size_t)i * N;
+            cplx hij = cg_dot(vi, w, N);
+            Hm[i * k + j] = hij;
+            for (size_t p = 0; p < N; p++)
+                w[p] -= hij * vi[p];
+        }
+        double hn = cg_norm(w, N);
+        Hm[(j + 1) * k + j] = hn;
+        kk = j + 1;
+        if (hn == 0.0)
+            break;
+        for (size_t p = 0; p < N; p++)
+            V[(size_t)(j + 1) * N + p] = w[p] / hn;
+    }
+    {
+        /* least squares min || beta e_1 - Hm y || over y in C^kk by
+         * Householder QR of the (kk+1) x kk matrix */
+        int m = kk + 1;
+        cplx *A = malloc((size_t)m * kk * sizeof(cplx)), *rhs = calloc(m, sizeof(cplx));
+        cplx *y = calloc(kk > 0 ? kk : 1, sizeof(cplx));
+        for (int i = 0; i < m; i++)
+            for (int j = 0; j < kk; j++)
+                A[i * kk + j] = Hm[i * k + j];
+        rhs[0] = beta;
+        for (int c = 0; c < kk; c++) {
+            double nrm = 0.0;
+            for (int i = c; i < m; i++)
+                nrm += creal(A[i * kk + c] * conj(A[i * kk + c]));
+            nrm = sqrt(nrm);
+            if (nrm == 0.0)
+                continue;
+            cplx a0 = A[c * kk + c];
+            cplx ph = cabs(a0) > 0.0 ? a0 / cabs(a0) : 1.0;
+            cplx *u = calloc(m, sizeof(cplx));
+            for (int i = c; i < m; i++)
+                u[i] = A[i * kk + c];
+            u[c] += ph * nrm;
+            double un = 0.0;
+            for (int i = c; i < m; i++)
+                un += creal(u[i] * conj(u[i]));
+            for (int j = c; j < kk; j++) {
+                cplx t = 0.0;
+                for (int i = c; i < m; i++)
+                    t += conj(u[i]) * A[i * kk + j];
+                for (int i = c; i < m; i++)
+                    A[i * kk + j] -= 2.0 * u[i] * t / un;
+            }
+            cplx t = 0.0;
+            for (int i = c; i < m; i++)
+                t += conj(u[i]) * rhs[i];
+            for (int i = c; i < m; i++)
+                rhs[i] -= 2.0 * u[i] * t / un;
+            free(u);
+        }
+        for (int i = kk - 1; i >= 0; i--) {
+            cplx t = rhs[i];
+            for (int j = i + 1; j < kk; j++)
+                t -= A[i * kk + j] * y[j];
+            y[i] = t / A[i * kk + i];
+        }
+        for (int j = 0; j < kk; j++)
+            for (size_t p = 0; p < N; p++)
+                x[p] += Dinv[p] * y[j] * V[(size_t)j * N + p];
+        free(A);
+        free(rhs);
+        free(y);
+    }
+out:
+    free(V);
+    free(z);
+    free(w);
+    free(Dinv);
+    free(Hm);
+}
+
+/* Coarsest solver: 0 = exact (banded LU), k > 0 = GMRES(k) with Jacobi. */
+int orc_hier_set_coarse_gmres(orc_hier *H, int k)
+{
+    if (!H || k < 0)
+        return -1;
+    H->coarse_gmres = k;
+    return 0;
+}
+
 /*
  * v = V-cycle(0, f) on the shifted operator M of level l (Algorithm 1 with
  * one pre- and one post-relaxation).  On the coarsest level the system is
@@ -331,6 +467,14 @@ static void vcycle_level(const orc_hier *H, int l, const cplx *f, cplx *v)
     size_t N = (size_t)n * n;
     double h = H->h[l], om = H->omega, sh = H->beta;
     if (l == H->levels - 1) {
+        if (H->coarse_gmres > 0) {
+            /* Algorithm 1 at the deepest level: the pre-relaxation is
+             * overwritten by the solve (GMRES from zero); the
+             * post-relaxation follows the inexact solve */
+            coarse_gmres(H, l, H->coarse_gmres, f, v);
+            orc_jacobi(n, h, om, H->kappa[l], H->gamma[l], sh, H->weight, f, v);
+            return;
+        }
         memcpy(v, f, N * sizeof(cplx));
         band_solve(H->coarse, v);
         return;

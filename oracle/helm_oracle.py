@@ -74,6 +74,8 @@ def lib():
                                  C.c_int, _dp, _dp, _dp, C.POINTER(_Stats)]
         L.orc_fgmres.restype = C.c_int
         L.orc_hier_residual_A.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        L.orc_hier_set_coarse_gmres.argtypes = [C.c_void_p, C.c_int]
+        L.orc_hier_set_coarse_gmres.restype = C.c_int
         _lib = L
     return _lib
 
@@ -159,7 +161,10 @@ def band_solve(kappa, gamma, omega, b, shift=0.0, h=None):
 class Hierarchy:
     """SL multigrid hierarchy (section 2.2) plus the FGMRES driver."""
 
-    def __init__(self, kappa, gamma, omega, levels, beta=0.5, weight=0.8):
+    def __init__(self, kappa, gamma, omega, levels, beta=0.5, weight=0.8, coarse_gmres=0):
+        """coarse_gmres = k > 0: the coarsest level is solved by k GMRES
+        steps with the Jacobi preconditioner from zero, then one damped
+        Jacobi post-relaxation (section 4's setting); 0: exactly."""
         self.kappa0 = _r(kappa)
         self.gamma0 = _r(gamma)
         self.n = self.kappa0.shape[0]
@@ -172,6 +177,9 @@ class Hierarchy:
         if not h:
             raise ValueError("invalid hierarchy (size / levels) or singular coarse operator")
         self._h = h
+        self.coarse_gmres = int(coarse_gmres)
+        if lib().orc_hier_set_coarse_gmres(h, self.coarse_gmres) != 0:
+            raise ValueError("coarse_gmres must be >= 0")
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

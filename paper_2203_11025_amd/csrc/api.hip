@@ -157,7 +157,7 @@ int ensure_vcycle_ws(helm_handle *h, int nb)
         size_t Nl = (size_t)h->lv[l].n * h->lv[l].n;
         if (dmalloc(&h->wf[l], Nl * nb) || dmalloc(&h->wv[l], Nl * nb)) return HELM_E_NOMEM;
     }
-    if (dmalloc(&h->cpart, coarse_scratch(h->Nc, nb))) return HELM_E_NOMEM;
+    if (dmalloc(&h->cpart, coarse_ws(h, nb))) return HELM_E_NOMEM;
     h->ws_nb = nb;
     return HELM_OK;
 }
@@ -177,12 +177,18 @@ int vcycle(helm_handle *h, const float2 *f, size_t fs, float2 *v, size_t vs, int
     return HELM_OK;
 }
 
+// complex elements of the coarsest solve's workspace for nb fields
+size_t coarse_ws(const helm_handle *h, int nb)
+{
+    return h->coarse_gmres > 0 ? coarse_gmres_elems(h->Nc, h->coarse_gmres, nb) : coarse_scratch(h->Nc, nb);
+}
+
 size_t vcycle_ws_elems(const helm_handle *h, int nb)
 {
     auto up = [](size_t e) { return (e + 31) & ~(size_t)31; };  // 256-byte aligned pieces
     size_t tot = 0;
     for (int l = 1; l < h->levels; ++l) tot += 2 * up((size_t)h->lv[l].n * h->lv[l].n * nb);
-    return tot + up(coarse_scratch(h->Nc, nb));
+    return tot + up(coarse_ws(h, nb));
 }
 
 void vcycle_carve(const helm_handle *h, int nb, float2 *base, VcycleWs &ws)
@@ -218,8 +224,12 @@ void vcycle_with(helm_handle *h, const VcycleWs &ws, const float2 *f, size_t fs,
                     l == 0 ? scale : nullptr);
     }
     size_t Nc = (size_t)h->Nc;
-    launch_coarse_solve(h->Xc, h->Nc, ws.wf[L - 1], Nc, ws.wv[L - 1], Nc, nb, active, s, nullptr, 0,
-                        ws.cpart);
+    if (h->coarse_gmres > 0)
+        launch_coarse_gmres(h->lv[L - 1], sh, w, h->coarse_gmres, ws.wf[L - 1], Nc, ws.wv[L - 1], Nc, nb, active, s,
+                            ws.cpart);
+    else
+        launch_coarse_solve(h->Xc, h->Nc, ws.wf[L - 1], Nc, ws.wv[L - 1], Nc, nb, active, s, nullptr, 0,
+                            ws.cpart);
     // prolongate and post-relax up to the finest level
     for (int l = L - 2; l >= 0; --l) {
         size_t Nl = (size_t)h->lv[l].n * h->lv[l].n;
@@ -258,11 +268,16 @@ int helm_setup(const float *slowness, double omega, const float *gamma, int n,
         return HELM_E_SHAPE;
     }
     double beta = 0.5, jw = 0.8;
-    int levels = 0;
+    int levels = 0, cgm = 0;
     if (opts) {
         beta = opts->beta;
         jw = opts->jacobi_weight;
         levels = opts->levels;
+        cgm = opts->coarse_gmres;
+    }
+    if (cgm < 0 || cgm > 30) {
+        set_error("helm_setup: coarse_gmres must be in [0, 30]");
+        return HELM_E_INVALID;
     }
     if (!(jw > 0.0 && jw < 2.0) || !(beta >= 0.0) || !std::isfinite(beta)) {
         set_error("helm_setup: jacobi_weight must be in (0, 2) and beta >= 0");
@@ -277,6 +292,10 @@ int helm_setup(const float *slowness, double omega, const float *gamma, int n,
         return HELM_E_SHAPE;
     }
     const int nl = n >> (levels - 1);
+    if (cgm > 0 && levels < 2) {
+        set_error("helm_setup: a GMRES coarsest solver needs at least two levels");
+        return HELM_E_SHAPE;
+    }
     if (nl > 128) {
         set_error("helm_setup: coarsest grid larger than 128^2 (dense inverse too big); use more levels");
         return HELM_E_SHAPE;
@@ -288,6 +307,7 @@ int helm_setup(const float *slowness, double omega, const float *gamma, int n,
     h->omega = omega;
     h->beta = beta;
     h->jacobi_w = jw;
+    h->coarse_gmres = cgm;
     size_t N = (size_t)n * n;
     int rc = HELM_OK;
     auto fail = [&](int code) {
@@ -321,6 +341,11 @@ int helm_setup(const float *slowness, double omega, const float *gamma, int n,
             set_error("helm_setup: slowness or gamma holds a non-finite value");
             return fail(HELM_E_INVALID);
         }
+    h->Nc = nl * nl;
+    if (cgm > 0) {  // no inverse: the coarsest level is solved by GMRES each cycle
+        *out = h;
+        return HELM_OK;
+    }
     const int stp = 1 << (levels - 1);
     std::vector<std::complex<double>> mass((size_t)nl * nl);
     for (int I = 0; I < nl; ++I)

@@ -13,6 +13,7 @@ struct helm_handle {
     double omega = 0.0;
     double beta = 0.5;
     double jacobi_w = 0.8;
+    int coarse_gmres = 0;      // 0: dense inverse Xc; k > 0: GMRES(k) + Jacobi (coarse_gmres.hip)
     float *kappa0 = nullptr;   // fine slowness copy (float [n][n])
     float *gamma0 = nullptr;   // fine attenuation copy (float [n][n])
     std::vector<helm::Level> lv;
@@ -36,7 +37,7 @@ struct helm_handle {
 namespace helm {
 // Workspace of one V-cycle over nb fields: per level l >= 1 the restricted
 // right-hand side f_l and the correction v_l ([nb][n_l][n_l] each), and the
-// partial sums of the coarsest-level GEMM (coarse_scratch(Nc, nb)).
+// workspace of the coarsest solve (coarse_ws(h, nb)).
 struct VcycleWs {
     static constexpr int MAXL = 12;
     float2 *wf[MAXL] = {}, *wv[MAXL] = {};
@@ -44,6 +45,9 @@ struct VcycleWs {
 };
 // complex elements of a VcycleWs carved from one buffer, and the carving
 size_t vcycle_ws_elems(const helm_handle *h, int nb);
+// complex elements of the coarsest solve's workspace (GEMM partial sums, or
+// the GMRES vectors of a GMRES coarsest solver) for nb fields
+size_t coarse_ws(const helm_handle *h, int nb);
 void vcycle_carve(const helm_handle *h, int nb, float2 *base, VcycleWs &ws);
 // the V-cycle on a given workspace: kernel launches only (no allocation)
 void vcycle_with(helm_handle *h, const VcycleWs &ws, const float2 *f, size_t fs, float2 *v, size_t vs,

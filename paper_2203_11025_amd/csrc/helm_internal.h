@@ -79,6 +79,14 @@ void launch_coarse_solve(const float2 *X, int N, const float2 *f, size_t fs, flo
                          size_t vs, int nb, const int *active, hipStream_t s,
                          const double *scale = nullptr, int accumulate = 0, float2 *scratch = nullptr);
 
+// Coarsest solve by k GMRES steps with the Jacobi right preconditioner from
+// zero, then one damped Jacobi sweep (weight w) on the shifted operator;
+// one workgroup per field; `work` holds coarse_gmres_elems(N, k, nb)
+// complex values.  HELM_E_INVALID when k or the grid is out of range.
+size_t coarse_gmres_elems(int Nc, int k, int nb);
+int launch_coarse_gmres(const Level &L, float shift, float w, int k, const float2 *f, size_t fs, float2 *v,
+                        size_t vs, int nb, const int *active, hipStream_t s, float2 *work);
+
 // mode 0: y = f - Op x;  mode 1: y = x + w D^-1 (f - Op x);  mode 2: y = w D^-1 f.
 // With fscale, field b of f is read as fscale[b] f_b.
 void launch_resjac(const Level &L, float shift, float w, int mode, const float2 *x, size_t xs,

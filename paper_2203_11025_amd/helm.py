@@ -38,7 +38,8 @@ class HelmError(RuntimeError):
 
 
 class _Opts(C.Structure):
-    _fields_ = [("beta", C.c_double), ("jacobi_weight", C.c_double), ("levels", C.c_int)]
+    _fields_ = [("beta", C.c_double), ("jacobi_weight", C.c_double), ("levels", C.c_int),
+                ("coarse_gmres", C.c_int)]
 
 
 class FgmresOpts(C.Structure):
@@ -146,12 +147,12 @@ class Handle:
     """One medium: the multigrid hierarchy of helm_setup."""
 
     def __init__(self, slowness, gamma, omega, levels=0, beta=0.5, jacobi_weight=0.8,
-                 stream=None):
+                 stream=None, coarse_gmres=0):
         n = slowness.shape[-1]
         if tuple(slowness.shape) != (n, n) or tuple(gamma.shape) != (n, n):
             raise HelmError("slowness and gamma must be [n, n]")
         self._keep = (slowness, gamma)
-        opts = _Opts(beta, jacobi_weight, levels)
+        opts = _Opts(beta, jacobi_weight, levels, int(coarse_gmres))
         h = C.c_void_p()
         _check(lib().helm_setup(_dev(slowness, torch.float32, "slowness"), float(omega),
                                 _dev(gamma, torch.float32, "gamma"), n, C.byref(opts),

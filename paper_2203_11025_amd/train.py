@@ -116,8 +116,8 @@ class Batches:
 
         b = 0
         while b < self.batch:
-            g = 1
-            while b + g < self.batch and med[b + g] == med[b]:
+            g = 1  # a group of at most 32 samples of one medium
+            while b + g < self.batch and med[b + g] == med[b] and g < 32:
                 g += 1
             q = np.ones((1, 1))
             if g > 1:

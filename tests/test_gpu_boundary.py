@@ -163,7 +163,12 @@ def test_save_load_resumes_training_bit_for_bit(mods, tmp_path):
 @pytest.mark.parametrize("k", [1, 3, 10])
 def test_k_step_triples_match_the_oracle(mods, oracle, k):
     """eq. 3.8 with k FGMRES(M_V) steps from zero: the device's DCGS2 and the
-    oracle's MGS reach the same iterate up to rounding; r and e to 1e-5."""
+    oracle's MGS reach the same iterate up to rounding.  The iterate carries
+    complex64 rounding relative to its own size (about ||x||), while r = b -
+    A x~ shrinks by the k-step reduction, so r and e are compared relative to
+    ||b|| = ||A x|| and ||x|| (1e-5), and the device's triple must satisfy
+    A e = r to 1e-5 ||b|| (FP64 check of its outputs); the residual norms
+    agree to 1%."""
     helm, unet, _ = mods
     n, nb = 64, 2
     kap, gam, om, h = medium(helm, n, 7)
@@ -176,7 +181,13 @@ def test_k_step_triples_match_the_oracle(mods, oracle, k):
     for b in range(nb):
         ro, eo, its = U.training_triple_k(H, x[b], k)
         assert its == k
-        assert rel(r[b], ro) <= 1e-5 and rel(e[b], eo) <= 1e-5, (k, rel(r[b], ro), rel(e[b], eo))
+        bb = oracle.apply(kap, gam, om, x[b].astype(complex))
+        nb_, nx = np.linalg.norm(bb), np.linalg.norm(x[b])
+        dr, de = np.linalg.norm(r[b] - ro) / nb_, np.linalg.norm(e[b] - eo) / nx
+        assert dr <= 1e-5 and de <= 1e-5, (k, dr, de)
+        cons = np.linalg.norm(oracle.apply(kap, gam, om, e[b].astype(complex)) - r[b]) / nb_
+        assert cons <= 1e-5, (k, cons)
+        assert abs(np.linalg.norm(r[b]) / np.linalg.norm(ro) - 1) <= 1e-2
 
 
 def test_triples_mix_matches_the_oracle(mods):
@@ -194,3 +205,21 @@ def test_triples_mix_matches_the_oracle(mods):
     with pytest.raises(helm.HelmError, match="overlap"):
         t = torch.from_numpy(r).cuda()
         helm.triples_mix(t, torch.from_numpy(e).cuda(), torch.from_numpy(c).cuda(), t[:nout], eo)
+
+
+def test_training_with_random_k_augmentation_and_schedule(mods):
+    """A run over a fixed data set of 32 samples with k drawn from 1..10 per
+    sample, linear-combination augmentation and the section-4 schedule
+    (scaled: t0 = 2 epochs): the batch doubles at epochs 2 and 3, every loss
+    is finite, and the cursor ends after four epochs."""
+    helm, unet, train = mods
+    n = 64
+    _, _, _, h = medium(helm, n, 8)
+    net = unet.UNet(widths=(32, 64))
+    net.init(5)
+    sched = lambda ep: train.paper_schedule(ep, lr0=1e-3, batch0=4, t0=2)
+    losses = train.train(net, [h], steps=4, seed=3, dataset=32, ksteps="random", augment=True,
+                         schedule=sched)
+    assert len(losses) == 8 + 8 + 4 + 2
+    assert all(np.isfinite(losses))
+    assert net.cursor() == (3, 4 * 32)
