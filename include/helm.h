@@ -150,6 +150,11 @@ typedef struct {
                             and the true residual) into a HIP graph once and
                             replay it; default 0.  Ignored while the profiling
                             hook is active.                                      */
+    void *encoder;       /* unet_net* encoder of an encoder-solver `net`, or
+                            NULL.  Given, each problem's medium is encoded
+                            (unet_pair_encode_medium) right before its solve,
+                            so one call takes any number of media; without it
+                            the solver must hold the one problem's context.  */
 } helm_fgmres_opts;
 
 typedef struct {
@@ -196,6 +201,31 @@ int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int *rhs_per_p
                       const float *const *b, double *const *x,
                       const helm_fgmres_opts *opts, helm_fgmres_stats *stats,
                       void *stream);
+
+/*
+ * helm_block_fgmres_solve -- block restarted flexible GMRES(m) (the solver
+ * of the paper's experiments, section 4: Calandra et al., block size 10,
+ * m = 10) on one medium: the nrhs right-hand sides are taken in blocks of
+ * `block` consecutive fields (the last block may be smaller), and the
+ * fields of a block share one block Krylov space.  Per block and cycle:
+ * R = B - A X in FP64 (stored complex64) = V_0 beta by Cholesky QR applied
+ * twice; each step applies the preconditioner to the block (M_V, M_CU or
+ * M_VU as in helm_fgmres_solve), W = A Z_j, two classical block
+ * Gram-Schmidt passes and Cholesky QR twice; the block Hessenberg
+ * least-squares problem is solved in FP64 by Householder QR; X (complex128)
+ * += Z Y at the cycle's end or when every column's estimate is below tol.
+ * Gram entries accumulate in FP64 in a fixed order.
+ *   b : complex64 [nrhs][n][n];  x : complex128 [nrhs][n][n] (output).
+ *   opts : m, tol, maxit (block steps), prec, net as for helm_fgmres_solve
+ *          (stall_ratio, graph and encoder are ignored); NULL = m 10,
+ *          tol 1e-7, maxit 20000, M_V.  (m + 1) block^2 <= 4096, block <= 16.
+ *   stats : host array [nrhs]; iterations = block steps of that field's
+ *          block; rho per column from the block least-squares residual.
+ * Synchronises `stream` several times per block step.  Returns
+ * HELM_NOT_CONVERGED if a field misses tol within maxit steps.
+ */
+int helm_block_fgmres_solve(helm_handle *h, int nrhs, const float *b, double *x, int block,
+                            const helm_fgmres_opts *opts, helm_fgmres_stats *stats, void *stream);
 
 /*
  * helm_training_triples -- supervised training data (section 3.4, eq.

@@ -146,6 +146,14 @@ int unet_pair_encode(unet_net *encoder, unet_net *solver, const float *kappa_c, 
                      void *stream);
 
 /*
+ * unet_pair_encode_medium -- unet_pair_encode for the medium of handle h:
+ * the encoder runs on the slowness injected at the coarse points of h (the
+ * network grid n/2) and the solver keeps that one context (nb = 1).  The
+ * handle keeps a float [n/2][n/2] buffer for the coarse slowness.
+ */
+int unet_pair_encode_medium(unet_net *encoder, unet_net *solver, helm_handle *h, void *stream);
+
+/*
  * unet_pair_loss_grad -- the loss of unet_loss_grad with the solver fed
  * the contexts the encoder computes (training-mode BN in both) from each
  * sample's batch->kappa_c; gradients of both networks (joint training).

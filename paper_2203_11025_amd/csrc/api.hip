@@ -382,6 +382,7 @@ void helm_destroy(helm_handle *h)
     dev_free(h->tx);
     dev_free(h->tpart);
     dev_free(h->txt);
+    dev_free(h->kcoarse);
     for (auto p : h->wf) dev_free(p);
     for (auto p : h->wv) dev_free(p);
     for (auto &L : h->lv) dev_free(L.mass);

@@ -1,0 +1,530 @@
+// Block flexible GMRES (the solver of the paper's experiments, section 4:
+// block restarted FGMRES(m) of Calandra, Gratton, Langou, Pinel and Vasseur
+// with s right-hand sides sharing one block Krylov space).
+//
+// One cycle from X (complex128):
+//   R = B - A X (FP64 residual, stored complex64), R = V_0 beta
+//   step j:  Z_j = Prec(V_j) (s fields at once), W = A Z_j,
+//            two classical block Gram-Schmidt passes C = [V_0..V_j]^H W,
+//            W -= [V_0..V_j] C, and W = V_{j+1} H_{j+1,j} by Cholesky QR
+//            applied twice (G = W^H W = R^H R, W <- W R^-1).
+//   X += [Z_0..Z_j] Y with Y = argmin ||E_1 beta - Hbar Y||_F.
+// Vectors are complex64; every Gram entry accumulates in FP64 and is reduced
+// in a fixed order; the block Hessenberg matrix, its least-squares problem
+// (Householder QR), the Cholesky factors and X are FP64.  The small dense
+// steps run on the host (s <= 16, (m + 1) s^2 <= 4096): a block step
+// synchronises once per Gram matrix and coefficient upload.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "handle.h"
+#include "unet_net.h"
+
+namespace helm {
+
+namespace {
+
+typedef std::complex<double> cd;
+constexpr int BF_T = 256, BF_TI = 2, BF_SMAX = 16;
+
+__device__ __forceinline__ double bf_wsum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// part[chunk][i][k] = sum over the chunk's points of conj(A_i) B_k for basis
+// vectors i in [i0, i0 + BF_TI) (blockIdx.x tile) and columns k < s (SM >=
+// s slots).  A_i = A + i * N, B_k = B + k * N.  grid (ceil(na / BF_TI),
+// nchunk): the i-tiles of one chunk run together, so B's chunk is read from
+// HBM once and from the L2 by the other tiles.
+template <int SM>
+__global__ __launch_bounds__(BF_T) void k_block_gram(const float2 *__restrict__ A, int na,
+                                                     const float2 *__restrict__ Bv, int s, size_t N, int chunk,
+                                                     double2 *__restrict__ part)
+{
+    const int i0 = blockIdx.x * BF_TI, c = blockIdx.y;
+    const size_t p0 = (size_t)c * chunk, p1 = std::min(N, p0 + (size_t)chunk);
+    double ar[BF_TI][SM], ai[BF_TI][SM];
+#pragma unroll
+    for (int i = 0; i < BF_TI; ++i)
+#pragma unroll
+        for (int k = 0; k < SM; ++k) ar[i][k] = ai[i][k] = 0.0;
+    for (size_t p = p0 + threadIdx.x; p < p1; p += BF_T) {
+        float2 a[BF_TI];
+#pragma unroll
+        for (int i = 0; i < BF_TI; ++i) a[i] = i0 + i < na ? A[(size_t)(i0 + i) * N + p] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < SM; ++k) {
+            if (k < s) {
+                const float2 b = Bv[(size_t)k * N + p];
+#pragma unroll
+                for (int i = 0; i < BF_TI; ++i) {
+                    ar[i][k] += (double)a[i].x * b.x + (double)a[i].y * b.y;
+                    ai[i][k] += (double)a[i].x * b.y - (double)a[i].y * b.x;
+                }
+            }
+        }
+    }
+    __shared__ double sr[BF_T / 64][BF_TI * SM], si[BF_T / 64][BF_TI * SM];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < BF_TI; ++i)
+#pragma unroll
+        for (int k = 0; k < SM; ++k) {
+            const double x = bf_wsum(ar[i][k]), y = bf_wsum(ai[i][k]);
+            if (lane == 0) {
+                sr[wv][i * SM + k] = x;
+                si[wv][i * SM + k] = y;
+            }
+        }
+    __syncthreads();
+    for (int q = threadIdx.x; q < BF_TI * SM; q += BF_T) {
+        const int i = q / SM, k = q - i * SM;
+        if (i0 + i < na && k < s) {
+            double x = 0.0, y = 0.0;
+            for (int w = 0; w < BF_T / 64; ++w) {
+                x += sr[w][q];
+                y += si[w][q];
+            }
+            part[((size_t)c * na + i0 + i) * s + k] = make_double2(x, y);
+        }
+    }
+}
+
+// out[i][k] = sum over chunks (in order) of part[chunk][i][k]
+__global__ void k_block_gram_sum(const double2 *__restrict__ part, int nchunk, int nik, double2 *__restrict__ out)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nik) return;
+    double x = 0.0, y = 0.0;
+    for (int c = 0; c < nchunk; ++c) {
+        const double2 v = part[(size_t)c * nik + q];
+        x += v.x;
+        y += v.y;
+    }
+    out[q] = make_double2(x, y);
+}
+
+// Per point p, with P = sum_{i < na} A_i[p] C[i][k] (C double2 [na][s]):
+//   MODE 0: Out_k[p] -= P      (complex64; the Gram-Schmidt update)
+//   MODE 1: Out_k[p]  = P      (complex64, Out may be A: every A_i[p] is
+//                               read before any Out_k[p] is written)
+//   MODE 2: X_k[p]   += P      (complex128; the solution update, FP64)
+// Sums in i order; FP32 products for MODE 0 and 1, FP64 for MODE 2.
+template <int SM, int MODE>
+__global__ __launch_bounds__(BF_T) void k_block_combine(const float2 *A, int na, const double2 *__restrict__ C,
+                                                        int s, size_t N, float2 *Out, double2 *__restrict__ X)
+{
+    extern __shared__ double2 cs[];  // [na][s]
+    for (int q = threadIdx.x; q < na * s; q += BF_T) cs[q] = C[q];
+    __syncthreads();
+    for (size_t p = (size_t)blockIdx.x * BF_T + threadIdx.x; p < N; p += (size_t)gridDim.x * BF_T) {
+        if constexpr (MODE == 2) {
+            double xr[SM], xi[SM];
+#pragma unroll
+            for (int k = 0; k < SM; ++k) xr[k] = xi[k] = 0.0;
+            for (int i = 0; i < na; ++i) {
+                const float2 a = A[(size_t)i * N + p];
+#pragma unroll
+                for (int k = 0; k < SM; ++k)
+                    if (k < s) {
+                        const double2 c = cs[i * s + k];
+                        xr[k] += a.x * c.x - a.y * c.y;
+                        xi[k] += a.x * c.y + a.y * c.x;
+                    }
+            }
+#pragma unroll
+            for (int k = 0; k < SM; ++k)
+                if (k < s) {
+                    double2 &x = X[(size_t)k * N + p];
+                    x = make_double2(x.x + xr[k], x.y + xi[k]);
+                }
+        } else {
+            float xr[SM], xi[SM];
+#pragma unroll
+            for (int k = 0; k < SM; ++k) xr[k] = xi[k] = 0.f;
+            for (int i = 0; i < na; ++i) {
+                const float2 a = A[(size_t)i * N + p];
+#pragma unroll
+                for (int k = 0; k < SM; ++k)
+                    if (k < s) {
+                        const double2 c = cs[i * s + k];
+                        const float cr = (float)c.x, ci = (float)c.y;
+                        xr[k] = fmaf(a.x, cr, fmaf(-a.y, ci, xr[k]));
+                        xi[k] = fmaf(a.x, ci, fmaf(a.y, cr, xi[k]));
+                    }
+            }
+#pragma unroll
+            for (int k = 0; k < SM; ++k)
+                if (k < s) {
+                    float2 &o = Out[(size_t)k * N + p];
+                    if (MODE == 0)
+                        o = make_float2(o.x - xr[k], o.y - xi[k]);
+                    else
+                        o = make_float2(xr[k], xi[k]);
+                }
+        }
+    }
+}
+
+struct BlockWork {
+    size_t N = 0;
+    int s = 0, m = 0, nchunk = 0, chunk = 0;
+    float2 *V = nullptr, *Z = nullptr, *t1 = nullptr, *t2 = nullptr;
+    double2 *part = nullptr, *G = nullptr, *C = nullptr;
+    double *rpart = nullptr;
+    ~BlockWork()
+    {
+        dev_free(V);
+        dev_free(Z);
+        dev_free(t1);
+        dev_free(t2);
+        dev_free(part);
+        dev_free(G);
+        dev_free(C);
+        dev_free(rpart);
+    }
+};
+
+int sm_of(int s) { return s <= 4 ? 4 : s <= 8 ? 8 : 16; }
+
+// G (host, na x s, row-major) = A^H B over N points
+int gram(BlockWork &w, const float2 *A, int na, const float2 *B, int s, std::vector<cd> &G, hipStream_t st)
+{
+    const dim3 grid((na + BF_TI - 1) / BF_TI, w.nchunk);
+#define BF_G(S) hipLaunchKernelGGL(k_block_gram<S>, grid, dim3(BF_T), 0, st, A, na, B, s, w.N, w.chunk, w.part)
+    switch (sm_of(s)) {
+    case 4: BF_G(4); break;
+    case 8: BF_G(8); break;
+    default: BF_G(16); break;
+    }
+#undef BF_G
+    const int nik = na * s;
+    hipLaunchKernelGGL(k_block_gram_sum, dim3((nik + 255) / 256), dim3(256), 0, st, w.part, w.nchunk, nik, w.G);
+    std::vector<double2> h(nik);
+    HELM_HIP_CHECK(hipMemcpyAsync(h.data(), w.G, nik * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HELM_HIP_CHECK(hipStreamSynchronize(st));
+    G.resize(nik);
+    for (int q = 0; q < nik; ++q) G[q] = cd(h[q].x, h[q].y);
+    return HELM_OK;
+}
+
+template <int MODE>
+int combine(BlockWork &w, const float2 *A, int na, const std::vector<cd> &C, int s, float2 *Out, double2 *X,
+            hipStream_t st)
+{
+    std::vector<double2> h(na * s);
+    for (int q = 0; q < na * s; ++q) h[q] = make_double2(C[q].real(), C[q].imag());
+    HELM_HIP_CHECK(hipMemcpyAsync(w.C, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+    const int gx = (int)std::min<size_t>(2048, (w.N + BF_T - 1) / BF_T);
+    const size_t lds = (size_t)na * s * sizeof(double2);
+#define BF_C(S) hipLaunchKernelGGL((k_block_combine<S, MODE>), dim3(gx), dim3(BF_T), lds, st, A, na, w.C, s, w.N, Out, X)
+    switch (sm_of(s)) {
+    case 4: BF_C(4); break;
+    case 8: BF_C(8); break;
+    default: BF_C(16); break;
+    }
+#undef BF_C
+    // the host copy of C must outlive the transfer
+    HELM_HIP_CHECK(hipStreamSynchronize(st));
+    return HELM_OK;
+}
+
+// Cholesky of the Hermitian s x s G = R^H R (R upper); false if not positive
+bool cholesky(const std::vector<cd> &G, int s, std::vector<cd> &R)
+{
+    R.assign((size_t)s * s, cd(0.0));
+    for (int j = 0; j < s; ++j) {
+        double d = G[j * s + j].real();
+        for (int k = 0; k < j; ++k) d -= std::norm(R[k * s + j]);
+        if (!(d > 0.0)) return false;
+        R[j * s + j] = std::sqrt(d);
+        for (int i = j + 1; i < s; ++i) {
+            cd t = G[j * s + i];
+            for (int k = 0; k < j; ++k) t -= std::conj(R[k * s + j]) * R[k * s + i];
+            R[j * s + i] = t / R[j * s + j].real();
+        }
+    }
+    return true;
+}
+
+// inverse of an upper-triangular s x s matrix
+std::vector<cd> tri_inv(const std::vector<cd> &R, int s)
+{
+    std::vector<cd> X((size_t)s * s, cd(0.0));
+    for (int c = 0; c < s; ++c) {
+        X[c * s + c] = 1.0 / R[c * s + c];
+        for (int i = c - 1; i >= 0; --i) {
+            cd t = 0.0;
+            for (int k = i + 1; k <= c; ++k) t += R[i * s + k] * X[k * s + c];
+            X[i * s + c] = -t / R[i * s + i];
+        }
+    }
+    return X;
+}
+
+std::vector<cd> matmul(const std::vector<cd> &A, const std::vector<cd> &B, int n, int k, int m)
+{
+    std::vector<cd> C((size_t)n * m, cd(0.0));
+    for (int i = 0; i < n; ++i)
+        for (int q = 0; q < k; ++q)
+            for (int j = 0; j < m; ++j) C[i * m + j] += A[i * k + q] * B[q * m + j];
+    return C;
+}
+
+// W (s fields) = Q R by Cholesky QR applied twice; W is overwritten by Q,
+// R (s x s upper, row-major) returned.  False on a rank-deficient block.
+int chol_qr2(BlockWork &w, float2 *W, int s, std::vector<cd> &R, bool &ok, hipStream_t st)
+{
+    R.assign((size_t)s * s, cd(0.0));
+    for (int i = 0; i < s; ++i) R[i * s + i] = 1.0;
+    ok = true;
+    for (int pass = 0; pass < 2; ++pass) {
+        std::vector<cd> G, Rk;
+        int rc = gram(w, W, s, W, s, G, st);
+        if (rc) return rc;
+        if (!cholesky(G, s, Rk)) {
+            ok = false;
+            return HELM_OK;
+        }
+        if ((rc = combine<1>(w, W, s, tri_inv(Rk, s), s, W, nullptr, st))) return rc;
+        R = matmul(Rk, R, s, s, s);
+    }
+    return HELM_OK;
+}
+
+// min ||E - H Y||_F by Householder QR (H: rows x cols, E: rows x s, row-major);
+// returns Y (cols x s) and the column norms of E - H Y
+void block_lsq(std::vector<cd> H, std::vector<cd> E, int rows, int cols, int s, std::vector<cd> &Y,
+               std::vector<double> &res)
+{
+    for (int c = 0; c < cols; ++c) {
+        double nrm = 0.0;
+        for (int i = c; i < rows; ++i) nrm += std::norm(H[i * cols + c]);
+        nrm = std::sqrt(nrm);
+        if (nrm == 0.0) continue;
+        const cd a0 = H[c * cols + c];
+        const cd ph = std::abs(a0) > 0.0 ? a0 / std::abs(a0) : cd(1.0);
+        std::vector<cd> u(rows, cd(0.0));
+        for (int i = c; i < rows; ++i) u[i] = H[i * cols + c];
+        u[c] += ph * nrm;
+        double un = 0.0;
+        for (int i = c; i < rows; ++i) un += std::norm(u[i]);
+        for (int j = c; j < cols; ++j) {
+            cd t = 0.0;
+            for (int i = c; i < rows; ++i) t += std::conj(u[i]) * H[i * cols + j];
+            for (int i = c; i < rows; ++i) H[i * cols + j] -= 2.0 * u[i] * t / un;
+        }
+        for (int j = 0; j < s; ++j) {
+            cd t = 0.0;
+            for (int i = c; i < rows; ++i) t += std::conj(u[i]) * E[i * s + j];
+            for (int i = c; i < rows; ++i) E[i * s + j] -= 2.0 * u[i] * t / un;
+        }
+    }
+    Y.assign((size_t)cols * s, cd(0.0));
+    for (int j = 0; j < s; ++j)
+        for (int i = cols - 1; i >= 0; --i) {
+            cd t = E[i * s + j];
+            for (int k = i + 1; k < cols; ++k) t -= H[i * cols + k] * Y[k * s + j];
+            Y[i * s + j] = H[i * cols + i] != cd(0.0) ? t / H[i * cols + i] : cd(0.0);
+        }
+    res.assign(s, 0.0);
+    for (int j = 0; j < s; ++j) {
+        double r = 0.0;
+        for (int i = cols; i < rows; ++i) r += std::norm(E[i * s + j]);
+        res[j] = std::sqrt(r);
+    }
+}
+
+// z = Prec(v) for s fields
+int block_prec(helm_handle *h, BlockWork &w, int prec, unet_net *net, const float2 *v, float2 *z, int s,
+               hipStream_t st)
+{
+    const size_t N = w.N;
+    const Level &L0 = h->lv[0];
+    const float jw = (float)h->jacobi_w;
+    if (prec == HELM_PREC_SL) return vcycle(h, v, N, z, N, s, nullptr, st);
+    int rc;
+    if (prec == HELM_PREC_UNET_DEFL) {  // e0 = Net(v), z = e0 + V(0, v - A e0)
+        if ((rc = net->wrap_apply(h, v, N, z, N, s, 0, st))) return rc;
+        launch_resjac(L0, 0.f, jw, 0, z, N, v, N, w.t2, N, s, nullptr, st);
+        return vcycle(h, w.t2, N, z, N, s, nullptr, st, nullptr, 1);
+    }
+    // Algorithm 2: e1 = w D^-1 v, e2 = e1 + Net(v - A e1), z = e2 + w D^-1 (v - A e2)
+    launch_resjac(L0, 0.f, jw, 2, v, N, v, N, w.t1, N, s, nullptr, st);
+    launch_resjac(L0, 0.f, jw, 0, w.t1, N, v, N, w.t2, N, s, nullptr, st);
+    if ((rc = net->wrap_apply(h, w.t2, N, w.t1, N, s, 1, st))) return rc;
+    launch_resjac(L0, 0.f, jw, 1, w.t1, N, v, N, z, N, s, nullptr, st);
+    return HELM_OK;
+}
+
+// one block of s right-hand sides
+int block_solve(helm_handle *h, BlockWork &w, int s, const float2 *b, double2 *x, int m, double tol, int maxit,
+                int prec, unet_net *net, helm_fgmres_stats *stats, hipStream_t st)
+{
+    const size_t N = w.N;
+    const int nblk = 256;
+    HELM_HIP_CHECK(hipMemsetAsync(x, 0, (size_t)s * N * sizeof(double2), st));
+    std::vector<double> bn(s), rel(s, 1.0), rp((size_t)s * nblk);
+    std::vector<int> t6(s, -1), t7(s, -1);
+    std::vector<double> e6(s, 0.0), e7(s, 0.0);
+    int its = 0, cycles = 0;
+    bool first = true;
+    for (;;) {
+        // R = B - A X in FP64, stored complex64 in slot 0, with its norms
+        launch_true_residual(h->kappa0, h->gamma0, h->n, h->omega, b, N, x, N, w.V, N, w.rpart, nblk, s, nullptr,
+                             st);
+        HELM_HIP_CHECK(hipMemcpyAsync(rp.data(), w.rpart, rp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HELM_HIP_CHECK(hipStreamSynchronize(st));
+        bool all = true;
+        for (int k = 0; k < s; ++k) {
+            double r2 = 0.0;
+            for (int q = 0; q < nblk; ++q) r2 += rp[(size_t)k * nblk + q];
+            if (first) bn[k] = std::sqrt(r2);
+            rel[k] = bn[k] > 0.0 ? std::sqrt(r2) / bn[k] : 0.0;
+            all = all && rel[k] <= tol;
+        }
+        first = false;
+        if (all || its >= maxit) break;
+        std::vector<cd> beta;
+        bool ok;
+        int rc = chol_qr2(w, w.V, s, beta, ok, st);
+        if (rc) return rc;
+        if (!ok) break;  // rank-deficient residual block
+        const int M1 = (m + 1) * s, MS = m * s;
+        std::vector<cd> Hb((size_t)M1 * MS, cd(0.0)), E((size_t)M1 * s, cd(0.0)), Y;
+        for (int i = 0; i < s; ++i)
+            for (int k = 0; k < s; ++k) E[i * s + k] = beta[i * s + k];
+        std::vector<double> est;
+        int kk = 0;
+        for (int j = 0; j < m; ++j) {
+            float2 *Vj = w.V + (size_t)j * s * N, *Zj = w.Z + (size_t)j * s * N, *W = w.V + (size_t)(j + 1) * s * N;
+            if ((rc = block_prec(h, w, prec, net, Vj, Zj, s, st))) return rc;
+            launch_apply(h->lv[0], 0.f, Zj, N, W, N, s, nullptr, st);
+            const int na = (j + 1) * s;
+            for (int pass = 0; pass < 2; ++pass) {
+                std::vector<cd> Cg;
+                if ((rc = gram(w, w.V, na, W, s, Cg, st))) return rc;
+                if ((rc = combine<0>(w, w.V, na, Cg, s, W, nullptr, st))) return rc;
+                for (int i = 0; i < na; ++i)
+                    for (int k = 0; k < s; ++k) Hb[(size_t)i * MS + j * s + k] += Cg[i * s + k];
+            }
+            std::vector<cd> Rn;
+            if ((rc = chol_qr2(w, W, s, Rn, ok, st))) return rc;
+            for (int i = 0; i < s; ++i)
+                for (int k = 0; k < s; ++k) Hb[(size_t)(na + i) * MS + j * s + k] = ok ? Rn[i * s + k] : cd(0.0);
+            ++its;
+            kk = j + 1;
+            // least squares over the first (j + 2) s rows and (j + 1) s columns
+            const int rows = (j + 2) * s, cols = (j + 1) * s;
+            std::vector<cd> Hs((size_t)rows * cols), Es((size_t)rows * s);
+            for (int r = 0; r < rows; ++r) {
+                for (int c = 0; c < cols; ++c) Hs[(size_t)r * cols + c] = Hb[(size_t)r * MS + c];
+                for (int k = 0; k < s; ++k) Es[(size_t)r * s + k] = E[(size_t)r * s + k];
+            }
+            block_lsq(Hs, Es, rows, cols, s, Y, est);
+            bool done = true;
+            for (int k = 0; k < s; ++k) {
+                const double e = bn[k] > 0.0 ? est[k] / bn[k] : 0.0;
+                if (t6[k] < 0 && e <= 1e-6) t6[k] = its, e6[k] = e;
+                if (t7[k] < 0 && e <= 1e-7) t7[k] = its, e7[k] = e;
+                done = done && e <= tol;
+            }
+            if (!ok || done || its >= maxit) break;
+        }
+        if ((rc = combine<2>(w, w.Z, kk * s, Y, s, nullptr, x, st))) return rc;
+        ++cycles;
+    }
+    for (int k = 0; k < s && stats; ++k) {
+        helm_fgmres_stats &o = stats[k];
+        o.iterations = its;
+        o.restarts = cycles;
+        o.converged = rel[k] <= tol;
+        o.fallback = 0;
+        o.true_relres = rel[k];
+        o.its_1e6 = t6[k] >= 0 ? t6[k] : its;
+        o.its_1e7 = t7[k] >= 0 ? t7[k] : its;
+        o.rho_1e6 = t6[k] > 0 ? std::pow(e6[k], 1.0 / t6[k]) : 0.0;
+        o.rho_1e7 = t7[k] > 0 ? std::pow(e7[k], 1.0 / t7[k]) : 0.0;
+    }
+    bool conv = true;
+    for (int k = 0; k < s; ++k) conv = conv && rel[k] <= tol;
+    return conv ? HELM_OK : HELM_NOT_CONVERGED;
+}
+
+}  // namespace
+
+}  // namespace helm
+
+using namespace helm;
+
+extern "C" int helm_block_fgmres_solve(helm_handle *h, int nrhs, const float *b, double *x, int block,
+                                       const helm_fgmres_opts *opts, helm_fgmres_stats *stats, void *stream)
+{
+    if (!h || nrhs < 0 || (nrhs > 0 && (!b || !x)) || block < 1 || block > BF_SMAX) {
+        set_error("helm_block_fgmres_solve: invalid argument (block size in [1, 16])");
+        return HELM_E_INVALID;
+    }
+    if (nrhs == 0) return HELM_OK;
+    int m = 10, maxit = 20000, prec = HELM_PREC_SL;
+    double tol = 1e-7;
+    unet_net *net = nullptr;
+    if (opts) {
+        m = opts->m;
+        tol = opts->tol;
+        maxit = opts->maxit;
+        prec = opts->prec;
+        net = (unet_net *)opts->net;
+    }
+    const int sb0 = std::min(block, nrhs);
+    if (m < 1 || (size_t)(m + 1) * sb0 * sb0 > 4096 || !(tol > 0.0) || maxit < 0) {
+        // the coefficients of one update, (m + 1) s x s complex doubles, sit in 64 KB of LDS
+        set_error("helm_block_fgmres_solve: m >= 1 with (m + 1) * block^2 <= 4096, tol > 0, maxit >= 0");
+        return HELM_E_INVALID;
+    }
+    if (prec != HELM_PREC_SL && prec != HELM_PREC_UNET_CGC && prec != HELM_PREC_UNET_DEFL) {
+        set_error("helm_block_fgmres_solve: unknown preconditioner");
+        return HELM_E_INVALID;
+    }
+    if (prec != HELM_PREC_SL &&
+        (!net || !net->cfg.head || h->n % (1 << net->cfg.levels) ||
+         (net->cfg.context && (!net->ctx_valid || !net->ctx_shared || net->ctx_H != h->n / 2)))) {
+        set_error("helm_block_fgmres_solve: the network preconditioners need opts->net with a head (an "
+                  "encoder-solver's solver holding this medium's context)");
+        return HELM_E_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int s = std::min(block, nrhs);
+    BlockWork w;
+    w.N = (size_t)h->n * h->n;
+    w.s = s;
+    w.m = m;
+    w.chunk = 8192;
+    w.nchunk = (int)((w.N + w.chunk - 1) / w.chunk);
+    const size_t nab = (size_t)(m + 1) * s;
+    if (dev_malloc(&w.V, nab * w.N * sizeof(float2)) != hipSuccess ||
+        dev_malloc(&w.Z, (size_t)m * s * w.N * sizeof(float2)) != hipSuccess ||
+        dev_malloc(&w.t1, (size_t)s * w.N * sizeof(float2)) != hipSuccess ||
+        dev_malloc(&w.t2, (size_t)s * w.N * sizeof(float2)) != hipSuccess ||
+        dev_malloc(&w.part, (size_t)w.nchunk * nab * s * sizeof(double2)) != hipSuccess ||
+        dev_malloc(&w.G, nab * s * sizeof(double2)) != hipSuccess ||
+        dev_malloc(&w.C, nab * s * sizeof(double2)) != hipSuccess ||
+        dev_malloc(&w.rpart, (size_t)s * 256 * sizeof(double)) != hipSuccess) {
+        set_error("helm_block_fgmres_solve: device allocation failed");
+        return HELM_E_NOMEM;
+    }
+    int status = HELM_OK;
+    const size_t N = w.N;
+    for (int b0 = 0; b0 < nrhs; b0 += s) {
+        const int sb = std::min(s, nrhs - b0);
+        int rc = block_solve(h, w, sb, (const float2 *)b + (size_t)b0 * N, (double2 *)x + (size_t)b0 * N, m, tol,
+                             maxit, prec, net, stats ? stats + b0 : nullptr, st);
+        if (rc < 0) return rc;
+        if (rc == HELM_NOT_CONVERGED) status = HELM_NOT_CONVERGED;
+    }
+    HELM_HIP_CHECK(hipGetLastError());
+    return status;
+}

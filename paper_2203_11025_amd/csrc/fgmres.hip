@@ -550,8 +550,9 @@ extern "C" int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int
     }
     int m = 20, maxit = 20000, prec = HELM_PREC_SL, graph = 0;
     double tol = 1e-7, stall = 0.0;
-    unet_net *net = nullptr;
+    unet_net *net = nullptr, *enc = nullptr;
     if (opts) {
+        enc = (unet_net *)opts->encoder;
         graph = opts->graph;
         m = opts->m;
         tol = opts->tol;
@@ -572,10 +573,17 @@ extern "C" int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int
         set_error("helm_fgmres_solve: the network preconditioners need opts->net");
         return HELM_E_INVALID;
     }
-    if (net && (!net->cfg.head || (net->cfg.context && (nprob != 1 || !net->ctx_valid || !net->ctx_shared)))) {
-        // a solver's context belongs to one medium: encode it first
+    if (enc && (!net || !net->cfg.context || prec == HELM_PREC_SL)) {
+        set_error("helm_fgmres_solve: opts->encoder goes with an encoder-solver's solver as opts->net");
+        return HELM_E_INVALID;
+    }
+    if (net && (!net->cfg.head ||
+                (net->cfg.context && !enc && (nprob != 1 || !net->ctx_valid || !net->ctx_shared)))) {
+        // a solver's context belongs to one medium: encode it first, or pass
+        // the encoder so that every problem's medium is encoded in turn
         set_error("helm_fgmres_solve: a network with a head is needed; an encoder-solver's solver takes "
-                  "one problem whose medium was encoded with unet_pair_encode (nb = 1)");
+                  "one problem whose medium was encoded with unet_pair_encode (nb = 1), or any number of "
+                  "problems with opts->encoder");
         return HELM_E_INVALID;
     }
     std::vector<int> offs(nprob + 1, 0);
@@ -585,7 +593,8 @@ extern "C" int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int
             return HELM_E_INVALID;
         }
         if (rhs_per_prob[p] > 0 && net &&
-            (probs[p]->n % (1 << net->cfg.levels) || (net->cfg.context && net->ctx_H != probs[p]->n / 2))) {
+            (probs[p]->n % (1 << net->cfg.levels) ||
+             (net->cfg.context && !enc && net->ctx_H != probs[p]->n / 2))) {
             set_error("helm_fgmres_solve: grid size not divisible by 2^levels of the network");
             return HELM_E_SHAPE;
         }
@@ -615,7 +624,18 @@ extern "C" int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int
     }
     const int T = (int)std::min<size_t>(8, groups.size());
     if (T <= 1 || net || prof_enabled()) {
-        for (int p = 0; p < nprob; ++p) {
+        // one after another (the network's workspace is shared); with an
+        // encoder, in order of grid size, so the network's workspaces and
+        // context buffers are resized once per size
+        std::vector<int> order(nprob);
+        for (int p = 0; p < nprob; ++p) order[p] = p;
+        if (enc)
+            std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return probs[a]->n < probs[c]->n; });
+        for (int p : order) {
+            if (enc && rhs_per_prob[p] > 0) {
+                int rce = unet_pair_encode_medium(enc, net, probs[p], s);
+                if (rce) return rce;
+            }
             run(p, s);
             if (rcs[p] < 0) return rcs[p];
         }

@@ -32,6 +32,7 @@ struct helm_handle {
     float2 *tw = nullptr, *tx = nullptr;
     double *tpart = nullptr;
     double2 *txt = nullptr;  // the k-step FGMRES iterate x~ (complex128)
+    float *kcoarse = nullptr;  // slowness at the coarse points, [n/2][n/2] (encoder input)
 };
 
 namespace helm {

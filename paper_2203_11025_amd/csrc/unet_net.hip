@@ -1031,6 +1031,23 @@ int unet_pair_encode(unet_net *enc, unet_net *sol, const float *kappa_c, int nb,
     return HELM_OK;
 }
 
+int unet_pair_encode_medium(unet_net *enc, unet_net *sol, helm_handle *h, void *stream)
+{
+    int rc = check_pair(enc, sol, "unet_pair_encode_medium");
+    if (rc) return rc;
+    if (!h || h->n % (1 << enc->cfg.levels)) {
+        set_error("unet_pair_encode_medium: invalid handle (n divisible by 2^levels)");
+        return HELM_E_INVALID;
+    }
+    const int nc = h->n / 2;
+    if (!h->kcoarse && dev_malloc(&h->kcoarse, (size_t)nc * nc * sizeof(float)) != hipSuccess) {
+        set_error("unet_pair_encode_medium: out of device memory");
+        return HELM_E_NOMEM;
+    }
+    if ((rc = helm_coarse_slowness(h, h->kcoarse, stream))) return rc;
+    return unet_pair_encode(enc, sol, h->kcoarse, 1, nc, stream);
+}
+
 int unet_pair_loss_grad(unet_net *enc, unet_net *sol, const unet_batch *batch, double *loss_out,
                         float *enc_grads, float *sol_grads, void *stream)
 {

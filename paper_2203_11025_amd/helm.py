@@ -27,6 +27,7 @@ EXPORTS = [
     "helm_profile_read", "helm_profile_stop", "helm_profile_sample", "helm_autotune", "helm_autotune_entries", "helm_autotune_force", "helm_training_triples", "helm_coarse_slowness",
     "helm_sl_vcycle_noalloc", "helm_sl_vcycle_noalloc_bytes", "helm_sl_vcycle_noalloc_max_bytes",
     "helm_training_triples_seeded", "helm_set_allocator", "helm_allocated_bytes", "helm_triples_mix",
+    "helm_block_fgmres_solve",
 ]
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -44,7 +45,8 @@ class _Opts(C.Structure):
 
 class FgmresOpts(C.Structure):
     _fields_ = [("m", C.c_int), ("tol", C.c_double), ("maxit", C.c_int), ("prec", C.c_int),
-                ("net", C.c_void_p), ("stall_ratio", C.c_double), ("graph", C.c_int)]
+                ("net", C.c_void_p), ("stall_ratio", C.c_double), ("graph", C.c_int),
+                ("encoder", C.c_void_p)]
 
 
 class FgmresStats(C.Structure):
@@ -89,6 +91,9 @@ def lib():
                                         C.POINTER(vp), C.POINTER(FgmresOpts),
                                         C.POINTER(FgmresStats), vp]
         L.helm_fgmres_solve.restype = ip
+        L.helm_block_fgmres_solve.argtypes = [vp, ip, vp, vp, ip, C.POINTER(FgmresOpts), C.POINTER(FgmresStats),
+                                              vp]
+        L.helm_block_fgmres_solve.restype = ip
         L.helm_last_error.argtypes = []
         L.helm_last_error.restype = C.c_char_p
         L.helm_training_triples.argtypes = [vp, vp, vp, vp, ip, vp]
@@ -255,10 +260,12 @@ class Handle:
 
 
 def fgmres_solve(problems, rhs, m=20, tol=1e-7, maxit=20000, prec="sl", net=None,
-                 stall_ratio=0.0, xs=None, stream=None, graph=False):
+                 stall_ratio=0.0, xs=None, stream=None, graph=False, encoder=None):
     """Solve A x = b for every right-hand side of every problem.
 
     problems: list of Handle; rhs: list of complex64 tensors [nrhs_p, n_p, n_p].
+    encoder: with an encoder-solver `net`, the encoder that encodes every
+    problem's medium before its solve (any number of media per call).
     Returns (list of complex128 solutions, list of per-RHS stat dicts, status).
     """
     nprob = len(problems)
@@ -274,10 +281,27 @@ def fgmres_solve(problems, rhs, m=20, tol=1e-7, maxit=20000, prec="sl", net=None
     total = sum(b.shape[0] for b in rhs)
     stats = (FgmresStats * max(total, 1))()
     opts = FgmresOpts(m, tol, maxit, PREC[prec] if isinstance(prec, str) else int(prec),
-                      C.c_void_p(net.ptr.value if net is not None else 0), stall_ratio, int(graph))
+                      C.c_void_p(net.ptr.value if net is not None else 0), stall_ratio, int(graph),
+                      C.c_void_p(encoder.ptr.value if encoder is not None else 0))
     rc = _check(lib().helm_fgmres_solve(probs, nprob, counts, bp, xp, C.byref(opts), stats,
                                         _stream(stream)), "helm_fgmres_solve")
     return xs, [stats[i].as_dict() for i in range(total)], rc
+
+
+def block_fgmres_solve(problem, b, block=10, m=10, tol=1e-7, maxit=20000, prec="sl", net=None, x=None,
+                       stream=None):
+    """Block FGMRES(m) on one problem, blocks of `block` right-hand sides
+    (helm_block_fgmres_solve).  Returns (complex128 solution, stats, status)."""
+    b = problem._batch(b, "b")
+    x = torch.empty(b.shape, dtype=torch.complex128, device=b.device) if x is None else x
+    nrhs = b.shape[0]
+    stats = (FgmresStats * max(nrhs, 1))()
+    opts = FgmresOpts(m, tol, maxit, PREC[prec] if isinstance(prec, str) else int(prec),
+                      C.c_void_p(net.ptr.value if net is not None else 0), 0.0, 0, C.c_void_p(0))
+    rc = _check(lib().helm_block_fgmres_solve(problem.ptr, nrhs, _dev(b, torch.complex64, "b"),
+                                              _dev(x, torch.complex128, "x"), int(block), C.byref(opts), stats,
+                                              _stream(stream)), "helm_block_fgmres_solve")
+    return x, [stats[i].as_dict() for i in range(nrhs)], rc
 
 
 def profile_start(*families, every=1):

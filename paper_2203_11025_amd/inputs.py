@@ -30,6 +30,7 @@ __all__ = [
     "point_sources",
     "complex_gaussian",
     "config_problem",
+    "config_problems",
 ]
 
 
@@ -173,3 +174,34 @@ def config_problem(name: str) -> dict:
         raise ValueError(f"unknown workload {name!r}")
     return dict(n=n, kappa=kappa, gamma=sponge_gamma(n), omega=omega_for_ppw(n),
                 b=b, levels=levels, m=m, tol=1e-7, sigma=sigma)
+
+
+def config_problems(name: str, count: int | None = None) -> list:
+    """The uneven batch: a list of problems (dicts as config_problem gives).
+
+    uneven24 : 24 layered media (3-8 seeded horizontal layers, slowness in
+               [0.25, 1] with a +/-10% smooth perturbation, seed 100 + k) of
+               sizes drawn from {256, 512, 1024, 2048} (seed 4), 8 point
+               sources each (seed 200 + k), omega for 10 points per
+               wavelength, the levels rule of the other workloads (coarsest
+               64^2), FGMRES(20) to 1e-7.  `count` keeps the first count media.
+    uneven6  : six layered media, one of each size 256^2..2048^2 and two more
+               (256^2, 512^2), 8 sources each, the same recipe.
+    """
+    if name == "uneven24":
+        sizes = [int(v) for v in np.random.default_rng(4).choice([256, 512, 1024, 2048], size=24)]
+    elif name == "uneven6":
+        sizes = [256, 512, 1024, 2048, 256, 512]
+    else:
+        raise ValueError(f"unknown workload {name!r}")
+    if count is not None:
+        sizes = sizes[:count]
+    out = []
+    for k, n in enumerate(sizes):
+        levels = 1
+        while (n >> (levels - 1)) > 64:
+            levels += 1
+        out.append(dict(n=n, kappa=layered_medium(n, seed=100 + k), gamma=sponge_gamma(n),
+                        omega=omega_for_ppw(n), b=point_sources(n, 8, seed=200 + k), levels=levels, m=20,
+                        tol=1e-7, sigma=None))
+    return out

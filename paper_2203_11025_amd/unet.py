@@ -11,7 +11,8 @@ from .helm import HelmError, _check, _dev, _stream, lib as _helm_lib
 EXPORTS = ["unet_create", "unet_destroy", "unet_num_params", "unet_num_buffers", "unet_init",
            "unet_set_params", "unet_get_params", "unet_forward", "unet_infer",
            "unet_loss_grad", "unet_train_step", "unet_pair_encode", "unet_pair_loss_grad",
-           "unet_pair_train_step", "unet_save", "unet_load", "unet_set_cursor", "unet_get_cursor"]
+           "unet_pair_train_step", "unet_save", "unet_load", "unet_set_cursor", "unet_get_cursor",
+           "unet_pair_encode_medium"]
 
 
 class Cfg(C.Structure):
@@ -67,6 +68,8 @@ def lib():
         L.unet_pair_train_step.argtypes = [vp, vp, C.POINTER(Batch), C.POINTER(TrainOpts),
                                            C.POINTER(C.c_double), vp]
         L.unet_pair_train_step.restype = ip
+        L.unet_pair_encode_medium.argtypes = [vp, vp, vp, vp]
+        L.unet_pair_encode_medium.restype = ip
         L.unet_save.argtypes = [vp, C.c_char_p, vp]
         L.unet_save.restype = ip
         L.unet_load.argtypes = [vp, C.c_char_p, vp]
@@ -203,6 +206,12 @@ def pair_encode(encoder, solver, kappa_c, stream=None):
         k = k[None]
     _check(lib().unet_pair_encode(encoder.ptr, solver.ptr, _dev(k, torch.float32, "kappa_c"),
                                   k.shape[0], k.shape[-1], _stream(stream)), "unet_pair_encode")
+
+
+def pair_encode_medium(encoder, solver, handle, stream=None):
+    """Encode the medium of a helm Handle (its coarse slowness) into the solver."""
+    _check(lib().unet_pair_encode_medium(encoder.ptr, solver.ptr, handle.ptr, _stream(stream)),
+           "unet_pair_encode_medium")
 
 
 def pair_loss_grad(encoder, solver, r, e, kappa_c, stream=None):

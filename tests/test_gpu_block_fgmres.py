@@ -1,0 +1,103 @@
+"""Block FGMRES (section 4: block restarted FGMRES(10), block size 10) on the
+GPU against the oracle's block FGMRES and the exact solution, through the C
+ABI."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import block_fgmres as BF
+from paper_2203_11025_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_2203_11025_amd import helm, unet
+
+    assert torch.cuda.is_available()
+    unet.lib()
+    return helm, unet
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _problem(helm, n, seed, levels):
+    kap = inputs.smooth_medium(n, max(2.0, n / 16), seed=seed)
+    gam = inputs.sponge_gamma(n, width=min(16, n // 8))
+    om = inputs.omega_for_ppw(n)
+    h = helm.Handle(torch.from_numpy(kap).cuda(), torch.from_numpy(gam).cuda(), om, levels=levels)
+    return kap, gam, om, h
+
+
+@pytest.mark.parametrize("n,levels,nrhs,block,m", [(128, 3, 7, 3, 10), (64, 2, 10, 10, 10), (96, 2, 4, 4, 6)])
+def test_block_fgmres_matches_the_exact_solution_and_the_oracle(H, oracle, n, levels, nrhs, block, m):
+    """Blocks of 3 + 3 + 1, one block of 10, and a 96^2 grid: every field
+    reaches the FP64 tolerance, the solution matches the exact solution of
+    the discrete system to 1e-5, and the block iteration counts are the
+    oracle's within 10% (R23)."""
+    helm, _ = H
+    kap, gam, om, h = _problem(helm, n, n + nrhs, levels)
+    b = inputs.point_sources(n, nrhs, seed=5, margin=min(16, n // 8)).astype(np.complex64)
+    x, st, rc = helm.block_fgmres_solve(h, torch.from_numpy(b).cuda(), block=block, m=m, tol=1e-7)
+    assert rc == 0 and all(s["converged"] and s["true_relres"] <= 1e-7 for s in st)
+    x = x.cpu().numpy()
+    solve = oracle.direct_solver(kap, gam, om)
+    ho = oracle.Hierarchy(kap, gam, om, levels)
+    for b0 in range(0, nrhs, block):
+        blk = b[b0:b0 + block]
+        xo, so = BF.block_fgmres(ho, blk.astype(complex), m=m, tol=1e-7)
+        its = st[b0]["iterations"]
+        assert abs(its - so["iterations"]) <= max(2, 0.1 * so["iterations"]), (b0, its, so["iterations"])
+        for k in range(blk.shape[0]):
+            ref = solve(blk[k])
+            assert rel(x[b0 + k], ref) <= 1e-5, (b0 + k, rel(x[b0 + k], ref))
+
+
+def test_block_of_one_is_fgmres(H):
+    """Block size 1 runs the same method as helm_fgmres_solve (another
+    orthogonalisation and stop bookkeeping): same iterations within 10%,
+    same solution to 1e-5."""
+    helm, _ = H
+    n = 128
+    kap, gam, om, h = _problem(helm, n, 9, 3)
+    b = torch.from_numpy(inputs.point_sources(n, 2, seed=6)).cuda()
+    xb, sb, rcb = helm.block_fgmres_solve(h, b, block=1, m=10, tol=1e-7)
+    xs, ss, rcs = helm.fgmres_solve([h], [b], m=10, tol=1e-7)
+    assert rcb == 0 and rcs == 0
+    for k in range(2):
+        assert abs(sb[k]["iterations"] - ss[k]["iterations"]) <= max(2, 0.1 * ss[k]["iterations"])
+        assert rel(xb.cpu().numpy()[k], xs[0].cpu().numpy()[k]) <= 1e-5
+
+
+def test_block_fgmres_with_network_preconditioners(H, oracle):
+    """M_VU and M_CU inside block FGMRES with a seeded network: both converge
+    to the FP64 tolerance and to the exact solution."""
+    helm, unet = H
+    n = 64
+    kap, gam, om, h = _problem(helm, n, 12, 2)
+    net = unet.UNet(widths=(32, 64))
+    net.init(4)
+    b = inputs.point_sources(n, 4, seed=8, margin=8).astype(np.complex64)
+    solve = oracle.direct_solver(kap, gam, om)
+    for prec in ("unet_defl", "unet_cgc"):
+        x, st, rc = helm.block_fgmres_solve(h, torch.from_numpy(b).cuda(), block=4, m=10, tol=1e-7, prec=prec,
+                                            net=net, maxit=500)
+        assert rc == 0 and all(s["true_relres"] <= 1e-7 for s in st), prec
+        x = x.cpu().numpy()
+        for k in range(4):
+            assert rel(x[k], solve(b[k])) <= 1e-5, (prec, k)
+
+
+def test_block_fgmres_argument_checks(H):
+    helm, _ = H
+    kap, gam, om, h = _problem(helm, 64, 3, 2)
+    b = torch.zeros((2, 64, 64), dtype=torch.complex64, device="cuda")
+    with pytest.raises(helm.HelmError, match="block size"):
+        helm.block_fgmres_solve(h, b, block=17)
+    with pytest.raises(helm.HelmError, match="4096"):
+        helm.block_fgmres_solve(h, b, block=2, m=1100)
+    x, st, rc = helm.block_fgmres_solve(h, b, block=2)
+    assert rc == 0 and np.count_nonzero(x.cpu().numpy()) == 0
