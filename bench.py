@@ -46,8 +46,11 @@ def parse():
     ap.add_argument("--workload", default="multi1024")
     ap.add_argument("--prec", default="unet_defl", choices=["unet_defl", "unet_cgc"])
     ap.add_argument("--retrain", type=int, default=200, help="mini-retraining Adam steps")
-    ap.add_argument("--retrain-lr", type=float, default=1e-4,
-                    help="mini-retraining learning rate (the pretraining ended at 1e-4)")
+    ap.add_argument("--retrain-lr", type=float, default=1e-3,
+                    help="mini-retraining learning rate")
+    ap.add_argument("--retrain-k", default="random",
+                    help="FGMRES steps k of the retraining triples (eq. 3.8): an int, or 'random' for "
+                         "k drawn from 1..10 per sample")
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--stall-ratio", type=float, default=0.0,
                     help="fall back to M_V on stalls (0 = never; the uneven-batch setting uses 0.95)")
@@ -188,7 +191,8 @@ def main():
     # mini-retraining on the medium (section 3.4), timed on its own
     sync()
     t0 = time.perf_counter()
-    losses = train.train_pair(enc, sol, [h], steps=a.retrain, batch=16, lr=a.retrain_lr, seed=11)
+    rk = a.retrain_k if a.retrain_k == "random" else int(a.retrain_k)
+    losses = train.train_pair(enc, sol, [h], steps=a.retrain, batch=16, lr=a.retrain_lr, seed=11, ksteps=rk)
     sync()
     t_retrain = time.perf_counter() - t0
     if losses:
@@ -301,7 +305,7 @@ def main():
                         f"{a.prec} with the encoder-solver pair; SL = V(1,1) {h.levels} levels",
             "n": P["n"], "nrhs": nrhs, "prec": a.prec,
             "network": "pretrained" if pretrained else "seeded init",
-            "retrain_steps": a.retrain, "retrain_lr": a.retrain_lr, "graph": graph, "autotune": not a.no_autotune,
+            "retrain_steps": a.retrain, "retrain_lr": a.retrain_lr, "retrain_k": a.retrain_k, "graph": graph, "autotune": not a.no_autotune,
         },
         "unet_sl": {"s_per_rhs": value, "iterations_mean": float(np.mean(its_net)),
                     "iterations_max": int(max(its_net)), "true_relres_max": relres_net,
