@@ -46,6 +46,21 @@ typedef struct {
                        convolution and of its first up convolution           */
     int head;       /* 1: 1x1 head; 0: encoder (in_ch 1, context 0) whose
                        outputs are the per-level contexts                    */
+    int arch;       /* 0: the network above (default).  1: the paper's own
+                       network (section 3.1, eq. 3.1-3.3) on the FINE grid:
+                       in_ch 4 = (Re r^, Im r^, kappa^2, gamma), levels L
+                       below the fine grid with widths c_1..c_L (any >= 1);
+                       level l: x = elu(BN(R_l x)) with R_l a 5x5 stride-2
+                       convolution, then ResNet blocks x = elu(BN(x + K2
+                       elu(BN(K1 x)))) with 3x3 K1, K2 (one per level, three
+                       at level L); up: y = cat(BN(P elu(y)), x^(l)) with P a
+                       5x5 stride-2 transposed convolution (padding 2, output
+                       padding 1); output e = P_1 elu(y^(1)) (2 channels, with
+                       a bias).  Parameters per layer in that order: weight
+                       (convolution [cout][cin][5|3][5|3], transposed
+                       [cin][cout][5][5]), BN weight and bias (the output
+                       layer: its bias); buffers: BN running mean and variance
+                       per layer.  FP32 throughout; head 1, context 0.        */
 } unet_cfg;
 
 /* Create a network with zero parameters (set them with unet_set_params). */
@@ -72,6 +87,7 @@ int unet_get_params(unet_net *net, float *params, float *buffers, void *stream);
 /*
  * unet_forward -- plain network application.
  *   x   : device float [B][in_ch][H][W]; H, W divisible by 2^(levels-1)
+ *         (arch 1: H = W divisible by 2^levels)
  *   out : device float [B][out_ch][H][W]
  *   training = 0: BN with running statistics; 1: batch statistics (the
  *   running statistics are not updated).
@@ -86,6 +102,8 @@ int unet_forward(unet_net *net, const float *x, int B, int H, int W, float *out,
  *   |R(h^2 r)|,  kappa_c the slowness injected at the coarse points.
  * R, P: full-weighting restriction and bilinear prolongation (eq. 2.9); the
  * h^2 scaling follows section 3.4; s makes the map positively homogeneous.
+ * arch 1 (the paper's network, whose transfers are learned):
+ *   e = s Net(h^2 r / s, kappa^2, gamma) on the fine grid, s = RMS of |h^2 r|.
  * An all-zero residual gives e = 0.
  *   r, e : complex64 [nrhs][n][n]; must not overlap.
  */
@@ -98,6 +116,11 @@ typedef struct {
     const float *r;       /* complex64 [nb][n][n] residuals                      */
     const float *e;       /* complex64 [nb][n][n] errors (A e = r)               */
     const float *kappa_c; /* float [nb][n/2][n/2] coarse slowness                */
+    /* arch 1 only (the paper's network reads the fine medium): slowness and
+       attenuation, float [nb][n][n], or [n][n] shared by the batch when
+       fine_shared is 1; NULL for arch 0 */
+    const float *kappa_f, *gamma_f;
+    int fine_shared;
 } unet_batch;
 
 typedef struct {
@@ -174,7 +197,7 @@ int unet_pair_train_step(unet_net *encoder, unet_net *solver, const unet_batch *
  * with Adam) and the training-data cursor (the seed and the next sample index
  * of helm_training_triples_seeded).  The file is a host file at `path`
  * (written to path + ".tmp", then renamed): the 8-byte tag "HELMUNT1", int32
- * in_ch, out_ch, levels, widths[6] (0 past levels), context, head; int64
+ * in_ch, out_ch, levels, widths[6] (0 past levels), context, head, arch; int64
  * num_params, num_buffers; int32 Adam step; uint64 data seed, next sample
  * index; FP32 parameters, buffers, first moments, second moments, all
  * little-endian.  unet_load requires a network of the same configuration

@@ -548,8 +548,11 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
 // buffers: while the MFMAs read one stage, the next stage's copy is in
 // flight into the other buffer, and no registers stage it.  Slots are
 // XOR-swizzled so fragment reads spread over all banks: halo piece (pixel p,
-// 8-channel segment s) sits in slot 4 p + (s ^ ((p / 4) % 4)), weight piece
-// (channel c, tap t, segment s) in slot 4 (9 c + t) + (s ^ ((c / 4) % 4)).
+// 8-channel segment s) sits in slot 4 p + (s ^ ((p / 2) % 4)), weight piece
+// (channel c, tap t, segment s) in slot 4 (9 c + t) + (s ^ ((c / 2) % 4)): any
+// 8 consecutive lanes of one segment (the lanes a 16-byte LDS read serves
+// together) hit distinct 16-byte bank groups (no bank-conflict cycles in the
+// counters).
 // Pieces outside the image, the source's channels or Cout read as zero.
 // RW: the weights change per stage (more than one 32-channel chunk).
 typedef __attribute__((address_space(3))) void lds_void;
@@ -676,7 +679,7 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
             const int blk = k * NWV + wv, q = blk * 64 + lane;
             int off;
             if (k < HIN) {
-                const int pix = q >> 2, seg = (q & 3) ^ ((pix >> 2) & 3);
+                const int pix = q >> 2, seg = (q & 3) ^ ((pix >> 1) & 3);
                 const int hy = pix / HX, y = y0 + hy, x = x0 + pix - hy * HX;
                 const bool ok = real && !upc && q < HSL && coff + seg * 8 < Cs && y >= 0 && y < H && x >= 0 &&
                                 x < W;
@@ -746,7 +749,7 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
                             for (int z = 0; z < 8; ++z) e[z] = (bf16)(wy[p][0] * h0.v[z] + wy[p][1] * h1.v[z]);
                         }
                         const int pix = (2 * k + p) * HX + 2 * m + q;
-                        lds_st16(hb + pix * 4 + (seg ^ ((pix >> 2) & 3)), o);
+                        lds_st16(hb + pix * 4 + (seg ^ ((pix >> 1) & 3)), o);
                     }
                 }
             }
@@ -761,7 +764,7 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
 #pragma unroll
         for (int k = 0; k < WIN; ++k) {
             const int blk = k * NWV + wv, q = blk * 64 + lane;
-            const int co = q / 36, r = q - co * 36, tap = r >> 2, seg = (r & 3) ^ ((co >> 2) & 3);
+            const int co = q / 36, r = q - co * 36, tap = r >> 2, seg = (r & 3) ^ ((co >> 1) & 3);
             woff[k] = real && q < WSL ? ((co * 9 + tap) * wst + seg * 8) * 2 : BUF_NONE;
             dma16(wr, wbuf + blk * 64, woff[k]);
         }
@@ -798,7 +801,7 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
 #pragma unroll
             for (int r = 0; r < WMF + 2; ++r) {
                 const int p = (wrow + r) * HX + (lane & 15) + kx;
-                a[r] = *reinterpret_cast<const lbf16x8 *>(hbuf + p * 4 + (seg ^ ((p >> 2) & 3)));
+                a[r] = *reinterpret_cast<const lbf16x8 *>(hbuf + p * 4 + (seg ^ ((p >> 1) & 3)));
             }
 #pragma unroll
             for (int ky = 0; ky < 3; ++ky) {
@@ -811,7 +814,7 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
                         bw[nf] = wreg[tap][nf];
                     else
                         bw[nf] = *reinterpret_cast<const lbf16x8 *>(wbuf + (co * 9 + tap) * 4 +
-                                                                    (seg ^ ((co >> 2) & 3)));
+                                                                    (seg ^ ((co >> 1) & 3)));
                 }
 #pragma unroll
                 for (int mf = 0; mf < WMF; ++mf)
@@ -837,7 +840,7 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
 #pragma unroll
             for (int nf = 0; nf < NF; ++nf) {
                 const int co = nf * 16 + (lane & 15);
-                wreg[tap][nf] = *reinterpret_cast<const lbf16x8 *>(wA + (co * 9 + tap) * 4 + (seg ^ ((co >> 2) & 3)));
+                wreg[tap][nf] = *reinterpret_cast<const lbf16x8 *>(wA + (co * 9 + tap) * 4 + (seg ^ ((co >> 1) & 3)));
             }
     } else if (!RW) {
         issue_w(wB, 0, true);  // one chunk: both weight buffers hold it for the whole kernel

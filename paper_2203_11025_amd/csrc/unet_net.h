@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "../../include/unet.h"
+#include "paper_net.h"
 #include "unet_internal.h"
 
 struct helm_handle;
@@ -33,6 +34,11 @@ struct unet_net {
     float *P = nullptr, *G = nullptr, *M = nullptr, *V = nullptr, *BUF = nullptr;
     float *scale = nullptr, *shift = nullptr;  // folded inference BN
     int step = 0;
+    // arch 1: the paper's network (owns its workspace; P, G, M, V and BUF
+    // above are shared with it) and the loss of its last batch
+    helm::PaperNet *pn = nullptr;
+    double pn_loss = 0.0;
+    int init_paper(const unet_cfg &c);
     // training-data cursor saved with the state: the seed of the sample
     // generator and the index of the next sample to draw
     uint64_t data_seed = 0, data_next = 0;

@@ -82,6 +82,7 @@ void unet_net::free_ws()
 
 unet_net::~unet_net()
 {
+    delete pn;
     free_ws();
     for (auto p : ctxbuf) dev_free(p);
     for (auto p : cmap) dev_free(p);
@@ -100,6 +101,25 @@ unet_net::~unet_net()
     dev_free(BUF);
     dev_free(scale);
     dev_free(shift);
+}
+
+int unet_net::init_paper(const unet_cfg &c)
+{
+    cfg = c;
+    pn = new PaperNet();
+    pn->build(c.widths, c.levels, c.in_ch, c.out_ch, 3);
+    nparams = pn->nparams;
+    nbuf = pn->nbuf;
+    int rc;
+    if ((rc = dalloc(&P, nparams)) || (rc = dalloc(&G, nparams)) || (rc = dalloc(&M, nparams)) ||
+        (rc = dalloc(&V, nparams)) || (rc = dalloc(&BUF, nbuf)))
+        return rc;
+    pn->P = P;
+    pn->G = G;
+    pn->M = M;
+    pn->V = V;
+    pn->BUF = BUF;
+    return pn->alloc_params();
 }
 
 int unet_net::init(const unet_cfg &c)
@@ -561,6 +581,10 @@ void unet_net::adam_update(const unet_train_opts &o, double count, hipStream_t s
 
 void unet_net::repack(hipStream_t st)
 {
+    if (pn) {  // FP32 weights are used as they are; fold the inference BN
+        pn->refold(st);
+        return;
+    }
     if (cmap_valid) {  // the context maps hold the previous weights
         cmap_valid = 0;
         ++gen;  // captured graphs that add the maps are stale
@@ -585,6 +609,16 @@ int unet_net::wrap_apply(helm_handle *h, const float2 *r, size_t rs, float2 *e, 
     if (nnet < 0) {
         nnet = nb;
         idx = pos = nullptr;
+    }
+    if (pn) {  // the paper's network on the fine grid
+        if (nnet > 0) {
+            int rc = pn->ensure_ws(nnet, n, false);
+            if (rc) return rc;
+            pn->input(r, rs, nnet, n, h->kappa0, h->gamma0, 0, idx, fscale, st);
+            pn->forward(nnet, false, st);
+        }
+        pn->output(nb, n, e, es, accumulate, mask, pos, st);
+        return HELM_OK;
     }
     if (nnet > 0) {
         int rc = ensure_ws(nnet, nc, nc, false);
@@ -645,6 +679,28 @@ int unet_create(const unet_cfg *cfg, unet_net **out)
         return HELM_E_INVALID;
     }
     *out = nullptr;
+    if (cfg->arch == 1) {
+        bool ok = cfg->levels >= 1 && cfg->levels <= 6 && cfg->in_ch == 4 && cfg->out_ch == 2 && cfg->head == 1 &&
+                  cfg->context == 0;
+        for (int l = 0; ok && l < cfg->levels; ++l) ok = cfg->widths[l] >= 1 && cfg->widths[l] <= 512;
+        if (!ok) {
+            set_error("unet_create: the paper's network (arch 1) takes levels 1..6, widths in [1, 512], in_ch 4, "
+                      "out_ch 2, head 1, context 0");
+            return HELM_E_INVALID;
+        }
+        auto *net = new unet_net();
+        int rc = net->init_paper(*cfg);
+        if (rc) {
+            delete net;
+            return rc;
+        }
+        *out = net;
+        return HELM_OK;
+    }
+    if (cfg->arch != 0) {
+        set_error("unet_create: arch must be 0 or 1");
+        return HELM_E_INVALID;
+    }
     if (cfg->levels < 1 || cfg->levels > 6 || cfg->in_ch < 1 || cfg->in_ch > 32 ||
         (cfg->head && cfg->out_ch != 2) || (!cfg->head && cfg->context)) {
         set_error("unet_create: unsupported configuration (levels 1..6, in_ch 1..32, out_ch 2 with a "
@@ -687,6 +743,12 @@ int unet_set_params(unet_net *net, const float *params, const float *buffers, vo
             std::fill(b.begin() + l.rm_off, b.begin() + l.rm_off + l.cout, 0.f);
             std::fill(b.begin() + l.rv_off, b.begin() + l.rv_off + l.cout, 1.f);
         }
+        if (net->pn)
+            for (const auto &l : net->pn->layers)
+                if (l.kind != PL_OUT) {
+                    std::fill(b.begin() + l.rm_off, b.begin() + l.rm_off + l.co, 0.f);
+                    std::fill(b.begin() + l.rv_off, b.begin() + l.rv_off + l.co, 1.f);
+                }
         HELM_HIP_CHECK(hipMemcpyAsync(net->BUF, b.data(), net->nbuf * 4, hipMemcpyHostToDevice, st));
         HELM_HIP_CHECK(hipStreamSynchronize(st));
     }
@@ -700,14 +762,14 @@ int unet_set_params(unet_net *net, const float *params, const float *buffers, vo
 
 // ---------------------------------------------------------------- state files
 // Layout (little-endian): the 8-byte tag "HELMUNT1", then int32 in_ch,
-// out_ch, levels, widths[6], context, head; int64 nparams, nbuf; int32 Adam
+// out_ch, levels, widths[6], context, head, arch; int64 nparams, nbuf; int32 Adam
 // step; uint64 data seed, next sample index; then FP32 arrays: parameters
 // [nparams], BN buffers [nbuf], Adam first moments [nparams], second moments
 // [nparams].
 static const char STATE_TAG[8] = {'H', 'E', 'L', 'M', 'U', 'N', 'T', '1'};
 
 struct StateHead {
-    int32_t cfg[11];
+    int32_t cfg[12];
     int64_t np, nb;
     int32_t step;
     uint64_t seed, next;
@@ -716,9 +778,9 @@ struct StateHead {
 static void state_head(const unet_net *net, StateHead &h)
 {
     const unet_cfg &c = net->cfg;
-    int32_t v[11] = {c.in_ch, c.out_ch, c.levels, 0, 0, 0, 0, 0, 0, c.context, c.head};
+    int32_t v[12] = {c.in_ch, c.out_ch, c.levels, 0, 0, 0, 0, 0, 0, c.context, c.head, c.arch};
     for (int l = 0; l < 6; ++l) v[3 + l] = l < c.levels ? c.widths[l] : 0;
-    std::copy(v, v + 11, h.cfg);
+    std::copy(v, v + 12, h.cfg);
     h.np = (int64_t)net->nparams;
     h.nb = (int64_t)net->nbuf;
     h.step = net->step;
@@ -780,7 +842,7 @@ int unet_load(unet_net *net, const char *path, void *stream)
     bool ok = read_all(f, tag, 8) && std::equal(tag, tag + 8, STATE_TAG) && read_all(f, h.cfg, sizeof h.cfg) &&
               read_all(f, &h.np, 8) && read_all(f, &h.nb, 8) && read_all(f, &h.step, 4) &&
               read_all(f, &h.seed, 8) && read_all(f, &h.next, 8);
-    if (!ok || !std::equal(h.cfg, h.cfg + 11, mine.cfg) || h.np != mine.np || h.nb != mine.nb || h.step < 0) {
+    if (!ok || !std::equal(h.cfg, h.cfg + 12, mine.cfg) || h.np != mine.np || h.nb != mine.nb || h.step < 0) {
         fclose(f);
         set_error(std::string("unet_load: ") + path + " is not a state file of a network of this configuration");
         return HELM_E_INVALID;
@@ -855,12 +917,25 @@ int unet_init(unet_net *net, unsigned long long seed, void *stream)
     std::vector<float> p(net->nparams, 0.f);
     uint64_t st = seed * 0x2545F4914F6CDD1Dull + 1;
     const double gain2 = 2.0 / (1.0 + SLOPE * SLOPE);  // LeakyReLU(0.2) gain squared
+    if (net->pn) {
+        // the paper's network: normal weights with std sqrt(2 / fan-in) (fan-in
+        // cin K^2, a quarter of it for the stride-2 transposed convolutions),
+        // BN weight 1, biases 0
+        for (const auto &l : net->pn->layers) {
+            const bool tr = l.kind == PL_UP || l.kind == PL_OUT;
+            const double fan = (double)l.ci * l.K * l.K / (tr ? 4.0 : 1.0);
+            const double sd = std::sqrt(2.0 / fan);
+            for (size_t i = 0; i < (size_t)l.ci * l.co * l.K * l.K; ++i) p[l.w_off + i] = (float)(sd * normal01(st));
+            if (l.kind != PL_OUT)
+                for (int c = 0; c < l.co; ++c) p[l.g_off + c] = 1.f;
+        }
+    }
     for (auto &l : net->L) {
         const double sd = std::sqrt(gain2 / (9.0 * l.cin_real));
         for (size_t i = 0; i < (size_t)l.cout * l.cin_real * 9; ++i) p[l.w_off + i] = (float)(sd * normal01(st));
         for (int c = 0; c < l.cout; ++c) p[l.g_off + c] = 1.f;
     }
-    if (net->cfg.head) {
+    if (net->cfg.head && !net->pn) {
         const double sd = std::sqrt(1.0 / net->cfg.widths[0]);
         for (size_t i = 0; i < (size_t)net->cfg.out_ch * net->cfg.widths[0]; ++i)
             p[net->head_w + i] = (float)(sd * normal01(st));
@@ -910,6 +985,22 @@ int unet_forward(unet_net *net, const float *x, int B, int H, int W, float *out,
         return HELM_E_SHAPE;
     }
     hipStream_t st = (hipStream_t)stream;
+    if (net->pn) {
+        if (H != W || H % (1 << net->cfg.levels)) {
+            set_error("unet_forward: the paper's network needs H = W divisible by 2^levels");
+            return HELM_E_SHAPE;
+        }
+        int rc = net->pn->ensure_ws(B, H, training != 0);
+        if (rc) return rc;
+        const size_t N = (size_t)H * W;
+        HELM_HIP_CHECK(hipMemcpyAsync(net->pn->T[net->pn->x0t].v, x, (size_t)B * 4 * N * sizeof(float),
+                                      hipMemcpyDeviceToDevice, st));
+        net->pn->forward(B, training != 0, st);
+        HELM_HIP_CHECK(hipMemcpyAsync(out, net->pn->T[net->pn->outt].v, (size_t)B * 2 * N * sizeof(float),
+                                      hipMemcpyDeviceToDevice, st));
+        HELM_HIP_CHECK(hipGetLastError());
+        return HELM_OK;
+    }
     if (!net->cfg.head) {
         set_error("unet_forward: an encoder has no head output (use unet_pair_encode)");
         return HELM_E_INVALID;
@@ -956,6 +1047,24 @@ int unet_infer(unet_net *net, helm_handle *h, const float *r, float *e, int nrhs
 int unet_loss_grad(unet_net *net, const unet_batch *batch, double *loss_out, float *grads,
                    void *stream)
 {
+    if (net && net->pn) {
+        if (!batch || !batch->r || !batch->e || !batch->kappa_f || !batch->gamma_f || batch->nb < 1 ||
+            batch->n % (1 << net->cfg.levels)) {
+            set_error("unet_loss_grad: the paper's network needs r, e, kappa_f, gamma_f and n divisible by "
+                      "2^levels");
+            return HELM_E_INVALID;
+        }
+        hipStream_t st = (hipStream_t)stream;
+        const size_t N = (size_t)batch->n * batch->n;
+        int rc = net->pn->loss_grad((const float2 *)batch->r, (const float2 *)batch->e, batch->kappa_f,
+                                    batch->gamma_f, batch->fine_shared ? 0 : N, batch->nb, batch->n, &net->pn_loss,
+                                    st);
+        if (rc) return rc;
+        if (grads) HELM_HIP_CHECK(hipMemcpyAsync(grads, net->G, net->nparams * 4, hipMemcpyDeviceToDevice, st));
+        if (loss_out) *loss_out = net->pn_loss;
+        HELM_HIP_CHECK(hipGetLastError());
+        return HELM_OK;
+    }
     if (!net || !batch || !batch->r || !batch->e || !batch->kappa_c || batch->nb < 1) {
         set_error("unet_loss_grad: invalid argument");
         return HELM_E_INVALID;
@@ -989,6 +1098,13 @@ int unet_train_step(unet_net *net, const unet_batch *batch, const unet_train_opt
     hipStream_t st = (hipStream_t)stream;
     int rc = unet_loss_grad(net, batch, nullptr, nullptr, stream);
     if (rc) return rc;
+    if (net->pn) {
+        net->pn->update_running(batch->nb, st);  // the statistics of this batch, before the refold
+        net->adam_update(o, 0.0, st);
+        if (loss_out) *loss_out = net->pn_loss;
+        HELM_HIP_CHECK(hipGetLastError());
+        return HELM_OK;
+    }
     net->adam_update(o, (double)batch->nb * (batch->n / 2) * (batch->n / 2), st);
     if (loss_out) {
         HELM_HIP_CHECK(hipMemcpyAsync(loss_out, net->dloss, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1000,8 +1116,8 @@ int unet_train_step(unet_net *net, const unet_batch *batch, const unet_train_opt
 
 static int check_pair(const unet_net *enc, const unet_net *sol, const char *who)
 {
-    if (!enc || !sol || enc->cfg.head || enc->cfg.in_ch != 1 || !sol->cfg.context || !sol->cfg.head ||
-        enc->cfg.levels != sol->cfg.levels) {
+    if (!enc || !sol || enc->pn || sol->pn || enc->cfg.head || enc->cfg.in_ch != 1 || !sol->cfg.context ||
+        !sol->cfg.head || enc->cfg.levels != sol->cfg.levels) {
         set_error(std::string(who) + ": needs an encoder (head 0, in_ch 1) and a solver (context 1) "
                                      "with the same levels");
         return HELM_E_INVALID;

@@ -105,6 +105,8 @@ class Batches:
             b += c
         if self.augment:
             self._mix(seed, pos0, med)
+        # the batch's one medium (None when it mixes media)
+        self.medium = med[0] if all(m == med[0] for m in med) else None
         return self.r, self.e, self.kc
 
     def _mix(self, seed, pos0, med):
@@ -148,7 +150,7 @@ def _run(step_fn, net, handles, steps, batch, lr, seed, per_medium, log, time_bu
         r, e, kc = data.fill(seed, pos)
         pos += data.batch
         net.set_cursor(seed, pos)
-        losses.append(step_fn(r, e, kc, lr_))
+        losses.append(step_fn(r, e, kc, lr_, data))
 
     if schedule is None:
         for step in range(steps):
@@ -189,7 +191,7 @@ def train_pair(encoder, solver, handles, steps, batch=16, lr=1e-3, seed=0, per_m
     Returns the list of losses."""
     from .unet import pair_train_step
 
-    def step_fn(r, e, kc, lr_):
+    def step_fn(r, e, kc, lr_, data):
         return pair_train_step(encoder, solver, r, e, kc, lr=lr_)
 
     return _run(step_fn, solver, handles, steps, batch, lr, seed, per_medium, log, time_budget, resume,
@@ -202,7 +204,13 @@ def train(net, handles, steps, batch=16, lr=1e-3, seed=0, per_medium=None, log=N
     size).  Returns the list of losses; stops early when `time_budget`
     seconds have elapsed."""
 
-    def step_fn(r, e, kc, lr_):
+    def step_fn(r, e, kc, lr_, data):
+        if getattr(net, "arch", 0) == 1:
+            # the paper's network reads the fine medium: one medium per batch
+            if data.medium is None:
+                raise ValueError("the paper's network trains on batches of one medium (per_medium >= batch)")
+            h = handles[data.medium]
+            return net.train_step(r, e, kc, lr=lr_, kappa_f=h._keep[0], gamma_f=h._keep[1])
         return net.train_step(r, e, kc, lr=lr_)
 
     return _run(step_fn, net, handles, steps, batch, lr, seed, per_medium, log, time_budget, resume,

@@ -17,12 +17,13 @@ EXPORTS = ["unet_create", "unet_destroy", "unet_num_params", "unet_num_buffers",
 
 class Cfg(C.Structure):
     _fields_ = [("in_ch", C.c_int), ("out_ch", C.c_int), ("levels", C.c_int),
-                ("widths", C.c_int * 6), ("context", C.c_int), ("head", C.c_int)]
+                ("widths", C.c_int * 6), ("context", C.c_int), ("head", C.c_int), ("arch", C.c_int)]
 
 
 class Batch(C.Structure):
     _fields_ = [("nb", C.c_int), ("n", C.c_int), ("r", C.c_void_p), ("e", C.c_void_p),
-                ("kappa_c", C.c_void_p)]
+                ("kappa_c", C.c_void_p), ("kappa_f", C.c_void_p), ("gamma_f", C.c_void_p),
+                ("fine_shared", C.c_int)]
 
 
 class TrainOpts(C.Structure):
@@ -86,11 +87,16 @@ class UNet:
     """context=True: the solver of an encoder-solver pair; head=False: an
     encoder (in_ch 1), whose per-level outputs are the solver's contexts."""
 
-    def __init__(self, widths=(32, 64, 128, 256), in_ch=3, out_ch=2, context=False, head=True):
+    def __init__(self, widths=(32, 64, 128, 256), in_ch=3, out_ch=2, context=False, head=True, arch=0):
+        """arch=1: the paper's own network (section 3.1) on the fine grid,
+        widths c_1..c_L of its levels below the fine grid."""
         if not head:
             in_ch = 1
+        if arch == 1:
+            in_ch = 4
         cfg = Cfg(in_ch, out_ch, len(widths), (C.c_int * 6)(*list(widths) + [0] * (6 - len(widths))),
-                  int(context), int(head))
+                  int(context), int(head), int(arch))
+        self.arch = int(arch)
         h = C.c_void_p()
         _check(lib().unet_create(C.byref(cfg), C.byref(h)), "unet_create")
         self._h = h
@@ -175,22 +181,27 @@ class UNet:
         return e
 
     @staticmethod
-    def _batch(r, e, kappa_c):
+    def _batch(r, e, kappa_c, kappa_f=None, gamma_f=None):
+        """kappa_f / gamma_f: the fine medium for the paper's network, [n, n]
+        (shared by the batch) or [nb, n, n]."""
         nb, n = r.shape[0], r.shape[-1]
-        bt = Batch(nb, n, _dev(r, torch.complex64, "r"), _dev(e, torch.complex64, "e"),
-                   _dev(kappa_c, torch.float32, "kappa_c"))
-        return bt
+        kc = C.c_void_p(0) if kappa_c is None else _dev(kappa_c, torch.float32, "kappa_c")
+        kf = C.c_void_p(0) if kappa_f is None else _dev(kappa_f, torch.float32, "kappa_f")
+        gf = C.c_void_p(0) if gamma_f is None else _dev(gamma_f, torch.float32, "gamma_f")
+        shared = int(kappa_f is not None and kappa_f.dim() == 2)
+        return Batch(nb, n, _dev(r, torch.complex64, "r"), _dev(e, torch.complex64, "e"), kc, kf, gf, shared)
 
-    def loss_grad(self, r, e, kappa_c, stream=None):
-        bt = self._batch(r, e, kappa_c)
+    def loss_grad(self, r, e, kappa_c, stream=None, kappa_f=None, gamma_f=None):
+        bt = self._batch(r, e, kappa_c, kappa_f, gamma_f)
         g = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
         loss = C.c_double()
         _check(lib().unet_loss_grad(self._h, C.byref(bt), C.byref(loss), _dev(g, torch.float32, "g"),
                                     _stream(stream)), "unet_loss_grad")
         return loss.value, g
 
-    def train_step(self, r, e, kappa_c, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
-        bt = self._batch(r, e, kappa_c)
+    def train_step(self, r, e, kappa_c, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None, kappa_f=None,
+                   gamma_f=None):
+        bt = self._batch(r, e, kappa_c, kappa_f, gamma_f)
         o = TrainOpts(lr, beta1, beta2, eps)
         loss = C.c_double()
         _check(lib().unet_train_step(self._h, C.byref(bt), C.byref(o), C.byref(loss),
