@@ -9,7 +9,8 @@ SL V(1,1) with 5 levels (coarsest 64^2 solved exactly).  The learned
 preconditioner is the encoder-solver pair used as deflation beside the SL
 V-cycle (M_VU, eq. 3.4 with the context of eq. 3.5), starting from the
 pretrained weights when they are present (else seeded initial weights), after
-200 mini-retraining Adam steps on triples of this medium (batch 16).
+200 mini-retraining Adam steps on triples of this medium (batch 16, k of
+eq. 3.8 drawn from 1..10 FGMRES steps per sample, lr 1e-3).
 
 One timed step = the encoder pass on the medium plus the complete batched
 solve of all right-hand sides, inputs resident in HBM.  The plain-SL solve of
@@ -131,10 +132,21 @@ def cpu_baseline(P, enc, sol, prec, gpu_iterations, budget_s):
     t0 = time.perf_counter()
     H.fgmres(b, m=P["m"], tol=1e-30, maxit=k, prec=f)
     dt = time.perf_counter() - t0
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": dt / k * gpu_iterations,
         "unit": "s/RHS",
         "cores": torch.get_num_threads(),
+        "cpu_model": model,
+        "host_cpus": os.cpu_count(),
         "kind": "oracle",
         "sample": f"first {k} FGMRES({P['m']}) iterations of the same {P['n']}^2 {prec} solve of one "
                   f"right-hand side ({dt:.1f} s; FP64 C sweeps on one core, FP32 PyTorch CPU network "
