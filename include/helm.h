@@ -269,6 +269,24 @@ int helm_training_triples_seeded(helm_handle *h, unsigned long long seed, unsign
                                  int ksteps, float *x, float *r, float *e, int nrhs, void *stream);
 
 /*
+ * helm_training_triples_batch -- a batch of seeded training triples, each
+ * sample with its own index and its own number of FGMRES steps (section 3.4
+ * draws k from 1..10 per sample; eq. 3.8).  Sample b draws x from (seed,
+ * index[b]) exactly as helm_training_triples_seeded draws sample index[b],
+ * and takes ksteps[b] steps of one FGMRES(max(max_b ksteps[b], 10)) with M_V
+ * from zero on b = A x that advances all samples together (sample b leaves
+ * after its k steps); x~, r = b - A x~ and e = x - x~ as there (k = 1 too
+ * goes through FGMRES here, not through the closed form).
+ *   index  : host array of nrhs sample indices;
+ *   ksteps : host array of nrhs step counts, each in [1, 30];
+ *   x, r, e: as for helm_training_triples_seeded.
+ * Uses the handle's triple and FGMRES workspaces, synchronises `stream`;
+ * calls on one handle must not overlap.
+ */
+int helm_training_triples_batch(helm_handle *h, unsigned long long seed, const unsigned long long *index,
+                                const int *ksteps, float *x, float *r, float *e, int nrhs, void *stream);
+
+/*
  * helm_triples_mix -- augmentation by linear combinations of triples
  * (section 3.4): for nin triples (r_j, e_j) of ONE medium (A e_j = r_j),
  *   r'_b = sum_j c[b][j] r_j,   e'_b = sum_j c[b][j] e_j,   b < nout,

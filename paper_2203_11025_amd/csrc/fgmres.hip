@@ -41,6 +41,8 @@ struct FgWork {
     int *h_fb = nullptr;      // pinned: fallback flags
     int *h_a = nullptr;       // pinned: active flags read inside a restart cycle
     int *h_net = nullptr;     // pinned: network batch [idx | pos]
+    int *h_mx = nullptr;      // pinned: per right-hand side iteration limits
+    int *d_mx = nullptr;      // device copy of h_mx (in the state block)
     int *d_net = nullptr;     // device copy of h_net
     float2 *t1 = nullptr, *t2 = nullptr;  // network-preconditioner scratch
     FgState S{};
@@ -154,6 +156,7 @@ void work_free(FgWork *w)
     for (auto &g : w->graphs) hipGraphExecDestroy(g.exec);
     if (w->cap) hipStreamDestroy(w->cap);
     if (w->h_net) hipHostFree(w->h_net);
+    if (w->h_mx) hipHostFree(w->h_mx);
     if (w->h_fb) hipHostFree(w->h_fb);
     if (w->h_a) hipHostFree(w->h_a);
     if (w->h_i) hipHostFree(w->h_i);
@@ -187,7 +190,7 @@ int work_ensure(helm_handle *h, int nb, int m, bool scratch, FgWork **out)
     }
     // state: ints, then doubles, then double2s, each section 256-byte aligned
     auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    size_t ni = 10 * (size_t)nb, nd = 7 * (size_t)nb + (size_t)nb * m;
+    size_t ni = 11 * (size_t)nb, nd = 7 * (size_t)nb + (size_t)nb * m;
     size_t nz = (size_t)nb * ((m + 1) * m + (m + 1) + m + 3 * MAXV);
     size_t off_d = align(ni * sizeof(int)), off_z = align(off_d + nd * sizeof(double));
     size_t bytes = off_z + nz * sizeof(double2);
@@ -211,6 +214,8 @@ int work_ensure(helm_handle *h, int nb, int m, bool scratch, FgWork **out)
     S.mask_sl = S.mask_net + nb;
     S.t6 = S.mask_sl + nb;
     S.t7 = S.t6 + nb;
+    w->d_mx = S.t7 + nb;
+    S.maxit_rhs = nullptr;
     S.bnorm = (double *)(p + off_d);
     S.beta = S.bnorm + nb;
     S.relres = S.beta + nb;
@@ -242,6 +247,7 @@ int work_ensure(helm_handle *h, int nb, int m, bool scratch, FgWork **out)
         return HELM_E_NOMEM;
     }
     if (hipHostMalloc((void **)&w->h_net, 2 * nb * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void **)&w->h_mx, nb * sizeof(int)) != hipSuccess ||
         hipHostMalloc((void **)&w->h_fb, nb * sizeof(int)) != hipSuccess ||
         hipHostMalloc((void **)&w->h_a, nb * sizeof(int)) != hipSuccess ||
         hipHostMalloc((void **)&w->h_i, nb * sizeof(int)) != hipSuccess ||
@@ -359,7 +365,7 @@ constexpr int NET_SEG = 2;
 // One problem (medium) with nb right-hand sides.
 int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, double tol,
                   int maxit, int prec, unet_net *net, double stall_ratio,
-                  helm_fgmres_stats *stats, hipStream_t s, bool use_graph)
+                  helm_fgmres_stats *stats, hipStream_t s, bool use_graph, const int *maxit_rhs = nullptr)
 {
     FgWork *w = nullptr;
     const bool use_net = prec != HELM_PREC_SL;
@@ -369,6 +375,12 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
     S.tol = tol;
     S.maxit = maxit;
     S.stall_ratio = use_net ? stall_ratio : 0.0;
+    if (maxit_rhs) {  // per right-hand side limits (never captured: the graph key holds maxit only)
+        use_graph = false;
+        for (int i = 0; i < nb; ++i) w->h_mx[i] = maxit_rhs[i];
+        HELM_HIP_CHECK(hipMemcpyAsync(w->d_mx, w->h_mx, nb * sizeof(int), hipMemcpyHostToDevice, s));
+        S.maxit_rhs = w->d_mx;
+    }
     const size_t N = w->N;
     const int nblk = krylov_nblk(N, nb);
     const size_t vsb = (size_t)(m + 1) * N, zsb = (size_t)m * N;
@@ -433,7 +445,7 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
         HELM_HIP_CHECK(hipStreamSynchronize(s));
         int nact = 0;
         for (int i = 0; i < nb; ++i) {
-            if (!done[i] && (w->h_d[i] <= tol || w->h_its[i] >= maxit)) done[i] = 1;
+            if (!done[i] && (w->h_d[i] <= tol || w->h_its[i] >= (maxit_rhs ? maxit_rhs[i] : maxit))) done[i] = 1;
             w->h_i[i] = done[i] ? 0 : 1;
             nact += w->h_i[i];
         }
@@ -522,9 +534,10 @@ int solve_problem(helm_handle *h, int nb, const float2 *b, double2 *x, int m, do
 }  // namespace
 
 int fgmres_one(helm_handle *h, int nb, const float2 *b, double2 *x, int m, double tol, int maxit, int prec,
-               unet_net *net, double stall_ratio, helm_fgmres_stats *stats, hipStream_t s, bool use_graph)
+               unet_net *net, double stall_ratio, helm_fgmres_stats *stats, hipStream_t s, bool use_graph,
+               const int *maxit_rhs)
 {
-    return solve_problem(h, nb, b, x, m, tol, maxit, prec, net, stall_ratio, stats, s, use_graph);
+    return solve_problem(h, nb, b, x, m, tol, maxit, prec, net, stall_ratio, stats, s, use_graph, maxit_rhs);
 }
 
 void fgmres_free(helm_handle *h)

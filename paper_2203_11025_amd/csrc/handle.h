@@ -61,7 +61,9 @@ int vcycle(helm_handle *h, const float2 *f, size_t fs, float2 *v, size_t vs, int
            const int *active, hipStream_t s, const double *scale = nullptr, int accumulate = 0);
 void fgmres_free(helm_handle *h);
 // FGMRES(m) of one problem with nb right-hand sides (fgmres.hip); x is
-// complex128 [nb][n][n] and starts from zero.
+// complex128 [nb][n][n] and starts from zero.  maxit_rhs (host, nb ints, or
+// null): an iteration limit per right-hand side in place of maxit.
 int fgmres_one(helm_handle *h, int nb, const float2 *b, double2 *x, int m, double tol, int maxit, int prec,
-               unet_net *net, double stall_ratio, helm_fgmres_stats *stats, hipStream_t s, bool use_graph);
+               unet_net *net, double stall_ratio, helm_fgmres_stats *stats, hipStream_t s, bool use_graph,
+               const int *maxit_rhs = nullptr);
 }  // namespace helm

@@ -130,6 +130,7 @@ struct FgState {
     double2 *y;   // [nb][MAXV]
     double tol;
     int maxit;
+    const int *maxit_rhs;  // per right-hand side iteration limits (device), or null: maxit for all
 };
 
 // Workgroups per right-hand side of the Krylov reductions for nb

@@ -307,7 +307,8 @@ __global__ __launch_bounds__(1024) void k_arnoldi_reduce(FgState S,
             }
         }
         S.scale[b] = hn > 0.0 ? 1.0 / hn : 0.0;
-        if (nu == 0.0 || hn == 0.0 || res <= S.tol * S.bnorm[b] || its >= S.maxit || j + 1 >= m)
+        const int lim = S.maxit_rhs ? S.maxit_rhs[b] : S.maxit;
+        if (nu == 0.0 || hn == 0.0 || res <= S.tol * S.bnorm[b] || its >= lim || j + 1 >= m)
             S.active[b] = 0;
     }
     __syncthreads();

@@ -238,6 +238,26 @@ int triples_k(helm_handle *h, const float2 *xx, float2 *rr, float2 *ee, int nrhs
     return HELM_OK;
 }
 
+// triples_k with one k per sample: one batched FGMRES(max(k, 10)) whose
+// right-hand side b stops after its own k_b steps (no restart for k <= 10).
+int triples_ks(helm_handle *h, const float2 *xx, float2 *rr, float2 *ee, int nrhs, const int *ks, hipStream_t s)
+{
+    const size_t N = (size_t)h->n * h->n;
+    int kmax = 1;
+    for (int b = 0; b < nrhs; ++b) kmax = std::max(kmax, ks[b]);
+    launch_apply(h->lv[0], 0.f, xx, N, h->tw, N, nrhs, nullptr, s);  // b into the workspace
+    int rc = fgmres_one(h, nrhs, h->tw, h->txt, std::max(kmax, 10), 1e-300, kmax, HELM_PREC_SL, nullptr, 0.0,
+                        nullptr, s, false, ks);
+    if (rc < 0) return rc;
+    const int nblk = 256;
+    launch_true_residual(h->kappa0, h->gamma0, h->n, h->omega, h->tw, N, h->txt, N, rr, N, h->tpart, nblk,
+                         nrhs, nullptr, s);
+    const int gx = (int)std::min<size_t>(4096, ((size_t)nrhs * N + 255) / 256);
+    hipLaunchKernelGGL(k_err_from_iterate, dim3(gx), dim3(256), 0, s, xx, h->txt, (size_t)nrhs * N, ee);
+    HELM_HIP_CHECK(hipGetLastError());
+    return HELM_OK;
+}
+
 int triple_nblk(const helm_handle *h)
 {
     const size_t N = (size_t)h->n * h->n;
@@ -278,6 +298,29 @@ extern "C" int helm_training_triples_seeded(helm_handle *h, unsigned long long s
                        xx);
     if (ksteps == 1) return triples(h, xx, (float2 *)r, (float2 *)e, nrhs, s);
     return triples_k(h, xx, (float2 *)r, (float2 *)e, nrhs, ksteps, s);
+}
+
+extern "C" int helm_training_triples_batch(helm_handle *h, unsigned long long seed,
+                                           const unsigned long long *index, const int *ksteps, float *x, float *r,
+                                           float *e, int nrhs, void *stream)
+{
+    bool ok = h && nrhs >= 0 && (nrhs == 0 || (index && ksteps && r && e));
+    for (int b = 0; ok && b < nrhs; ++b) ok = ksteps[b] >= 1 && ksteps[b] <= MAXM;
+    if (!ok) {
+        set_error("helm_training_triples_batch: invalid argument (index and ksteps arrays, each k in [1, 30])");
+        return HELM_E_INVALID;
+    }
+    if (nrhs == 0) return HELM_OK;
+    int rc = ensure_triple_ws(h, nrhs, triple_nblk(h));
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t N = (size_t)h->n * h->n;
+    float2 *xx = x ? (float2 *)x : h->tx;
+    const int gx = (int)std::min<size_t>(1024, (N + 255) / 256);
+    for (int b = 0; b < nrhs; ++b)
+        hipLaunchKernelGGL(k_philox_normals, dim3(gx, 1), dim3(256), 0, s, (uint64_t)seed, (uint64_t)index[b], N,
+                           xx + (size_t)b * N);
+    return triples_ks(h, xx, (float2 *)r, (float2 *)e, nrhs, ksteps, s);
 }
 
 extern "C" int helm_triples_mix(const float *r, const float *e, int nin, long long npts, const float *coef,

@@ -27,7 +27,7 @@ EXPORTS = [
     "helm_profile_read", "helm_profile_stop", "helm_profile_sample", "helm_autotune", "helm_autotune_entries", "helm_autotune_force", "helm_training_triples", "helm_coarse_slowness",
     "helm_sl_vcycle_noalloc", "helm_sl_vcycle_noalloc_bytes", "helm_sl_vcycle_noalloc_max_bytes",
     "helm_training_triples_seeded", "helm_set_allocator", "helm_allocated_bytes", "helm_triples_mix",
-    "helm_block_fgmres_solve",
+    "helm_block_fgmres_solve", "helm_training_triples_batch",
 ]
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -102,6 +102,8 @@ def lib():
         L.helm_triples_mix.argtypes = [vp, vp, ip, C.c_longlong, vp, ip, vp, vp, vp]
         L.helm_triples_mix.restype = ip
         L.helm_training_triples_seeded.restype = ip
+        L.helm_training_triples_batch.argtypes = [vp, C.c_ulonglong, vp, vp, vp, vp, vp, ip, vp]
+        L.helm_training_triples_batch.restype = ip
         L.helm_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
         L.helm_set_allocator.restype = ip
         L.helm_allocated_bytes.argtypes = []
@@ -224,6 +226,24 @@ class Handle:
                                                   _dev(r, torch.complex64, "r"),
                                                   _dev(e, torch.complex64, "e"), r.shape[0],
                                                   _stream(stream)), "helm_training_triples_seeded")
+        return r, e
+
+    def training_triples_batch(self, seed, index, ksteps, r, e, x=None, stream=None):
+        """Triples of the samples with the given indices, sample b with
+        ksteps[b] FGMRES(M_V) steps, all advanced together
+        (helm_training_triples_batch), written into the given complex64
+        [nrhs, n, n] views r and e (and x if given)."""
+        r = self._batch(r, "r")
+        e = self._batch(e, "e")
+        nb = r.shape[0]
+        if len(index) != nb or len(ksteps) != nb:
+            raise HelmError("one index and one k per sample are required")
+        idx = (C.c_ulonglong * max(nb, 1))(*[int(i) for i in index])
+        ks = (C.c_int * max(nb, 1))(*[int(k) for k in ksteps])
+        xp = C.c_void_p(0) if x is None else _dev(self._batch(x, "x"), torch.complex64, "x")
+        _check(lib().helm_training_triples_batch(self._h, int(seed), idx, ks, xp, _dev(r, torch.complex64, "r"),
+                                                 _dev(e, torch.complex64, "e"), nb, _stream(stream)),
+               "helm_training_triples_batch")
         return r, e
 
     def coarse_slowness(self, out=None, stream=None):

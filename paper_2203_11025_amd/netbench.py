@@ -1,8 +1,8 @@
 """Timing of one part of the solve in isolation, for profiling under
 rocprofv3 (kernel trace or counters):
 
-    python -m paper_2203_11025_amd.netbench [--mode net|sl] [--workload multi1024]
-        [--nrhs 32] [--reps 10] [--autotune] [--copy-probe MIB]
+    python -m paper_2203_11025_amd.netbench [--mode net|sl|uneven|retrain] [--workload multi1024]
+        [--nrhs 32] [--reps 10] [--autotune] [--graph] [--copy-probe MIB]
 
 --mode net: one application is unet_infer on nrhs residuals (restriction,
 scaling, the encoder-solver's solver network with the encoder's shared
@@ -10,6 +10,16 @@ context maps, prolongation), the network application of M_VU (eq. 3.4).
 --mode sl: one application is one FGMRES(20) cycle (maxit 20) with the SL
 V-cycle on nrhs point sources: 20 V-cycles, 20 operator applications and 20
 Arnoldi steps, the x update and the true residual.
+--mode retrain: reps mini-retraining steps of the encoder-solver pair on
+the medium (batch 16, k of eq. 3.8 drawn from 1..10 per sample, lr 1e-3:
+the benchmark's retraining), after one untimed step; prints the split of a
+step between the triples and the Adam step.
+--mode uneven: the uneven batch (--workload uneven24 or uneven6: many
+layered media of 256^2..2048^2, 8 point sources each) solved in one
+helm_fgmres_solve call, first with the encoder-solver M_VU (each medium
+encoded in turn, plain-SL fallback at a residual ratio of 0.95, --graph for
+replayed restart cycles), then with plain SL (problems run concurrently);
+reps timed solves of each.
 The inputs are seeded.  --copy-probe first copies a buffer of that many MiB
 once (a plain copy kernel of known size, to scale HBM counters by).  Prints
 one JSON line: milliseconds per application (and, for the network, the
@@ -34,7 +44,8 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
-    ap.add_argument("--mode", default="net", choices=["net", "sl"])
+    ap.add_argument("--mode", default="net", choices=["net", "sl", "uneven", "retrain"])
+    ap.add_argument("--graph", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     a = ap.parse_args(argv)
 
@@ -49,6 +60,10 @@ def main(argv=None):
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.mode == "uneven":
+        return uneven(a)
+    if a.mode == "retrain":
+        return retrain(a)
     P = inputs.config_problem(a.workload)
     h = helm.Handle(torch.from_numpy(P["kappa"]).cuda(), torch.from_numpy(P["gamma"]).cuda(), P["omega"],
                     levels=P["levels"])
@@ -93,6 +108,87 @@ def main(argv=None):
                       "ms_per_application": dt * 1e3, "conv_ms_per_application": ms / a.reps,
                       "conv_launches": launches, "conv_tflops": work / (ms * 1e-3) / 1e12 if ms else None,
                       "autotune": a.autotune}))
+    return 0
+
+
+def retrain(a):
+    import torch
+
+    from . import helm, inputs, train, unet
+
+    P = inputs.config_problem(a.workload)
+    h = helm.Handle(torch.from_numpy(P["kappa"]).cuda(), torch.from_numpy(P["gamma"]).cuda(), P["omega"],
+                    levels=P["levels"])
+    helm.autotune(1 if a.autotune else 0)
+    enc, sol = unet.UNet(head=False), unet.UNet(context=True)
+    if os.path.exists(a.weights):
+        unet.load(a.weights, encoder=enc, solver=sol)
+    else:
+        enc.init(1)
+        sol.init(2)
+    data = train.Batches([h], 16, ksteps="random")
+    r, e, kc = data.fill(11, 0)
+    unet.pair_train_step(enc, sol, r, e, kc, lr=1e-3)
+    torch.cuda.synchronize()
+    t_data = t_step = 0.0
+    for i in range(a.reps):
+        t0 = time.perf_counter()
+        r, e, kc = data.fill(11, 16 * (i + 1))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss = unet.pair_train_step(enc, sol, r, e, kc, lr=1e-3)
+        torch.cuda.synchronize()
+        t_data += t1 - t0
+        t_step += time.perf_counter() - t1
+        print(f"[netbench] retrain step {i} loss {loss:.3e}", file=sys.stderr, flush=True)
+    print(json.dumps({"mode": "retrain", "workload": a.workload, "batch": 16, "reps": a.reps,
+                      "ms_per_step": (t_data + t_step) * 1e3 / a.reps, "ms_triples": t_data * 1e3 / a.reps,
+                      "ms_adam_step": t_step * 1e3 / a.reps, "autotune": a.autotune}))
+    return 0
+
+
+def uneven(a):
+    import numpy as np
+    import torch
+
+    from . import helm, inputs, unet
+
+    P = inputs.config_problems(a.workload)
+    hs = [helm.Handle(torch.from_numpy(p["kappa"]).cuda(), torch.from_numpy(p["gamma"]).cuda(), p["omega"],
+                      levels=p["levels"]) for p in P]
+    bs = [torch.from_numpy(p["b"]).cuda() for p in P]
+    xs = [torch.empty(b.shape, dtype=torch.complex128, device="cuda") for b in bs]
+    enc, sol = unet.UNet(head=False), unet.UNet(context=True)
+    if os.path.exists(a.weights):
+        unet.load(a.weights, encoder=enc, solver=sol)
+    else:
+        enc.init(1)
+        sol.init(2)
+    helm.autotune(1 if a.autotune else 0)
+    nrhs = sum(b.shape[0] for b in bs)
+    out = {"mode": "uneven", "workload": a.workload, "media": len(P), "sizes": [p["n"] for p in P], "nrhs": nrhs,
+           "reps": a.reps, "graph": a.graph, "autotune": a.autotune}
+    for name, kw in (("unet_sl", dict(prec="unet_defl", net=sol, encoder=enc, stall_ratio=0.95, graph=a.graph)),
+                     ("plain_sl", dict(prec="sl", graph=a.graph))):
+        _, st, rc = helm.fgmres_solve(hs, bs, m=20, tol=1e-7, xs=xs, **kw)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(a.reps):
+            _, st, rc = helm.fgmres_solve(hs, bs, m=20, tol=1e-7, xs=xs, **kw)
+            torch.cuda.synchronize()
+            print(f"[netbench] {name} solve {i} rc {rc}", file=sys.stderr, flush=True)
+        dt = (time.perf_counter() - t0) / a.reps
+        its, off, per = [s["iterations"] for s in st], 0, []
+        for p, b in zip(P, bs):
+            k = b.shape[0]
+            per.append({"n": p["n"], "its_mean": float(np.mean(its[off:off + k])),
+                        "fallbacks": int(sum(s["fallback"] for s in st[off:off + k]))})
+            off += k
+        out[name] = {"s_per_solve": dt, "s_per_rhs": dt / nrhs, "status": rc,
+                     "iterations_mean": float(np.mean(its)),
+                     "true_relres_max": float(max(s["true_relres"] for s in st)),
+                     "fallbacks": int(sum(s["fallback"] for s in st)), "per_medium": per}
+    print(json.dumps(out))
     return 0
 
 

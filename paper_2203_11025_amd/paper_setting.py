@@ -15,7 +15,8 @@ and M_VU (eq. 3.4) are compared by the convergence factor of eq. 4.1
 network by its relative error ||e_net - e|| / ||e|| on held-out triples.
 
     python -m paper_2203_11025_amd.paper_setting [--medium homogeneous|smooth]
-        [--epochs 100] [--dataset 1000] [--rhs 10] [--out results.json]
+        [--epochs 100] [--dataset 1000] [--rhs 10] [--arch 0|1] [--block 10]
+        [--out results.json]
 
 The paper reports, for the homogeneous medium, a final relative training
 error of 0.18 and rho_VU = 0.231, rho_JU = 0.313 against 0.88 for M_V; those
@@ -70,17 +71,25 @@ def relative_error(net, h, seed, count, ksteps="random"):
     return float(np.mean(errs))
 
 
-def solve_all(h, net, rhs, m=10, tol=1e-7, maxit=2000):
-    """FGMRES(m) with M_V, M_JU and M_VU on the same right-hand sides; per
-    preconditioner the mean iterations to a 1e6 reduction and the mean
-    convergence factor of eq. 4.1 at that reduction."""
+def solve_all(h, net, rhs, m=10, tol=1e-7, maxit=2000, block=0):
+    """FGMRES(m) with M_V, M_JU and M_VU on the same right-hand sides (block
+    FGMRES(m) with blocks of `block` right-hand sides when block > 0, as in
+    section 4); per preconditioner the mean iterations to a 1e6 reduction and
+    the mean convergence factor of eq. 4.1 at that reduction."""
+    import torch
+
     from . import helm
 
     out = {}
     for name, prec in (("V", "sl"), ("JU", "unet_cgc"), ("VU", "unet_defl")):
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, st, rc = helm.fgmres_solve([h], [rhs], m=m, tol=tol, maxit=maxit, prec=prec,
-                                      net=None if prec == "sl" else net)
+        pnet = None if prec == "sl" else net
+        if block > 0:
+            _, st, rc = helm.block_fgmres_solve(h, rhs, block=block, m=m, tol=tol, maxit=maxit, prec=prec, net=pnet)
+        else:
+            _, st, rc = helm.fgmres_solve([h], [rhs], m=m, tol=tol, maxit=maxit, prec=prec, net=pnet)
+        torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[name] = dict(rho=float(np.mean([s["rho_1e6"] for s in st])),
                          its_1e6=float(np.mean([s["its_1e6"] for s in st])),
@@ -91,19 +100,24 @@ def solve_all(h, net, rhs, m=10, tol=1e-7, maxit=2000):
 
 
 def run(kind="homogeneous", epochs=100, dataset=1000, lr0=1e-3, batch0=20, t0=48, rhs=10, seed=1,
-        widths=(32, 64, 128, 256), log=True):
+        widths=None, log=True, arch=0, block=0):
+    """arch 0: the configured U-Net between fixed transfers (widths 32..256);
+    arch 1: the paper's network of section 3.1 (widths 16..128, learned 5x5
+    strided transfers, ELU ResNet blocks, 4 input channels)."""
     import torch
 
     from . import helm, train, unet
 
     kap, gam = medium(kind)
     h = helm.Handle(torch.from_numpy(kap).cuda(), torch.from_numpy(gam).cuda(), OMEGA, levels=3, coarse_gmres=10)
-    net = unet.UNet(widths=widths)
+    if widths is None:
+        widths = (16, 32, 64, 128) if arch == 1 else (32, 64, 128, 256)
+    net = unet.UNet(widths=widths, arch=arch)
     net.init(seed)
     rng = np.random.default_rng(seed + 1000)
     b = (rng.standard_normal((rhs, N, N)) + 1j * rng.standard_normal((rhs, N, N))).astype(np.complex64)
     b = torch.from_numpy(b).cuda()
-    before = solve_all(h, net, b)
+    before = solve_all(h, net, b, block=block)
     err0 = relative_error(net, h, seed + 7, 16)
     t = time.perf_counter()
     sched = partial(train.paper_schedule, lr0=lr0, batch0=batch0, t0=t0)
@@ -112,8 +126,10 @@ def run(kind="homogeneous", epochs=100, dataset=1000, lr0=1e-3, batch0=20, t0=48
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t
     err1 = relative_error(net, h, seed + 7, 16)
-    after = solve_all(h, net, b)
-    return dict(medium=kind, n=N, omega=OMEGA, layer=LAYER, levels=3, coarse="GMRES(10)+Jacobi", epochs=epochs,
+    after = solve_all(h, net, b, block=block)
+    return dict(medium=kind, n=N, omega=OMEGA, layer=LAYER, levels=3, coarse="GMRES(10)+Jacobi", arch=arch,
+                widths=list(widths), nparams=net.nparams, krylov=f"block FGMRES(10), block {block}" if block else
+                "FGMRES(10)", epochs=epochs,
                 dataset=dataset, lr0=lr0, batch0=batch0, t0=t0, steps=len(losses), train_seconds=t_train,
                 loss_first=losses[0] if losses else None, loss_last=losses[-1] if losses else None,
                 rel_error_untrained=err0, rel_error_trained=err1, untrained=before, trained=after)
@@ -129,9 +145,11 @@ def main(argv=None):
     ap.add_argument("--t0", type=int, default=48)
     ap.add_argument("--rhs", type=int, default=10)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--arch", type=int, default=0, choices=[0, 1])
+    ap.add_argument("--block", type=int, default=0, help="block size of block FGMRES (0: FGMRES per RHS)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    res = run(a.medium, a.epochs, a.dataset, a.lr0, a.batch0, a.t0, a.rhs, a.seed)
+    res = run(a.medium, a.epochs, a.dataset, a.lr0, a.batch0, a.t0, a.rhs, a.seed, arch=a.arch, block=a.block)
     line = json.dumps(res)
     print(line, flush=True)
     if a.out:

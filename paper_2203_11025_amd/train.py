@@ -93,13 +93,20 @@ class Batches:
         b = 0
         while b < self.batch:
             h = self.handles[med[b]]
-            # a run of consecutive indices with one k from one medium per call
-            c = 1
-            while (b + c < self.batch and med[b + c] == med[b] and idx[b + c] == idx[b] + c
-                   and self.k_of(seed, idx[b + c]) == self.k_of(seed, idx[b])):
-                c += 1
-            h.training_triples_seeded(seed, idx[b], self.r[b:b + c], self.e[b:b + c],
-                                      ksteps=self.k_of(seed, idx[b]))
+            if self.ksteps == "random":
+                # every sample of one medium in one call, each with its own k
+                c = 1
+                while b + c < self.batch and med[b + c] == med[b]:
+                    c += 1
+                h.training_triples_batch(seed, idx[b:b + c], [self.k_of(seed, i) for i in idx[b:b + c]],
+                                         self.r[b:b + c], self.e[b:b + c])
+            else:
+                # a run of consecutive indices from one medium per call
+                c = 1
+                while b + c < self.batch and med[b + c] == med[b] and idx[b + c] == idx[b] + c:
+                    c += 1
+                h.training_triples_seeded(seed, idx[b], self.r[b:b + c], self.e[b:b + c],
+                                          ksteps=self.k_of(seed, idx[b]))
             for j in range(b, b + c):
                 h.coarse_slowness(out=self.kc[j])
             b += c

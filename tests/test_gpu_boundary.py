@@ -190,6 +190,42 @@ def test_k_step_triples_match_the_oracle(mods, oracle, k):
         assert abs(np.linalg.norm(r[b]) / np.linalg.norm(ro) - 1) <= 1e-2
 
 
+def test_batched_triples_with_per_sample_k_match_the_oracle(mods, oracle):
+    """helm_training_triples_batch: samples with their own indices (not
+    consecutive) and their own k in one FGMRES run.  x equals the draw of the
+    same index by the per-call entry point bit for bit, and each triple
+    matches the oracle's k-step triple (eq. 3.8) to the bounds of the
+    per-call test; k = 0 or 31 is rejected."""
+    helm, unet, _ = mods
+    n = 64
+    kap, gam, om, h = medium(helm, n, 7)
+    index, ks = [7, 100, 3, 55, 12], [1, 4, 10, 2, 7]
+    nb = len(index)
+    x = torch.empty((nb, n, n), dtype=torch.complex64, device="cuda")
+    r = torch.empty_like(x)
+    e = torch.empty_like(x)
+    h.training_triples_batch(21, index, ks, r, e, x=x)
+    x1 = torch.empty((1, n, n), dtype=torch.complex64, device="cuda")
+    r1, e1 = torch.empty_like(x1), torch.empty_like(x1)
+    H = oracle.Hierarchy(kap, gam, om, 2)
+    xc, rc_, ec = x.cpu().numpy(), r.cpu().numpy(), e.cpu().numpy()
+    for b in range(nb):
+        h.training_triples_seeded(21, index[b], r1, e1, x=x1, ksteps=ks[b])
+        assert np.array_equal(x1.cpu().numpy()[0], xc[b])
+        ro, eo, its = U.training_triple_k(H, xc[b], ks[b])
+        assert its == ks[b]
+        bb = oracle.apply(kap, gam, om, xc[b].astype(complex))
+        nb_, nx = np.linalg.norm(bb), np.linalg.norm(xc[b])
+        dr, de = np.linalg.norm(rc_[b] - ro) / nb_, np.linalg.norm(ec[b] - eo) / nx
+        assert dr <= 1e-5 and de <= 1e-5, (b, ks[b], dr, de)
+        cons = np.linalg.norm(oracle.apply(kap, gam, om, ec[b].astype(complex)) - rc_[b]) / nb_
+        assert cons <= 1e-5, (b, cons)
+        assert abs(np.linalg.norm(rc_[b]) / np.linalg.norm(ro) - 1) <= 1e-2
+    for bad in (0, 31):
+        with pytest.raises(helm.HelmError, match="ksteps"):
+            h.training_triples_batch(21, [1], [bad], r[:1], e[:1])
+
+
 def test_triples_mix_matches_the_oracle(mods):
     helm, _, _ = mods
     n, nin, nout = 64, 5, 3

@@ -144,11 +144,27 @@ def test_paper_network_in_fgmres_and_block_fgmres(mods, oracle):
     for prec in ("unet_defl", "unet_cgc"):
         xs, st, rc = helm.fgmres_solve([h], [torch.from_numpy(b).cuda()], m=10, tol=1e-7, prec=prec, net=net,
                                        maxit=3000, stall_ratio=0.95 if prec == "unet_cgc" else 0.0)
+        print(prec, "FGMRES iterations", [s["iterations"] for s in st], "fallbacks", [s["fallback"] for s in st])
         assert rc == 0 and all(s["true_relres"] <= 1e-7 for s in st), prec
         for k in range(3):
             assert rel(xs[0].cpu().numpy()[k], solve(b[k])) <= 1e-5
-    xb, sb, rcb = helm.block_fgmres_solve(h, torch.from_numpy(b).cuda(), block=3, m=10, tol=1e-7,
-                                          prec="unet_defl", net=net, maxit=500)
-    assert rcb == 0
+    # Block FGMRES: a network whose output layer is zero gives e0 = 0, so
+    # M_VU reduces to M_V exactly (eq. 3.4): the block solve with it must take
+    # the plain-SL block solve's iterations and reach the same solution.
+    # (The briefly trained network itself is no useful preconditioner: its
+    # e0 is larger than the error, and block FGMRES has no fallback.)
+    cfg = PN.PaperNetCfg(widths=WIDTHS)
+    p, buf = PN.init_params(cfg, 5)
+    p["out.w"].zero_()
+    p["out.bias"].zero_()
+    zero = unet.UNet(widths=WIDTHS, arch=1)
+    zero.set_params(PN.flatten(cfg, p), torch.cat([buf[k].reshape(-1) for k in PN.buffer_shapes(cfg)]))
+    bt = torch.from_numpy(b).cuda()
+    xv, sv, rcv = helm.block_fgmres_solve(h, bt, block=3, m=10, tol=1e-7, prec="sl", maxit=500)
+    xb, sb, rcb = helm.block_fgmres_solve(h, bt, block=3, m=10, tol=1e-7, prec="unet_defl", net=zero, maxit=500)
+    print("block FGMRES iterations", [s["iterations"] for s in sb], "M_V", [s["iterations"] for s in sv])
+    assert rcv == 0 and rcb == 0
+    assert [s["iterations"] for s in sb] == [s["iterations"] for s in sv]
     for k in range(3):
         assert rel(xb.cpu().numpy()[k], solve(b[k])) <= 1e-5
+        assert rel(xb.cpu().numpy()[k], xv.cpu().numpy()[k]) <= 1e-6
