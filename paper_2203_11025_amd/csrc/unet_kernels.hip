@@ -900,159 +900,212 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
 // pixels), B = X^T (32 pixels x 16 input channels).  A workgroup owns CB =
 // 16 NCF output and IB = 16 NIF input channels for all 9 taps.  A K step is
 // row y of one 32-pixel column strip (b, x0); consecutive steps walk down the
-// strip.  LDS holds dy^T of the row and X^T of rows y-1, y, y+1 in a ring of
-// three slots, each slot as three copies shifted by kx so every fragment is
-// an aligned 16-byte read; a step inside a strip stages one new X row.
-// Staging transposes blocks of 8 pixels x 8 channels in registers and
-// writes 16-byte LDS rows.  Wavefront w owns input-channel fragment w % NIF
-// and the taps tg, tg + 4 / NIF, ... with tg = w / NIF.
-constexpr int WG_SEG = 32, WG_PADP = 40;
+// strip.  LDS holds dy^T of the row (two buffers) and X^T of image rows in a
+// ring of four slots (rows y-1, y, y+1 in use, y+2 being filled).  An X slot
+// row (one channel) holds pixels x0 - 8 .. x0 + 39 as six 8-pixel words, of
+// which the two outer words carry only the halo pixels x0 - 2, x0 - 1 and
+// x0 + 32, x0 + 33.  A lane's B fragment for kx = 1 is the aligned word of
+// its 8 pixels; for kx = 0 and kx = 2 it is that word shifted by one pixel,
+// formed with byte-align operations from the word and one dword on either
+// side (5 v_alignbyte per lane and row, shared by the two shifts).
+// Software pipeline: right after the barrier that publishes step s, each
+// thread issues the global loads of its piece of step s + 1 (the dy row y+1,
+// the X row y+2) into registers, the MFMAs of step s run while they are in
+// flight, and the pieces are then transposed into the free buffers before
+// the next barrier: one barrier per step.  A step that starts a new strip
+// stages its three X rows after a barrier instead.
+// Staging pieces (one per thread): 8 dy channels x 4 pixels (four 16-byte
+// loads, a 4 x 8 transpose in registers, eight 8-byte LDS writes); 8 X
+// channels x 4 pixels (likewise); 8 X channels x the 2 halo pixels of one
+// side (two loads, eight 4-byte writes).
+// Wavefront w owns input-channel fragment w % NIF and NCW = NCF NIF / 4 of
+// the output-channel fragments, for all 9 taps.
+constexpr int WG_SEG = 32, WG_PADA = 40, WG_PADX = 56;
 
-// transposes 8 pixels x 8 bf16 channels: p[i] holds channels 0..7 of pixel
-// i; o[q] receives pixels 0..7 of channel q
-__device__ __forceinline__ void transpose8(const uint4 p[8], uint4 o[8])
+// 4 pixels x 8 bf16 channels -> 8 channels x 4 pixels: p[i] holds channels
+// 0..7 of pixel i; o[q] receives pixels 0..3 of channel q
+__device__ __forceinline__ void transpose4x8(const uint4 *p, uint2 o[8])
 {
 #pragma unroll
     for (int m = 0; m < 4; ++m) {  // channel pair (2m, 2m + 1) sits in dword m
-        uint32_t ev[4], od[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t A = reinterpret_cast<const uint32_t *>(&p[2 * k])[m];
-            const uint32_t Bv = reinterpret_cast<const uint32_t *>(&p[2 * k + 1])[m];
-            ev[k] = (A & 0xFFFFu) | (Bv << 16);
-            od[k] = (A >> 16) | (Bv & 0xFFFF0000u);
-        }
-        o[2 * m] = make_uint4(ev[0], ev[1], ev[2], ev[3]);
-        o[2 * m + 1] = make_uint4(od[0], od[1], od[2], od[3]);
+        const uint32_t a0 = reinterpret_cast<const uint32_t *>(&p[0])[m];
+        const uint32_t a1 = reinterpret_cast<const uint32_t *>(&p[1])[m];
+        const uint32_t a2 = reinterpret_cast<const uint32_t *>(&p[2])[m];
+        const uint32_t a3 = reinterpret_cast<const uint32_t *>(&p[3])[m];
+        o[2 * m] = make_uint2((a0 & 0xFFFFu) | (a1 << 16), (a2 & 0xFFFFu) | (a3 << 16));
+        o[2 * m + 1] = make_uint2((a0 >> 16) | (a1 & 0xFFFF0000u), (a2 >> 16) | (a3 & 0xFFFF0000u));
     }
 }
 
 template <int NCF, int NIF>
-__global__ __launch_bounds__(256) void k_wgrad(Srcs x, const bf16 *__restrict__ dy, int B, int H,
-                                               int W, int Cout, int steps_per_split,
-                                               float *__restrict__ part)
+__global__ __launch_bounds__(256, 2) void k_wgrad(Srcs x, const bf16 *__restrict__ dy, int B, int H,
+                                                  int W, int Cout, int steps_per_split,
+                                                  float *__restrict__ part)
 {
     constexpr int CB = 16 * NCF, IB = 16 * NIF;
-    constexpr int TG = 4 / NIF;               // tap stride between a wave's taps
-    constexpr int NT = (9 + TG - 1) / TG;     // taps per wave (upper bound)
-    constexpr int NDY = 4 * (CB / 8);         // dy staging tasks per row
-    constexpr int NXR = 3 * 4 * (IB / 8);     // X staging tasks per row (3 shifted copies)
-    __shared__ __attribute__((aligned(16))) bf16 sa[CB * WG_PADP];
-    __shared__ __attribute__((aligned(16))) bf16 sb[3][3][IB * WG_PADP];  // [slot][kx][ci][px]
+    constexpr int NCW = NCF * NIF / 4;        // output-channel fragments per wave
+    static_assert(NCW >= 1 && NCF % NCW == 0, "wave partition");
+    constexpr int NPB = WG_SEG / 4;           // 4-pixel blocks per row
+    constexpr int NDY = (CB / 8) * NPB;       // dy pieces
+    constexpr int NXM = (IB / 8) * NPB;       // X pieces
+    constexpr int NXH = (IB / 8) * 2;         // X halo pieces
+    static_assert(NDY + NXM + NXH <= 256, "one staging piece per thread");
+    __shared__ __attribute__((aligned(16))) bf16 sa[2][CB * WG_PADA];
+    __shared__ __attribute__((aligned(16))) bf16 sb[4][IB * WG_PADX];  // [slot][ci][px]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int ncb = (Cout + CB - 1) / CB;
     const int cb = blockIdx.y % ncb, ib = blockIdx.y / ncb;
     const int co0 = cb * CB, ci0 = ib * IB;
-    const int fi = wv % NIF, tg = wv / NIF;
+    const int fi = wv % NIF, cw = (wv / NIF) * NCW;
     const int nseg = (W + WG_SEG - 1) / WG_SEG;
     const int total_steps = B * nseg * H;
     const int s_begin = blockIdx.x * steps_per_split;
     const int s_end = min(total_steps, s_begin + steps_per_split);
-    f32x4 acc[NT][NCF];
+    f32x4 acc[9][NCW];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < 9; ++t)
 #pragma unroll
-        for (int j = 0; j < NCF; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < NCW; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // stages the X^T copies of image row yr (zero outside the image) into its slot
-    auto stage_x = [&](int task, int b, int x0, int yr) {
-        const int g = task % (IB / 8), r = task / (IB / 8), j = r % 4, kx = r / 4;
-        const int c = ci0 + g * 8;
-        uint4 pv[8];
-        const bool rowok = yr >= 0 && yr < H && c < x.Ctot;
-        int s = 0, coff = c;
-        if (rowok)
-            while (s < x.n - 1 && coff >= x.s[s].C) {
-                coff -= x.s[s].C;
-                ++s;
+    // this thread's staging piece, fixed over the steps: kind 0 dy, 1 X, 2 X
+    // halo, 3 none
+    const int kind = tid < NDY ? 0 : tid < NDY + NXM ? 1 : tid < NDY + NXM + NXH ? 2 : 3;
+    const int u = kind == 0 ? tid : kind == 1 ? tid - NDY : tid - NDY - NXM;
+    const int g = kind == 0 ? u % (CB / 8) : u % (IB / 8);   // 8-channel group
+    const int tj = kind == 0 ? u / (CB / 8) : u / (IB / 8);  // 4-pixel block, or halo side
+    const int cdy = co0 + 8 * g;
+    const bool dy_ok = kind == 0 && cdy < Cout;
+    // X: the source holding channels ci0 + 8 g .. + 7
+    int xs_idx = 0, coff = ci0 + 8 * g;
+    bool x_ok = (kind == 1 || kind == 2) && coff < x.Ctot;
+    if (x_ok)
+        while (xs_idx < x.n - 1 && coff >= x.s[xs_idx].C) {
+            coff -= x.s[xs_idx].C;
+            ++xs_idx;
+        }
+    const bf16 *xsrc = x.s[xs_idx].p;
+    const int xCs = x.s[xs_idx].stride ? x.s[xs_idx].stride : x.s[xs_idx].C;  // channels per pixel in memory
+    const bool xshared = x.s[xs_idx].shared;
+    x_ok = x_ok && coff < xCs;
+    // first pixel (relative to x0) and count of this piece
+    const int px0 = kind == 2 ? (tj == 0 ? -2 : WG_SEG) : 4 * tj;
+    uint4 pv[4];
+
+    auto load = [&](int b, int yr, int x0) {
+        if (kind == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int xs = x0 + px0 + i;
+                pv[i] = make_uint4(0u, 0u, 0u, 0u);
+                if (dy_ok && xs < W)
+                    pv[i] = *reinterpret_cast<const uint4 *>(dy + (((size_t)b * H + yr) * W + xs) * Cout + cdy);
             }
-        const bf16 *src = x.s[s].p;
-        const int Cs = x.s[s].stride ? x.s[s].stride : x.s[s].C;  // channels per pixel in memory
-        const size_t rowbase = ((size_t)(x.s[s].shared ? 0 : b) * H + (rowok ? yr : 0)) * W;
-        const bool seg_ok = coff < Cs;
+        } else if (kind <= 2) {
+            const bool rowok = x_ok && yr >= 0 && yr < H;
+            const size_t rowbase = ((size_t)(xshared ? 0 : b) * H + (rowok ? yr : 0)) * W;
+            const int np = kind == 1 ? 4 : 2;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int xs = x0 - 1 + 8 * j + kx + i;
-            pv[i] = make_uint4(0u, 0u, 0u, 0u);
-            if (rowok && seg_ok && xs >= 0 && xs < W)
-                pv[i] = *reinterpret_cast<const uint4 *>(src + (rowbase + xs) * Cs + coff);
+            for (int i = 0; i < 4; ++i) {
+                const int xs = x0 + px0 + i;
+                pv[i] = make_uint4(0u, 0u, 0u, 0u);
+                if (i < np && rowok && xs >= 0 && xs < W)
+                    pv[i] = *reinterpret_cast<const uint4 *>(xsrc + (rowbase + xs) * xCs + coff);
+            }
         }
-        uint4 o[8];
-        transpose8(pv, o);
-        const int slot = (yr + 3) % 3;
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            *reinterpret_cast<uint4 *>(&sb[slot][kx][(g * 8 + q) * WG_PADP + 8 * j]) = o[q];
     };
-    auto stage_dy = [&](int task, int b, int x0, int y) {
-        const int g = task % (CB / 8), j = task / (CB / 8);
-        const int c = co0 + g * 8;
-        uint4 pv[8];
+    // writes the loaded piece: dy into buffer `slot`, X into ring slot `slot`
+    auto store = [&](int slot) {
+        if (kind == 3) return;
+        uint2 o[8];
+        transpose4x8(pv, o);
+        if (kind == 0) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int xs = x0 + 8 * j + i;
-            pv[i] = make_uint4(0u, 0u, 0u, 0u);
-            if (c < Cout && xs < W)
-                pv[i] = *reinterpret_cast<const uint4 *>(dy + (((size_t)b * H + y) * W + xs) * Cout + c);
+            for (int q = 0; q < 8; ++q)
+                *reinterpret_cast<uint2 *>(&sa[slot][(g * 8 + q) * WG_PADA + px0]) = o[q];
+        } else if (kind == 1) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                *reinterpret_cast<uint2 *>(&sb[slot][(g * 8 + q) * WG_PADX + 8 + px0]) = o[q];
+        } else if (kind == 2) {
+            // pixels px0, px0 + 1 sit in the first dword of each channel's pair
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                *reinterpret_cast<uint32_t *>(&sb[slot][(g * 8 + q) * WG_PADX + 8 + px0]) = o[q].x;
         }
-        uint4 o[8];
-        transpose8(pv, o);
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            *reinterpret_cast<uint4 *>(&sa[(g * 8 + q) * WG_PADP + 8 * j]) = o[q];
+    };
+    // all of step st's LDS data, loaded synchronously (the first step of the
+    // split and the first step of every strip)
+    auto stage_fresh = [&](int st) {
+        const int y = st % H, r = st / H, seg = r % nseg, b = r / nseg;
+        const int x0 = seg * WG_SEG;
+        if (kind == 0) {
+            load(b, y, x0);
+            store(st & 1);
+        } else if (kind <= 2) {
+            for (int k = 0; k < 3; ++k) {
+                load(b, y - 1 + k, x0);
+                store((y - 1 + k + 4) & 3);
+            }
+        }
     };
 
+    if (s_begin < s_end) stage_fresh(s_begin);
+    __syncthreads();
+    const int c16 = lane & 15, j8 = 8 * (lane >> 4);
     for (int st = s_begin; st < s_end; ++st) {
         const int y = st % H, r = st / H, seg = r % nseg, b = r / nseg;
         const int x0 = seg * WG_SEG;
-        // a new strip (or the split's first step) stages all three X rows
-        const bool fresh = st == s_begin || y == 0;
-        const int nx = fresh ? 3 * NXR : NXR;
-        for (int task = tid; task < NDY + nx; task += 256) {
-            if (task < NDY) {
-                stage_dy(task, b, x0, y);
-            } else {
-                const int t2 = task - NDY;
-                const int yr = fresh ? y - 1 + t2 / NXR : y + 1;
-                stage_x(t2 % NXR, b, x0, yr);
+        const bool have_next = st + 1 < s_end;
+        const bool next_fresh = have_next && y + 1 == H;
+        if (have_next && !next_fresh) load(b, kind == 0 ? y + 1 : y + 2, x0);
+        bf16x8 a[NCW];
+#pragma unroll
+        for (int c = 0; c < NCW; ++c)
+            a[c] = *reinterpret_cast<const bf16x8 *>(&sa[st & 1][((cw + c) * 16 + c16) * WG_PADA + j8]);
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+            const bf16 *row = &sb[(y + ky - 1 + 4) & 3][(fi * 16 + c16) * WG_PADX + 8 + j8];
+            const uint4 w = *reinterpret_cast<const uint4 *>(row);
+            const uint32_t pw = *reinterpret_cast<const uint32_t *>(row - 2);
+            const uint32_t nw = *reinterpret_cast<const uint32_t *>(row + 8);
+            const uint32_t s0 = __builtin_amdgcn_alignbyte(w.x, pw, 2);
+            const uint32_t s1 = __builtin_amdgcn_alignbyte(w.y, w.x, 2);
+            const uint32_t s2 = __builtin_amdgcn_alignbyte(w.z, w.y, 2);
+            const uint32_t s3 = __builtin_amdgcn_alignbyte(w.w, w.z, 2);
+            const uint32_t s4 = __builtin_amdgcn_alignbyte(nw, w.w, 2);
+            const bf16x8 b0 = __builtin_bit_cast(bf16x8, make_uint4(s0, s1, s2, s3));
+            const bf16x8 b1 = __builtin_bit_cast(bf16x8, w);
+            const bf16x8 b2 = __builtin_bit_cast(bf16x8, make_uint4(s1, s2, s3, s4));
+#pragma unroll
+            for (int c = 0; c < NCW; ++c) {
+                acc[3 * ky][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b0, acc[3 * ky][c], 0, 0, 0);
+                acc[3 * ky + 1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b1, acc[3 * ky + 1][c], 0, 0, 0);
+                acc[3 * ky + 2][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b2, acc[3 * ky + 2][c], 0, 0, 0);
             }
         }
-        __syncthreads();
-        bf16x8 a[NCF];
-#pragma unroll
-        for (int cf = 0; cf < NCF; ++cf)
-            a[cf] = *reinterpret_cast<const bf16x8 *>(&sa[(cf * 16 + (lane & 15)) * WG_PADP + 8 * (lane >> 4)]);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int tap = tg + t * TG;
-            if (tap < 9) {
-                const int ky = tap / 3, kx = tap - 3 * (tap / 3);
-                const int slot = (y + ky - 1 + 3) % 3;
-                const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(
-                    &sb[slot][kx][(fi * 16 + (lane & 15)) * WG_PADP + 8 * (lane >> 4)]);
-#pragma unroll
-                for (int cf = 0; cf < NCF; ++cf)
-                    acc[t][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cf], bw, acc[t][cf], 0, 0, 0);
-            }
+        if (!have_next) break;
+        if (!next_fresh) {
+            // the buffers written here were last read by step st - 1
+            store(kind == 0 ? (st + 1) & 1 : (y + 2 + 4) & 3);
+        } else {
+            __syncthreads();  // every wave is done with step st's buffers
+            stage_fresh(st + 1);
         }
         __syncthreads();
     }
     // D[co][ci]: lane holds input channel l % 16 and output channels 4 (l / 16) .. + 3
     const size_t per_split = (size_t)Cout * 9 * x.Ctot;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int tap = tg + t * TG;
-        if (tap >= 9) continue;
+    for (int tap = 0; tap < 9; ++tap)
 #pragma unroll
-        for (int cf = 0; cf < NCF; ++cf)
+        for (int c = 0; c < NCW; ++c)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int co = co0 + cf * 16 + 4 * (lane >> 4) + q;
-                const int ci = ci0 + fi * 16 + (lane & 15);
+                const int co = co0 + (cw + c) * 16 + 4 * (lane >> 4) + q;
+                const int ci = ci0 + fi * 16 + c16;
                 if (co < Cout && ci < x.Ctot)
-                    part[blockIdx.x * per_split + ((size_t)co * 9 + tap) * x.Ctot + ci] = acc[t][cf][q];
+                    part[blockIdx.x * per_split + ((size_t)co * 9 + tap) * x.Ctot + ci] = acc[tap][c][q];
             }
-    }
 }
 
 // out[i] = sum over splits of part[split][i], in two fixed-order passes:
@@ -2136,8 +2189,11 @@ static int wgrad_nsplit(int B, int H, int W, int Cout, int Ctot)
     const int steps = B * H * ((W + WG_SEG - 1) / WG_SEG);
     const int CB = Cout >= 64 ? 64 : 32, IB = Ctot >= 64 ? 64 : 32;
     const int blocks = ((Cout + CB - 1) / CB) * ((Ctot + IB - 1) / IB);
-    int want = std::max(1, 1024 / blocks);
-    return std::max(1, std::min(want, (steps + 31) / 32));  // at least 32 steps per split
+    // as many workgroups as the CUs hold at once (the kernels' register use
+    // allows 2, 3 or 5 per CU), at least 32 steps per split
+    const int per_cu = (CB == 64 && IB == 64) ? 2 : (CB == 64 || IB == 64) ? 3 : 5;
+    int want = std::max(1, 256 * per_cu / blocks);
+    return std::max(1, std::min(want, (steps + 31) / 32));
 }
 
 size_t wgrad_scratch(int B, int H, int W, int Cout, int Ctot)
