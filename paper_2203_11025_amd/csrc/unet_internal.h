@@ -56,12 +56,23 @@ struct Srcs {
 // and of a raw (mode 0) convolution:
 //   raw16    : write the raw output as FP16 [B][H][W][Cout] here instead
 //              of out32
+//   nseg ... : route channel ranges of the FP32 raw output: range k is
+//              [seg_hi[k-1], seg_hi[k]) (from 0; the last ends at Cout);
+//              with seg_p[k] its channels are written to seg_p[k] (seg_C[k]
+//              channels per pixel, at channel c - seg_hi[k-1]; stored, not
+//              added), without it they go to out32 as usual.  Boundaries and
+//              seg_C are multiples of 4.
+constexpr int CONV_MAX_SEG = 4;
 struct ConvEpi {
     bf16 *pool = nullptr;
     const float *head_w = nullptr, *head_b = nullptr;
     float *head_out = nullptr;
     const _Float16 *cmap = nullptr;
     _Float16 *raw16 = nullptr;
+    int nseg = 0;
+    float *seg_p[CONV_MAX_SEG] = {};
+    int seg_hi[CONV_MAX_SEG] = {};
+    int seg_C[CONV_MAX_SEG] = {};
 };
 void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout, int mode,
                     float *out32, bf16 *out16, const float *scale, const float *shift,

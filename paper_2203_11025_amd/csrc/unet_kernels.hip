@@ -149,12 +149,29 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[MF][NF], int lane, in
                 if (pix_ok && (full_co || co0 + nf * 16 + 4 * (lane >> 4) < Cout)) {
                     const f32x4 v = acc[mf][nf];
                     if (mode == 0) {
-                        if (epi.raw16)
+                        if (epi.raw16) {
                             *reinterpret_cast<f16x4 *>(epi.raw16 + base + nf * 16) =
                                 f16x4{(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
-                        else
+                        } else if (epi.nseg) {
+                            // the channel range holding this lane's four channels
+                            const int c = co0 + nf * 16 + 4 * (lane >> 4);
+                            int k = 0, lo = 0;
+                            while (k < epi.nseg - 1 && c >= epi.seg_hi[k]) {
+                                lo = epi.seg_hi[k];
+                                ++k;
+                            }
+                            if (epi.seg_p[k]) {
+                                *reinterpret_cast<float4 *>(epi.seg_p[k] +
+                                                            (((size_t)b * H + y) * W + x) * epi.seg_C[k] +
+                                                            (c - lo)) = make_float4(v[0], v[1], v[2], v[3]);
+                            } else {
+                                *reinterpret_cast<float4 *>(out32 + base + nf * 16) =
+                                    make_float4(v[0], v[1], v[2], v[3]);
+                            }
+                        } else {
                             *reinterpret_cast<float4 *>(out32 + base + nf * 16) =
                                 make_float4(v[0], v[1], v[2], v[3]);
+                        }
                     } else {
                         const f16x4 m = mp[mf][nf];
                         float z0 = (v[0] + (float)m[0]) * sc[nf].x + sh[nf].x;
@@ -1487,6 +1504,55 @@ __global__ void k_up2_bwd(const float *__restrict__ dout, int cstride, int coff,
     }
 }
 
+// The same for 8 consecutive channels per thread (two 16-byte loads per
+// fine pixel; C, cstride and coff multiples of 4): the same products summed
+// in the same order.
+__global__ void k_up2_bwd8(const float *__restrict__ dout, int cstride, int coff, int B, int h, int w,
+                           int C, float *__restrict__ din, int accumulate)
+{
+    const int H = 2 * h, W = 2 * w, C8 = C / 8;
+    const size_t n = (size_t)B * h * w * C8;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C8) * 8;
+        const size_t r = i / C8;
+        const int xi = (int)(r % w);
+        const size_t r2 = r / w;
+        const int yi = (int)(r2 % h), b = (int)(r2 / h);
+        int oy[4], ox[4];
+        float wy[4], wx[4];
+        up_adj(yi, h, oy, wy);
+        up_adj(xi, w, ox, wx);
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int a = 0; a < 4; ++a) {
+            if (wy[a] == 0.f) continue;
+            for (int d = 0; d < 4; ++d) {
+                if (wx[d] == 0.f) continue;
+                const float wt = wy[a] * wx[d];
+                const float *src = dout + (((size_t)b * H + oy[a]) * W + ox[d]) * cstride + coff + c;
+                const float4 u = *reinterpret_cast<const float4 *>(src);
+                const float4 v = *reinterpret_cast<const float4 *>(src + 4);
+                acc[0] += wt * u.x;
+                acc[1] += wt * u.y;
+                acc[2] += wt * u.z;
+                acc[3] += wt * u.w;
+                acc[4] += wt * v.x;
+                acc[5] += wt * v.y;
+                acc[6] += wt * v.z;
+                acc[7] += wt * v.w;
+            }
+        }
+        float4 *o = reinterpret_cast<float4 *>(din + r * C + c);
+        if (accumulate) {
+            const float4 p0 = o[0], p1 = o[1];
+            o[0] = make_float4(p0.x + acc[0], p0.y + acc[1], p0.z + acc[2], p0.w + acc[3]);
+            o[1] = make_float4(p1.x + acc[4], p1.y + acc[5], p1.z + acc[6], p1.w + acc[7]);
+        } else {
+            o[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+            o[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+        }
+    }
+}
+
 __global__ void k_slice_add(const float *__restrict__ src, int cstride, int coff, size_t P, int C,
                             float *__restrict__ dst, int accumulate)
 {
@@ -2064,7 +2130,7 @@ int conv_variant(const Srcs &in, int mode, const ConvEpi &epi)
 {
     return mode | ((epi.pool != nullptr) << 1) | ((epi.head_out != nullptr) << 2) |
            ((epi.cmap != nullptr) << 3) | ((in.wstride != 0 && in.wstride != in.Ctot) << 4) |
-           (conv_in8(in) << 5) | ((epi.raw16 != nullptr) << 6) | ((in.s[0].up != 0) << 7);
+           (conv_in8(in) << 5) | ((epi.raw16 != nullptr) << 6) | ((in.s[0].up != 0) << 7) | ((epi.nseg > 0) << 8);
 }
 
 struct Tuner {
@@ -2093,6 +2159,10 @@ ConvShape conv_tune(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
 {
     ConvShape best = conv_default(H, Cout);
     float best_ms = 1e30f;
+    // the timing runs write everything to out32 (the caller's launch after
+    // tuning routes the ranges)
+    ConvEpi tepi = epi;
+    tepi.nseg = 0;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return best;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -2104,10 +2174,10 @@ ConvShape conv_tune(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
         for (int per_cu : {1, 2, 4, 8}) {
             if (kind == 0 && in.s[0].up) continue;  // runs on k_conv3x3d only
             ConvShape c = conv_candidate(kind, mf, per_cu, Cout);
-            conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s, epi);  // warm
+            conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s, tepi);  // warm
             hipEventRecord(e0, s);
             for (int r = 0; r < 3; ++r)
-                conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s, epi);
+                conv_dispatch(c, in, B, H, W, Wt, Cout, mode, out32, out16, scale, shift, slope, s, tepi);
             hipEventRecord(e1, s);
             float ms = 0.f;
             if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
@@ -2286,6 +2356,11 @@ void launch_up2_bwd(const float *dout, int cstride, int coff, int B, int h, int 
                     float *din, int accumulate, hipStream_t s)
 {
     size_t n = (size_t)B * h * w * C;
+    if (C % 8 == 0 && cstride % 4 == 0 && coff % 4 == 0) {
+        hipLaunchKernelGGL(k_up2_bwd8, dim3(grid_for(n / 8)), dim3(256), 0, s, dout, cstride, coff, B, h, w, C,
+                           din, accumulate);
+        return;
+    }
     hipLaunchKernelGGL(k_up2_bwd, dim3(grid_for(n)), dim3(256), 0, s, dout, cstride, coff, B, h, w, C,
                        din, accumulate);
 }

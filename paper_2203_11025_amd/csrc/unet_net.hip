@@ -477,22 +477,68 @@ void unet_net::layers_backward(int B, int H, int W, hipStream_t st)
         launch_unpack_wgrad(dW, l.cout, l.cin_real, l.map, l.cin_pad, G + l.w_off, st);
         const bool has_ctx = cfg.context && l.name.back() == 'a';
         if (i == 0 && !has_ctx) continue;  // no gradient w.r.t. the network input
-        // data gradient: a 3x3 convolution of dy with the flipped, transposed weights
+        // data gradient: a 3x3 convolution of dy with the flipped, transposed
+        // weights.  Its channel ranges that are the first contribution to
+        // another tensor's gradient are stored straight into it by the
+        // convolution's epilogue: the previous activation of a 'b' layer
+        // (its only consumer), the skip input of a decoder 'a' layer (the
+        // pooling's share comes later, from the encoder layer below), and the
+        // context of a decoder 'a' layer or of the bottom encoder layer (the
+        // encoder 'a' layer of the same level adds its share later).  The
+        // ranges read through the pooling or the upsampling adjoint stay in
+        // dX, and so does the context share that is added second.
+        const std::string &nm = l.name;
+        const int lev = l.level;
+        ConvEpi de;
+        int hi = 0;
+        // at most a gap, the skip input, a gap and the context: 4 ranges
+        auto route = [&](int lo, int C, float *p) {
+            if (lo > hi) {  // a gap stays in dX
+                de.seg_p[de.nseg] = nullptr;
+                de.seg_hi[de.nseg] = lo;
+                de.seg_C[de.nseg++] = 0;
+            }
+            de.seg_p[de.nseg] = p;
+            de.seg_hi[de.nseg] = lo + C;
+            de.seg_C[de.nseg++] = C;
+            hi = lo + C;
+        };
+        if (i > 0 && nm.back() == 'b') {
+            route(0, l.cout, act[i - 1].g);
+        } else if (i > 0 && nm[0] == 'd') {
+            // dec{lev}a: [upsampled, skip (, context)]
+            route(cfg.widths[lev + 1], cfg.widths[lev], act[enc_index(lev, 'b')].g);
+        }
+        // the context is the last source; a decoder layer of its level (dec
+        // layers run first here) has written gctx[lev] already unless this
+        // is the bottom level
+        const bool ctx_first = has_ctx && (nm[0] == 'd' || lev == Lv - 1);
+        if (ctx_first) route(l.cin_pad - cfg.widths[lev], cfg.widths[lev], gctx[lev]);
+        if (de.nseg == 0) {
+            // nothing routed: the plain epilogue
+        } else if (hi < l.cin_pad) {
+            de.seg_p[de.nseg] = nullptr;
+            de.seg_hi[de.nseg] = l.cin_pad;
+            de.seg_C[de.nseg++] = 0;
+        }
+        // one range covering every channel: the plain epilogue into it
+        float *out = dX;
+        if (de.nseg == 1 && de.seg_p[0] && de.seg_C[0] == l.cin_pad) {
+            out = de.seg_p[0];
+            de.nseg = 0;
+        }
         Srcs ds{};
         ds.n = 1;
         ds.Ctot = l.cout;
         ds.s[0] = {dy, l.cout, 0};
         prof_mark(HELM_PROF_CONV, st, true);
-        launch_conv3x3(ds, B, Hl, Wl, l.Wd, l.cin_pad, 0, dX, nullptr, nullptr, nullptr, SLOPE, st);
+        launch_conv3x3(ds, B, Hl, Wl, l.Wd, l.cin_pad, 0, out, nullptr, nullptr, nullptr, SLOPE, st, de);
         prof_mark(HELM_PROF_CONV, st, false, flops);
-        const std::string &nm = l.name;
-        const int lev = l.level;
-        if (has_ctx)  // the context is the last source
-            launch_slice_add(dX, l.cin_pad, l.cin_pad - cfg.widths[lev], Pl, cfg.widths[lev], gctx[lev], 1,
-                             st);
+        if (has_ctx && !ctx_first)
+            launch_slice_add(dX, l.cin_pad, l.cin_pad - cfg.widths[lev], Pl, cfg.widths[lev], gctx[lev], 1, st);
         if (i == 0) continue;
         if (nm.back() == 'b') {
-            launch_slice_add(dX, l.cin_pad, 0, Pl, l.cout, act[i - 1].g, 1, st);
+            // routed above
         } else if (nm[0] == 'e') {
             // enc{lev}a, lev >= 1: through the max pooling into enc{lev-1}b
             int src_layer = enc_index(lev - 1, 'b');
@@ -502,8 +548,6 @@ void unet_net::layers_backward(int B, int H, int W, hipStream_t st)
             // dec{lev}a: [upsampled, skip (, context)]
             int prev = (lev == Lv - 2) ? enc_index(Lv - 1, 'b') : dec_index(lev + 1, 'b');
             launch_up2_bwd(dX, l.cin_pad, 0, B, Hl / 2, Wl / 2, cfg.widths[lev + 1], act[prev].g, 1, st);
-            launch_slice_add(dX, l.cin_pad, cfg.widths[lev + 1], Pl, cfg.widths[lev],
-                             act[enc_index(lev, 'b')].g, 1, st);
         }
     }
 }
