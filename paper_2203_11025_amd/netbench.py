@@ -13,7 +13,8 @@ Arnoldi steps, the x update and the true residual.
 --mode retrain: reps mini-retraining steps of the encoder-solver pair on
 the medium (batch 16, k of eq. 3.8 drawn from 1..10 per sample, lr 1e-3:
 the benchmark's retraining), after one untimed step; prints the split of a
-step between the triples and the Adam step.
+step between the triples and the Adam step, and the rates of the weight-
+gradient and the other convolutions from the library's timing hook.
 --mode uneven: the uneven batch (--workload uneven24 or uneven6: many
 layered media of 256^2..2048^2, 8 point sources each) solved in one
 helm_fgmres_solve call, first with the encoder-solver M_VU (each medium
@@ -130,6 +131,7 @@ def retrain(a):
     r, e, kc = data.fill(11, 0)
     unet.pair_train_step(enc, sol, r, e, kc, lr=1e-3)
     torch.cuda.synchronize()
+    helm.profile_start("wgrad", "conv")
     t_data = t_step = 0.0
     for i in range(a.reps):
         t0 = time.perf_counter()
@@ -141,9 +143,14 @@ def retrain(a):
         t_data += t1 - t0
         t_step += time.perf_counter() - t1
         print(f"[netbench] retrain step {i} loss {loss:.3e}", file=sys.stderr, flush=True)
+    wms, wn, ww = helm.profile_read("wgrad")
+    cms, cn, cw = helm.profile_read("conv")
+    helm.profile_stop()
     print(json.dumps({"mode": "retrain", "workload": a.workload, "batch": 16, "reps": a.reps,
                       "ms_per_step": (t_data + t_step) * 1e3 / a.reps, "ms_triples": t_data * 1e3 / a.reps,
-                      "ms_adam_step": t_step * 1e3 / a.reps, "autotune": a.autotune}))
+                      "ms_adam_step": t_step * 1e3 / a.reps, "autotune": a.autotune,
+                      "wgrad_ms_per_step": wms / a.reps, "wgrad_tflops": ww / (wms * 1e-3) / 1e12 if wms else None,
+                      "conv_ms_per_step": cms / a.reps, "conv_tflops": cw / (cms * 1e-3) / 1e12 if cms else None}))
     return 0
 
 
