@@ -90,8 +90,7 @@ struct unet_net {
                    const helm::ConvEpi &epi = helm::ConvEpi());
     void forward_from_x0(int B, int H, int W, bool training, hipStream_t st);
     void backward(int B, int H, int W, hipStream_t st);  // zero, head, layers
-    void zero_act_grads(int B, int H, int W, hipStream_t st);
-    void layers_backward(int B, int H, int W, hipStream_t st);
+    void layers_backward(int B, int H, int W, hipStream_t st, bool seeded);
     int output_layer(int level) const;  // layer whose activation is level's output
     void repack(hipStream_t st);
     void refold(hipStream_t st);

@@ -438,28 +438,25 @@ void unet_net::forward_from_x0(int B, int H, int W, bool training, hipStream_t s
     launch_head_fwd(act[last].a, (size_t)B * H * W, cfg.widths[0], P + head_w, P + head_b, out, st);
 }
 
-void unet_net::zero_act_grads(int B, int H, int W, hipStream_t st)
-{
-    for (size_t i = 0; i < L.size(); ++i) {
-        size_t Pl = (size_t)B * (H >> L[i].level) * (W >> L[i].level);
-        hipMemsetAsync(act[i].g, 0, Pl * L[i].cout * sizeof(float), st);
-    }
-    if (cfg.context)
-        for (int l = 0; l < cfg.levels; ++l)
-            hipMemsetAsync(gctx[l], 0, (size_t)B * (H >> l) * (W >> l) * cfg.widths[l] * sizeof(float), st);
-}
-
+// Every activation gradient and context gradient is first stored, then
+// added to, so none is cleared: the head stores the last layer's; a 'b'
+// layer's data gradient stores its 'a' layer's; a decoder 'a' layer's stores
+// its skip input's and its level's context gradient (the encoder layer below
+// adds the pooling share, the encoder 'a' layer of the level adds its context
+// share); the bottom encoder 'a' layer stores its context gradient; the
+// upsampling adjoint stores the gradient of the tensor it reads (its only
+// consumer), or adds to it when the caller seeded that gradient (`seeded`:
+// an encoder whose outputs carry the solver's context gradients).
 void unet_net::backward(int B, int H, int W, hipStream_t st)
 {
     const int Lv = cfg.levels;
-    zero_act_grads(B, H, W, st);
     int last = Lv >= 2 ? dec_index(0, 'b') : enc_index(0, 'b');
     launch_head_bwd(gout, act[last].a, (size_t)B * H * W, cfg.widths[0], P + head_w, act[last].g, red,
                     G + head_w, G + head_b, st);
-    layers_backward(B, H, W, st);
+    layers_backward(B, H, W, st, false);
 }
 
-void unet_net::layers_backward(int B, int H, int W, hipStream_t st)
+void unet_net::layers_backward(int B, int H, int W, hipStream_t st, bool seeded)
 {
     const int Lv = cfg.levels;
     for (int i = (int)L.size() - 1; i >= 0; --i) {
@@ -547,7 +544,8 @@ void unet_net::layers_backward(int B, int H, int W, hipStream_t st)
         } else {
             // dec{lev}a: [upsampled, skip (, context)]
             int prev = (lev == Lv - 2) ? enc_index(Lv - 1, 'b') : dec_index(lev + 1, 'b');
-            launch_up2_bwd(dX, l.cin_pad, 0, B, Hl / 2, Wl / 2, cfg.widths[lev + 1], act[prev].g, 1, st);
+            launch_up2_bwd(dX, l.cin_pad, 0, B, Hl / 2, Wl / 2, cfg.widths[lev + 1], act[prev].g, seeded ? 1 : 0,
+                           st);
         }
     }
 }
@@ -1230,11 +1228,12 @@ int unet_pair_loss_grad(unet_net *enc, unet_net *sol, const unet_batch *batch, d
     if (rc) return rc;
     // the gradient reaching each context flows back through the encoder
     HELM_HIP_CHECK(hipMemsetAsync(enc->G, 0, enc->nparams * sizeof(float), st));
-    enc->zero_act_grads(nb, nc, nc, st);
+    // seed the encoder's output gradients (stores; the encoder's backward
+    // adds the upsampling shares to them)
     for (int l = 0; l < enc->cfg.levels; ++l)
         launch_slice_add(sol->gctx[l], enc->cfg.widths[l], 0, (size_t)nb * (nc >> l) * (nc >> l),
-                         enc->cfg.widths[l], enc->act[enc->output_layer(l)].g, 1, st);
-    enc->layers_backward(nb, nc, nc, st);
+                         enc->cfg.widths[l], enc->act[enc->output_layer(l)].g, 0, st);
+    enc->layers_backward(nb, nc, nc, st, true);
     // the training-mode context is not the medium's inference context
     sol->clear_context();
     if (enc_grads)

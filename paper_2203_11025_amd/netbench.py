@@ -47,6 +47,8 @@ def main(argv=None):
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--mode", default="net", choices=["net", "sl", "uneven", "retrain"])
     ap.add_argument("--graph", action="store_true")
+    ap.add_argument("--uneven-prec", default="both", choices=["both", "unet", "sl"],
+                    help="--mode uneven: which solves to time")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     a = ap.parse_args(argv)
 
@@ -175,8 +177,11 @@ def uneven(a):
     nrhs = sum(b.shape[0] for b in bs)
     out = {"mode": "uneven", "workload": a.workload, "media": len(P), "sizes": [p["n"] for p in P], "nrhs": nrhs,
            "reps": a.reps, "graph": a.graph, "autotune": a.autotune}
-    for name, kw in (("unet_sl", dict(prec="unet_defl", net=sol, encoder=enc, stall_ratio=0.95, graph=a.graph)),
-                     ("plain_sl", dict(prec="sl", graph=a.graph))):
+    runs = (("unet_sl", dict(prec="unet_defl", net=sol, encoder=enc, stall_ratio=0.95, graph=a.graph)),
+            ("plain_sl", dict(prec="sl", graph=a.graph)))
+    for name, kw in runs:
+        if (a.uneven_prec == "unet" and name != "unet_sl") or (a.uneven_prec == "sl" and name != "plain_sl"):
+            continue
         _, st, rc = helm.fgmres_solve(hs, bs, m=20, tol=1e-7, xs=xs, **kw)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -16,7 +16,7 @@ network by its relative error ||e_net - e|| / ||e|| on held-out triples.
 
     python -m paper_2203_11025_amd.paper_setting [--medium homogeneous|smooth]
         [--epochs 100] [--dataset 1000] [--rhs 10] [--arch 0|1] [--block 10]
-        [--out results.json]
+        [--sweep] [--out results.json]
 
 The paper reports, for the homogeneous medium, a final relative training
 error of 0.18 and rho_VU = 0.231, rho_JU = 0.313 against 0.88 for M_V; those
@@ -99,8 +99,20 @@ def solve_all(h, net, rhs, m=10, tol=1e-7, maxit=2000, block=0):
     return out
 
 
+def sweep(h, net, rhs):
+    """The influence of the block size and of the subspace size (section
+    4.3.5): block FGMRES(10) with blocks of 1, 2, 5 and 10 right-hand sides,
+    and block FGMRES(m) with blocks of 10 for m = 5, 10, 20; per setting and
+    preconditioner the mean rho of eq. 4.1 and the mean iterations to 1e-7."""
+    out = []
+    for block, m in ((1, 10), (2, 10), (5, 10), (10, 10), (10, 5), (10, 20)):
+        r = solve_all(h, net, rhs, m=m, block=block)
+        out.append({"block": block, "m": m, **{k: {"rho": v["rho"], "its": v["its"]} for k, v in r.items()}})
+    return out
+
+
 def run(kind="homogeneous", epochs=100, dataset=1000, lr0=1e-3, batch0=20, t0=48, rhs=10, seed=1,
-        widths=None, log=True, arch=0, block=0):
+        widths=None, log=True, arch=0, block=0, do_sweep=False):
     """arch 0: the configured U-Net between fixed transfers (widths 32..256);
     arch 1: the paper's network of section 3.1 (widths 16..128, learned 5x5
     strided transfers, ELU ResNet blocks, 4 input channels)."""
@@ -127,12 +139,13 @@ def run(kind="homogeneous", epochs=100, dataset=1000, lr0=1e-3, batch0=20, t0=48
     t_train = time.perf_counter() - t
     err1 = relative_error(net, h, seed + 7, 16)
     after = solve_all(h, net, b, block=block)
+    swept = sweep(h, net, b) if do_sweep else None
     return dict(medium=kind, n=N, omega=OMEGA, layer=LAYER, levels=3, coarse="GMRES(10)+Jacobi", arch=arch,
                 widths=list(widths), nparams=net.nparams, krylov=f"block FGMRES(10), block {block}" if block else
                 "FGMRES(10)", epochs=epochs,
                 dataset=dataset, lr0=lr0, batch0=batch0, t0=t0, steps=len(losses), train_seconds=t_train,
                 loss_first=losses[0] if losses else None, loss_last=losses[-1] if losses else None,
-                rel_error_untrained=err0, rel_error_trained=err1, untrained=before, trained=after)
+                rel_error_untrained=err0, rel_error_trained=err1, untrained=before, trained=after, sweep=swept)
 
 
 def main(argv=None):
@@ -147,9 +160,11 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--arch", type=int, default=0, choices=[0, 1])
     ap.add_argument("--block", type=int, default=0, help="block size of block FGMRES (0: FGMRES per RHS)")
+    ap.add_argument("--sweep", action="store_true", help="after training, sweep the block and subspace sizes")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    res = run(a.medium, a.epochs, a.dataset, a.lr0, a.batch0, a.t0, a.rhs, a.seed, arch=a.arch, block=a.block)
+    res = run(a.medium, a.epochs, a.dataset, a.lr0, a.batch0, a.t0, a.rhs, a.seed, arch=a.arch, block=a.block,
+              do_sweep=a.sweep)
     line = json.dumps(res)
     print(line, flush=True)
     if a.out:

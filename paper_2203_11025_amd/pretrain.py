@@ -3,6 +3,7 @@ section 3.3) on triples the method generates (eq. 3.8-3.9) from many smooth
 random media, all in the library's kernels.
 
     python -m paper_2203_11025_amd.pretrain --minutes 15 --out PATH
+    python -m paper_2203_11025_amd.pretrain --plain --media 200 --ksteps random --minutes 13 --out PATH
 
 Media: n^2 grids (default 512, network on 256^2), slowness from seeded white
 noise smoothed by a Gaussian of sigma n/32 cells mapped to [0.25, 1], seeds
@@ -13,6 +14,11 @@ saved weights (e.g. fine-tuning at a larger grid).  The
 weights are saved every `--save-every` seconds and at the end; a short
 evaluation compares FGMRES iterations of M_VU and plain SL on a held-out
 medium.
+
+--plain trains one plain U-Net (no encoder; the network of M_CU in
+Algorithm 2) instead, and evaluates it on 8 held-out media (seeds 90000 +
+k) with the centre point source: FGMRES(20) iterations to 1e-7 with M_CU,
+with M_VU and with plain SL.
 """
 from __future__ import annotations
 
@@ -49,6 +55,60 @@ def evaluate(enc, sol, n, seed, nrhs, dev):
             float(np.mean([s["iterations"] for s in st_sl])))
 
 
+def evaluate_plain(net, n, dev, media=8):
+    """Per held-out medium (seeds 90000 + k, centre source): iterations of
+    FGMRES(20) to 1e-7 with M_CU, M_VU (the plain network, maxit 2000, no
+    fallback) and plain SL."""
+    out = []
+    for k in range(media):
+        h = make_medium(n, 90000 + k, dev)
+        b = torch.from_numpy(inputs.point_source(n)[None]).to(dev)
+        row = {"seed": 90000 + k}
+        for name, prec in (("M_CU", "unet_cgc"), ("M_VU", "unet_defl"), ("M_V", "sl")):
+            _, st, rc = helm.fgmres_solve([h], [b], m=20, tol=1e-7, maxit=2000, prec=prec,
+                                          net=None if prec == "sl" else net)
+            row[name] = st[0]["iterations"] if rc == 0 else None
+        out.append(row)
+        print(f"[pretrain] held-out medium {90000 + k}: " +
+              ", ".join(f"{k2} {v}" for k2, v in row.items() if k2 != "seed"), flush=True)
+    return out
+
+
+def main_plain(a, dev):
+    t_start = time.perf_counter()
+    handles = [make_medium(a.n, 10000 + i, dev) for i in range(a.media)]
+    torch.cuda.synchronize()
+    print(f"[pretrain] {a.media} media of {a.n}^2 ready ({time.perf_counter() - t_start:.1f} s)", flush=True)
+    net = unet.UNet()
+    if a.resume:
+        net.load_state(a.resume)
+    else:
+        net.init(a.seed)
+    ks = a.ksteps if a.ksteps == "random" else int(a.ksteps)
+    budget = a.minutes * 60.0
+    t0 = time.perf_counter()
+    step, chunk, hist = 0, 500, []
+    while step < a.max_steps and time.perf_counter() - t0 < budget:
+        k = min(chunk, a.max_steps - step)
+        # consecutive chunks continue the same run: the data cursor lives in the network
+        losses = train.train(net, handles, steps=k, batch=a.batch, lr=a.lr, seed=a.seed, per_medium=a.per_medium,
+                             ksteps=ks, resume=step > 0 or bool(a.resume))
+        step += len(losses)
+        hist.extend(losses)
+        print(f"[pretrain] step {step} loss {np.mean(hist[-chunk:]):.4e} ({time.perf_counter() - t0:.0f} s)",
+              flush=True)
+    net.save_state(a.out)
+    torch.cuda.synchronize()
+    print(f"[pretrain] {step} steps in {time.perf_counter() - t0:.0f} s; saved {a.out}", flush=True)
+    rows = evaluate_plain(net, a.n, dev)
+    for name in ("M_CU", "M_VU", "M_V"):
+        v = [r[name] for r in rows]
+        ok = [x for x in v if x is not None]
+        print(f"[pretrain] {name}: mean {np.mean(ok) if ok else float('nan'):.1f} iterations over {len(ok)} of "
+              f"{len(v)} media converged", flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=512)
@@ -65,8 +125,12 @@ def main(argv=None):
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--save-every", type=float, default=120.0)
     ap.add_argument("--log-every", type=int, default=500)
+    ap.add_argument("--plain", action="store_true", help="train one plain U-Net (M_CU's network)")
+    ap.add_argument("--ksteps", default="1", help="FGMRES steps k of eq. 3.8: an int or 'random' (1..10)")
     a = ap.parse_args(argv)
     dev = torch.device("cuda:0")
+    if a.plain:
+        return main_plain(a, dev)
     t_start = time.perf_counter()
     handles = [make_medium(a.n, 10000 + i, dev) for i in range(a.media)]
     torch.cuda.synchronize()
