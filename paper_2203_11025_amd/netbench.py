@@ -1,7 +1,7 @@
 """Timing of one part of the solve in isolation, for profiling under
 rocprofv3 (kernel trace or counters):
 
-    python -m paper_2203_11025_amd.netbench [--mode net|sl|uneven|retrain] [--workload multi1024]
+    python -m paper_2203_11025_amd.netbench [--mode net|sl|uneven|retrain|papernet] [--workload multi1024]
         [--nrhs 32] [--reps 10] [--autotune] [--graph] [--copy-probe MIB]
 
 --mode net: one application is unet_infer on nrhs residuals (restriction,
@@ -15,6 +15,11 @@ the medium (batch 16, k of eq. 3.8 drawn from 1..10 per sample, lr 1e-3:
 the benchmark's retraining), after one untimed step; prints the split of a
 step between the triples and the Adam step, and the rates of the weight-
 gradient and the other convolutions from the library's timing hook.
+--mode papernet: the paper's network (section 3.1; widths 16..128, 4
+levels) on an n x n grid (--n, default 128) for a batch of --nrhs samples:
+milliseconds per inference forward pass and per training step (forward,
+loss, backward, Adam), with the convolutions' FLOPs counted as 2 per
+multiply-add.
 --mode uneven: the uneven batch (--workload uneven24 or uneven6: many
 layered media of 256^2..2048^2, 8 point sources each) solved in one
 helm_fgmres_solve call, first with the encoder-solver M_VU (each medium
@@ -45,8 +50,9 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
-    ap.add_argument("--mode", default="net", choices=["net", "sl", "uneven", "retrain"])
+    ap.add_argument("--mode", default="net", choices=["net", "sl", "uneven", "retrain", "papernet"])
     ap.add_argument("--graph", action="store_true")
+    ap.add_argument("--n", type=int, default=128, help="--mode papernet: fine grid")
     ap.add_argument("--uneven-prec", default="both", choices=["both", "unet", "sl"],
                     help="--mode uneven: which solves to time")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
@@ -67,6 +73,8 @@ def main(argv=None):
         return uneven(a)
     if a.mode == "retrain":
         return retrain(a)
+    if a.mode == "papernet":
+        return papernet(a)
     P = inputs.config_problem(a.workload)
     h = helm.Handle(torch.from_numpy(P["kappa"]).cuda(), torch.from_numpy(P["gamma"]).cuda(), P["omega"],
                     levels=P["levels"])
@@ -153,6 +161,61 @@ def retrain(a):
                       "ms_adam_step": t_step * 1e3 / a.reps, "autotune": a.autotune,
                       "wgrad_ms_per_step": wms / a.reps, "wgrad_tflops": ww / (wms * 1e-3) / 1e12 if wms else None,
                       "conv_ms_per_step": cms / a.reps, "conv_tflops": cw / (cms * 1e-3) / 1e12 if cms else None}))
+    return 0
+
+
+def papernet_flops(n, widths=(16, 32, 64, 128), cin=4, cout=2, coarsest_blocks=3):
+    """FLOPs of one forward pass of the paper's network for one sample."""
+    L = len(widths)
+    f, c = 0.0, cin
+    for l in range(1, L + 1):
+        m = (n >> l) ** 2
+        f += 2 * 25 * c * widths[l - 1] * m  # 5x5 stride-2 convolution
+        f += (coarsest_blocks if l == L else 1) * 2 * (2 * 9 * widths[l - 1] ** 2 * m)  # ResNet blocks
+        c = widths[l - 1]
+    ch = widths[L - 1]
+    for l in range(L - 1, 0, -1):  # transposed 5x5: every input point scatters to K^2 outputs
+        f += 2 * 25 * ch * widths[l - 1] * (n >> (l + 1)) ** 2
+        ch = 2 * widths[l - 1]
+    f += 2 * 25 * ch * cout * (n >> 1) ** 2
+    return f
+
+
+def papernet(a):
+    import numpy as np
+    import torch
+
+    from . import helm, inputs, unet
+
+    n, B = a.n, a.nrhs
+    widths = (16, 32, 64, 128)
+    net = unet.UNet(widths=widths, arch=1)
+    net.init(1)
+    rng = np.random.default_rng(5)
+    x = torch.from_numpy(rng.standard_normal((B, 4, n, n), dtype=np.float32)).cuda()
+    net.forward(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.reps):
+        net.forward(x)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / a.reps
+    kap = torch.from_numpy(inputs.smooth_medium(n, max(2.0, n / 16), seed=1)).cuda()
+    gam = torch.from_numpy(inputs.sponge_gamma(n, width=min(16, n // 8))).cuda()
+    r = torch.from_numpy((rng.standard_normal((B, n, n)) + 1j * rng.standard_normal((B, n, n))).astype(np.complex64)).cuda()
+    e = torch.from_numpy((rng.standard_normal((B, n, n)) + 1j * rng.standard_normal((B, n, n))).astype(np.complex64)).cuda()
+    net.train_step(r, e, None, lr=1e-4, kappa_f=kap, gamma_f=gam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.reps):
+        net.train_step(r, e, None, lr=1e-4, kappa_f=kap, gamma_f=gam)
+        print(f"[netbench] papernet train step {i}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / a.reps
+    f = papernet_flops(n, widths) * B
+    print(json.dumps({"mode": "papernet", "n": n, "batch": B, "reps": a.reps, "gflop_forward": f / 1e9,
+                      "ms_forward": t_fwd * 1e3, "tflops_forward": f / t_fwd / 1e12,
+                      "ms_train_step": t_train * 1e3, "tflops_train_step": 3 * f / t_train / 1e12}))
     return 0
 
 
