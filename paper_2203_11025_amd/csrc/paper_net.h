@@ -53,9 +53,15 @@ struct PaperNet {
     std::vector<PTensor> T;
     std::vector<POp> ops;
     int x0t = -1, outt = -1;
-    double *sq = nullptr, *part = nullptr, *red = nullptr;
+    double *sq = nullptr, *part = nullptr, *red = nullptr, *rpart = nullptr;
     float *dlast = nullptr, *dlast_buf = nullptr;
     size_t dlast_n = 0;
+    float *wpk = nullptr;  // repacked weights of one gather
+    float *wgp = nullptr;  // weight-gradient partials
+    void wgrad(const float *co, int coC, int coOff, int Cc, int Hc, const float *fi, int fiC, int fiOff, int Cf, int Hf,
+               int s, int K, int pad, int B, float *dW, hipStream_t st);
+    void gather(int mode, const float *in, int inC, int inOff, int Cin, int Hin, const float *W, float *out,
+                int outC, int outOff, int Cout, int Hout, int s, int K, int pad, int acc, int B, hipStream_t st);
 
     ~PaperNet();
     void build(const int *widths, int levels, int in_ch, int out_ch, int coarsest_blocks);

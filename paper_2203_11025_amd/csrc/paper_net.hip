@@ -15,10 +15,8 @@
 //   gather to fine:   fine(i) = sum W coarse((i + pad - a) / s) (transposed
 //                     convolution; data gradient of a convolution)
 //   weight gradient:  dW[a] = sum coarse(I) fine(s I + a - pad)
-// A workgroup owns one (sample, output channel) pair, so its weight reads
-// are uniform across the workgroup.  BN statistics and every reduction
-// accumulate in FP64 in a fixed order.  These are plain VALU kernels: the
-// network is small and runs on the 128^2 grid of the paper's experiments.
+// The two gathers run as implicit GEMMs on FP32 MFMA; the weight gradient,
+// BN statistics and every reduction accumulate in FP64 in a fixed order.
 #include <cmath>
 #include <string>
 #include <vector>
@@ -32,6 +30,7 @@ namespace helm {
 namespace {
 
 constexpr int PN_T = 256;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double pn_wsum(double v)
 {
@@ -51,126 +50,414 @@ __device__ __forceinline__ double pn_bsum(double v, double *sh)
     return t;
 }
 
-// out (+)= gather to coarse; grid (tiles of Hc*Wc, B*Cc)
-__global__ __launch_bounds__(PN_T) void k_pn_gc(const float *__restrict__ in, int inC, int inOff, int Cf, int Hf,
-                                                int Wf, const float *__restrict__ W, float *__restrict__ out,
-                                                int outC, int outOff, int Cc, int Hc, int Wc, int s, int K, int pad,
-                                                int acc)
+// ------------------------------------------------------------ MFMA gathers
+// The two gathers as implicit GEMMs on FP32 MFMA (v_mfma_f32_16x16x4_f32:
+// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16], and rows
+// 4 (l / 16) .. + 3 of column l % 16 of D).  The output points form
+// lattices on which every tap is a plain offset: a gather to coarse has one
+// lattice, the coarse grid, with input point s (Y, X) + (a - pad, c - pad);
+// a gather to fine with s = 2 splits the fine grid into the four classes
+// (py, px) = (i % 2, j % 2), each the lattice (Y, X) -> (2 Y + py, 2 X + px),
+// reached by the taps a = py + pad (mod 2) with input point (Y, X) +
+// ((py + pad - a) / 2, (px + pad - c) / 2); with s = 1 the offsets are
+// (pad - a, pad - c).  Per class the GEMM is
+//   D[out channel][point] = sum over (in channel, tap) of Wp[in][tap][out] X[in][point + offset(tap)],
+// Wp the weights repacked so that output channels are contiguous.  A
+// workgroup (4 wavefronts; wavefront w owns output channels 16 w .. + 15 of
+// a block of 64) owns an 8 x 16 tile of one lattice (8 pixel fragments, one
+// per lattice row) and walks the input channels four at a time (one MFMA K
+// step per tap): the input patch under the tile and the chunk's weights go
+// to LDS, the next chunk's loads are in flight in registers during the
+// current chunk's MFMAs (two LDS buffers, one barrier per chunk), and each
+// tap costs a wavefront one A read, 8 B reads and 8 MFMAs.
+constexpr int PM_TY = 8, PM_TX = 16, PM_CI = 4, PM_CO = 64;
+
+struct PmArgs {
+    const float *in;
+    int inC, inOff, Cin, Hin, Win;
+    const float *Wp;  // [Cin][K * K][Cout]
+    float *out;
+    int outC, outOff, Cout, Hout, Wout;
+    int mode, s, K, pad, acc;  // mode 0: gather to coarse, 1: gather to fine
+    int tiles_x, tiles_per_class;
+};
+
+// Wp[i][t][o] = W[o * wco + i * wci + t] for t < K * K
+__global__ void k_pn_wpack(const float *__restrict__ W, int Cout, int Cin, int KK, int wco, int wci,
+                           float *__restrict__ Wp)
 {
-    const int b = blockIdx.y / Cc, oc = blockIdx.y - b * Cc;
-    const int q = blockIdx.x * PN_T + threadIdx.x;
-    if (q >= Hc * Wc) return;
-    const int I = q / Wc, J = q - I * Wc;
-    const float *w = W + (size_t)oc * Cf * K * K;
-    const float *x = in + ((size_t)b * inC + inOff) * Hf * Wf;
-    float sum = 0.f;
-    for (int fc = 0; fc < Cf; ++fc) {
-        const float *xf = x + (size_t)fc * Hf * Wf;
-        const float *wf = w + (size_t)fc * K * K;
-        for (int a = 0; a < K; ++a) {
-            const int i = s * I + a - pad;
-            if (i < 0 || i >= Hf) continue;
-            for (int c = 0; c < K; ++c) {
-                const int j = s * J + c - pad;
-                if (j < 0 || j >= Wf) continue;
-                sum = fmaf(wf[a * K + c], xf[(size_t)i * Wf + j], sum);
-            }
-        }
+    const size_t n = (size_t)Cin * KK * Cout;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int o = (int)(e % Cout);
+        const size_t r = e / Cout;
+        const int t = (int)(r % KK), i = (int)(r / KK);
+        Wp[e] = W[(size_t)o * wco + (size_t)i * wci + t];
     }
-    float *o = out + (((size_t)b * outC + outOff + oc) * Hc + I) * Wc + J;
-    *o = acc ? *o + sum : sum;
 }
 
-// out (+)= gather to fine; grid (tiles of Hf*Wf, B*Cf)
-__global__ __launch_bounds__(PN_T) void k_pn_gf(const float *__restrict__ in, int inC, int inOff, int Cc, int Hc,
-                                                int Wc, const float *__restrict__ W, float *__restrict__ out,
-                                                int outC, int outOff, int Cf, int Hf, int Wf, int s, int K, int pad,
-                                                int acc)
+// IS: input step of the lattice (s for a gather to coarse, else 1); MAXT:
+// taps of a class at most; PHM x PWM: the largest input patch of a tile
+template <int IS, int MAXT, int PHM, int PWM>
+__global__ __launch_bounds__(256, 2) void k_pn_mm(PmArgs g)
 {
-    const int b = blockIdx.y / Cf, fc = blockIdx.y - b * Cf;
-    const int q = blockIdx.x * PN_T + threadIdx.x;
-    if (q >= Hf * Wf) return;
-    const int i = q / Wf, j = q - i * Wf;
-    const float *x = in + ((size_t)b * inC + inOff) * Hc * Wc;
-    float sum = 0.f;
-    for (int cc = 0; cc < Cc; ++cc) {
-        const float *xc = x + (size_t)cc * Hc * Wc;
-        const float *wc = W + ((size_t)cc * Cf + fc) * K * K;
-        for (int a = 0; a < K; ++a) {
-            const int ti = i + pad - a;
-            if (ti < 0 || ti % s) continue;
-            const int I = ti / s;
-            if (I >= Hc) continue;
-            for (int c = 0; c < K; ++c) {
-                const int tj = j + pad - c;
-                if (tj < 0 || tj % s) continue;
-                const int J = tj / s;
-                if (J >= Wc) continue;
-                sum = fmaf(wc[a * K + c], xc[(size_t)I * Wc + J], sum);
+    constexpr int PS = PHM * PWM;                          // patch floats per channel
+    constexpr int NP = (PM_CI * PS + 255) / 256;           // patch loads per thread
+    constexpr int NW = (MAXT * PM_CI * PM_CO + 255) / 256;  // weight loads per thread
+    __shared__ float sP[2][PM_CI * PS];
+    __shared__ float sW[2][MAXT * PM_CI * PM_CO];
+    __shared__ int sT[MAXT];    // per tap: (dy + 64) | (dx + 64) << 8 | (a K + c) << 16
+    __shared__ int sI[3];       // taps, dymin, dxmin
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int cls = blockIdx.x / g.tiles_per_class, tile = blockIdx.x - cls * g.tiles_per_class;
+    const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
+    const int co0 = blockIdx.y * PM_CO, b = blockIdx.z;
+    const int os = g.mode == 0 ? 1 : g.s;
+    const int py = cls / os, px = cls - py * os;
+    const int LY = (g.Hout - py + os - 1) / os, LX = (g.Wout - px + os - 1) / os;
+    const int Y0 = ty * PM_TY, X0 = tx * PM_TX;
+    if (tid == 0) {
+        int nt = 0, dymin = 1 << 20, dxmin = 1 << 20;
+        for (int a = 0; a < g.K; ++a) {
+            int dy;
+            if (g.mode == 0) {
+                dy = a - g.pad;
+            } else {
+                const int q = py + g.pad - a;
+                if (((q % g.s) + g.s) % g.s) continue;
+                dy = q / g.s;
+            }
+            for (int c = 0; c < g.K; ++c) {
+                int dx;
+                if (g.mode == 0) {
+                    dx = c - g.pad;
+                } else {
+                    const int q = px + g.pad - c;
+                    if (((q % g.s) + g.s) % g.s) continue;
+                    dx = q / g.s;
+                }
+                if (nt < MAXT) sT[nt++] = (dy + 64) | ((dx + 64) << 8) | ((a * g.K + c) << 16);
+                dymin = min(dymin, dy);
+                dxmin = min(dxmin, dx);
             }
         }
+        sI[0] = nt;
+        sI[1] = dymin;
+        sI[2] = dxmin;
     }
-    float *o = out + (((size_t)b * outC + outOff + fc) * Hf + i) * Wf + j;
-    *o = acc ? *o + sum : sum;
+    __syncthreads();
+    const int nt = sI[0], dymin = sI[1], dxmin = sI[2];
+    const int row0 = IS * Y0 + dymin, col0 = IS * X0 + dxmin;
+    const float *inb = g.in + ((size_t)b * g.inC + g.inOff) * g.Hin * g.Win;
+    float pp[NP], pw[NW];
+    // global loads of chunk ic0 into registers (zero outside the image, the
+    // input channels or the output channels)
+    auto load = [&](int ic0) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const int e = tid + 256 * q;
+            float v = 0.f;
+            if (e < PM_CI * PS) {
+                const int ch = e / PS, rem = e - ch * PS, r = rem / PWM, c = rem - r * PWM;
+                const int ic = ic0 + ch, y = row0 + r, x = col0 + c;
+                if (ic < g.Cin && y >= 0 && y < g.Hin && x >= 0 && x < g.Win)
+                    v = inb[((size_t)ic * g.Hin + y) * g.Win + x];
+            }
+            pp[q] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const int e = tid + 256 * q;
+            float v = 0.f;
+            if (e < MAXT * PM_CI * PM_CO) {
+                const int o = e % PM_CO, ic = (e / PM_CO) % PM_CI, t = e / (PM_CO * PM_CI);
+                if (t < nt && ic0 + ic < g.Cin && co0 + o < g.Cout)
+                    v = g.Wp[((size_t)(ic0 + ic) * g.K * g.K + (sT[t] >> 16)) * g.Cout + co0 + o];
+            }
+            pw[q] = v;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const int e = tid + 256 * q;
+            if (e < PM_CI * PS) sP[buf][e] = pp[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const int e = tid + 256 * q;
+            if (e < MAXT * PM_CI * PM_CO) sW[buf][e] = pw[q];
+        }
+    };
+    f32x4 acc[PM_TY];
+#pragma unroll
+    for (int f = 0; f < PM_TY; ++f) acc[f] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nch = (g.Cin + PM_CI - 1) / PM_CI;
+    load(0);
+    store(0);
+    __syncthreads();
+    const int k = lane >> 4, j = lane & 15;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        const bool more = ch + 1 < nch;
+        if (more) load((ch + 1) * PM_CI);
+        const float *P = &sP[buf][k * PS + IS * j];
+        const float *Wb = &sW[buf][k * PM_CO + wv * 16 + j];
+        for (int t = 0; t < nt; ++t) {
+            const int tv = sT[t];
+            const int dy = (tv & 255) - 64 - dymin, dx = ((tv >> 8) & 255) - 64 - dxmin;
+            const float a = Wb[t * PM_CI * PM_CO];
+            const float *Pt = P + dy * PWM + dx;
+#pragma unroll
+            for (int f = 0; f < PM_TY; ++f)
+                acc[f] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Pt[IS * f * PWM], acc[f], 0, 0, 0);
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+    }
+    // lane holds output channels co0 + 16 wv + 4 k .. + 3 at lattice point (Y0 + f, X0 + j)
+    const int X = X0 + j;
+    if (X >= LX) return;
+#pragma unroll
+    for (int f = 0; f < PM_TY; ++f) {
+        const int Y = Y0 + f;
+        if (Y >= LY) continue;
+        const int oy = os * Y + py, ox = os * X + px;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int oc = co0 + wv * 16 + 4 * k + r;
+            if (oc >= g.Cout) continue;
+            float *o = g.out + (((size_t)b * g.outC + g.outOff + oc) * g.Hout + oy) * g.Wout + ox;
+            *o = g.acc ? *o + acc[f][r] : acc[f][r];
+        }
+    }
 }
 
-// dW[cc][fc][a][c] += sum over samples and coarse points of coarse * fine;
-// one workgroup per (cc, fc), K*K FP64 accumulators per thread
-template <int K>
-__global__ __launch_bounds__(PN_T) void k_pn_wg(const float *__restrict__ co, int coC, int coOff, int Cc, int Hc,
-                                                int Wc, const float *__restrict__ fi, int fiC, int fiOff, int Cf,
-                                                int Hf, int Wf, int B, int s, int pad, float *__restrict__ dW)
+// ------------------------------------------------------- MFMA weight gradient
+// dW[cc][fc][a][c] = sum over samples and coarse points (I, J) of
+// co[cc](I, J) fi[fc](s I + a - pad, s J + c - pad), per tap a GEMM over the
+// points: D[cc][fc] += sum_p co[cc][p] fi_tap[fc][p] on FP32 MFMA (K step: 4
+// consecutive points of a tile row).  A workgroup (4 wavefronts; wavefront w
+// owns coarse channels 16 w .. + 15 of a block of 64, all K * K taps) owns 16
+// fine channels and a range of 8 x 16 point tiles (split over the points);
+// per tile the coarse values and the fine patch under the tile go to LDS,
+// the next tile's loads in flight in registers during the MFMAs.  Partial
+// sums per split, reduced in a fixed order by k_pn_wsum.  With K = 5 the 25
+// taps' accumulators leave no registers for the prefetch, and a tile's
+// staging waits for its loads after the barrier (the tile's 800 MFMAs per
+// wavefront cover that).
+constexpr int PW_TY = 8, PW_TX = 16, PW_CC = 64, PW_FC = 16, PW_SC = PW_TY * PW_TX + 4;
+
+template <int S, int K>
+__global__ __launch_bounds__(256, 2) void k_pn_mmw(const float *__restrict__ co, int coC, int coOff, int Cc, int Hc,
+                                                   const float *__restrict__ fi, int fiC, int fiOff, int Cf, int Hf,
+                                                   int pad, int tiles_x, int tiles_per_sample, int ntiles,
+                                                   int per_split, float *__restrict__ part)
 {
-    const int cc = blockIdx.x / Cf, fc = blockIdx.x - cc * Cf;
-    double acc[K * K];
+    constexpr int KK = K * K;
+    constexpr int PH = S * (PW_TY - 1) + K, PWD = S * (PW_TX - 1) + K;  // fine patch under a tile
+    constexpr int PSF = PH * PWD;
+    constexpr bool PF = K <= 3;                         // prefetch the next tile in registers
+    constexpr int NC = PF ? PW_CC * PW_TY * PW_TX / 256 : 1;  // coarse loads per thread
+    constexpr int NF = PF ? (PW_FC * PSF + 255) / 256 : 1;    // fine loads per thread
+    __shared__ float sC[PW_CC * PW_SC];
+    __shared__ float sF[PW_FC * PSF];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ncb = (Cc + PW_CC - 1) / PW_CC;
+    const int cc0 = (blockIdx.y % ncb) * PW_CC, fc0 = (blockIdx.y / ncb) * PW_FC;
+    const int t_begin = blockIdx.x * per_split, t_end = min(ntiles, t_begin + per_split);
+    f32x4 acc[KK];
 #pragma unroll
-    for (int t = 0; t < K * K; ++t) acc[t] = 0.0;
-    const size_t per = (size_t)Hc * Wc;
-    for (size_t q = threadIdx.x; q < (size_t)B * per; q += PN_T) {
-        const int b = (int)(q / per);
-        const int r = (int)(q - (size_t)b * per), I = r / Wc, J = r - I * Wc;
-        const float g = co[(((size_t)b * coC + coOff + cc) * Hc + I) * Wc + J];
-        if (g == 0.f) continue;
-        const float *xf = fi + ((size_t)b * fiC + fiOff + fc) * Hf * Wf;
+    for (int t = 0; t < KK; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float pc[NC], pf[NF];
+    // the tile's values straight into LDS (no prefetch)
+    auto stage = [&](int tl) {
+        const int b = tl / tiles_per_sample, r = tl - b * tiles_per_sample;
+        const int Y0 = (r / tiles_x) * PW_TY, X0 = (r - (r / tiles_x) * tiles_x) * PW_TX;
+        const float *cb = co + ((size_t)b * coC + coOff) * Hc * Hc;
+        const float *fb = fi + ((size_t)b * fiC + fiOff) * Hf * Hf;
+        for (int e = tid; e < PW_CC * PW_TY * PW_TX; e += 256) {
+            const int c = e / (PW_TY * PW_TX), p = e - c * (PW_TY * PW_TX);
+            const int Y = Y0 + p / PW_TX, X = X0 + p % PW_TX;
+            float v = 0.f;
+            if (cc0 + c < Cc && Y < Hc && X < Hc) v = cb[((size_t)(cc0 + c) * Hc + Y) * Hc + X];
+            sC[c * PW_SC + p] = v;
+        }
+        const int y0 = S * Y0 - pad, x0 = S * X0 - pad;
+        for (int e = tid; e < PW_FC * PSF; e += 256) {
+            const int c = e / PSF, rem = e - c * PSF, rr = rem / PWD, cl = rem - rr * PWD;
+            const int y = y0 + rr, x = x0 + cl;
+            float v = 0.f;
+            if (fc0 + c < Cf && y >= 0 && y < Hf && x >= 0 && x < Hf) v = fb[((size_t)(fc0 + c) * Hf + y) * Hf + x];
+            sF[e] = v;
+        }
+    };
+    auto load = [&](int tl) {
+        const int b = tl / tiles_per_sample, r = tl - b * tiles_per_sample;
+        const int Y0 = (r / tiles_x) * PW_TY, X0 = (r - (r / tiles_x) * tiles_x) * PW_TX;
+        const float *cb = co + ((size_t)b * coC + coOff) * Hc * Hc;
+        const float *fb = fi + ((size_t)b * fiC + fiOff) * Hf * Hf;
 #pragma unroll
-        for (int a = 0; a < K; ++a) {
-            const int i = s * I + a - pad;
+        for (int q = 0; q < NC; ++q) {
+            const int e = tid + 256 * q;
+            const int c = e / (PW_TY * PW_TX), p = e - c * (PW_TY * PW_TX);
+            const int Y = Y0 + p / PW_TX, X = X0 + p % PW_TX;
+            float v = 0.f;
+            if (cc0 + c < Cc && Y < Hc && X < Hc) v = cb[((size_t)(cc0 + c) * Hc + Y) * Hc + X];
+            pc[q] = v;
+        }
+        const int y0 = S * Y0 - pad, x0 = S * X0 - pad;
 #pragma unroll
-            for (int c = 0; c < K; ++c) {
-                const int j = s * J + c - pad;
-                if (i >= 0 && i < Hf && j >= 0 && j < Wf) acc[a * K + c] += (double)g * xf[(size_t)i * Wf + j];
+        for (int q = 0; q < NF; ++q) {
+            const int e = tid + 256 * q;
+            float v = 0.f;
+            if (e < PW_FC * PSF) {
+                const int c = e / PSF, rem = e - c * PSF, rr = rem / PWD, cl = rem - rr * PWD;
+                const int y = y0 + rr, x = x0 + cl;
+                if (fc0 + c < Cf && y >= 0 && y < Hf && x >= 0 && x < Hf)
+                    v = fb[((size_t)(fc0 + c) * Hf + y) * Hf + x];
             }
+            pf[q] = v;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const int e = tid + 256 * q;
+            const int c = e / (PW_TY * PW_TX), p = e - c * (PW_TY * PW_TX);
+            sC[c * PW_SC + p] = pc[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+            const int e = tid + 256 * q;
+            if (e < PW_FC * PSF) sF[e] = pf[q];
+        }
+    };
+    const int k = lane >> 4, j = lane & 15;
+    if (t_begin < t_end) {
+        if constexpr (PF) {
+            load(t_begin);
+            store();
+        } else {
+            stage(t_begin);
         }
     }
-    __shared__ double sh[4];
+    __syncthreads();
+    for (int tl = t_begin; tl < t_end; ++tl) {
+        const bool more = tl + 1 < t_end;
+        if constexpr (PF)
+            if (more) load(tl + 1);
+        // points p = 4 q + k of the tile: row p / 16, column p % 16
+        const float *Cw = &sC[(wv * 16 + j) * PW_SC + k];
+        const float *Fj = &sF[j * PSF];
+#pragma unroll 2
+        for (int q = 0; q < PW_TY * PW_TX / 4; ++q) {
+            const int p = 4 * q + k, py = p / PW_TX, px = p % PW_TX;
+            const float a = Cw[4 * q];
+            const float *Fp = Fj + S * py * PWD + S * px;
 #pragma unroll
-    for (int t = 0; t < K * K; ++t) {
-        const double v = pn_bsum(acc[t], sh);
-        if (threadIdx.x == 0) dW[((size_t)cc * Cf + fc) * K * K + t] += (float)v;
+            for (int ta = 0; ta < K; ++ta)
+#pragma unroll
+                for (int tc = 0; tc < K; ++tc)
+                    acc[ta * K + tc] =
+                        __builtin_amdgcn_mfma_f32_16x16x4f32(a, Fp[ta * PWD + tc], acc[ta * K + tc], 0, 0, 0);
+        }
+        if (more) {
+            __syncthreads();  // every wavefront is done with this tile
+            if constexpr (PF)
+                store();
+            else
+                stage(tl + 1);
+            __syncthreads();
+        }
+    }
+    // D[cc][fc]: lane holds fine channel fc0 + j and coarse channels cc0 + 16 wv + 4 k .. + 3
+    const size_t per = (size_t)Cc * Cf * KK;
+#pragma unroll
+    for (int t = 0; t < KK; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int cc = cc0 + wv * 16 + 4 * k + r, fc = fc0 + j;
+            if (cc < Cc && fc < Cf) part[blockIdx.x * per + ((size_t)cc * Cf + fc) * KK + t] = acc[t][r];
+        }
+}
+
+// dW[e] += sum over splits of part[split][e] (FP64, split order)
+__global__ void k_pn_wsum(const float *__restrict__ part, int nsplit, size_t n, float *__restrict__ dW)
+{
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int q = 0; q < nsplit; ++q) s += part[(size_t)q * n + e];
+        dW[e] += (float)s;
     }
 }
 
 // BN statistics of channel c (blockIdx.x) over B x HW: mean, var (biased),
 // and the scale / shift of the batch normalisation with weight g, bias bb
-__global__ __launch_bounds__(PN_T) void k_pn_bn_stats(const float *__restrict__ y, int yC, int yOff, int B, int HW,
-                                                      const float *__restrict__ g, const float *__restrict__ bb,
-                                                      float eps, float *__restrict__ mean, float *__restrict__ var,
-                                                      float *__restrict__ rstd, float *__restrict__ sc,
-                                                      float *__restrict__ sf)
+// The per-channel reductions over B x HW values run in nsplit contiguous
+// ranges per channel (grid (nsplit, C)), each block writing its FP64 pair
+// to part[(c nsplit + split) 2 + k]; k_pn_psum adds a channel's pairs in
+// split order.
+__device__ __forceinline__ void pn_range(int B, int HW, int nsplit, size_t &q0, size_t &q1)
 {
-    const int c = blockIdx.x;
+    const size_t N = (size_t)B * HW, per = (N + nsplit - 1) / nsplit;
+    q0 = (size_t)blockIdx.x * per;
+    q1 = q0 + per < N ? q0 + per : N;
+}
+
+__device__ __forceinline__ void pn_put(double s1, double s2, int nsplit, double *part)
+{
+    __shared__ double sh[4];
+    s1 = pn_bsum(s1, sh);
+    s2 = pn_bsum(s2, sh);
+    if (threadIdx.x == 0) {
+        const size_t o = ((size_t)blockIdx.y * nsplit + blockIdx.x) * 2;
+        part[o] = s1;
+        part[o + 1] = s2;
+    }
+}
+
+// sums[2 c + k] = sum over splits of part (thread per channel)
+__global__ void k_pn_psum(const double *__restrict__ part, int nsplit, int C, double *__restrict__ sums)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
     double s1 = 0.0, s2 = 0.0;
-    for (size_t q = threadIdx.x; q < (size_t)B * HW; q += PN_T) {
+    for (int q = 0; q < nsplit; ++q) {
+        s1 += part[((size_t)c * nsplit + q) * 2];
+        s2 += part[((size_t)c * nsplit + q) * 2 + 1];
+    }
+    sums[2 * c] = s1;
+    sums[2 * c + 1] = s2;
+}
+
+// partial sums of y and y^2 of channel blockIdx.y
+__global__ __launch_bounds__(PN_T) void k_pn_bn_stats(const float *__restrict__ y, int yC, int yOff, int B, int HW,
+                                                      int nsplit, double *__restrict__ part)
+{
+    const int c = blockIdx.y;
+    size_t q0, q1;
+    pn_range(B, HW, nsplit, q0, q1);
+    double s1 = 0.0, s2 = 0.0;
+    for (size_t q = q0 + threadIdx.x; q < q1; q += PN_T) {
         const size_t b = q / HW, p = q - b * HW;
         const double v = y[((b * yC) + yOff + c) * HW + p];
         s1 += v;
         s2 += v * v;
     }
-    __shared__ double sh[4];
-    s1 = pn_bsum(s1, sh);
-    s2 = pn_bsum(s2, sh);
-    if (threadIdx.x == 0) {
-        const double N = (double)B * HW, m = s1 / N, vv = std::max(s2 / N - m * m, 0.0);
+    pn_put(s1, s2, nsplit, part);
+}
+
+// mean, var (biased), rstd and the BN scale / shift from the sums (thread per channel)
+__global__ void k_pn_bn_stats_fin(const double *__restrict__ sums, int C, double N, const float *__restrict__ g,
+                                  const float *__restrict__ bb, float eps, float *__restrict__ mean,
+                                  float *__restrict__ var, float *__restrict__ rstd, float *__restrict__ sc,
+                                  float *__restrict__ sf)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const double s1 = sums[2 * c], s2 = sums[2 * c + 1];
+    {
+        const double m = s1 / N, vv = std::max(s2 / N - m * m, 0.0);
         const double r = 1.0 / std::sqrt(vv + (double)eps);
         mean[c] = (float)m;
         var[c] = (float)vv;
@@ -201,12 +488,14 @@ __global__ __launch_bounds__(PN_T) void k_pn_bn_bsum(const float *__restrict__ d
                                                      const float *__restrict__ a, int aC, int aOff,
                                                      const float *__restrict__ y, int yC, int yOff, int B, int HW,
                                                      const float *__restrict__ mean, const float *__restrict__ rstd,
-                                                     int act, double *__restrict__ red)
+                                                     int act, int nsplit, double *__restrict__ part)
 {
-    const int c = blockIdx.x;
+    const int c = blockIdx.y;
+    size_t q0, q1;
+    pn_range(B, HW, nsplit, q0, q1);
     double s1 = 0.0, s2 = 0.0;
     const float m = mean[c], r = rstd[c];
-    for (size_t q = threadIdx.x; q < (size_t)B * HW; q += PN_T) {
+    for (size_t q = q0 + threadIdx.x; q < q1; q += PN_T) {
         const size_t b = q / HW, p = q - b * HW;
         float dz = dout[((b * dC) + dOff + c) * HW + p];
         if (act) {
@@ -217,13 +506,7 @@ __global__ __launch_bounds__(PN_T) void k_pn_bn_bsum(const float *__restrict__ d
         s1 += dz;
         s2 += (double)dz * yh;
     }
-    __shared__ double sh[4];
-    s1 = pn_bsum(s1, sh);
-    s2 = pn_bsum(s2, sh);
-    if (threadIdx.x == 0) {
-        red[2 * c] = s1;
-        red[2 * c + 1] = s2;
-    }
+    pn_put(s1, s2, nsplit, part);
 }
 
 // dy += g rstd (dz - sum dz / N - yhat sum dz yhat / N); grid (tiles, B*C)
@@ -291,19 +574,26 @@ __global__ void k_pn_bias(float *__restrict__ out, int C, int HW, const float *_
     if (p < HW) out[(size_t)blockIdx.y * HW + p] += bias[c];
 }
 
-// dbias[c] += sum over samples and points of dout (one block per channel)
-__global__ __launch_bounds__(PN_T) void k_pn_bias_g(const float *__restrict__ dout, int B, int C, int HW,
-                                                    float *__restrict__ db)
+// partial sums over samples and points of dout of channel blockIdx.y (the bias gradient)
+__global__ __launch_bounds__(PN_T) void k_pn_bias_g(const float *__restrict__ dout, int B, int C, int HW, int nsplit,
+                                                    double *__restrict__ part)
 {
-    const int c = blockIdx.x;
+    const int c = blockIdx.y;
+    size_t q0, q1;
+    pn_range(B, HW, nsplit, q0, q1);
     double s = 0.0;
-    for (size_t q = threadIdx.x; q < (size_t)B * HW; q += PN_T) {
+    for (size_t q = q0 + threadIdx.x; q < q1; q += PN_T) {
         const size_t b = q / HW, p = q - b * HW;
         s += dout[(b * C + c) * HW + p];
     }
-    __shared__ double sh[4];
-    s = pn_bsum(s, sh);
-    if (threadIdx.x == 0) db[c] += (float)s;
+    pn_put(s, 0.0, nsplit, part);
+}
+
+// db[c] += sums[2 c] (thread per channel)
+__global__ void k_pn_bias_fin(const double *__restrict__ sums, int C, float *__restrict__ db)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < C) db[c] += (float)sums[2 * c];
 }
 
 // network input: sample q reads field b = idx ? idx[q] : q, scaled by
@@ -396,6 +686,13 @@ __global__ __launch_bounds__(PN_T) void k_pn_loss(const float *__restrict__ out,
 
 int tiles(size_t n) { return (int)((n + PN_T - 1) / PN_T); }
 
+// ranges per channel of a reduction over n values: about 1024 blocks in all,
+// at most 64 per channel (so C nsplit <= 1024 for C <= 512), 1024 values each at least
+int pn_nsplit(int C, size_t n)
+{
+    return (int)std::max<size_t>(1, std::min<size_t>({(size_t)64, (size_t)(1024 / C), n / 1024}));
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ PaperNet
@@ -456,6 +753,53 @@ void PaperNet::build(const int *widths, int levels, int in_ch, int out_ch, int c
 
 PaperNet::~PaperNet() { free_all(); }
 
+// one gather (mode 0: to coarse, 1: to fine; see above) through the MFMA
+// kernel: the weights W[c_coarse][c_fine][K][K] are repacked output-channel
+// contiguous into wpk first
+void PaperNet::gather(int mode, const float *in, int inC, int inOff, int Cin, int Hin, const float *W, float *out,
+                      int outC, int outOff, int Cout, int Hout, int s, int K, int pad, int acc, int B, hipStream_t st)
+{
+    const int KK = K * K;
+    const int wco = mode == 0 ? Cin * KK : KK, wci = mode == 0 ? KK : Cout * KK;
+    const size_t nw = (size_t)Cin * KK * Cout;
+    hipLaunchKernelGGL(k_pn_wpack, dim3((unsigned)std::min<size_t>(1024, (nw + 255) / 256)), dim3(256), 0, st, W,
+                       Cout, Cin, KK, wco, wci, wpk);
+    PmArgs g{in, inC, inOff, Cin, Hin, Hin, wpk, out, outC, outOff, Cout, Hout, Hout, mode, s, K, pad, acc, 0, 0};
+    const int os = mode == 0 ? 1 : s;
+    const int L = (Hout + os - 1) / os;  // lattice side of class (0, 0), the largest
+    g.tiles_x = (L + PM_TX - 1) / PM_TX;
+    g.tiles_per_class = g.tiles_x * ((L + PM_TY - 1) / PM_TY);
+    const dim3 grid(g.tiles_per_class * os * os, (Cout + PM_CO - 1) / PM_CO, B);
+    if (mode == 0 && s == 2 && K == 5)
+        hipLaunchKernelGGL((k_pn_mm<2, 25, 19, 35>), grid, dim3(256), 0, st, g);
+    else  // mode 0 with s = 1, K = 3; mode 1 with s = 2, K = 5 or s = 1, K = 3 (checked at build)
+        hipLaunchKernelGGL((k_pn_mm<1, 9, 10, 18>), grid, dim3(256), 0, st, g);
+}
+
+// dW (+)= the weight gradient of one transfer or ResNet convolution (coarse
+// tensor co, fine tensor fi; see k_pn_mmw), split over the points so that
+// about 512 workgroups run
+void PaperNet::wgrad(const float *co, int coC, int coOff, int Cc, int Hc, const float *fi, int fiC, int fiOff, int Cf,
+                     int Hf, int s, int K, int pad, int B, float *dW, hipStream_t st)
+{
+    const int tiles_x = (Hc + PW_TX - 1) / PW_TX, tps = tiles_x * ((Hc + PW_TY - 1) / PW_TY);
+    const int ntiles = B * tps;
+    const int blocks = ((Cc + PW_CC - 1) / PW_CC) * ((Cf + PW_FC - 1) / PW_FC);
+    int nsplit = std::max(1, std::min(512 / blocks, ntiles));
+    const int per = (ntiles + nsplit - 1) / nsplit;
+    nsplit = (ntiles + per - 1) / per;
+    const size_t n = (size_t)Cc * Cf * K * K;
+    const dim3 grid(nsplit, blocks);
+    if (s == 2 && K == 5)
+        hipLaunchKernelGGL((k_pn_mmw<2, 5>), grid, dim3(256), 0, st, co, coC, coOff, Cc, Hc, fi, fiC, fiOff, Cf, Hf,
+                           pad, tiles_x, tps, ntiles, per, wgp);
+    else  // s = 1, K = 3 (checked at build)
+        hipLaunchKernelGGL((k_pn_mmw<1, 3>), grid, dim3(256), 0, st, co, coC, coOff, Cc, Hc, fi, fiC, fiOff, Cf, Hf,
+                           pad, tiles_x, tps, ntiles, per, wgp);
+    hipLaunchKernelGGL(k_pn_wsum, dim3((unsigned)std::min<size_t>(2048, (n + 255) / 256)), dim3(256), 0, st, wgp,
+                       nsplit, n, dW);
+}
+
 void PaperNet::free_ws()
 {
     for (auto &t : T) {
@@ -467,9 +811,11 @@ void PaperNet::free_ws()
     (void)dev_free(sq);
     (void)dev_free(part);
     (void)dev_free(red);
+    (void)dev_free(rpart);
     sq = nullptr;
     part = nullptr;
     red = nullptr;
+    rpart = nullptr;
     wsB = wsN = 0;
     wsTrain = false;
 }
@@ -479,14 +825,23 @@ void PaperNet::free_all()
     free_ws();
     (void)dev_free(bnf);
     (void)dev_free(dlast_buf);
-    bnf = dlast_buf = nullptr;
+    (void)dev_free(wpk);
+    (void)dev_free(wgp);
+    bnf = dlast_buf = wpk = wgp = nullptr;
 }
 
 // the BN scratch arrays; the parameters, their gradient, the Adam moments
 // and the buffers belong to the owning unet_net
 int PaperNet::alloc_params()
 {
-    if (dev_malloc(&bnf, std::max<size_t>(7 * (nbuf / 2), 1) * 4) != hipSuccess) {
+    size_t nw = 1;
+    for (const auto &l : layers) nw = std::max(nw, (size_t)l.ci * l.co * l.K * l.K);
+    // weight-gradient partials: at most 512 / blocks splits of Cc Cf K^2, so
+    // 512 x 64 x 16 x 25 floats, or one layer's weights when a layer has
+    // more than 512 blocks
+    const size_t np = std::max(nw, (size_t)512 * PW_CC * PW_FC * 25);
+    if (dev_malloc(&bnf, std::max<size_t>(7 * (nbuf / 2), 1) * 4) != hipSuccess ||
+        dev_malloc(&wpk, nw * sizeof(float)) != hipSuccess || dev_malloc(&wgp, np * sizeof(float)) != hipSuccess) {
         set_error("unet (paper network): device allocation failed");
         return HELM_E_NOMEM;
     }
@@ -595,7 +950,8 @@ int PaperNet::ensure_ws(int B, int n, bool train)
     ops.push_back(POp{PO_BIAS, {outt, 0, cout}, {}, {outt, 0, cout}, li});
     if (dev_malloc(&sq, (size_t)wsB * sizeof(double)) != hipSuccess ||
         dev_malloc(&part, (size_t)wsB * sizeof(double)) != hipSuccess ||
-        dev_malloc(&red, 2 * 512 * sizeof(double)) != hipSuccess)
+        dev_malloc(&red, 2 * 512 * sizeof(double)) != hipSuccess ||
+        dev_malloc(&rpart, 2 * 1024 * sizeof(double)) != hipSuccess)
         return fail();
     return HELM_OK;
 }
@@ -608,19 +964,19 @@ void PaperNet::forward(int B, bool training, hipStream_t st)
         if (o.kind == PO_CONV || o.kind == PO_CONVT) {
             const PLayer &l = layers[o.layer];
             const float *Wt = P + l.w_off;
-            if (o.kind == PO_CONV)
-                hipLaunchKernelGGL(k_pn_gc, dim3(tiles((size_t)no * no), B * l.co), dim3(PN_T), 0, st, ti.v, ti.C,
-                                   o.in.off, l.ci, ni, ni, Wt, to.v, to.C, o.out.off, l.co, no, no, o.s, l.K, o.pad, 0);
-            else
-                hipLaunchKernelGGL(k_pn_gf, dim3(tiles((size_t)no * no), B * l.co), dim3(PN_T), 0, st, ti.v, ti.C,
-                                   o.in.off, l.ci, ni, ni, Wt, to.v, to.C, o.out.off, l.co, no, no, o.s, l.K, o.pad, 0);
+            gather(o.kind == PO_CONV ? 0 : 1, ti.v, ti.C, o.in.off, l.ci, ni, Wt, to.v, to.C, o.out.off, l.co, no,
+                   o.s, l.K, o.pad, 0, B, st);
         } else if (o.kind == PO_BN) {
             const PLayer &l = layers[o.layer];
             float *sc, *sf;
             if (training) {
-                hipLaunchKernelGGL(k_pn_bn_stats, dim3(l.co), dim3(PN_T), 0, st, ti.v, ti.C, o.in.off, B, ni * ni,
-                                   P + l.g_off, P + l.b_off, 1e-5f, bnarr(l.bn, 0), bnarr(l.bn, 1), bnarr(l.bn, 2),
-                                   bnarr(l.bn, 3), bnarr(l.bn, 4));
+                const int ns = pn_nsplit(l.co, (size_t)B * ni * ni);
+                hipLaunchKernelGGL(k_pn_bn_stats, dim3(ns, l.co), dim3(PN_T), 0, st, ti.v, ti.C, o.in.off, B, ni * ni,
+                                   ns, rpart);
+                hipLaunchKernelGGL(k_pn_psum, dim3((l.co + 63) / 64), dim3(64), 0, st, rpart, ns, l.co, red);
+                hipLaunchKernelGGL(k_pn_bn_stats_fin, dim3((l.co + 63) / 64), dim3(64), 0, st, red, l.co,
+                                   (double)B * ni * ni, P + l.g_off, P + l.b_off, 1e-5f, bnarr(l.bn, 0),
+                                   bnarr(l.bn, 1), bnarr(l.bn, 2), bnarr(l.bn, 3), bnarr(l.bn, 4));
                 sc = bnarr(l.bn, 3);
                 sf = bnarr(l.bn, 4);
             } else {
@@ -659,28 +1015,23 @@ void PaperNet::backward(int B, hipStream_t st)
             // out = gather_coarse(in): d in += gather_fine(d out), dW += wg(coarse = d out, fine = in)
             const PLayer &l = layers[o.layer];
             if (o.in.t != x0t)
-                hipLaunchKernelGGL(k_pn_gf, dim3(tiles((size_t)ni * ni), B * l.ci), dim3(PN_T), 0, st, to.g, to.C,
-                                   o.out.off, l.co, no, no, P + l.w_off, ti.g, ti.C, o.in.off, l.ci, ni, ni, o.s, l.K,
-                                   o.pad, 1);
-            if (l.K == 5)
-                hipLaunchKernelGGL(k_pn_wg<5>, dim3(l.co * l.ci), dim3(PN_T), 0, st, to.g, to.C, o.out.off, l.co, no,
-                                   no, ti.v, ti.C, o.in.off, l.ci, ni, ni, B, o.s, o.pad, G + l.w_off);
-            else
-                hipLaunchKernelGGL(k_pn_wg<3>, dim3(l.co * l.ci), dim3(PN_T), 0, st, to.g, to.C, o.out.off, l.co, no,
-                                   no, ti.v, ti.C, o.in.off, l.ci, ni, ni, B, o.s, o.pad, G + l.w_off);
+                gather(1, to.g, to.C, o.out.off, l.co, no, P + l.w_off, ti.g, ti.C, o.in.off, l.ci, ni, o.s, l.K, o.pad,
+                       1, B, st);
+            wgrad(to.g, to.C, o.out.off, l.co, no, ti.v, ti.C, o.in.off, l.ci, ni, o.s, l.K, o.pad, B, G + l.w_off, st);
         } else if (o.kind == PO_CONVT) {
             // out = gather_fine(in): d in += gather_coarse(d out), dW += wg(coarse = in, fine = d out)
             const PLayer &l = layers[o.layer];
-            hipLaunchKernelGGL(k_pn_gc, dim3(tiles((size_t)ni * ni), B * l.ci), dim3(PN_T), 0, st, to.g, to.C,
-                               o.out.off, l.co, no, no, P + l.w_off, ti.g, ti.C, o.in.off, l.ci, ni, ni, o.s, l.K,
-                               o.pad, 1);
-            hipLaunchKernelGGL(k_pn_wg<5>, dim3(l.ci * l.co), dim3(PN_T), 0, st, ti.v, ti.C, o.in.off, l.ci, ni, ni,
-                               to.g, to.C, o.out.off, l.co, no, no, B, o.s, o.pad, G + l.w_off);
+            gather(0, to.g, to.C, o.out.off, l.co, no, P + l.w_off, ti.g, ti.C, o.in.off, l.ci, ni, o.s, l.K, o.pad,
+                   1, B, st);
+            wgrad(ti.v, ti.C, o.in.off, l.ci, ni, to.g, to.C, o.out.off, l.co, no, o.s, l.K, o.pad, B, G + l.w_off, st);
         } else if (o.kind == PO_BN) {
             const PLayer &l = layers[o.layer];
             const int act = o.act ? 1 : 0;
-            hipLaunchKernelGGL(k_pn_bn_bsum, dim3(l.co), dim3(PN_T), 0, st, to.g, to.C, o.out.off, to.v, to.C,
-                               o.out.off, ti.v, ti.C, o.in.off, B, ni * ni, bnarr(l.bn, 0), bnarr(l.bn, 2), act, red);
+            const int ns = pn_nsplit(l.co, (size_t)B * ni * ni);
+            hipLaunchKernelGGL(k_pn_bn_bsum, dim3(ns, l.co), dim3(PN_T), 0, st, to.g, to.C, o.out.off, to.v, to.C,
+                               o.out.off, ti.v, ti.C, o.in.off, B, ni * ni, bnarr(l.bn, 0), bnarr(l.bn, 2), act, ns,
+                               rpart);
+            hipLaunchKernelGGL(k_pn_psum, dim3((l.co + 63) / 64), dim3(64), 0, st, rpart, ns, l.co, red);
             hipLaunchKernelGGL(k_pn_bn_bapply, dim3(tiles((size_t)ni * ni), B * l.co), dim3(PN_T), 0, st, to.g, to.C,
                                o.out.off, to.v, to.C, o.out.off, ti.v, ti.C, o.in.off, ti.g, ti.C, o.in.off, B, l.co,
                                ni * ni, bnarr(l.bn, 0), bnarr(l.bn, 2), P + l.g_off, act, red);
@@ -696,7 +1047,10 @@ void PaperNet::backward(int B, hipStream_t st)
                                T[o.in2.t].g, n);
         } else if (o.kind == PO_BIAS) {
             const PLayer &l = layers[o.layer];
-            hipLaunchKernelGGL(k_pn_bias_g, dim3(l.co), dim3(PN_T), 0, st, to.g, B, l.co, no * no, G + l.b_off);
+            const int ns = pn_nsplit(l.co, (size_t)B * no * no);
+            hipLaunchKernelGGL(k_pn_bias_g, dim3(ns, l.co), dim3(PN_T), 0, st, to.g, B, l.co, no * no, ns, rpart);
+            hipLaunchKernelGGL(k_pn_psum, dim3((l.co + 63) / 64), dim3(64), 0, st, rpart, ns, l.co, red);
+            hipLaunchKernelGGL(k_pn_bias_fin, dim3((l.co + 63) / 64), dim3(64), 0, st, red, l.co, G + l.b_off);
         }
     }
 }
