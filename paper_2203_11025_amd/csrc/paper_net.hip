@@ -63,14 +63,15 @@ __device__ __forceinline__ double pn_bsum(double v, double *sh)
 // (pad - a, pad - c).  Per class the GEMM is
 //   D[out channel][point] = sum over (in channel, tap) of Wp[in][tap][out] X[in][point + offset(tap)],
 // Wp the weights repacked so that output channels are contiguous.  A
-// workgroup (4 wavefronts; wavefront w owns output channels 16 w .. + 15 of
-// a block of 64) owns an 8 x 16 tile of one lattice (8 pixel fragments, one
+// workgroup (NWV = 1, 2 or 4 wavefronts, as many as the output channels
+// fill; wavefront w owns output channels 16 w .. + 15 of the block) owns an
+// 8 x 16 tile of one lattice (8 pixel fragments, one
 // per lattice row) and walks the input channels four at a time (one MFMA K
 // step per tap): the input patch under the tile and the chunk's weights go
 // to LDS, the next chunk's loads are in flight in registers during the
 // current chunk's MFMAs (two LDS buffers, one barrier per chunk), and each
 // tap costs a wavefront one A read, 8 B reads and 8 MFMAs.
-constexpr int PM_TY = 8, PM_TX = 16, PM_CI = 4, PM_CO = 64;
+constexpr int PM_TY = 8, PM_TX = 16, PM_CI = 4;
 
 struct PmArgs {
     const float *in;
@@ -97,20 +98,21 @@ __global__ void k_pn_wpack(const float *__restrict__ W, int Cout, int Cin, int K
 
 // IS: input step of the lattice (s for a gather to coarse, else 1); MAXT:
 // taps of a class at most; PHM x PWM: the largest input patch of a tile
-template <int IS, int MAXT, int PHM, int PWM>
-__global__ __launch_bounds__(256, 2) void k_pn_mm(PmArgs g)
+template <int IS, int MAXT, int PHM, int PWM, int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_pn_mm(PmArgs g)
 {
+    constexpr int NT = 64 * NWV, CO = 16 * NWV;            // threads; output channels per workgroup
     constexpr int PS = PHM * PWM;                          // patch floats per channel
-    constexpr int NP = (PM_CI * PS + 255) / 256;           // patch loads per thread
-    constexpr int NW = (MAXT * PM_CI * PM_CO + 255) / 256;  // weight loads per thread
+    constexpr int NP = (PM_CI * PS + NT - 1) / NT;         // patch loads per thread
+    constexpr int NW = (MAXT * PM_CI * CO + NT - 1) / NT;   // weight loads per thread
     __shared__ float sP[2][PM_CI * PS];
-    __shared__ float sW[2][MAXT * PM_CI * PM_CO];
+    __shared__ float sW[2][MAXT * PM_CI * CO];
     __shared__ int sT[MAXT];    // per tap: (dy + 64) | (dx + 64) << 8 | (a K + c) << 16
     __shared__ int sI[3];       // taps, dymin, dxmin
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int cls = blockIdx.x / g.tiles_per_class, tile = blockIdx.x - cls * g.tiles_per_class;
     const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
-    const int co0 = blockIdx.y * PM_CO, b = blockIdx.z;
+    const int co0 = blockIdx.y * CO, b = blockIdx.z;
     const int os = g.mode == 0 ? 1 : g.s;
     const int py = cls / os, px = cls - py * os;
     const int LY = (g.Hout - py + os - 1) / os, LX = (g.Wout - px + os - 1) / os;
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(256, 2) void k_pn_mm(PmArgs g)
     auto load = [&](int ic0) {
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            const int e = tid + 256 * q;
+            const int e = tid + NT * q;
             float v = 0.f;
             if (e < PM_CI * PS) {
                 const int ch = e / PS, rem = e - ch * PS, r = rem / PWM, c = rem - r * PWM;
@@ -166,10 +168,10 @@ __global__ __launch_bounds__(256, 2) void k_pn_mm(PmArgs g)
         }
 #pragma unroll
         for (int q = 0; q < NW; ++q) {
-            const int e = tid + 256 * q;
+            const int e = tid + NT * q;
             float v = 0.f;
-            if (e < MAXT * PM_CI * PM_CO) {
-                const int o = e % PM_CO, ic = (e / PM_CO) % PM_CI, t = e / (PM_CO * PM_CI);
+            if (e < MAXT * PM_CI * CO) {
+                const int o = e % CO, ic = (e / CO) % PM_CI, t = e / (CO * PM_CI);
                 if (t < nt && ic0 + ic < g.Cin && co0 + o < g.Cout)
                     v = g.Wp[((size_t)(ic0 + ic) * g.K * g.K + (sT[t] >> 16)) * g.Cout + co0 + o];
             }
@@ -179,13 +181,13 @@ __global__ __launch_bounds__(256, 2) void k_pn_mm(PmArgs g)
     auto store = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            const int e = tid + 256 * q;
+            const int e = tid + NT * q;
             if (e < PM_CI * PS) sP[buf][e] = pp[q];
         }
 #pragma unroll
         for (int q = 0; q < NW; ++q) {
-            const int e = tid + 256 * q;
-            if (e < MAXT * PM_CI * PM_CO) sW[buf][e] = pw[q];
+            const int e = tid + NT * q;
+            if (e < MAXT * PM_CI * CO) sW[buf][e] = pw[q];
         }
     };
     f32x4 acc[PM_TY];
@@ -201,11 +203,11 @@ __global__ __launch_bounds__(256, 2) void k_pn_mm(PmArgs g)
         const bool more = ch + 1 < nch;
         if (more) load((ch + 1) * PM_CI);
         const float *P = &sP[buf][k * PS + IS * j];
-        const float *Wb = &sW[buf][k * PM_CO + wv * 16 + j];
+        const float *Wb = &sW[buf][k * CO + wv * 16 + j];
         for (int t = 0; t < nt; ++t) {
             const int tv = sT[t];
             const int dy = (tv & 255) - 64 - dymin, dx = ((tv >> 8) & 255) - 64 - dxmin;
-            const float a = Wb[t * PM_CI * PM_CO];
+            const float a = Wb[t * PM_CI * CO];
             const float *Pt = P + dy * PWM + dx;
 #pragma unroll
             for (int f = 0; f < PM_TY; ++f)
@@ -769,11 +771,24 @@ void PaperNet::gather(int mode, const float *in, int inC, int inOff, int Cin, in
     const int L = (Hout + os - 1) / os;  // lattice side of class (0, 0), the largest
     g.tiles_x = (L + PM_TX - 1) / PM_TX;
     g.tiles_per_class = g.tiles_x * ((L + PM_TY - 1) / PM_TY);
-    const dim3 grid(g.tiles_per_class * os * os, (Cout + PM_CO - 1) / PM_CO, B);
-    if (mode == 0 && s == 2 && K == 5)
-        hipLaunchKernelGGL((k_pn_mm<2, 25, 19, 35>), grid, dim3(256), 0, st, g);
-    else  // mode 0 with s = 1, K = 3; mode 1 with s = 2, K = 5 or s = 1, K = 3 (checked at build)
-        hipLaunchKernelGGL((k_pn_mm<1, 9, 10, 18>), grid, dim3(256), 0, st, g);
+    // wavefronts per workgroup: as many 16-channel fragments as Cout fills, at most 4
+    const int nwv = Cout <= 16 ? 1 : Cout <= 32 ? 2 : 4;
+    const dim3 grid(g.tiles_per_class * os * os, (Cout + 16 * nwv - 1) / (16 * nwv), B);
+    const bool big = mode == 0 && s == 2 && K == 5;  // else mode 0 with s = 1, K = 3, or mode 1 (checked at build)
+#define PN_MM(NWV)                                                                        \
+    do {                                                                                  \
+        if (big)                                                                          \
+            hipLaunchKernelGGL((k_pn_mm<2, 25, 19, 35, NWV>), grid, dim3(64 * NWV), 0, st, g); \
+        else                                                                              \
+            hipLaunchKernelGGL((k_pn_mm<1, 9, 10, 18, NWV>), grid, dim3(64 * NWV), 0, st, g);  \
+    } while (0)
+    if (nwv == 1)
+        PN_MM(1);
+    else if (nwv == 2)
+        PN_MM(2);
+    else
+        PN_MM(4);
+#undef PN_MM
 }
 
 // dW (+)= the weight gradient of one transfer or ResNet convolution (coarse
