@@ -149,6 +149,7 @@ def main(argv=None):
         unet.save(tmp, encoder=enc, solver=sol)
         os.replace(tmp, a.out)
 
+    ks = a.ksteps if a.ksteps == "random" else int(a.ksteps)
     budget = a.minutes * 60.0
     t0 = time.perf_counter()
     last_save = t0
@@ -160,7 +161,7 @@ def main(argv=None):
             f = min(1.0, (time.perf_counter() - t0) / budget)
             lr = a.lr + (a.lr_final - a.lr) * f
         losses = train.train_pair(enc, sol, handles, steps=k, batch=a.batch, lr=lr,
-                                  seed=a.seed * 100003 + step, per_medium=a.per_medium)
+                                  seed=a.seed * 100003 + step, per_medium=a.per_medium, ksteps=ks)
         # rotate the starting medium so consecutive chunks see every medium
         handles = handles[k * a.batch // a.per_medium % len(handles):] + \
             handles[:k * a.batch // a.per_medium % len(handles)]
