@@ -73,6 +73,9 @@ struct ConvEpi {
     float *seg_p[CONV_MAX_SEG] = {};
     int seg_hi[CONV_MAX_SEG] = {};
     int seg_C[CONV_MAX_SEG] = {};
+    // set by launch_conv3x3: the bf16 output exceeds the last-level cache,
+    // so its stores stream past the caches (nontemporal)
+    int nt = 0;
 };
 void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout, int mode,
                     float *out32, bf16 *out16, const float *scale, const float *shift,

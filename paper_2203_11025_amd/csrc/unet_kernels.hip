@@ -96,10 +96,35 @@ __device__ __forceinline__ f8 up_blend8(const f8 &a00, const f8 &a01, const f8 &
 // pixel x = lane % 16 column of the tile, channels co0 + 16 nf + 4 (lane /
 // 16) .. + 3 of fragment nf.  bn(c, sc, sh) gives the folded BN of block
 // channels c .. c + 3.  Clears acc.
-template <int MF, int NF, int EPI, class BN>
-__device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[MF][NF], int lane, int b, int y0, int x, int H, int W,
-                                              int Cout, int co0, int mode, float *__restrict__ out32,
-                                              bf16 *__restrict__ out16, float slope, const ConvEpi &epi, BN bn)
+// Issues (without waiting) the context-map loads of the epilogue below for
+// the same tile rows, pixel and channels: branch-free buffer loads, pieces
+// outside the image or Cout read as zero.
+template <int MF, int NF>
+__device__ __forceinline__ void conv_cmap_issue(f16x4 (&mp)[MF][NF], int lane, int y0, int x, int H, int W, int Cout,
+                                                int co0, const ConvEpi &epi)
+{
+    const bool full_co = co0 + 16 * NF <= Cout;
+    const __amdgpu_buffer_rsrc_t mr =
+        __builtin_amdgcn_make_buffer_rsrc((void *)epi.cmap, 0, (int)((size_t)H * W * Cout * 2), BUF_DWORD3);
+#pragma unroll
+    for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+        for (int nf = 0; nf < NF; ++nf) {
+            const int y = y0 + mf, c = co0 + 4 * (lane >> 4) + nf * 16;
+            const bool ok = y < H && x < W && (full_co || c < Cout);
+            mp[mf][nf] = __builtin_bit_cast(
+                f16x4, __builtin_amdgcn_raw_buffer_load_b64(mr, ok ? ((y * W + x) * Cout + c) * 2 : BUF_NONE, 0, 0));
+        }
+}
+
+// PRE: the caller has issued the context-map loads into mp with
+// conv_cmap_issue (so that they overlap its MFMAs); otherwise the epilogue
+// issues them itself.
+template <int MF, int NF, int EPI, bool PRE = false, class BN>
+__device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[MF][NF], f16x4 (&mp)[MF][NF], int lane, int b, int y0,
+                                              int x, int H, int W, int Cout, int co0, int mode,
+                                              float *__restrict__ out32, bf16 *__restrict__ out16, float slope,
+                                              const ConvEpi &epi, BN bn)
 {
     constexpr int CO = 16 * NF;
     if constexpr (EPI == 0) {
@@ -111,23 +136,10 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[MF][NF], int lane, in
         float4 sc[NF], sh[NF];
 #pragma unroll
         for (int nf = 0; nf < NF; ++nf) bn(nf * 16 + 4 * (lane >> 4), sc[nf], sh[nf]);
-        // the context map of the whole tile first: branch-free buffer loads
-        // (pieces outside the image or Cout read as zero), so that they all
-        // issue before the first wait
-        f16x4 mp[MF][NF];
+        // the context map of the whole tile first (all loads issue before
+        // the first wait)
         if (mode == 1 && epi.cmap) {
-            const __amdgpu_buffer_rsrc_t mr = __builtin_amdgcn_make_buffer_rsrc(
-                (void *)epi.cmap, 0, (int)((size_t)H * W * Cout * 2), BUF_DWORD3);
-#pragma unroll
-            for (int mf = 0; mf < MF; ++mf)
-#pragma unroll
-                for (int nf = 0; nf < NF; ++nf) {
-                    const int y = y0 + mf, c = co0 + 4 * (lane >> 4) + nf * 16;
-                    const bool ok = y < H && x < W && (full_co || c < Cout);
-                    mp[mf][nf] = __builtin_bit_cast(
-                        f16x4, __builtin_amdgcn_raw_buffer_load_b64(mr, ok ? ((y * W + x) * Cout + c) * 2 : BUF_NONE,
-                                                                   0, 0));
-                }
+            if constexpr (!PRE) conv_cmap_issue<MF, NF>(mp, lane, y0, x, H, W, Cout, co0, epi);
             // one wait here, on every lane: waits left inside the divergent
             // store branches below would make the compiler wait for all
             // memory operations at the next write of these registers (the
@@ -139,6 +151,55 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[MF][NF], int lane, in
 #pragma unroll
                 for (int nf = 0; nf < NF; ++nf) mp[mf][nf] = f16x4{};
         }
+        if (NF % 2 == 0 && mode == 1) {
+            // 16-byte stores: lanes l and l ^ 16 swap one of their two
+            // fragments' 8 bytes, so that lane (x, q) holds 8 consecutive
+            // channels of fragment pair np: 4 q .. 4 q + 7 of fragment np (q
+            // even) or 16 + 4 (q - 1) .. of fragment np + 1 (q odd)
+            const int q = lane >> 4;
+            const bool odd = q & 1;
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+            for (int mf = 0; mf < MF; ++mf) {
+                const int y = y0 + mf;
+                const bool pix_ok = y < H && x < W;
+                const size_t pbase = (((size_t)b * H + y) * W + x) * Cout + co0;
+#pragma unroll
+                for (int np = 0; np < NF; np += 2) {
+                    uint2 o[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int nf = np + h;
+                        const f32x4 v = acc[mf][nf];
+                        const f16x4 m = mp[mf][nf];
+                        float z0 = (v[0] + (float)m[0]) * sc[nf].x + sh[nf].x;
+                        float z1 = (v[1] + (float)m[1]) * sc[nf].y + sh[nf].y;
+                        float z2 = (v[2] + (float)m[2]) * sc[nf].z + sh[nf].z;
+                        float z3 = (v[3] + (float)m[3]) * sc[nf].w + sh[nf].w;
+                        z0 = z0 > 0.f ? z0 : slope * z0;
+                        z1 = z1 > 0.f ? z1 : slope * z1;
+                        z2 = z2 > 0.f ? z2 : slope * z2;
+                        z3 = z3 > 0.f ? z3 : slope * z3;
+                        const bf16x4 t = {(bf16)z0, (bf16)z1, (bf16)z2, (bf16)z3};
+                        o[h] = __builtin_bit_cast(uint2, t);
+                        acc[mf][nf] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    }
+                    const uint2 snd = odd ? o[0] : o[1];
+                    const uint2 rcv = make_uint2((unsigned)__shfl_xor((int)snd.x, 16), (unsigned)__shfl_xor((int)snd.y, 16));
+                    const uint4 d = odd ? make_uint4(rcv.x, rcv.y, o[1].x, o[1].y) : make_uint4(o[0].x, o[0].y, rcv.x, rcv.y);
+                    const int ch = odd ? (np + 1) * 16 + 4 * (q - 1) : np * 16 + 4 * q;
+                    if (pix_ok && (full_co || co0 + ch < Cout)) {
+                        if (epi.nt) {
+                            const u32x4 dv = {d.x, d.y, d.z, d.w};
+                            __builtin_nontemporal_store(dv, reinterpret_cast<u32x4 *>(out16 + pbase + ch));
+                        } else {
+                            *reinterpret_cast<uint4 *>(out16 + pbase + ch) = d;
+                        }
+                    }
+                }
+            }
+        } else
 #pragma unroll
         for (int mf = 0; mf < MF; ++mf) {
             const int y = y0 + mf;
@@ -543,7 +604,8 @@ __global__ __launch_bounds__(256, NF == 4 ? 2 : 1) void k_conv3x3(Srcs in, int B
         }
         if (st % nch == nch - 1) {
             // the tile is complete
-            conv_epilogue<MF, NF, EPI>(acc, lane, b, ty * TH + wv * MF, tx * TW + (lane & 15), H, W, Cout, co0,
+            f16x4 mp[MF][NF];
+            conv_epilogue<MF, NF, EPI>(acc, mp, lane, b, ty * TH + wv * MF, tx * TW + (lane & 15), H, W, Cout, co0,
                                        mode, out32, out16, slope, epi, [&](int c, float4 &sc, float4 &sh) {
                                            sc = *reinterpret_cast<const float4 *>(&ssc[c]);
                                            sh = *reinterpret_cast<const float4 *>(&ssh[c]);
@@ -809,6 +871,7 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
     }
 
     bf16x8 wreg[WREG ? 9 : 1][WREG ? NF : 1];
+    f16x4 mp[WMF][WNF];  // context map of the tile being finished
     // MFMAs of one stage from the given buffers
     auto compute = [&](const luint4 *hbuf, const luint4 *wbuf) {
         const int seg = lane >> 4;
@@ -882,6 +945,10 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
         if constexpr (UP) {
             if (in.s[0].up && (st % nch) * 32 < in.s[0].C) build_up(ch_, tx, ty);
         }
+        // the last chunk of a tile: its context map loads overlap the MFMAs
+        const bool last = st % nch == nch - 1;
+        if (EPI == 0 && last && mode == 1 && epi.cmap)
+            conv_cmap_issue<WMF, WNF>(mp, lane, ty * TH + wrow, tx * TW + (lane & 15), H, W, Cout, co0 + wco, epi);
         compute(ch_, cw_);
         // (no instructions: keeps the offset registers allocated until here;
         // the constraint names a GPU register class, so the host pass skips it)
@@ -893,8 +960,8 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
             for (int q = 0; q < WIN; ++q) asm volatile("" ::"v"(woff[q]));
         }
 #endif
-        if (st % nch == nch - 1) {
-            conv_epilogue<WMF, WNF, EPI>(acc, lane, b, ty * TH + wrow, tx * TW + (lane & 15), H, W, Cout,
+        if (last) {
+            conv_epilogue<WMF, WNF, EPI, true>(acc, mp, lane, b, ty * TH + wrow, tx * TW + (lane & 15), H, W, Cout,
                                          co0 + wco, mode, out32, out16, slope, epi,
                                          [&](int c, float4 &sc, float4 &sh) {
                                              // c = 16 nf + 4 (lane / 16) (+ 0): fragment nf's registers
@@ -2193,10 +2260,17 @@ ConvShape conv_tune(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cou
 
 }  // namespace
 
+// bf16 outputs above this size are stored nontemporally (MI355X: 256 MB of
+// last-level cache; a smaller output can still be read back from it by the
+// next layer)
+constexpr size_t CONV_NT_BYTES = 320ull << 20;
+
 void launch_conv3x3(const Srcs &in, int B, int H, int W, const bf16 *Wt, int Cout, int mode,
                     float *out32, bf16 *out16, const float *scale, const float *shift,
-                    float slope, hipStream_t s, const ConvEpi &epi)
+                    float slope, hipStream_t s, const ConvEpi &epi_in)
 {
+    ConvEpi epi = epi_in;
+    epi.nt = (size_t)B * H * W * Cout * sizeof(bf16) > CONV_NT_BYTES;
     ConvShape c = conv_default(H, Cout);
     {
         std::lock_guard<std::mutex> lk(g_tune.mu);
