@@ -60,8 +60,9 @@ struct Srcs {
 //              [seg_hi[k-1], seg_hi[k]) (from 0; the last ends at Cout);
 //              with seg_p[k] its channels are written to seg_p[k] (seg_C[k]
 //              channels per pixel, at channel c - seg_hi[k-1]; stored, not
-//              added), without it they go to out32 as usual.  Boundaries and
-//              seg_C are multiples of 4.
+//              added), without it they go to out32 as usual.  Boundaries
+//              are multiples of 16 (one range per 16-channel fragment),
+//              seg_C a multiple of 4.
 constexpr int CONV_MAX_SEG = 4;
 struct ConvEpi {
     bf16 *pool = nullptr;

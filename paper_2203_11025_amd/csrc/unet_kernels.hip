@@ -214,10 +214,13 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[MF][NF], f16x4 (&mp)[
                             *reinterpret_cast<f16x4 *>(epi.raw16 + base + nf * 16) =
                                 f16x4{(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
                         } else if (epi.nseg) {
-                            // the channel range holding this lane's four channels
-                            const int c = co0 + nf * 16 + 4 * (lane >> 4);
+                            // the channel range holding fragment nf (range
+                            // ends are multiples of 16, so the choice is the
+                            // same on every lane: scalar loads of the range
+                            // table, no per-lane gather)
+                            const int c0 = __builtin_amdgcn_readfirstlane(co0 + nf * 16), c = c0 + 4 * (lane >> 4);
                             int k = 0, lo = 0;
-                            while (k < epi.nseg - 1 && c >= epi.seg_hi[k]) {
+                            while (k < epi.nseg - 1 && c0 >= epi.seg_hi[k]) {
                                 lo = epi.seg_hi[k];
                                 ++k;
                             }
