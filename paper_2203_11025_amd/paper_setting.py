@@ -101,7 +101,7 @@ def solve_all(h, net, rhs, m=10, tol=1e-7, maxit=2000, block=0):
 
 def sweep(h, net, rhs):
     """The influence of the block size and of the subspace size (section
-    4.3.5): block FGMRES(10) with blocks of 1, 2, 5 and 10 right-hand sides,
+    4.3.4): block FGMRES(10) with blocks of 1, 2, 5 and 10 right-hand sides,
     and block FGMRES(m) with blocks of 10 for m = 5, 10, 20; per setting and
     preconditioner the mean rho of eq. 4.1 and the mean iterations to 1e-7."""
     out = []
