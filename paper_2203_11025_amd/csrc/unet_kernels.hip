@@ -118,9 +118,13 @@ __device__ __forceinline__ void conv_cmap_issue(f16x4 (&mp)[MF][NF], int lane, i
 }
 
 // PRE: the caller has issued the context-map loads into mp with
-// conv_cmap_issue (so that they overlap its MFMAs); otherwise the epilogue
-// issues them itself.
-template <int MF, int NF, int EPI, bool PRE = false, class BN>
+// conv_cmap_issue (so that they overlap its MFMAs), and PREWAIT vector memory
+// operations issued after them may stay in flight when they are waited for;
+// otherwise the epilogue issues them itself.  The plain epilogue (EPI 0)
+// stores with buffer stores on every lane (pieces outside the image or Cout
+// fall outside the buffer's range and are dropped), so it issues a fixed
+// number of vector memory operations: MF NF / 2 in mode 1, MF NF in mode 0.
+template <int MF, int NF, int EPI, bool PRE = false, int PREWAIT = 0, class BN>
 __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[MF][NF], f16x4 (&mp)[MF][NF], int lane, int b, int y0,
                                               int x, int H, int W, int Cout, int co0, int mode,
                                               float *__restrict__ out32, bf16 *__restrict__ out16, float slope,
@@ -128,6 +132,7 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[MF][NF], f16x4 (&mp)[
 {
     constexpr int CO = 16 * NF;
     if constexpr (EPI == 0) {
+        static_assert(NF % 2 == 0, "fragment pairs");
         // the tile is complete: lane (l % 16, l / 16) holds pixel x0 + l % 16
         // of each row and channels 4 (l / 16) .. + 3 of each fragment
         const bool full_co = co0 + CO <= Cout;
@@ -140,18 +145,25 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[MF][NF], f16x4 (&mp)[
         // the first wait)
         if (mode == 1 && epi.cmap) {
             if constexpr (!PRE) conv_cmap_issue<MF, NF>(mp, lane, y0, x, H, W, Cout, co0, epi);
-            // one wait here, on every lane: waits left inside the divergent
-            // store branches below would make the compiler wait for all
-            // memory operations at the next write of these registers (the
-            // next stage's copy issue)
-            __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0); expcnt, lgkmcnt untouched
+            // one wait here, on every lane
+            if constexpr (PRE && PREWAIT > 0)
+                __builtin_amdgcn_s_waitcnt((PREWAIT & 15) | ((PREWAIT >> 4) << 14) | (7 << 4) | (15 << 8));
+            else
+                __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0); expcnt, lgkmcnt untouched
         } else {
 #pragma unroll
             for (int mf = 0; mf < MF; ++mf)
 #pragma unroll
                 for (int nf = 0; nf < NF; ++nf) mp[mf][nf] = f16x4{};
         }
-        if (NF % 2 == 0 && mode == 1) {
+        // this wavefront's rows: yw .. yw + rows - 1 of image b
+        const int yw = __builtin_amdgcn_readfirstlane(y0);
+        const int rows = max(0, min(MF, H - yw));  // 0 for rows past a ragged image's end
+        const size_t row0 = ((size_t)b * H + yw) * W;
+        const bool x_ok = x < W;
+        typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+        typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+        if (mode == 1) {
             // 16-byte stores: lanes l and l ^ 16 swap one of their two
             // fragments' 8 bytes, so that lane (x, q) holds 8 consecutive
             // channels of fragment pair np: 4 q .. 4 q + 7 of fragment np (q
@@ -159,12 +171,10 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[MF][NF], f16x4 (&mp)[
             const int q = lane >> 4;
             const bool odd = q & 1;
             typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-            typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+            const __amdgpu_buffer_rsrc_t r16 = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(out16 + row0 * Cout), 0, (int)((size_t)rows * W * Cout * 2), BUF_DWORD3);
 #pragma unroll
             for (int mf = 0; mf < MF; ++mf) {
-                const int y = y0 + mf;
-                const bool pix_ok = y < H && x < W;
-                const size_t pbase = (((size_t)b * H + y) * W + x) * Cout + co0;
 #pragma unroll
                 for (int np = 0; np < NF; np += 2) {
                     uint2 o[2];
@@ -186,72 +196,61 @@ __device__ __forceinline__ void conv_epilogue(f32x4 (&acc)[MF][NF], f16x4 (&mp)[
                         acc[mf][nf] = f32x4{0.f, 0.f, 0.f, 0.f};
                     }
                     const uint2 snd = odd ? o[0] : o[1];
-                    const uint2 rcv = make_uint2((unsigned)__shfl_xor((int)snd.x, 16), (unsigned)__shfl_xor((int)snd.y, 16));
-                    const uint4 d = odd ? make_uint4(rcv.x, rcv.y, o[1].x, o[1].y) : make_uint4(o[0].x, o[0].y, rcv.x, rcv.y);
+                    const uint2 rcv =
+                        make_uint2((unsigned)__shfl_xor((int)snd.x, 16), (unsigned)__shfl_xor((int)snd.y, 16));
+                    const u32x4 d = odd ? u32x4{rcv.x, rcv.y, o[1].x, o[1].y} : u32x4{o[0].x, o[0].y, rcv.x, rcv.y};
                     const int ch = odd ? (np + 1) * 16 + 4 * (q - 1) : np * 16 + 4 * q;
-                    if (pix_ok && (full_co || co0 + ch < Cout)) {
-                        if (epi.nt) {
-                            const u32x4 dv = {d.x, d.y, d.z, d.w};
-                            __builtin_nontemporal_store(dv, reinterpret_cast<u32x4 *>(out16 + pbase + ch));
-                        } else {
-                            *reinterpret_cast<uint4 *>(out16 + pbase + ch) = d;
-                        }
-                    }
+                    const bool ok = mf < rows && x_ok && (full_co || co0 + ch < Cout);
+                    const int off = ok ? (int)((((size_t)mf * W + x) * Cout + co0 + ch) * 2) : BUF_NONE;
+                    if (epi.nt)
+                        __builtin_amdgcn_raw_buffer_store_b128(d, r16, off, 0, 2);  // nontemporal
+                    else
+                        __builtin_amdgcn_raw_buffer_store_b128(d, r16, off, 0, 0);
                 }
             }
-        } else
-#pragma unroll
-        for (int mf = 0; mf < MF; ++mf) {
-            const int y = y0 + mf;
-            const bool pix_ok = y < H && x < W;
-            const size_t base = (((size_t)b * H + y) * W + x) * Cout + co0 + 4 * (lane >> 4);
+        } else {
+            // raw FP32 (or FP16 with raw16) output, optionally routed by
+            // channel range
+            const __amdgpu_buffer_rsrc_t r32 = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(out32 + row0 * Cout), 0, (int)((size_t)rows * W * Cout * 4), BUF_DWORD3);
 #pragma unroll
             for (int nf = 0; nf < NF; ++nf) {
-                if (pix_ok && (full_co || co0 + nf * 16 + 4 * (lane >> 4) < Cout)) {
-                    const f32x4 v = acc[mf][nf];
-                    if (mode == 0) {
-                        if (epi.raw16) {
-                            *reinterpret_cast<f16x4 *>(epi.raw16 + base + nf * 16) =
-                                f16x4{(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
-                        } else if (epi.nseg) {
-                            // the channel range holding fragment nf (range
-                            // ends are multiples of 16, so the choice is the
-                            // same on every lane: scalar loads of the range
-                            // table, no per-lane gather)
-                            const int c0 = __builtin_amdgcn_readfirstlane(co0 + nf * 16), c = c0 + 4 * (lane >> 4);
-                            int k = 0, lo = 0;
-                            while (k < epi.nseg - 1 && c0 >= epi.seg_hi[k]) {
-                                lo = epi.seg_hi[k];
-                                ++k;
-                            }
-                            if (epi.seg_p[k]) {
-                                *reinterpret_cast<float4 *>(epi.seg_p[k] +
-                                                            (((size_t)b * H + y) * W + x) * epi.seg_C[k] +
-                                                            (c - lo)) = make_float4(v[0], v[1], v[2], v[3]);
-                            } else {
-                                *reinterpret_cast<float4 *>(out32 + base + nf * 16) =
-                                    make_float4(v[0], v[1], v[2], v[3]);
-                            }
-                        } else {
-                            *reinterpret_cast<float4 *>(out32 + base + nf * 16) =
-                                make_float4(v[0], v[1], v[2], v[3]);
-                        }
-                    } else {
-                        const f16x4 m = mp[mf][nf];
-                        float z0 = (v[0] + (float)m[0]) * sc[nf].x + sh[nf].x;
-                        float z1 = (v[1] + (float)m[1]) * sc[nf].y + sh[nf].y;
-                        float z2 = (v[2] + (float)m[2]) * sc[nf].z + sh[nf].z;
-                        float z3 = (v[3] + (float)m[3]) * sc[nf].w + sh[nf].w;
-                        z0 = z0 > 0.f ? z0 : slope * z0;
-                        z1 = z1 > 0.f ? z1 : slope * z1;
-                        z2 = z2 > 0.f ? z2 : slope * z2;
-                        z3 = z3 > 0.f ? z3 : slope * z3;
-                        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-                        bf16x4 o = {(bf16)z0, (bf16)z1, (bf16)z2, (bf16)z3};
-                        *reinterpret_cast<bf16x4 *>(out16 + base + nf * 16) = o;
+                // the channel range holding fragment nf (range ends are
+                // multiples of 16, so the choice is the same on every lane)
+                const int c0 = __builtin_amdgcn_readfirstlane(co0 + nf * 16), c = c0 + 4 * (lane >> 4);
+                const bool c_ok = full_co || c < Cout;
+                __amdgpu_buffer_rsrc_t rr = r32;
+                int cs = Cout, cc = c;
+                if (epi.raw16) {
+                    rr = __builtin_amdgcn_make_buffer_rsrc((void *)(epi.raw16 + row0 * Cout), 0,
+                                                           (int)((size_t)rows * W * Cout * 2), BUF_DWORD3);
+                } else if (epi.nseg) {
+                    int k = 0, lo = 0;
+                    while (k < epi.nseg - 1 && c0 >= epi.seg_hi[k]) {
+                        lo = epi.seg_hi[k];
+                        ++k;
+                    }
+                    if (epi.seg_p[k]) {
+                        cs = epi.seg_C[k];
+                        cc = c - lo;
+                        rr = __builtin_amdgcn_make_buffer_rsrc((void *)(epi.seg_p[k] + row0 * cs), 0,
+                                                               (int)((size_t)rows * W * cs * 4), BUF_DWORD3);
                     }
                 }
-                acc[mf][nf] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int mf = 0; mf < MF; ++mf) {
+                    const f32x4 v = acc[mf][nf];
+                    const bool ok = mf < rows && x_ok && c_ok;
+                    if (epi.raw16) {
+                        const f16x4 h4 = {(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
+                        const int off = ok ? (int)((((size_t)mf * W + x) * Cout + c) * 2) : BUF_NONE;
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, h4), rr, off, 0, 0);
+                    } else {
+                        const int off = ok ? (int)((((size_t)mf * W + x) * cs + cc) * 4) : BUF_NONE;
+                        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rr, off, 0, 0);
+                    }
+                    acc[mf][nf] = f32x4{0.f, 0.f, 0.f, 0.f};
+                }
             }
         }
     } else {
@@ -964,17 +963,73 @@ __global__ __launch_bounds__(512, 1) void k_conv3x3d(Srcs in, int B, int H, int 
         }
 #endif
         if (last) {
-            conv_epilogue<WMF, WNF, EPI, true>(acc, mp, lane, b, ty * TH + wrow, tx * TW + (lane & 15), H, W, Cout,
-                                         co0 + wco, mode, out32, out16, slope, epi,
-                                         [&](int c, float4 &sc, float4 &sh) {
-                                             // c = 16 nf + 4 (lane / 16) (+ 0): fragment nf's registers
-                                             sc = bsc[c >> 4];
-                                             sh = bsh[c >> 4];
-                                         });
+            conv_epilogue<WMF, WNF, EPI, true>(acc, mp, lane, b, ty * TH + wrow, tx * TW + (lane & 15), H,
+                                                         W, Cout, co0 + wco, mode, out32, out16, slope, epi,
+                                                         [&](int c, float4 &sc, float4 &sh) {
+                                                             // c = 16 nf + 4 (lane / 16) (+ 0):
+                                                             // fragment nf's registers
+                                                             sc = bsc[c >> 4];
+                                                             sh = bsh[c >> 4];
+                                                         });
             advance(tx, ty, b);
         }
         wg_barrier();  // every wavefront is done with these buffers
     };
+    // Several chunks per tile (weights copied with every stage), plain
+    // epilogue: one barrier per stage.  After the barrier every wavefront is
+    // done with the previous stage, so the next stage's copies go into its
+    // buffers then; the epilogue's stores (a fixed number, see
+    // conv_epilogue) stay in flight across the next stage's wait, which
+    // counts them: completion is reported in issue order.
+    if constexpr (RW && !UP && EPI == 0) {
+        constexpr int NST1 = WMF * WNF / 2, NST0 = WMF * WNF;  // epilogue stores in mode 1 / 0
+        bool prev_epi = false;
+        auto step1 = [&](luint4 *__restrict__ ch_, luint4 *__restrict__ cw_, luint4 *__restrict__ nh_,
+                         luint4 *__restrict__ nw_, int st) {
+            if (!prev_epi)
+                WAIT_VM(0);  // this stage's copies
+            else if (mode == 1)
+                WAIT_VM(NST1);  // ... but not the previous epilogue's stores
+            else
+                WAIT_VM(NST0);
+            wg_barrier();
+            const bool last = st % nch == nch - 1;
+            // context-map loads before the copies, so that the epilogue's wait
+            // for them leaves the copies in flight
+            if (last && mode == 1 && epi.cmap)
+                conv_cmap_issue<WMF, WNF>(mp, lane, ty * TH + wrow, tx * TW + (lane & 15), H, W, Cout, co0 + wco,
+                                          epi);
+            const bool more = st + 1 < nstage;
+            if (more && ++nchk == nch) {
+                nchk = 0;
+                advance(ntx, nty, nbb);
+            }
+            issue_halo(nh_, ntx, nty, nbb, nchk, more);
+            issue_w(nw_, nchk, more);
+            compute(ch_, cw_);
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+            for (int q = 0; q < HINT; ++q) asm volatile("" ::"v"(hoff[q]));
+#pragma unroll
+            for (int q = 0; q < WIN; ++q) asm volatile("" ::"v"(woff[q]));
+#endif
+            if (last) {
+                conv_epilogue<WMF, WNF, EPI, true, NISS>(acc, mp, lane, b, ty * TH + wrow, tx * TW + (lane & 15), H,
+                                                         W, Cout, co0 + wco, mode, out32, out16, slope, epi,
+                                                         [&](int c, float4 &sc, float4 &sh) {
+                                                             sc = bsc[c >> 4];
+                                                             sh = bsh[c >> 4];
+                                                         });
+                advance(tx, ty, b);
+            }
+            prev_epi = last;
+        };
+        for (int st = 0; st < nstage; st += 2) {
+            step1(hA, wA, hB, wB, st);
+            if (st + 1 < nstage) step1(hB, wB, hA, wA, st + 1);
+        }
+        return;
+    }
     for (int st = 0; st < nstage; st += 2) {
         step(hA, wA, hB, wB, st);
         if (st + 1 < nstage) step(hB, wB, hA, wA, st + 1);
