@@ -16,7 +16,8 @@ One timed step = the encoder pass on the medium plus the complete batched
 solve of all right-hand sides, inputs resident in HBM.  The plain-SL solve of
 the same right-hand sides is timed the same way.  `value` is the U-Net + SL
 seconds per right-hand side; the mini-retraining is timed separately and also
-reported amortised over the batch.
+reported amortised over the batch.  Both solves also report the mean
+convergence factor of eq. 4.1 at a 1e6 and a 1e7 residual reduction.
 
 Prints one JSON line.  Runs on one GPU only.
 """
@@ -86,6 +87,15 @@ def measured_traffic(kernel):
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != m2.group(1):
         return None
     return float(m1.group(1))
+
+
+def rho_means(stats):
+    """Mean convergence factor of eq. 4.1 over the right-hand sides at a
+    1e6 and a 1e7 residual reduction (helm_fgmres_stats rho_1e6 / rho_1e7)."""
+    import numpy as np
+
+    return {"rho_1e6_mean": float(np.mean([s["rho_1e6"] for s in stats])),
+            "rho_1e7_mean": float(np.mean([s["rho_1e7"] for s in stats]))}
 
 
 def log(msg):
@@ -321,10 +331,11 @@ def main():
         },
         "unet_sl": {"s_per_rhs": value, "iterations_mean": float(np.mean(its_net)),
                     "iterations_max": int(max(its_net)), "true_relres_max": relres_net,
+                    **rho_means(st_net),
                     "fallbacks": int(sum(s["fallback"] for s in st_net)), "status": rc_net},
         "plain_sl": {"s_per_rhs": sl_value, "iterations_mean": float(np.mean(its_sl)),
                      "iterations_max": int(max(its_sl)), "true_relres_max": relres_sl,
-                     "status": rc_sl},
+                     **rho_means(st_sl), "status": rc_sl},
         "speedup_vs_plain_sl": sl_value / value,
         "retrain": {"steps": a.retrain, "seconds": t_retrain,
                     "loss_first": losses[0] if losses else None,
