@@ -296,48 +296,102 @@ int chol_qr2(BlockWork &w, float2 *W, int s, std::vector<cd> &R, bool &ok, hipSt
     return HELM_OK;
 }
 
-// min ||E - H Y||_F by Householder QR (H: rows x cols, E: rows x s, row-major);
-// returns Y (cols x s) and the column norms of E - H Y
-void block_lsq(std::vector<cd> H, std::vector<cd> E, int rows, int cols, int s, std::vector<cd> &Y,
-               std::vector<double> &res)
-{
-    for (int c = 0; c < cols; ++c) {
-        double nrm = 0.0;
-        for (int i = c; i < rows; ++i) nrm += std::norm(H[i * cols + c]);
-        nrm = std::sqrt(nrm);
-        if (nrm == 0.0) continue;
-        const cd a0 = H[c * cols + c];
-        const cd ph = std::abs(a0) > 0.0 ? a0 / std::abs(a0) : cd(1.0);
-        std::vector<cd> u(rows, cd(0.0));
-        for (int i = c; i < rows; ++i) u[i] = H[i * cols + c];
-        u[c] += ph * nrm;
-        double un = 0.0;
-        for (int i = c; i < rows; ++i) un += std::norm(u[i]);
-        for (int j = c; j < cols; ++j) {
+// Least squares of a block FGMRES cycle, min || E - H Y || with H the block
+// Hessenberg matrix ((m + 1) s x m s) and E the first block column scaled by
+// the Cholesky factor of the residual block, by Householder reflections
+// computed one block column at a time as the Arnoldi process adds it: step j
+// applies the reflections of the earlier columns to the new block column,
+// then finds its own s reflections over rows j s .. (j + 2) s - 1 (the
+// Hessenberg structure leaves nothing below) and applies them to E.  The
+// reduced block column stays in H (upper triangular part R), so a step costs
+// O(j s^3) instead of refactoring O((j s)^3).  Each reflection is I - 2 u u^H
+// / (u^H u) with u = x + phase(x_0) ||x|| e_0 on its column's sub-diagonal
+// part.
+struct BlockLsq {
+    int s = 0, M1 = 0, MS = 0;
+    std::vector<cd> H, E;           // [M1][MS], [M1][s], reduced in place
+    std::vector<std::vector<cd>> u;  // reflection of column c, rows c .. c + u[c].size() - 1
+    std::vector<double> un;          // u^H u (0: no reflection)
+
+    void reset(int s_, int m, const std::vector<cd> &beta)
+    {
+        s = s_;
+        M1 = (m + 1) * s;
+        MS = m * s;
+        H.assign((size_t)M1 * MS, cd(0.0));
+        E.assign((size_t)M1 * s, cd(0.0));
+        for (int i = 0; i < s; ++i)
+            for (int k = 0; k < s; ++k) E[(size_t)i * s + k] = beta[(size_t)i * s + k];
+        u.assign(MS, {});
+        un.assign(MS, 0.0);
+    }
+    cd &h(int r, int c) { return H[(size_t)r * MS + c]; }
+    // applies reflection c to column j of H (ncols = 1) or to E (all s columns)
+    void reflect_h(int c, int j)
+    {
+        if (un[c] == 0.0) return;
+        const std::vector<cd> &v = u[c];
+        cd t = 0.0;
+        for (size_t i = 0; i < v.size(); ++i) t += std::conj(v[i]) * h(c + (int)i, j);
+        t *= 2.0 / un[c];
+        for (size_t i = 0; i < v.size(); ++i) h(c + (int)i, j) -= v[i] * t;
+    }
+    void reflect_e(int c)
+    {
+        if (un[c] == 0.0) return;
+        const std::vector<cd> &v = u[c];
+        for (int q = 0; q < s; ++q) {
             cd t = 0.0;
-            for (int i = c; i < rows; ++i) t += std::conj(u[i]) * H[i * cols + j];
-            for (int i = c; i < rows; ++i) H[i * cols + j] -= 2.0 * u[i] * t / un;
-        }
-        for (int j = 0; j < s; ++j) {
-            cd t = 0.0;
-            for (int i = c; i < rows; ++i) t += std::conj(u[i]) * E[i * s + j];
-            for (int i = c; i < rows; ++i) E[i * s + j] -= 2.0 * u[i] * t / un;
+            for (size_t i = 0; i < v.size(); ++i) t += std::conj(v[i]) * E[(size_t)(c + i) * s + q];
+            t *= 2.0 / un[c];
+            for (size_t i = 0; i < v.size(); ++i) E[(size_t)(c + i) * s + q] -= v[i] * t;
         }
     }
-    Y.assign((size_t)cols * s, cd(0.0));
-    for (int j = 0; j < s; ++j)
-        for (int i = cols - 1; i >= 0; --i) {
-            cd t = E[i * s + j];
-            for (int k = i + 1; k < cols; ++k) t -= H[i * cols + k] * Y[k * s + j];
-            Y[i * s + j] = H[i * cols + i] != cd(0.0) ? t / H[i * cols + i] : cd(0.0);
+    // block column j of H (rows 0 .. (j + 2) s - 1) has been filled: reduce
+    // it; res[q] = the least-squares residual norm of right-hand side q
+    void add_column(int j, std::vector<double> &res)
+    {
+        const int c0 = j * s, rows = (j + 2) * s;
+        for (int k = 0; k < s; ++k)
+            for (int c = 0; c < c0; ++c) reflect_h(c, c0 + k);
+        for (int k = 0; k < s; ++k) {
+            const int c = c0 + k;
+            double nrm = 0.0;
+            for (int i = c; i < rows; ++i) nrm += std::norm(h(i, c));
+            nrm = std::sqrt(nrm);
+            if (nrm == 0.0) continue;
+            const cd a0 = h(c, c);
+            const cd ph = std::abs(a0) > 0.0 ? a0 / std::abs(a0) : cd(1.0);
+            std::vector<cd> v(rows - c);
+            for (int i = c; i < rows; ++i) v[i - c] = h(i, c);
+            v[0] += ph * nrm;
+            double n2 = 0.0;
+            for (const cd &z : v) n2 += std::norm(z);
+            u[c] = std::move(v);
+            un[c] = n2;
+            for (int kk = k; kk < s; ++kk) reflect_h(c, c0 + kk);
+            reflect_e(c);
         }
-    res.assign(s, 0.0);
-    for (int j = 0; j < s; ++j) {
-        double r = 0.0;
-        for (int i = cols; i < rows; ++i) r += std::norm(E[i * s + j]);
-        res[j] = std::sqrt(r);
+        res.assign(s, 0.0);
+        for (int q = 0; q < s; ++q) {
+            double r = 0.0;
+            for (int i = (j + 1) * s; i < rows; ++i) r += std::norm(E[(size_t)i * s + q]);
+            res[q] = std::sqrt(r);
+        }
     }
-}
+    // Y ((kk s) x s) from the reduced system of the first kk block columns
+    void solve(int kk, std::vector<cd> &Y)
+    {
+        const int cols = kk * s;
+        Y.assign((size_t)cols * s, cd(0.0));
+        for (int q = 0; q < s; ++q)
+            for (int i = cols - 1; i >= 0; --i) {
+                cd t = E[(size_t)i * s + q];
+                for (int k = i + 1; k < cols; ++k) t -= h(i, k) * Y[(size_t)k * s + q];
+                Y[(size_t)i * s + q] = h(i, i) != cd(0.0) ? t / h(i, i) : cd(0.0);
+            }
+    }
+};
 
 // z = Prec(v) for s fields
 int block_prec(helm_handle *h, BlockWork &w, int prec, unet_net *net, const float2 *v, float2 *z, int s,
@@ -373,6 +427,7 @@ int block_solve(helm_handle *h, BlockWork &w, int s, const float2 *b, double2 *x
     std::vector<double> e6(s, 0.0), e7(s, 0.0);
     int its = 0, cycles = 0;
     bool first = true;
+    BlockLsq lsq;
     for (;;) {
         // R = B - A X in FP64, stored complex64 in slot 0, with its norms
         launch_true_residual(h->kappa0, h->gamma0, h->n, h->omega, b, N, x, N, w.V, N, w.rpart, nblk, s, nullptr,
@@ -394,10 +449,8 @@ int block_solve(helm_handle *h, BlockWork &w, int s, const float2 *b, double2 *x
         int rc = chol_qr2(w, w.V, s, beta, ok, st);
         if (rc) return rc;
         if (!ok) break;  // rank-deficient residual block
-        const int M1 = (m + 1) * s, MS = m * s;
-        std::vector<cd> Hb((size_t)M1 * MS, cd(0.0)), E((size_t)M1 * s, cd(0.0)), Y;
-        for (int i = 0; i < s; ++i)
-            for (int k = 0; k < s; ++k) E[i * s + k] = beta[i * s + k];
+        lsq.reset(s, m, beta);
+        std::vector<cd> Y;
         std::vector<double> est;
         int kk = 0;
         for (int j = 0; j < m; ++j) {
@@ -410,22 +463,16 @@ int block_solve(helm_handle *h, BlockWork &w, int s, const float2 *b, double2 *x
                 if ((rc = gram(w, w.V, na, W, s, Cg, st))) return rc;
                 if ((rc = combine<0>(w, w.V, na, Cg, s, W, nullptr, st))) return rc;
                 for (int i = 0; i < na; ++i)
-                    for (int k = 0; k < s; ++k) Hb[(size_t)i * MS + j * s + k] += Cg[i * s + k];
+                    for (int k = 0; k < s; ++k) lsq.h(i, j * s + k) += Cg[i * s + k];
             }
             std::vector<cd> Rn;
             if ((rc = chol_qr2(w, W, s, Rn, ok, st))) return rc;
             for (int i = 0; i < s; ++i)
-                for (int k = 0; k < s; ++k) Hb[(size_t)(na + i) * MS + j * s + k] = ok ? Rn[i * s + k] : cd(0.0);
+                for (int k = 0; k < s; ++k) lsq.h(na + i, j * s + k) = ok ? Rn[i * s + k] : cd(0.0);
             ++its;
             kk = j + 1;
             // least squares over the first (j + 2) s rows and (j + 1) s columns
-            const int rows = (j + 2) * s, cols = (j + 1) * s;
-            std::vector<cd> Hs((size_t)rows * cols), Es((size_t)rows * s);
-            for (int r = 0; r < rows; ++r) {
-                for (int c = 0; c < cols; ++c) Hs[(size_t)r * cols + c] = Hb[(size_t)r * MS + c];
-                for (int k = 0; k < s; ++k) Es[(size_t)r * s + k] = E[(size_t)r * s + k];
-            }
-            block_lsq(Hs, Es, rows, cols, s, Y, est);
+            lsq.add_column(j, est);
             bool done = true;
             for (int k = 0; k < s; ++k) {
                 const double e = bn[k] > 0.0 ? est[k] / bn[k] : 0.0;
@@ -435,6 +482,7 @@ int block_solve(helm_handle *h, BlockWork &w, int s, const float2 *b, double2 *x
             }
             if (!ok || done || its >= maxit) break;
         }
+        lsq.solve(kk, Y);
         if ((rc = combine<2>(w, w.Z, kk * s, Y, s, nullptr, x, st))) return rc;
         ++cycles;
     }
