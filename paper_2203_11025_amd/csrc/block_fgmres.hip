@@ -11,9 +11,11 @@
 //   X += [Z_0..Z_j] Y with Y = argmin ||E_1 beta - Hbar Y||_F.
 // Vectors are complex64; every Gram entry accumulates in FP64 and is reduced
 // in a fixed order; the block Hessenberg matrix, its least-squares problem
-// (Householder QR), the Cholesky factors and X are FP64.  The small dense
-// steps run on the host (s <= 16, (m + 1) s^2 <= 4096): a block step
-// synchronises once per Gram matrix and coefficient upload.
+// (Householder QR), the Cholesky factors and X are FP64.  The Gram
+// matrices, the Cholesky factors and the updates stay on the device; a
+// block step synchronises once, to bring the new Hessenberg block column and
+// the factor to the host, which reduces the least-squares problem (s <= 16,
+// (m + 1) s^2 <= 4096).
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -95,7 +97,10 @@ __global__ __launch_bounds__(BF_T) void k_block_gram(const float2 *__restrict__ 
 }
 
 // out[i][k] = sum over chunks (in order) of part[chunk][i][k]
-__global__ void k_block_gram_sum(const double2 *__restrict__ part, int nchunk, int nik, double2 *__restrict__ out)
+// out = the Gram matrix; hc_mode 1 also stores it to hc, 2 adds it to hc
+// (the two Gram-Schmidt passes' coefficients of one Hessenberg block column)
+__global__ void k_block_gram_sum(const double2 *__restrict__ part, int nchunk, int nik, double2 *__restrict__ out,
+                                 double2 *__restrict__ hc, int hc_mode)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nik) return;
@@ -106,6 +111,84 @@ __global__ void k_block_gram_sum(const double2 *__restrict__ part, int nchunk, i
         y += v.y;
     }
     out[q] = make_double2(x, y);
+    if (hc_mode == 1) hc[q] = make_double2(x, y);
+    else if (hc_mode == 2) hc[q] = make_double2(hc[q].x + x, hc[q].y + y);
+}
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zcmul(double2 a, double2 b)  // conj(a) b
+{
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// One Cholesky QR pass on the device (one workgroup, s <= 16): the Gram
+// matrix G = W^H W = R^H R (R upper, real diagonal), Rinv = R^-1 for the
+// update W <- W R^-1, and the accumulated factor Ra <- R Ra (Ra <- R on the
+// first pass).  *fail records a pivot that is not positive (then Rinv is
+// the identity and W is left as it is).
+__global__ __launch_bounds__(256) void k_block_chol(const double2 *__restrict__ G, int s, double2 *__restrict__ Rinv,
+                                                    double2 *__restrict__ Ra, int pass, int *__restrict__ fail)
+{
+    __shared__ double2 R[BF_SMAX][BF_SMAX], X[BF_SMAX][BF_SMAX], A[BF_SMAX][BF_SMAX];
+    __shared__ int bad;
+    const int t = threadIdx.x, i = t / BF_SMAX, k = t % BF_SMAX;
+    if (t == 0) bad = 0;
+    R[i][k] = X[i][k] = make_double2(0.0, 0.0);
+    A[i][k] = (pass > 0 && i < s && k < s) ? Ra[i * s + k] : make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int j = 0; j < s; ++j) {
+        if (t == 0) {
+            double d = G[j * s + j].x;
+            for (int q = 0; q < j; ++q) d -= R[q][j].x * R[q][j].x + R[q][j].y * R[q][j].y;
+            if (!(d > 0.0)) {
+                bad = 1;
+                d = 1.0;
+            }
+            R[j][j] = make_double2(sqrt(d), 0.0);
+        }
+        __syncthreads();
+        if (t > j && t < s) {
+            double2 v = G[j * s + t];
+            for (int q = 0; q < j; ++q) {
+                const double2 p = zcmul(R[q][j], R[q][t]);
+                v.x -= p.x;
+                v.y -= p.y;
+            }
+            R[j][t] = make_double2(v.x / R[j][j].x, v.y / R[j][j].x);
+        }
+        __syncthreads();
+    }
+    if (t < s) {  // column t of R^-1 by back substitution
+        const int c = t;
+        X[c][c] = make_double2(1.0 / R[c][c].x, 0.0);
+        for (int r = c - 1; r >= 0; --r) {
+            double2 v = make_double2(0.0, 0.0);
+            for (int q = r + 1; q <= c; ++q) {
+                const double2 p = zmul(R[r][q], X[q][c]);
+                v.x += p.x;
+                v.y += p.y;
+            }
+            X[r][c] = make_double2(-v.x / R[r][r].x, -v.y / R[r][r].x);
+        }
+    }
+    __syncthreads();
+    if (i < s && k < s) {
+        Rinv[i * s + k] = bad ? make_double2(i == k ? 1.0 : 0.0, 0.0) : X[i][k];
+        double2 v = R[i][k];
+        if (pass > 0) {
+            v = make_double2(0.0, 0.0);
+            for (int q = 0; q < s; ++q) {
+                const double2 p = zmul(R[i][q], A[q][k]);
+                v.x += p.x;
+                v.y += p.y;
+            }
+        }
+        Ra[i * s + k] = v;
+    }
+    if (t == 0 && (pass == 0 || bad)) *fail = bad;
 }
 
 // Per point p, with P = sum_{i < na} A_i[p] C[i][k] (C double2 [na][s]):
@@ -172,12 +255,17 @@ __global__ __launch_bounds__(BF_T) void k_block_combine(const float2 *A, int na,
 
 struct BlockWork {
     size_t N = 0;
-    int s = 0, m = 0, nchunk = 0, chunk = 0;
+    int s = 0, m = 0, nchunk = 0;  // nchunk: most Gram point chunks (part's size)
     float2 *V = nullptr, *Z = nullptr, *t1 = nullptr, *t2 = nullptr;
     double2 *part = nullptr, *G = nullptr, *C = nullptr;
+    double2 *Hc = nullptr, *Ra = nullptr;  // Hessenberg block column, accumulated Cholesky factor
+    int *fail = nullptr;
     double *rpart = nullptr;
     ~BlockWork()
     {
+        dev_free(Hc);
+        dev_free(Ra);
+        dev_free(fail);
         dev_free(V);
         dev_free(Z);
         dev_free(t1);
@@ -191,11 +279,20 @@ struct BlockWork {
 
 int sm_of(int s) { return s <= 4 ? 4 : s <= 8 ? 8 : 16; }
 
-// G (host, na x s, row-major) = A^H B over N points
-int gram(BlockWork &w, const float2 *A, int na, const float2 *B, int s, std::vector<cd> &G, hipStream_t st)
+// w.G (device, na x s, row-major) = A^H B over N points; hc_mode as
+// k_block_gram_sum (w.Hc)
+void gram(BlockWork &w, const float2 *A, int na, const float2 *B, int s, int hc_mode, hipStream_t st)
 {
-    const dim3 grid((na + BF_TI - 1) / BF_TI, w.nchunk);
-#define BF_G(S) hipLaunchKernelGGL(k_block_gram<S>, grid, dim3(BF_T), 0, st, A, na, B, s, w.N, w.chunk, w.part)
+    // enough point chunks for about 2048 workgroups over the row tiles (a
+    // small grid or a thin block would otherwise leave most of the GPU idle),
+    // within the workspace's chunk count (chunks of at least 256 points; of
+    // 8192 points or fewer on large grids)
+    const int ntiles = (na + BF_TI - 1) / BF_TI;
+    const int nck = (int)std::min<size_t>(
+        w.nchunk, std::max<size_t>((w.N + 8191) / 8192, (size_t)(2048 + ntiles - 1) / ntiles));
+    const int chunk = (int)((w.N + nck - 1) / nck);
+    const dim3 grid(ntiles, nck);
+#define BF_G(S) hipLaunchKernelGGL(k_block_gram<S>, grid, dim3(BF_T), 0, st, A, na, B, s, w.N, chunk, w.part)
     switch (sm_of(s)) {
     case 4: BF_G(4); break;
     case 8: BF_G(8); break;
@@ -203,96 +300,48 @@ int gram(BlockWork &w, const float2 *A, int na, const float2 *B, int s, std::vec
     }
 #undef BF_G
     const int nik = na * s;
-    hipLaunchKernelGGL(k_block_gram_sum, dim3((nik + 255) / 256), dim3(256), 0, st, w.part, w.nchunk, nik, w.G);
-    std::vector<double2> h(nik);
-    HELM_HIP_CHECK(hipMemcpyAsync(h.data(), w.G, nik * sizeof(double2), hipMemcpyDeviceToHost, st));
-    HELM_HIP_CHECK(hipStreamSynchronize(st));
-    G.resize(nik);
-    for (int q = 0; q < nik; ++q) G[q] = cd(h[q].x, h[q].y);
-    return HELM_OK;
+    hipLaunchKernelGGL(k_block_gram_sum, dim3((nik + 255) / 256), dim3(256), 0, st, w.part, nck, nik, w.G, w.Hc,
+                       hc_mode);
 }
 
+// the combination of k_block_combine with device coefficients C [na][s]
 template <int MODE>
-int combine(BlockWork &w, const float2 *A, int na, const std::vector<cd> &C, int s, float2 *Out, double2 *X,
-            hipStream_t st)
+void combine(BlockWork &w, const float2 *A, int na, const double2 *C, int s, float2 *Out, double2 *X, hipStream_t st)
 {
-    std::vector<double2> h(na * s);
-    for (int q = 0; q < na * s; ++q) h[q] = make_double2(C[q].real(), C[q].imag());
-    HELM_HIP_CHECK(hipMemcpyAsync(w.C, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice, st));
     const int gx = (int)std::min<size_t>(2048, (w.N + BF_T - 1) / BF_T);
     const size_t lds = (size_t)na * s * sizeof(double2);
-#define BF_C(S) hipLaunchKernelGGL((k_block_combine<S, MODE>), dim3(gx), dim3(BF_T), lds, st, A, na, w.C, s, w.N, Out, X)
+#define BF_C(S) hipLaunchKernelGGL((k_block_combine<S, MODE>), dim3(gx), dim3(BF_T), lds, st, A, na, C, s, w.N, Out, X)
     switch (sm_of(s)) {
     case 4: BF_C(4); break;
     case 8: BF_C(8); break;
     default: BF_C(16); break;
     }
 #undef BF_C
-    // the host copy of C must outlive the transfer
-    HELM_HIP_CHECK(hipStreamSynchronize(st));
-    return HELM_OK;
 }
 
-// Cholesky of the Hermitian s x s G = R^H R (R upper); false if not positive
-bool cholesky(const std::vector<cd> &G, int s, std::vector<cd> &R)
+// W (s fields) = Q R by Cholesky QR applied twice, on the device: W is
+// overwritten by Q, R (s x s upper, row-major) left in w.Ra, *w.fail set on a
+// rank-deficient block.  No host synchronisation.
+void chol_qr2(BlockWork &w, float2 *W, int s, hipStream_t st)
 {
-    R.assign((size_t)s * s, cd(0.0));
-    for (int j = 0; j < s; ++j) {
-        double d = G[j * s + j].real();
-        for (int k = 0; k < j; ++k) d -= std::norm(R[k * s + j]);
-        if (!(d > 0.0)) return false;
-        R[j * s + j] = std::sqrt(d);
-        for (int i = j + 1; i < s; ++i) {
-            cd t = G[j * s + i];
-            for (int k = 0; k < j; ++k) t -= std::conj(R[k * s + j]) * R[k * s + i];
-            R[j * s + i] = t / R[j * s + j].real();
-        }
-    }
-    return true;
-}
-
-// inverse of an upper-triangular s x s matrix
-std::vector<cd> tri_inv(const std::vector<cd> &R, int s)
-{
-    std::vector<cd> X((size_t)s * s, cd(0.0));
-    for (int c = 0; c < s; ++c) {
-        X[c * s + c] = 1.0 / R[c * s + c];
-        for (int i = c - 1; i >= 0; --i) {
-            cd t = 0.0;
-            for (int k = i + 1; k <= c; ++k) t += R[i * s + k] * X[k * s + c];
-            X[i * s + c] = -t / R[i * s + i];
-        }
-    }
-    return X;
-}
-
-std::vector<cd> matmul(const std::vector<cd> &A, const std::vector<cd> &B, int n, int k, int m)
-{
-    std::vector<cd> C((size_t)n * m, cd(0.0));
-    for (int i = 0; i < n; ++i)
-        for (int q = 0; q < k; ++q)
-            for (int j = 0; j < m; ++j) C[i * m + j] += A[i * k + q] * B[q * m + j];
-    return C;
-}
-
-// W (s fields) = Q R by Cholesky QR applied twice; W is overwritten by Q,
-// R (s x s upper, row-major) returned.  False on a rank-deficient block.
-int chol_qr2(BlockWork &w, float2 *W, int s, std::vector<cd> &R, bool &ok, hipStream_t st)
-{
-    R.assign((size_t)s * s, cd(0.0));
-    for (int i = 0; i < s; ++i) R[i * s + i] = 1.0;
-    ok = true;
     for (int pass = 0; pass < 2; ++pass) {
-        std::vector<cd> G, Rk;
-        int rc = gram(w, W, s, W, s, G, st);
-        if (rc) return rc;
-        if (!cholesky(G, s, Rk)) {
-            ok = false;
-            return HELM_OK;
-        }
-        if ((rc = combine<1>(w, W, s, tri_inv(Rk, s), s, W, nullptr, st))) return rc;
-        R = matmul(Rk, R, s, s, s);
+        gram(w, W, s, W, s, 0, st);
+        hipLaunchKernelGGL(k_block_chol, dim3(1), dim3(BF_SMAX * BF_SMAX), 0, st, w.G, s, w.C, w.Ra, pass, w.fail);
+        combine<1>(w, W, s, w.C, s, W, nullptr, st);
     }
+}
+
+// the accumulated Cholesky factor and failure flag of chol_qr2 (synchronises)
+int chol_result(BlockWork &w, int s, std::vector<cd> &R, bool &ok, hipStream_t st)
+{
+    std::vector<double2> h((size_t)s * s);
+    int f = 0;
+    HELM_HIP_CHECK(hipMemcpyAsync(h.data(), w.Ra, h.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HELM_HIP_CHECK(hipMemcpyAsync(&f, w.fail, sizeof(int), hipMemcpyDeviceToHost, st));
+    HELM_HIP_CHECK(hipStreamSynchronize(st));
+    R.resize(h.size());
+    for (size_t q = 0; q < h.size(); ++q) R[q] = cd(h[q].x, h[q].y);
+    ok = f == 0;
     return HELM_OK;
 }
 
@@ -446,7 +495,8 @@ int block_solve(helm_handle *h, BlockWork &w, int s, const float2 *b, double2 *x
         if (all || its >= maxit) break;
         std::vector<cd> beta;
         bool ok;
-        int rc = chol_qr2(w, w.V, s, beta, ok, st);
+        chol_qr2(w, w.V, s, st);
+        int rc = chol_result(w, s, beta, ok, st);
         if (rc) return rc;
         if (!ok) break;  // rank-deficient residual block
         lsq.reset(s, m, beta);
@@ -458,15 +508,20 @@ int block_solve(helm_handle *h, BlockWork &w, int s, const float2 *b, double2 *x
             if ((rc = block_prec(h, w, prec, net, Vj, Zj, s, st))) return rc;
             launch_apply(h->lv[0], 0.f, Zj, N, W, N, s, nullptr, st);
             const int na = (j + 1) * s;
+            // two Gram-Schmidt passes (their coefficients summed into w.Hc)
+            // and the Cholesky QR, all on the device; one round trip brings
+            // the Hessenberg block column and the factor back
             for (int pass = 0; pass < 2; ++pass) {
-                std::vector<cd> Cg;
-                if ((rc = gram(w, w.V, na, W, s, Cg, st))) return rc;
-                if ((rc = combine<0>(w, w.V, na, Cg, s, W, nullptr, st))) return rc;
-                for (int i = 0; i < na; ++i)
-                    for (int k = 0; k < s; ++k) lsq.h(i, j * s + k) += Cg[i * s + k];
+                gram(w, w.V, na, W, s, pass == 0 ? 1 : 2, st);
+                combine<0>(w, w.V, na, w.G, s, W, nullptr, st);
             }
+            chol_qr2(w, W, s, st);
+            std::vector<double2> hc((size_t)na * s);
+            HELM_HIP_CHECK(hipMemcpyAsync(hc.data(), w.Hc, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
             std::vector<cd> Rn;
-            if ((rc = chol_qr2(w, W, s, Rn, ok, st))) return rc;
+            if ((rc = chol_result(w, s, Rn, ok, st))) return rc;
+            for (int i = 0; i < na; ++i)
+                for (int k = 0; k < s; ++k) lsq.h(i, j * s + k) = cd(hc[(size_t)i * s + k].x, hc[(size_t)i * s + k].y);
             for (int i = 0; i < s; ++i)
                 for (int k = 0; k < s; ++k) lsq.h(na + i, j * s + k) = ok ? Rn[i * s + k] : cd(0.0);
             ++its;
@@ -483,7 +538,14 @@ int block_solve(helm_handle *h, BlockWork &w, int s, const float2 *b, double2 *x
             if (!ok || done || its >= maxit) break;
         }
         lsq.solve(kk, Y);
-        if ((rc = combine<2>(w, w.Z, kk * s, Y, s, nullptr, x, st))) return rc;
+        if (kk > 0) {
+            std::vector<double2> yh(Y.size());
+            for (size_t q = 0; q < Y.size(); ++q) yh[q] = make_double2(Y[q].real(), Y[q].imag());
+            HELM_HIP_CHECK(hipMemcpyAsync(w.C, yh.data(), yh.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+            combine<2>(w, w.Z, kk * s, w.C, s, nullptr, x, st);
+            // the host copy of Y must outlive the transfer
+            HELM_HIP_CHECK(hipStreamSynchronize(st));
+        }
         ++cycles;
     }
     for (int k = 0; k < s && stats; ++k) {
@@ -550,8 +612,8 @@ extern "C" int helm_block_fgmres_solve(helm_handle *h, int nrhs, const float *b,
     w.N = (size_t)h->n * h->n;
     w.s = s;
     w.m = m;
-    w.chunk = 8192;
-    w.nchunk = (int)((w.N + w.chunk - 1) / w.chunk);
+    // Gram partial sums: up to nchunk point chunks per launch (see gram())
+    w.nchunk = (int)std::max((w.N + 8191) / 8192, std::min<size_t>((w.N + 255) / 256, 256));
     const size_t nab = (size_t)(m + 1) * s;
     if (dev_malloc(&w.V, nab * w.N * sizeof(float2)) != hipSuccess ||
         dev_malloc(&w.Z, (size_t)m * s * w.N * sizeof(float2)) != hipSuccess ||
@@ -560,6 +622,9 @@ extern "C" int helm_block_fgmres_solve(helm_handle *h, int nrhs, const float *b,
         dev_malloc(&w.part, (size_t)w.nchunk * nab * s * sizeof(double2)) != hipSuccess ||
         dev_malloc(&w.G, nab * s * sizeof(double2)) != hipSuccess ||
         dev_malloc(&w.C, nab * s * sizeof(double2)) != hipSuccess ||
+        dev_malloc(&w.Hc, nab * s * sizeof(double2)) != hipSuccess ||
+        dev_malloc(&w.Ra, (size_t)BF_SMAX * BF_SMAX * sizeof(double2)) != hipSuccess ||
+        dev_malloc(&w.fail, sizeof(int)) != hipSuccess ||
         dev_malloc(&w.rpart, (size_t)s * 256 * sizeof(double)) != hipSuccess) {
         set_error("helm_block_fgmres_solve: device allocation failed");
         return HELM_E_NOMEM;
