@@ -32,9 +32,11 @@ def _problem(helm, n, seed, levels):
     return kap, gam, om, h
 
 
-@pytest.mark.parametrize("n,levels,nrhs,block,m", [(128, 3, 7, 3, 10), (64, 2, 10, 10, 10), (96, 2, 4, 4, 6)])
+@pytest.mark.parametrize("n,levels,nrhs,block,m", [(128, 3, 7, 3, 10), (64, 2, 10, 10, 10), (96, 2, 4, 4, 6),
+                                                    (48, 2, 16, 16, 5)])
 def test_block_fgmres_matches_the_exact_solution_and_the_oracle(H, oracle, n, levels, nrhs, block, m):
-    """Blocks of 3 + 3 + 1, one block of 10, and a 96^2 grid: every field
+    """Blocks of 3 + 3 + 1, one block of 10, a 96^2 grid and the largest
+    block (16, with the device-side Cholesky QR at its full size): every field
     reaches the FP64 tolerance, the solution matches the exact solution of
     the discrete system to 1e-5, and the block iteration counts are the
     oracle's within 10% (R23)."""
