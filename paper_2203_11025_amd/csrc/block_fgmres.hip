@@ -283,13 +283,13 @@ int sm_of(int s) { return s <= 4 ? 4 : s <= 8 ? 8 : 16; }
 // k_block_gram_sum (w.Hc)
 void gram(BlockWork &w, const float2 *A, int na, const float2 *B, int s, int hc_mode, hipStream_t st)
 {
-    // enough point chunks for about 2048 workgroups over the row tiles (a
+    // enough point chunks for about 256 workgroups over the row tiles (a
     // small grid or a thin block would otherwise leave most of the GPU idle),
     // within the workspace's chunk count (chunks of at least 256 points; of
     // 8192 points or fewer on large grids)
     const int ntiles = (na + BF_TI - 1) / BF_TI;
     const int nck = (int)std::min<size_t>(
-        w.nchunk, std::max<size_t>((w.N + 8191) / 8192, (size_t)(2048 + ntiles - 1) / ntiles));
+        w.nchunk, std::max<size_t>((w.N + 8191) / 8192, (size_t)(256 + ntiles - 1) / ntiles));
     const int chunk = (int)((w.N + nck - 1) / nck);
     const dim3 grid(ntiles, nck);
 #define BF_G(S) hipLaunchKernelGGL(k_block_gram<S>, grid, dim3(BF_T), 0, st, A, na, B, s, w.N, chunk, w.part)
