@@ -98,18 +98,24 @@ __global__ __launch_bounds__(BF_T) void k_block_gram(const float2 *__restrict__ 
 
 // out[i][k] = sum over chunks (in order) of part[chunk][i][k]
 // out = the Gram matrix; hc_mode 1 also stores it to hc, 2 adds it to hc
-// (the two Gram-Schmidt passes' coefficients of one Hessenberg block column)
-__global__ void k_block_gram_sum(const double2 *__restrict__ part, int nchunk, int nik, double2 *__restrict__ out,
-                                 double2 *__restrict__ hc, int hc_mode)
+// (the two Gram-Schmidt passes' coefficients of one Hessenberg block column).
+// One wavefront per entry: lane l sums chunks l, l + 64, ..., then the
+// lanes' sums are added in a fixed butterfly order.
+__global__ __launch_bounds__(256) void k_block_gram_sum(const double2 *__restrict__ part, int nchunk, int nik,
+                                                        double2 *__restrict__ out, double2 *__restrict__ hc,
+                                                        int hc_mode)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nik) return;
+    const int q = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (q >= nik) return;  // whole wavefronts leave together
     double x = 0.0, y = 0.0;
-    for (int c = 0; c < nchunk; ++c) {
+    for (int c = lane; c < nchunk; c += 64) {
         const double2 v = part[(size_t)c * nik + q];
         x += v.x;
         y += v.y;
     }
+    x = bf_wsum(x);
+    y = bf_wsum(y);
+    if (lane != 0) return;
     out[q] = make_double2(x, y);
     if (hc_mode == 1) hc[q] = make_double2(x, y);
     else if (hc_mode == 2) hc[q] = make_double2(hc[q].x + x, hc[q].y + y);
@@ -300,8 +306,7 @@ void gram(BlockWork &w, const float2 *A, int na, const float2 *B, int s, int hc_
     }
 #undef BF_G
     const int nik = na * s;
-    hipLaunchKernelGGL(k_block_gram_sum, dim3((nik + 255) / 256), dim3(256), 0, st, w.part, nck, nik, w.G, w.Hc,
-                       hc_mode);
+    hipLaunchKernelGGL(k_block_gram_sum, dim3((nik + 3) / 4), dim3(256), 0, st, w.part, nck, nik, w.G, w.Hc, hc_mode);
 }
 
 // the combination of k_block_combine with device coefficients C [na][s]
