@@ -21,6 +21,7 @@
 #include <complex>
 #include <vector>
 
+#include "block_lsq.h"
 #include "handle.h"
 #include "unet_net.h"
 
@@ -28,7 +29,6 @@ namespace helm {
 
 namespace {
 
-typedef std::complex<double> cd;
 constexpr int BF_T = 256, BF_TI = 2, BF_SMAX = 16;
 
 __device__ __forceinline__ double bf_wsum(double v)
@@ -349,103 +349,6 @@ int chol_result(BlockWork &w, int s, std::vector<cd> &R, bool &ok, hipStream_t s
     ok = f == 0;
     return HELM_OK;
 }
-
-// Least squares of a block FGMRES cycle, min || E - H Y || with H the block
-// Hessenberg matrix ((m + 1) s x m s) and E the first block column scaled by
-// the Cholesky factor of the residual block, by Householder reflections
-// computed one block column at a time as the Arnoldi process adds it: step j
-// applies the reflections of the earlier columns to the new block column,
-// then finds its own s reflections over rows j s .. (j + 2) s - 1 (the
-// Hessenberg structure leaves nothing below) and applies them to E.  The
-// reduced block column stays in H (upper triangular part R), so a step costs
-// O(j s^3) instead of refactoring O((j s)^3).  Each reflection is I - 2 u u^H
-// / (u^H u) with u = x + phase(x_0) ||x|| e_0 on its column's sub-diagonal
-// part.
-struct BlockLsq {
-    int s = 0, M1 = 0, MS = 0;
-    std::vector<cd> H, E;           // [M1][MS], [M1][s], reduced in place
-    std::vector<std::vector<cd>> u;  // reflection of column c, rows c .. c + u[c].size() - 1
-    std::vector<double> un;          // u^H u (0: no reflection)
-
-    void reset(int s_, int m, const std::vector<cd> &beta)
-    {
-        s = s_;
-        M1 = (m + 1) * s;
-        MS = m * s;
-        H.assign((size_t)M1 * MS, cd(0.0));
-        E.assign((size_t)M1 * s, cd(0.0));
-        for (int i = 0; i < s; ++i)
-            for (int k = 0; k < s; ++k) E[(size_t)i * s + k] = beta[(size_t)i * s + k];
-        u.assign(MS, {});
-        un.assign(MS, 0.0);
-    }
-    cd &h(int r, int c) { return H[(size_t)r * MS + c]; }
-    // applies reflection c to column j of H (ncols = 1) or to E (all s columns)
-    void reflect_h(int c, int j)
-    {
-        if (un[c] == 0.0) return;
-        const std::vector<cd> &v = u[c];
-        cd t = 0.0;
-        for (size_t i = 0; i < v.size(); ++i) t += std::conj(v[i]) * h(c + (int)i, j);
-        t *= 2.0 / un[c];
-        for (size_t i = 0; i < v.size(); ++i) h(c + (int)i, j) -= v[i] * t;
-    }
-    void reflect_e(int c)
-    {
-        if (un[c] == 0.0) return;
-        const std::vector<cd> &v = u[c];
-        for (int q = 0; q < s; ++q) {
-            cd t = 0.0;
-            for (size_t i = 0; i < v.size(); ++i) t += std::conj(v[i]) * E[(size_t)(c + i) * s + q];
-            t *= 2.0 / un[c];
-            for (size_t i = 0; i < v.size(); ++i) E[(size_t)(c + i) * s + q] -= v[i] * t;
-        }
-    }
-    // block column j of H (rows 0 .. (j + 2) s - 1) has been filled: reduce
-    // it; res[q] = the least-squares residual norm of right-hand side q
-    void add_column(int j, std::vector<double> &res)
-    {
-        const int c0 = j * s, rows = (j + 2) * s;
-        for (int k = 0; k < s; ++k)
-            for (int c = 0; c < c0; ++c) reflect_h(c, c0 + k);
-        for (int k = 0; k < s; ++k) {
-            const int c = c0 + k;
-            double nrm = 0.0;
-            for (int i = c; i < rows; ++i) nrm += std::norm(h(i, c));
-            nrm = std::sqrt(nrm);
-            if (nrm == 0.0) continue;
-            const cd a0 = h(c, c);
-            const cd ph = std::abs(a0) > 0.0 ? a0 / std::abs(a0) : cd(1.0);
-            std::vector<cd> v(rows - c);
-            for (int i = c; i < rows; ++i) v[i - c] = h(i, c);
-            v[0] += ph * nrm;
-            double n2 = 0.0;
-            for (const cd &z : v) n2 += std::norm(z);
-            u[c] = std::move(v);
-            un[c] = n2;
-            for (int kk = k; kk < s; ++kk) reflect_h(c, c0 + kk);
-            reflect_e(c);
-        }
-        res.assign(s, 0.0);
-        for (int q = 0; q < s; ++q) {
-            double r = 0.0;
-            for (int i = (j + 1) * s; i < rows; ++i) r += std::norm(E[(size_t)i * s + q]);
-            res[q] = std::sqrt(r);
-        }
-    }
-    // Y ((kk s) x s) from the reduced system of the first kk block columns
-    void solve(int kk, std::vector<cd> &Y)
-    {
-        const int cols = kk * s;
-        Y.assign((size_t)cols * s, cd(0.0));
-        for (int q = 0; q < s; ++q)
-            for (int i = cols - 1; i >= 0; --i) {
-                cd t = E[(size_t)i * s + q];
-                for (int k = i + 1; k < cols; ++k) t -= h(i, k) * Y[(size_t)k * s + q];
-                Y[(size_t)i * s + q] = h(i, i) != cd(0.0) ? t / h(i, i) : cd(0.0);
-            }
-    }
-};
 
 // z = Prec(v) for s fields
 int block_prec(helm_handle *h, BlockWork &w, int prec, unet_net *net, const float2 *v, float2 *z, int s,
