@@ -35,7 +35,7 @@ def driver(tmp_path_factory):
     return exe
 
 
-def _hessenberg(rng, s, m, rank_drop=False):
+def _hessenberg(rng, s, m):
     M1, MS = (m + 1) * s, m * s
     H = np.zeros((M1, MS), np.complex128)
     for j in range(m):
@@ -43,8 +43,6 @@ def _hessenberg(rng, s, m, rank_drop=False):
         H[:rows, j * s:(j + 1) * s] = rng.standard_normal((rows, s)) + 1j * rng.standard_normal((rows, s))
         # sub-diagonal block upper triangular, as Cholesky QR leaves it
         H[(j + 1) * s:rows, j * s:(j + 1) * s] = np.triu(H[(j + 1) * s:rows, j * s:(j + 1) * s])
-    if rank_drop:
-        H[(2 * s):(3 * s), s:2 * s] = 0.0  # a breakdown: H_{2,1} = 0
     beta = np.triu(rng.standard_normal((s, s)) + 1j * rng.standard_normal((s, s)))
     return beta, H
 
