@@ -221,7 +221,11 @@ int helm_fgmres_solve(helm_handle *const *probs, int nprob, const int *rhs_per_p
  *          tol 1e-7, maxit 20000, M_V.  (m + 1) block^2 <= 4096, block <= 16.
  *   stats : host array [nrhs]; iterations = block steps of that field's
  *          block; rho per column from the block least-squares residual.
- * Synchronises `stream` several times per block step.  Returns
+ * Synchronises `stream` once per block step and once per cycle start.
+ * A block whose residual block is rank-deficient at a cycle start (a zero
+ * right-hand side, or fields with linearly dependent residuals) cannot be
+ * factored by Cholesky QR: its fields are then solved again from zero one
+ * at a time (block size 1; their stats count only that solve).  Returns
  * HELM_NOT_CONVERGED if a field misses tol within maxit steps.
  */
 int helm_block_fgmres_solve(helm_handle *h, int nrhs, const float *b, double *x, int block,

@@ -373,8 +373,10 @@ int block_prec(helm_handle *h, BlockWork &w, int prec, unet_net *net, const floa
 }
 
 // one block of s right-hand sides
+// (*rank_deficient is set when a cycle starts from a residual block that
+// Cholesky QR cannot factor; the block then stops with its current x)
 int block_solve(helm_handle *h, BlockWork &w, int s, const float2 *b, double2 *x, int m, double tol, int maxit,
-                int prec, unet_net *net, helm_fgmres_stats *stats, hipStream_t st)
+                int prec, unet_net *net, helm_fgmres_stats *stats, hipStream_t st, bool *rank_deficient)
 {
     const size_t N = w.N;
     const int nblk = 256;
@@ -406,7 +408,10 @@ int block_solve(helm_handle *h, BlockWork &w, int s, const float2 *b, double2 *x
         chol_qr2(w, w.V, s, st);
         int rc = chol_result(w, s, beta, ok, st);
         if (rc) return rc;
-        if (!ok) break;  // rank-deficient residual block
+        if (!ok) {  // rank-deficient residual block
+            if (rank_deficient) *rank_deficient = true;
+            break;
+        }
         lsq.reset(s, m, beta);
         std::vector<cd> Y;
         std::vector<double> est;
@@ -541,9 +546,24 @@ extern "C" int helm_block_fgmres_solve(helm_handle *h, int nrhs, const float *b,
     const size_t N = w.N;
     for (int b0 = 0; b0 < nrhs; b0 += s) {
         const int sb = std::min(s, nrhs - b0);
+        bool rank_deficient = false;
         int rc = block_solve(h, w, sb, (const float2 *)b + (size_t)b0 * N, (double2 *)x + (size_t)b0 * N, m, tol,
-                             maxit, prec, net, stats ? stats + b0 : nullptr, st);
+                             maxit, prec, net, stats ? stats + b0 : nullptr, st, &rank_deficient);
         if (rc < 0) return rc;
+        if (rank_deficient && sb > 1) {
+            // a zero right-hand side or linearly dependent residuals: the
+            // block's fields are solved one at a time instead (block size
+            // 1, where only a zero residual, which has converged, is
+            // rank-deficient)
+            rc = HELM_OK;
+            for (int k = 0; k < sb; ++k) {
+                const size_t o = (size_t)(b0 + k) * N;
+                int rk = block_solve(h, w, 1, (const float2 *)b + o, (double2 *)x + o, m, tol, maxit, prec, net,
+                                     stats ? stats + b0 + k : nullptr, st, nullptr);
+                if (rk < 0) return rk;
+                if (rk == HELM_NOT_CONVERGED) rc = HELM_NOT_CONVERGED;
+            }
+        }
         if (rc == HELM_NOT_CONVERGED) status = HELM_NOT_CONVERGED;
     }
     HELM_HIP_CHECK(hipGetLastError());
